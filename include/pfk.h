@@ -1,0 +1,187 @@
+/*
+ * pfk -- pipelined flexible Krylov solvers on one AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the library libpfk.so.  It solves A x = b with a flexible
+ * (nonlinear, inner-iterative) preconditioner B, by the methods of Sanan,
+ * Schnepp and May, "Pipelined, Flexible Krylov Subspace Methods":
+ *   FCG (Alg. 2) and its pipelined form PIPEFCG (Alg. 8),
+ *   GCR (Alg. 9) and PIPEGCR (Alg. 11),
+ *   FGMRES (Alg. 13) and PIPEFGMRES (Alg. 15).
+ * Each takes (A, B, b, x0) as in the paper's listings; FGMRES types also take
+ * the restart length m.  Every step of the solve runs in the library's HIP
+ * kernels on the GPU; the host only enqueues work and reads a status word.
+ *
+ * Operators (the problem class of the paper's experiments, section 6: viscous
+ * "sinker" problems with strongly varying viscosity) are second-order finite
+ * differences on the unit square/cube with homogeneous Dirichlet boundaries:
+ *   (A u)_i = h^-2 sum_f k_f (u_i - u_nb) + h^-1 sum_f (max(v_f,0) u_i + min(v_f,0) u_nb)
+ * over the 2*dim faces f of node i, h = 1/(n+1), u_nb = 0 on the boundary,
+ * k_f = 2 eta_a eta_b / (eta_a + eta_b) (harmonic mean of the node viscosities)
+ * and v_f the outward face-normal velocity (first-order upwind convection).
+ * This is the 5-point (2D) / 7-point (3D) stencil of the section 7 model.
+ *
+ * Layouts.  Unknown vectors hold the N = n^dim interior nodes, x fastest.
+ * eta holds (n+2)^dim values on the padded grid (boundary ring included), x
+ * fastest.  face_vel holds three such padded arrays (x, y, z components);
+ * component c at padded node p is the velocity on the face between p and
+ * p + e_c.  All floating point is IEEE FP64 unless a precision option says
+ * otherwise.
+ *
+ * Errors.  Functions return a pfk_status; a negative value is an error and
+ * pfk_last_error() gives a message (per calling thread).  No exceptions cross
+ * the ABI.  On any return from pfk_solve, x holds the last iterate.
+ *
+ * Ownership.  The caller owns b, x, the workspace and the streams it passes;
+ * the library owns copies of the coefficients (made at create time), its own
+ * auxiliary streams and events.  A handle may be used by one solve at a time
+ * unless each concurrent solve has its own workspace and session.
+ *
+ * Streams.  `stream` arguments are hipStream_t values passed as void*; NULL
+ * is the default stream.  Calls order themselves after work already queued on
+ * that stream and leave later work on it ordered after their own.
+ */
+#ifndef PFK_H
+#define PFK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pfk_operator_s* pfk_operator;
+typedef struct pfk_precond_s* pfk_precond;
+typedef struct pfk_session_s* pfk_session;
+
+typedef enum {
+  PFK_FCG = 0,        /* Alg. 2: two blocking reductions per iteration        */
+  PFK_PIPEFCG = 1,    /* Alg. 8: one reduction, overlapped with B and A        */
+  PFK_GCR = 2,        /* Alg. 9                                                */
+  PFK_PIPEGCR = 3,    /* Alg. 11: one reduction, overlapped with B             */
+  PFK_FGMRES = 4,     /* Alg. 13                                               */
+  PFK_PIPEFGMRES = 5  /* Alg. 15: one reduction, overlapped with B and A       */
+} pfk_method;
+
+typedef enum {
+  PFK_PC_NONE = 0,              /* B(v) = v                                         */
+  PFK_PC_JACOBI = 1,            /* B(v) = D^-1 v, D = diag(A) (linear)               */
+  PFK_PC_JACOBI_PCG = 2,        /* k iterations of Jacobi-PCG on A y = v from y = 0  */
+  PFK_PC_JACOBI_GMRES = 3,      /* one GMRES(k) cycle on A D^-1 t = v from 0, y = D^-1 t */
+  PFK_PC_BLOCK_JACOBI_PCG = 4   /* k Jacobi-PCG iterations inside every cubic block of
+                                   `block` nodes per axis (section 6.2's block Jacobi) */
+} pfk_pc_kind;
+
+typedef enum {
+  PFK_FP64 = 0,            /* everything in FP64                                        */
+  PFK_FP32_BF16COEF = 1    /* preconditioner inner sweeps in FP32 with BF16-stored eta;
+                              the outer method stays FP64                                */
+} pfk_precision;
+
+typedef enum {
+  PFK_OK = 0,
+  PFK_NOT_CONVERGED = 1,   /* maxit reached (or restarts exhausted by residual gaps)  */
+  PFK_ERR_ARG = -1,
+  PFK_ERR_OOM = -2,
+  PFK_ERR_HIP = -3,
+  PFK_ERR_NONFINITE = -4,  /* NaN/Inf met in the residual                             */
+  PFK_ERR_BREAKDOWN = -5   /* breakdown of the initial direction, or more than
+                              max_restarts breakdown restarts                        */
+} pfk_status;
+
+typedef struct {
+  int truncation;          /* window rule (section 5): 0 standard min(j, nu_max),
+                              1 Notay max(1, j mod (nu_max+1)), 2 min(j, j mod nu_max + 1) */
+  double shift_sigma;      /* PIPEFGMRES constant shift; NaN => estimated by
+                              pfk_estimate_sigma (10 power steps)                    */
+  int graph_iters;         /* iterations per captured graph launch (>= 1)            */
+  int use_graph;           /* 1: replay hipGraphs; 0: launch kernels directly         */
+  int host_sync;           /* unpipelined methods only: 1 copies every reduction
+                              result to the host and waits (a blocking reduction)    */
+  int max_restarts;        /* breakdown / residual-gap restarts allowed               */
+  int force_breakdown_at;  /* test hook: force a breakdown at this iteration (-1 off) */
+} pfk_solve_opts;
+
+typedef struct {
+  int iterations;          /* solution updates (CG/CR) or Arnoldi columns (GMRES)    */
+  int restarts;            /* breakdown and residual-gap restarts                     */
+  int converged;           /* 1 if the true residual ended <= rtol * ||b||             */
+  int status;              /* the pfk_status the solve returned                        */
+  double true_rel_resid;   /* ||b - A x|| / ||b|| at exit (0 when b = 0)               */
+  double* history;         /* caller buffer (host) or NULL: history[i] = residual
+                              measure after iteration i (recurred ||r_i|| for CG/CR,
+                              the Givens estimate for GMRES), history[0] = ||r_0||    */
+  int history_cap;         /* entries available in history                            */
+  int history_len;         /* entries written (iterations + 1, capped)                */
+} pfk_solve_info;
+
+/* Defaults: standard truncation, sigma estimated, graph_iters 8, graphs on,
+ * no host sync, 10 restarts, no forced breakdown. */
+void pfk_default_opts(pfk_solve_opts* opts);
+
+/* Operator A of dimension 2 or 3 with n[0..dim) interior nodes per axis (x, y, z;
+ * n[0] == n[1] (== n[2]) is required: the mesh width is h = 1/(n+1) on every
+ * axis).  eta: (n+2)^dim viscosities > 0; face_vel: NULL for the symmetric
+ * diffusion operator, else 3*(n+2)^3 velocities (3D only).  The arrays are
+ * host pointers (ptr_is_device = 0) or device pointers (1); they are copied.
+ * Errors: PFK_ERR_ARG on bad sizes or non-positive eta, PFK_ERR_OOM, PFK_ERR_HIP. */
+int pfk_operator_create(int dim, const int64_t n[3], const double* eta, const double* face_vel,
+                        int ptr_is_device, pfk_operator* out);
+void pfk_operator_destroy(pfk_operator A);
+/* Number of unknowns N. */
+int64_t pfk_operator_size(pfk_operator A);
+/* y = A x for device vectors of N values (enqueued on stream, asynchronous). */
+int pfk_operator_apply(pfk_operator A, const double* x, double* y, void* stream);
+/* D^-1 (device, N values): the Jacobi scaling the preconditioners use. */
+int pfk_operator_diag_inv(pfk_operator A, double* dinv, void* stream);
+
+/* Preconditioner B of the given kind with `inner_its` inner iterations
+ * (1..32; ignored for NONE and JACOBI), precision, and `block` nodes per axis
+ * for BLOCK_JACOBI_PCG (4 or 8).  Errors: PFK_ERR_ARG. */
+int pfk_precond_create(pfk_operator A, pfk_pc_kind kind, int inner_its, pfk_precision prec,
+                       int block, pfk_precond* out);
+void pfk_precond_destroy(pfk_precond B);
+/* y = B(v) for device vectors (synchronous w.r.t. stream completion of the call). */
+int pfk_precond_apply(pfk_precond B, const double* v, double* y, void* stream);
+
+/* Bytes of workspace pfk_solve needs for this method, window/restart length
+ * `mmax` (1..64) and iteration limit `maxit`. */
+size_t pfk_workspace_bytes(pfk_operator A, pfk_precond B, pfk_method method, int mmax, int maxit);
+
+/* Solve A x = b.  b, x: device vectors of N values; x holds x0 on entry and
+ * the last iterate on return.  Stops at the first iteration whose residual
+ * measure is <= rtol * ||b||_2 and whose true residual confirms it, or after
+ * maxit iterations.  mmax: window length nu_max (FCG/GCR types) or restart
+ * length m (FGMRES types).  workspace: device memory of ws_bytes >=
+ * pfk_workspace_bytes(...), or NULL to let the library allocate it for the
+ * call.  opts may be NULL (defaults); info may be NULL.  Returns PFK_OK,
+ * PFK_NOT_CONVERGED or an error.  b == 0 returns x = 0 after 0 iterations. */
+int pfk_solve(pfk_operator A, pfk_precond B, pfk_method method, const double* b, double* x,
+              double rtol, int maxit, int mmax, void* workspace, size_t ws_bytes, void* stream,
+              const pfk_solve_opts* opts, pfk_solve_info* info);
+
+/* Sessions split pfk_solve into asynchronous steps (for timing and serving):
+ * create binds the buffers, start enqueues the set-up and start-up phase,
+ * iterate enqueues `iters` more iterations without waiting, sync waits and
+ * reports.  Iterations enqueued after the solve stopped change nothing. */
+int pfk_session_create(pfk_operator A, pfk_precond B, pfk_method method, const double* b, double* x,
+                       double rtol, int maxit, int mmax, void* workspace, size_t ws_bytes,
+                       void* stream, const pfk_solve_opts* opts, pfk_session* out);
+int pfk_session_start(pfk_session S);
+int pfk_session_iterate(pfk_session S, int iters);
+int pfk_session_sync(pfk_session S, pfk_solve_info* info);
+void pfk_session_destroy(pfk_session S);
+
+/* PIPEFGMRES shift: Rayleigh quotient of v -> A B(v) after `its` power steps
+ * from the normalised ones vector (the largest eigenvalue of the
+ * right-preconditioned operator, sections 4.4 and 5). */
+int pfk_estimate_sigma(pfk_operator A, pfk_precond B, int its, double* sigma, void* stream);
+
+/* Message of the last error on this thread ("" if none). */
+const char* pfk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PFK_H */

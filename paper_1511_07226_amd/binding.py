@@ -1,0 +1,297 @@
+"""ctypes binding of libpfk (argument marshalling only).
+
+Names follow the C ABI of include/pfk.h.  Device vectors are torch tensors of
+dtype float64 on a HIP device; host arrays are numpy float64.  Nothing here
+computes: every operation is a call into the library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "libpfk.so")
+
+FCG, PIPEFCG, GCR, PIPEGCR, FGMRES, PIPEFGMRES = range(6)
+METHODS = {"fcg": FCG, "pipefcg": PIPEFCG, "gcr": GCR, "pipegcr": PIPEGCR,
+           "fgmres": FGMRES, "pipefgmres": PIPEFGMRES}
+PC_NONE, PC_JACOBI, PC_JACOBI_PCG, PC_JACOBI_GMRES, PC_BLOCK_JACOBI_PCG = range(5)
+PC_KINDS = {"none": PC_NONE, "jacobi": PC_JACOBI, "jacobi_pcg": PC_JACOBI_PCG,
+            "jacobi_gmres": PC_JACOBI_GMRES, "block_jacobi_pcg": PC_BLOCK_JACOBI_PCG}
+FP64, FP32_BF16COEF = 0, 1
+
+STATUS_NAMES = {0: "ok", 1: "not_converged", -1: "err_arg", -2: "err_oom", -3: "err_hip",
+                -4: "err_nonfinite", -5: "err_breakdown"}
+
+# every symbol include/pfk.h declares
+EXPORTED = [
+    "pfk_default_opts", "pfk_operator_create", "pfk_operator_destroy", "pfk_operator_size",
+    "pfk_operator_apply", "pfk_operator_diag_inv", "pfk_precond_create", "pfk_precond_destroy",
+    "pfk_precond_apply", "pfk_workspace_bytes", "pfk_solve", "pfk_session_create",
+    "pfk_session_start", "pfk_session_iterate", "pfk_session_sync", "pfk_session_destroy",
+    "pfk_estimate_sigma", "pfk_last_error",
+]
+
+
+class PfkError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("truncation", C.c_int), ("shift_sigma", C.c_double), ("graph_iters", C.c_int),
+                ("use_graph", C.c_int), ("host_sync", C.c_int), ("max_restarts", C.c_int),
+                ("force_breakdown_at", C.c_int)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("restarts", C.c_int), ("converged", C.c_int),
+                ("status", C.c_int), ("true_rel_resid", C.c_double),
+                ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int), ("history_len", C.c_int)]
+
+
+@dataclass
+class SolveInfo:
+    status: int
+    iterations: int
+    restarts: int
+    converged: bool
+    true_rel_resid: float
+    history: np.ndarray
+
+    @property
+    def status_name(self) -> str:
+        return STATUS_NAMES.get(self.status, str(self.status))
+
+
+_lib_handle = None
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Load libpfk.so (raises if it has not been built)."""
+    global _lib_handle
+    if _lib_handle is not None:
+        return _lib_handle
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_1511_07226_amd.build`")
+    L = C.CDLL(_LIB_PATH)
+    vp, i64p = C.c_void_p, C.POINTER(C.c_int64)
+    sig = {
+        "pfk_default_opts": (None, [C.POINTER(SolveOpts)]),
+        "pfk_operator_create": (C.c_int, [C.c_int, i64p, vp, vp, C.c_int, C.POINTER(vp)]),
+        "pfk_operator_destroy": (None, [vp]),
+        "pfk_operator_size": (C.c_int64, [vp]),
+        "pfk_operator_apply": (C.c_int, [vp, vp, vp, vp]),
+        "pfk_operator_diag_inv": (C.c_int, [vp, vp, vp]),
+        "pfk_precond_create": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(vp)]),
+        "pfk_precond_destroy": (None, [vp]),
+        "pfk_precond_apply": (C.c_int, [vp, vp, vp, vp]),
+        "pfk_workspace_bytes": (C.c_size_t, [vp, vp, C.c_int, C.c_int, C.c_int]),
+        "pfk_solve": (C.c_int, [vp, vp, C.c_int, vp, vp, C.c_double, C.c_int, C.c_int, vp, C.c_size_t,
+                                vp, C.POINTER(SolveOpts), C.POINTER(_Info)]),
+        "pfk_session_create": (C.c_int, [vp, vp, C.c_int, vp, vp, C.c_double, C.c_int, C.c_int, vp,
+                                         C.c_size_t, vp, C.POINTER(SolveOpts), C.POINTER(vp)]),
+        "pfk_session_start": (C.c_int, [vp]),
+        "pfk_session_iterate": (C.c_int, [vp, C.c_int]),
+        "pfk_session_sync": (C.c_int, [vp, C.POINTER(_Info)]),
+        "pfk_session_destroy": (None, [vp]),
+        "pfk_estimate_sigma": (C.c_int, [vp, vp, C.c_int, C.POINTER(C.c_double), vp]),
+        "pfk_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib_handle = L
+    return L
+
+
+def _check(code: int, allow_positive: bool = False) -> int:
+    if code < 0 or (code > 0 and not allow_positive):
+        raise PfkError(code, lib().pfk_last_error().decode())
+    return code
+
+
+def _stream_ptr(stream) -> int | None:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _dev_ptr(t, N: int | None = None, name: str = "vector") -> int:
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float64 torch tensor on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if N is not None and t.numel() != N:
+        raise ValueError(f"{name} has {t.numel()} values, expected {N}")
+    return t.data_ptr()
+
+
+def default_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    lib().pfk_default_opts(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Operator:
+    """A = -div(eta grad .) [+ upwind div(v .)] on n^dim interior nodes."""
+
+    def __init__(self, dim: int, n: int, eta: np.ndarray, vel: np.ndarray | None = None):
+        eta = np.ascontiguousarray(eta, dtype=np.float64)
+        if eta.size != (n + 2) ** dim:
+            raise ValueError("eta must hold (n+2)^dim values")
+        nn = (C.c_int64 * 3)(n, n, n if dim == 3 else 1)
+        velp = None
+        if vel is not None:
+            vel = np.ascontiguousarray(vel, dtype=np.float64)
+            if vel.size != 3 * (n + 2) ** 3:
+                raise ValueError("vel must hold 3*(n+2)^3 values")
+            velp = vel.ctypes.data
+        h = C.c_void_p()
+        _check(lib().pfk_operator_create(dim, nn, eta.ctypes.data, velp, 0, C.byref(h)))
+        self._h = h
+        self.dim, self.n = dim, n
+        self.N = int(lib().pfk_operator_size(h))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib_handle is not None:
+            _lib_handle.pfk_operator_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def apply(self, x, y=None, stream=None):
+        import torch
+        if y is None:
+            y = torch.empty_like(x)
+        _check(lib().pfk_operator_apply(self._h, _dev_ptr(x, self.N, "x"), _dev_ptr(y, self.N, "y"),
+                                        _stream_ptr(stream)))
+        return y
+
+    def diag_inv(self, stream=None):
+        import torch
+        d = torch.empty(self.N, dtype=torch.float64, device="cuda")
+        _check(lib().pfk_operator_diag_inv(self._h, d.data_ptr(), _stream_ptr(stream)))
+        return d
+
+
+class Precond:
+    """Flexible preconditioner B of the given kind on operator A."""
+
+    def __init__(self, A: Operator, kind: str = "jacobi_pcg", inner_its: int = 5,
+                 precision: int = FP64, block: int = 8):
+        h = C.c_void_p()
+        _check(lib().pfk_precond_create(A.handle, PC_KINDS[kind], inner_its, precision, block, C.byref(h)))
+        self._h = h
+        self.A = A
+        self.kind, self.inner_its, self.precision, self.block = kind, inner_its, precision, block
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib_handle is not None:
+            _lib_handle.pfk_precond_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def apply(self, v, y=None, stream=None):
+        import torch
+        if y is None:
+            y = torch.empty_like(v)
+        _check(lib().pfk_precond_apply(self._h, _dev_ptr(v, self.A.N, "v"), _dev_ptr(y, self.A.N, "y"),
+                                       _stream_ptr(stream)))
+        return y
+
+
+def workspace_bytes(A: Operator, B: Precond, method: str, mmax: int, maxit: int) -> int:
+    return int(lib().pfk_workspace_bytes(A.handle, B.handle, METHODS[method], mmax, maxit))
+
+
+def _info_struct(cap: int):
+    info = _Info()
+    hist = np.zeros(max(cap, 1), dtype=np.float64)
+    info.history = hist.ctypes.data_as(C.POINTER(C.c_double))
+    info.history_cap = cap
+    return info, hist
+
+
+def _to_info(code: int, info: _Info, hist: np.ndarray) -> SolveInfo:
+    return SolveInfo(code, info.iterations, info.restarts, bool(info.converged), info.true_rel_resid,
+                     hist[: info.history_len].copy())
+
+
+def solve(A: Operator, B: Precond, method: str, b, x, rtol: float = 1e-8, maxit: int = 500,
+          mmax: int = 30, workspace=None, stream=None, **opts) -> SolveInfo:
+    """Solve A x = b in place on x (device float64 tensors).  Returns SolveInfo."""
+    o = default_opts(**opts)
+    info, hist = _info_struct(maxit + 1)
+    wsp, wsb = (None, 0)
+    if workspace is not None:
+        wsp, wsb = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    code = lib().pfk_solve(A.handle, B.handle, METHODS[method], _dev_ptr(b, A.N, "b"), _dev_ptr(x, A.N, "x"),
+                           float(rtol), int(maxit), int(mmax), wsp, wsb, _stream_ptr(stream), C.byref(o),
+                           C.byref(info))
+    _check(code, allow_positive=True)
+    return _to_info(code, info, hist)
+
+
+class Session:
+    """Asynchronous solve: start(), iterate(k), sync()."""
+
+    def __init__(self, A: Operator, B: Precond, method: str, b, x, rtol: float = 1e-8, maxit: int = 500,
+                 mmax: int = 30, workspace=None, stream=None, **opts):
+        self.A, self.B, self.b, self.x = A, B, b, x
+        self.maxit = maxit
+        o = default_opts(**opts)
+        wsp, wsb = (None, 0)
+        if workspace is not None:
+            wsp, wsb = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+        h = C.c_void_p()
+        _check(lib().pfk_session_create(A.handle, B.handle, METHODS[method], _dev_ptr(b, A.N, "b"),
+                                        _dev_ptr(x, A.N, "x"), float(rtol), int(maxit), int(mmax), wsp, wsb,
+                                        _stream_ptr(stream), C.byref(o), C.byref(h)))
+        self._h = h
+        self._ws = workspace
+
+    def start(self):
+        _check(lib().pfk_session_start(self._h))
+
+    def iterate(self, iters: int):
+        _check(lib().pfk_session_iterate(self._h, int(iters)))
+
+    def sync(self) -> SolveInfo:
+        info, hist = _info_struct(self.maxit + 1)
+        code = lib().pfk_session_sync(self._h, C.byref(info))
+        _check(code, allow_positive=True)
+        return _to_info(code, info, hist)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().pfk_session_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

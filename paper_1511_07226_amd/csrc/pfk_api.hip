@@ -1,0 +1,769 @@
+// C ABI of libpfk (see include/pfk.h): operators, preconditioners, sessions
+// and the host driver that enqueues the kernels of one solve on two HIP
+// streams, captured into hipGraphs.
+//
+// Stream plan of one pipelined iteration (PIPEFCG):
+//
+//   s1: update(j) --fork--> PC kernels (v = w - r) --> m = u + B(v), n = A m --join--> update(j+1)
+//   s2:             \-----> reduction finish + scalar recurrences -----------/
+//
+// The reduction of iteration j+1 is produced by update(j) as per-workgroup
+// partial sums; finishing it (and computing beta, eta, alpha, the test) runs
+// on s2 while s1 applies B and A -- the single-GPU form of the paper's
+// non-blocking all-reduce overlapped with the preconditioner and operator.
+// The unpipelined methods run the same kernels in one stream with each
+// reduction consumed right after it is produced.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pfk.h"
+#include "pfk_cg.hpp"
+
+using namespace pfk;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(PFK_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+extern "C" const char* pfk_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// helper kernels
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+k_dinv(Grid g, StencilGeom sg, double* __restrict__ dinv) {
+  // D_ii is the stencil applied to the unit vector at i, read at i.
+  auto Z = [&](long long) { return 0.0; };
+  for_tile_nodes(g, sg, [&](int i, int j, int k, long long idx) {
+    dinv[idx] = 1.0 / stencil_at(g, i, j, k, idx, 1.0, Z);
+  });
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_dot(long long N, const double* __restrict__ a, const double* __restrict__ b, double* part) {
+  double acc[1] = {0.0};
+  for (long long e = gtid(); e < N; e += gstride()) acc[0] += a[e] * b[e];
+  block_partials<1>(acc, 1, part, gridDim.x);
+}
+
+// tol = rtol*||b||; with b = 0 the solve is finished (x is zeroed separately).
+__global__ void __launch_bounds__(kBlock)
+k_setup_tol(const double* part, int P, double rtol, SolveState* st, double* hist) {
+  const double bb = block_sum_column(part, P, 0);
+  if (threadIdx.x != 0) return;
+  st->bnorm = sqrt(bb);
+  st->tol = rtol * st->bnorm;
+  if (bb == 0.0) {
+    st->bzero = 1;
+    st->status = kDone;
+    hist[0] = 0.0;
+    st->hist_started = 1;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_zero_if_done(long long N, double* __restrict__ x, const SolveState* st) {
+  if (!st->bzero) return;
+  for (long long e = gtid(); e < N; e += gstride()) x[e] = 0.0;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_pc_write(long long N, PcOutDesc pd, double* __restrict__ y, SolveState* st) {
+  if (read_status(st) != kRunning) return;
+  const PcOut pc = make_pc_out(pd, &st->pc);
+  for (long long e = gtid(); e < N; e += gstride()) y[e] = pc(e);
+}
+
+__global__ void k_set_running(SolveState* st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) st->status = kRunning;
+}
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+struct pfk_operator_s {
+  int dim = 0;
+  int64_t n[3] = {1, 1, 1};
+  long long N = 0;
+  double h = 0.0;
+  double* eta = nullptr;   // padded
+  double* vel = nullptr;   // 3 * padded or null
+  double* dinv = nullptr;  // N
+  long long npad = 0;
+  StencilGeom sg{};
+  int pv_blocks = 0;       // workgroups of pointwise kernels
+
+  Grid grid() const {
+    Grid g;
+    g.dim = dim;
+    g.nx = (int)n[0];
+    g.ny = (int)n[1];
+    g.nz = dim == 3 ? (int)n[2] : 1;
+    g.N = N;
+    g.sy = n[0] + 2;
+    g.sz = (n[0] + 2) * (n[1] + 2);
+    g.vstride = npad;
+    g.h2inv = 1.0 / (h * h);
+    g.hinv = 1.0 / h;
+    g.eta = eta;
+    g.vel = vel;
+    return g;
+  }
+};
+
+struct pfk_precond_s {
+  pfk_operator A = nullptr;
+  int kind = 0;
+  int k = 1;
+  int prec = 0;
+  int block = 8;
+  // private buffers for pfk_precond_apply
+  char* scratch = nullptr;
+  size_t scratch_bytes = 0;
+};
+
+static StencilGeom make_geom(int dim, int nx, int ny, int nz) {
+  StencilGeom sg;
+  sg.tiles_x = (nx + kTileX - 1) / kTileX;
+  sg.tiles_y = (ny + kTileY - 1) / kTileY;
+  const int tiles = sg.tiles_x * sg.tiles_y;
+  const int target = 2048;
+  int chunks = dim == 3 ? std::max(1, std::min(nz, (target + tiles - 1) / tiles)) : 1;
+  sg.zc = (nz + chunks - 1) / chunks;
+  sg.zchunks = (nz + sg.zc - 1) / sg.zc;
+  return sg;
+}
+
+static int pointwise_blocks(long long N) {
+  long long b = (N + kBlock - 1) / kBlock;
+  return (int)std::max<long long>(1, std::min<long long>(b, 2048));
+}
+
+extern "C" void pfk_default_opts(pfk_solve_opts* o) {
+  if (!o) return;
+  o->truncation = 0;
+  o->shift_sigma = NAN;
+  o->graph_iters = 8;
+  o->use_graph = 1;
+  o->host_sync = 0;
+  o->max_restarts = 10;
+  o->force_breakdown_at = -1;
+}
+
+extern "C" int pfk_operator_create(int dim, const int64_t n[3], const double* eta, const double* face_vel,
+                                   int ptr_is_device, pfk_operator* out) {
+  if (!out) return fail(PFK_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (dim != 2 && dim != 3) return fail(PFK_ERR_ARG, "dim must be 2 or 3");
+  if (!n || !eta) return fail(PFK_ERR_ARG, "n and eta are required");
+  for (int a = 0; a < dim; ++a)
+    if (n[a] < 1 || n[a] > 4096) return fail(PFK_ERR_ARG, "n out of range 1..4096");
+  for (int a = 1; a < dim; ++a)
+    if (n[a] != n[0]) return fail(PFK_ERR_ARG, "the grid must have the same n on every axis");
+  if (face_vel && dim != 3) return fail(PFK_ERR_ARG, "face velocities are 3D only");
+  auto* A = new (std::nothrow) pfk_operator_s();
+  if (!A) return fail(PFK_ERR_OOM, "host allocation");
+  A->dim = dim;
+  A->n[0] = n[0];
+  A->n[1] = n[1];
+  A->n[2] = dim == 3 ? n[2] : 1;
+  A->N = A->n[0] * A->n[1] * A->n[2];
+  A->h = 1.0 / (double)(n[0] + 1);
+  A->npad = (n[0] + 2) * (n[1] + 2) * (dim == 3 ? (n[2] + 2) : 1);
+  A->sg = make_geom(dim, (int)A->n[0], (int)A->n[1], (int)A->n[2]);
+  A->pv_blocks = pointwise_blocks(A->N);
+  const hipMemcpyKind kind = ptr_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  // validate eta > 0 (host copy when given device memory)
+  std::vector<double> heta((size_t)A->npad);
+  if (hipMemcpy(heta.data(), eta, sizeof(double) * A->npad,
+                ptr_is_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost) != hipSuccess) {
+    delete A;
+    return fail(PFK_ERR_HIP, "copying eta");
+  }
+  for (double v : heta)
+    if (!(v > 0.0) || !std::isfinite(v)) {
+      delete A;
+      return fail(PFK_ERR_ARG, "eta must be finite and positive");
+    }
+  if (hipMalloc(&A->eta, sizeof(double) * A->npad) != hipSuccess ||
+      hipMalloc(&A->dinv, sizeof(double) * A->N) != hipSuccess ||
+      (face_vel && hipMalloc(&A->vel, 3 * sizeof(double) * A->npad) != hipSuccess)) {
+    pfk_operator_destroy(A);
+    return fail(PFK_ERR_OOM, "device allocation for the operator");
+  }
+  if (hipMemcpy(A->eta, eta, sizeof(double) * A->npad, kind) != hipSuccess ||
+      (face_vel && hipMemcpy(A->vel, face_vel, 3 * sizeof(double) * A->npad, kind) != hipSuccess)) {
+    pfk_operator_destroy(A);
+    return fail(PFK_ERR_HIP, "copying coefficients");
+  }
+  hipLaunchKernelGGL(k_dinv, dim3(A->sg.blocks()), dim3(kBlock), 0, 0, A->grid(), A->sg, A->dinv);
+  if (hipDeviceSynchronize() != hipSuccess) {
+    pfk_operator_destroy(A);
+    return fail(PFK_ERR_HIP, "computing the diagonal");
+  }
+  *out = A;
+  return PFK_OK;
+}
+
+extern "C" void pfk_operator_destroy(pfk_operator A) {
+  if (!A) return;
+  if (A->eta) (void)hipFree(A->eta);
+  if (A->vel) (void)hipFree(A->vel);
+  if (A->dinv) (void)hipFree(A->dinv);
+  delete A;
+}
+
+extern "C" int64_t pfk_operator_size(pfk_operator A) { return A ? A->N : 0; }
+
+extern "C" int pfk_operator_apply(pfk_operator A, const double* x, double* y, void* stream) {
+  if (!A || !x || !y) return fail(PFK_ERR_ARG, "null argument");
+  hipLaunchKernelGGL(k_apply, dim3(A->sg.blocks()), dim3(kBlock), 0, (hipStream_t)stream, A->grid(), A->sg,
+                     x, y);
+  HIPCHK(hipGetLastError());
+  return PFK_OK;
+}
+
+extern "C" int pfk_operator_diag_inv(pfk_operator A, double* dinv, void* stream) {
+  if (!A || !dinv) return fail(PFK_ERR_ARG, "null argument");
+  HIPCHK(hipMemcpyAsync(dinv, A->dinv, sizeof(double) * A->N, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return PFK_OK;
+}
+
+extern "C" int pfk_precond_create(pfk_operator A, pfk_pc_kind kind, int inner_its, pfk_precision prec,
+                                  int block, pfk_precond* out) {
+  if (!out || !A) return fail(PFK_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (kind < PFK_PC_NONE || kind > PFK_PC_BLOCK_JACOBI_PCG) return fail(PFK_ERR_ARG, "unknown preconditioner");
+  if ((kind == PFK_PC_JACOBI_PCG || kind == PFK_PC_JACOBI_GMRES || kind == PFK_PC_BLOCK_JACOBI_PCG) &&
+      (inner_its < 1 || inner_its > kMaxInner))
+    return fail(PFK_ERR_ARG, "inner_its must be 1..32");
+  if (prec != PFK_FP64 && prec != PFK_FP32_BF16COEF) return fail(PFK_ERR_ARG, "unknown precision");
+  if (kind == PFK_PC_JACOBI_GMRES || kind == PFK_PC_BLOCK_JACOBI_PCG || prec != PFK_FP64)
+    return fail(PFK_ERR_ARG, "preconditioner kind/precision not available in this build");
+  auto* B = new (std::nothrow) pfk_precond_s();
+  if (!B) return fail(PFK_ERR_OOM, "host allocation");
+  B->A = A;
+  B->kind = kind;
+  B->k = (kind == PFK_PC_NONE || kind == PFK_PC_JACOBI) ? 1 : inner_its;
+  B->prec = prec;
+  B->block = block;
+  *out = B;
+  return PFK_OK;
+}
+
+extern "C" void pfk_precond_destroy(pfk_precond B) {
+  if (!B) return;
+  if (B->scratch) (void)hipFree(B->scratch);
+  delete B;
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+enum Vec { V_R, V_U, V_W, V_M, V_N, V_PC_P0, V_PC_P1, V_PC_Q, V_PC_RHO, V_PC_Y, V_TMP, V_COUNT };
+enum Win { W_P, W_S, W_Q, W_Z, W_COUNT };
+enum Part { PT_MAIN, PT_A, PT_B, PT_PC0, PT_PC1, PT_COUNT };
+
+struct Layout {
+  size_t state = 0, hist = 0;
+  size_t vec[V_COUNT] = {};
+  size_t win[W_COUNT] = {};
+  size_t part[PT_COUNT] = {};
+  long long ld = 0;
+  int nwin = 0;
+  size_t total = 0;
+};
+
+int windows_of(int method) {
+  switch (method) {
+    case PFK_FCG: return 2;
+    case PFK_PIPEFCG: return 4;
+    default: return 0;
+  }
+}
+
+Layout make_layout(const pfk_operator_s* A, int method, int mmax, int maxit) {
+  Layout L;
+  size_t off = 0;
+  L.state = off;
+  off = align_up(off + sizeof(SolveState));
+  L.hist = off;
+  off = align_up(off + sizeof(double) * (size_t)(maxit + 2));
+  L.ld = (A->N + 31) / 32 * 32;
+  const size_t vbytes = align_up(sizeof(double) * (size_t)L.ld);
+  for (int v = 0; v < V_COUNT; ++v) {
+    L.vec[v] = off;
+    off += vbytes;
+  }
+  L.nwin = windows_of(method);
+  for (int w = 0; w < W_COUNT; ++w) {
+    L.win[w] = off;
+    if (w < L.nwin) off += vbytes * (size_t)mmax;
+  }
+  const int P = std::max(A->sg.blocks(), A->pv_blocks);
+  const size_t pbytes = align_up(sizeof(double) * (size_t)P * (kNuMax + 4));
+  for (int p = 0; p < PT_COUNT; ++p) {
+    L.part[p] = off;
+    off += pbytes;
+  }
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+extern "C" size_t pfk_workspace_bytes(pfk_operator A, pfk_precond, pfk_method method, int mmax, int maxit) {
+  if (!A || mmax < 1 || mmax > kNuMax || maxit < 0) return 0;
+  return make_layout(A, method, mmax, maxit).total;
+}
+
+// ---------------------------------------------------------------------------
+// sessions
+// ---------------------------------------------------------------------------
+struct pfk_session_s {
+  pfk_operator A = nullptr;
+  pfk_precond B = nullptr;
+  int method = 0;
+  const double* b = nullptr;
+  double* x = nullptr;
+  double rtol = 0.0;
+  int maxit = 0, mmax = 0;
+  pfk_solve_opts opts{};
+  char* ws = nullptr;
+  bool ws_owned = false;
+  Layout L;
+  hipStream_t user = nullptr, s1 = nullptr, s2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_user = nullptr, ev_done = nullptr;
+  hipGraphExec_t g_start = nullptr, g_iter = nullptr;
+  SolveState* st = nullptr;
+  double* hist = nullptr;
+  SolveState* host_state = nullptr;   // pinned
+  int restarts = 0;
+
+  double* vec(int v) const { return (double*)(ws + L.vec[v]); }
+  Window win(int w) const { return Window{(double*)(ws + L.win[w]), L.ld}; }
+  double* part(int p) const { return (double*)(ws + L.part[p]); }
+  Grid grid() const { return A->grid(); }
+  int Ps() const { return A->sg.blocks(); }
+  int Pv() const { return A->pv_blocks; }
+};
+
+namespace {
+
+#define LAUNCH(kernel, blocks, stream, ...) \
+  hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kBlock), 0, stream, __VA_ARGS__)
+
+// Enqueue the inner solve B(v), v = c1*X1 + c2*X2; returns how the consumer
+// evaluates B(v).
+PcOutDesc enqueue_pc(pfk_session_s* S, hipStream_t s, const double* X1, double c1, const double* X2,
+                     double c2) {
+  const pfk_operator_s* A = S->A;
+  PcOutDesc d{};
+  d.kind = S->B->kind;
+  d.k = S->B->k;
+  d.X1 = X1; d.c1 = c1; d.X2 = X2; d.c2 = c2;
+  d.dinv = A->dinv;
+  if (d.kind != kPcJacobiPcg) return d;
+  const Grid g = S->grid();
+  double* pp[2] = {S->vec(V_PC_P0), S->vec(V_PC_P1)};
+  double* q = S->vec(V_PC_Q);
+  double* rho = S->vec(V_PC_RHO);
+  double* y = S->vec(V_PC_Y);
+  double* part[2] = {S->part(PT_PC0), S->part(PT_PC1)};
+  LAUNCH(k_pcg_a1, S->Ps(), s, g, A->sg, A->dinv, X1, c1, X2, c2, pp[0], q, part[0], S->st);
+  int t = 1, Pprev = S->Ps();
+  for (int j = 1; j < d.k; ++j) {
+    LAUNCH(k_pcg_b, S->Pv(), s, j, A->N, A->dinv, X1, c1, X2, c2, pp[(j - 1) & 1], q, rho, y,
+           part[(t - 1) & 1], Pprev, part[t & 1], S->st);
+    Pprev = S->Pv();
+    ++t;
+    LAUNCH(k_pcg_a, S->Ps(), s, j + 1, g, A->sg, A->dinv, rho, pp[(j - 1) & 1], pp[j & 1], q,
+           part[(t - 1) & 1], Pprev, part[t & 1], S->st);
+    Pprev = S->Ps();
+    ++t;
+  }
+  d.y = y;
+  d.pk = pp[(d.k - 1) & 1];
+  d.part = part[(t - 1) & 1];
+  d.P = Pprev;
+  return d;
+}
+
+void enqueue_pipefcg_update(pfk_session_s* S, hipStream_t s) {
+  LAUNCH(k_pipefcg_update, S->Pv(), s, S->A->N, S->win(W_P), S->win(W_S), S->win(W_Q), S->win(W_Z),
+         S->x, S->vec(V_R), S->vec(V_U), S->vec(V_W), S->vec(V_M), S->vec(V_N), S->part(PT_MAIN), S->st);
+}
+
+void enqueue_fcg_dots(pfk_session_s* S, hipStream_t s, int init, const PcOutDesc& pd) {
+  LAUNCH(k_fcg_dots, S->Pv(), s, S->A->N, init, pd, S->win(W_S), S->vec(V_R), S->vec(V_U),
+         S->part(PT_MAIN), S->st);
+}
+
+void enqueue_fcg_maxpy(pfk_session_s* S, hipStream_t s) {
+  LAUNCH(k_fcg_maxpy, S->Pv(), s, S->A->N, S->win(W_P), S->vec(V_U), S->st);
+}
+
+// FCG: the part of an iteration after x, r have been updated, also used for
+// the start-up (init = 1): u = B(r), reduction 1, p = u + sum beta p,
+// s = A p, reduction 2.
+void enqueue_fcg_body(pfk_session_s* S, hipStream_t s, int init) {
+  PcOutDesc pd = enqueue_pc(S, s, S->vec(V_R), 1.0, nullptr, 0.0);
+  enqueue_fcg_dots(S, s, init, pd);
+  LAUNCH(k_fcg_scalars1, 1, s, init, S->part(PT_MAIN), S->Pv(), S->st, S->hist);
+  enqueue_fcg_maxpy(S, s);
+  LAUNCH(k_fcg_apply, S->Ps(), s, S->grid(), S->A->sg, S->win(W_P), S->win(W_S), S->part(PT_A), S->st);
+  LAUNCH(k_fcg_scalars2, 1, s, init, S->part(PT_A), S->Ps(), S->st);
+}
+
+// Start (or restart) from the current x.
+void enqueue_start(pfk_session_s* S, hipStream_t s) {
+  const pfk_operator_s* A = S->A;
+  const Grid g = S->grid();
+  LAUNCH(k_restart, 1, s, S->st);
+  LAUNCH(k_residual, S->Ps(), s, g, A->sg, S->b, (const double*)S->x, S->vec(V_R), S->part(PT_A));
+  switch (S->method) {
+    case PFK_FCG:
+      LAUNCH(k_init_test, 1, s, S->part(PT_A), S->Ps(), S->st, S->hist);
+      enqueue_fcg_body(S, s, 1);
+      break;
+    case PFK_PIPEFCG: {
+      // u_0 = B(r_0), w_0 = A u_0, gamma_0 = <u_0,r_0>, delta_0 = <u_0,w_0>
+      PcOutDesc pd = enqueue_pc(S, s, S->vec(V_R), 1.0, nullptr, 0.0);
+      LAUNCH(k_apply_pc_out, S->Ps(), s, g, A->sg, pd, (const double*)nullptr, 0.0, S->vec(V_U), S->vec(V_W), 1,
+             (const double*)S->vec(V_R), S->part(PT_B), S->st);
+      // m_0 = B(w_0), n_0 = A m_0
+      pd = enqueue_pc(S, s, S->vec(V_W), 1.0, nullptr, 0.0);
+      LAUNCH(k_apply_pc_out, S->Ps(), s, g, A->sg, pd, (const double*)nullptr, 0.0, S->vec(V_M), S->vec(V_N), 0,
+             (const double*)nullptr, S->part(PT_B), S->st);
+      LAUNCH(k_pipefcg_init_scalars, 1, s, S->part(PT_A), S->Ps(), S->part(PT_B), S->Ps(), S->st, S->hist);
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+// One iteration.
+void enqueue_iteration(pfk_session_s* S) {
+  const pfk_operator_s* A = S->A;
+  hipStream_t s1 = S->s1, s2 = S->s2;
+  switch (S->method) {
+    case PFK_FCG:
+      LAUNCH(k_fcg_xr, S->Pv(), s1, A->N, S->win(W_P), S->win(W_S), S->x, S->vec(V_R), S->st);
+      enqueue_fcg_body(S, s1, 0);
+      break;
+    case PFK_PIPEFCG: {
+      enqueue_pipefcg_update(S, s1);
+      // fork: finish the reduction on s2 while s1 applies B and A
+      (void)hipEventRecord(S->ev_fork, s1);
+      (void)hipStreamWaitEvent(s2, S->ev_fork, 0);
+      LAUNCH(k_pipefcg_scalars, 1, s2, S->part(PT_MAIN), S->Pv(), S->st, S->hist);
+      (void)hipEventRecord(S->ev_join, s2);
+      PcOutDesc pd = enqueue_pc(S, s1, S->vec(V_W), 1.0, S->vec(V_R), -1.0);
+      LAUNCH(k_apply_pc_out, S->Ps(), s1, S->grid(), A->sg, pd, (const double*)S->vec(V_U), 1.0, S->vec(V_M),
+             S->vec(V_N), 0, (const double*)nullptr, S->part(PT_B), S->st);
+      (void)hipStreamWaitEvent(s1, S->ev_join, 0);
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+void enqueue_true_check(pfk_session_s* S, hipStream_t s) {
+  const pfk_operator_s* A = S->A;
+  LAUNCH(k_residual, S->Ps(), s, S->grid(), A->sg, S->b, (const double*)S->x, S->vec(V_R), S->part(PT_A));
+  LAUNCH(k_true_check, 1, s, S->part(PT_A), S->Ps(), S->st);
+}
+
+int capture(pfk_session_s* S, hipGraphExec_t* out, int what, int iters) {
+  hipGraph_t graph = nullptr;
+  HIPCHK(hipStreamBeginCapture(S->s1, hipStreamCaptureModeThreadLocal));
+  if (what == 0) {
+    enqueue_start(S, S->s1);
+  } else {
+    for (int i = 0; i < iters; ++i) enqueue_iteration(S);
+  }
+  HIPCHK(hipStreamEndCapture(S->s1, &graph));
+  hipError_t e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(PFK_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  return PFK_OK;
+}
+
+int launch_start(pfk_session_s* S) {
+  if (S->opts.use_graph) {
+    if (!S->g_start) {
+      int rc = capture(S, &S->g_start, 0, 0);
+      if (rc) return rc;
+    }
+    HIPCHK(hipGraphLaunch(S->g_start, S->s1));
+  } else {
+    enqueue_start(S, S->s1);
+  }
+  HIPCHK(hipGetLastError());
+  return PFK_OK;
+}
+
+int launch_iters(pfk_session_s* S, int iters) {
+  if (S->opts.use_graph) {
+    if (!S->g_iter) {
+      int rc = capture(S, &S->g_iter, 1, S->opts.graph_iters);
+      if (rc) return rc;
+    }
+    const int gi = S->opts.graph_iters;
+    for (int done = 0; done < iters; done += gi) HIPCHK(hipGraphLaunch(S->g_iter, S->s1));
+  } else {
+    for (int i = 0; i < iters; ++i) enqueue_iteration(S);
+  }
+  HIPCHK(hipGetLastError());
+  return PFK_OK;
+}
+
+int read_state(pfk_session_s* S) {
+  HIPCHK(hipMemcpyAsync(S->host_state, S->st, sizeof(SolveState), hipMemcpyDeviceToHost, S->s1));
+  HIPCHK(hipStreamSynchronize(S->s1));
+  return PFK_OK;
+}
+
+}  // namespace
+
+extern "C" int pfk_session_create(pfk_operator A, pfk_precond B, pfk_method method, const double* b, double* x,
+                                  double rtol, int maxit, int mmax, void* workspace, size_t ws_bytes,
+                                  void* stream, const pfk_solve_opts* opts, pfk_session* out) {
+  if (!out) return fail(PFK_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!A || !B || !b || !x) return fail(PFK_ERR_ARG, "null argument");
+  if (B->A != A) return fail(PFK_ERR_ARG, "preconditioner was made for another operator");
+  if (method != PFK_FCG && method != PFK_PIPEFCG)
+    return fail(PFK_ERR_ARG, "method not available in this build");
+  if (mmax < 1 || mmax > kNuMax) return fail(PFK_ERR_ARG, "mmax must be 1..64");
+  if (maxit < 0) return fail(PFK_ERR_ARG, "maxit must be >= 0");
+  if (!(rtol >= 0.0)) return fail(PFK_ERR_ARG, "rtol must be >= 0");
+  auto* S = new (std::nothrow) pfk_session_s();
+  if (!S) return fail(PFK_ERR_OOM, "host allocation");
+  S->A = A; S->B = B; S->method = method; S->b = b; S->x = x; S->rtol = rtol;
+  S->maxit = maxit; S->mmax = mmax;
+  pfk_default_opts(&S->opts);
+  if (opts) S->opts = *opts;
+  if (S->opts.graph_iters < 1) S->opts.graph_iters = 1;
+  if (S->opts.truncation < 0 || S->opts.truncation > 2) {
+    delete S;
+    return fail(PFK_ERR_ARG, "truncation must be 0, 1 or 2");
+  }
+  S->L = make_layout(A, method, mmax, maxit);
+  if (workspace) {
+    if (ws_bytes < S->L.total) {
+      delete S;
+      return fail(PFK_ERR_ARG, "workspace too small: need " + std::to_string(S->L.total) + " bytes");
+    }
+    S->ws = (char*)workspace;
+  } else {
+    if (hipMalloc(&S->ws, S->L.total) != hipSuccess) {
+      delete S;
+      return fail(PFK_ERR_OOM, "workspace allocation of " + std::to_string(S->L.total) + " bytes");
+    }
+    S->ws_owned = true;
+  }
+  S->st = (SolveState*)(S->ws + S->L.state);
+  S->hist = (double*)(S->ws + S->L.hist);
+  S->user = (hipStream_t)stream;
+  if (hipStreamCreateWithFlags(&S->s1, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&S->s2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&S->ev_join, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&S->ev_user, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&S->ev_done, hipEventDisableTiming) != hipSuccess ||
+      hipHostMalloc(&S->host_state, sizeof(SolveState), hipHostMallocDefault) != hipSuccess) {
+    pfk_session_destroy(S);
+    return fail(PFK_ERR_HIP, "creating streams/events");
+  }
+  *out = S;
+  return PFK_OK;
+}
+
+extern "C" void pfk_session_destroy(pfk_session S) {
+  if (!S) return;
+  if (S->s1) (void)hipStreamSynchronize(S->s1);
+  if (S->g_start) (void)hipGraphExecDestroy(S->g_start);
+  if (S->g_iter) (void)hipGraphExecDestroy(S->g_iter);
+  if (S->ev_fork) (void)hipEventDestroy(S->ev_fork);
+  if (S->ev_join) (void)hipEventDestroy(S->ev_join);
+  if (S->ev_user) (void)hipEventDestroy(S->ev_user);
+  if (S->ev_done) (void)hipEventDestroy(S->ev_done);
+  if (S->s1) (void)hipStreamDestroy(S->s1);
+  if (S->s2) (void)hipStreamDestroy(S->s2);
+  if (S->host_state) (void)hipHostFree(S->host_state);
+  if (S->ws_owned && S->ws) (void)hipFree(S->ws);
+  delete S;
+}
+
+extern "C" int pfk_session_start(pfk_session S) {
+  if (!S) return fail(PFK_ERR_ARG, "null session");
+  // order after the caller's queued work
+  HIPCHK(hipEventRecord(S->ev_user, S->user));
+  HIPCHK(hipStreamWaitEvent(S->s1, S->ev_user, 0));
+  const double sigma = std::isnan(S->opts.shift_sigma) ? 0.0 : S->opts.shift_sigma;
+  LAUNCH(k_setup, 1, S->s1, S->st, 0.0, S->maxit, S->mmax, S->opts.truncation, S->opts.force_breakdown_at,
+         sigma);
+  LAUNCH(k_dot, S->Pv(), S->s1, S->A->N, S->b, S->b, S->part(PT_A));
+  LAUNCH(k_setup_tol, 1, S->s1, S->part(PT_A), S->Pv(), S->rtol, S->st, S->hist);
+  LAUNCH(k_zero_if_done, S->Pv(), S->s1, S->A->N, S->x, S->st);
+  S->restarts = 0;
+  int rc = launch_start(S);
+  if (rc) return rc;
+  HIPCHK(hipEventRecord(S->ev_done, S->s1));
+  HIPCHK(hipStreamWaitEvent(S->user, S->ev_done, 0));
+  return PFK_OK;
+}
+
+extern "C" int pfk_session_iterate(pfk_session S, int iters) {
+  if (!S) return fail(PFK_ERR_ARG, "null session");
+  if (iters <= 0) return PFK_OK;
+  HIPCHK(hipEventRecord(S->ev_user, S->user));
+  HIPCHK(hipStreamWaitEvent(S->s1, S->ev_user, 0));
+  int rc = launch_iters(S, iters);
+  if (rc) return rc;
+  HIPCHK(hipEventRecord(S->ev_done, S->s1));
+  HIPCHK(hipStreamWaitEvent(S->user, S->ev_done, 0));
+  return PFK_OK;
+}
+
+static int fill_info(pfk_session_s* S, int rc, pfk_solve_info* info) {
+  if (!info) return rc;
+  const SolveState& h = *S->host_state;
+  info->iterations = h.it;
+  info->restarts = S->restarts;
+  info->status = rc;
+  double bn = 0.0;
+  info->converged = (h.status == kDone) ? 1 : 0;
+  bn = h.bnorm;
+  info->true_rel_resid = bn > 0.0 ? h.true_res / bn : 0.0;
+  info->history_len = 0;
+  if (info->history && info->history_cap > 0) {
+    const int n = std::min(info->history_cap, h.hist_started ? h.it + 1 : 0);
+    if (n > 0 && hipMemcpy(info->history, S->hist, sizeof(double) * n, hipMemcpyDeviceToHost) == hipSuccess)
+      info->history_len = n;
+  }
+  return rc;
+}
+
+extern "C" int pfk_session_sync(pfk_session S, pfk_solve_info* info) {
+  if (!S) return fail(PFK_ERR_ARG, "null session");
+  int rc = read_state(S);
+  if (rc) return rc;
+  const int status = S->host_state->status;
+  int code = PFK_OK;
+  if (status == kRunning || status == kMaxit || status == kCycleEnd) code = PFK_NOT_CONVERGED;
+  if (status == kNonfinite) code = PFK_ERR_NONFINITE;
+  if (status == kBreakdown0) code = PFK_ERR_BREAKDOWN;
+  if (status == kBreakdown || status == kGap || status == kConverged) code = PFK_NOT_CONVERGED;
+  return fill_info(S, code, info);
+}
+
+// The full solve: start, iterate in graph chunks, check the true residual on
+// convergence, restart on breakdown or residual gap.
+extern "C" int pfk_solve(pfk_operator A, pfk_precond B, pfk_method method, const double* b, double* x,
+                         double rtol, int maxit, int mmax, void* workspace, size_t ws_bytes, void* stream,
+                         const pfk_solve_opts* opts, pfk_solve_info* info) {
+  pfk_session S = nullptr;
+  int rc = pfk_session_create(A, B, method, b, x, rtol, maxit, mmax, workspace, ws_bytes, stream, opts, &S);
+  if (rc) return rc;
+  rc = pfk_session_start(S);
+  int code = PFK_NOT_CONVERGED;
+  const int max_restarts = S->opts.max_restarts;
+  while (rc == PFK_OK) {
+    rc = read_state(S);
+    if (rc) break;
+    const int status = S->host_state->status;
+    if (status == kRunning) {
+      rc = launch_iters(S, S->opts.graph_iters);
+      continue;
+    }
+    if (status == kConverged) {
+      enqueue_true_check(S, S->s1);
+      continue;
+    }
+    if (status == kDone) { code = PFK_OK; break; }
+    if (status == kMaxit) { code = PFK_NOT_CONVERGED; break; }
+    if (status == kNonfinite) { code = PFK_ERR_NONFINITE; break; }
+    if (status == kBreakdown0) { code = PFK_ERR_BREAKDOWN; break; }
+    if (status == kBreakdown || status == kGap) {
+      if (S->host_state->it >= S->maxit) { code = PFK_NOT_CONVERGED; break; }
+      if (++S->restarts > max_restarts) {
+        code = status == kBreakdown ? PFK_ERR_BREAKDOWN : PFK_NOT_CONVERGED;
+        break;
+      }
+      rc = launch_start(S);
+      continue;
+    }
+    code = PFK_NOT_CONVERGED;
+    break;
+  }
+  if (rc == PFK_OK) {
+    // the true residual at exit (also after maxit)
+    if (!S->host_state->bzero) enqueue_true_check(S, S->s1);
+    rc = read_state(S);
+  }
+  if (rc == PFK_OK) {
+    fill_info(S, code, info);
+    if (info) info->converged = (code == PFK_OK) ? 1 : 0;
+  } else if (info) {
+    info->status = rc;
+  }
+  (void)hipEventRecord(S->ev_done, S->s1);
+  (void)hipStreamWaitEvent(S->user, S->ev_done, 0);
+  pfk_session_destroy(S);
+  return rc ? rc : code;
+}
+
+extern "C" int pfk_precond_apply(pfk_precond B, const double* v, double* y, void* stream) {
+  if (!B || !v || !y) return fail(PFK_ERR_ARG, "null argument");
+  pfk_operator A = B->A;
+  Layout L = make_layout(A, PFK_FCG, 1, 1);
+  if (!B->scratch || B->scratch_bytes < L.total) {
+    if (B->scratch) (void)hipFree(B->scratch);
+    B->scratch = nullptr;
+    if (hipMalloc(&B->scratch, L.total) != hipSuccess) return fail(PFK_ERR_OOM, "preconditioner scratch");
+    B->scratch_bytes = L.total;
+  }
+  pfk_session_s S;
+  S.A = A; S.B = B; S.ws = B->scratch; S.L = L; S.mmax = 1;
+  S.st = (SolveState*)(S.ws + L.state);
+  hipStream_t s = (hipStream_t)stream;
+  LAUNCH(k_set_running, 1, s, S.st);
+  PcOutDesc pd = enqueue_pc(&S, s, v, 1.0, nullptr, 0.0);
+  LAUNCH(k_pc_write, A->pv_blocks, s, A->N, pd, y, S.st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return PFK_OK;
+}
+
+extern "C" int pfk_estimate_sigma(pfk_operator, pfk_precond, int, double*, void*) {
+  return fail(PFK_ERR_ARG, "not available in this build");
+}

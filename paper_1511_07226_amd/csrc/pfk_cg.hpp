@@ -1,0 +1,476 @@
+// Outer kernels of the CG family: FCG (Alg. 2) and PIPEFCG (Alg. 8), plus the
+// kernels every method shares (solve set-up, r = b - A x, the operator
+// applied to a combination of vectors, the true-residual check).
+//
+// Direction windows are ring buffers: direction d (counted from the last
+// (re)start) lives in slot d mod nu_max of each window array, whose vectors
+// are `ld` doubles apart.  The scalar recurrences run in single-workgroup
+// kernels (k_*_scalars) that leave their results in SolveState; the vector
+// kernels read them there.  Every kernel returns at once when the solve is no
+// longer running, so iterations enqueued after convergence change nothing.
+#pragma once
+#include "pfk_pc.hpp"
+
+namespace pfk {
+
+struct Window {
+  double* base;
+  long long ld;
+  __device__ __forceinline__ double* slot(int s) const { return base + (long long)s * ld; }
+};
+
+// ---------------------------------------------------------------------------
+// Shared kernels
+// ---------------------------------------------------------------------------
+__global__ void k_setup(SolveState* st, double tol, int maxit, int nu_max, int trunc, int force_it,
+                        double sigma) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  st->status = kRunning;
+  st->it = 0;
+  st->j = 0;
+  st->nu_max = nu_max;
+  st->trunc = trunc;
+  st->maxit = maxit;
+  st->force_it = force_it;
+  st->hist_started = 0;
+  st->nu = 0;
+  st->tol = tol;
+  st->alpha = 0.0;
+  st->sigma = sigma;
+  st->true_res = 0.0;
+  st->col = 0;
+  st->bzero = 0;
+  st->bnorm = 0.0;
+}
+
+// Start (or restart) a cycle from the current x: the pipeline is flushed.
+__global__ void k_restart(SolveState* st) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  st->status = st->bzero ? kDone : kRunning;
+  st->j = 0;
+  st->nu = 0;
+  st->col = 0;
+}
+
+// r = b - A x, partial <r, r>.
+__global__ void __launch_bounds__(kBlock)
+k_residual(Grid g, StencilGeom sg, const double* __restrict__ b, const double* __restrict__ x,
+           double* __restrict__ r, double* part) {
+  double acc[1] = {0.0};
+  auto X = [&](long long t) { return x[t]; };
+  for_tile_nodes(g, sg, [&](int i, int j, int k, long long idx) {
+    const double rv = b[idx] - stencil_at(g, i, j, k, idx, x[idx], X);
+    r[idx] = rv;
+    acc[0] += rv * rv;
+  });
+  block_partials<1>(acc, 1, part, sg.blocks());
+}
+
+// y = A x (library entry point for operator checks).
+__global__ void __launch_bounds__(kBlock)
+k_apply(Grid g, StencilGeom sg, const double* __restrict__ x, double* __restrict__ y) {
+  auto X = [&](long long t) { return x[t]; };
+  for_tile_nodes(g, sg, [&](int i, int j, int k, long long idx) {
+    y[idx] = stencil_at(g, i, j, k, idx, x[idx], X);
+  });
+}
+
+// O = c3*X3 + B(v) at every node, N = A O.  With `dots`: partials <O, R>, <O, N>.
+// Used for u_0/w_0 and m_0/n_0 of PIPEFCG's start-up and for m_i, n_i in its
+// loop (m_i = u_i + B(w_i - r_i), n_i = A m_i).
+__global__ void __launch_bounds__(kBlock)
+k_apply_pc_out(Grid g, StencilGeom sg, PcOutDesc pd, const double* X3, double c3,
+               double* __restrict__ O, double* __restrict__ Nout,
+               int dots, const double* __restrict__ R, double* part, SolveState* st) {
+  if (read_status(st) != kRunning) return;
+  const PcOut pc = make_pc_out(pd, &st->pc);
+  auto M = [&](long long t) { double v = pc(t); if (X3 != nullptr) v += c3 * X3[t]; return v; };
+  double acc[2] = {0.0, 0.0};
+  for_tile_nodes(g, sg, [&](int i, int j, int k, long long idx) {
+    const double mc = M(idx);
+    const double nv = stencil_at(g, i, j, k, idx, mc, M);
+    O[idx] = mc;
+    Nout[idx] = nv;
+    if (dots) {
+      acc[0] += mc * R[idx];
+      acc[1] += mc * nv;
+    }
+  });
+  if (dots) block_partials<2>(acc, 2, part, sg.blocks());
+}
+
+// True-residual verdict after a recurred convergence: kDone or kGap.
+__global__ void __launch_bounds__(kBlock)
+k_true_check(const double* part, int P, SolveState* st) {
+  const double rr = block_sum_column(part, P, 0);
+  if (threadIdx.x == 0) {
+    const double res = sqrt(rr);
+    st->true_res = res;
+    st->status = (res <= st->tol) ? kDone : kGap;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// PIPEFCG
+// ---------------------------------------------------------------------------
+// Start-up scalars: history[0], the test on ||r_0||, eta_0 = delta_0, alpha_0.
+__global__ void __launch_bounds__(kBlock)
+k_pipefcg_init_scalars(const double* part_r, int P_r, const double* part_ud, int P_ud,
+                       SolveState* st, double* hist) {
+  if (read_status(st) != kRunning) return;
+  const double rr = block_sum_column(part_r, P_r, 0);
+  const double gamma = block_sum_column(part_ud, P_ud, 0);
+  const double delta = block_sum_column(part_ud, P_ud, 1);
+  if (threadIdx.x != 0) return;
+  const double res = sqrt(rr);
+  if (!st->hist_started) { hist[0] = res; st->hist_started = 1; }
+  if (!isfinite(res)) { st->status = kNonfinite; return; }
+  if (res <= st->tol) { st->status = kConverged; return; }
+  if (!(delta > 0.0) || !isfinite(delta)) { st->status = kBreakdown0; return; }
+  st->eta_ring[0] = delta;
+  st->alpha = gamma / delta;
+  st->j = 0;
+  st->nu = 0;
+  if (st->it >= st->maxit) st->status = kMaxit;
+}
+
+// One fused pass for direction j (= st->j):
+//   p_j = u_j + sum beta p_d,  s_j = w_j + sum beta s_d,
+//   q_j = m_j + sum beta q_d,  z_j = n_j + sum beta z_d      (written to slot j)
+//   x += alpha p_j, r -= alpha s_j, u -= alpha q_j, w -= alpha z_j
+// and the single reduction of iteration j+1 on the updated vectors:
+//   gamma = <u,r>, delta = <u,w>, rho = <r,r>, <u, s_d> for d in window(j+1).
+// The window dots reuse the s_d loads of the MAXPY.  Each thread owns two
+// nodes per step (coalesced across the wave); the per-direction dot is summed
+// over the wave at once and accumulated in LDS, so the register footprint
+// does not grow with the window.
+__global__ void __launch_bounds__(kBlock)
+k_pipefcg_update(long long N, Window P, Window S, Window Q, Window Z,
+                 double* __restrict__ x, double* __restrict__ r, double* __restrict__ u,
+                 double* __restrict__ w, const double* __restrict__ m, const double* __restrict__ n,
+                 double* part, const SolveState* st) {
+  if (read_status(st) != kRunning) return;
+  __shared__ double s_beta[kNuMax];
+  __shared__ long long s_off[kNuMax];
+  __shared__ double s_dot[kWaves][kNuMax + 4];
+  const int j = st->j;
+  const int numax = st->nu_max;
+  const int nu = trunc_nu(st->trunc, j, numax);         // window of this update
+  const int nu1 = trunc_nu(st->trunc, j + 1, numax);    // window of the next reduction
+  const int shift = 1 + nu - nu1;                       // first window entry the next dots keep
+  const double alpha = st->alpha;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int t = threadIdx.x; t < nu; t += kBlock) {
+    s_beta[t] = st->beta[t];
+    s_off[t] = (long long)((j - nu + t) % numax) * P.ld;
+  }
+  for (int t = threadIdx.x; t < kWaves * (kNuMax + 4); t += kBlock) (&s_dot[0][0])[t] = 0.0;
+  __syncthreads();
+  const long long ns = (long long)(j % numax) * P.ld;
+  double gam = 0.0, del = 0.0, rho = 0.0, dnew = 0.0;
+  const long long step = 2LL * gstride();
+  for (long long e0 = 2LL * blockIdx.x * kBlock + threadIdx.x; e0 < N; e0 += step) {
+    const long long e1 = e0 + kBlock;
+    const bool h1 = e1 < N;
+    const double u0 = u[e0], u1 = h1 ? u[e1] : 0.0;
+    const double w0 = w[e0], w1 = h1 ? w[e1] : 0.0;
+    double p0 = u0, p1 = u1;
+    double q0 = m[e0], q1 = h1 ? m[e1] : 0.0;
+    double z0 = n[e0], z1 = h1 ? n[e1] : 0.0;
+#pragma unroll 4
+    for (int t = 0; t < nu; ++t) {
+      const double b = s_beta[t];
+      const long long o = s_off[t];
+      p0 += b * P.base[o + e0];
+      q0 += b * Q.base[o + e0];
+      z0 += b * Z.base[o + e0];
+      if (h1) {
+        p1 += b * P.base[o + e1];
+        q1 += b * Q.base[o + e1];
+        z1 += b * Z.base[o + e1];
+      }
+    }
+    const double un0 = u0 - alpha * q0, un1 = u1 - alpha * q1;
+    const double wn0 = w0 - alpha * z0, wn1 = w1 - alpha * z1;
+    double s0 = w0, s1 = w1;
+#pragma unroll 4
+    for (int t = 0; t < nu; ++t) {
+      const double b = s_beta[t];
+      const long long o = s_off[t];
+      const double sd0 = S.base[o + e0];
+      const double sd1 = h1 ? S.base[o + e1] : 0.0;
+      s0 += b * sd0;
+      s1 += b * sd1;
+      if (t >= shift) {
+        const double d = wave_sum(un0 * sd0 + un1 * sd1);
+        if (lane == 0) s_dot[wid][t - shift] += d;
+      }
+    }
+    const double rn0 = r[e0] - alpha * s0;
+    x[e0] += alpha * p0;
+    P.base[ns + e0] = p0;
+    S.base[ns + e0] = s0;
+    Q.base[ns + e0] = q0;
+    Z.base[ns + e0] = z0;
+    u[e0] = un0;
+    w[e0] = wn0;
+    r[e0] = rn0;
+    gam += un0 * rn0;
+    del += un0 * wn0;
+    rho += rn0 * rn0;
+    dnew += un0 * s0;
+    if (h1) {
+      const double rn1 = r[e1] - alpha * s1;
+      x[e1] += alpha * p1;
+      P.base[ns + e1] = p1;
+      S.base[ns + e1] = s1;
+      Q.base[ns + e1] = q1;
+      Z.base[ns + e1] = z1;
+      u[e1] = un1;
+      w[e1] = wn1;
+      r[e1] = rn1;
+      gam += un1 * rn1;
+      del += un1 * wn1;
+      rho += rn1 * rn1;
+      dnew += un1 * s1;
+    }
+  }
+  // columns: gamma, delta, rho, then <u, s_d> for d = j+1-nu1 .. j (the last is s_j)
+  const int ncol = 3 + nu1;
+  {
+    const double a0 = wave_sum(gam), a1 = wave_sum(del), a2 = wave_sum(rho), a3 = wave_sum(dnew);
+    if (lane == 0) {
+      s_dot[wid][kNuMax] = a0;
+      s_dot[wid][kNuMax + 1] = a1;
+      s_dot[wid][kNuMax + 2] = a2;
+      s_dot[wid][nu1 - 1] = a3;
+    }
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncol; c += kBlock) {
+    const int src = c < 3 ? kNuMax + c : c - 3;
+    double acc = 0.0;
+#pragma unroll
+    for (int wv = 0; wv < kWaves; ++wv) acc += s_dot[wv][src];
+    part[(long long)c * gridDim.x + blockIdx.x] = acc;
+  }
+}
+
+// Scalars of iteration j+1 from the fused reduction: iteration count,
+// history, convergence test, beta_{j+1,d} = -<u,s_d>/eta_d,
+// eta_{j+1} = delta - sum beta^2 eta_d (breakdown if not positive), alpha.
+__global__ void __launch_bounds__(kBlock)
+k_pipefcg_scalars(const double* part, int P, SolveState* st, double* hist) {
+  __shared__ double col[kNuMax + 3];
+  if (read_status(st) != kRunning) return;
+  const int j1 = st->j + 1;
+  const int nu1 = trunc_nu(st->trunc, j1, st->nu_max);
+  for (int c = 0; c < 3 + nu1; ++c) {
+    const double v = block_sum_column(part, P, c);
+    if (threadIdx.x == 0) col[c] = v;
+  }
+  if (threadIdx.x != 0) return;
+  const int it = st->it + 1;
+  st->it = it;
+  st->j = j1;
+  const double res = sqrt(col[2]);
+  hist[it] = res;
+  if (!isfinite(res)) { st->status = kNonfinite; return; }
+  if (res <= st->tol) { st->status = kConverged; return; }
+  const int numax = st->nu_max;
+  double eta = col[1];
+  for (int t = 0; t < nu1; ++t) {
+    const int d = j1 - nu1 + t;
+    const double ed = st->eta_ring[d % numax];
+    const double b = -col[3 + t] / ed;
+    st->beta[t] = b;
+    eta -= b * b * ed;
+  }
+  st->nu = nu1;
+  st->eta_new = eta;
+  st->gamma = col[0];
+  const bool forced = (st->force_it == it);
+  if (forced) st->force_it = -1;
+  if (forced || !(eta > 0.0) || !isfinite(eta)) { st->status = kBreakdown; return; }
+  st->eta_ring[j1 % numax] = eta;
+  st->alpha = col[0] / eta;
+  if (it >= st->maxit) st->status = kMaxit;
+}
+
+// ---------------------------------------------------------------------------
+// FCG
+// ---------------------------------------------------------------------------
+// x += alpha p_j, r -= alpha s_j for the newest direction j = st->j.
+__global__ void __launch_bounds__(kBlock)
+k_fcg_xr(long long N, Window P, Window S, double* __restrict__ x, double* __restrict__ r,
+         const SolveState* st) {
+  if (read_status(st) != kRunning) return;
+  const int slot = st->j % st->nu_max;
+  const double alpha = st->alpha;
+  const double* p = P.slot(slot);
+  const double* s = S.slot(slot);
+  for (long long e = gtid(); e < N; e += gstride()) {
+    x[e] += alpha * p[e];
+    r[e] -= alpha * s[e];
+  }
+}
+
+// u = B(r) (finished from the inner solve's last step) and the first
+// reduction of iteration j+1: gamma = <u,r>, rho = <r,r>, <u, s_d> over the
+// window.  With `init` the window is empty (start-up, u_0 = B(r_0)).
+__global__ void __launch_bounds__(kBlock)
+k_fcg_dots(long long N, int init, PcOutDesc pd, Window S, const double* __restrict__ r,
+           double* __restrict__ uout, double* part, SolveState* st) {
+  if (read_status(st) != kRunning) return;
+  const PcOut pc = make_pc_out(pd, &st->pc);
+  __shared__ long long s_off[kNuMax];
+  __shared__ double s_dot[kWaves][kNuMax + 2];
+  const int j1 = st->j + 1;
+  const int numax = st->nu_max;
+  const int nu = init ? 0 : trunc_nu(st->trunc, j1, numax);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int t = threadIdx.x; t < nu; t += kBlock) s_off[t] = (long long)((j1 - nu + t) % numax) * S.ld;
+  for (int t = threadIdx.x; t < kWaves * (kNuMax + 2); t += kBlock) (&s_dot[0][0])[t] = 0.0;
+  __syncthreads();
+  double gam = 0.0, rho = 0.0;
+  const long long step = 2LL * gstride();
+  for (long long e0 = 2LL * blockIdx.x * kBlock + threadIdx.x; e0 < N; e0 += step) {
+    const long long e1 = e0 + kBlock;
+    const bool h1 = e1 < N;
+    const double u0 = pc(e0), u1 = h1 ? pc(e1) : 0.0;
+    const double r0 = r[e0], r1 = h1 ? r[e1] : 0.0;
+    uout[e0] = u0;
+    if (h1) uout[e1] = u1;
+    gam += u0 * r0 + u1 * r1;
+    rho += r0 * r0 + r1 * r1;
+#pragma unroll 4
+    for (int t = 0; t < nu; ++t) {
+      const long long o = s_off[t];
+      const double d = wave_sum(u0 * S.base[o + e0] + (h1 ? u1 * S.base[o + e1] : 0.0));
+      if (lane == 0) s_dot[wid][2 + t] += d;
+    }
+  }
+  {
+    const double a0 = wave_sum(gam), a1 = wave_sum(rho);
+    if (lane == 0) { s_dot[wid][0] = a0; s_dot[wid][1] = a1; }
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < 2 + nu; c += kBlock) {
+    double acc = 0.0;
+#pragma unroll
+    for (int wv = 0; wv < kWaves; ++wv) acc += s_dot[wv][c];
+    part[(long long)c * gridDim.x + blockIdx.x] = acc;
+  }
+}
+
+// First-reduction scalars: iteration count, history, test, beta.
+__global__ void __launch_bounds__(kBlock)
+k_fcg_scalars1(int init, const double* part, int P, SolveState* st, double* hist) {
+  __shared__ double col[kNuMax + 2];
+  if (read_status(st) != kRunning) return;
+  const int j1 = init ? 0 : st->j + 1;
+  const int nu = init ? 0 : trunc_nu(st->trunc, j1, st->nu_max);
+  for (int c = 0; c < 2 + nu; ++c) {
+    const double v = block_sum_column(part, P, c);
+    if (threadIdx.x == 0) col[c] = v;
+  }
+  if (threadIdx.x != 0) return;
+  st->gamma = col[0];
+  st->nu = nu;
+  st->j = j1;
+  if (init) return;
+  const int it = st->it + 1;
+  st->it = it;
+  const double res = sqrt(col[1]);
+  hist[it] = res;
+  if (!isfinite(res)) { st->status = kNonfinite; return; }
+  if (res <= st->tol) { st->status = kConverged; return; }
+  const int numax = st->nu_max;
+  for (int t = 0; t < nu; ++t) {
+    const int d = j1 - nu + t;
+    st->beta[t] = -col[2 + t] / st->eta_ring[d % numax];
+  }
+}
+
+// p_j = u + sum beta p_d into slot j.
+__global__ void __launch_bounds__(kBlock)
+k_fcg_maxpy(long long N, Window P, const double* __restrict__ u, const SolveState* st) {
+  if (read_status(st) != kRunning) return;
+  __shared__ double s_beta[kNuMax];
+  __shared__ long long s_off[kNuMax];
+  const int j = st->j, nu = st->nu, numax = st->nu_max;
+  for (int t = threadIdx.x; t < nu; t += kBlock) {
+    s_beta[t] = st->beta[t];
+    s_off[t] = (long long)((j - nu + t) % numax) * P.ld;
+  }
+  __syncthreads();
+  double* pn = P.slot(j % numax);
+  const long long step = 2LL * gstride();
+  for (long long e0 = 2LL * blockIdx.x * kBlock + threadIdx.x; e0 < N; e0 += step) {
+    const long long e1 = e0 + kBlock;
+    const bool h1 = e1 < N;
+    double p0 = u[e0], p1 = h1 ? u[e1] : 0.0;
+#pragma unroll 4
+    for (int t = 0; t < nu; ++t) {
+      const double b = s_beta[t];
+      const long long o = s_off[t];
+      p0 += b * P.base[o + e0];
+      if (h1) p1 += b * P.base[o + e1];
+    }
+    pn[e0] = p0;
+    if (h1) pn[e1] = p1;
+  }
+}
+
+// s_j = A p_j, partial eta_j = <p_j, s_j>.
+__global__ void __launch_bounds__(kBlock)
+k_fcg_apply(Grid g, StencilGeom sg, Window P, Window S, double* part, const SolveState* st) {
+  if (read_status(st) != kRunning) return;
+  const int slot = st->j % st->nu_max;
+  const double* p = P.slot(slot);
+  double* s = S.slot(slot);
+  double acc[1] = {0.0};
+  auto Pf = [&](long long t) { return p[t]; };
+  for_tile_nodes(g, sg, [&](int i, int j, int k, long long idx) {
+    const double pc = p[idx];
+    const double sv = stencil_at(g, i, j, k, idx, pc, Pf);
+    s[idx] = sv;
+    acc[0] += pc * sv;
+  });
+  block_partials<1>(acc, 1, part, sg.blocks());
+}
+
+// Second-reduction scalars: eta_j, breakdown check, alpha_j.
+__global__ void __launch_bounds__(kBlock)
+k_fcg_scalars2(int init, const double* part, int P, SolveState* st) {
+  if (read_status(st) != kRunning) return;
+  const double eta = block_sum_column(part, P, 0);
+  if (threadIdx.x != 0) return;
+  const int j = st->j;
+  if (!init) {
+    const bool forced = (st->force_it == st->it);
+    if (forced) st->force_it = -1;
+    if (forced || !(eta > 0.0) || !isfinite(eta)) { st->status = kBreakdown; return; }
+  } else if (!(eta > 0.0) || !isfinite(eta)) {
+    st->status = kBreakdown0;
+    return;
+  }
+  st->eta_ring[j % st->nu_max] = eta;
+  st->alpha = st->gamma / eta;
+  if (st->it >= st->maxit) st->status = kMaxit;
+}
+
+// FCG start-up test on ||r_0|| (history[0]).
+__global__ void __launch_bounds__(kBlock)
+k_init_test(const double* part, int P, SolveState* st, double* hist) {
+  if (read_status(st) != kRunning) return;
+  const double rr = block_sum_column(part, P, 0);
+  if (threadIdx.x != 0) return;
+  const double res = sqrt(rr);
+  if (!st->hist_started) { hist[0] = res; st->hist_started = 1; }
+  if (!isfinite(res)) { st->status = kNonfinite; return; }
+  if (res <= st->tol) st->status = kConverged;
+  else if (st->it >= st->maxit) st->status = kMaxit;
+}
+
+}  // namespace pfk

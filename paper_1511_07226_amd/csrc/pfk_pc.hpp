@@ -1,0 +1,189 @@
+// Preconditioner kernels B(v) for the flexible outer methods.
+//
+// The input is v = c1*X1 + c2*X2 (X2 may be null), formed on the fly.  The
+// output is consumed by the next kernel of the outer method through a PcOut
+// descriptor, so the last inner step and the outer method's use of B(v) run
+// in one pass.
+//
+// Global k-step Jacobi-PCG (PCG of Alg. 3 with M = diag(A), from y = 0):
+//   A_1 : p_1 = D^-1 v, q = A p_1;           partials <p_1,q>, <v,p_1>
+//   B_j : alpha_j = gamma_j / <p_j,q>;  y += alpha_j p_j;  rho -= alpha_j q;
+//         partial gamma_{j+1} = <rho, D^-1 rho>                 (j < k)
+//   A_j : beta_j = gamma_j/gamma_{j-1};  p_j = D^-1 rho + beta_j p_{j-1};
+//         q = A p_j;  partial <p_j,q>                            (2 <= j <= k)
+//   tail: y + alpha_k p_k, folded into the consumer.
+// Every kernel reduces the partials of its predecessor in its prologue (all
+// workgroups in the same fixed order), so no extra launch sits between them.
+// Guards as in the definition: a zero preconditioned residual returns 0 and
+// a non-positive curvature <p,q> returns the current iterate; the stop is
+// recorded per step in PcScalars so later steps leave y untouched.
+#pragma once
+#include "pfk_state.hpp"
+
+namespace pfk {
+
+enum PcKind : int { kPcNone = 0, kPcJacobi = 1, kPcJacobiPcg = 2, kPcJacobiGmres = 3, kPcBlockPcg = 4 };
+
+// Host-filled description of where B(v) comes from.
+struct PcOutDesc {
+  int kind;
+  int k;                        // inner iterations
+  const double* X1; double c1;  // v = c1*X1 + c2*X2
+  const double* X2; double c2;
+  const double* dinv;
+  const double* y;              // inner iterate (PCG), or final output (block PCG)
+  const double* pk;             // last inner direction (PCG)
+  const double* part;           // partials of the last inner kernel (PCG: <p_k,q>; A_1 also <v,p_1>)
+  int P;
+};
+
+// Device-side evaluator of B(v) at a node, built in the consumer's prologue.
+struct PcOut {
+  int kind;
+  const double* X1; double c1;
+  const double* X2; double c2;
+  const double* dinv;
+  const double* y;
+  const double* pk;
+  double alpha;
+  int use_y;                    // false when k == 1 (y is still zero)
+  int add_p;                    // false when the inner solve stopped before step k
+  __device__ __forceinline__ double v(long long t) const {
+    double r = c1 * X1[t];
+    if (X2 != nullptr) r += c2 * X2[t];
+    return r;
+  }
+  __device__ __forceinline__ double operator()(long long t) const {
+    switch (kind) {
+      case kPcNone: return v(t);
+      case kPcJacobi: return dinv[t] * v(t);
+      case kPcBlockPcg: return y[t];
+      default: {
+        double r = use_y ? y[t] : 0.0;
+        if (add_p) r += alpha * pk[t];
+        return r;
+      }
+    }
+  }
+};
+
+// Finish the inner PCG (alpha_k from the last A_k partials) or pass through.
+// Every thread of the workgroup must call this.
+__device__ __forceinline__ PcOut make_pc_out(const PcOutDesc& d, PcScalars* pcs) {
+  PcOut o;
+  o.kind = d.kind; o.X1 = d.X1; o.c1 = d.c1; o.X2 = d.X2; o.c2 = d.c2; o.dinv = d.dinv;
+  o.y = d.y; o.pk = d.pk; o.alpha = 0.0; o.use_y = d.k > 1; o.add_p = 0;
+  if (d.kind == kPcJacobiPcg) {
+    const double pq = block_sum_column(d.part, d.P, 0);
+    double gk;
+    int stopped;
+    if (d.k == 1) {
+      gk = block_sum_column(d.part, d.P, 1);
+      stopped = (gk == 0.0);
+    } else {
+      gk = pcs->gamma[d.k];
+      stopped = pcs->stopped[d.k - 1];
+    }
+    stopped = stopped || !(pq > 0.0);
+    o.add_p = !stopped;
+    o.alpha = stopped ? 0.0 : gk / pq;
+  }
+  return o;
+}
+
+// ---- A_1: p_1 = D^-1 v, q = A p_1 -------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+k_pcg_a1(Grid g, StencilGeom sg, const double* __restrict__ dinv,
+         const double* X1, double c1, const double* X2, double c2,
+         double* __restrict__ pout, double* __restrict__ qout,
+         double* part, const SolveState* st) {
+  if (read_status(st) != kRunning) return;
+  double acc[2] = {0.0, 0.0};
+  auto V = [&](long long t) { double r = c1 * X1[t]; if (X2 != nullptr) r += c2 * X2[t]; return r; };
+  auto Pf = [&](long long t) { return dinv[t] * V(t); };
+  for_tile_nodes(g, sg, [&](int i, int j, int k, long long idx) {
+    const double vc = V(idx);
+    const double pc = dinv[idx] * vc;
+    const double q = stencil_at(g, i, j, k, idx, pc, Pf);
+    pout[idx] = pc;
+    qout[idx] = q;
+    acc[0] += pc * q;
+    acc[1] += vc * pc;
+  });
+  block_partials<2>(acc, 2, part, sg.blocks());
+}
+
+// ---- B_j (1 <= j < k): y += alpha p, rho -= alpha q, partial <rho, D^-1 rho> --
+__global__ void __launch_bounds__(kBlock)
+k_pcg_b(int jstep, long long N, const double* __restrict__ dinv,
+        const double* X1, double c1, const double* X2, double c2,
+        const double* __restrict__ p, const double* __restrict__ q,
+        double* __restrict__ rho, double* __restrict__ y,
+        const double* part_in, int P_in, double* part_out, SolveState* st) {
+  if (read_status(st) != kRunning) return;
+  PcScalars* pcs = &st->pc;
+  const double pq = block_sum_column(part_in, P_in, 0);
+  double gj;
+  int stopped;
+  if (jstep == 1) {
+    gj = block_sum_column(part_in, P_in, 1);
+    stopped = (gj == 0.0);
+  } else {
+    gj = pcs->gamma[jstep];
+    stopped = pcs->stopped[jstep - 1];
+  }
+  stopped = stopped || !(pq > 0.0);
+  const double alpha = stopped ? 0.0 : gj / pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (jstep == 1) pcs->gamma[1] = gj;
+    pcs->stopped[jstep] = stopped;
+  }
+  double acc[1] = {0.0};
+  for (long long e = gtid(); e < N; e += gstride()) {
+    double r;
+    double yv;
+    if (jstep == 1) {
+      r = c1 * X1[e];
+      if (X2 != nullptr) r += c2 * X2[e];
+      yv = 0.0;
+    } else {
+      r = rho[e];
+      yv = y[e];
+    }
+    if (!stopped) {
+      yv += alpha * p[e];
+      r -= alpha * q[e];
+    }
+    y[e] = yv;
+    rho[e] = r;
+    acc[0] += r * (dinv[e] * r);
+  }
+  block_partials<1>(acc, 1, part_out, gridDim.x);
+}
+
+// ---- A_j (2 <= j <= k): p_j = D^-1 rho + beta p_{j-1}, q = A p_j -------------
+__global__ void __launch_bounds__(kBlock)
+k_pcg_a(int jstep, Grid g, StencilGeom sg, const double* __restrict__ dinv,
+        const double* __restrict__ rho, const double* __restrict__ pprev,
+        double* __restrict__ pout, double* __restrict__ qout,
+        const double* part_in, int P_in, double* part_out, SolveState* st) {
+  if (read_status(st) != kRunning) return;
+  PcScalars* pcs = &st->pc;
+  const double gj = block_sum_column(part_in, P_in, 0);
+  const double gprev = pcs->gamma[jstep - 1];
+  const int stopped = pcs->stopped[jstep - 1];
+  const double beta = (stopped || gprev == 0.0) ? 0.0 : gj / gprev;
+  if (blockIdx.x == 0 && threadIdx.x == 0) pcs->gamma[jstep] = gj;
+  double acc[1] = {0.0};
+  auto Pf = [&](long long t) { return dinv[t] * rho[t] + beta * pprev[t]; };
+  for_tile_nodes(g, sg, [&](int i, int j, int k, long long idx) {
+    const double pc = Pf(idx);
+    const double q = stencil_at(g, i, j, k, idx, pc, Pf);
+    pout[idx] = pc;
+    qout[idx] = q;
+    acc[0] += pc * q;
+  });
+  block_partials<1>(acc, 1, part_out, sg.blocks());
+}
+
+}  // namespace pfk

@@ -1,0 +1,82 @@
+// Device-resident solver state: the scalar block every kernel of a solve reads
+// (status, iteration counters, alpha/beta/eta of the direction window, the
+// Hessenberg least-squares data of the GMRES family) and the preconditioner's
+// per-application scalars.  It lives in the caller's workspace; the host only
+// reads it (asynchronously) between graph launches.
+#pragma once
+#include "pfk_device.hpp"
+
+namespace pfk {
+
+enum Status : int {
+  kRunning = 0,
+  kConverged = 1,    // recurred residual below tolerance; true residual still to check
+  kBreakdown = 2,    // norm breakdown: restart from the current x
+  kMaxit = 3,
+  kBreakdown0 = 4,   // breakdown of the initial direction: unrecoverable
+  kCycleEnd = 5,     // GMRES family: restart length reached
+  kNonfinite = 6,
+  kDone = 7,         // true residual confirmed below tolerance
+  kGap = 8,          // true residual above tolerance: restart from x
+};
+
+constexpr int kMaxInner = 32;      // largest inner iteration count of a preconditioner
+
+struct PcScalars {                 // one inner solve's scalars, indexed by inner step
+  double gamma[kMaxInner + 2];
+  int stopped[kMaxInner + 2];
+  // inner GMRES: Hessenberg, Givens data and solution coefficients
+  double h[(kMaxInner + 1) * kMaxInner];
+  double cs[kMaxInner], sn[kMaxInner], g[kMaxInner + 1], c[kMaxInner];
+  double beta0;
+  int ncol;
+};
+
+struct SolveState {
+  int status;
+  int it;            // iterations completed since the start of the solve
+  int j;             // CG/CR: index of the newest direction since the last (re)start
+  int nu_max;        // window length (CG/CR) or restart length (GMRES)
+  int trunc;         // truncation rule: 0 min(j,nu_max), 1 max(1, j mod (nu_max+1)), 2 min(j, j mod nu_max + 1)
+  int maxit;
+  int force_it;      // test hook: iteration at which a breakdown is forced (one-shot), -1 off
+  int hist_started;
+  int nu;            // number of window directions of the current update
+  int bzero;         // b == 0: the solve is finished with x = 0
+  double tol;        // rtol * ||b||_2
+  double alpha;      // step length of the next solution update
+  double gamma, delta, rho, eta_new;
+  double sigma;      // PIPEFGMRES shift
+  double true_res;
+  double bnorm;      // ||b||_2
+  double eta_ring[kNuMax];   // eta of direction d at slot d mod nu_max
+  double beta[kNuMax];       // beta of the current update, window order (oldest first)
+  // GMRES family (restart length m <= kNuMax)
+  int col;           // Arnoldi columns finished in this cycle
+  int pad1;
+  double beta0;      // ||r_0|| of the cycle
+  double hbar[kNuMax + 1];
+  double hn;         // norm of the new basis vector (h_{i,i-1})
+  double R[(kNuMax + 1) * kNuMax];   // rotated Hessenberg, column-major (m+1) x m
+  double cs[kNuMax], sn[kNuMax], g[kNuMax + 1], y[kNuMax];
+  PcScalars pc;
+};
+
+__host__ __device__ inline int trunc_nu(int rule, int j, int numax) {
+  if (j < 1) return 0;
+  if (rule == 1) {
+    const int m = j % (numax + 1);
+    return m < 1 ? 1 : m;
+  }
+  if (rule == 2) {
+    const int m = j % numax + 1;
+    return m < j ? m : j;
+  }
+  return j < numax ? j : numax;
+}
+
+__device__ __forceinline__ int read_status(const SolveState* st) {
+  return __hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace pfk
