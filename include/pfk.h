@@ -172,6 +172,15 @@ int pfk_session_iterate(pfk_session S, int iters);
 int pfk_session_sync(pfk_session S, pfk_solve_info* info);
 void pfk_session_destroy(pfk_session S);
 
+/* Kernel timing for roofline accounting: enqueues `iters` iterations with
+ * kernels launched directly (no graph) and HIP events recorded on each
+ * kernel's own stream right before and after it; waits, then reports per
+ * kernel name (static strings owned by the library) the summed milliseconds
+ * and launch count, for up to `cap` kernels.  Returns the number of distinct
+ * kernels (may exceed cap) or a negative pfk_status. */
+int pfk_session_profile(pfk_session S, int iters, int cap, const char** names, double* total_ms,
+                        int* launches);
+
 /* PIPEFGMRES shift: Rayleigh quotient of v -> A B(v) after `its` power steps
  * from the normalised ones vector (the largest eigenvalue of the
  * right-preconditioned operator, sections 4.4 and 5). */

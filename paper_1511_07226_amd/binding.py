@@ -33,7 +33,7 @@ EXPORTED = [
     "pfk_operator_apply", "pfk_operator_diag_inv", "pfk_precond_create", "pfk_precond_destroy",
     "pfk_precond_apply", "pfk_workspace_bytes", "pfk_solve", "pfk_session_create",
     "pfk_session_start", "pfk_session_iterate", "pfk_session_sync", "pfk_session_destroy",
-    "pfk_estimate_sigma", "pfk_last_error",
+    "pfk_session_profile", "pfk_estimate_sigma", "pfk_last_error",
 ]
 
 
@@ -104,6 +104,8 @@ def lib():
         "pfk_session_iterate": (C.c_int, [vp, C.c_int]),
         "pfk_session_sync": (C.c_int, [vp, C.POINTER(_Info)]),
         "pfk_session_destroy": (None, [vp]),
+        "pfk_session_profile": (C.c_int, [vp, C.c_int, C.c_int, C.POINTER(C.c_char_p),
+                                          C.POINTER(C.c_double), C.POINTER(C.c_int)]),
         "pfk_estimate_sigma": (C.c_int, [vp, vp, C.c_int, C.POINTER(C.c_double), vp]),
         "pfk_last_error": (C.c_char_p, []),
     }
@@ -284,6 +286,17 @@ class Session:
         code = lib().pfk_session_sync(self._h, C.byref(info))
         _check(code, allow_positive=True)
         return _to_info(code, info, hist)
+
+    def profile(self, iters: int) -> dict:
+        """Per-kernel event timing over `iters` directly launched iterations:
+        {kernel name: (total ms, launches)}."""
+        cap = 64
+        names = (C.c_char_p * cap)()
+        ms = (C.c_double * cap)()
+        cnt = (C.c_int * cap)()
+        n = lib().pfk_session_profile(self._h, int(iters), cap, names, ms, cnt)
+        _check(min(n, 0))
+        return {names[i].decode(): (ms[i], cnt[i]) for i in range(min(n, cap))}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -359,7 +359,7 @@ struct pfk_session_s {
   Layout L;
   hipStream_t user = nullptr, s1 = nullptr, s2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_user = nullptr, ev_done = nullptr;
-  hipGraphExec_t g_start = nullptr, g_iter = nullptr;
+  hipGraphExec_t g_start = nullptr, g_iter = nullptr, g_one = nullptr;
   SolveState* st = nullptr;
   double* hist = nullptr;
   SolveState* host_state = nullptr;   // pinned
@@ -375,8 +375,44 @@ struct pfk_session_s {
 
 namespace {
 
-#define LAUNCH(kernel, blocks, stream, ...) \
-  hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kBlock), 0, stream, __VA_ARGS__)
+// Optional per-kernel timing (pfk_session_profile): HIP events recorded on
+// the launching stream immediately before and after each kernel.
+struct KernelProfiler {
+  struct Rec {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  hipEvent_t get() {
+    if (used == pool.size()) {
+      hipEvent_t e = nullptr;
+      (void)hipEventCreate(&e);
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  ~KernelProfiler() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+thread_local KernelProfiler* g_prof = nullptr;
+
+#define LAUNCH(kernel, blocks, stream, ...)                                              \
+  do {                                                                                   \
+    hipEvent_t ea_ = nullptr;                                                            \
+    if (g_prof) {                                                                        \
+      ea_ = g_prof->get();                                                               \
+      (void)hipEventRecord(ea_, stream);                                                 \
+    }                                                                                    \
+    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kBlock), 0, stream, __VA_ARGS__);      \
+    if (g_prof) {                                                                        \
+      hipEvent_t eb_ = g_prof->get();                                                    \
+      (void)hipEventRecord(eb_, stream);                                                 \
+      g_prof->recs.push_back({#kernel, ea_, eb_});                                       \
+    }                                                                                    \
+  } while (0)
 
 // Enqueue the inner solve B(v), v = c1*X1 + c2*X2; returns how the consumer
 // evaluates B(v).
@@ -537,7 +573,15 @@ int launch_iters(pfk_session_s* S, int iters) {
       if (rc) return rc;
     }
     const int gi = S->opts.graph_iters;
-    for (int done = 0; done < iters; done += gi) HIPCHK(hipGraphLaunch(S->g_iter, S->s1));
+    int done = 0;
+    for (; done + gi <= iters; done += gi) HIPCHK(hipGraphLaunch(S->g_iter, S->s1));
+    if (done < iters) {
+      if (!S->g_one) {
+        int rc = capture(S, &S->g_one, 1, 1);
+        if (rc) return rc;
+      }
+      for (; done < iters; ++done) HIPCHK(hipGraphLaunch(S->g_one, S->s1));
+    }
   } else {
     for (int i = 0; i < iters; ++i) enqueue_iteration(S);
   }
@@ -565,6 +609,7 @@ extern "C" int pfk_session_create(pfk_operator A, pfk_precond B, pfk_method meth
   if (mmax < 1 || mmax > kNuMax) return fail(PFK_ERR_ARG, "mmax must be 1..64");
   if (maxit < 0) return fail(PFK_ERR_ARG, "maxit must be >= 0");
   if (!(rtol >= 0.0)) return fail(PFK_ERR_ARG, "rtol must be >= 0");
+  if (((uintptr_t)b | (uintptr_t)x) % 16 != 0) return fail(PFK_ERR_ARG, "b and x must be 16-byte aligned");
   auto* S = new (std::nothrow) pfk_session_s();
   if (!S) return fail(PFK_ERR_OOM, "host allocation");
   S->A = A; S->B = B; S->method = method; S->b = b; S->x = x; S->rtol = rtol;
@@ -612,6 +657,7 @@ extern "C" void pfk_session_destroy(pfk_session S) {
   if (S->s1) (void)hipStreamSynchronize(S->s1);
   if (S->g_start) (void)hipGraphExecDestroy(S->g_start);
   if (S->g_iter) (void)hipGraphExecDestroy(S->g_iter);
+  if (S->g_one) (void)hipGraphExecDestroy(S->g_one);
   if (S->ev_fork) (void)hipEventDestroy(S->ev_fork);
   if (S->ev_join) (void)hipEventDestroy(S->ev_join);
   if (S->ev_user) (void)hipEventDestroy(S->ev_user);
@@ -762,6 +808,44 @@ extern "C" int pfk_precond_apply(pfk_precond B, const double* v, double* y, void
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
   return PFK_OK;
+}
+
+extern "C" int pfk_session_profile(pfk_session S, int iters, int cap, const char** names, double* total_ms,
+                                   int* launches) {
+  if (!S || iters < 0 || cap < 0) return fail(PFK_ERR_ARG, "bad argument");
+  HIPCHK(hipEventRecord(S->ev_user, S->user));
+  HIPCHK(hipStreamWaitEvent(S->s1, S->ev_user, 0));
+  KernelProfiler prof;
+  g_prof = &prof;
+  for (int i = 0; i < iters; ++i) enqueue_iteration(S);
+  g_prof = nullptr;
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(S->s1));
+  std::vector<const char*> nm;
+  std::vector<double> ms;
+  std::vector<int> cnt;
+  for (const auto& r : prof.recs) {
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
+    size_t c = 0;
+    while (c < nm.size() && std::strcmp(nm[c], r.name) != 0) ++c;
+    if (c == nm.size()) {
+      nm.push_back(r.name);
+      ms.push_back(0.0);
+      cnt.push_back(0);
+    }
+    ms[c] += t;
+    cnt[c] += 1;
+  }
+  const int n = (int)nm.size();
+  for (int c = 0; c < n && c < cap; ++c) {
+    if (names) names[c] = nm[c];
+    if (total_ms) total_ms[c] = ms[c];
+    if (launches) launches[c] = cnt[c];
+  }
+  HIPCHK(hipEventRecord(S->ev_done, S->s1));
+  HIPCHK(hipStreamWaitEvent(S->user, S->ev_done, 0));
+  return n;
 }
 
 extern "C" int pfk_estimate_sigma(pfk_operator, pfk_precond, int, double*, void*) {

@@ -57,22 +57,22 @@ __global__ void __launch_bounds__(kBlock)
 k_residual(Grid g, StencilGeom sg, const double* __restrict__ b, const double* __restrict__ x,
            double* __restrict__ r, double* part) {
   double acc[1] = {0.0};
-  auto X = [&](long long t) { return x[t]; };
-  for_tile_nodes(g, sg, [&](int i, int j, int k, long long idx) {
-    const double rv = b[idx] - stencil_at(g, i, j, k, idx, x[idx], X);
+  auto in = [&](long long t) { return x[t]; };
+  auto sink = [&](long long idx, double, double Au) {
+    const double rv = b[idx] - Au;
     r[idx] = rv;
     acc[0] += rv * rv;
-  });
+  };
+  stencil_march(g, sg, in, sink);
   block_partials<1>(acc, 1, part, sg.blocks());
 }
 
 // y = A x (library entry point for operator checks).
 __global__ void __launch_bounds__(kBlock)
 k_apply(Grid g, StencilGeom sg, const double* __restrict__ x, double* __restrict__ y) {
-  auto X = [&](long long t) { return x[t]; };
-  for_tile_nodes(g, sg, [&](int i, int j, int k, long long idx) {
-    y[idx] = stencil_at(g, i, j, k, idx, x[idx], X);
-  });
+  auto in = [&](long long t) { return x[t]; };
+  auto sink = [&](long long idx, double, double Au) { y[idx] = Au; };
+  stencil_march(g, sg, in, sink);
 }
 
 // O = c3*X3 + B(v) at every node, N = A O.  With `dots`: partials <O, R>, <O, N>.
@@ -84,18 +84,17 @@ k_apply_pc_out(Grid g, StencilGeom sg, PcOutDesc pd, const double* X3, double c3
                int dots, const double* __restrict__ R, double* part, SolveState* st) {
   if (read_status(st) != kRunning) return;
   const PcOut pc = make_pc_out(pd, &st->pc);
-  auto M = [&](long long t) { double v = pc(t); if (X3 != nullptr) v += c3 * X3[t]; return v; };
+  auto in = [&](long long t) { double v = pc(t); if (X3 != nullptr) v += c3 * X3[t]; return v; };
   double acc[2] = {0.0, 0.0};
-  for_tile_nodes(g, sg, [&](int i, int j, int k, long long idx) {
-    const double mc = M(idx);
-    const double nv = stencil_at(g, i, j, k, idx, mc, M);
+  auto sink = [&](long long idx, double mc, double nv) {
     O[idx] = mc;
     Nout[idx] = nv;
     if (dots) {
       acc[0] += mc * R[idx];
       acc[1] += mc * nv;
     }
-  });
+  };
+  stencil_march(g, sg, in, sink);
   if (dots) block_partials<2>(acc, 2, part, sg.blocks());
 }
 
@@ -134,16 +133,27 @@ k_pipefcg_init_scalars(const double* part_r, int P_r, const double* part_ud, int
   if (st->it >= st->maxit) st->status = kMaxit;
 }
 
+// Two consecutive doubles per lane: one 16-byte access (the scalar tail of
+// an odd N reads/writes only .x).
+__device__ __forceinline__ double2 ld2(const double* p, long long e, bool full) {
+  if (full) return *reinterpret_cast<const double2*>(p + e);
+  return make_double2(p[e], 0.0);
+}
+__device__ __forceinline__ void st2(double* p, long long e, double2 v, bool full) {
+  if (full) *reinterpret_cast<double2*>(p + e) = v;
+  else p[e] = v.x;
+}
+
 // One fused pass for direction j (= st->j):
 //   p_j = u_j + sum beta p_d,  s_j = w_j + sum beta s_d,
 //   q_j = m_j + sum beta q_d,  z_j = n_j + sum beta z_d      (written to slot j)
 //   x += alpha p_j, r -= alpha s_j, u -= alpha q_j, w -= alpha z_j
 // and the single reduction of iteration j+1 on the updated vectors:
 //   gamma = <u,r>, delta = <u,w>, rho = <r,r>, <u, s_d> for d in window(j+1).
-// The window dots reuse the s_d loads of the MAXPY.  Each thread owns two
-// nodes per step (coalesced across the wave); the per-direction dot is summed
-// over the wave at once and accumulated in LDS, so the register footprint
-// does not grow with the window.
+// The window dots reuse the s_d loads of the MAXPY.  Each lane owns two
+// consecutive nodes (16-byte accesses); the per-direction dot is summed over
+// the wave at once and accumulated in LDS, so the register footprint does not
+// grow with the window.  Vectors must be 16-byte aligned.
 __global__ void __launch_bounds__(kBlock)
 k_pipefcg_update(long long N, Window P, Window S, Window Q, Window Z,
                  double* __restrict__ x, double* __restrict__ r, double* __restrict__ u,
@@ -168,72 +178,50 @@ k_pipefcg_update(long long N, Window P, Window S, Window Q, Window Z,
   __syncthreads();
   const long long ns = (long long)(j % numax) * P.ld;
   double gam = 0.0, del = 0.0, rho = 0.0, dnew = 0.0;
-  const long long step = 2LL * gstride();
-  for (long long e0 = 2LL * blockIdx.x * kBlock + threadIdx.x; e0 < N; e0 += step) {
-    const long long e1 = e0 + kBlock;
-    const bool h1 = e1 < N;
-    const double u0 = u[e0], u1 = h1 ? u[e1] : 0.0;
-    const double w0 = w[e0], w1 = h1 ? w[e1] : 0.0;
-    double p0 = u0, p1 = u1;
-    double q0 = m[e0], q1 = h1 ? m[e1] : 0.0;
-    double z0 = n[e0], z1 = h1 ? n[e1] : 0.0;
+  const long long npair = (N + 1) / 2;
+  for (long long qi = gtid(); qi < npair; qi += gstride()) {
+    const long long e = 2 * qi;
+    const bool full = e + 1 < N;
+    const double2 u0 = ld2(u, e, full), w0 = ld2(w, e, full);
+    double2 p = u0, q = ld2(m, e, full), z = ld2(n, e, full);
 #pragma unroll 4
     for (int t = 0; t < nu; ++t) {
       const double b = s_beta[t];
-      const long long o = s_off[t];
-      p0 += b * P.base[o + e0];
-      q0 += b * Q.base[o + e0];
-      z0 += b * Z.base[o + e0];
-      if (h1) {
-        p1 += b * P.base[o + e1];
-        q1 += b * Q.base[o + e1];
-        z1 += b * Z.base[o + e1];
-      }
+      const long long o = s_off[t] + e;
+      const double2 pv = ld2(P.base, o, full), qv = ld2(Q.base, o, full), zv = ld2(Z.base, o, full);
+      p.x += b * pv.x; p.y += b * pv.y;
+      q.x += b * qv.x; q.y += b * qv.y;
+      z.x += b * zv.x; z.y += b * zv.y;
     }
-    const double un0 = u0 - alpha * q0, un1 = u1 - alpha * q1;
-    const double wn0 = w0 - alpha * z0, wn1 = w1 - alpha * z1;
-    double s0 = w0, s1 = w1;
+    const double2 un = make_double2(u0.x - alpha * q.x, u0.y - alpha * q.y);
+    const double2 wn = make_double2(w0.x - alpha * z.x, w0.y - alpha * z.y);
+    double2 sv = w0;
 #pragma unroll 4
     for (int t = 0; t < nu; ++t) {
       const double b = s_beta[t];
-      const long long o = s_off[t];
-      const double sd0 = S.base[o + e0];
-      const double sd1 = h1 ? S.base[o + e1] : 0.0;
-      s0 += b * sd0;
-      s1 += b * sd1;
+      const double2 sd = ld2(S.base, s_off[t] + e, full);
+      sv.x += b * sd.x; sv.y += b * sd.y;
       if (t >= shift) {
-        const double d = wave_sum(un0 * sd0 + un1 * sd1);
+        const double d = wave_sum(un.x * sd.x + un.y * sd.y);
         if (lane == 0) s_dot[wid][t - shift] += d;
       }
     }
-    const double rn0 = r[e0] - alpha * s0;
-    x[e0] += alpha * p0;
-    P.base[ns + e0] = p0;
-    S.base[ns + e0] = s0;
-    Q.base[ns + e0] = q0;
-    Z.base[ns + e0] = z0;
-    u[e0] = un0;
-    w[e0] = wn0;
-    r[e0] = rn0;
-    gam += un0 * rn0;
-    del += un0 * wn0;
-    rho += rn0 * rn0;
-    dnew += un0 * s0;
-    if (h1) {
-      const double rn1 = r[e1] - alpha * s1;
-      x[e1] += alpha * p1;
-      P.base[ns + e1] = p1;
-      S.base[ns + e1] = s1;
-      Q.base[ns + e1] = q1;
-      Z.base[ns + e1] = z1;
-      u[e1] = un1;
-      w[e1] = wn1;
-      r[e1] = rn1;
-      gam += un1 * rn1;
-      del += un1 * wn1;
-      rho += rn1 * rn1;
-      dnew += un1 * s1;
-    }
+    const double2 r0 = ld2(r, e, full);
+    const double2 rn = make_double2(r0.x - alpha * sv.x, r0.y - alpha * sv.y);
+    double2 x0 = ld2(x, e, full);
+    x0.x += alpha * p.x; x0.y += alpha * p.y;
+    st2(x, e, x0, full);
+    st2(P.base, ns + e, p, full);
+    st2(S.base, ns + e, sv, full);
+    st2(Q.base, ns + e, q, full);
+    st2(Z.base, ns + e, z, full);
+    st2(u, e, un, full);
+    st2(w, e, wn, full);
+    st2(r, e, rn, full);
+    gam += un.x * rn.x + un.y * rn.y;
+    del += un.x * wn.x + un.y * wn.y;
+    rho += rn.x * rn.x + rn.y * rn.y;
+    dnew += un.x * sv.x + un.y * sv.y;
   }
   // columns: gamma, delta, rho, then <u, s_d> for d = j+1-nu1 .. j (the last is s_j)
   const int ncol = 3 + nu1;
@@ -430,13 +418,12 @@ k_fcg_apply(Grid g, StencilGeom sg, Window P, Window S, double* part, const Solv
   const double* p = P.slot(slot);
   double* s = S.slot(slot);
   double acc[1] = {0.0};
-  auto Pf = [&](long long t) { return p[t]; };
-  for_tile_nodes(g, sg, [&](int i, int j, int k, long long idx) {
-    const double pc = p[idx];
-    const double sv = stencil_at(g, i, j, k, idx, pc, Pf);
+  auto in = [&](long long t) { return p[t]; };
+  auto sink = [&](long long idx, double pc, double sv) {
     s[idx] = sv;
     acc[0] += pc * sv;
-  });
+  };
+  stencil_march(g, sg, in, sink);
   block_partials<1>(acc, 1, part, sg.blocks());
 }
 

@@ -1,7 +1,8 @@
 // Device-side building blocks shared by every kernel of the library:
-// launch geometry, the variable-coefficient stencil evaluated at one node,
-// wave/workgroup reductions that write per-workgroup partial sums, and the
-// consumer-side deterministic reduction of those partials.
+// launch geometry, the variable-coefficient stencil (one node at a time, and
+// the z-marching tile engine the hot kernels use), wave/workgroup reductions
+// that write per-workgroup partial sums, and the consumer-side deterministic
+// reduction of those partials.
 //
 // Layout conventions (the same as the C ABI):
 //   * unknown vectors: N = nx*ny*nz FP64 values (nz = 1 in 2D), x fastest;
@@ -19,7 +20,8 @@ namespace pfk {
 constexpr int kBlock = 256;        // threads per workgroup: four 64-wide waves
 constexpr int kWaves = kBlock / 64;
 constexpr int kTileX = 64;         // stencil tile: 64 x-nodes (one wave per row) ...
-constexpr int kTileY = 4;          // ... by 4 y-rows
+constexpr int kTileY = 8;          // ... by 8 y-rows, two rows per thread
+constexpr int kHalo = 2 * kTileX + 2 * kTileY;   // in-plane halo nodes of a tile
 constexpr int kNuMax = 64;         // largest window / restart length supported
 
 // ---------------------------------------------------------------------------
@@ -41,51 +43,60 @@ __device__ __forceinline__ long long padded_index(const Grid& g, int i, int j, i
   return (g.dim == 3 ? (long long)(k + 1) * g.sz : 0) + (long long)(j + 1) * g.sy + (i + 1);
 }
 
+__device__ __forceinline__ long long vec_index(const Grid& g, int i, int j, int k) {
+  return ((long long)k * g.ny + j) * g.nx + i;
+}
+
 __device__ __forceinline__ double harmonic(double a, double b) { return 2.0 * a * b / (a + b); }
 
-// (A u) at interior node (i,j,k), flat index idx, given u at the node (uc) and
-// an accessor U(flat index) for its interior neighbours.  Diffusion:
-// h^-2 sum_f k_f (u_c - u_nb), k_f the harmonic mean of eta; Dirichlet
-// neighbours contribute u_nb = 0.  Convection (if g.vel): first-order upwind
-// flux h^-1 sum_f (max(v_f,0) u_c + min(v_f,0) u_nb) with outward v_f.
-template <class F>
-__device__ __forceinline__ double stencil_at(const Grid& g, int i, int j, int k, long long idx,
-                                             double uc, F&& U) {
-  const long long pc = padded_index(g, i, j, k);
-  const double ec = g.eta[pc];
-  const double un_xp = (i + 1 < g.nx) ? U(idx + 1) : 0.0;
-  const double un_xm = (i > 0) ? U(idx - 1) : 0.0;
-  const double un_yp = (j + 1 < g.ny) ? U(idx + g.nx) : 0.0;
-  const double un_ym = (j > 0) ? U(idx - g.nx) : 0.0;
-  double acc = harmonic(ec, g.eta[pc + 1]) * (uc - un_xp) + harmonic(ec, g.eta[pc - 1]) * (uc - un_xm) +
-               harmonic(ec, g.eta[pc + g.sy]) * (uc - un_yp) + harmonic(ec, g.eta[pc - g.sy]) * (uc - un_ym);
-  double un_zp = 0.0, un_zm = 0.0;
-  if (g.dim == 3) {
-    const long long nxy = (long long)g.nx * g.ny;
-    un_zp = (k + 1 < g.nz) ? U(idx + nxy) : 0.0;
-    un_zm = (k > 0) ? U(idx - nxy) : 0.0;
-    acc += harmonic(ec, g.eta[pc + g.sz]) * (uc - un_zp) + harmonic(ec, g.eta[pc - g.sz]) * (uc - un_zm);
-  }
+// (A u) at the node with padded index pc from its value uc, its six
+// neighbour values (0 on the Dirichlet boundary) and the viscosities at the
+// node and its neighbours.  Diffusion: h^-2 sum_f k_f (u_c - u_nb) with k_f
+// the harmonic mean of eta; convection (if g.vel): first-order upwind flux
+// h^-1 sum_f (max(v_f,0) u_c + min(v_f,0) u_nb) with v_f the outward normal
+// velocity.  Faces are taken in the order x+, x-, y+, y-, z+, z-.
+__device__ __forceinline__ double apply_faces(const Grid& g, long long pc, double uc, double ec,
+                                              double exp_, double exm, double eyp, double eym,
+                                              double ezp, double ezm, double uxp, double uxm,
+                                              double uyp, double uym, double uzp, double uzm) {
+  double acc = harmonic(ec, exp_) * (uc - uxp) + harmonic(ec, exm) * (uc - uxm) +
+               harmonic(ec, eyp) * (uc - uyp) + harmonic(ec, eym) * (uc - uym);
+  if (g.dim == 3) acc += harmonic(ec, ezp) * (uc - uzp) + harmonic(ec, ezm) * (uc - uzm);
   acc *= g.h2inv;
   if (g.vel != nullptr) {
     const double* vx = g.vel;
     const double* vy = g.vel + g.vstride;
     const double* vz = g.vel + 2 * g.vstride;
     double c = 0.0, v;
-    v = vx[pc];            c += fmax(v, 0.0) * uc + fmin(v, 0.0) * un_xp;
-    v = -vx[pc - 1];       c += fmax(v, 0.0) * uc + fmin(v, 0.0) * un_xm;
-    v = vy[pc];            c += fmax(v, 0.0) * uc + fmin(v, 0.0) * un_yp;
-    v = -vy[pc - g.sy];    c += fmax(v, 0.0) * uc + fmin(v, 0.0) * un_ym;
+    v = vx[pc];            c += fmax(v, 0.0) * uc + fmin(v, 0.0) * uxp;
+    v = -vx[pc - 1];       c += fmax(v, 0.0) * uc + fmin(v, 0.0) * uxm;
+    v = vy[pc];            c += fmax(v, 0.0) * uc + fmin(v, 0.0) * uyp;
+    v = -vy[pc - g.sy];    c += fmax(v, 0.0) * uc + fmin(v, 0.0) * uym;
     if (g.dim == 3) {
-      v = vz[pc];          c += fmax(v, 0.0) * uc + fmin(v, 0.0) * un_zp;
-      v = -vz[pc - g.sz];  c += fmax(v, 0.0) * uc + fmin(v, 0.0) * un_zm;
+      v = vz[pc];          c += fmax(v, 0.0) * uc + fmin(v, 0.0) * uzp;
+      v = -vz[pc - g.sz];  c += fmax(v, 0.0) * uc + fmin(v, 0.0) * uzm;
     }
     acc += g.hinv * c;
   }
   return acc;
 }
 
-// Stencil launch geometry: a workgroup owns a 64 x 4 tile of x-y nodes and
+// (A u) at interior node (i,j,k), flat index idx, one node at a time: U is an
+// accessor for interior neighbour values.
+template <class F>
+__device__ __forceinline__ double stencil_at(const Grid& g, int i, int j, int k, long long idx,
+                                             double uc, F&& U) {
+  const long long pc = padded_index(g, i, j, k);
+  const long long nxy = (long long)g.nx * g.ny;
+  const bool d3 = g.dim == 3;
+  return apply_faces(g, pc, uc, g.eta[pc], g.eta[pc + 1], g.eta[pc - 1], g.eta[pc + g.sy], g.eta[pc - g.sy],
+                     d3 ? g.eta[pc + g.sz] : 0.0, d3 ? g.eta[pc - g.sz] : 0.0,
+                     (i + 1 < g.nx) ? U(idx + 1) : 0.0, (i > 0) ? U(idx - 1) : 0.0,
+                     (j + 1 < g.ny) ? U(idx + g.nx) : 0.0, (j > 0) ? U(idx - g.nx) : 0.0,
+                     (d3 && k + 1 < g.nz) ? U(idx + nxy) : 0.0, (d3 && k > 0) ? U(idx - nxy) : 0.0);
+}
+
+// Stencil launch geometry: a workgroup owns a 64 x 8 tile of x-y nodes and
 // walks `zc` consecutive z-planes, so the number of workgroups (and of
 // reduction partials) is tiles_x * tiles_y * ceil(nz/zc).
 struct StencilGeom {
@@ -93,21 +104,104 @@ struct StencilGeom {
   __host__ __device__ int blocks() const { return tiles_x * tiles_y * zchunks; }
 };
 
-// Iterate the nodes a workgroup owns in a stencil launch.
+// Workgroup ids are dealt round-robin to the 8 XCDs (each with its own L2).
+// Give each XCD a contiguous run of tiles (x fastest, then y, then z-chunk)
+// so the halo rows and planes that neighbouring tiles share stay in one L2.
+__device__ __forceinline__ int xcd_tile(int nblocks) {
+  const int b = blockIdx.x;
+  const int full = nblocks & ~7;
+  if (b >= full) return b;
+  return (b & 7) * (full >> 3) + (b >> 3);
+}
+
+// Iterate the nodes a workgroup owns in a stencil launch (one node at a time).
 template <class F>
 __device__ __forceinline__ void for_tile_nodes(const Grid& g, const StencilGeom& sg, F&& body) {
-  const int b = blockIdx.x;
-  const int tx = b % sg.tiles_x;
-  const int ty = (b / sg.tiles_x) % sg.tiles_y;
-  const int tz = b / (sg.tiles_x * sg.tiles_y);
+  const int L = xcd_tile(sg.blocks());
+  const int tx = L % sg.tiles_x;
+  const int ty = (L / sg.tiles_x) % sg.tiles_y;
+  const int tz = L / (sg.tiles_x * sg.tiles_y);
   const int i = tx * kTileX + (threadIdx.x & 63);
-  const int j = ty * kTileY + (threadIdx.x >> 6);
-  if (i >= g.nx || j >= g.ny) return;
   const int k0 = tz * sg.zc;
   const int k1 = min(g.nz, k0 + sg.zc);
+  for (int r = 0; r < 2; ++r) {
+    const int j = ty * kTileY + (threadIdx.x >> 6) + 4 * r;
+    if (i >= g.nx || j >= g.ny) continue;
+    for (int k = k0; k < k1; ++k) body(i, j, k, vec_index(g, i, j, k));
+  }
+}
+
+// The hot stencil engine.  A workgroup walks its tile up the z-axis.  Each
+// node's input value u = in(flat index) is formed once: z-neighbours stay in
+// registers (three planes), in-plane neighbours come from an LDS copy of the
+// current plane with a one-node halo (halo values are formed by 144 of the
+// 256 threads).  Values outside the domain are 0 (Dirichlet).  For every
+// interior node the engine calls sink(flat index, u, (A u)).
+template <class In, class Sink>
+__device__ __forceinline__ void stencil_march(const Grid& g, const StencilGeom& sg, const In& in, Sink& sink) {
+  __shared__ double su[kTileY + 2][kTileX + 2];
+  const int L = xcd_tile(sg.blocks());
+  const int tx = L % sg.tiles_x;
+  const int ty = (L / sg.tiles_x) % sg.tiles_y;
+  const int tz = L / (sg.tiles_x * sg.tiles_y);
+  const int lane = threadIdx.x & 63, wrow = threadIdx.x >> 6;
+  const int i0 = tx * kTileX, j0 = ty * kTileY;
+  const int i = i0 + lane;
+  const int k0 = tz * sg.zc;
+  const int k1 = min(g.nz, k0 + sg.zc);
+  const bool d3 = g.dim == 3;
+  int jr[2];
+  bool valid[2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    jr[r] = j0 + wrow + 4 * r;
+    valid[r] = i < g.nx && jr[r] < g.ny;
+  }
+  // this thread's halo node (if any) and its LDS slot
+  const int t = threadIdx.x;
+  int hi = 0, hj = 0, hr = 0, hc = 0;
+  if (t < kTileX) { hi = i0 + t; hj = j0 - 1; hr = 0; hc = t + 1; }
+  else if (t < 2 * kTileX) { hi = i0 + t - kTileX; hj = j0 + kTileY; hr = kTileY + 1; hc = t - kTileX + 1; }
+  else if (t < 2 * kTileX + kTileY) { hi = i0 - 1; hj = j0 + t - 2 * kTileX; hr = hj - j0 + 1; hc = 0; }
+  else if (t < kHalo) { hi = i0 + kTileX; hj = j0 + t - 2 * kTileX - kTileY; hr = hj - j0 + 1; hc = kTileX + 1; }
+  const bool has_halo = t < kHalo;
+  const bool hvalid = has_halo && hi >= 0 && hi < g.nx && hj >= 0 && hj < g.ny;
+
+  double um[2], uc[2], up[2], em[2], ec[2], ep[2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    um[r] = (valid[r] && d3 && k0 > 0) ? in(vec_index(g, i, jr[r], k0 - 1)) : 0.0;
+    uc[r] = (valid[r] && k0 < k1) ? in(vec_index(g, i, jr[r], k0)) : 0.0;
+    em[r] = (valid[r] && d3) ? g.eta[padded_index(g, i, jr[r], k0 - 1)] : 0.0;
+    ec[r] = valid[r] ? g.eta[padded_index(g, i, jr[r], k0)] : 0.0;
+  }
   for (int k = k0; k < k1; ++k) {
-    const long long idx = ((long long)k * g.ny + j) * g.nx + i;
-    body(i, j, k, idx);
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      up[r] = (valid[r] && k + 1 < g.nz) ? in(vec_index(g, i, jr[r], k + 1)) : 0.0;
+      ep[r] = (valid[r] && d3) ? g.eta[padded_index(g, i, jr[r], k + 1)] : 0.0;
+    }
+    const double hv = hvalid ? in(vec_index(g, hi, hj, k)) : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 2; ++r) su[wrow + 4 * r + 1][lane + 1] = uc[r];
+    if (has_halo) su[hr][hc] = hv;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      if (valid[r]) {
+        const int row = wrow + 4 * r + 1;
+        const long long pc = padded_index(g, i, jr[r], k);
+        const double Au = apply_faces(g, pc, uc[r], ec[r], g.eta[pc + 1], g.eta[pc - 1], g.eta[pc + g.sy],
+                                      g.eta[pc - g.sy], ep[r], em[r], su[row][lane + 2], su[row][lane],
+                                      su[row + 1][lane + 1], su[row - 1][lane + 1], up[r], um[r]);
+        sink(vec_index(g, i, jr[r], k), uc[r], Au);
+      }
+      um[r] = uc[r];
+      uc[r] = up[r];
+      em[r] = ec[r];
+      ec[r] = ep[r];
+    }
   }
 }
 

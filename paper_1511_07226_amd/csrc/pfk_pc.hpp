@@ -100,16 +100,14 @@ k_pcg_a1(Grid g, StencilGeom sg, const double* __restrict__ dinv,
   if (read_status(st) != kRunning) return;
   double acc[2] = {0.0, 0.0};
   auto V = [&](long long t) { double r = c1 * X1[t]; if (X2 != nullptr) r += c2 * X2[t]; return r; };
-  auto Pf = [&](long long t) { return dinv[t] * V(t); };
-  for_tile_nodes(g, sg, [&](int i, int j, int k, long long idx) {
-    const double vc = V(idx);
-    const double pc = dinv[idx] * vc;
-    const double q = stencil_at(g, i, j, k, idx, pc, Pf);
+  auto in = [&](long long t) { return dinv[t] * V(t); };
+  auto sink = [&](long long idx, double pc, double q) {
     pout[idx] = pc;
     qout[idx] = q;
     acc[0] += pc * q;
-    acc[1] += vc * pc;
-  });
+    acc[1] += V(idx) * pc;
+  };
+  stencil_march(g, sg, in, sink);
   block_partials<2>(acc, 2, part, sg.blocks());
 }
 
@@ -175,14 +173,13 @@ k_pcg_a(int jstep, Grid g, StencilGeom sg, const double* __restrict__ dinv,
   const double beta = (stopped || gprev == 0.0) ? 0.0 : gj / gprev;
   if (blockIdx.x == 0 && threadIdx.x == 0) pcs->gamma[jstep] = gj;
   double acc[1] = {0.0};
-  auto Pf = [&](long long t) { return dinv[t] * rho[t] + beta * pprev[t]; };
-  for_tile_nodes(g, sg, [&](int i, int j, int k, long long idx) {
-    const double pc = Pf(idx);
-    const double q = stencil_at(g, i, j, k, idx, pc, Pf);
+  auto in = [&](long long t) { return dinv[t] * rho[t] + beta * pprev[t]; };
+  auto sink = [&](long long idx, double pc, double q) {
     pout[idx] = pc;
     qout[idx] = q;
     acc[0] += pc * q;
-  });
+  };
+  stencil_march(g, sg, in, sink);
   block_partials<1>(acc, 1, part_out, sg.blocks());
 }
 
