@@ -24,7 +24,7 @@
 #include <vector>
 
 #include "../../include/pfk.h"
-#include "pfk_cg.hpp"
+#include "pfk_gmres.hpp"
 
 using namespace pfk;
 
@@ -238,7 +238,7 @@ extern "C" int64_t pfk_operator_size(pfk_operator A) { return A ? A->N : 0; }
 extern "C" int pfk_operator_apply(pfk_operator A, const double* x, double* y, void* stream) {
   if (!A || !x || !y) return fail(PFK_ERR_ARG, "null argument");
   hipLaunchKernelGGL(k_apply, dim3(A->sg.blocks()), dim3(kBlock), 0, (hipStream_t)stream, A->grid(), A->sg,
-                     x, y);
+                     x, y, (const SolveState*)nullptr);
   HIPCHK(hipGetLastError());
   return PFK_OK;
 }
@@ -258,7 +258,9 @@ extern "C" int pfk_precond_create(pfk_operator A, pfk_pc_kind kind, int inner_it
       (inner_its < 1 || inner_its > kMaxInner))
     return fail(PFK_ERR_ARG, "inner_its must be 1..32");
   if (prec != PFK_FP64 && prec != PFK_FP32_BF16COEF) return fail(PFK_ERR_ARG, "unknown precision");
-  if (kind == PFK_PC_JACOBI_GMRES || kind == PFK_PC_BLOCK_JACOBI_PCG || prec != PFK_FP64)
+  if (kind == PFK_PC_JACOBI_GMRES && inner_its > kMaxInnerGmres)
+    return fail(PFK_ERR_ARG, "inner GMRES supports at most 8 steps");
+  if (kind == PFK_PC_BLOCK_JACOBI_PCG || prec != PFK_FP64)
     return fail(PFK_ERR_ARG, "preconditioner kind/precision not available in this build");
   auto* B = new (std::nothrow) pfk_precond_s();
   if (!B) return fail(PFK_ERR_OOM, "host allocation");
@@ -285,29 +287,41 @@ namespace {
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-enum Vec { V_R, V_U, V_W, V_M, V_N, V_PC_P0, V_PC_P1, V_PC_Q, V_PC_RHO, V_PC_Y, V_TMP, V_COUNT };
-enum Win { W_P, W_S, W_Q, W_Z, W_COUNT };
+enum Vec {
+  V_R, V_U, V_W, V_M, V_N,                       // outer work vectors
+  V_PC_P0, V_PC_P1, V_PC_Q, V_PC_RHO, V_PC_Y,    // inner PCG
+  V_X0, V_Z, V_VIN,                              // GMRES family: cycle start x, z / wbar, basis input
+  V_COUNT
+};
+enum Win { W_P, W_S, W_Q, W_Z, W_PCV, W_COUNT };  // W_PCV: inner GMRES basis
 enum Part { PT_MAIN, PT_A, PT_B, PT_PC0, PT_PC1, PT_COUNT };
 
 struct Layout {
   size_t state = 0, hist = 0;
   size_t vec[V_COUNT] = {};
   size_t win[W_COUNT] = {};
+  int slots[W_COUNT] = {};
   size_t part[PT_COUNT] = {};
   long long ld = 0;
-  int nwin = 0;
   size_t total = 0;
 };
 
-int windows_of(int method) {
+// Window slots per method: CG/CR types keep nu_max directions in P, S (and
+// Q, Z for the pipelined ones); GMRES types keep the basis P (m+1 columns),
+// U (m, or m+1 for PIPEFGMRES) and PIPEFGMRES's zbar (m+1).
+void window_slots(int method, int mmax, int* slots) {
+  for (int w = 0; w < W_COUNT; ++w) slots[w] = 0;
   switch (method) {
-    case PFK_FCG: return 2;
-    case PFK_PIPEFCG: return 4;
-    default: return 0;
+    case PFK_FCG: case PFK_GCR: slots[W_P] = slots[W_S] = mmax; break;
+    case PFK_PIPEGCR: slots[W_P] = slots[W_S] = slots[W_Q] = mmax; break;
+    case PFK_PIPEFCG: slots[W_P] = slots[W_S] = slots[W_Q] = slots[W_Z] = mmax; break;
+    case PFK_FGMRES: slots[W_P] = mmax + 1; slots[W_S] = mmax; break;
+    case PFK_PIPEFGMRES: slots[W_P] = slots[W_S] = slots[W_Q] = mmax + 1; break;
+    default: break;
   }
 }
 
-Layout make_layout(const pfk_operator_s* A, int method, int mmax, int maxit) {
+Layout make_layout(const pfk_operator_s* A, const pfk_precond_s* B, int method, int mmax, int maxit) {
   Layout L;
   size_t off = 0;
   L.state = off;
@@ -320,10 +334,11 @@ Layout make_layout(const pfk_operator_s* A, int method, int mmax, int maxit) {
     L.vec[v] = off;
     off += vbytes;
   }
-  L.nwin = windows_of(method);
+  window_slots(method, mmax, L.slots);
+  if (B && B->kind == PFK_PC_JACOBI_GMRES) L.slots[W_PCV] = B->k + 1;
   for (int w = 0; w < W_COUNT; ++w) {
     L.win[w] = off;
-    if (w < L.nwin) off += vbytes * (size_t)mmax;
+    off += vbytes * (size_t)L.slots[w];
   }
   const int P = std::max(A->sg.blocks(), A->pv_blocks);
   const size_t pbytes = align_up(sizeof(double) * (size_t)P * (kNuMax + 4));
@@ -337,9 +352,9 @@ Layout make_layout(const pfk_operator_s* A, int method, int mmax, int maxit) {
 
 }  // namespace
 
-extern "C" size_t pfk_workspace_bytes(pfk_operator A, pfk_precond, pfk_method method, int mmax, int maxit) {
+extern "C" size_t pfk_workspace_bytes(pfk_operator A, pfk_precond B, pfk_method method, int mmax, int maxit) {
   if (!A || mmax < 1 || mmax > kNuMax || maxit < 0) return 0;
-  return make_layout(A, method, mmax, maxit).total;
+  return make_layout(A, B, method, mmax, maxit).total;
 }
 
 // ---------------------------------------------------------------------------
@@ -353,6 +368,7 @@ struct pfk_session_s {
   double* x = nullptr;
   double rtol = 0.0;
   int maxit = 0, mmax = 0;
+  double sigma = 0.0;
   pfk_solve_opts opts{};
   char* ws = nullptr;
   bool ws_owned = false;
@@ -416,76 +432,117 @@ thread_local KernelProfiler* g_prof = nullptr;
 
 // Enqueue the inner solve B(v), v = c1*X1 + c2*X2; returns how the consumer
 // evaluates B(v).
-PcOutDesc enqueue_pc(pfk_session_s* S, hipStream_t s, const double* X1, double c1, const double* X2,
-                     double c2) {
-  const pfk_operator_s* A = S->A;
+// How a consumer evaluates B(v) after enqueue_pc(v): which buffers hold the
+// inner solve's last state (the same buffers every time).
+PcOutDesc pc_out_desc(const pfk_session_s* S, const double* X1, double c1, const double* X2, double c2) {
   PcOutDesc d{};
   d.kind = S->B->kind;
   d.k = S->B->k;
   d.X1 = X1; d.c1 = c1; d.X2 = X2; d.c2 = c2;
-  d.dinv = A->dinv;
-  if (d.kind != kPcJacobiPcg) return d;
-  const Grid g = S->grid();
-  double* pp[2] = {S->vec(V_PC_P0), S->vec(V_PC_P1)};
-  double* q = S->vec(V_PC_Q);
-  double* rho = S->vec(V_PC_RHO);
-  double* y = S->vec(V_PC_Y);
-  double* part[2] = {S->part(PT_PC0), S->part(PT_PC1)};
-  LAUNCH(k_pcg_a1, S->Ps(), s, g, A->sg, A->dinv, X1, c1, X2, c2, pp[0], q, part[0], S->st);
-  int t = 1, Pprev = S->Ps();
-  for (int j = 1; j < d.k; ++j) {
-    LAUNCH(k_pcg_b, S->Pv(), s, j, A->N, A->dinv, X1, c1, X2, c2, pp[(j - 1) & 1], q, rho, y,
-           part[(t - 1) & 1], Pprev, part[t & 1], S->st);
-    Pprev = S->Pv();
-    ++t;
-    LAUNCH(k_pcg_a, S->Ps(), s, j + 1, g, A->sg, A->dinv, rho, pp[(j - 1) & 1], pp[j & 1], q,
-           part[(t - 1) & 1], Pprev, part[t & 1], S->st);
-    Pprev = S->Ps();
-    ++t;
+  d.dinv = S->A->dinv;
+  if (d.kind == kPcJacobiPcg) {
+    // A_1, (B_j, A_{j+1}) alternate the partial buffers: A_k writes PC0
+    d.y = S->vec(V_PC_Y);
+    d.pk = S->vec((d.k - 1) & 1 ? V_PC_P1 : V_PC_P0);
+    d.part = S->part(PT_PC0);
+    d.P = S->Ps();
+  } else if (d.kind == kPcJacobiGmres) {
+    // G0, (GA_j, GO_j): every GO_j writes PC0
+    d.part = S->part(PT_PC0);
+    d.P = S->Pv();
+    d.vbase = S->win(W_PCV).base;
+    d.ldv = S->L.ld;
   }
-  d.y = y;
-  d.pk = pp[(d.k - 1) & 1];
-  d.part = part[(t - 1) & 1];
-  d.P = Pprev;
   return d;
 }
 
-void enqueue_pipefcg_update(pfk_session_s* S, hipStream_t s) {
-  LAUNCH(k_pipefcg_update, S->Pv(), s, S->A->N, S->win(W_P), S->win(W_S), S->win(W_Q), S->win(W_Z),
-         S->x, S->vec(V_R), S->vec(V_U), S->vec(V_W), S->vec(V_M), S->vec(V_N), S->part(PT_MAIN), S->st);
+PcOutDesc enqueue_pc(pfk_session_s* S, hipStream_t s, const double* X1, double c1, const double* X2,
+                     double c2) {
+  const pfk_operator_s* A = S->A;
+  const PcOutDesc d = pc_out_desc(S, X1, c1, X2, c2);
+  const Grid g = S->grid();
+  double* part[2] = {S->part(PT_PC0), S->part(PT_PC1)};
+  if (d.kind == kPcJacobiPcg) {
+    double* pp[2] = {S->vec(V_PC_P0), S->vec(V_PC_P1)};
+    double* q = S->vec(V_PC_Q);
+    double* rho = S->vec(V_PC_RHO);
+    double* y = S->vec(V_PC_Y);
+    LAUNCH(k_pcg_a1, S->Ps(), s, g, A->sg, A->dinv, X1, c1, X2, c2, pp[0], q, part[0], S->st);
+    int t = 1, Pprev = S->Ps();
+    for (int j = 1; j < d.k; ++j) {
+      LAUNCH(k_pcg_b, S->Pv(), s, j, A->N, A->dinv, X1, c1, X2, c2, pp[(j - 1) & 1], q, rho, y,
+             part[(t - 1) & 1], Pprev, part[t & 1], S->st);
+      Pprev = S->Pv();
+      ++t;
+      LAUNCH(k_pcg_a, S->Ps(), s, j + 1, g, A->sg, A->dinv, rho, pp[(j - 1) & 1], pp[j & 1], q,
+             part[(t - 1) & 1], Pprev, part[t & 1], S->st);
+      Pprev = S->Ps();
+      ++t;
+    }
+  } else if (d.kind == kPcJacobiGmres) {
+    const Window V = S->win(W_PCV);
+    double* w = S->vec(V_PC_Q);
+    LAUNCH(k_gmpc_start, S->Pv(), s, A->N, d.k, X1, c1, X2, c2, V.base, part[0], S->st);
+    int t = 1, Pprev = S->Pv();
+    for (int j = 0; j < d.k; ++j) {
+      LAUNCH(k_gmpc_apply, S->Ps(), s, j, g, A->sg, A->dinv, (const double*)V.base, V.ld, w,
+             part[(t - 1) & 1], Pprev, part[t & 1], S->st);
+      Pprev = S->Ps();
+      ++t;
+      LAUNCH(k_gmpc_orth, S->Pv(), s, j, d.k, A->N, V.base, V.ld, (const double*)w, part[(t - 1) & 1], Pprev,
+             part[t & 1], S->st);
+      Pprev = S->Pv();
+      ++t;
+    }
+  }
+  return d;
 }
 
-void enqueue_fcg_dots(pfk_session_s* S, hipStream_t s, int init, const PcOutDesc& pd) {
-  LAUNCH(k_fcg_dots, S->Pv(), s, S->A->N, init, pd, S->win(W_S), S->vec(V_R), S->vec(V_U),
-         S->part(PT_MAIN), S->st);
+void enqueue_multidot(pfk_session_s* S, hipStream_t s, int init, int from_pc, const PcOutDesc& pd,
+                      const double* Vin, double* Vout) {
+  LAUNCH(k_multidot, S->Pv(), s, S->A->N, init, from_pc, pd, Vin, Vout, (const double*)S->vec(V_R),
+         S->win(W_S), S->part(PT_MAIN), S->st);
 }
 
-void enqueue_fcg_maxpy(pfk_session_s* S, hipStream_t s) {
-  LAUNCH(k_fcg_maxpy, S->Pv(), s, S->A->N, S->win(W_P), S->vec(V_U), S->st);
-}
-
-// FCG: the part of an iteration after x, r have been updated, also used for
-// the start-up (init = 1): u = B(r), reduction 1, p = u + sum beta p,
-// s = A p, reduction 2.
-void enqueue_fcg_body(pfk_session_s* S, hipStream_t s, int init) {
+// FCG / GCR: the part of an iteration after x, r have been updated, also
+// the start-up (init = 1).
+//   FCG: u = B(r); reduction 1 (<u,r>, <r,r>, <u,s_d>); p = u + sum beta p;
+//        s = A p with reduction 2 (<p,s>)
+//   GCR: u = B(r), t = A u; reduction 1 (<r,r>, <t,s_d>); p = u + sum beta p,
+//        s = t + sum beta s with reduction 2 (<r,s>, <s,s>)
+void enqueue_cg_body(pfk_session_s* S, hipStream_t s, int init) {
+  const Grid g = S->grid();
   PcOutDesc pd = enqueue_pc(S, s, S->vec(V_R), 1.0, nullptr, 0.0);
-  enqueue_fcg_dots(S, s, init, pd);
-  LAUNCH(k_fcg_scalars1, 1, s, init, S->part(PT_MAIN), S->Pv(), S->st, S->hist);
-  enqueue_fcg_maxpy(S, s);
-  LAUNCH(k_fcg_apply, S->Ps(), s, S->grid(), S->A->sg, S->win(W_P), S->win(W_S), S->part(PT_A), S->st);
-  LAUNCH(k_fcg_scalars2, 1, s, init, S->part(PT_A), S->Ps(), S->st);
+  if (S->method == PFK_FCG) {
+    enqueue_multidot(S, s, init, 1, pd, nullptr, S->vec(V_U));
+    LAUNCH(k_cg_scalars1, 1, s, init, S->part(PT_MAIN), S->Pv(), S->st, S->hist);
+    LAUNCH(k_fcg_maxpy, S->Pv(), s, S->A->N, S->win(W_P), (const double*)S->vec(V_U), (const SolveState*)S->st);
+    LAUNCH(k_fcg_apply, S->Ps(), s, g, S->A->sg, S->win(W_P), S->win(W_S), S->part(PT_A), (const SolveState*)S->st);
+    LAUNCH(k_cg_scalars2, 1, s, 0, init, S->part(PT_A), S->Ps(), S->st);
+  } else {
+    LAUNCH(k_apply_pc_out, S->Ps(), s, g, S->A->sg, pd, (const double*)nullptr, 0.0, S->vec(V_U), S->vec(V_W), 0,
+           (const double*)nullptr, S->part(PT_B), S->st);
+    enqueue_multidot(S, s, init, 0, pd, S->vec(V_W), nullptr);
+    LAUNCH(k_cg_scalars1, 1, s, init, S->part(PT_MAIN), S->Pv(), S->st, S->hist);
+    LAUNCH(k_gcr_maxpy, S->Pv(), s, S->A->N, S->win(W_P), S->win(W_S), (const double*)S->vec(V_U),
+           (const double*)S->vec(V_W), (const double*)S->vec(V_R), S->part(PT_A), (const SolveState*)S->st);
+    LAUNCH(k_cg_scalars2, 1, s, 1, init, S->part(PT_A), S->Pv(), S->st);
+  }
 }
 
 // Start (or restart) from the current x.
 void enqueue_start(pfk_session_s* S, hipStream_t s) {
   const pfk_operator_s* A = S->A;
   const Grid g = S->grid();
+  const bool gm = S->method == PFK_FGMRES || S->method == PFK_PIPEFGMRES;
   LAUNCH(k_restart, 1, s, S->st);
-  LAUNCH(k_residual, S->Ps(), s, g, A->sg, S->b, (const double*)S->x, S->vec(V_R), S->part(PT_A));
+  LAUNCH(k_residual, S->Ps(), s, g, A->sg, S->b, (const double*)S->x, S->vec(V_R), S->part(PT_A),
+         gm ? S->vec(V_X0) : nullptr);
   switch (S->method) {
     case PFK_FCG:
+    case PFK_GCR:
       LAUNCH(k_init_test, 1, s, S->part(PT_A), S->Ps(), S->st, S->hist);
-      enqueue_fcg_body(S, s, 1);
+      enqueue_cg_body(S, s, 1);
       break;
     case PFK_PIPEFCG: {
       // u_0 = B(r_0), w_0 = A u_0, gamma_0 = <u_0,r_0>, delta_0 = <u_0,w_0>
@@ -499,6 +556,40 @@ void enqueue_start(pfk_session_s* S, hipStream_t s) {
       LAUNCH(k_pipefcg_init_scalars, 1, s, S->part(PT_A), S->Ps(), S->part(PT_B), S->Ps(), S->st, S->hist);
       break;
     }
+    case PFK_PIPEGCR: {
+      LAUNCH(k_init_test, 1, s, S->part(PT_A), S->Ps(), S->st, S->hist);
+      // u_0 = B(r_0), s_0 = A u_0 (kept in w), gamma_0 = <r_0,s_0>, eta_0 = <s_0,s_0>
+      PcOutDesc pd = enqueue_pc(S, s, S->vec(V_R), 1.0, nullptr, 0.0);
+      LAUNCH(k_apply_pc_out, S->Ps(), s, g, A->sg, pd, (const double*)nullptr, 0.0, S->vec(V_U), S->vec(V_W), 0,
+             (const double*)nullptr, S->part(PT_B), S->st);
+      enqueue_multidot(S, s, 1, 0, pd, S->vec(V_W), nullptr);
+      // q_0 = B(s_0), consumed by the first update
+      enqueue_pc(S, s, S->vec(V_W), 1.0, nullptr, 0.0);
+      LAUNCH(k_pipegcr_init_scalars, 1, s, S->part(PT_MAIN), S->Pv(), S->st);
+      break;
+    }
+    case PFK_FGMRES:
+      LAUNCH(k_gm_cycle_start, 1, s, S->part(PT_A), S->Ps(), S->st, S->hist);
+      LAUNCH(k_gm_scale, S->Pv(), s, A->N, (const double*)S->vec(V_R), 0, S->win(W_P), S->vec(V_VIN),
+             (const SolveState*)S->st);
+      break;
+    case PFK_PIPEFGMRES: {
+      LAUNCH(k_gm_cycle_start, 1, s, S->part(PT_A), S->Ps(), S->st, S->hist);
+      LAUNCH(k_gm_scale, S->Pv(), s, A->N, (const double*)S->vec(V_R), 0, S->win(W_P), S->vec(V_VIN),
+             (const SolveState*)S->st);
+      // u~_0 = B(p_0), zbar_0 = A u~_0 - sigma p_0, first reduction
+      PcOutDesc pd = enqueue_pc(S, s, S->vec(V_VIN), 1.0, nullptr, 0.0);
+      LAUNCH(k_pgm_apply0, S->Ps(), s, g, A->sg, pd, S->win(W_S), S->win(W_P), S->win(W_Q), S->vec(V_M),
+             S->part(PT_MAIN), S->st);
+      // qbar_0 = B(zbar_0), wbar_0 = A qbar_0
+      pd = enqueue_pc(S, s, S->vec(V_M), 1.0, nullptr, 0.0);
+      LAUNCH(k_apply_pc_out, S->Ps(), s, g, A->sg, pd, (const double*)nullptr, 0.0, (double*)nullptr,
+             S->vec(V_Z), 0, (const double*)nullptr, S->part(PT_B), S->st);
+      LAUNCH(k_pgm_scalars, 1, s, S->part(PT_MAIN), S->Ps(), S->st, S->hist);   // partials of k_pgm_apply0
+      LAUNCH(k_gm_update_x, S->Pv(), s, A->N, S->win(W_S), (const double*)S->vec(V_X0), S->x,
+             (const SolveState*)S->st);
+      break;
+    }
     default:
       break;
   }
@@ -507,23 +598,74 @@ void enqueue_start(pfk_session_s* S, hipStream_t s) {
 // One iteration.
 void enqueue_iteration(pfk_session_s* S) {
   const pfk_operator_s* A = S->A;
+  const Grid g = S->grid();
   hipStream_t s1 = S->s1, s2 = S->s2;
   switch (S->method) {
     case PFK_FCG:
-      LAUNCH(k_fcg_xr, S->Pv(), s1, A->N, S->win(W_P), S->win(W_S), S->x, S->vec(V_R), S->st);
-      enqueue_fcg_body(S, s1, 0);
+    case PFK_GCR:
+      LAUNCH(k_fcg_xr, S->Pv(), s1, A->N, S->win(W_P), S->win(W_S), S->x, S->vec(V_R), (const SolveState*)S->st);
+      enqueue_cg_body(S, s1, 0);
       break;
     case PFK_PIPEFCG: {
-      enqueue_pipefcg_update(S, s1);
+      LAUNCH(k_pipefcg_update, S->Pv(), s1, A->N, S->win(W_P), S->win(W_S), S->win(W_Q), S->win(W_Z), S->x,
+             S->vec(V_R), S->vec(V_U), S->vec(V_W), (const double*)S->vec(V_M), (const double*)S->vec(V_N),
+             S->part(PT_MAIN), (const SolveState*)S->st);
       // fork: finish the reduction on s2 while s1 applies B and A
       (void)hipEventRecord(S->ev_fork, s1);
       (void)hipStreamWaitEvent(s2, S->ev_fork, 0);
       LAUNCH(k_pipefcg_scalars, 1, s2, S->part(PT_MAIN), S->Pv(), S->st, S->hist);
       (void)hipEventRecord(S->ev_join, s2);
       PcOutDesc pd = enqueue_pc(S, s1, S->vec(V_W), 1.0, S->vec(V_R), -1.0);
-      LAUNCH(k_apply_pc_out, S->Ps(), s1, S->grid(), A->sg, pd, (const double*)S->vec(V_U), 1.0, S->vec(V_M),
+      LAUNCH(k_apply_pc_out, S->Ps(), s1, g, A->sg, pd, (const double*)S->vec(V_U), 1.0, S->vec(V_M),
              S->vec(V_N), 0, (const double*)nullptr, S->part(PT_B), S->st);
       (void)hipStreamWaitEvent(s1, S->ev_join, 0);
+      break;
+    }
+    case PFK_PIPEGCR: {
+      // the inner solve's output of the previous iteration: B(w - r)
+      const PcOutDesc pd_prev = pc_out_desc(S, S->vec(V_W), 1.0, S->vec(V_R), -1.0);
+      LAUNCH(k_pipegcr_update, S->Pv(), s1, A->N, S->win(W_P), S->win(W_S), S->win(W_Q), S->x, S->vec(V_R),
+             S->vec(V_U), (const double*)S->vec(V_W), pd_prev, S->st);
+      LAUNCH(k_apply, S->Ps(), s1, g, A->sg, (const double*)S->vec(V_U), S->vec(V_W), (const SolveState*)S->st);
+      enqueue_multidot(S, s1, 0, 0, pd_prev, S->vec(V_W), nullptr);
+      (void)hipEventRecord(S->ev_fork, s1);
+      (void)hipStreamWaitEvent(s2, S->ev_fork, 0);
+      LAUNCH(k_pipefcg_scalars, 1, s2, S->part(PT_MAIN), S->Pv(), S->st, S->hist);
+      (void)hipEventRecord(S->ev_join, s2);
+      enqueue_pc(S, s1, S->vec(V_W), 1.0, S->vec(V_R), -1.0);
+      (void)hipStreamWaitEvent(s1, S->ev_join, 0);
+      break;
+    }
+    case PFK_FGMRES: {
+      PcOutDesc pd = enqueue_pc(S, s1, S->vec(V_VIN), 1.0, nullptr, 0.0);
+      LAUNCH(k_fgm_apply, S->Ps(), s1, g, A->sg, pd, S->win(W_S), S->vec(V_Z), S->st);
+      LAUNCH(k_fgm_dots, S->Pv(), s1, A->N, S->win(W_P), (const double*)S->vec(V_Z), S->part(PT_MAIN),
+             (const SolveState*)S->st);
+      LAUNCH(k_gm_hbar, 1, s1, S->part(PT_MAIN), S->Pv(), S->st);
+      LAUNCH(k_fgm_orth, S->Pv(), s1, A->N, S->win(W_P), (const double*)S->vec(V_Z), S->part(PT_A),
+             (const SolveState*)S->st);
+      LAUNCH(k_fgm_column, 1, s1, S->part(PT_A), S->Pv(), S->st, S->hist);
+      LAUNCH(k_gm_scale, S->Pv(), s1, A->N, (const double*)nullptr, 1, S->win(W_P), S->vec(V_VIN),
+             (const SolveState*)S->st);
+      LAUNCH(k_gm_update_x, S->Pv(), s1, A->N, S->win(W_S), (const double*)S->vec(V_X0), S->x,
+             (const SolveState*)S->st);
+      break;
+    }
+    case PFK_PIPEFGMRES: {
+      // the inner solve's output of the previous iteration: qbar = B(zbar)
+      const PcOutDesc pd_prev = pc_out_desc(S, S->vec(V_M), 1.0, nullptr, 0.0);
+      LAUNCH(k_pgm_update, S->Pv(), s1, A->N, S->win(W_P), S->win(W_S), S->win(W_Q), pd_prev,
+             (const double*)S->vec(V_Z), S->vec(V_M), S->part(PT_MAIN), S->st);
+      (void)hipEventRecord(S->ev_fork, s1);
+      (void)hipStreamWaitEvent(s2, S->ev_fork, 0);
+      LAUNCH(k_pgm_scalars, 1, s2, S->part(PT_MAIN), S->Pv(), S->st, S->hist);
+      (void)hipEventRecord(S->ev_join, s2);
+      PcOutDesc pd = enqueue_pc(S, s1, S->vec(V_M), 1.0, nullptr, 0.0);
+      LAUNCH(k_apply_pc_out, S->Ps(), s1, g, A->sg, pd, (const double*)nullptr, 0.0, (double*)nullptr,
+             S->vec(V_Z), 0, (const double*)nullptr, S->part(PT_B), S->st);
+      (void)hipStreamWaitEvent(s1, S->ev_join, 0);
+      LAUNCH(k_gm_update_x, S->Pv(), s1, A->N, S->win(W_S), (const double*)S->vec(V_X0), S->x,
+             (const SolveState*)S->st);
       break;
     }
     default:
@@ -533,8 +675,26 @@ void enqueue_iteration(pfk_session_s* S) {
 
 void enqueue_true_check(pfk_session_s* S, hipStream_t s) {
   const pfk_operator_s* A = S->A;
-  LAUNCH(k_residual, S->Ps(), s, S->grid(), A->sg, S->b, (const double*)S->x, S->vec(V_R), S->part(PT_A));
+  LAUNCH(k_residual, S->Ps(), s, S->grid(), A->sg, S->b, (const double*)S->x, S->vec(V_R), S->part(PT_A),
+         (double*)nullptr);
   LAUNCH(k_true_check, 1, s, S->part(PT_A), S->Ps(), S->st);
+}
+
+// sigma of PIPEFGMRES: Rayleigh quotient of v -> A B(v) after `its` power steps
+// from the normalised ones vector.  Uses the session's work vectors.
+void enqueue_sigma_estimate(pfk_session_s* S, hipStream_t s, int its) {
+  const pfk_operator_s* A = S->A;
+  double* v = S->vec(V_VIN);
+  double* w = S->vec(V_Z);
+  LAUNCH(k_set_running, 1, s, S->st);
+  LAUNCH(k_fill, S->Pv(), s, A->N, v, 1.0 / std::sqrt((double)A->N));
+  for (int i = 0; i < its; ++i) {
+    PcOutDesc pd = enqueue_pc(S, s, v, 1.0, nullptr, 0.0);
+    LAUNCH(k_apply_pc_out, S->Ps(), s, S->grid(), A->sg, pd, (const double*)nullptr, 0.0, (double*)nullptr, w, 0,
+           (const double*)nullptr, S->part(PT_B), S->st);
+    LAUNCH(k_dot2, S->Pv(), s, A->N, (const double*)v, (const double*)w, S->part(PT_MAIN));
+    LAUNCH(k_power_step, S->Pv(), s, A->N, (const double*)S->part(PT_MAIN), S->Pv(), v, (const double*)w, S->st);
+  }
 }
 
 int capture(pfk_session_s* S, hipGraphExec_t* out, int what, int iters) {
@@ -604,8 +764,7 @@ extern "C" int pfk_session_create(pfk_operator A, pfk_precond B, pfk_method meth
   *out = nullptr;
   if (!A || !B || !b || !x) return fail(PFK_ERR_ARG, "null argument");
   if (B->A != A) return fail(PFK_ERR_ARG, "preconditioner was made for another operator");
-  if (method != PFK_FCG && method != PFK_PIPEFCG)
-    return fail(PFK_ERR_ARG, "method not available in this build");
+  if (method < PFK_FCG || method > PFK_PIPEFGMRES) return fail(PFK_ERR_ARG, "unknown method");
   if (mmax < 1 || mmax > kNuMax) return fail(PFK_ERR_ARG, "mmax must be 1..64");
   if (maxit < 0) return fail(PFK_ERR_ARG, "maxit must be >= 0");
   if (!(rtol >= 0.0)) return fail(PFK_ERR_ARG, "rtol must be >= 0");
@@ -621,7 +780,7 @@ extern "C" int pfk_session_create(pfk_operator A, pfk_precond B, pfk_method meth
     delete S;
     return fail(PFK_ERR_ARG, "truncation must be 0, 1 or 2");
   }
-  S->L = make_layout(A, method, mmax, maxit);
+  S->L = make_layout(A, B, method, mmax, maxit);
   if (workspace) {
     if (ws_bytes < S->L.total) {
       delete S;
@@ -674,9 +833,18 @@ extern "C" int pfk_session_start(pfk_session S) {
   // order after the caller's queued work
   HIPCHK(hipEventRecord(S->ev_user, S->user));
   HIPCHK(hipStreamWaitEvent(S->s1, S->ev_user, 0));
-  const double sigma = std::isnan(S->opts.shift_sigma) ? 0.0 : S->opts.shift_sigma;
+  if (S->method == PFK_PIPEFGMRES && std::isnan(S->opts.shift_sigma)) {
+    // sigma estimated once per session, before the set-up
+    enqueue_sigma_estimate(S, S->s1, 10);
+    HIPCHK(hipGetLastError());
+    int rc0 = read_state(S);
+    if (rc0) return rc0;
+    S->sigma = S->host_state->sigma;
+  } else {
+    S->sigma = std::isnan(S->opts.shift_sigma) ? 0.0 : S->opts.shift_sigma;
+  }
   LAUNCH(k_setup, 1, S->s1, S->st, 0.0, S->maxit, S->mmax, S->opts.truncation, S->opts.force_breakdown_at,
-         sigma);
+         S->sigma);
   LAUNCH(k_dot, S->Pv(), S->s1, S->A->N, S->b, S->b, S->part(PT_A));
   LAUNCH(k_setup_tol, 1, S->s1, S->part(PT_A), S->Pv(), S->rtol, S->st, S->hist);
   LAUNCH(k_zero_if_done, S->Pv(), S->s1, S->A->N, S->x, S->st);
@@ -755,6 +923,12 @@ extern "C" int pfk_solve(pfk_operator A, pfk_precond B, pfk_method method, const
       enqueue_true_check(S, S->s1);
       continue;
     }
+    if (status == kCycleEnd) {
+      // GMRES family: the restart length was reached; x = x0 + U y is in place
+      if (S->host_state->it >= S->maxit) { code = PFK_NOT_CONVERGED; break; }
+      rc = launch_start(S);
+      continue;
+    }
     if (status == kDone) { code = PFK_OK; break; }
     if (status == kMaxit) { code = PFK_NOT_CONVERGED; break; }
     if (status == kNonfinite) { code = PFK_ERR_NONFINITE; break; }
@@ -791,7 +965,7 @@ extern "C" int pfk_solve(pfk_operator A, pfk_precond B, pfk_method method, const
 extern "C" int pfk_precond_apply(pfk_precond B, const double* v, double* y, void* stream) {
   if (!B || !v || !y) return fail(PFK_ERR_ARG, "null argument");
   pfk_operator A = B->A;
-  Layout L = make_layout(A, PFK_FCG, 1, 1);
+  Layout L = make_layout(A, B, PFK_FCG, 1, 1);
   if (!B->scratch || B->scratch_bytes < L.total) {
     if (B->scratch) (void)hipFree(B->scratch);
     B->scratch = nullptr;
@@ -848,6 +1022,27 @@ extern "C" int pfk_session_profile(pfk_session S, int iters, int cap, const char
   return n;
 }
 
-extern "C" int pfk_estimate_sigma(pfk_operator, pfk_precond, int, double*, void*) {
-  return fail(PFK_ERR_ARG, "not available in this build");
+extern "C" int pfk_estimate_sigma(pfk_operator A, pfk_precond B, int its, double* sigma, void* stream) {
+  if (!A || !B || !sigma || its < 1) return fail(PFK_ERR_ARG, "bad argument");
+  if (B->A != A) return fail(PFK_ERR_ARG, "preconditioner was made for another operator");
+  Layout L = make_layout(A, B, PFK_FCG, 1, 1);
+  char* ws = nullptr;
+  if (hipMalloc(&ws, L.total) != hipSuccess) return fail(PFK_ERR_OOM, "sigma estimate workspace");
+  pfk_session_s S;
+  S.A = A; S.B = B; S.ws = ws; S.L = L; S.mmax = 1;
+  S.st = (SolveState*)(S.ws + L.state);
+  hipStream_t s = (hipStream_t)stream;
+  enqueue_sigma_estimate(&S, s, its);
+  SolveState* h = nullptr;
+  int rc = PFK_OK;
+  if (hipGetLastError() != hipSuccess || hipHostMalloc(&h, sizeof(SolveState), hipHostMallocDefault) != hipSuccess ||
+      hipMemcpyAsync(h, S.st, sizeof(SolveState), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    rc = fail(PFK_ERR_HIP, "sigma estimate");
+  } else {
+    *sigma = h->sigma;
+  }
+  if (h) (void)hipHostFree(h);
+  (void)hipFree(ws);
+  return rc;
 }

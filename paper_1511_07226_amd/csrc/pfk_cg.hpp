@@ -52,13 +52,14 @@ __global__ void k_restart(SolveState* st) {
   st->col = 0;
 }
 
-// r = b - A x, partial <r, r>.
+// r = b - A x, partial <r, r>; optionally a copy x0 = x (GMRES cycle start).
 __global__ void __launch_bounds__(kBlock)
 k_residual(Grid g, StencilGeom sg, const double* __restrict__ b, const double* __restrict__ x,
-           double* __restrict__ r, double* part) {
+           double* __restrict__ r, double* part, double* __restrict__ x0) {
   double acc[1] = {0.0};
   auto in = [&](long long t) { return x[t]; };
-  auto sink = [&](long long idx, double, double Au) {
+  auto sink = [&](long long idx, double xc, double Au) {
+    if (x0 != nullptr) x0[idx] = xc;
     const double rv = b[idx] - Au;
     r[idx] = rv;
     acc[0] += rv * rv;
@@ -67,9 +68,10 @@ k_residual(Grid g, StencilGeom sg, const double* __restrict__ b, const double* _
   block_partials<1>(acc, 1, part, sg.blocks());
 }
 
-// y = A x (library entry point for operator checks).
+// y = A x (operator checks; PIPEGCR's w = A u when st is given).
 __global__ void __launch_bounds__(kBlock)
-k_apply(Grid g, StencilGeom sg, const double* __restrict__ x, double* __restrict__ y) {
+k_apply(Grid g, StencilGeom sg, const double* __restrict__ x, double* __restrict__ y, const SolveState* st) {
+  if (st != nullptr && read_status(st) != kRunning) return;
   auto in = [&](long long t) { return x[t]; };
   auto sink = [&](long long idx, double, double Au) { y[idx] = Au; };
   stencil_march(g, sg, in, sink);
@@ -87,7 +89,7 @@ k_apply_pc_out(Grid g, StencilGeom sg, PcOutDesc pd, const double* X3, double c3
   auto in = [&](long long t) { double v = pc(t); if (X3 != nullptr) v += c3 * X3[t]; return v; };
   double acc[2] = {0.0, 0.0};
   auto sink = [&](long long idx, double mc, double nv) {
-    O[idx] = mc;
+    if (O != nullptr) O[idx] = mc;
     Nout[idx] = nv;
     if (dots) {
       acc[0] += mc * R[idx];
@@ -179,9 +181,12 @@ k_pipefcg_update(long long N, Window P, Window S, Window Q, Window Z,
   const long long ns = (long long)(j % numax) * P.ld;
   double gam = 0.0, del = 0.0, rho = 0.0, dnew = 0.0;
   const long long npair = (N + 1) / 2;
-  for (long long qi = gtid(); qi < npair; qi += gstride()) {
-    const long long e = 2 * qi;
-    const bool full = e + 1 < N;
+  // the trip count is uniform per wave (the in-loop wave sums need every lane);
+  // lanes past the end compute on element 0 and contribute nothing
+  for (long long qw = gtid() - lane; qw < npair; qw += gstride()) {
+    const bool act = qw + lane < npair;
+    const long long e = act ? 2 * (qw + lane) : 0;
+    const bool full = act && e + 1 < N;
     const double2 u0 = ld2(u, e, full), w0 = ld2(w, e, full);
     double2 p = u0, q = ld2(m, e, full), z = ld2(n, e, full);
 #pragma unroll 4
@@ -193,8 +198,9 @@ k_pipefcg_update(long long N, Window P, Window S, Window Q, Window Z,
       q.x += b * qv.x; q.y += b * qv.y;
       z.x += b * zv.x; z.y += b * zv.y;
     }
-    const double2 un = make_double2(u0.x - alpha * q.x, u0.y - alpha * q.y);
+    double2 un = make_double2(u0.x - alpha * q.x, u0.y - alpha * q.y);
     const double2 wn = make_double2(w0.x - alpha * z.x, w0.y - alpha * z.y);
+    if (!act) un = make_double2(0.0, 0.0);
     double2 sv = w0;
 #pragma unroll 4
     for (int t = 0; t < nu; ++t) {
@@ -206,6 +212,7 @@ k_pipefcg_update(long long N, Window P, Window S, Window Q, Window Z,
         if (lane == 0) s_dot[wid][t - shift] += d;
       }
     }
+    if (!act) continue;
     const double2 r0 = ld2(r, e, full);
     const double2 rn = make_double2(r0.x - alpha * sv.x, r0.y - alpha * sv.y);
     double2 x0 = ld2(x, e, full);
@@ -253,10 +260,7 @@ k_pipefcg_scalars(const double* part, int P, SolveState* st, double* hist) {
   if (read_status(st) != kRunning) return;
   const int j1 = st->j + 1;
   const int nu1 = trunc_nu(st->trunc, j1, st->nu_max);
-  for (int c = 0; c < 3 + nu1; ++c) {
-    const double v = block_sum_column(part, P, c);
-    if (threadIdx.x == 0) col[c] = v;
-  }
+  block_sum_columns(part, P, 3 + nu1, col);
   if (threadIdx.x != 0) return;
   const int it = st->it + 1;
   st->it = it;
@@ -286,7 +290,7 @@ k_pipefcg_scalars(const double* part, int P, SolveState* st, double* hist) {
 }
 
 // ---------------------------------------------------------------------------
-// FCG
+// FCG and GCR (two blocking reductions per iteration)
 // ---------------------------------------------------------------------------
 // x += alpha p_j, r -= alpha s_j for the newest direction j = st->j.
 __global__ void __launch_bounds__(kBlock)
@@ -303,47 +307,76 @@ k_fcg_xr(long long N, Window P, Window S, double* __restrict__ x, double* __rest
   }
 }
 
-// u = B(r) (finished from the inner solve's last step) and the first
-// reduction of iteration j+1: gamma = <u,r>, rho = <r,r>, <u, s_d> over the
-// window.  With `init` the window is empty (start-up, u_0 = B(r_0)).
+// The multi-dot of one vector V against R, itself and the window:
+// columns <V,R>, <V,V>, <R,R>, then <V, S_d> for d in window(j+1), j = st->j
+// (an empty window with `init`).  V is read from Vin, or formed from the
+// preconditioner's output (from_pc) and written to Vout.
+//   FCG:     V = u = B(r), R = r  (gamma = <u,r>, the test on <r,r>, <u,s_d>)
+//   GCR:     V = t = A u,  R = r  (the test on <r,r>, <t,s_d>)
+//   PIPEGCR: V = w = A u,  R = r  (gamma, delta, rho, <w,s_d>: its single reduction)
 __global__ void __launch_bounds__(kBlock)
-k_fcg_dots(long long N, int init, PcOutDesc pd, Window S, const double* __restrict__ r,
-           double* __restrict__ uout, double* part, SolveState* st) {
+k_multidot(long long N, int init, int from_pc, PcOutDesc pd, const double* __restrict__ Vin,
+           double* __restrict__ Vout, const double* __restrict__ R, Window S, double* part, SolveState* st) {
   if (read_status(st) != kRunning) return;
-  const PcOut pc = make_pc_out(pd, &st->pc);
+  PcOut pc{};
+  if (from_pc) pc = make_pc_out(pd, &st->pc);
   __shared__ long long s_off[kNuMax];
-  __shared__ double s_dot[kWaves][kNuMax + 2];
+  __shared__ double s_dot[kWaves][kNuMax + 3];
   const int j1 = st->j + 1;
   const int numax = st->nu_max;
   const int nu = init ? 0 : trunc_nu(st->trunc, j1, numax);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int t = threadIdx.x; t < nu; t += kBlock) s_off[t] = (long long)((j1 - nu + t) % numax) * S.ld;
-  for (int t = threadIdx.x; t < kWaves * (kNuMax + 2); t += kBlock) (&s_dot[0][0])[t] = 0.0;
+  for (int t = threadIdx.x; t < kWaves * (kNuMax + 3); t += kBlock) (&s_dot[0][0])[t] = 0.0;
   __syncthreads();
-  double gam = 0.0, rho = 0.0;
+  double vr = 0.0, vv = 0.0, rr = 0.0;
   const long long step = 2LL * gstride();
-  for (long long e0 = 2LL * blockIdx.x * kBlock + threadIdx.x; e0 < N; e0 += step) {
+  // wave-uniform trip count (wave sums inside); lanes past the end contribute 0
+  for (long long w0 = 2LL * blockIdx.x * kBlock + threadIdx.x - lane; w0 < N; w0 += step) {
+    const long long e0 = w0 + lane;
+    const bool h0 = e0 < N;
     const long long e1 = e0 + kBlock;
     const bool h1 = e1 < N;
-    const double u0 = pc(e0), u1 = h1 ? pc(e1) : 0.0;
-    const double r0 = r[e0], r1 = h1 ? r[e1] : 0.0;
-    uout[e0] = u0;
-    if (h1) uout[e1] = u1;
-    gam += u0 * r0 + u1 * r1;
-    rho += r0 * r0 + r1 * r1;
-#pragma unroll 4
-    for (int t = 0; t < nu; ++t) {
+    double v0 = 0.0, v1 = 0.0;
+    if (from_pc) {
+      if (h0) v0 = pc(e0);
+      if (h1) v1 = pc(e1);
+      if (h0) Vout[e0] = v0;
+      if (h1) Vout[e1] = v1;
+    } else {
+      if (h0) v0 = Vin[e0];
+      if (h1) v1 = Vin[e1];
+    }
+    const double r0 = h0 ? R[e0] : 0.0, r1 = h1 ? R[e1] : 0.0;
+    vr += v0 * r0 + v1 * r1;
+    vv += v0 * v0 + v1 * v1;
+    rr += r0 * r0 + r1 * r1;
+    int t = 0;
+    for (; t + 4 <= nu; t += 4) {
+      double a[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const long long o = s_off[t + q];
+        a[q] = (h0 ? v0 * S.base[o + e0] : 0.0) + (h1 ? v1 * S.base[o + e1] : 0.0);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double d = wave_sum(a[q]);
+        if (lane == 0) s_dot[wid][3 + t + q] += d;
+      }
+    }
+    for (; t < nu; ++t) {
       const long long o = s_off[t];
-      const double d = wave_sum(u0 * S.base[o + e0] + (h1 ? u1 * S.base[o + e1] : 0.0));
-      if (lane == 0) s_dot[wid][2 + t] += d;
+      const double d = wave_sum((h0 ? v0 * S.base[o + e0] : 0.0) + (h1 ? v1 * S.base[o + e1] : 0.0));
+      if (lane == 0) s_dot[wid][3 + t] += d;
     }
   }
   {
-    const double a0 = wave_sum(gam), a1 = wave_sum(rho);
-    if (lane == 0) { s_dot[wid][0] = a0; s_dot[wid][1] = a1; }
+    const double a0 = wave_sum(vr), a1 = wave_sum(vv), a2 = wave_sum(rr);
+    if (lane == 0) { s_dot[wid][0] = a0; s_dot[wid][1] = a1; s_dot[wid][2] = a2; }
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < 2 + nu; c += kBlock) {
+  for (int c = threadIdx.x; c < 3 + nu; c += kBlock) {
     double acc = 0.0;
 #pragma unroll
     for (int wv = 0; wv < kWaves; ++wv) acc += s_dot[wv][c];
@@ -351,17 +384,16 @@ k_fcg_dots(long long N, int init, PcOutDesc pd, Window S, const double* __restri
   }
 }
 
-// First-reduction scalars: iteration count, history, test, beta.
+// First-reduction scalars of FCG/GCR from k_multidot's columns: the
+// iteration count, history and test on ||r||, beta_d = -<V,s_d>/eta_d, and
+// (FCG) gamma = <u, r>.  With `init` only j = 0 and gamma are set.
 __global__ void __launch_bounds__(kBlock)
-k_fcg_scalars1(int init, const double* part, int P, SolveState* st, double* hist) {
-  __shared__ double col[kNuMax + 2];
+k_cg_scalars1(int init, const double* part, int P, SolveState* st, double* hist) {
+  __shared__ double col[kNuMax + 3];
   if (read_status(st) != kRunning) return;
   const int j1 = init ? 0 : st->j + 1;
   const int nu = init ? 0 : trunc_nu(st->trunc, j1, st->nu_max);
-  for (int c = 0; c < 2 + nu; ++c) {
-    const double v = block_sum_column(part, P, c);
-    if (threadIdx.x == 0) col[c] = v;
-  }
+  block_sum_columns(part, P, 3 + nu, col);
   if (threadIdx.x != 0) return;
   st->gamma = col[0];
   st->nu = nu;
@@ -369,18 +401,18 @@ k_fcg_scalars1(int init, const double* part, int P, SolveState* st, double* hist
   if (init) return;
   const int it = st->it + 1;
   st->it = it;
-  const double res = sqrt(col[1]);
+  const double res = sqrt(col[2]);
   hist[it] = res;
   if (!isfinite(res)) { st->status = kNonfinite; return; }
   if (res <= st->tol) { st->status = kConverged; return; }
   const int numax = st->nu_max;
   for (int t = 0; t < nu; ++t) {
     const int d = j1 - nu + t;
-    st->beta[t] = -col[2 + t] / st->eta_ring[d % numax];
+    st->beta[t] = -col[3 + t] / st->eta_ring[d % numax];
   }
 }
 
-// p_j = u + sum beta p_d into slot j.
+// p_j = u + sum beta p_d into slot j (FCG).
 __global__ void __launch_bounds__(kBlock)
 k_fcg_maxpy(long long N, Window P, const double* __restrict__ u, const SolveState* st) {
   if (read_status(st) != kRunning) return;
@@ -393,24 +425,64 @@ k_fcg_maxpy(long long N, Window P, const double* __restrict__ u, const SolveStat
   }
   __syncthreads();
   double* pn = P.slot(j % numax);
-  const long long step = 2LL * gstride();
-  for (long long e0 = 2LL * blockIdx.x * kBlock + threadIdx.x; e0 < N; e0 += step) {
-    const long long e1 = e0 + kBlock;
-    const bool h1 = e1 < N;
-    double p0 = u[e0], p1 = h1 ? u[e1] : 0.0;
-#pragma unroll 4
-    for (int t = 0; t < nu; ++t) {
-      const double b = s_beta[t];
-      const long long o = s_off[t];
-      p0 += b * P.base[o + e0];
-      if (h1) p1 += b * P.base[o + e1];
+  const long long npair = (N + 1) / 2;
+  for (long long qi = gtid(); qi < npair; qi += gstride()) {
+    const long long e = 2 * qi;
+    const bool full = e + 1 < N;
+    double2 p = ld2(u, e, full);
+    int t = 0;
+    for (; t + 4 <= nu; t += 4) {
+      double2 v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = ld2(P.base, s_off[t + q] + e, full);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) { p.x += s_beta[t + q] * v[q].x; p.y += s_beta[t + q] * v[q].y; }
     }
-    pn[e0] = p0;
-    if (h1) pn[e1] = p1;
+    for (; t < nu; ++t) {
+      const double2 v = ld2(P.base, s_off[t] + e, full);
+      p.x += s_beta[t] * v.x; p.y += s_beta[t] * v.y;
+    }
+    st2(pn, e, p, full);
   }
 }
 
-// s_j = A p_j, partial eta_j = <p_j, s_j>.
+// GCR: p_j = u + sum beta p_d, s_j = t + sum beta s_d into slot j, partials
+// <r, s_j>, <s_j, s_j> (gamma and eta of the second reduction).
+__global__ void __launch_bounds__(kBlock)
+k_gcr_maxpy(long long N, Window P, Window S, const double* __restrict__ u, const double* __restrict__ t_,
+            const double* __restrict__ r, double* part, const SolveState* st) {
+  if (read_status(st) != kRunning) return;
+  __shared__ double s_beta[kNuMax];
+  __shared__ long long s_off[kNuMax];
+  const int j = st->j, nu = st->nu, numax = st->nu_max;
+  for (int t = threadIdx.x; t < nu; t += kBlock) {
+    s_beta[t] = st->beta[t];
+    s_off[t] = (long long)((j - nu + t) % numax) * P.ld;
+  }
+  __syncthreads();
+  const long long ns = (long long)(j % numax) * P.ld;
+  double acc[2] = {0.0, 0.0};
+  const long long npair = (N + 1) / 2;
+  for (long long qi = gtid(); qi < npair; qi += gstride()) {
+    const long long e = 2 * qi;
+    const bool full = e + 1 < N;
+    double2 p = ld2(u, e, full), s = ld2(t_, e, full);
+    for (int t = 0; t < nu; ++t) {
+      const double b = s_beta[t];
+      const double2 pv = ld2(P.base, s_off[t] + e, full), sv = ld2(S.base, s_off[t] + e, full);
+      p.x += b * pv.x; p.y += b * pv.y;
+      s.x += b * sv.x; s.y += b * sv.y;
+    }
+    st2(P.base, ns + e, p, full);
+    st2(S.base, ns + e, s, full);
+    const double2 rv = ld2(r, e, full);
+    acc[0] += rv.x * s.x + rv.y * s.y;
+    acc[1] += s.x * s.x + s.y * s.y;
+  }
+  block_partials<2>(acc, 2, part, gridDim.x);
+}
+
+// s_j = A p_j, partial eta_j = <p_j, s_j> (FCG).
 __global__ void __launch_bounds__(kBlock)
 k_fcg_apply(Grid g, StencilGeom sg, Window P, Window S, double* part, const SolveState* st) {
   if (read_status(st) != kRunning) return;
@@ -427,12 +499,16 @@ k_fcg_apply(Grid g, StencilGeom sg, Window P, Window S, double* part, const Solv
   block_partials<1>(acc, 1, part, sg.blocks());
 }
 
-// Second-reduction scalars: eta_j, breakdown check, alpha_j.
+// Second-reduction scalars: eta_j (FCG: <p,s>; GCR: <s,s> with gamma = <r,s>),
+// breakdown check, alpha_j.
 __global__ void __launch_bounds__(kBlock)
-k_fcg_scalars2(int init, const double* part, int P, SolveState* st) {
+k_cg_scalars2(int gcr, int init, const double* part, int P, SolveState* st) {
   if (read_status(st) != kRunning) return;
-  const double eta = block_sum_column(part, P, 0);
+  const double c0 = block_sum_column(part, P, 0);
+  const double c1 = gcr ? block_sum_column(part, P, 1) : 0.0;
   if (threadIdx.x != 0) return;
+  const double eta = gcr ? c1 : c0;
+  if (gcr) st->gamma = c0;
   const int j = st->j;
   if (!init) {
     const bool forced = (st->force_it == st->it);
@@ -447,7 +523,7 @@ k_fcg_scalars2(int init, const double* part, int P, SolveState* st) {
   if (st->it >= st->maxit) st->status = kMaxit;
 }
 
-// FCG start-up test on ||r_0|| (history[0]).
+// Start-up test on ||r_0|| (history[0]).
 __global__ void __launch_bounds__(kBlock)
 k_init_test(const double* part, int P, SolveState* st, double* hist) {
   if (read_status(st) != kRunning) return;
@@ -458,6 +534,68 @@ k_init_test(const double* part, int P, SolveState* st, double* hist) {
   if (!isfinite(res)) { st->status = kNonfinite; return; }
   if (res <= st->tol) st->status = kConverged;
   else if (st->it >= st->maxit) st->status = kMaxit;
+}
+
+// ---------------------------------------------------------------------------
+// PIPEGCR (Alg. 11)
+// ---------------------------------------------------------------------------
+// Start-up scalars from the start-up multi-dot (V = w_0 = s_0 = A u_0,
+// R = r_0): gamma_0 = <r_0, s_0>, eta_0 = <s_0, s_0>, alpha_0.
+__global__ void __launch_bounds__(kBlock)
+k_pipegcr_init_scalars(const double* part, int P, SolveState* st) {
+  if (read_status(st) != kRunning) return;
+  const double gamma = block_sum_column(part, P, 0);
+  const double eta = block_sum_column(part, P, 1);
+  if (threadIdx.x != 0) return;
+  if (!(eta > 0.0) || !isfinite(eta)) { st->status = kBreakdown0; return; }
+  st->eta_ring[0] = eta;
+  st->alpha = gamma / eta;
+  st->j = 0;
+  st->nu = 0;
+  if (st->it >= st->maxit) st->status = kMaxit;
+}
+
+// Direction j (= st->j):  p_j = u + sum beta p_d,  s_j = w + sum beta s_d,
+// q_j = m + sum beta q_d into slot j, then x += alpha p_j, r -= alpha s_j,
+// u -= alpha q_j.  m = u + B(w - r) is evaluated from the inner solve's
+// output; for the first direction after a (re)start it is q_0's B(s_0).
+__global__ void __launch_bounds__(kBlock)
+k_pipegcr_update(long long N, Window P, Window S, Window Q, double* __restrict__ x, double* __restrict__ r,
+                 double* __restrict__ u, const double* __restrict__ w, PcOutDesc pd, SolveState* st) {
+  if (read_status(st) != kRunning) return;
+  __shared__ double s_beta[kNuMax];
+  __shared__ long long s_off[kNuMax];
+  const int j = st->j;
+  const int numax = st->nu_max;
+  const int nu = trunc_nu(st->trunc, j, numax);
+  const double alpha = st->alpha;
+  const bool first = (j == 0);
+  if (first) pd.X2 = nullptr;                  // q_0 = B(s_0): the start-up input was w alone
+  const PcOut pc = make_pc_out(pd, &st->pc);
+  const double cu = first ? 0.0 : 1.0;
+  for (int t = threadIdx.x; t < nu; t += kBlock) {
+    s_beta[t] = st->beta[t];
+    s_off[t] = (long long)((j - nu + t) % numax) * P.ld;
+  }
+  __syncthreads();
+  const long long ns = (long long)(j % numax) * P.ld;
+  for (long long e = gtid(); e < N; e += gstride()) {
+    const double ue = u[e];
+    double p = ue, s = w[e], q = cu * ue + pc(e);
+    for (int t = 0; t < nu; ++t) {
+      const double b = s_beta[t];
+      const long long o = s_off[t] + e;
+      p += b * P.base[o];
+      s += b * S.base[o];
+      q += b * Q.base[o];
+    }
+    P.base[ns + e] = p;
+    S.base[ns + e] = s;
+    Q.base[ns + e] = q;
+    x[e] += alpha * p;
+    r[e] -= alpha * s;
+    u[e] = ue - alpha * q;
+  }
 }
 
 }  // namespace pfk

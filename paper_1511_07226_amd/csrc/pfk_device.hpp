@@ -262,6 +262,20 @@ __device__ __forceinline__ double block_sum_column(const double* part, int P, in
   return r;
 }
 
+// Sum columns 0..ncol-1 of P partials into out[] (shared memory), one wave
+// per column in turn, fixed order.  Every thread must call this; out[] is
+// valid for all threads on return.
+__device__ __forceinline__ void block_sum_columns(const double* part, int P, int ncol, double* out) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int c = wid; c < ncol; c += kWaves) {
+    double s = 0.0;
+    for (int b = lane; b < P; b += 64) s += part[(long long)c * P + b];
+    s = wave_sum(s);
+    if (lane == 0) out[c] = s;
+  }
+  __syncthreads();
+}
+
 // Grid-stride geometry for pointwise kernels.
 __device__ __forceinline__ long long gtid() { return (long long)blockIdx.x * kBlock + threadIdx.x; }
 __device__ __forceinline__ long long gstride() { return (long long)gridDim.x * kBlock; }

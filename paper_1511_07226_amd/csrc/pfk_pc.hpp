@@ -12,6 +12,14 @@
 //   A_j : beta_j = gamma_j/gamma_{j-1};  p_j = D^-1 rho + beta_j p_{j-1};
 //         q = A p_j;  partial <p_j,q>                            (2 <= j <= k)
 //   tail: y + alpha_k p_k, folded into the consumer.
+// Global k-step right-Jacobi GMRES (one GMRES(k) cycle on A D^-1 t = v from
+// t = 0, classical Gram-Schmidt; the basis is stored unnormalised with its
+// scales in PcScalars::vs):
+//   G0  : V_0 = v;                               partial ||v||^2
+//   GA_j: w = A D^-1 V_j;                        partials <V_i, w>, i <= j
+//   GO_j: h_ij; V_{j+1} = w - sum h_ij V_i;      partial ||V_{j+1}||^2
+//   tail: least squares on the (k+1) x k Hessenberg by Givens rotations in
+//         the consumer's prologue, B(v) = D^-1 sum c_j V_j.
 // Every kernel reduces the partials of its predecessor in its prologue (all
 // workgroups in the same fixed order), so no extra launch sits between them.
 // Guards as in the definition: a zero preconditioned residual returns 0 and
@@ -33,8 +41,11 @@ struct PcOutDesc {
   const double* dinv;
   const double* y;              // inner iterate (PCG), or final output (block PCG)
   const double* pk;             // last inner direction (PCG)
-  const double* part;           // partials of the last inner kernel (PCG: <p_k,q>; A_1 also <v,p_1>)
+  const double* part;           // partials of the last inner kernel (PCG: <p_k,q>; A_1 also <v,p_1>;
+                                //   GMRES: ||V_k||^2)
   int P;
+  const double* vbase;          // inner GMRES basis (k+1 stored vectors, ldv apart)
+  long long ldv;
 };
 
 // Device-side evaluator of B(v) at a node, built in the consumer's prologue.
@@ -48,6 +59,10 @@ struct PcOut {
   double alpha;
   int use_y;                    // false when k == 1 (y is still zero)
   int add_p;                    // false when the inner solve stopped before step k
+  const double* vbase;          // inner GMRES: B(v) = dinv * sum cf_j V_j
+  long long ldv;
+  int nv;
+  const double* cf;             // nv coefficients (in LDS)
   __device__ __forceinline__ double v(long long t) const {
     double r = c1 * X1[t];
     if (X2 != nullptr) r += c2 * X2[t];
@@ -58,6 +73,11 @@ struct PcOut {
       case kPcNone: return v(t);
       case kPcJacobi: return dinv[t] * v(t);
       case kPcBlockPcg: return y[t];
+      case kPcJacobiGmres: {
+        double r = 0.0;
+        for (int q = 0; q < nv; ++q) r += cf[q] * vbase[(long long)q * ldv + t];
+        return dinv[t] * r;
+      }
       default: {
         double r = use_y ? y[t] : 0.0;
         if (add_p) r += alpha * pk[t];
@@ -87,6 +107,54 @@ __device__ __forceinline__ PcOut make_pc_out(const PcOutDesc& d, PcScalars* pcs)
     stopped = stopped || !(pq > 0.0);
     o.add_p = !stopped;
     o.alpha = stopped ? 0.0 : gk / pq;
+  }
+  o.vbase = d.vbase;
+  o.ldv = d.ldv;
+  o.nv = 0;
+  o.cf = nullptr;
+  if (d.kind == kPcJacobiGmres) {
+    // least squares min || beta0 e_0 - H c || over the active columns (Givens)
+    __shared__ double s_cf[kMaxInnerGmres];
+    __shared__ double H[(kMaxInnerGmres + 1) * kMaxInnerGmres];
+    __shared__ double g[kMaxInnerGmres + 1], cs[kMaxInnerGmres], sn[kMaxInnerGmres], yv[kMaxInnerGmres];
+    __shared__ int s_nv;
+    const int nc = pcs->ncol;
+    const double hk = (nc == d.k) ? sqrt(block_sum_column(d.part, d.P, 0)) : 0.0;
+    if (threadIdx.x == 0) {
+      constexpr int L = kMaxInner + 1, M = kMaxInnerGmres + 1;
+      for (int jj = 0; jj < nc; ++jj)
+        for (int ii = 0; ii <= jj + 1; ++ii) H[jj * M + ii] = pcs->h[jj * L + ii];
+      if (nc == d.k && nc > 0) H[(nc - 1) * M + nc] = hk;
+      for (int ii = 0; ii <= nc; ++ii) g[ii] = 0.0;
+      g[0] = pcs->beta0;
+      for (int jj = 0; jj < nc; ++jj) {
+        double* col = &H[jj * M];
+        for (int ii = 0; ii < jj; ++ii) {
+          const double a = col[ii], b = col[ii + 1];
+          col[ii] = cs[ii] * a + sn[ii] * b;
+          col[ii + 1] = -sn[ii] * a + cs[ii] * b;
+        }
+        const double a = col[jj], b = col[jj + 1];
+        const double dd = hypot(a, b);
+        cs[jj] = dd == 0.0 ? 1.0 : a / dd;
+        sn[jj] = dd == 0.0 ? 0.0 : b / dd;
+        col[jj] = dd;
+        col[jj + 1] = 0.0;
+        const double gi = g[jj];
+        g[jj] = cs[jj] * gi;
+        g[jj + 1] = -sn[jj] * gi;
+      }
+      for (int ii = nc - 1; ii >= 0; --ii) {
+        double acc = g[ii];
+        for (int jj = ii + 1; jj < nc; ++jj) acc -= H[jj * M + ii] * yv[jj];
+        yv[ii] = acc / H[ii * M + ii];
+      }
+      for (int ii = 0; ii < nc; ++ii) s_cf[ii] = yv[ii] * pcs->vs[ii];
+      s_nv = nc;
+    }
+    __syncthreads();
+    o.nv = s_nv;
+    o.cf = s_cf;
   }
   return o;
 }
@@ -181,6 +249,86 @@ k_pcg_a(int jstep, Grid g, StencilGeom sg, const double* __restrict__ dinv,
   };
   stencil_march(g, sg, in, sink);
   block_partials<1>(acc, 1, part_out, sg.blocks());
+}
+
+// ---- inner GMRES -----------------------------------------------------------
+// G0: V_0 = v (stored unnormalised), partial ||v||^2.
+__global__ void __launch_bounds__(kBlock)
+k_gmpc_start(long long N, int k, const double* X1, double c1, const double* X2, double c2,
+             double* __restrict__ V0, double* part_out, SolveState* st) {
+  if (read_status(st) != kRunning) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->pc.ncol = k;
+  double acc[1] = {0.0};
+  for (long long e = gtid(); e < N; e += gstride()) {
+    double v = c1 * X1[e];
+    if (X2 != nullptr) v += c2 * X2[e];
+    V0[e] = v;
+    acc[0] += v * v;
+  }
+  block_partials<1>(acc, 1, part_out, gridDim.x);
+}
+
+// GA_j: scale of V_j from the previous norm (a zero norm ends the cycle:
+// beta = 0 gives B(v) = 0, a zero subdiagonal is a happy breakdown), then
+// w = A D^-1 V_j and partials <stored V_i, w> for i <= j.
+__global__ void __launch_bounds__(kBlock)
+k_gmpc_apply(int jstep, Grid g, StencilGeom sg, const double* __restrict__ dinv, const double* Vbase,
+             long long ldv, double* __restrict__ w, const double* part_in, int P_in, double* part_out,
+             SolveState* st) {
+  if (read_status(st) != kRunning) return;
+  PcScalars* pcs = &st->pc;
+  if (jstep >= pcs->ncol) return;
+  const double nrm = sqrt(block_sum_column(part_in, P_in, 0));
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (jstep == 0) pcs->beta0 = nrm;
+    else pcs->h[(jstep - 1) * (kMaxInner + 1) + jstep] = nrm;
+    pcs->vs[jstep] = nrm == 0.0 ? 0.0 : 1.0 / nrm;
+    if (nrm == 0.0) pcs->ncol = jstep;
+  }
+  if (nrm == 0.0) return;
+  const double sj = 1.0 / nrm;
+  const double* Vj = Vbase + (long long)jstep * ldv;
+  double acc[kMaxInnerGmres];
+#pragma unroll
+  for (int q = 0; q < kMaxInnerGmres; ++q) acc[q] = 0.0;
+  auto in = [&](long long t) { return dinv[t] * (sj * Vj[t]); };
+  auto sink = [&](long long idx, double, double Au) {
+    w[idx] = Au;
+#pragma unroll
+    for (int q = 0; q < kMaxInnerGmres; ++q)
+      if (q <= jstep) acc[q] += Vbase[(long long)q * ldv + idx] * Au;
+  };
+  stencil_march(g, sg, in, sink);
+  block_partials<kMaxInnerGmres>(acc, jstep + 1, part_out, sg.blocks());
+}
+
+// GO_j: h_ij = <V_i, w> (classical Gram-Schmidt), V_{j+1} = w - sum h_ij V_i
+// stored unnormalised (not stored for the last step), partial ||V_{j+1}||^2.
+__global__ void __launch_bounds__(kBlock)
+k_gmpc_orth(int jstep, int k, long long N, double* Vbase, long long ldv, const double* __restrict__ w,
+            const double* part_in, int P_in, double* part_out, SolveState* st) {
+  if (read_status(st) != kRunning) return;
+  PcScalars* pcs = &st->pc;
+  if (jstep >= pcs->ncol) return;
+  __shared__ double coef[kMaxInnerGmres];
+  for (int q = 0; q <= jstep; ++q) {
+    const double hq = pcs->vs[q] * block_sum_column(part_in, P_in, q);
+    if (threadIdx.x == 0) {
+      coef[q] = hq * pcs->vs[q];
+      if (blockIdx.x == 0) pcs->h[jstep * (kMaxInner + 1) + q] = hq;
+    }
+  }
+  __syncthreads();
+  const bool store = jstep + 1 < k;
+  double* Vn = Vbase + (long long)(jstep + 1) * ldv;
+  double acc[1] = {0.0};
+  for (long long e = gtid(); e < N; e += gstride()) {
+    double v = w[e];
+    for (int q = 0; q <= jstep; ++q) v -= coef[q] * Vbase[(long long)q * ldv + e];
+    if (store) Vn[e] = v;
+    acc[0] += v * v;
+  }
+  block_partials<1>(acc, 1, part_out, gridDim.x);
 }
 
 }  // namespace pfk

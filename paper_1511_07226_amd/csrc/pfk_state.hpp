@@ -25,12 +25,15 @@ constexpr int kMaxInner = 32;      // largest inner iteration count of a precond
 struct PcScalars {                 // one inner solve's scalars, indexed by inner step
   double gamma[kMaxInner + 2];
   int stopped[kMaxInner + 2];
-  // inner GMRES: Hessenberg, Givens data and solution coefficients
+  // inner GMRES: Hessenberg h(i,j) at h[j*(kMaxInner+1)+i], basis scales
+  // (V_j = vs[j] * stored vector j), active columns
   double h[(kMaxInner + 1) * kMaxInner];
-  double cs[kMaxInner], sn[kMaxInner], g[kMaxInner + 1], c[kMaxInner];
+  double vs[kMaxInner + 1];
   double beta0;
   int ncol;
 };
+
+constexpr int kMaxInnerGmres = 8;  // inner GMRES steps supported
 
 struct SolveState {
   int status;
@@ -53,10 +56,13 @@ struct SolveState {
   double beta[kNuMax];       // beta of the current update, window order (oldest first)
   // GMRES family (restart length m <= kNuMax)
   int col;           // Arnoldi columns finished in this cycle
+  int pend;          // 1: the cycle ended and x = x0 + U y is (re)applied by k_gm_update_x
+  int ycols;         // columns of y
   int pad1;
   double beta0;      // ||r_0|| of the cycle
   double hbar[kNuMax + 1];
   double hn;         // norm of the new basis vector (h_{i,i-1})
+  double inv_hn;     // 1 / hn, scales the next basis vectors
   double R[(kNuMax + 1) * kNuMax];   // rotated Hessenberg, column-major (m+1) x m
   double cs[kNuMax], sn[kNuMax], g[kNuMax + 1], y[kNuMax];
   PcScalars pc;
