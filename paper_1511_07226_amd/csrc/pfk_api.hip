@@ -59,6 +59,32 @@ k_dinv(Grid g, StencilGeom sg, double* __restrict__ dinv) {
   });
 }
 
+// D^-1 of the mixed-precision inner operator (BF16 eta, FP32 velocities),
+// in FP32: the inner stencil applied to the unit vector at i.
+__global__ void __launch_bounds__(kBlock)
+k_dinv_mixed(GridM g, StencilGeom sg, float* __restrict__ dinv) {
+  const int L = xcd_tile(sg.blocks());
+  const int tx = L % sg.tiles_x;
+  const int ty = (L / sg.tiles_x) % sg.tiles_y;
+  const int tz = L / (sg.tiles_x * sg.tiles_y);
+  const int i = tx * kTileX + (threadIdx.x & 63);
+  const int k0 = tz * sg.zc;
+  const int k1 = min(g.nz, k0 + sg.zc);
+  for (int r = 0; r < 2; ++r) {
+    const int j = ty * kTileY + (threadIdx.x >> 6) + 4 * r;
+    if (i >= g.nx || j >= g.ny) continue;
+    for (int k = k0; k < k1; ++k) {
+      const long long pc = padded_index(g, i, j, k);
+      const bool d3 = g.dim == 3;
+      auto E = [&](long long q) { return to_real(g.eta[q]); };
+      const float d = apply_faces<float>(g, pc, 1.0f, E(pc), E(pc + 1), E(pc - 1), E(pc + g.sy), E(pc - g.sy),
+                                         d3 ? E(pc + g.sz) : 0.0f, d3 ? E(pc - g.sz) : 0.0f, 0.f, 0.f, 0.f, 0.f,
+                                         0.f, 0.f);
+      dinv[vec_index(g, i, j, k)] = 1.0f / d;
+    }
+  }
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_dot(long long N, const double* __restrict__ a, const double* __restrict__ b, double* part) {
   double acc[1] = {0.0};
@@ -112,6 +138,20 @@ struct pfk_operator_s {
   long long npad = 0;
   StencilGeom sg{};
   int pv_blocks = 0;       // workgroups of pointwise kernels
+  // mixed-precision inner operator (made when a mixed preconditioner is created)
+  __hip_bfloat16* eta_bf16 = nullptr;
+  float* vel_f32 = nullptr;
+  float* dinv_f32 = nullptr;
+
+  GridM grid_mixed() const {
+    GridM g;
+    const Grid d = grid();
+    g.dim = d.dim; g.nx = d.nx; g.ny = d.ny; g.nz = d.nz; g.N = d.N; g.sy = d.sy; g.sz = d.sz;
+    g.vstride = d.vstride; g.h2inv = d.h2inv; g.hinv = d.hinv;
+    g.eta = eta_bf16;
+    g.vel = vel ? vel_f32 : nullptr;
+    return g;
+  }
 
   Grid grid() const {
     Grid g;
@@ -230,6 +270,9 @@ extern "C" void pfk_operator_destroy(pfk_operator A) {
   if (A->eta) (void)hipFree(A->eta);
   if (A->vel) (void)hipFree(A->vel);
   if (A->dinv) (void)hipFree(A->dinv);
+  if (A->eta_bf16) (void)hipFree(A->eta_bf16);
+  if (A->vel_f32) (void)hipFree(A->vel_f32);
+  if (A->dinv_f32) (void)hipFree(A->dinv_f32);
   delete A;
 }
 
@@ -249,6 +292,55 @@ extern "C" int pfk_operator_diag_inv(pfk_operator A, double* dinv, void* stream)
   return PFK_OK;
 }
 
+// Round a finite double to the nearest BF16, ties to even, directly from the
+// 52-bit mantissa (no intermediate FP32 rounding).  Values here are positive
+// normal numbers (viscosities).
+static uint16_t bf16_rne(double x) {
+  uint64_t b;
+  std::memcpy(&b, &x, 8);
+  const uint64_t sign = b >> 63;
+  int e = (int)((b >> 52) & 0x7FF) - 1023 + 127;
+  uint64_t m = b & ((1ULL << 52) - 1);
+  if (x == 0.0) return (uint16_t)(sign << 15);
+  uint64_t m7 = m >> 45;
+  const uint64_t rem = m & ((1ULL << 45) - 1);
+  const uint64_t half = 1ULL << 44;
+  if (rem > half || (rem == half && (m7 & 1))) {
+    ++m7;
+    if (m7 == 128) { m7 = 0; ++e; }
+  }
+  if (e <= 0) e = 0, m7 = 0;            // flush (not reached for viscosities)
+  if (e >= 255) e = 254, m7 = 127;      // clamp (not reached for viscosities)
+  return (uint16_t)((sign << 15) | ((uint64_t)e << 7) | m7);
+}
+
+// BF16 eta, FP32 velocities and the FP32 D^-1 of that inner operator.
+static int ensure_mixed(pfk_operator_s* A) {
+  if (A->eta_bf16) return PFK_OK;
+  std::vector<double> heta((size_t)A->npad);
+  if (hipMemcpy(heta.data(), A->eta, sizeof(double) * A->npad, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(PFK_ERR_HIP, "reading eta");
+  std::vector<uint16_t> hb((size_t)A->npad);
+  for (size_t i = 0; i < hb.size(); ++i) hb[i] = bf16_rne(heta[i]);
+  if (hipMalloc(&A->eta_bf16, 2 * A->npad) != hipSuccess || hipMalloc(&A->dinv_f32, 4 * A->N) != hipSuccess)
+    return fail(PFK_ERR_OOM, "mixed-precision operator");
+  if (hipMemcpy(A->eta_bf16, hb.data(), 2 * A->npad, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(PFK_ERR_HIP, "copying eta");
+  if (A->vel) {
+    std::vector<double> hv((size_t)(3 * A->npad));
+    std::vector<float> hf(hv.size());
+    if (hipMemcpy(hv.data(), A->vel, sizeof(double) * hv.size(), hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(PFK_ERR_HIP, "reading velocities");
+    for (size_t i = 0; i < hv.size(); ++i) hf[i] = (float)hv[i];
+    if (hipMalloc(&A->vel_f32, sizeof(float) * hf.size()) != hipSuccess) return fail(PFK_ERR_OOM, "velocities");
+    if (hipMemcpy(A->vel_f32, hf.data(), sizeof(float) * hf.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(PFK_ERR_HIP, "copying velocities");
+  }
+  hipLaunchKernelGGL(k_dinv_mixed, dim3(A->sg.blocks()), dim3(kBlock), 0, 0, A->grid_mixed(), A->sg, A->dinv_f32);
+  if (hipDeviceSynchronize() != hipSuccess) return fail(PFK_ERR_HIP, "mixed diagonal");
+  return PFK_OK;
+}
+
 extern "C" int pfk_precond_create(pfk_operator A, pfk_pc_kind kind, int inner_its, pfk_precision prec,
                                   int block, pfk_precond* out) {
   if (!out || !A) return fail(PFK_ERR_ARG, "null argument");
@@ -260,8 +352,12 @@ extern "C" int pfk_precond_create(pfk_operator A, pfk_pc_kind kind, int inner_it
   if (prec != PFK_FP64 && prec != PFK_FP32_BF16COEF) return fail(PFK_ERR_ARG, "unknown precision");
   if (kind == PFK_PC_JACOBI_GMRES && inner_its > kMaxInnerGmres)
     return fail(PFK_ERR_ARG, "inner GMRES supports at most 8 steps");
-  if (kind == PFK_PC_BLOCK_JACOBI_PCG || prec != PFK_FP64)
-    return fail(PFK_ERR_ARG, "preconditioner kind/precision not available in this build");
+  if (kind == PFK_PC_BLOCK_JACOBI_PCG)
+    return fail(PFK_ERR_ARG, "preconditioner kind not available in this build");
+  if (prec == PFK_FP32_BF16COEF && (kind == PFK_PC_JACOBI_PCG || kind == PFK_PC_JACOBI_GMRES)) {
+    const int rc = ensure_mixed(A);
+    if (rc) return rc;
+  }
   auto* B = new (std::nothrow) pfk_precond_s();
   if (!B) return fail(PFK_ERR_OOM, "host allocation");
   B->A = A;
@@ -438,8 +534,10 @@ PcOutDesc pc_out_desc(const pfk_session_s* S, const double* X1, double c1, const
   PcOutDesc d{};
   d.kind = S->B->kind;
   d.k = S->B->k;
+  d.fp32 = S->B->prec == PFK_FP32_BF16COEF && (d.kind == kPcJacobiPcg || d.kind == kPcJacobiGmres);
   d.X1 = X1; d.c1 = c1; d.X2 = X2; d.c2 = c2;
   d.dinv = S->A->dinv;
+  d.dinv_in = d.fp32 ? (const void*)S->A->dinv_f32 : (const void*)S->A->dinv;
   if (d.kind == kPcJacobiPcg) {
     // A_1, (B_j, A_{j+1}) alternate the partial buffers: A_k writes PC0
     d.y = S->vec(V_PC_Y);
@@ -456,45 +554,59 @@ PcOutDesc pc_out_desc(const pfk_session_s* S, const double* X1, double c1, const
   return d;
 }
 
-PcOutDesc enqueue_pc(pfk_session_s* S, hipStream_t s, const double* X1, double c1, const double* X2,
-                     double c2) {
+// The inner solve's kernels in arithmetic type T on operator description G
+// (FP64 on the outer operator, or FP32 on the BF16 one).  Its work vectors
+// are the session's inner vectors viewed as T.
+template <class T, class G>
+void enqueue_pc_kernels(pfk_session_s* S, hipStream_t s, const PcOutDesc& d, const G& g, const T* dinv) {
   const pfk_operator_s* A = S->A;
-  const PcOutDesc d = pc_out_desc(S, X1, c1, X2, c2);
-  const Grid g = S->grid();
+  const double *X1 = d.X1, *X2 = d.X2;
+  const double c1 = d.c1, c2 = d.c2;
   double* part[2] = {S->part(PT_PC0), S->part(PT_PC1)};
   if (d.kind == kPcJacobiPcg) {
-    double* pp[2] = {S->vec(V_PC_P0), S->vec(V_PC_P1)};
-    double* q = S->vec(V_PC_Q);
-    double* rho = S->vec(V_PC_RHO);
-    double* y = S->vec(V_PC_Y);
-    LAUNCH(k_pcg_a1, S->Ps(), s, g, A->sg, A->dinv, X1, c1, X2, c2, pp[0], q, part[0], S->st);
+    T* pp[2] = {(T*)S->vec(V_PC_P0), (T*)S->vec(V_PC_P1)};
+    T* q = (T*)S->vec(V_PC_Q);
+    T* rho = (T*)S->vec(V_PC_RHO);
+    T* y = (T*)S->vec(V_PC_Y);
+    LAUNCH((k_pcg_a1<T, G>), S->Ps(), s, g, A->sg, dinv, X1, c1, X2, c2, pp[0], q, part[0],
+           (const SolveState*)S->st);
     int t = 1, Pprev = S->Ps();
     for (int j = 1; j < d.k; ++j) {
-      LAUNCH(k_pcg_b, S->Pv(), s, j, A->N, A->dinv, X1, c1, X2, c2, pp[(j - 1) & 1], q, rho, y,
-             part[(t - 1) & 1], Pprev, part[t & 1], S->st);
+      LAUNCH((k_pcg_b<T>), S->Pv(), s, j, A->N, dinv, X1, c1, X2, c2, (const T*)pp[(j - 1) & 1], (const T*)q, rho,
+             y, (const double*)part[(t - 1) & 1], Pprev, part[t & 1], S->st);
       Pprev = S->Pv();
       ++t;
-      LAUNCH(k_pcg_a, S->Ps(), s, j + 1, g, A->sg, A->dinv, rho, pp[(j - 1) & 1], pp[j & 1], q,
-             part[(t - 1) & 1], Pprev, part[t & 1], S->st);
+      LAUNCH((k_pcg_a<T, G>), S->Ps(), s, j + 1, g, A->sg, dinv, (const T*)rho, (const T*)pp[(j - 1) & 1],
+             pp[j & 1], q, (const double*)part[(t - 1) & 1], Pprev, part[t & 1], S->st);
       Pprev = S->Ps();
       ++t;
     }
   } else if (d.kind == kPcJacobiGmres) {
-    const Window V = S->win(W_PCV);
-    double* w = S->vec(V_PC_Q);
-    LAUNCH(k_gmpc_start, S->Pv(), s, A->N, d.k, X1, c1, X2, c2, V.base, part[0], S->st);
+    T* V = (T*)S->win(W_PCV).base;
+    const long long ldv = S->L.ld;
+    T* w = (T*)S->vec(V_PC_Q);
+    LAUNCH((k_gmpc_start<T>), S->Pv(), s, A->N, d.k, X1, c1, X2, c2, V, part[0], S->st);
     int t = 1, Pprev = S->Pv();
     for (int j = 0; j < d.k; ++j) {
-      LAUNCH(k_gmpc_apply, S->Ps(), s, j, g, A->sg, A->dinv, (const double*)V.base, V.ld, w,
-             part[(t - 1) & 1], Pprev, part[t & 1], S->st);
+      LAUNCH((k_gmpc_apply<T, G>), S->Ps(), s, j, g, A->sg, dinv, (const T*)V, ldv, w,
+             (const double*)part[(t - 1) & 1], Pprev, part[t & 1], S->st);
       Pprev = S->Ps();
       ++t;
-      LAUNCH(k_gmpc_orth, S->Pv(), s, j, d.k, A->N, V.base, V.ld, (const double*)w, part[(t - 1) & 1], Pprev,
-             part[t & 1], S->st);
+      LAUNCH((k_gmpc_orth<T>), S->Pv(), s, j, d.k, A->N, V, ldv, (const T*)w, (const double*)part[(t - 1) & 1],
+             Pprev, part[t & 1], S->st);
       Pprev = S->Pv();
       ++t;
     }
   }
+}
+
+// Enqueue the inner solve B(v), v = c1*X1 + c2*X2; returns how the consumer
+// evaluates B(v).
+PcOutDesc enqueue_pc(pfk_session_s* S, hipStream_t s, const double* X1, double c1, const double* X2,
+                     double c2) {
+  const PcOutDesc d = pc_out_desc(S, X1, c1, X2, c2);
+  if (d.fp32) enqueue_pc_kernels<float>(S, s, d, S->A->grid_mixed(), (const float*)S->A->dinv_f32);
+  else enqueue_pc_kernels<double>(S, s, d, S->grid(), (const double*)S->A->dinv);
   return d;
 }
 

@@ -64,7 +64,7 @@ k_residual(Grid g, StencilGeom sg, const double* __restrict__ b, const double* _
     r[idx] = rv;
     acc[0] += rv * rv;
   };
-  stencil_march(g, sg, in, sink);
+  stencil_march<double>(g, sg, in, sink);
   block_partials<1>(acc, 1, part, sg.blocks());
 }
 
@@ -74,7 +74,7 @@ k_apply(Grid g, StencilGeom sg, const double* __restrict__ x, double* __restrict
   if (st != nullptr && read_status(st) != kRunning) return;
   auto in = [&](long long t) { return x[t]; };
   auto sink = [&](long long idx, double, double Au) { y[idx] = Au; };
-  stencil_march(g, sg, in, sink);
+  stencil_march<double>(g, sg, in, sink);
 }
 
 // O = c3*X3 + B(v) at every node, N = A O.  With `dots`: partials <O, R>, <O, N>.
@@ -96,7 +96,7 @@ k_apply_pc_out(Grid g, StencilGeom sg, PcOutDesc pd, const double* X3, double c3
       acc[1] += mc * nv;
     }
   };
-  stencil_march(g, sg, in, sink);
+  stencil_march<double>(g, sg, in, sink);
   if (dots) block_partials<2>(acc, 2, part, sg.blocks());
 }
 
@@ -495,7 +495,7 @@ k_fcg_apply(Grid g, StencilGeom sg, Window P, Window S, double* part, const Solv
     s[idx] = sv;
     acc[0] += pc * sv;
   };
-  stencil_march(g, sg, in, sink);
+  stencil_march<double>(g, sg, in, sink);
   block_partials<1>(acc, 1, part, sg.blocks());
 }
 

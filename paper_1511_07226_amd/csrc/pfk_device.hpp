@@ -25,75 +25,86 @@ constexpr int kHalo = 2 * kTileX + 2 * kTileY;   // in-plane halo nodes of a til
 constexpr int kNuMax = 64;         // largest window / restart length supported
 
 // ---------------------------------------------------------------------------
-// Operator description passed by value to kernels.
+// Operator description passed by value to kernels.  C is the stored
+// viscosity type, V the face-velocity type: FP64/FP64 for the operator of the
+// outer iteration, BF16/FP32 for the mixed-precision inner solve.
 // ---------------------------------------------------------------------------
-template <class C>
+template <class C, class V = C>
 struct GridT {
   int dim, nx, ny, nz;             // interior sizes; nz == 1 for 2D
   long long N;                     // nx*ny*nz
   long long sy, sz;                // padded strides: nx+2 and (nx+2)(ny+2)
   long long vstride;               // padded node count (offset between velocity components)
   double h2inv, hinv;              // 1/h^2 and 1/h
-  const C* eta;                    // padded viscosity (FP64, or BF16 for the mixed inner solve)
-  const C* vel;                    // 3*vstride face velocities or nullptr
+  const C* eta;                    // padded viscosity
+  const V* vel;                    // 3*vstride face velocities or nullptr
 };
-using Grid = GridT<double>;
+using Grid = GridT<double, double>;
+using GridM = GridT<__hip_bfloat16, float>;
 
-__device__ __forceinline__ long long padded_index(const Grid& g, int i, int j, int k) {
+__device__ __forceinline__ double to_real(double x) { return x; }
+__device__ __forceinline__ float to_real(float x) { return x; }
+__device__ __forceinline__ float to_real(__hip_bfloat16 x) { return __bfloat162float(x); }
+
+template <class G>
+__device__ __forceinline__ long long padded_index(const G& g, int i, int j, int k) {
   return (g.dim == 3 ? (long long)(k + 1) * g.sz : 0) + (long long)(j + 1) * g.sy + (i + 1);
 }
 
-__device__ __forceinline__ long long vec_index(const Grid& g, int i, int j, int k) {
+template <class G>
+__device__ __forceinline__ long long vec_index(const G& g, int i, int j, int k) {
   return ((long long)k * g.ny + j) * g.nx + i;
 }
 
-__device__ __forceinline__ double harmonic(double a, double b) { return 2.0 * a * b / (a + b); }
+template <class T>
+__device__ __forceinline__ T harmonic(T a, T b) { return T(2) * a * b / (a + b); }
 
 // (A u) at the node with padded index pc from its value uc, its six
 // neighbour values (0 on the Dirichlet boundary) and the viscosities at the
-// node and its neighbours.  Diffusion: h^-2 sum_f k_f (u_c - u_nb) with k_f
-// the harmonic mean of eta; convection (if g.vel): first-order upwind flux
-// h^-1 sum_f (max(v_f,0) u_c + min(v_f,0) u_nb) with v_f the outward normal
-// velocity.  Faces are taken in the order x+, x-, y+, y-, z+, z-.
-__device__ __forceinline__ double apply_faces(const Grid& g, long long pc, double uc, double ec,
-                                              double exp_, double exm, double eyp, double eym,
-                                              double ezp, double ezm, double uxp, double uxm,
-                                              double uyp, double uym, double uzp, double uzm) {
-  double acc = harmonic(ec, exp_) * (uc - uxp) + harmonic(ec, exm) * (uc - uxm) +
-               harmonic(ec, eyp) * (uc - uyp) + harmonic(ec, eym) * (uc - uym);
+// node and its neighbours, in arithmetic type T.  Diffusion:
+// h^-2 sum_f k_f (u_c - u_nb) with k_f the harmonic mean of eta; convection
+// (if g.vel): first-order upwind flux h^-1 sum_f (max(v_f,0) u_c +
+// min(v_f,0) u_nb) with v_f the outward normal velocity.  Faces are taken in
+// the order x+, x-, y+, y-, z+, z-.
+template <class T, class G>
+__device__ __forceinline__ T apply_faces(const G& g, long long pc, T uc, T ec, T exp_, T exm, T eyp, T eym,
+                                         T ezp, T ezm, T uxp, T uxm, T uyp, T uym, T uzp, T uzm) {
+  T acc = harmonic(ec, exp_) * (uc - uxp) + harmonic(ec, exm) * (uc - uxm) +
+          harmonic(ec, eyp) * (uc - uyp) + harmonic(ec, eym) * (uc - uym);
   if (g.dim == 3) acc += harmonic(ec, ezp) * (uc - uzp) + harmonic(ec, ezm) * (uc - uzm);
-  acc *= g.h2inv;
+  acc *= T(g.h2inv);
   if (g.vel != nullptr) {
-    const double* vx = g.vel;
-    const double* vy = g.vel + g.vstride;
-    const double* vz = g.vel + 2 * g.vstride;
-    double c = 0.0, v;
-    v = vx[pc];            c += fmax(v, 0.0) * uc + fmin(v, 0.0) * uxp;
-    v = -vx[pc - 1];       c += fmax(v, 0.0) * uc + fmin(v, 0.0) * uxm;
-    v = vy[pc];            c += fmax(v, 0.0) * uc + fmin(v, 0.0) * uyp;
-    v = -vy[pc - g.sy];    c += fmax(v, 0.0) * uc + fmin(v, 0.0) * uym;
+    const auto* vx = g.vel;
+    const auto* vy = g.vel + g.vstride;
+    const auto* vz = g.vel + 2 * g.vstride;
+    const T zero = T(0);
+    T c = zero, v;
+    v = T(to_real(vx[pc]));            c += fmax(v, zero) * uc + fmin(v, zero) * uxp;
+    v = -T(to_real(vx[pc - 1]));       c += fmax(v, zero) * uc + fmin(v, zero) * uxm;
+    v = T(to_real(vy[pc]));            c += fmax(v, zero) * uc + fmin(v, zero) * uyp;
+    v = -T(to_real(vy[pc - g.sy]));    c += fmax(v, zero) * uc + fmin(v, zero) * uym;
     if (g.dim == 3) {
-      v = vz[pc];          c += fmax(v, 0.0) * uc + fmin(v, 0.0) * uzp;
-      v = -vz[pc - g.sz];  c += fmax(v, 0.0) * uc + fmin(v, 0.0) * uzm;
+      v = T(to_real(vz[pc]));          c += fmax(v, zero) * uc + fmin(v, zero) * uzp;
+      v = -T(to_real(vz[pc - g.sz]));  c += fmax(v, zero) * uc + fmin(v, zero) * uzm;
     }
-    acc += g.hinv * c;
+    acc += T(g.hinv) * c;
   }
   return acc;
 }
 
-// (A u) at interior node (i,j,k), flat index idx, one node at a time: U is an
-// accessor for interior neighbour values.
+// (A u) at interior node (i,j,k), flat index idx, one node at a time, FP64:
+// U is an accessor for interior neighbour values.
 template <class F>
 __device__ __forceinline__ double stencil_at(const Grid& g, int i, int j, int k, long long idx,
                                              double uc, F&& U) {
   const long long pc = padded_index(g, i, j, k);
   const long long nxy = (long long)g.nx * g.ny;
   const bool d3 = g.dim == 3;
-  return apply_faces(g, pc, uc, g.eta[pc], g.eta[pc + 1], g.eta[pc - 1], g.eta[pc + g.sy], g.eta[pc - g.sy],
-                     d3 ? g.eta[pc + g.sz] : 0.0, d3 ? g.eta[pc - g.sz] : 0.0,
-                     (i + 1 < g.nx) ? U(idx + 1) : 0.0, (i > 0) ? U(idx - 1) : 0.0,
-                     (j + 1 < g.ny) ? U(idx + g.nx) : 0.0, (j > 0) ? U(idx - g.nx) : 0.0,
-                     (d3 && k + 1 < g.nz) ? U(idx + nxy) : 0.0, (d3 && k > 0) ? U(idx - nxy) : 0.0);
+  return apply_faces<double>(g, pc, uc, g.eta[pc], g.eta[pc + 1], g.eta[pc - 1], g.eta[pc + g.sy],
+                             g.eta[pc - g.sy], d3 ? g.eta[pc + g.sz] : 0.0, d3 ? g.eta[pc - g.sz] : 0.0,
+                             (i + 1 < g.nx) ? U(idx + 1) : 0.0, (i > 0) ? U(idx - 1) : 0.0,
+                             (j + 1 < g.ny) ? U(idx + g.nx) : 0.0, (j > 0) ? U(idx - g.nx) : 0.0,
+                             (d3 && k + 1 < g.nz) ? U(idx + nxy) : 0.0, (d3 && k > 0) ? U(idx - nxy) : 0.0);
 }
 
 // Stencil launch geometry: a workgroup owns a 64 x 8 tile of x-y nodes and
@@ -131,15 +142,16 @@ __device__ __forceinline__ void for_tile_nodes(const Grid& g, const StencilGeom&
   }
 }
 
-// The hot stencil engine.  A workgroup walks its tile up the z-axis.  Each
-// node's input value u = in(flat index) is formed once: z-neighbours stay in
-// registers (three planes), in-plane neighbours come from an LDS copy of the
-// current plane with a one-node halo (halo values are formed by 144 of the
-// 256 threads).  Values outside the domain are 0 (Dirichlet).  For every
-// interior node the engine calls sink(flat index, u, (A u)).
-template <class In, class Sink>
-__device__ __forceinline__ void stencil_march(const Grid& g, const StencilGeom& sg, const In& in, Sink& sink) {
-  __shared__ double su[kTileY + 2][kTileX + 2];
+// The hot stencil engine, in arithmetic type T.  A workgroup walks its tile
+// up the z-axis.  Each node's input value u = in(flat index) is formed once:
+// z-neighbours stay in registers (three planes), in-plane neighbours come from
+// an LDS copy of the current plane with a one-node halo (halo values are
+// formed by 144 of the 256 threads).  Values outside the domain are 0
+// (Dirichlet).  For every interior node the engine calls
+// sink(flat index, u, (A u)).
+template <class T, class G, class In, class Sink>
+__device__ __forceinline__ void stencil_march(const G& g, const StencilGeom& sg, const In& in, Sink& sink) {
+  __shared__ T su[kTileY + 2][kTileX + 2];
   const int L = xcd_tile(sg.blocks());
   const int tx = L % sg.tiles_x;
   const int ty = (L / sg.tiles_x) % sg.tiles_y;
@@ -150,6 +162,7 @@ __device__ __forceinline__ void stencil_march(const Grid& g, const StencilGeom& 
   const int k0 = tz * sg.zc;
   const int k1 = min(g.nz, k0 + sg.zc);
   const bool d3 = g.dim == 3;
+  const T zero = T(0);
   int jr[2];
   bool valid[2];
 #pragma unroll
@@ -167,21 +180,21 @@ __device__ __forceinline__ void stencil_march(const Grid& g, const StencilGeom& 
   const bool has_halo = t < kHalo;
   const bool hvalid = has_halo && hi >= 0 && hi < g.nx && hj >= 0 && hj < g.ny;
 
-  double um[2], uc[2], up[2], em[2], ec[2], ep[2];
+  T um[2], uc[2], up[2], em[2], ec[2], ep[2];
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
-    um[r] = (valid[r] && d3 && k0 > 0) ? in(vec_index(g, i, jr[r], k0 - 1)) : 0.0;
-    uc[r] = (valid[r] && k0 < k1) ? in(vec_index(g, i, jr[r], k0)) : 0.0;
-    em[r] = (valid[r] && d3) ? g.eta[padded_index(g, i, jr[r], k0 - 1)] : 0.0;
-    ec[r] = valid[r] ? g.eta[padded_index(g, i, jr[r], k0)] : 0.0;
+    um[r] = (valid[r] && d3 && k0 > 0) ? in(vec_index(g, i, jr[r], k0 - 1)) : zero;
+    uc[r] = (valid[r] && k0 < k1) ? in(vec_index(g, i, jr[r], k0)) : zero;
+    em[r] = (valid[r] && d3) ? T(to_real(g.eta[padded_index(g, i, jr[r], k0 - 1)])) : zero;
+    ec[r] = valid[r] ? T(to_real(g.eta[padded_index(g, i, jr[r], k0)])) : zero;
   }
   for (int k = k0; k < k1; ++k) {
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-      up[r] = (valid[r] && k + 1 < g.nz) ? in(vec_index(g, i, jr[r], k + 1)) : 0.0;
-      ep[r] = (valid[r] && d3) ? g.eta[padded_index(g, i, jr[r], k + 1)] : 0.0;
+      up[r] = (valid[r] && k + 1 < g.nz) ? in(vec_index(g, i, jr[r], k + 1)) : zero;
+      ep[r] = (valid[r] && d3) ? T(to_real(g.eta[padded_index(g, i, jr[r], k + 1)])) : zero;
     }
-    const double hv = hvalid ? in(vec_index(g, hi, hj, k)) : 0.0;
+    const T hv = hvalid ? in(vec_index(g, hi, hj, k)) : zero;
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 2; ++r) su[wrow + 4 * r + 1][lane + 1] = uc[r];
@@ -192,9 +205,10 @@ __device__ __forceinline__ void stencil_march(const Grid& g, const StencilGeom& 
       if (valid[r]) {
         const int row = wrow + 4 * r + 1;
         const long long pc = padded_index(g, i, jr[r], k);
-        const double Au = apply_faces(g, pc, uc[r], ec[r], g.eta[pc + 1], g.eta[pc - 1], g.eta[pc + g.sy],
-                                      g.eta[pc - g.sy], ep[r], em[r], su[row][lane + 2], su[row][lane],
-                                      su[row + 1][lane + 1], su[row - 1][lane + 1], up[r], um[r]);
+        const T Au = apply_faces<T>(g, pc, uc[r], ec[r], T(to_real(g.eta[pc + 1])), T(to_real(g.eta[pc - 1])),
+                                    T(to_real(g.eta[pc + g.sy])), T(to_real(g.eta[pc - g.sy])), ep[r], em[r],
+                                    su[row][lane + 2], su[row][lane], su[row + 1][lane + 1],
+                                    su[row - 1][lane + 1], up[r], um[r]);
         sink(vec_index(g, i, jr[r], k), uc[r], Au);
       }
       um[r] = uc[r];

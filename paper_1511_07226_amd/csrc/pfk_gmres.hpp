@@ -120,7 +120,7 @@ k_fgm_apply(Grid g, StencilGeom sg, PcOutDesc pd, Window U, double* __restrict__
     uc[idx] = u;
     z[idx] = Au;
   };
-  stencil_march(g, sg, in, sink);
+  stencil_march<double>(g, sg, in, sink);
 }
 
 // First reduction: <p_j, z> for j <= c.
@@ -230,7 +230,7 @@ k_pgm_apply0(Grid g, StencilGeom sg, PcOutDesc pd, Window U, Window P, Window ZB
     acc[0] += pv * zb;
     acc[1] += zb * zb;
   };
-  stencil_march(g, sg, in, sink);
+  stencil_march<double>(g, sg, in, sink);
   block_partials<2>(acc, 2, part, sg.blocks());
 }
 

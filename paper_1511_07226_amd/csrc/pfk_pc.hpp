@@ -25,6 +25,13 @@
 // Guards as in the definition: a zero preconditioned residual returns 0 and
 // a non-positive curvature <p,q> returns the current iterate; the stop is
 // recorded per step in PcScalars so later steps leave y untouched.
+//
+// Precision: the kernels are templated on the arithmetic type T of the inner
+// sweeps and the operator description G.  FP64 uses the outer operator; the
+// mixed form runs the sweeps in FP32 on BF16-stored viscosity (FP32 velocity
+// and D^-1).  Conversions happen only at the boundary: v enters as FP64 and is
+// rounded to T, B(v) leaves as T widened to FP64.  Reductions accumulate in
+// FP64 in every form.
 #pragma once
 #include "pfk_state.hpp"
 
@@ -36,30 +43,39 @@ enum PcKind : int { kPcNone = 0, kPcJacobi = 1, kPcJacobiPcg = 2, kPcJacobiGmres
 struct PcOutDesc {
   int kind;
   int k;                        // inner iterations
+  int fp32;                     // inner sweeps in FP32 (float buffers below)
   const double* X1; double c1;  // v = c1*X1 + c2*X2
   const double* X2; double c2;
-  const double* dinv;
-  const double* y;              // inner iterate (PCG), or final output (block PCG)
-  const double* pk;             // last inner direction (PCG)
+  const double* dinv;           // FP64 D^-1 (kinds none / jacobi)
+  const void* dinv_in;          // D^-1 of the inner sweeps (T)
+  const void* y;                // inner iterate (PCG), or final output (block PCG) (T)
+  const void* pk;               // last inner direction (PCG) (T)
   const double* part;           // partials of the last inner kernel (PCG: <p_k,q>; A_1 also <v,p_1>;
                                 //   GMRES: ||V_k||^2)
   int P;
-  const double* vbase;          // inner GMRES basis (k+1 stored vectors, ldv apart)
+  const void* vbase;            // inner GMRES basis (k+1 stored vectors, ldv apart) (T)
   long long ldv;
 };
+
+template <class T>
+__device__ __forceinline__ double ldw(const void* p, long long t) {
+  return (double)static_cast<const T*>(p)[t];
+}
 
 // Device-side evaluator of B(v) at a node, built in the consumer's prologue.
 struct PcOut {
   int kind;
+  int fp32;
   const double* X1; double c1;
   const double* X2; double c2;
   const double* dinv;
-  const double* y;
-  const double* pk;
+  const void* dinv_in;
+  const void* y;
+  const void* pk;
   double alpha;
   int use_y;                    // false when k == 1 (y is still zero)
   int add_p;                    // false when the inner solve stopped before step k
-  const double* vbase;          // inner GMRES: B(v) = dinv * sum cf_j V_j
+  const void* vbase;            // inner GMRES: B(v) = dinv * sum cf_j V_j
   long long ldv;
   int nv;
   const double* cf;             // nv coefficients (in LDS)
@@ -68,30 +84,35 @@ struct PcOut {
     if (X2 != nullptr) r += c2 * X2[t];
     return r;
   }
+  __device__ __forceinline__ double w(const void* p, long long t) const {
+    return fp32 ? ldw<float>(p, t) : ldw<double>(p, t);
+  }
   __device__ __forceinline__ double operator()(long long t) const {
     switch (kind) {
       case kPcNone: return v(t);
       case kPcJacobi: return dinv[t] * v(t);
-      case kPcBlockPcg: return y[t];
+      case kPcBlockPcg: return w(y, t);
       case kPcJacobiGmres: {
         double r = 0.0;
-        for (int q = 0; q < nv; ++q) r += cf[q] * vbase[(long long)q * ldv + t];
-        return dinv[t] * r;
+        for (int q = 0; q < nv; ++q) r += cf[q] * w(vbase, (long long)q * ldv + t);
+        return w(dinv_in, t) * r;
       }
       default: {
-        double r = use_y ? y[t] : 0.0;
-        if (add_p) r += alpha * pk[t];
+        double r = use_y ? w(y, t) : 0.0;
+        if (add_p) r += alpha * w(pk, t);
         return r;
       }
     }
   }
 };
 
-// Finish the inner PCG (alpha_k from the last A_k partials) or pass through.
-// Every thread of the workgroup must call this.
+// Finish the inner solve (PCG: alpha_k from the last A_k partials; GMRES:
+// the small least squares) or pass through.  Every thread of the workgroup
+// must call this.
 __device__ __forceinline__ PcOut make_pc_out(const PcOutDesc& d, PcScalars* pcs) {
   PcOut o;
-  o.kind = d.kind; o.X1 = d.X1; o.c1 = d.c1; o.X2 = d.X2; o.c2 = d.c2; o.dinv = d.dinv;
+  o.kind = d.kind; o.fp32 = d.fp32;
+  o.X1 = d.X1; o.c1 = d.c1; o.X2 = d.X2; o.c2 = d.c2; o.dinv = d.dinv; o.dinv_in = d.dinv_in;
   o.y = d.y; o.pk = d.pk; o.alpha = 0.0; o.use_y = d.k > 1; o.add_p = 0;
   if (d.kind == kPcJacobiPcg) {
     const double pq = block_sum_column(d.part, d.P, 0);
@@ -160,31 +181,33 @@ __device__ __forceinline__ PcOut make_pc_out(const PcOutDesc& d, PcScalars* pcs)
 }
 
 // ---- A_1: p_1 = D^-1 v, q = A p_1 -------------------------------------------
+template <class T, class G>
 __global__ void __launch_bounds__(kBlock)
-k_pcg_a1(Grid g, StencilGeom sg, const double* __restrict__ dinv,
+k_pcg_a1(G g, StencilGeom sg, const T* __restrict__ dinv,
          const double* X1, double c1, const double* X2, double c2,
-         double* __restrict__ pout, double* __restrict__ qout,
+         T* __restrict__ pout, T* __restrict__ qout,
          double* part, const SolveState* st) {
   if (read_status(st) != kRunning) return;
   double acc[2] = {0.0, 0.0};
-  auto V = [&](long long t) { double r = c1 * X1[t]; if (X2 != nullptr) r += c2 * X2[t]; return r; };
+  auto V = [&](long long t) { double r = c1 * X1[t]; if (X2 != nullptr) r += c2 * X2[t]; return T(r); };
   auto in = [&](long long t) { return dinv[t] * V(t); };
-  auto sink = [&](long long idx, double pc, double q) {
+  auto sink = [&](long long idx, T pc, T q) {
     pout[idx] = pc;
     qout[idx] = q;
-    acc[0] += pc * q;
-    acc[1] += V(idx) * pc;
+    acc[0] += (double)pc * (double)q;
+    acc[1] += (double)V(idx) * (double)pc;
   };
-  stencil_march(g, sg, in, sink);
+  stencil_march<T>(g, sg, in, sink);
   block_partials<2>(acc, 2, part, sg.blocks());
 }
 
 // ---- B_j (1 <= j < k): y += alpha p, rho -= alpha q, partial <rho, D^-1 rho> --
+template <class T>
 __global__ void __launch_bounds__(kBlock)
-k_pcg_b(int jstep, long long N, const double* __restrict__ dinv,
+k_pcg_b(int jstep, long long N, const T* __restrict__ dinv,
         const double* X1, double c1, const double* X2, double c2,
-        const double* __restrict__ p, const double* __restrict__ q,
-        double* __restrict__ rho, double* __restrict__ y,
+        const T* __restrict__ p, const T* __restrict__ q,
+        T* __restrict__ rho, T* __restrict__ y,
         const double* part_in, int P_in, double* part_out, SolveState* st) {
   if (read_status(st) != kRunning) return;
   PcScalars* pcs = &st->pc;
@@ -199,19 +222,20 @@ k_pcg_b(int jstep, long long N, const double* __restrict__ dinv,
     stopped = pcs->stopped[jstep - 1];
   }
   stopped = stopped || !(pq > 0.0);
-  const double alpha = stopped ? 0.0 : gj / pq;
+  const T alpha = T(stopped ? 0.0 : gj / pq);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (jstep == 1) pcs->gamma[1] = gj;
     pcs->stopped[jstep] = stopped;
   }
   double acc[1] = {0.0};
   for (long long e = gtid(); e < N; e += gstride()) {
-    double r;
-    double yv;
+    T r;
+    T yv;
     if (jstep == 1) {
-      r = c1 * X1[e];
-      if (X2 != nullptr) r += c2 * X2[e];
-      yv = 0.0;
+      double rv = c1 * X1[e];
+      if (X2 != nullptr) rv += c2 * X2[e];
+      r = T(rv);
+      yv = T(0);
     } else {
       r = rho[e];
       yv = y[e];
@@ -222,48 +246,51 @@ k_pcg_b(int jstep, long long N, const double* __restrict__ dinv,
     }
     y[e] = yv;
     rho[e] = r;
-    acc[0] += r * (dinv[e] * r);
+    acc[0] += (double)r * (double)(dinv[e] * r);
   }
   block_partials<1>(acc, 1, part_out, gridDim.x);
 }
 
 // ---- A_j (2 <= j <= k): p_j = D^-1 rho + beta p_{j-1}, q = A p_j -------------
+template <class T, class G>
 __global__ void __launch_bounds__(kBlock)
-k_pcg_a(int jstep, Grid g, StencilGeom sg, const double* __restrict__ dinv,
-        const double* __restrict__ rho, const double* __restrict__ pprev,
-        double* __restrict__ pout, double* __restrict__ qout,
+k_pcg_a(int jstep, G g, StencilGeom sg, const T* __restrict__ dinv,
+        const T* __restrict__ rho, const T* __restrict__ pprev,
+        T* __restrict__ pout, T* __restrict__ qout,
         const double* part_in, int P_in, double* part_out, SolveState* st) {
   if (read_status(st) != kRunning) return;
   PcScalars* pcs = &st->pc;
   const double gj = block_sum_column(part_in, P_in, 0);
   const double gprev = pcs->gamma[jstep - 1];
   const int stopped = pcs->stopped[jstep - 1];
-  const double beta = (stopped || gprev == 0.0) ? 0.0 : gj / gprev;
+  const T beta = T((stopped || gprev == 0.0) ? 0.0 : gj / gprev);
   if (blockIdx.x == 0 && threadIdx.x == 0) pcs->gamma[jstep] = gj;
   double acc[1] = {0.0};
   auto in = [&](long long t) { return dinv[t] * rho[t] + beta * pprev[t]; };
-  auto sink = [&](long long idx, double pc, double q) {
+  auto sink = [&](long long idx, T pc, T q) {
     pout[idx] = pc;
     qout[idx] = q;
-    acc[0] += pc * q;
+    acc[0] += (double)pc * (double)q;
   };
-  stencil_march(g, sg, in, sink);
+  stencil_march<T>(g, sg, in, sink);
   block_partials<1>(acc, 1, part_out, sg.blocks());
 }
 
 // ---- inner GMRES -----------------------------------------------------------
 // G0: V_0 = v (stored unnormalised), partial ||v||^2.
+template <class T>
 __global__ void __launch_bounds__(kBlock)
 k_gmpc_start(long long N, int k, const double* X1, double c1, const double* X2, double c2,
-             double* __restrict__ V0, double* part_out, SolveState* st) {
+             T* __restrict__ V0, double* part_out, SolveState* st) {
   if (read_status(st) != kRunning) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) st->pc.ncol = k;
   double acc[1] = {0.0};
   for (long long e = gtid(); e < N; e += gstride()) {
     double v = c1 * X1[e];
     if (X2 != nullptr) v += c2 * X2[e];
-    V0[e] = v;
-    acc[0] += v * v;
+    const T vt = T(v);
+    V0[e] = vt;
+    acc[0] += (double)vt * (double)vt;
   }
   block_partials<1>(acc, 1, part_out, gridDim.x);
 }
@@ -271,9 +298,10 @@ k_gmpc_start(long long N, int k, const double* X1, double c1, const double* X2, 
 // GA_j: scale of V_j from the previous norm (a zero norm ends the cycle:
 // beta = 0 gives B(v) = 0, a zero subdiagonal is a happy breakdown), then
 // w = A D^-1 V_j and partials <stored V_i, w> for i <= j.
+template <class T, class G>
 __global__ void __launch_bounds__(kBlock)
-k_gmpc_apply(int jstep, Grid g, StencilGeom sg, const double* __restrict__ dinv, const double* Vbase,
-             long long ldv, double* __restrict__ w, const double* part_in, int P_in, double* part_out,
+k_gmpc_apply(int jstep, G g, StencilGeom sg, const T* __restrict__ dinv, const T* Vbase,
+             long long ldv, T* __restrict__ w, const double* part_in, int P_in, double* part_out,
              SolveState* st) {
   if (read_status(st) != kRunning) return;
   PcScalars* pcs = &st->pc;
@@ -286,26 +314,27 @@ k_gmpc_apply(int jstep, Grid g, StencilGeom sg, const double* __restrict__ dinv,
     if (nrm == 0.0) pcs->ncol = jstep;
   }
   if (nrm == 0.0) return;
-  const double sj = 1.0 / nrm;
-  const double* Vj = Vbase + (long long)jstep * ldv;
+  const T sj = T(1.0 / nrm);
+  const T* Vj = Vbase + (long long)jstep * ldv;
   double acc[kMaxInnerGmres];
 #pragma unroll
   for (int q = 0; q < kMaxInnerGmres; ++q) acc[q] = 0.0;
   auto in = [&](long long t) { return dinv[t] * (sj * Vj[t]); };
-  auto sink = [&](long long idx, double, double Au) {
+  auto sink = [&](long long idx, T, T Au) {
     w[idx] = Au;
 #pragma unroll
     for (int q = 0; q < kMaxInnerGmres; ++q)
-      if (q <= jstep) acc[q] += Vbase[(long long)q * ldv + idx] * Au;
+      if (q <= jstep) acc[q] += (double)Vbase[(long long)q * ldv + idx] * (double)Au;
   };
-  stencil_march(g, sg, in, sink);
+  stencil_march<T>(g, sg, in, sink);
   block_partials<kMaxInnerGmres>(acc, jstep + 1, part_out, sg.blocks());
 }
 
 // GO_j: h_ij = <V_i, w> (classical Gram-Schmidt), V_{j+1} = w - sum h_ij V_i
 // stored unnormalised (not stored for the last step), partial ||V_{j+1}||^2.
+template <class T>
 __global__ void __launch_bounds__(kBlock)
-k_gmpc_orth(int jstep, int k, long long N, double* Vbase, long long ldv, const double* __restrict__ w,
+k_gmpc_orth(int jstep, int k, long long N, T* Vbase, long long ldv, const T* __restrict__ w,
             const double* part_in, int P_in, double* part_out, SolveState* st) {
   if (read_status(st) != kRunning) return;
   PcScalars* pcs = &st->pc;
@@ -320,13 +349,13 @@ k_gmpc_orth(int jstep, int k, long long N, double* Vbase, long long ldv, const d
   }
   __syncthreads();
   const bool store = jstep + 1 < k;
-  double* Vn = Vbase + (long long)(jstep + 1) * ldv;
+  T* Vn = Vbase + (long long)(jstep + 1) * ldv;
   double acc[1] = {0.0};
   for (long long e = gtid(); e < N; e += gstride()) {
-    double v = w[e];
-    for (int q = 0; q <= jstep; ++q) v -= coef[q] * Vbase[(long long)q * ldv + e];
+    T v = w[e];
+    for (int q = 0; q <= jstep; ++q) v -= T(coef[q]) * Vbase[(long long)q * ldv + e];
     if (store) Vn[e] = v;
-    acc[0] += v * v;
+    acc[0] += (double)v * (double)v;
   }
   block_partials<1>(acc, 1, part_out, gridDim.x);
 }
