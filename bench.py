@@ -104,7 +104,52 @@ def cpu_baseline(prob, method):
                       f"start-up alone ({t_start:.1f} s), numpy FP64, 1 thread"}
 
 
+def _short_kernel_name(name: str) -> str:
+    base = name.split("(")[0].replace("void ", "").strip()
+    head, sep, tmpl = base.partition("<")
+    return head.split("::")[-1] + (("<" + tmpl.replace("pfk::", "")) if sep else "")
+
+
+def trace_summary(trace_csv: str, kernel: str, skip: int) -> str:
+    """Per-kernel statistics from a rocprofv3 kernel trace (CSV), plus the
+    steady-state mean of `kernel`: its dispatches after the first `skip` of
+    every run of consecutive dispatches (the window fills during the first nu
+    iterations, so early dispatches move fewer bytes)."""
+    import csv
+    rows = []
+    with open(trace_csv, newline="") as f:
+        for r in csv.DictReader(f):
+            rows.append((int(r["Dispatch_Id"]), _short_kernel_name(r["Kernel_Name"]),
+                         int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    rows.sort()
+    stats = {}
+    for _, name, ns in rows:
+        s = stats.setdefault(name, [0, 0])
+        s[0] += 1
+        s[1] += ns
+    lines = [f"{'kernel':48s} {'calls':>7s} {'avg_ms':>10s} {'total_ms':>10s}"]
+    for name, (c, tot) in sorted(stats.items(), key=lambda kv: -kv[1][1])[:20]:
+        lines.append(f"{name[:48]:48s} {c:7d} {tot / c / 1e6:10.4f} {tot / 1e6:10.2f}")
+    durs = [ns for _, name, ns in rows if name == kernel]
+    steady = durs[skip:]
+    if steady:
+        steady_sorted = sorted(steady)
+        lines.append(f"\n{kernel}: {len(durs)} dispatches; steady state (dispatch {skip + 1} on): "
+                     f"{len(steady)} dispatches, mean {sum(steady) / len(steady) / 1e6:.4f} ms, "
+                     f"median {steady_sorted[len(steady) // 2] / 1e6:.4f} ms, "
+                     f"min {steady_sorted[0] / 1e6:.4f} ms, max {steady_sorted[-1] / 1e6:.4f} ms")
+    return "\n".join(lines)
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--trace-summary":
+        sp = argparse.ArgumentParser()
+        sp.add_argument("--trace-summary", required=True, help="rocprofv3 *_kernel_trace.csv")
+        sp.add_argument("--kernel", default="k_pipefcg_update")
+        sp.add_argument("--skip", type=int, default=NU + 1)
+        a = sp.parse_args()
+        print(trace_summary(a.trace_summary, a.kernel, a.skip))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=60)

@@ -69,7 +69,9 @@ typedef enum {
   PFK_PC_JACOBI_PCG = 2,        /* k iterations of Jacobi-PCG on A y = v from y = 0  */
   PFK_PC_JACOBI_GMRES = 3,      /* one GMRES(k) cycle on A D^-1 t = v from 0, y = D^-1 t */
   PFK_PC_BLOCK_JACOBI_PCG = 4   /* k Jacobi-PCG iterations inside every cubic block of
-                                   `block` nodes per axis (section 6.2's block Jacobi) */
+                                   `block` nodes per axis (square in 2D), on the block's
+                                   principal submatrix with its own scalars: the block
+                                   Jacobi of the experiments (section 6.2)             */
 } pfk_pc_kind;
 
 typedef enum {
@@ -136,8 +138,12 @@ int pfk_operator_apply(pfk_operator A, const double* x, double* y, void* stream)
 int pfk_operator_diag_inv(pfk_operator A, double* dinv, void* stream);
 
 /* Preconditioner B of the given kind with `inner_its` inner iterations
- * (1..32; ignored for NONE and JACOBI), precision, and `block` nodes per axis
- * for BLOCK_JACOBI_PCG (4 or 8).  Errors: PFK_ERR_ARG. */
+ * (1..32, at most 8 for JACOBI_GMRES; ignored for NONE and JACOBI), precision
+ * (FP32_BF16COEF applies to the three inner-iterative kinds), and `block` nodes
+ * per axis for BLOCK_JACOBI_PCG (8; blocks start at interior index 0, the last
+ * one per axis is ragged).  The handle refers to A, which must outlive it.
+ * Errors: PFK_ERR_ARG (bad kind, count, precision or block), PFK_ERR_OOM,
+ * PFK_ERR_HIP. */
 int pfk_precond_create(pfk_operator A, pfk_pc_kind kind, int inner_its, pfk_precision prec,
                        int block, pfk_precond* out);
 void pfk_precond_destroy(pfk_precond B);

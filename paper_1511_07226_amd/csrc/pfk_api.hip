@@ -352,9 +352,10 @@ extern "C" int pfk_precond_create(pfk_operator A, pfk_pc_kind kind, int inner_it
   if (prec != PFK_FP64 && prec != PFK_FP32_BF16COEF) return fail(PFK_ERR_ARG, "unknown precision");
   if (kind == PFK_PC_JACOBI_GMRES && inner_its > kMaxInnerGmres)
     return fail(PFK_ERR_ARG, "inner GMRES supports at most 8 steps");
-  if (kind == PFK_PC_BLOCK_JACOBI_PCG)
-    return fail(PFK_ERR_ARG, "preconditioner kind not available in this build");
-  if (prec == PFK_FP32_BF16COEF && (kind == PFK_PC_JACOBI_PCG || kind == PFK_PC_JACOBI_GMRES)) {
+  if (kind == PFK_PC_BLOCK_JACOBI_PCG && block != kBjEdge)
+    return fail(PFK_ERR_ARG, "block-Jacobi PCG supports blocks of 8 nodes per axis");
+  if (prec == PFK_FP32_BF16COEF &&
+      (kind == PFK_PC_JACOBI_PCG || kind == PFK_PC_JACOBI_GMRES || kind == PFK_PC_BLOCK_JACOBI_PCG)) {
     const int rc = ensure_mixed(A);
     if (rc) return rc;
   }
@@ -534,7 +535,8 @@ PcOutDesc pc_out_desc(const pfk_session_s* S, const double* X1, double c1, const
   PcOutDesc d{};
   d.kind = S->B->kind;
   d.k = S->B->k;
-  d.fp32 = S->B->prec == PFK_FP32_BF16COEF && (d.kind == kPcJacobiPcg || d.kind == kPcJacobiGmres);
+  d.fp32 = S->B->prec == PFK_FP32_BF16COEF &&
+           (d.kind == kPcJacobiPcg || d.kind == kPcJacobiGmres || d.kind == kPcBlockPcg);
   d.X1 = X1; d.c1 = c1; d.X2 = X2; d.c2 = c2;
   d.dinv = S->A->dinv;
   d.dinv_in = d.fp32 ? (const void*)S->A->dinv_f32 : (const void*)S->A->dinv;
@@ -544,6 +546,8 @@ PcOutDesc pc_out_desc(const pfk_session_s* S, const double* X1, double c1, const
     d.pk = S->vec((d.k - 1) & 1 ? V_PC_P1 : V_PC_P0);
     d.part = S->part(PT_PC0);
     d.P = S->Ps();
+  } else if (d.kind == kPcBlockPcg) {
+    d.y = S->vec(V_PC_Y);
   } else if (d.kind == kPcJacobiGmres) {
     // G0, (GA_j, GO_j): every GO_j writes PC0
     d.part = S->part(PT_PC0);
@@ -580,6 +584,17 @@ void enqueue_pc_kernels(pfk_session_s* S, hipStream_t s, const PcOutDesc& d, con
              pp[j & 1], q, (const double*)part[(t - 1) & 1], Pprev, part[t & 1], S->st);
       Pprev = S->Ps();
       ++t;
+    }
+  } else if (d.kind == kPcBlockPcg) {
+    T* y = (T*)S->vec(V_PC_Y);
+    const int wy = ((int)A->n[1] + kBjEdge - 1) / kBjEdge;
+    if (A->dim == 3) {
+      const int wx = (int)((A->n[0] + 2 * kBjEdge - 1) / (2 * kBjEdge));
+      const int wz = (int)((A->n[2] + kBjEdge - 1) / kBjEdge);
+      LAUNCH((k_block_pcg<T, G, 1>), wx * wy * wz, s, g, wx, wy, d.k, X1, c1, X2, c2, y, (const SolveState*)S->st);
+    } else {
+      const int wx = (int)((A->n[0] + 4 * kBjEdge - 1) / (4 * kBjEdge));
+      LAUNCH((k_block_pcg<T, G, 0>), wx * wy, s, g, wx, wy, d.k, X1, c1, X2, c2, y, (const SolveState*)S->st);
     }
   } else if (d.kind == kPcJacobiGmres) {
     T* V = (T*)S->win(W_PCV).base;

@@ -360,4 +360,201 @@ k_gmpc_orth(int jstep, int k, long long N, T* Vbase, long long ldv, const T* __r
   block_partials<1>(acc, 1, part_out, gridDim.x);
 }
 
+// ---- block-Jacobi PCG ------------------------------------------------------
+// The per-block inner solve of the experiments (section 6.2): the domain is
+// cut into cubes of kBjEdge nodes per axis (squares in 2D) starting at
+// interior index 0, the last block per axis ragged.  Each block runs k steps
+// of Jacobi-PCG from y = 0 on its principal submatrix A_bb (couplings to
+// other blocks dropped, the diagonal of A kept whole) with its own scalars
+// and guards, so the whole inner solve is one kernel with no device-wide
+// synchronisation: v is read once and B(v) written once.
+//
+// Shape: a 64-lane wave holds one 8 x 8 (x, y) plane of a block (lane =
+// 8 y + x).  3D: a block is two waves of four planes each and a workgroup
+// takes two x-adjacent blocks, so every 128-byte row segment of a vector is
+// read by one compute unit.  2D: a wave is a whole block, four x-adjacent
+// blocks per workgroup.  The block's coefficients (diagonal, D^-1 and the six
+// in-block off-diagonals) are formed once from the viscosity and velocities
+// and stay in registers; directions are exchanged through LDS.  Block dot
+// products accumulate in FP64: a butterfly over the wave (every lane ends
+// with the same bits, since a + b == b + a) and, in 3D, the block's two wave
+// sums through LDS in a fixed order.
+constexpr int kBjEdge = 8;
+
+template <int D3>
+struct BjShape {
+  static constexpr int NPT = D3 ? 4 : 1;        // planes (nodes) per thread
+  static constexpr int WPB = D3 ? 2 : 1;        // waves per block
+  static constexpr int BPW = kWaves / WPB;      // blocks per workgroup (along x)
+  static constexpr int ZL = D3 ? kBjEdge : 1;   // planes per block
+};
+
+__device__ __forceinline__ double wave_allsum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Diagonal and in-block off-diagonal couplings of node (i, j, k); zl is its
+// plane within the block.  (A_bb u)_c = d u_c - sum_f o_f u_f, faces in the
+// order x+, x-, y+, y-, z+, z-; o_f = 0 for a neighbour outside the block or
+// on the boundary.
+template <class T, class G>
+__device__ __forceinline__ void bj_coeffs(const G& g, int i, int j, int k, int lx, int ly, int zl, T& d,
+                                          T (&o)[6]) {
+  const long long pc = padded_index(g, i, j, k);
+  const bool d3 = g.dim == 3;
+  const T ec = T(to_real(g.eta[pc]));
+  T kf[6];
+  kf[0] = harmonic(ec, T(to_real(g.eta[pc + 1])));
+  kf[1] = harmonic(ec, T(to_real(g.eta[pc - 1])));
+  kf[2] = harmonic(ec, T(to_real(g.eta[pc + g.sy])));
+  kf[3] = harmonic(ec, T(to_real(g.eta[pc - g.sy])));
+  kf[4] = d3 ? harmonic(ec, T(to_real(g.eta[pc + g.sz]))) : T(0);
+  kf[5] = d3 ? harmonic(ec, T(to_real(g.eta[pc - g.sz]))) : T(0);
+  const bool in[6] = {lx + 1 < kBjEdge && i + 1 < g.nx, lx > 0,
+                      ly + 1 < kBjEdge && j + 1 < g.ny, ly > 0,
+                      d3 && zl + 1 < kBjEdge && k + 1 < g.nz, d3 && zl > 0};
+  const T h2 = T(g.h2inv);
+  T dd = T(0);
+#pragma unroll
+  for (int f = 0; f < 6; ++f) dd += kf[f];
+  dd *= h2;
+  T vn[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+  if (g.vel != nullptr) {
+    const auto* vx = g.vel;
+    const auto* vy = g.vel + g.vstride;
+    const auto* vz = g.vel + 2 * g.vstride;
+    vn[0] = T(to_real(vx[pc]));
+    vn[1] = -T(to_real(vx[pc - 1]));
+    vn[2] = T(to_real(vy[pc]));
+    vn[3] = -T(to_real(vy[pc - g.sy]));
+    if (d3) {
+      vn[4] = T(to_real(vz[pc]));
+      vn[5] = -T(to_real(vz[pc - g.sz]));
+    }
+    T up = T(0);
+#pragma unroll
+    for (int f = 0; f < 6; ++f) up += fmax(vn[f], T(0));
+    dd += T(g.hinv) * up;
+  }
+#pragma unroll
+  for (int f = 0; f < 6; ++f) o[f] = in[f] ? h2 * kf[f] - T(g.hinv) * fmin(vn[f], T(0)) : T(0);
+  d = dd;
+}
+
+// B(v) for every block, v = c1*X1 + c2*X2 (FP64, rounded to T), written to
+// yout (T).  Workgroups: wx * wy * wz, with wx = ceil(nx / (BPW * 8)),
+// wy = ceil(ny / 8), wz = ceil(nz / 8) (1 in 2D).
+template <class T, class G, int D3>
+__global__ void __launch_bounds__(kBlock)
+k_block_pcg(G g, int wx, int wy, int k, const double* X1, double c1, const double* X2, double c2,
+            T* __restrict__ yout, const SolveState* st) {
+  using Sh = BjShape<D3>;
+  constexpr int NPT = Sh::NPT, WPB = Sh::WPB, BPW = Sh::BPW, ZL = Sh::ZL;
+  if (read_status(st) != kRunning) return;
+  __shared__ T sp[BPW * ZL * 64];
+  __shared__ double sred[2][kWaves];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lx = lane & 7, ly = lane >> 3;
+  const int blk = wave / WPB, zh = wave % WPB;
+  const int b = blockIdx.x;
+  const int gx = b % wx, gy = (b / wx) % wy, gz = b / (wx * wy);
+  const int i = (gx * BPW + blk) * kBjEdge + lx;
+  const int j = gy * kBjEdge + ly;
+  const bool col = i < g.nx && j < g.ny;
+
+  T dg[NPT], dinv[NPT], o[NPT][6], r[NPT], p[NPT], q[NPT], y[NPT];
+  int slot[NPT];
+  bool valid[NPT];
+  double acc = 0.0;
+#pragma unroll
+  for (int n = 0; n < NPT; ++n) {
+    const int zl = zh * NPT + n;
+    const int kz = gz * ZL + zl;
+    slot[n] = ((blk * ZL + zl) * kBjEdge + ly) * kBjEdge + lx;
+    valid[n] = col && kz < g.nz;
+    y[n] = T(0);
+    if (valid[n]) {
+      bj_coeffs<T>(g, i, j, kz, lx, ly, zl, dg[n], o[n]);
+      dinv[n] = T(1) / dg[n];
+      const long long e = vec_index(g, i, j, kz);
+      double v = c1 * X1[e];
+      if (X2 != nullptr) v += c2 * X2[e];
+      r[n] = T(v);
+    } else {
+#pragma unroll
+      for (int f = 0; f < 6; ++f) o[n][f] = T(0);
+      dg[n] = T(1);
+      dinv[n] = T(0);
+      r[n] = T(0);
+    }
+    p[n] = dinv[n] * r[n];
+    acc += (double)r[n] * (double)p[n];
+  }
+
+  int par = 0;
+  auto bsum = [&](double part) -> double {
+    double s = wave_allsum(part);
+    if (WPB == 1) return s;
+    if (lane == 0) sred[par][wave] = s;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < WPB; ++w) t += sred[par][blk * WPB + w];
+    par ^= 1;
+    return t;
+  };
+
+  double gamma = bsum(acc);
+  bool live = gamma != 0.0;
+  for (int step = 1; step <= k; ++step) {
+#pragma unroll
+    for (int n = 0; n < NPT; ++n) sp[slot[n]] = p[n];
+    __syncthreads();
+    acc = 0.0;
+#pragma unroll
+    for (int n = 0; n < NPT; ++n) {
+      const int zl = zh * NPT + n;
+      const int s = slot[n];
+      const T nb0 = lx + 1 < kBjEdge ? sp[s + 1] : T(0);
+      const T nb1 = lx > 0 ? sp[s - 1] : T(0);
+      const T nb2 = ly + 1 < kBjEdge ? sp[s + kBjEdge] : T(0);
+      const T nb3 = ly > 0 ? sp[s - kBjEdge] : T(0);
+      T a = dg[n] * p[n] - (o[n][0] * nb0 + o[n][1] * nb1 + o[n][2] * nb2 + o[n][3] * nb3);
+      if (D3) {
+        const T nb4 = zl + 1 < kBjEdge ? sp[s + 64] : T(0);
+        const T nb5 = zl > 0 ? sp[s - 64] : T(0);
+        a -= o[n][4] * nb4 + o[n][5] * nb5;
+      }
+      q[n] = a;
+      acc += (double)p[n] * (double)a;
+    }
+    const double pq = bsum(acc);
+    live = live && pq > 0.0;
+    const double alpha = live ? gamma / pq : 0.0;
+    const T at = T(alpha);
+#pragma unroll
+    for (int n = 0; n < NPT; ++n) y[n] += at * p[n];
+    if (step < k) {
+      acc = 0.0;
+      T z[NPT];
+#pragma unroll
+      for (int n = 0; n < NPT; ++n) {
+        r[n] -= at * q[n];
+        z[n] = dinv[n] * r[n];
+        acc += (double)r[n] * (double)z[n];
+      }
+      const double gnew = bsum(acc);
+      const T beta = T(live ? gnew / gamma : 0.0);
+#pragma unroll
+      for (int n = 0; n < NPT; ++n) p[n] = z[n] + beta * p[n];
+      gamma = gnew;
+    }
+  }
+#pragma unroll
+  for (int n = 0; n < NPT; ++n)
+    if (valid[n]) yout[vec_index(g, i, j, gz * ZL + zh * NPT + n)] = y[n];
+}
+
 }  // namespace pfk
