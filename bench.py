@@ -66,22 +66,63 @@ def iteration_bytes(method: str, nu: int, k: int, N: int) -> float:
     return (fcg + pc - 1) * W * N
 
 
-def time_steps(pfk, torch, A, B, method, b, steps, warmup, graph_iters=10):
+def time_steps(pfk, torch, A, B, method, b, steps, warmup, mmax=NU, graph_iters=10, **opts):
+    """Steady-state timing of a CG/CR-type method: the window is filled first
+    (at least mmax + 2 iterations), then exactly `steps` iterations are timed
+    between two device synchronisations.  Returns the open session and seconds."""
     x = torch.zeros_like(b)
-    S = pfk.Session(A, B, method, b, x, rtol=0.0, maxit=10 ** 7, mmax=NU, graph_iters=graph_iters)
+    S = pfk.Session(A, B, method, b, x, rtol=0.0, maxit=10 ** 7, mmax=mmax, graph_iters=graph_iters, **opts)
     S.start()
-    S.iterate(max(warmup, NU + 2))       # fill the window: steady state
+    S.iterate(max(warmup, mmax + 2))
     info0 = S.sync()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     S.iterate(steps)
     torch.cuda.synchronize()
-    info1 = S.sync()
     dt = time.perf_counter() - t0
+    info1 = S.sync()
     if info1.status not in (0, 1) or info1.iterations - info0.iterations != steps:
         raise RuntimeError(f"{method}: expected {steps} steady iterations, got "
                            f"{info1.iterations - info0.iterations} (status {info1.status_name})")
     return S, dt
+
+
+def time_cycles(pfk, torch, A, B, method, b, cycles, m, **opts):
+    """Restarted GMRES types: one warm-up cycle, then `cycles` timed cycles of
+    m iterations, each followed by the restart's start-up (new residual,
+    basis vector and pipeline fill) as a restarted solve does.  Returns seconds."""
+    x = torch.zeros_like(b)
+    S = pfk.Session(A, B, method, b, x, rtol=0.0, maxit=10 ** 7, mmax=m, graph_iters=m, **opts)
+    S.start()
+    S.iterate(m)
+    S.start()
+    S.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(cycles):
+        S.iterate(m)
+        S.start()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    S.iterate(m)
+    info = S.sync()
+    S.close()
+    if info.iterations != m:
+        raise RuntimeError(f"{method}: a cycle ran {info.iterations} iterations, expected {m}")
+    return dt
+
+
+def time_to_solution(pfk, torch, A, B, method, b, rtol, maxit, mmax, **opts):
+    """One full solve from x = 0 (graphs captured inside the timed call)."""
+    x = torch.zeros_like(b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = pfk.solve(A, B, method, b, x, rtol=rtol, maxit=maxit, mmax=mmax, graph_iters=10, **opts)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"seconds": round(dt, 4), "iterations": info.iterations, "restarts": info.restarts,
+            "converged": bool(info.converged), "true_rel_resid": info.true_rel_resid,
+            "solves_per_s": round(1.0 / dt, 4)}, x
 
 
 def cpu_baseline(prob, method):
@@ -112,9 +153,9 @@ def _short_kernel_name(name: str) -> str:
 
 def trace_summary(trace_csv: str, kernel: str, skip: int) -> str:
     """Per-kernel statistics from a rocprofv3 kernel trace (CSV), plus the
-    steady-state mean of `kernel`: its dispatches after the first `skip` of
-    every run of consecutive dispatches (the window fills during the first nu
-    iterations, so early dispatches move fewer bytes)."""
+    steady-state mean of `kernel`: its dispatches after the first `skip` (the
+    window fills during the first nu iterations of a solve, so the early
+    dispatches move fewer bytes; the profiled command runs one such solve)."""
     import csv
     rows = []
     with open(trace_csv, newline="") as f:
@@ -156,6 +197,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--method", default="pipefcg", choices=["pipefcg", "fcg"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time only the FP64 PIPEFCG/FCG pair (for profiler runs)")
     ap.add_argument("--profile-iters", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -175,13 +218,14 @@ def main():
     B = pfk.Precond(A, "jacobi_pcg", INNER)
     b = torch.as_tensor(prob.b).cuda()
 
-    results = {}
-    sessions = {}
+    def rate(method, Bx, **opts):
+        S, dt = time_steps(pfk, torch, A, Bx, method, b, args.steps, args.warmup, **opts)
+        return S, {"it_per_s": round(args.steps / dt, 3), "ms_per_step": round(dt / args.steps * 1e3, 4)}
+
+    results, sessions = {}, {}
     for method in ("pipefcg", "fcg"):
         log(f"timing {method}: {args.warmup} warm-up + {args.steps} steps")
-        S, dt = time_steps(pfk, torch, A, B, method, b, args.steps, args.warmup)
-        results[method] = {"it_per_s": args.steps / dt, "ms_per_step": dt / args.steps * 1e3}
-        sessions[method] = S
+        sessions[method], results[method] = rate(method, B)
         log(f"{method}: {results[method]['it_per_s']:.1f} it/s")
 
     main_m = args.method
@@ -189,17 +233,86 @@ def main():
     # per-kernel event timing of the dominant kernel, on its own stream
     log("kernel timing pass")
     prof = sessions[main_m].profile(args.profile_iters)
-    upd_name = "k_pipefcg_update" if main_m == "pipefcg" else "k_fcg_dots"
+    upd_name = "k_pipefcg_update" if main_m == "pipefcg" else "k_multidot"
     ms, launches = prof.get(upd_name, (float("nan"), 0))
     avg_ms = ms / max(launches, 1)
     upd_bytes = window_update_bytes(main_m, NU, N) if main_m == "pipefcg" else (NU + 3) * 8.0 * N
     achieved = upd_bytes / (avg_ms * 1e-3) / 1e9
-    kernels = {k: {"avg_ms": v[0] / max(v[1], 1), "launches": v[1]} for k, v in prof.items()}
+    kernels = {k: {"avg_ms": round(v[0] / max(v[1], 1), 4), "launches": v[1]} for k, v in prof.items()}
     for S in sessions.values():
         S.close()
+    sessions.clear()
 
     it_bytes = {m: iteration_bytes(m, NU, INNER, N) for m in ("pipefcg", "fcg")}
     eff = {m: it_bytes[m] * results[m]["it_per_s"] / 1e9 for m in results}
+
+    extra = {}
+    if not args.headline_only:
+        # unpipelined baseline with a blocking (host-synchronised) reduction
+        log("timing fcg host-sync")
+        S, extra["fcg_host_sync"] = rate("fcg", B, host_sync=1)
+        S.close()
+        # mixed precision: FP32 inner sweeps on BF16 viscosity, FP64 outer
+        Bm = pfk.Precond(A, "jacobi_pcg", INNER, precision=pfk.FP32_BF16COEF)
+        for method in ("pipefcg", "fcg"):
+            log(f"timing {method} mixed")
+            S, extra[f"{method}_mixed"] = rate(method, Bm)
+            S.close()
+        # block-Jacobi inner solve (8^3 blocks, 5 PCG steps each), FP64 and mixed
+        Bb = pfk.Precond(A, "block_jacobi_pcg", INNER, block=8)
+        Bbm = pfk.Precond(A, "block_jacobi_pcg", INNER, precision=pfk.FP32_BF16COEF, block=8)
+        for tag, Bx in (("block", Bb), ("block_mixed", Bbm)):
+            for method in ("pipefcg", "fcg"):
+                log(f"timing {method} {tag}")
+                S, extra[f"{method}_{tag}"] = rate(method, Bx)
+                S.close()
+        del Bm, Bb, Bbm
+        # time to solution at rtol 1e-8 on config 2 (128^3, same recipe): the 256^3
+        # sinker needs more than a few thousand iterations with these inner solves.
+        # The global inner CG makes PIPEFCG stagnate, so solves use the block form;
+        # the mixed solution's error against the FP64 one is stated.
+        log("generating the 128^3 sinker workload (config 2)")
+        p2 = gen.config_problem("cfg2", seed=0)
+        A2 = pfk.Operator(p2.dim, p2.n, p2.eta)
+        b2 = torch.as_tensor(p2.b).cuda()
+        tts = {"workload": "128^3 sinker (20 spheres, eta 1e4/1), nu_max 30, block-Jacobi PCG (8^3, 5 steps)"}
+        xs = {}
+        for tag, prec in (("block", pfk.FP64), ("block_mixed", pfk.FP32_BF16COEF)):
+            Bx = pfk.Precond(A2, "block_jacobi_pcg", INNER, precision=prec, block=8)
+            for method in ("pipefcg", "fcg"):
+                log(f"solving {method} {tag} (128^3) to rtol 1e-8")
+                tts[f"{method}_{tag}"], xs[(method, tag)] = time_to_solution(
+                    pfk, torch, A2, Bx, method, b2, 1e-8, 8000, NU)
+        for method in ("pipefcg", "fcg"):
+            x64, xm = xs[(method, "block")], xs[(method, "block_mixed")]
+            tts[f"{method}_block_mixed"]["rel_err_vs_fp64_solution"] = float(
+                torch.linalg.vector_norm(xm - x64) / torch.linalg.vector_norm(x64))
+        extra["time_to_solution_rtol1e-8"] = tts
+        del xs, A2, b2, p2
+
+        # config 3: 256^3 convection-diffusion, GMRES(5) inner solve in FP32 on BF16 viscosity
+        log("generating the 256^3 convection-diffusion workload")
+        p3 = gen.config_problem("cfg3", seed=0)
+        A3 = pfk.Operator(p3.dim, p3.n, p3.eta, p3.vel)
+        B3 = pfk.Precond(A3, "jacobi_gmres", INNER, precision=pfk.FP32_BF16COEF)
+        b3 = torch.as_tensor(p3.b).cuda()
+        del p3
+        sigma = pfk.estimate_sigma(A3, B3)
+        cycles = max(1, math.ceil(args.steps / NU))
+        conv = {"workload": "256^3 conv-diff sinker (cell Peclet 5), outer FP64, B = GMRES(5) FP32/BF16",
+                "sigma": sigma}
+        for method in ("pipefgmres", "fgmres"):
+            log(f"timing {method}: {cycles} cycles of {NU}")
+            opts = {"shift_sigma": sigma} if method == "pipefgmres" else {}
+            dt = time_cycles(pfk, torch, A3, B3, method, b3, cycles, NU, **opts)
+            conv[method] = {"it_per_s": round(cycles * NU / dt, 3), "ms_per_step": round(dt / (cycles * NU) * 1e3, 4)}
+        for method in ("pipegcr", "gcr"):
+            log(f"timing {method}")
+            S, dt = time_steps(pfk, torch, A3, B3, method, b3, args.steps, args.warmup)
+            S.close()
+            conv[method] = {"it_per_s": round(args.steps / dt, 3), "ms_per_step": round(dt / args.steps * 1e3, 4)}
+        extra["conv_diff_256"] = conv
+        del A3, B3, b3
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -209,12 +322,12 @@ def main():
     value = results[main_m]["it_per_s"]
     out = {
         "metric": METRIC,
-        "value": round(value, 3),
+        "value": value,
         "unit": "outer_iters/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(results[main_m]["ms_per_step"], 4),
+        "ms_per_step": results[main_m]["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -229,11 +342,11 @@ def main():
                      "algorithmic_bytes_per_launch": upd_bytes},
         "cpu_baseline": cpu,
         "compare": {
-            other: {"it_per_s": round(results[other]["it_per_s"], 3),
-                    "ms_per_step": round(results[other]["ms_per_step"], 4)},
+            other: results[other],
             "pipelined_over_unpipelined": round(results["pipefcg"]["it_per_s"] / results["fcg"]["it_per_s"], 4),
             "algorithmic_GBps_whole_iteration": {m: round(v, 1) for m, v in eff.items()},
             "algorithmic_bytes_per_iteration": it_bytes,
+            **extra,
         },
         "kernels": kernels,
     }

@@ -115,6 +115,27 @@ def _edge_potential(dim_pts, rng, kmax: int = 2):
             out += a * np.sin(2.0 * math.pi * (kx * X + ky * Y + kz * Z) + phi)
         return out
 
+    def psi_grid(c, xs, ys, zs):
+        """psi(c) on the tensor grid xs (x) ys (x) zs, returned as [z][y][x]:
+        sin(t + phi) = Im(e^{i phi} e^{i 2 pi kx x} e^{i 2 pi ky y} e^{i 2 pi kz z}),
+        summed one axis at a time (the same value as psi up to rounding)."""
+        K = 2 * kmax + 1
+        C3 = np.zeros((K, K, K), dtype=np.complex128)          # [kx][ky][kz]
+        for (kx, ky, kz, a, phi) in coef[c]:
+            C3[kx + kmax, ky + kmax, kz + kmax] += a * np.exp(1j * phi)
+        kk = np.arange(-kmax, kmax + 1, dtype=np.float64)[:, None]
+        Ex = np.exp(2j * math.pi * kk * np.asarray(xs)[None, :])  # [kx][x]
+        Ey = np.exp(2j * math.pi * kk * np.asarray(ys)[None, :])
+        Ez = np.exp(2j * math.pi * kk * np.asarray(zs)[None, :])
+        T1 = np.einsum("abc,cz->abz", C3, Ez)                  # [kx][ky][z]
+        T2 = np.einsum("abz,by->azy", T1, Ey)                  # [kx][z][y]
+        out = np.zeros((len(zs), len(ys), len(xs)))
+        for a in range(K):
+            out += (T2[a][:, :, None] * Ex[a][None, None, :]).imag
+        return out
+
+    psi.grid = psi_grid
+
     return psi
 
 
@@ -132,12 +153,10 @@ def divfree_face_velocity(n: int, rng, cell_peclet: float = 5.0,
     h = 1.0 / (n + 1)
     psi = _edge_potential(3, rng)
     a = np.arange(n + 2, dtype=np.float64)
-    # index arrays [k][j][i]
-    K, J, I = np.meshgrid(a, a, a, indexing="ij")
 
     def P(c, di, dj, dk):
-        # potential component c at the dual edge offset by (di,dj,dk)*h/2
-        return psi(c, (I + di) * h, (J + dj) * h, (K + dk) * h)
+        # potential component c at the dual edge offset by (di,dj,dk)*h/2, as [k][j][i]
+        return psi.grid(c, (a + di) * h, (a + dj) * h, (a + dk) * h)
 
     # Psi_x on x-edges at (i, j+1/2, k+1/2); Psi_y at (i+1/2, j, k+1/2);
     # Psi_z at (i+1/2, j+1/2, k).

@@ -98,8 +98,9 @@ typedef struct {
                               pfk_estimate_sigma (10 power steps)                    */
   int graph_iters;         /* iterations per captured graph launch (>= 1)            */
   int use_graph;           /* 1: replay hipGraphs; 0: launch kernels directly         */
-  int host_sync;           /* unpipelined methods only: 1 copies every reduction
-                              result to the host and waits (a blocking reduction)    */
+  int host_sync;           /* FCG, GCR, FGMRES only (PFK_ERR_ARG otherwise): 1 copies
+                              every reduction result to the host and waits for it
+                              (a blocking reduction); turns graphs off               */
   int max_restarts;        /* breakdown / residual-gap restarts allowed               */
   int force_breakdown_at;  /* test hook: force a breakdown at this iteration (-1 off) */
 } pfk_solve_opts;
@@ -149,6 +150,36 @@ int pfk_precond_create(pfk_operator A, pfk_pc_kind kind, int inner_its, pfk_prec
 void pfk_precond_destroy(pfk_precond B);
 /* y = B(v) for device vectors (synchronous w.r.t. stream completion of the call). */
 int pfk_precond_apply(pfk_precond B, const double* v, double* y, void* stream);
+
+/* Launch geometry of A's kernels (performance only; results do not depend
+ * on it beyond rounding).  tile_x: stencil tiles of 64 x 8 (64) or 32 x 16
+ * (32) nodes; stencil_target: about this many workgroups per stencil launch
+ * (the z-range is cut into chunks); vector_blocks: workgroups of the vector
+ * kernels (window updates, multi-dots), which is also the number of partial
+ * sums each reduction finishes.  A session or solve takes the geometry A has
+ * when it is created.  Errors: PFK_ERR_ARG (tile_x not 32/64, counts outside
+ * 1..16384). */
+int pfk_operator_set_tiling(pfk_operator A, int tile_x, int stencil_target, int vector_blocks);
+int pfk_operator_get_tiling(pfk_operator A, int* tile_x, int* stencil_blocks, int* vector_blocks);
+
+typedef struct {
+  int tile_x;               /* chosen stencil tile width                          */
+  int stencil_blocks;       /* chosen workgroups per stencil launch               */
+  int vector_blocks;        /* chosen workgroups per vector launch                */
+  double ms_per_iteration;  /* best measured time of one outer iteration          */
+  double ms_default;        /* the same with the geometry A had before            */
+  int candidates;           /* configurations timed                               */
+} pfk_tuning;
+
+/* Autotuner: times outer iterations of `method` with B (window/restart mmax)
+ * on this GPU for each candidate geometry -- tile widths 64 and 32 with
+ * several z-chunkings, then vector workgroup counts from 64 up to N/512 --
+ * and sets the fastest on A (pfk_operator_set_tiling).  CG/CR types are timed
+ * over `reps` steady-state iterations, GMRES types over whole cycles.  Uses
+ * library-allocated memory (about one solve's workspace) and synchronises
+ * `stream`.  Errors: PFK_ERR_ARG, PFK_ERR_OOM, PFK_ERR_HIP. */
+int pfk_operator_autotune(pfk_operator A, pfk_precond B, pfk_method method, int mmax, int reps, void* stream,
+                          pfk_tuning* out);
 
 /* Bytes of workspace pfk_solve needs for this method, window/restart length
  * `mmax` (1..64) and iteration limit `maxit`. */

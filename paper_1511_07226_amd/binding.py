@@ -34,7 +34,16 @@ EXPORTED = [
     "pfk_precond_apply", "pfk_workspace_bytes", "pfk_solve", "pfk_session_create",
     "pfk_session_start", "pfk_session_iterate", "pfk_session_sync", "pfk_session_destroy",
     "pfk_session_profile", "pfk_estimate_sigma", "pfk_last_error",
+    "pfk_operator_set_tiling", "pfk_operator_get_tiling", "pfk_operator_autotune",
 ]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("tile_x", C.c_int), ("stencil_blocks", C.c_int), ("vector_blocks", C.c_int),
+                ("ms_per_iteration", C.c_double), ("ms_default", C.c_double), ("candidates", C.c_int)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class PfkError(RuntimeError):
@@ -108,6 +117,9 @@ def lib():
                                           C.POINTER(C.c_double), C.POINTER(C.c_int)]),
         "pfk_estimate_sigma": (C.c_int, [vp, vp, C.c_int, C.POINTER(C.c_double), vp]),
         "pfk_last_error": (C.c_char_p, []),
+        "pfk_operator_set_tiling": (C.c_int, [vp, C.c_int, C.c_int, C.c_int]),
+        "pfk_operator_get_tiling": (C.c_int, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+        "pfk_operator_autotune": (C.c_int, [vp, vp, C.c_int, C.c_int, C.c_int, vp, C.POINTER(Tuning)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -188,6 +200,22 @@ class Operator:
                                         _stream_ptr(stream)))
         return y
 
+    def tiling(self) -> tuple:
+        """(tile_x, stencil workgroups, vector workgroups) of this operator's launches."""
+        a, b, c = C.c_int(), C.c_int(), C.c_int()
+        _check(lib().pfk_operator_get_tiling(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def set_tiling(self, tile_x: int, stencil_target: int, vector_blocks: int):
+        _check(lib().pfk_operator_set_tiling(self._h, int(tile_x), int(stencil_target), int(vector_blocks)))
+
+    def autotune(self, B, method: str = "pipefcg", mmax: int = 30, reps: int = 5, stream=None) -> dict:
+        """Time candidate launch geometries on this GPU and keep the fastest."""
+        t = Tuning()
+        _check(lib().pfk_operator_autotune(self._h, B.handle, METHODS[method], int(mmax), int(reps),
+                                           _stream_ptr(stream), C.byref(t)))
+        return t.as_dict()
+
     def diag_inv(self, stream=None):
         import torch
         d = torch.empty(self.N, dtype=torch.float64, device="cuda")
@@ -227,6 +255,13 @@ class Precond:
 
 def workspace_bytes(A: Operator, B: Precond, method: str, mmax: int, maxit: int) -> int:
     return int(lib().pfk_workspace_bytes(A.handle, B.handle, METHODS[method], mmax, maxit))
+
+
+def estimate_sigma(A: Operator, B: Precond, its: int = 10, stream=None) -> float:
+    """PIPEFGMRES shift: Rayleigh quotient of v -> A B(v) after `its` power steps."""
+    sig = C.c_double()
+    _check(lib().pfk_estimate_sigma(A.handle, B.handle, int(its), C.byref(sig), _stream_ptr(stream)))
+    return sig.value
 
 
 def _info_struct(cap: int):

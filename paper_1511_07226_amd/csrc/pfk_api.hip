@@ -63,26 +63,15 @@ k_dinv(Grid g, StencilGeom sg, double* __restrict__ dinv) {
 // in FP32: the inner stencil applied to the unit vector at i.
 __global__ void __launch_bounds__(kBlock)
 k_dinv_mixed(GridM g, StencilGeom sg, float* __restrict__ dinv) {
-  const int L = xcd_tile(sg.blocks());
-  const int tx = L % sg.tiles_x;
-  const int ty = (L / sg.tiles_x) % sg.tiles_y;
-  const int tz = L / (sg.tiles_x * sg.tiles_y);
-  const int i = tx * kTileX + (threadIdx.x & 63);
-  const int k0 = tz * sg.zc;
-  const int k1 = min(g.nz, k0 + sg.zc);
-  for (int r = 0; r < 2; ++r) {
-    const int j = ty * kTileY + (threadIdx.x >> 6) + 4 * r;
-    if (i >= g.nx || j >= g.ny) continue;
-    for (int k = k0; k < k1; ++k) {
-      const long long pc = padded_index(g, i, j, k);
-      const bool d3 = g.dim == 3;
-      auto E = [&](long long q) { return to_real(g.eta[q]); };
-      const float d = apply_faces<float>(g, pc, 1.0f, E(pc), E(pc + 1), E(pc - 1), E(pc + g.sy), E(pc - g.sy),
-                                         d3 ? E(pc + g.sz) : 0.0f, d3 ? E(pc - g.sz) : 0.0f, 0.f, 0.f, 0.f, 0.f,
-                                         0.f, 0.f);
-      dinv[vec_index(g, i, j, k)] = 1.0f / d;
-    }
-  }
+  for_tile_nodes(g, sg, [&](int i, int j, int k, long long idx) {
+    const long long pc = padded_index(g, i, j, k);
+    const bool d3 = g.dim == 3;
+    auto E = [&](long long q) { return to_real(g.eta[q]); };
+    const float d = apply_faces<float>(g, pc, 1.0f, E(pc), E(pc + 1), E(pc - 1), E(pc + g.sy), E(pc - g.sy),
+                                       d3 ? E(pc + g.sz) : 0.0f, d3 ? E(pc - g.sz) : 0.0f, 0.f, 0.f, 0.f, 0.f,
+                                       0.f, 0.f);
+    dinv[idx] = 1.0f / d;
+  });
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -182,12 +171,15 @@ struct pfk_precond_s {
   size_t scratch_bytes = 0;
 };
 
-static StencilGeom make_geom(int dim, int nx, int ny, int nz) {
+// Stencil geometry for tile width tx (64: 64 x 8 tiles, 32: 32 x 16) and a
+// target of about `target` workgroups (the z-range is cut into chunks).
+static StencilGeom make_geom(int dim, int nx, int ny, int nz, int tx = 64, int target = 2048) {
   StencilGeom sg;
-  sg.tiles_x = (nx + kTileX - 1) / kTileX;
-  sg.tiles_y = (ny + kTileY - 1) / kTileY;
+  sg.tx = tx;
+  const int ty = 2 * kBlock / tx;
+  sg.tiles_x = (nx + tx - 1) / tx;
+  sg.tiles_y = (ny + ty - 1) / ty;
   const int tiles = sg.tiles_x * sg.tiles_y;
-  const int target = 2048;
   int chunks = dim == 3 ? std::max(1, std::min(nz, (target + tiles - 1) / tiles)) : 1;
   sg.zc = (nz + chunks - 1) / chunks;
   sg.zchunks = (nz + sg.zc - 1) / sg.zc;
@@ -418,7 +410,10 @@ void window_slots(int method, int mmax, int* slots) {
   }
 }
 
-Layout make_layout(const pfk_operator_s* A, const pfk_precond_s* B, int method, int mmax, int maxit) {
+// pmin: partial-sum arrays hold at least pmin workgroups (the autotuner's
+// largest candidate); otherwise the operator's current launch geometry.
+Layout make_layout(const pfk_operator_s* A, const pfk_precond_s* B, int method, int mmax, int maxit,
+                   int pmin = 0) {
   Layout L;
   size_t off = 0;
   L.state = off;
@@ -437,7 +432,7 @@ Layout make_layout(const pfk_operator_s* A, const pfk_precond_s* B, int method, 
     L.win[w] = off;
     off += vbytes * (size_t)L.slots[w];
   }
-  const int P = std::max(A->sg.blocks(), A->pv_blocks);
+  const int P = std::max(std::max(A->sg.blocks(), A->pv_blocks), pmin);
   const size_t pbytes = align_up(sizeof(double) * (size_t)P * (kNuMax + 4));
   for (int p = 0; p < PT_COUNT; ++p) {
     L.part[p] = off;
@@ -482,8 +477,12 @@ struct pfk_session_s {
   Window win(int w) const { return Window{(double*)(ws + L.win[w]), L.ld}; }
   double* part(int p) const { return (double*)(ws + L.part[p]); }
   Grid grid() const { return A->grid(); }
-  int Ps() const { return A->sg.blocks(); }
-  int Pv() const { return A->pv_blocks; }
+  // launch geometry, fixed when the session is made (the workspace's
+  // partial-sum arrays are sized for it)
+  StencilGeom sg{};
+  int pv = 0;
+  int Ps() const { return sg.blocks(); }
+  int Pv() const { return pv; }
 };
 
 namespace {
@@ -572,7 +571,7 @@ void enqueue_pc_kernels(pfk_session_s* S, hipStream_t s, const PcOutDesc& d, con
     T* q = (T*)S->vec(V_PC_Q);
     T* rho = (T*)S->vec(V_PC_RHO);
     T* y = (T*)S->vec(V_PC_Y);
-    LAUNCH((k_pcg_a1<T, G>), S->Ps(), s, g, A->sg, dinv, X1, c1, X2, c2, pp[0], q, part[0],
+    LAUNCH((k_pcg_a1<T, G>), S->Ps(), s, g, S->sg, dinv, X1, c1, X2, c2, pp[0], q, part[0],
            (const SolveState*)S->st);
     int t = 1, Pprev = S->Ps();
     for (int j = 1; j < d.k; ++j) {
@@ -580,7 +579,7 @@ void enqueue_pc_kernels(pfk_session_s* S, hipStream_t s, const PcOutDesc& d, con
              y, (const double*)part[(t - 1) & 1], Pprev, part[t & 1], S->st);
       Pprev = S->Pv();
       ++t;
-      LAUNCH((k_pcg_a<T, G>), S->Ps(), s, j + 1, g, A->sg, dinv, (const T*)rho, (const T*)pp[(j - 1) & 1],
+      LAUNCH((k_pcg_a<T, G>), S->Ps(), s, j + 1, g, S->sg, dinv, (const T*)rho, (const T*)pp[(j - 1) & 1],
              pp[j & 1], q, (const double*)part[(t - 1) & 1], Pprev, part[t & 1], S->st);
       Pprev = S->Ps();
       ++t;
@@ -603,7 +602,7 @@ void enqueue_pc_kernels(pfk_session_s* S, hipStream_t s, const PcOutDesc& d, con
     LAUNCH((k_gmpc_start<T>), S->Pv(), s, A->N, d.k, X1, c1, X2, c2, V, part[0], S->st);
     int t = 1, Pprev = S->Pv();
     for (int j = 0; j < d.k; ++j) {
-      LAUNCH((k_gmpc_apply<T, G>), S->Ps(), s, j, g, A->sg, dinv, (const T*)V, ldv, w,
+      LAUNCH((k_gmpc_apply<T, G>), S->Ps(), s, j, g, S->sg, dinv, (const T*)V, ldv, w,
              (const double*)part[(t - 1) & 1], Pprev, part[t & 1], S->st);
       Pprev = S->Ps();
       ++t;
@@ -631,6 +630,16 @@ void enqueue_multidot(pfk_session_s* S, hipStream_t s, int init, int from_pc, co
          S->win(W_S), S->part(PT_MAIN), S->st);
 }
 
+// The host-sync form of the unpipelined baselines: a reduction's result is
+// copied to the host, which waits for it before enqueuing more work (the
+// analogue of a blocking all-reduce).  host_sync turns graphs off, so this
+// never runs under capture.
+void host_wait(pfk_session_s* S, hipStream_t s) {
+  if (!S->opts.host_sync) return;
+  (void)hipMemcpyAsync(&S->host_state->gamma, &S->st->gamma, sizeof(double), hipMemcpyDeviceToHost, s);
+  (void)hipStreamSynchronize(s);
+}
+
 // FCG / GCR: the part of an iteration after x, r have been updated, also
 // the start-up (init = 1).
 //   FCG: u = B(r); reduction 1 (<u,r>, <r,r>, <u,s_d>); p = u + sum beta p;
@@ -643,17 +652,21 @@ void enqueue_cg_body(pfk_session_s* S, hipStream_t s, int init) {
   if (S->method == PFK_FCG) {
     enqueue_multidot(S, s, init, 1, pd, nullptr, S->vec(V_U));
     LAUNCH(k_cg_scalars1, 1, s, init, S->part(PT_MAIN), S->Pv(), S->st, S->hist);
+    host_wait(S, s);
     LAUNCH(k_fcg_maxpy, S->Pv(), s, S->A->N, S->win(W_P), (const double*)S->vec(V_U), (const SolveState*)S->st);
-    LAUNCH(k_fcg_apply, S->Ps(), s, g, S->A->sg, S->win(W_P), S->win(W_S), S->part(PT_A), (const SolveState*)S->st);
+    LAUNCH(k_fcg_apply, S->Ps(), s, g, S->sg, S->win(W_P), S->win(W_S), S->part(PT_A), (const SolveState*)S->st);
     LAUNCH(k_cg_scalars2, 1, s, 0, init, S->part(PT_A), S->Ps(), S->st);
+    host_wait(S, s);
   } else {
-    LAUNCH(k_apply_pc_out, S->Ps(), s, g, S->A->sg, pd, (const double*)nullptr, 0.0, S->vec(V_U), S->vec(V_W), 0,
+    LAUNCH(k_apply_pc_out, S->Ps(), s, g, S->sg, pd, (const double*)nullptr, 0.0, S->vec(V_U), S->vec(V_W), 0,
            (const double*)nullptr, S->part(PT_B), S->st);
     enqueue_multidot(S, s, init, 0, pd, S->vec(V_W), nullptr);
     LAUNCH(k_cg_scalars1, 1, s, init, S->part(PT_MAIN), S->Pv(), S->st, S->hist);
+    host_wait(S, s);
     LAUNCH(k_gcr_maxpy, S->Pv(), s, S->A->N, S->win(W_P), S->win(W_S), (const double*)S->vec(V_U),
            (const double*)S->vec(V_W), (const double*)S->vec(V_R), S->part(PT_A), (const SolveState*)S->st);
     LAUNCH(k_cg_scalars2, 1, s, 1, init, S->part(PT_A), S->Pv(), S->st);
+    host_wait(S, s);
   }
 }
 
@@ -663,7 +676,7 @@ void enqueue_start(pfk_session_s* S, hipStream_t s) {
   const Grid g = S->grid();
   const bool gm = S->method == PFK_FGMRES || S->method == PFK_PIPEFGMRES;
   LAUNCH(k_restart, 1, s, S->st);
-  LAUNCH(k_residual, S->Ps(), s, g, A->sg, S->b, (const double*)S->x, S->vec(V_R), S->part(PT_A),
+  LAUNCH(k_residual, S->Ps(), s, g, S->sg, S->b, (const double*)S->x, S->vec(V_R), S->part(PT_A),
          gm ? S->vec(V_X0) : nullptr);
   switch (S->method) {
     case PFK_FCG:
@@ -674,11 +687,11 @@ void enqueue_start(pfk_session_s* S, hipStream_t s) {
     case PFK_PIPEFCG: {
       // u_0 = B(r_0), w_0 = A u_0, gamma_0 = <u_0,r_0>, delta_0 = <u_0,w_0>
       PcOutDesc pd = enqueue_pc(S, s, S->vec(V_R), 1.0, nullptr, 0.0);
-      LAUNCH(k_apply_pc_out, S->Ps(), s, g, A->sg, pd, (const double*)nullptr, 0.0, S->vec(V_U), S->vec(V_W), 1,
+      LAUNCH(k_apply_pc_out, S->Ps(), s, g, S->sg, pd, (const double*)nullptr, 0.0, S->vec(V_U), S->vec(V_W), 1,
              (const double*)S->vec(V_R), S->part(PT_B), S->st);
       // m_0 = B(w_0), n_0 = A m_0
       pd = enqueue_pc(S, s, S->vec(V_W), 1.0, nullptr, 0.0);
-      LAUNCH(k_apply_pc_out, S->Ps(), s, g, A->sg, pd, (const double*)nullptr, 0.0, S->vec(V_M), S->vec(V_N), 0,
+      LAUNCH(k_apply_pc_out, S->Ps(), s, g, S->sg, pd, (const double*)nullptr, 0.0, S->vec(V_M), S->vec(V_N), 0,
              (const double*)nullptr, S->part(PT_B), S->st);
       LAUNCH(k_pipefcg_init_scalars, 1, s, S->part(PT_A), S->Ps(), S->part(PT_B), S->Ps(), S->st, S->hist);
       break;
@@ -687,7 +700,7 @@ void enqueue_start(pfk_session_s* S, hipStream_t s) {
       LAUNCH(k_init_test, 1, s, S->part(PT_A), S->Ps(), S->st, S->hist);
       // u_0 = B(r_0), s_0 = A u_0 (kept in w), gamma_0 = <r_0,s_0>, eta_0 = <s_0,s_0>
       PcOutDesc pd = enqueue_pc(S, s, S->vec(V_R), 1.0, nullptr, 0.0);
-      LAUNCH(k_apply_pc_out, S->Ps(), s, g, A->sg, pd, (const double*)nullptr, 0.0, S->vec(V_U), S->vec(V_W), 0,
+      LAUNCH(k_apply_pc_out, S->Ps(), s, g, S->sg, pd, (const double*)nullptr, 0.0, S->vec(V_U), S->vec(V_W), 0,
              (const double*)nullptr, S->part(PT_B), S->st);
       enqueue_multidot(S, s, 1, 0, pd, S->vec(V_W), nullptr);
       // q_0 = B(s_0), consumed by the first update
@@ -706,11 +719,11 @@ void enqueue_start(pfk_session_s* S, hipStream_t s) {
              (const SolveState*)S->st);
       // u~_0 = B(p_0), zbar_0 = A u~_0 - sigma p_0, first reduction
       PcOutDesc pd = enqueue_pc(S, s, S->vec(V_VIN), 1.0, nullptr, 0.0);
-      LAUNCH(k_pgm_apply0, S->Ps(), s, g, A->sg, pd, S->win(W_S), S->win(W_P), S->win(W_Q), S->vec(V_M),
+      LAUNCH(k_pgm_apply0, S->Ps(), s, g, S->sg, pd, S->win(W_S), S->win(W_P), S->win(W_Q), S->vec(V_M),
              S->part(PT_MAIN), S->st);
       // qbar_0 = B(zbar_0), wbar_0 = A qbar_0
       pd = enqueue_pc(S, s, S->vec(V_M), 1.0, nullptr, 0.0);
-      LAUNCH(k_apply_pc_out, S->Ps(), s, g, A->sg, pd, (const double*)nullptr, 0.0, (double*)nullptr,
+      LAUNCH(k_apply_pc_out, S->Ps(), s, g, S->sg, pd, (const double*)nullptr, 0.0, (double*)nullptr,
              S->vec(V_Z), 0, (const double*)nullptr, S->part(PT_B), S->st);
       LAUNCH(k_pgm_scalars, 1, s, S->part(PT_MAIN), S->Ps(), S->st, S->hist);   // partials of k_pgm_apply0
       LAUNCH(k_gm_update_x, S->Pv(), s, A->N, S->win(W_S), (const double*)S->vec(V_X0), S->x,
@@ -743,7 +756,7 @@ void enqueue_iteration(pfk_session_s* S) {
       LAUNCH(k_pipefcg_scalars, 1, s2, S->part(PT_MAIN), S->Pv(), S->st, S->hist);
       (void)hipEventRecord(S->ev_join, s2);
       PcOutDesc pd = enqueue_pc(S, s1, S->vec(V_W), 1.0, S->vec(V_R), -1.0);
-      LAUNCH(k_apply_pc_out, S->Ps(), s1, g, A->sg, pd, (const double*)S->vec(V_U), 1.0, S->vec(V_M),
+      LAUNCH(k_apply_pc_out, S->Ps(), s1, g, S->sg, pd, (const double*)S->vec(V_U), 1.0, S->vec(V_M),
              S->vec(V_N), 0, (const double*)nullptr, S->part(PT_B), S->st);
       (void)hipStreamWaitEvent(s1, S->ev_join, 0);
       break;
@@ -753,7 +766,7 @@ void enqueue_iteration(pfk_session_s* S) {
       const PcOutDesc pd_prev = pc_out_desc(S, S->vec(V_W), 1.0, S->vec(V_R), -1.0);
       LAUNCH(k_pipegcr_update, S->Pv(), s1, A->N, S->win(W_P), S->win(W_S), S->win(W_Q), S->x, S->vec(V_R),
              S->vec(V_U), (const double*)S->vec(V_W), pd_prev, S->st);
-      LAUNCH(k_apply, S->Ps(), s1, g, A->sg, (const double*)S->vec(V_U), S->vec(V_W), (const SolveState*)S->st);
+      LAUNCH(k_apply, S->Ps(), s1, g, S->sg, (const double*)S->vec(V_U), S->vec(V_W), (const SolveState*)S->st);
       enqueue_multidot(S, s1, 0, 0, pd_prev, S->vec(V_W), nullptr);
       (void)hipEventRecord(S->ev_fork, s1);
       (void)hipStreamWaitEvent(s2, S->ev_fork, 0);
@@ -765,13 +778,15 @@ void enqueue_iteration(pfk_session_s* S) {
     }
     case PFK_FGMRES: {
       PcOutDesc pd = enqueue_pc(S, s1, S->vec(V_VIN), 1.0, nullptr, 0.0);
-      LAUNCH(k_fgm_apply, S->Ps(), s1, g, A->sg, pd, S->win(W_S), S->vec(V_Z), S->st);
+      LAUNCH(k_fgm_apply, S->Ps(), s1, g, S->sg, pd, S->win(W_S), S->vec(V_Z), S->st);
       LAUNCH(k_fgm_dots, S->Pv(), s1, A->N, S->win(W_P), (const double*)S->vec(V_Z), S->part(PT_MAIN),
              (const SolveState*)S->st);
       LAUNCH(k_gm_hbar, 1, s1, S->part(PT_MAIN), S->Pv(), S->st);
+      host_wait(S, s1);
       LAUNCH(k_fgm_orth, S->Pv(), s1, A->N, S->win(W_P), (const double*)S->vec(V_Z), S->part(PT_A),
              (const SolveState*)S->st);
       LAUNCH(k_fgm_column, 1, s1, S->part(PT_A), S->Pv(), S->st, S->hist);
+      host_wait(S, s1);
       LAUNCH(k_gm_scale, S->Pv(), s1, A->N, (const double*)nullptr, 1, S->win(W_P), S->vec(V_VIN),
              (const SolveState*)S->st);
       LAUNCH(k_gm_update_x, S->Pv(), s1, A->N, S->win(W_S), (const double*)S->vec(V_X0), S->x,
@@ -788,7 +803,7 @@ void enqueue_iteration(pfk_session_s* S) {
       LAUNCH(k_pgm_scalars, 1, s2, S->part(PT_MAIN), S->Pv(), S->st, S->hist);
       (void)hipEventRecord(S->ev_join, s2);
       PcOutDesc pd = enqueue_pc(S, s1, S->vec(V_M), 1.0, nullptr, 0.0);
-      LAUNCH(k_apply_pc_out, S->Ps(), s1, g, A->sg, pd, (const double*)nullptr, 0.0, (double*)nullptr,
+      LAUNCH(k_apply_pc_out, S->Ps(), s1, g, S->sg, pd, (const double*)nullptr, 0.0, (double*)nullptr,
              S->vec(V_Z), 0, (const double*)nullptr, S->part(PT_B), S->st);
       (void)hipStreamWaitEvent(s1, S->ev_join, 0);
       LAUNCH(k_gm_update_x, S->Pv(), s1, A->N, S->win(W_S), (const double*)S->vec(V_X0), S->x,
@@ -802,7 +817,7 @@ void enqueue_iteration(pfk_session_s* S) {
 
 void enqueue_true_check(pfk_session_s* S, hipStream_t s) {
   const pfk_operator_s* A = S->A;
-  LAUNCH(k_residual, S->Ps(), s, S->grid(), A->sg, S->b, (const double*)S->x, S->vec(V_R), S->part(PT_A),
+  LAUNCH(k_residual, S->Ps(), s, S->grid(), S->sg, S->b, (const double*)S->x, S->vec(V_R), S->part(PT_A),
          (double*)nullptr);
   LAUNCH(k_true_check, 1, s, S->part(PT_A), S->Ps(), S->st);
 }
@@ -817,7 +832,7 @@ void enqueue_sigma_estimate(pfk_session_s* S, hipStream_t s, int its) {
   LAUNCH(k_fill, S->Pv(), s, A->N, v, 1.0 / std::sqrt((double)A->N));
   for (int i = 0; i < its; ++i) {
     PcOutDesc pd = enqueue_pc(S, s, v, 1.0, nullptr, 0.0);
-    LAUNCH(k_apply_pc_out, S->Ps(), s, S->grid(), A->sg, pd, (const double*)nullptr, 0.0, (double*)nullptr, w, 0,
+    LAUNCH(k_apply_pc_out, S->Ps(), s, S->grid(), S->sg, pd, (const double*)nullptr, 0.0, (double*)nullptr, w, 0,
            (const double*)nullptr, S->part(PT_B), S->st);
     LAUNCH(k_dot2, S->Pv(), s, A->N, (const double*)v, (const double*)w, S->part(PT_MAIN));
     LAUNCH(k_power_step, S->Pv(), s, A->N, (const double*)S->part(PT_MAIN), S->Pv(), v, (const double*)w, S->st);
@@ -907,7 +922,16 @@ extern "C" int pfk_session_create(pfk_operator A, pfk_precond B, pfk_method meth
     delete S;
     return fail(PFK_ERR_ARG, "truncation must be 0, 1 or 2");
   }
+  if (S->opts.host_sync) {
+    if (method != PFK_FCG && method != PFK_GCR && method != PFK_FGMRES) {
+      delete S;
+      return fail(PFK_ERR_ARG, "host_sync applies to FCG, GCR and FGMRES only");
+    }
+    S->opts.use_graph = 0;   // the host waits inside every iteration
+  }
   S->L = make_layout(A, B, method, mmax, maxit);
+  S->sg = A->sg;
+  S->pv = A->pv_blocks;
   if (workspace) {
     if (ws_bytes < S->L.total) {
       delete S;
@@ -1101,6 +1125,7 @@ extern "C" int pfk_precond_apply(pfk_precond B, const double* v, double* y, void
   }
   pfk_session_s S;
   S.A = A; S.B = B; S.ws = B->scratch; S.L = L; S.mmax = 1;
+  S.sg = A->sg; S.pv = A->pv_blocks;
   S.st = (SolveState*)(S.ws + L.state);
   hipStream_t s = (hipStream_t)stream;
   LAUNCH(k_set_running, 1, s, S.st);
@@ -1157,6 +1182,7 @@ extern "C" int pfk_estimate_sigma(pfk_operator A, pfk_precond B, int its, double
   if (hipMalloc(&ws, L.total) != hipSuccess) return fail(PFK_ERR_OOM, "sigma estimate workspace");
   pfk_session_s S;
   S.A = A; S.B = B; S.ws = ws; S.L = L; S.mmax = 1;
+  S.sg = A->sg; S.pv = A->pv_blocks;
   S.st = (SolveState*)(S.ws + L.state);
   hipStream_t s = (hipStream_t)stream;
   enqueue_sigma_estimate(&S, s, its);
@@ -1172,4 +1198,178 @@ extern "C" int pfk_estimate_sigma(pfk_operator A, pfk_precond B, int its, double
   if (h) (void)hipHostFree(h);
   (void)hipFree(ws);
   return rc;
+}
+
+// ---------------------------------------------------------------------------
+// launch geometry and its autotuner
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kMaxLaunchBlocks = 16384;   // largest workgroup count of a stencil or vector launch
+
+int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+}  // namespace
+
+extern "C" int pfk_operator_set_tiling(pfk_operator A, int tile_x, int stencil_target, int vector_blocks) {
+  if (!A) return fail(PFK_ERR_ARG, "null operator");
+  if (tile_x != 32 && tile_x != 64) return fail(PFK_ERR_ARG, "tile_x must be 32 or 64");
+  if (stencil_target < 1 || stencil_target > kMaxLaunchBlocks) return fail(PFK_ERR_ARG, "stencil_target out of range");
+  if (vector_blocks < 1 || vector_blocks > kMaxLaunchBlocks) return fail(PFK_ERR_ARG, "vector_blocks out of range");
+  const StencilGeom sg = make_geom(A->dim, (int)A->n[0], (int)A->n[1], (int)A->n[2], tile_x, stencil_target);
+  if (sg.blocks() > kMaxLaunchBlocks) return fail(PFK_ERR_ARG, "stencil launch too large");
+  A->sg = sg;
+  A->pv_blocks = vector_blocks;
+  return PFK_OK;
+}
+
+extern "C" int pfk_operator_get_tiling(pfk_operator A, int* tile_x, int* stencil_blocks, int* vector_blocks) {
+  if (!A) return fail(PFK_ERR_ARG, "null operator");
+  if (tile_x) *tile_x = A->sg.tx;
+  if (stencil_blocks) *stencil_blocks = A->sg.blocks();
+  if (vector_blocks) *vector_blocks = A->pv_blocks;
+  return PFK_OK;
+}
+
+// Time whole outer iterations of `method` with B on A for each candidate launch
+// geometry (coordinate search: stencil tile shape and z-chunking first, then
+// the vector kernels' workgroup count) and keep the fastest in A.  The solve
+// runs from b = 1, x = 0 with rtol = 0 in library-owned memory; the window is
+// filled before timing, so every timed iteration is a steady-state one.
+extern "C" int pfk_operator_autotune(pfk_operator A, pfk_precond B, pfk_method method, int mmax, int reps,
+                                     void* stream, pfk_tuning* out) {
+  if (!A || !B) return fail(PFK_ERR_ARG, "null argument");
+  if (B->A != A) return fail(PFK_ERR_ARG, "preconditioner was made for another operator");
+  if (method < PFK_FCG || method > PFK_PIPEFGMRES) return fail(PFK_ERR_ARG, "unknown method");
+  if (mmax < 1 || mmax > kNuMax) return fail(PFK_ERR_ARG, "mmax must be 1..64");
+  if (reps < 1) reps = 5;
+  const int nx = (int)A->n[0], ny = (int)A->n[1], nz = (int)A->n[2];
+  // candidates
+  std::vector<StencilGeom> geoms;
+  for (int tx : {64, 32})
+    for (int target : {512, 1024, 2048, 4096}) {
+      const StencilGeom g = make_geom(A->dim, nx, ny, nz, tx, target);
+      bool dup = false;
+      for (const auto& h : geoms) dup = dup || (h.tx == g.tx && h.zc == g.zc);
+      if (!dup && g.blocks() <= kMaxLaunchBlocks) geoms.push_back(g);
+    }
+  std::vector<int> pvs;
+  const int pv_cap = std::max(1, std::min(kMaxLaunchBlocks, ceil_div(A->N, 2LL * kBlock)));
+  for (int v = 64; v < pv_cap; v *= 2) pvs.push_back(v);
+  pvs.push_back(pv_cap);
+  int pmax = 0;
+  for (const auto& g : geoms) pmax = std::max(pmax, g.blocks());
+  for (int v : pvs) pmax = std::max(pmax, v);
+
+  const StencilGeom sg0 = A->sg;
+  const int pv0 = A->pv_blocks;
+  double* bx = nullptr;
+  if (hipMalloc(&bx, 2 * sizeof(double) * (size_t)((A->N + 31) / 32 * 32)) != hipSuccess)
+    return fail(PFK_ERR_OOM, "autotune vectors");
+  double* b = bx;
+  double* x = bx + (A->N + 31) / 32 * 32;
+  hipStream_t us = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_fill, dim3(A->pv_blocks), dim3(kBlock), 0, us, A->N, b, 1.0);
+  hipLaunchKernelGGL(k_fill, dim3(A->pv_blocks), dim3(kBlock), 0, us, A->N, x, 0.0);
+  pfk_solve_opts o;
+  pfk_default_opts(&o);
+  o.use_graph = 0;
+  // GMRES types are timed over whole cycles from a restart (a column's cost
+  // grows with its index); CG/CR types over steady-state iterations
+  const bool gm = method == PFK_FGMRES || method == PFK_PIPEFGMRES;
+  if (gm) reps = mmax;
+  if (method == PFK_PIPEFGMRES) {
+    double sig = 0.0;
+    const int r0 = pfk_estimate_sigma(A, B, 10, &sig, stream);
+    if (r0) {
+      (void)hipFree(bx);
+      return r0;
+    }
+    o.shift_sigma = sig;
+  }
+  const int warm = gm ? 0 : mmax + 2;
+  const int maxit = warm + (int)(geoms.size() + pvs.size() + 2) * (reps + mmax + 2) + 16;
+  pfk_session S = nullptr;
+  int rc = pfk_session_create(A, B, method, b, x, 0.0, maxit, mmax, nullptr, 0, stream, &o, &S);
+  if (rc) {
+    (void)hipFree(bx);
+    return rc;
+  }
+  // re-lay the workspace so every candidate's partial sums fit
+  (void)hipFree(S->ws);
+  S->L = make_layout(A, B, method, mmax, maxit, pmax);
+  if (hipMalloc(&S->ws, S->L.total) != hipSuccess) {
+    S->ws = nullptr;
+    pfk_session_destroy(S);
+    (void)hipFree(bx);
+    return fail(PFK_ERR_OOM, "autotune workspace");
+  }
+  S->st = (SolveState*)(S->ws + S->L.state);
+  S->hist = (double*)(S->ws + S->L.hist);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  double best = 0.0, dflt = 0.0;
+  int count = 0;
+  auto cleanup = [&]() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    pfk_session_destroy(S);
+    (void)hipFree(bx);
+  };
+  // mean time of `reps` iterations with the session's current geometry
+  // (restarted from x if the solve stopped, e.g. at a GMRES cycle end)
+  auto time_iters = [&](double* ms) -> int {
+    int r = read_state(S);
+    if (r) return r;
+    if (gm || S->host_state->status != kRunning || S->host_state->it + reps + 2 >= maxit) {
+      r = pfk_session_start(S);
+      if (r) return r;
+      for (int i = 0; i < warm; ++i) enqueue_iteration(S);
+    }
+    HIPCHK(hipEventRecord(e0, S->s1));
+    for (int i = 0; i < reps; ++i) enqueue_iteration(S);
+    HIPCHK(hipEventRecord(e1, S->s1));
+    HIPCHK(hipEventSynchronize(e1));
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, e0, e1));
+    *ms = (double)t / reps;
+    ++count;
+    return PFK_OK;
+  };
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    return fail(PFK_ERR_HIP, "autotune events");
+  }
+  rc = pfk_session_start(S);
+  if (!rc) {
+    for (int i = 0; i < warm; ++i) enqueue_iteration(S);
+    rc = time_iters(&dflt);   // the geometry the operator had
+  }
+  StencilGeom best_sg = sg0;
+  int best_pv = pv0;
+  best = dflt;
+  for (size_t c = 0; !rc && c < geoms.size(); ++c) {
+    S->sg = geoms[c];
+    double t = 0.0;
+    rc = time_iters(&t);
+    if (!rc && t < best) { best = t; best_sg = geoms[c]; }
+  }
+  S->sg = best_sg;
+  for (size_t c = 0; !rc && c < pvs.size(); ++c) {
+    S->pv = pvs[c];
+    double t = 0.0;
+    rc = time_iters(&t);
+    if (!rc && t < best) { best = t; best_pv = pvs[c]; }
+  }
+  if (!rc) HIPCHK(hipStreamSynchronize(S->s1));
+  cleanup();
+  if (rc) return rc;
+  A->sg = best_sg;
+  A->pv_blocks = best_pv;
+  if (out) {
+    out->tile_x = best_sg.tx;
+    out->stencil_blocks = best_sg.blocks();
+    out->vector_blocks = best_pv;
+    out->ms_per_iteration = best;
+    out->ms_default = dflt;
+    out->candidates = count;
+  }
+  return PFK_OK;
 }

@@ -19,9 +19,6 @@ namespace pfk {
 
 constexpr int kBlock = 256;        // threads per workgroup: four 64-wide waves
 constexpr int kWaves = kBlock / 64;
-constexpr int kTileX = 64;         // stencil tile: 64 x-nodes (one wave per row) ...
-constexpr int kTileY = 8;          // ... by 8 y-rows, two rows per thread
-constexpr int kHalo = 2 * kTileX + 2 * kTileY;   // in-plane halo nodes of a tile
 constexpr int kNuMax = 64;         // largest window / restart length supported
 
 // ---------------------------------------------------------------------------
@@ -107,77 +104,104 @@ __device__ __forceinline__ double stencil_at(const Grid& g, int i, int j, int k,
                              (d3 && k + 1 < g.nz) ? U(idx + nxy) : 0.0, (d3 && k > 0) ? U(idx - nxy) : 0.0);
 }
 
-// Stencil launch geometry: a workgroup owns a 64 x 8 tile of x-y nodes and
-// walks `zc` consecutive z-planes, so the number of workgroups (and of
-// reduction partials) is tiles_x * tiles_y * ceil(nz/zc).
+// Stencil launch geometry.  A workgroup owns a tile of x-y nodes, 64 x 8 or
+// 32 x 16 (two rows per thread either way), and walks `zc` consecutive
+// z-planes, so the number of workgroups (and of reduction partials) is
+// tiles_x * tiles_y * ceil(nz/zc).  The tile width is per operator: narrow
+// grids (n = 32, 96, ...) waste fewer lanes on 32-wide tiles.
 struct StencilGeom {
   int tiles_x, tiles_y, zc, zchunks;
+  int tx;                                   // tile width: 64 or 32
   __host__ __device__ int blocks() const { return tiles_x * tiles_y * zchunks; }
+};
+
+template <int TX>
+struct TileShape {
+  static constexpr int TY = 2 * kBlock / TX;       // tile rows: 8 or 16
+  static constexpr int RPW = 64 / TX;              // rows one wave covers in a pass
+  static constexpr int HALO = 2 * TX + 2 * TY;     // in-plane halo nodes
+  static_assert(HALO <= kBlock, "one halo node per thread at most");
 };
 
 // Workgroup ids are dealt round-robin to the 8 XCDs (each with its own L2).
 // Give each XCD a contiguous run of tiles (x fastest, then y, then z-chunk)
 // so the halo rows and planes that neighbouring tiles share stay in one L2.
-__device__ __forceinline__ int xcd_tile(int nblocks) {
-  const int b = blockIdx.x;
+// b is the workgroup's index within its launch (or within its system's range
+// of a batched launch, which starts at a multiple of 8).
+__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
   const int full = nblocks & ~7;
   if (b >= full) return b;
   return (b & 7) * (full >> 3) + (b >> 3);
 }
+__device__ __forceinline__ int xcd_tile(int nblocks) { return xcd_tile(blockIdx.x, nblocks); }
 
 // Iterate the nodes a workgroup owns in a stencil launch (one node at a time).
-template <class F>
-__device__ __forceinline__ void for_tile_nodes(const Grid& g, const StencilGeom& sg, F&& body) {
-  const int L = xcd_tile(sg.blocks());
+template <int TX, class G, class F>
+__device__ __forceinline__ void for_tile_nodes_t(const G& g, const StencilGeom& sg, int bid, F&& body) {
+  using S = TileShape<TX>;
+  const int L = xcd_tile(bid, sg.blocks());
   const int tx = L % sg.tiles_x;
   const int ty = (L / sg.tiles_x) % sg.tiles_y;
   const int tz = L / (sg.tiles_x * sg.tiles_y);
-  const int i = tx * kTileX + (threadIdx.x & 63);
+  const int lane = threadIdx.x & 63;
+  const int i = tx * TX + lane % TX;
+  const int r0 = (threadIdx.x >> 6) * S::RPW + lane / TX;
   const int k0 = tz * sg.zc;
   const int k1 = min(g.nz, k0 + sg.zc);
   for (int r = 0; r < 2; ++r) {
-    const int j = ty * kTileY + (threadIdx.x >> 6) + 4 * r;
+    const int j = ty * S::TY + r0 + r * (S::TY / 2);
     if (i >= g.nx || j >= g.ny) continue;
     for (int k = k0; k < k1; ++k) body(i, j, k, vec_index(g, i, j, k));
   }
+}
+template <class G, class F>
+__device__ __forceinline__ void for_tile_nodes(const G& g, const StencilGeom& sg, F&& body) {
+  if (sg.tx == 32) for_tile_nodes_t<32>(g, sg, blockIdx.x, body);
+  else for_tile_nodes_t<64>(g, sg, blockIdx.x, body);
 }
 
 // The hot stencil engine, in arithmetic type T.  A workgroup walks its tile
 // up the z-axis.  Each node's input value u = in(flat index) is formed once:
 // z-neighbours stay in registers (three planes), in-plane neighbours come from
 // an LDS copy of the current plane with a one-node halo (halo values are
-// formed by 144 of the 256 threads).  Values outside the domain are 0
+// formed by the first 2(TX+TY) threads).  Values outside the domain are 0
 // (Dirichlet).  For every interior node the engine calls
 // sink(flat index, u, (A u)).
-template <class T, class G, class In, class Sink>
-__device__ __forceinline__ void stencil_march(const G& g, const StencilGeom& sg, const In& in, Sink& sink) {
-  __shared__ T su[kTileY + 2][kTileX + 2];
-  const int L = xcd_tile(sg.blocks());
+template <int TX, class T, class G, class In, class Sink>
+__device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& sg, int bid, const In& in,
+                                                Sink& sink) {
+  using S = TileShape<TX>;
+  constexpr int TY = S::TY;
+  __shared__ T su[TY + 2][TX + 2];
+  const int L = xcd_tile(bid, sg.blocks());
   const int tx = L % sg.tiles_x;
   const int ty = (L / sg.tiles_x) % sg.tiles_y;
   const int tz = L / (sg.tiles_x * sg.tiles_y);
-  const int lane = threadIdx.x & 63, wrow = threadIdx.x >> 6;
-  const int i0 = tx * kTileX, j0 = ty * kTileY;
-  const int i = i0 + lane;
+  const int lane = threadIdx.x & 63;
+  const int xo = lane % TX;
+  const int r0 = (threadIdx.x >> 6) * S::RPW + lane / TX;
+  const int i0 = tx * TX, j0 = ty * TY;
+  const int i = i0 + xo;
   const int k0 = tz * sg.zc;
   const int k1 = min(g.nz, k0 + sg.zc);
   const bool d3 = g.dim == 3;
   const T zero = T(0);
-  int jr[2];
+  int jr[2], row[2];
   bool valid[2];
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
-    jr[r] = j0 + wrow + 4 * r;
+    row[r] = r0 + r * (TY / 2);
+    jr[r] = j0 + row[r];
     valid[r] = i < g.nx && jr[r] < g.ny;
   }
   // this thread's halo node (if any) and its LDS slot
   const int t = threadIdx.x;
   int hi = 0, hj = 0, hr = 0, hc = 0;
-  if (t < kTileX) { hi = i0 + t; hj = j0 - 1; hr = 0; hc = t + 1; }
-  else if (t < 2 * kTileX) { hi = i0 + t - kTileX; hj = j0 + kTileY; hr = kTileY + 1; hc = t - kTileX + 1; }
-  else if (t < 2 * kTileX + kTileY) { hi = i0 - 1; hj = j0 + t - 2 * kTileX; hr = hj - j0 + 1; hc = 0; }
-  else if (t < kHalo) { hi = i0 + kTileX; hj = j0 + t - 2 * kTileX - kTileY; hr = hj - j0 + 1; hc = kTileX + 1; }
-  const bool has_halo = t < kHalo;
+  if (t < TX) { hi = i0 + t; hj = j0 - 1; hr = 0; hc = t + 1; }
+  else if (t < 2 * TX) { hi = i0 + t - TX; hj = j0 + TY; hr = TY + 1; hc = t - TX + 1; }
+  else if (t < 2 * TX + TY) { hi = i0 - 1; hj = j0 + t - 2 * TX; hr = hj - j0 + 1; hc = 0; }
+  else if (t < S::HALO) { hi = i0 + TX; hj = j0 + t - 2 * TX - TY; hr = hj - j0 + 1; hc = TX + 1; }
+  const bool has_halo = t < S::HALO;
   const bool hvalid = has_halo && hi >= 0 && hi < g.nx && hj >= 0 && hj < g.ny;
 
   T um[2], uc[2], up[2], em[2], ec[2], ep[2];
@@ -197,18 +221,18 @@ __device__ __forceinline__ void stencil_march(const G& g, const StencilGeom& sg,
     const T hv = hvalid ? in(vec_index(g, hi, hj, k)) : zero;
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 2; ++r) su[wrow + 4 * r + 1][lane + 1] = uc[r];
+    for (int r = 0; r < 2; ++r) su[row[r] + 1][xo + 1] = uc[r];
     if (has_halo) su[hr][hc] = hv;
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
       if (valid[r]) {
-        const int row = wrow + 4 * r + 1;
+        const int rr = row[r] + 1;
         const long long pc = padded_index(g, i, jr[r], k);
         const T Au = apply_faces<T>(g, pc, uc[r], ec[r], T(to_real(g.eta[pc + 1])), T(to_real(g.eta[pc - 1])),
                                     T(to_real(g.eta[pc + g.sy])), T(to_real(g.eta[pc - g.sy])), ep[r], em[r],
-                                    su[row][lane + 2], su[row][lane], su[row + 1][lane + 1],
-                                    su[row - 1][lane + 1], up[r], um[r]);
+                                    su[rr][xo + 2], su[rr][xo], su[rr + 1][xo + 1], su[rr - 1][xo + 1], up[r],
+                                    um[r]);
         sink(vec_index(g, i, jr[r], k), uc[r], Au);
       }
       um[r] = uc[r];
@@ -217,6 +241,16 @@ __device__ __forceinline__ void stencil_march(const G& g, const StencilGeom& sg,
       ec[r] = ep[r];
     }
   }
+}
+
+template <class T, class G, class In, class Sink>
+__device__ __forceinline__ void stencil_march(const G& g, const StencilGeom& sg, int bid, const In& in, Sink& sink) {
+  if (sg.tx == 32) stencil_march_t<32, T>(g, sg, bid, in, sink);
+  else stencil_march_t<64, T>(g, sg, bid, in, sink);
+}
+template <class T, class G, class In, class Sink>
+__device__ __forceinline__ void stencil_march(const G& g, const StencilGeom& sg, const In& in, Sink& sink) {
+  stencil_march<T>(g, sg, (int)blockIdx.x, in, sink);
 }
 
 // ---------------------------------------------------------------------------

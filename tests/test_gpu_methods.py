@@ -156,3 +156,30 @@ def test_ragged_sizes_all_methods(pfk):
         prob = sym if method in ("fcg", "pipefcg") else conv
         ref, info, x, _ = _parity(pfk, method, prob, kind, 3, 30, 15)
         assert np.allclose(info.history, ref.history, rtol=1e-9), method
+
+
+@pytest.mark.parametrize("method", ["fcg", "gcr", "fgmres"])
+def test_host_sync_baseline_matches_device_form(pfk, method):
+    # the host-sync form runs the same kernels with the host waiting on every
+    # reduction: identical iterates, bit for bit
+    prob = _conv(16, seed=8) if method != "fcg" else gen.make_problem(3, 16, 4, 3.0, seed=8)
+    kind = "jacobi_gmres" if method != "fcg" else "jacobi_pcg"
+    _say("host sync", method)
+    Ag = pfk.Operator(prob.dim, prob.n, prob.eta, prob.vel)
+    Bg = pfk.Precond(Ag, kind, 3)
+    out = []
+    for hs in (0, 1):
+        x = _dev(np.zeros(Ag.N))
+        info = pfk.solve(Ag, Bg, method, _dev(prob.b), x, rtol=1e-8, maxit=400, mmax=30, host_sync=hs)
+        out.append((info, _host(x)))
+    (i0, x0), (i1, x1) = out
+    assert i0.converged and i1.converged and i0.iterations == i1.iterations
+    assert np.array_equal(i0.history, i1.history) and np.array_equal(x0, x1)
+
+
+def test_host_sync_rejected_for_pipelined(pfk):
+    prob = gen.make_problem(2, 16, 2, 2.0, seed=0)
+    Ag = pfk.Operator(2, 16, prob.eta)
+    Bg = pfk.Precond(Ag, "jacobi", 1)
+    with pytest.raises(RuntimeError):
+        pfk.solve(Ag, Bg, "pipefcg", _dev(prob.b), _dev(np.zeros(256)), host_sync=1)
