@@ -53,6 +53,8 @@ extern "C" {
 typedef struct pfk_operator_s* pfk_operator;
 typedef struct pfk_precond_s* pfk_precond;
 typedef struct pfk_session_s* pfk_session;
+typedef struct pfk_batch_s* pfk_batch;
+typedef struct pfk_server_s* pfk_server;
 
 typedef enum {
   PFK_FCG = 0,        /* Alg. 2: two blocking reductions per iteration        */
@@ -225,6 +227,94 @@ int pfk_estimate_sigma(pfk_operator A, pfk_precond B, int its, double* sigma, vo
 
 /* Message of the last error on this thread ("" if none). */
 const char* pfk_last_error(void);
+
+/* ---- batches --------------------------------------------------------------
+ * Many independent systems solved together (no paper counterpart: the
+ * experiments solve one system at a time).  Every phase of an outer iteration
+ * is one launch covering all running members: each member owns a range of the
+ * launch's workgroups sized by its own launch geometry (pfk_operator_set_tiling
+ * or pfk_operator_autotune), so systems of different sizes advance in the same
+ * launches; the PIPE methods' reduction finish runs on a second stream beside
+ * the preconditioner and operator launches, as in a single solve.  Each member
+ * computes exactly what a single pfk_solve with the same arguments computes.
+ *
+ * Methods: PIPEFCG, FCG, PIPEFGMRES (mmax = window or restart length).
+ * Preconditioners: NONE, JACOBI, BLOCK_JACOBI_PCG; all members of a batch share
+ * the dimension, the preconditioner kind and its precision.  opts as for
+ * pfk_solve except host_sync (rejected); graph_iters iterations are captured
+ * per graph (recaptured when the set of running members changes).
+ * Ownership: b, x and the workspace (or the library's allocation when NULL)
+ * must stay valid while the member is in the batch. */
+int pfk_batch_create(pfk_method method, int mmax, int capacity, void* stream, const pfk_solve_opts* opts,
+                     pfk_batch* out);
+void pfk_batch_destroy(pfk_batch T);
+/* Admit one system (set-up and start-up are enqueued at once); *slot receives
+ * its member index (0..capacity-1).  The workspace is sized by
+ * pfk_workspace_bytes(A, B, method, mmax, maxit).  Errors: PFK_ERR_ARG (full,
+ * unsupported preconditioner, a member of another kind), PFK_ERR_OOM. */
+int pfk_batch_add(pfk_batch T, pfk_operator A, pfk_precond B, const double* b, double* x, double rtol,
+                  int maxit, void* workspace, size_t ws_bytes, int* slot);
+/* Enqueue `iters` outer iterations of every running member (asynchronous). */
+int pfk_batch_step(pfk_batch T, int iters);
+/* Synchronise, then act on every running member's state as pfk_solve's loop
+ * does (true-residual check after a recurred convergence, restart at a GMRES
+ * cycle end, after a breakdown or a residual gap).  Members that ended are
+ * written to finished[0..cap) (*nfinished of them; their x is final once the
+ * stream reaches this point); *nrunning counts the others.  NULL outputs ok. */
+int pfk_batch_poll(pfk_batch T, int* finished, int cap, int* nfinished, int* nrunning);
+/* A member's pfk_solve_info (synchronising); returns its final pfk_status, or
+ * PFK_NOT_CONVERGED while it still runs. */
+int pfk_batch_info(pfk_batch T, int slot, pfk_solve_info* info);
+/* Release a member (its slot becomes free; its x keeps the last iterate). */
+int pfk_batch_remove(pfk_batch T, int slot);
+/* Workspace bytes of one member (the same as pfk_workspace_bytes). */
+size_t pfk_batch_workspace_bytes(pfk_operator A, pfk_precond B, pfk_method method, int mmax, int maxit);
+/* Solve `count` systems as one batch until every one has ended; infos[i] (may
+ * be NULL) receives each system's info.  Returns PFK_OK if all converged, else
+ * the first error or PFK_NOT_CONVERGED. */
+int pfk_solve_batched(int count, const pfk_operator* A, const pfk_precond* B, pfk_method method,
+                      const double* const* b, double* const* x, const double* rtol, int maxit, int mmax,
+                      void* stream, const pfk_solve_opts* opts, pfk_solve_info* infos);
+
+/* ---- serving -------------------------------------------------------------
+ * A request queue in front of continuously refilled batches (no paper
+ * counterpart).  Requests are admitted in arrival order while one fits a
+ * batch slot and the device-memory budget (each holds its workspace,
+ * pfk_workspace_bytes, from admission to retirement; workspaces come from a
+ * pool that keeps freed blocks).  Requests of one method, preconditioner kind,
+ * precision and dimension share a batch; batches run on their own streams, so
+ * a PIPEFCG batch and a PIPEFGMRES batch overlap on the device.  A request's
+ * result is bit-identical to a single pfk_solve of it, whatever else is being
+ * served. */
+typedef struct {
+  size_t hbm_budget;   /* bytes of workspace the admitted requests may hold       */
+  int max_active;      /* members per batch (1..4096)                             */
+  int step_iters;      /* outer iterations per scheduling round (graph length)    */
+  int mmax;            /* window / restart length of every request                */
+} pfk_server_config;
+
+typedef struct {
+  long long queued, active, completed;
+  size_t bytes_in_use;  /* workspaces of admitted requests                         */
+  size_t bytes_held;    /* device memory the pool holds (in use or cached)         */
+} pfk_server_status;
+
+int pfk_server_create(const pfk_server_config* cfg, void* stream, pfk_server* out);
+/* Destroys the batches and releases the pool (requests still running stop). */
+void pfk_server_destroy(pfk_server S);
+/* Queue a request; *id identifies it.  A, B, b and x stay owned by the caller
+ * and must stay valid until the request has completed.  Errors: PFK_ERR_ARG
+ * (method or preconditioner not batched, a request larger than the budget). */
+int pfk_server_submit(pfk_server S, pfk_operator A, pfk_precond B, pfk_method method, const double* b,
+                      double* x, double rtol, int maxit, long long* id);
+/* One scheduling round (admit, advance every batch by step_iters iterations,
+ * poll, retire); the ids that completed in this round go to
+ * completed[0..cap) (*ncompleted of them).  Synchronises the batch streams. */
+int pfk_server_progress(pfk_server S, long long* completed, int cap, int* ncompleted);
+/* Info of a completed request (history copied into info->history up to
+ * info->history_cap); returns its final pfk_status. */
+int pfk_server_result(pfk_server S, long long id, pfk_solve_info* info);
+int pfk_server_stats(pfk_server S, pfk_server_status* stats);
 
 #ifdef __cplusplus
 }

@@ -10,6 +10,6 @@ from .binding import (  # noqa: F401
     FCG, PIPEFCG, GCR, PIPEGCR, FGMRES, PIPEFGMRES, METHODS,
     PC_NONE, PC_JACOBI, PC_JACOBI_PCG, PC_JACOBI_GMRES, PC_BLOCK_JACOBI_PCG, PC_KINDS,
     FP64, FP32_BF16COEF,
-    PfkError, Operator, Precond, Session, SolveInfo, SolveOpts,
-    solve, workspace_bytes, estimate_sigma, lib, lib_path, EXPORTED,
+    PfkError, Operator, Precond, Session, SolveInfo, SolveOpts, Batch, Tuning, Server,
+    solve, solve_batched, workspace_bytes, estimate_sigma, lib, lib_path, EXPORTED,
 )

@@ -35,6 +35,10 @@ EXPORTED = [
     "pfk_session_start", "pfk_session_iterate", "pfk_session_sync", "pfk_session_destroy",
     "pfk_session_profile", "pfk_estimate_sigma", "pfk_last_error",
     "pfk_operator_set_tiling", "pfk_operator_get_tiling", "pfk_operator_autotune",
+    "pfk_batch_create", "pfk_batch_destroy", "pfk_batch_add", "pfk_batch_step", "pfk_batch_poll",
+    "pfk_batch_info", "pfk_batch_remove", "pfk_batch_workspace_bytes", "pfk_solve_batched",
+    "pfk_server_create", "pfk_server_destroy", "pfk_server_submit", "pfk_server_progress",
+    "pfk_server_result", "pfk_server_stats",
 ]
 
 
@@ -44,6 +48,15 @@ class Tuning(C.Structure):
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("hbm_budget", C.c_size_t), ("max_active", C.c_int), ("step_iters", C.c_int), ("mmax", C.c_int)]
+
+
+class ServerStatus(C.Structure):
+    _fields_ = [("queued", C.c_longlong), ("active", C.c_longlong), ("completed", C.c_longlong),
+                ("bytes_in_use", C.c_size_t), ("bytes_held", C.c_size_t)]
 
 
 class PfkError(RuntimeError):
@@ -120,6 +133,25 @@ def lib():
         "pfk_operator_set_tiling": (C.c_int, [vp, C.c_int, C.c_int, C.c_int]),
         "pfk_operator_get_tiling": (C.c_int, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
         "pfk_operator_autotune": (C.c_int, [vp, vp, C.c_int, C.c_int, C.c_int, vp, C.POINTER(Tuning)]),
+        "pfk_batch_create": (C.c_int, [C.c_int, C.c_int, C.c_int, vp, C.POINTER(SolveOpts), C.POINTER(vp)]),
+        "pfk_batch_destroy": (None, [vp]),
+        "pfk_batch_add": (C.c_int, [vp, vp, vp, vp, vp, C.c_double, C.c_int, vp, C.c_size_t,
+                                    C.POINTER(C.c_int)]),
+        "pfk_batch_step": (C.c_int, [vp, C.c_int]),
+        "pfk_batch_poll": (C.c_int, [vp, C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+        "pfk_batch_info": (C.c_int, [vp, C.c_int, C.POINTER(_Info)]),
+        "pfk_batch_remove": (C.c_int, [vp, C.c_int]),
+        "pfk_batch_workspace_bytes": (C.c_size_t, [vp, vp, C.c_int, C.c_int, C.c_int]),
+        "pfk_server_create": (C.c_int, [C.POINTER(ServerConfig), vp, C.POINTER(vp)]),
+        "pfk_server_destroy": (None, [vp]),
+        "pfk_server_submit": (C.c_int, [vp, vp, vp, C.c_int, vp, vp, C.c_double, C.c_int,
+                                        C.POINTER(C.c_longlong)]),
+        "pfk_server_progress": (C.c_int, [vp, C.POINTER(C.c_longlong), C.c_int, C.POINTER(C.c_int)]),
+        "pfk_server_result": (C.c_int, [vp, C.c_longlong, C.POINTER(_Info)]),
+        "pfk_server_stats": (C.c_int, [vp, C.POINTER(ServerStatus)]),
+        "pfk_solve_batched": (C.c_int, [C.c_int, C.POINTER(vp), C.POINTER(vp), C.c_int, C.POINTER(vp),
+                                        C.POINTER(vp), C.POINTER(C.c_double), C.c_int, C.c_int, vp,
+                                        C.POINTER(SolveOpts), C.POINTER(_Info)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -337,6 +369,143 @@ class Session:
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().pfk_session_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many systems advanced by shared launches: add(), step(k), poll(), info()."""
+
+    def __init__(self, method: str, mmax: int = 30, capacity: int = 64, stream=None, **opts):
+        o = default_opts(**opts)
+        h = C.c_void_p()
+        _check(lib().pfk_batch_create(METHODS[method], int(mmax), int(capacity), _stream_ptr(stream), C.byref(o),
+                                      C.byref(h)))
+        self._h = h
+        self.method, self.mmax, self.capacity = method, mmax, capacity
+        self._keep = {}            # slot -> objects that must outlive the member
+        self._maxit = {}
+
+    def add(self, A: Operator, B: Precond, b, x, rtol: float = 1e-8, maxit: int = 500, workspace=None) -> int:
+        wsp, wsb = (None, 0)
+        if workspace is not None:
+            wsp, wsb = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+        slot = C.c_int(-1)
+        _check(lib().pfk_batch_add(self._h, A.handle, B.handle, _dev_ptr(b, A.N, "b"), _dev_ptr(x, A.N, "x"),
+                                   float(rtol), int(maxit), wsp, wsb, C.byref(slot)))
+        self._keep[slot.value] = (A, B, b, x, workspace)
+        self._maxit[slot.value] = maxit
+        return slot.value
+
+    def step(self, iters: int):
+        _check(lib().pfk_batch_step(self._h, int(iters)))
+
+    def poll(self):
+        """Returns (finished slots, number still running)."""
+        cap = self.capacity
+        fin = (C.c_int * cap)()
+        nf, nr = C.c_int(0), C.c_int(0)
+        _check(lib().pfk_batch_poll(self._h, fin, cap, C.byref(nf), C.byref(nr)))
+        return [fin[i] for i in range(nf.value)], nr.value
+
+    def info(self, slot: int) -> SolveInfo:
+        info, hist = _info_struct(self._maxit[slot] + 1)
+        code = lib().pfk_batch_info(self._h, int(slot), C.byref(info))
+        _check(code, allow_positive=True)
+        return _to_info(code, info, hist)
+
+    def remove(self, slot: int):
+        _check(lib().pfk_batch_remove(self._h, int(slot)))
+        self._keep.pop(slot, None)
+        self._maxit.pop(slot, None)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().pfk_batch_destroy(self._h)
+            self._h = None
+        self._keep = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_batched(As, Bs, method: str, bs, xs, rtol=1e-8, maxit: int = 500, mmax: int = 30, stream=None,
+                  **opts):
+    """Solve every system (lists of operators, preconditioners, b and x tensors)
+    in one batch.  Returns (status code, [SolveInfo])."""
+    n = len(As)
+    o = default_opts(**opts)
+    rt = [float(rtol)] * n if np.isscalar(rtol) else [float(v) for v in rtol]
+    arrA = (C.c_void_p * n)(*[a.handle.value for a in As])
+    arrB = (C.c_void_p * n)(*[b.handle.value for b in Bs])
+    arrb = (C.c_void_p * n)(*[_dev_ptr(v, a.N, "b") for v, a in zip(bs, As)])
+    arrx = (C.c_void_p * n)(*[_dev_ptr(v, a.N, "x") for v, a in zip(xs, As)])
+    arrr = (C.c_double * n)(*rt)
+    infos = (_Info * n)()
+    hists = []
+    for i in range(n):
+        hist = np.zeros(maxit + 1, dtype=np.float64)
+        infos[i].history = hist.ctypes.data_as(C.POINTER(C.c_double))
+        infos[i].history_cap = maxit + 1
+        hists.append(hist)
+    code = lib().pfk_solve_batched(n, arrA, arrB, METHODS[method], arrb, arrx, arrr, int(maxit), int(mmax),
+                                   _stream_ptr(stream), C.byref(o), infos)
+    _check(code, allow_positive=True)
+    return code, [_to_info(infos[i].status, infos[i], hists[i]) for i in range(n)]
+
+
+class Server:
+    """Request queue in front of continuously refilled batches:
+    submit(), progress() -> completed ids, result(id), stats()."""
+
+    def __init__(self, hbm_budget: int, max_active: int = 64, step_iters: int = 10, mmax: int = 30, stream=None):
+        cfg = ServerConfig(int(hbm_budget), int(max_active), int(step_iters), int(mmax))
+        h = C.c_void_p()
+        _check(lib().pfk_server_create(C.byref(cfg), _stream_ptr(stream), C.byref(h)))
+        self._h = h
+        self.max_active = max_active
+        self._keep = {}
+        self._maxit = {}
+
+    def submit(self, A: Operator, B: Precond, method: str, b, x, rtol: float = 1e-8, maxit: int = 500) -> int:
+        rid = C.c_longlong(-1)
+        _check(lib().pfk_server_submit(self._h, A.handle, B.handle, METHODS[method], _dev_ptr(b, A.N, "b"),
+                                       _dev_ptr(x, A.N, "x"), float(rtol), int(maxit), C.byref(rid)))
+        self._keep[rid.value] = (A, B, b, x)
+        self._maxit[rid.value] = maxit
+        return rid.value
+
+    def progress(self) -> list:
+        cap = 4 * self.max_active + 16
+        done = (C.c_longlong * cap)()
+        n = C.c_int(0)
+        _check(lib().pfk_server_progress(self._h, done, cap, C.byref(n)))
+        return [done[i] for i in range(n.value)]
+
+    def result(self, rid: int) -> SolveInfo:
+        info, hist = _info_struct(self._maxit[rid] + 1)
+        code = lib().pfk_server_result(self._h, int(rid), C.byref(info))
+        _check(code, allow_positive=True)
+        self._keep.pop(rid, None)
+        return _to_info(code, info, hist)
+
+    def stats(self) -> dict:
+        st = ServerStatus()
+        _check(lib().pfk_server_stats(self._h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in st._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().pfk_server_destroy(self._h)
+            self._h = None
+        self._keep = {}
 
     def __del__(self):
         try:

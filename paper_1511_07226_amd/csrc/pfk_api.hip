@@ -24,7 +24,7 @@
 #include <vector>
 
 #include "../../include/pfk.h"
-#include "pfk_gmres.hpp"
+#include "pfk_batch.hpp"
 
 using namespace pfk;
 
@@ -472,6 +472,7 @@ struct pfk_session_s {
   double* hist = nullptr;
   SolveState* host_state = nullptr;   // pinned
   int restarts = 0;
+  bool owns_streams = true;           // false for members of a batch (the batch's streams)
 
   double* vec(int v) const { return (double*)(ws + L.vec[v]); }
   Window win(int w) const { return Window{(double*)(ws + L.win[w]), L.ld}; }
@@ -899,9 +900,22 @@ int read_state(pfk_session_s* S) {
 
 }  // namespace
 
+// Session set-up.  With borrowed streams (bs1 != NULL) the session uses the
+// caller's two streams and creates no streams or events of its own.
+static int session_make(pfk_operator A, pfk_precond B, pfk_method method, const double* b, double* x,
+                        double rtol, int maxit, int mmax, void* workspace, size_t ws_bytes, void* stream,
+                        const pfk_solve_opts* opts, hipStream_t bs1, hipStream_t bs2, pfk_session* out);
+
 extern "C" int pfk_session_create(pfk_operator A, pfk_precond B, pfk_method method, const double* b, double* x,
                                   double rtol, int maxit, int mmax, void* workspace, size_t ws_bytes,
                                   void* stream, const pfk_solve_opts* opts, pfk_session* out) {
+  return session_make(A, B, method, b, x, rtol, maxit, mmax, workspace, ws_bytes, stream, opts, nullptr, nullptr,
+                      out);
+}
+
+static int session_make(pfk_operator A, pfk_precond B, pfk_method method, const double* b, double* x,
+                        double rtol, int maxit, int mmax, void* workspace, size_t ws_bytes, void* stream,
+                        const pfk_solve_opts* opts, hipStream_t bs1, hipStream_t bs2, pfk_session* out) {
   if (!out) return fail(PFK_ERR_ARG, "out is NULL");
   *out = nullptr;
   if (!A || !B || !b || !x) return fail(PFK_ERR_ARG, "null argument");
@@ -948,6 +962,17 @@ extern "C" int pfk_session_create(pfk_operator A, pfk_precond B, pfk_method meth
   S->st = (SolveState*)(S->ws + S->L.state);
   S->hist = (double*)(S->ws + S->L.hist);
   S->user = (hipStream_t)stream;
+  if (bs1) {
+    S->owns_streams = false;
+    S->s1 = bs1;
+    S->s2 = bs2;
+    if (hipHostMalloc(&S->host_state, sizeof(SolveState), hipHostMallocDefault) != hipSuccess) {
+      pfk_session_destroy(S);
+      return fail(PFK_ERR_HIP, "pinned state");
+    }
+    *out = S;
+    return PFK_OK;
+  }
   if (hipStreamCreateWithFlags(&S->s1, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&S->s2, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming) != hipSuccess ||
@@ -972,18 +997,16 @@ extern "C" void pfk_session_destroy(pfk_session S) {
   if (S->ev_join) (void)hipEventDestroy(S->ev_join);
   if (S->ev_user) (void)hipEventDestroy(S->ev_user);
   if (S->ev_done) (void)hipEventDestroy(S->ev_done);
-  if (S->s1) (void)hipStreamDestroy(S->s1);
-  if (S->s2) (void)hipStreamDestroy(S->s2);
+  if (S->owns_streams && S->s1) (void)hipStreamDestroy(S->s1);
+  if (S->owns_streams && S->s2) (void)hipStreamDestroy(S->s2);
   if (S->host_state) (void)hipHostFree(S->host_state);
   if (S->ws_owned && S->ws) (void)hipFree(S->ws);
   delete S;
 }
 
-extern "C" int pfk_session_start(pfk_session S) {
-  if (!S) return fail(PFK_ERR_ARG, "null session");
-  // order after the caller's queued work
-  HIPCHK(hipEventRecord(S->ev_user, S->user));
-  HIPCHK(hipStreamWaitEvent(S->s1, S->ev_user, 0));
+// The shift estimate (PIPEFGMRES, when not given) and the solve's set-up
+// kernels (tolerance from ||b||, x = 0 when b = 0), on S->s1.
+static int session_setup(pfk_session_s* S) {
   if (S->method == PFK_PIPEFGMRES && std::isnan(S->opts.shift_sigma)) {
     // sigma estimated once per session, before the set-up
     enqueue_sigma_estimate(S, S->s1, 10);
@@ -1000,7 +1023,18 @@ extern "C" int pfk_session_start(pfk_session S) {
   LAUNCH(k_setup_tol, 1, S->s1, S->part(PT_A), S->Pv(), S->rtol, S->st, S->hist);
   LAUNCH(k_zero_if_done, S->Pv(), S->s1, S->A->N, S->x, S->st);
   S->restarts = 0;
-  int rc = launch_start(S);
+  HIPCHK(hipGetLastError());
+  return PFK_OK;
+}
+
+extern "C" int pfk_session_start(pfk_session S) {
+  if (!S) return fail(PFK_ERR_ARG, "null session");
+  // order after the caller's queued work
+  HIPCHK(hipEventRecord(S->ev_user, S->user));
+  HIPCHK(hipStreamWaitEvent(S->s1, S->ev_user, 0));
+  int rc = session_setup(S);
+  if (rc) return rc;
+  rc = launch_start(S);
   if (rc) return rc;
   HIPCHK(hipEventRecord(S->ev_done, S->s1));
   HIPCHK(hipStreamWaitEvent(S->user, S->ev_done, 0));
@@ -1371,5 +1405,659 @@ extern "C" int pfk_operator_autotune(pfk_operator A, pfk_precond B, pfk_method m
     out->ms_default = dflt;
     out->candidates = count;
   }
+  return PFK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches: many independent systems advanced by shared launches
+// ---------------------------------------------------------------------------
+struct pfk_batch_s {
+  int method = 0, mmax = 0;
+  pfk_solve_opts opts{};
+  hipStream_t user = nullptr, s1 = nullptr, s2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_user = nullptr, ev_done = nullptr;
+  int dim = 0, fp32 = -1, pc_kind = -1;   // shared by every member (fixed by the first one added)
+  struct Member {
+    pfk_session S = nullptr;
+    int state = 0;     // 0 free, 1 running, 2 finished
+    int code = 0;      // pfk_status once finished
+  };
+  std::vector<Member> mem;
+  // device tables of the running members (rebuilt when the running set changes)
+  std::vector<int> rows;                  // member index of each table row
+  BSys* d_sys = nullptr;
+  int* d_off = nullptr;                   // kBpCount arrays of (rows + 1) range starts
+  int* d_stat = nullptr;                  // 2 ints per row: status, iteration
+  int* h_stat = nullptr;                  // pinned copy
+  int cap_rows = 0;
+  int tot[kBpCount] = {};
+  bool dirty = true;
+  hipGraphExec_t graph = nullptr;
+};
+
+namespace {
+
+bool batch_method_ok(int m) { return m == PFK_PIPEFCG || m == PFK_FCG || m == PFK_PIPEFGMRES; }
+
+// The table record of one member (its session's buffers and geometry).
+BSys make_bsys(const pfk_session_s* S) {
+  const pfk_operator_s* A = S->A;
+  BSys d{};
+  d.N = A->N;
+  d.g = A->grid();
+  if (A->eta_bf16) d.gm = A->grid_mixed();
+  d.sg = S->sg;
+  d.Pv = S->Pv();
+  d.Ps = S->Ps();
+  d.bj_wy = (int)((A->n[1] + kBjEdge - 1) / kBjEdge);
+  if (A->dim == 3) {
+    d.bj_wx = (int)((A->n[0] + 2 * kBjEdge - 1) / (2 * kBjEdge));
+    d.bj_n = d.bj_wx * d.bj_wy * (int)((A->n[2] + kBjEdge - 1) / kBjEdge);
+  } else {
+    d.bj_wx = (int)((A->n[0] + 4 * kBjEdge - 1) / (4 * kBjEdge));
+    d.bj_n = d.bj_wx * d.bj_wy;
+  }
+  d.pc_k = S->B->k;
+  switch (S->method) {
+    case PFK_PIPEFCG: d.pd = pc_out_desc(S, S->vec(V_W), 1.0, S->vec(V_R), -1.0); break;
+    case PFK_FCG: d.pd = pc_out_desc(S, S->vec(V_R), 1.0, nullptr, 0.0); break;
+    default: d.pd = pc_out_desc(S, S->vec(V_M), 1.0, nullptr, 0.0); break;   // PIPEFGMRES: B(zbar)
+  }
+  d.P = S->win(W_P);
+  d.S = S->win(W_S);
+  d.Q = S->win(W_Q);
+  d.Z = S->win(W_Z);
+  d.x = S->x;
+  d.r = S->vec(V_R);
+  d.u = S->vec(V_U);
+  d.w = S->vec(V_W);
+  d.m = S->vec(V_M);
+  d.n = S->vec(V_N);
+  d.z = S->vec(V_Z);
+  d.x0 = S->vec(V_X0);
+  d.part_main = S->part(PT_MAIN);
+  d.part_a = S->part(PT_A);
+  d.part_b = S->part(PT_B);
+  d.st = S->st;
+  d.hist = S->hist;
+  return d;
+}
+
+int batch_rebuild(pfk_batch_s* T) {
+  HIPCHK(hipStreamSynchronize(T->s1));   // in-flight launches read the old tables
+  if (T->graph) {
+    (void)hipGraphExecDestroy(T->graph);
+    T->graph = nullptr;
+  }
+  T->rows.clear();
+  for (int i = 0; i < (int)T->mem.size(); ++i)
+    if (T->mem[i].state == 1) T->rows.push_back(i);
+  const int n = (int)T->rows.size();
+  if (n > T->cap_rows) {
+    if (T->d_sys) (void)hipFree(T->d_sys);
+    if (T->d_off) (void)hipFree(T->d_off);
+    if (T->d_stat) (void)hipFree(T->d_stat);
+    if (T->h_stat) (void)hipHostFree(T->h_stat);
+    T->d_sys = nullptr; T->d_off = nullptr; T->d_stat = nullptr; T->h_stat = nullptr;
+    T->cap_rows = 0;
+    if (hipMalloc(&T->d_sys, sizeof(BSys) * n) != hipSuccess ||
+        hipMalloc(&T->d_off, sizeof(int) * kBpCount * (n + 1)) != hipSuccess ||
+        hipMalloc(&T->d_stat, sizeof(int) * 2 * n) != hipSuccess ||
+        hipHostMalloc(&T->h_stat, sizeof(int) * 2 * n, hipHostMallocDefault) != hipSuccess)
+      return fail(PFK_ERR_OOM, "batch tables");
+    T->cap_rows = n;
+  }
+  std::vector<BSys> sys(n);
+  std::vector<int> off((size_t)kBpCount * (n + 1), 0);
+  for (int p = 0; p < kBpCount; ++p) T->tot[p] = 0;
+  for (int r = 0; r < n; ++r) {
+    sys[r] = make_bsys(T->mem[T->rows[r]].S);
+    const int cnt[kBpCount] = {sys[r].Pv, sys[r].Ps, sys[r].bj_n, 1};
+    for (int p = 0; p < kBpCount; ++p) {
+      off[(size_t)p * (n + 1) + r] = T->tot[p];
+      T->tot[p] += p == kBpOne ? 1 : (cnt[p] + 7) / 8 * 8;   // ranges start at multiples of 8
+    }
+  }
+  for (int p = 0; p < kBpCount; ++p) off[(size_t)p * (n + 1) + n] = T->tot[p];
+  if (n > 0) {
+    HIPCHK(hipMemcpy(T->d_sys, sys.data(), sizeof(BSys) * n, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(T->d_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice));
+  }
+  T->dirty = false;
+  return PFK_OK;
+}
+
+template <class T>
+void batch_block_pc(pfk_batch_s* Tb, const int* off, int n) {
+  hipStream_t s1 = Tb->s1;
+  if (Tb->dim == 3) LAUNCH((kb_block_pcg<T, 1>), Tb->tot[kBpBlk], s1, Tb->d_sys, off, n);
+  else LAUNCH((kb_block_pcg<T, 0>), Tb->tot[kBpBlk], s1, Tb->d_sys, off, n);
+}
+
+// One outer iteration of every running member.
+void enqueue_batch_iteration(pfk_batch_s* T) {
+  const int n = (int)T->rows.size();
+  const int* ov = T->d_off + kBpVec * (n + 1);
+  const int* os = T->d_off + kBpSten * (n + 1);
+  const int* ob = T->d_off + kBpBlk * (n + 1);
+  hipStream_t s1 = T->s1, s2 = T->s2;
+  const bool blockpc = T->pc_kind == kPcBlockPcg;
+  auto pc = [&]() {
+    if (!blockpc) return;
+    if (T->fp32) batch_block_pc<float>(T, ob, n);
+    else batch_block_pc<double>(T, ob, n);
+  };
+  switch (T->method) {
+    case PFK_PIPEFCG:
+      LAUNCH(kb_pipefcg_update, T->tot[kBpVec], s1, T->d_sys, ov, n);
+      (void)hipEventRecord(T->ev_fork, s1);
+      (void)hipStreamWaitEvent(s2, T->ev_fork, 0);
+      LAUNCH(kb_pipefcg_scalars, n, s2, T->d_sys);
+      (void)hipEventRecord(T->ev_join, s2);
+      pc();
+      LAUNCH(kb_apply_pc_out, T->tot[kBpSten], s1, T->d_sys, os, n, 1);
+      (void)hipStreamWaitEvent(s1, T->ev_join, 0);
+      break;
+    case PFK_FCG:
+      LAUNCH(kb_fcg_xr, T->tot[kBpVec], s1, T->d_sys, ov, n);
+      pc();
+      LAUNCH(kb_fcg_multidot, T->tot[kBpVec], s1, T->d_sys, ov, n);
+      LAUNCH(kb_cg_scalars1, n, s1, T->d_sys);
+      LAUNCH(kb_fcg_maxpy, T->tot[kBpVec], s1, T->d_sys, ov, n);
+      LAUNCH(kb_fcg_apply, T->tot[kBpSten], s1, T->d_sys, os, n);
+      LAUNCH(kb_cg_scalars2, n, s1, T->d_sys);
+      break;
+    default:   // PIPEFGMRES
+      LAUNCH(kb_pgm_update, T->tot[kBpVec], s1, T->d_sys, ov, n);
+      (void)hipEventRecord(T->ev_fork, s1);
+      (void)hipStreamWaitEvent(s2, T->ev_fork, 0);
+      LAUNCH(kb_pgm_scalars, n, s2, T->d_sys);
+      (void)hipEventRecord(T->ev_join, s2);
+      pc();
+      LAUNCH(kb_apply_pc_out, T->tot[kBpSten], s1, T->d_sys, os, n, 0);
+      (void)hipStreamWaitEvent(s1, T->ev_join, 0);
+      LAUNCH(kb_gm_update_x, T->tot[kBpVec], s1, T->d_sys, ov, n);
+      break;
+  }
+}
+
+}  // namespace
+
+extern "C" void pfk_batch_destroy(pfk_batch T) {
+  if (!T) return;
+  if (T->s1) (void)hipStreamSynchronize(T->s1);
+  for (auto& m : T->mem)
+    if (m.S) pfk_session_destroy(m.S);
+  if (T->graph) (void)hipGraphExecDestroy(T->graph);
+  if (T->d_sys) (void)hipFree(T->d_sys);
+  if (T->d_off) (void)hipFree(T->d_off);
+  if (T->d_stat) (void)hipFree(T->d_stat);
+  if (T->h_stat) (void)hipHostFree(T->h_stat);
+  for (hipEvent_t e : {T->ev_fork, T->ev_join, T->ev_user, T->ev_done})
+    if (e) (void)hipEventDestroy(e);
+  if (T->s1) (void)hipStreamDestroy(T->s1);
+  if (T->s2) (void)hipStreamDestroy(T->s2);
+  delete T;
+}
+
+extern "C" int pfk_batch_create(pfk_method method, int mmax, int capacity, void* stream,
+                                const pfk_solve_opts* opts, pfk_batch* out) {
+  if (!out) return fail(PFK_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!batch_method_ok(method)) return fail(PFK_ERR_ARG, "batches run PIPEFCG, FCG or PIPEFGMRES");
+  if (mmax < 1 || mmax > kNuMax) return fail(PFK_ERR_ARG, "mmax must be 1..64");
+  if (capacity < 1 || capacity > 4096) return fail(PFK_ERR_ARG, "capacity must be 1..4096");
+  auto* T = new (std::nothrow) pfk_batch_s();
+  if (!T) return fail(PFK_ERR_OOM, "host allocation");
+  T->method = method;
+  T->mmax = mmax;
+  pfk_default_opts(&T->opts);
+  if (opts) T->opts = *opts;
+  if (T->opts.graph_iters < 1) T->opts.graph_iters = 1;
+  if (T->opts.host_sync) {
+    delete T;
+    return fail(PFK_ERR_ARG, "host_sync does not apply to batches");
+  }
+  T->user = (hipStream_t)stream;
+  T->mem.resize(capacity);
+  if (hipStreamCreateWithFlags(&T->s1, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&T->s2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&T->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&T->ev_join, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&T->ev_user, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&T->ev_done, hipEventDisableTiming) != hipSuccess) {
+    pfk_batch_destroy(T);
+    return fail(PFK_ERR_HIP, "creating streams/events");
+  }
+  *out = T;
+  return PFK_OK;
+}
+
+extern "C" int pfk_batch_add(pfk_batch T, pfk_operator A, pfk_precond B, const double* b, double* x, double rtol,
+                             int maxit, void* workspace, size_t ws_bytes, int* slot) {
+  if (!T || !A || !B || !slot) return fail(PFK_ERR_ARG, "null argument");
+  *slot = -1;
+  const int kind = B->kind;
+  if (kind != kPcNone && kind != kPcJacobi && kind != kPcBlockPcg)
+    return fail(PFK_ERR_ARG, "batches take the NONE, JACOBI or BLOCK_JACOBI_PCG preconditioner");
+  const int fp32 = kind == kPcBlockPcg && B->prec == PFK_FP32_BF16COEF;
+  if (T->pc_kind >= 0 && (T->pc_kind != kind || T->fp32 != fp32 || T->dim != A->dim))
+    return fail(PFK_ERR_ARG, "every member of a batch has the same dimension, preconditioner kind and precision");
+  int s = -1;
+  for (int i = 0; i < (int)T->mem.size() && s < 0; ++i)
+    if (T->mem[i].state == 0) s = i;
+  if (s < 0) return fail(PFK_ERR_ARG, "batch is full");
+  pfk_session S = nullptr;
+  int rc = session_make(A, B, (pfk_method)T->method, b, x, rtol, maxit, T->mmax, workspace, ws_bytes, T->user,
+                        &T->opts, T->s1, T->s2, &S);
+  if (rc) return rc;
+  // order after the caller's queued work, then the set-up and the start-up
+  HIPCHK(hipEventRecord(T->ev_user, T->user));
+  HIPCHK(hipStreamWaitEvent(T->s1, T->ev_user, 0));
+  rc = session_setup(S);
+  if (rc) {
+    pfk_session_destroy(S);
+    return rc;
+  }
+  enqueue_start(S, T->s1);
+  HIPCHK(hipGetLastError());
+  T->pc_kind = kind;
+  T->fp32 = fp32;
+  T->dim = A->dim;
+  T->mem[s].S = S;
+  T->mem[s].state = 1;
+  T->mem[s].code = PFK_NOT_CONVERGED;
+  T->dirty = true;
+  *slot = s;
+  return PFK_OK;
+}
+
+extern "C" int pfk_batch_step(pfk_batch T, int iters) {
+  if (!T) return fail(PFK_ERR_ARG, "null batch");
+  if (iters <= 0) return PFK_OK;
+  if (T->dirty) {
+    int rc = batch_rebuild(T);
+    if (rc) return rc;
+  }
+  if (T->rows.empty()) return PFK_OK;
+  HIPCHK(hipEventRecord(T->ev_user, T->user));
+  HIPCHK(hipStreamWaitEvent(T->s1, T->ev_user, 0));
+  const int gi = T->opts.graph_iters;
+  int done = 0;
+  if (T->opts.use_graph && iters >= gi) {
+    if (!T->graph) {
+      hipGraph_t g = nullptr;
+      HIPCHK(hipStreamBeginCapture(T->s1, hipStreamCaptureModeThreadLocal));
+      for (int i = 0; i < gi; ++i) enqueue_batch_iteration(T);
+      HIPCHK(hipStreamEndCapture(T->s1, &g));
+      hipError_t e = hipGraphInstantiate(&T->graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return fail(PFK_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    for (; done + gi <= iters; done += gi) HIPCHK(hipGraphLaunch(T->graph, T->s1));
+  }
+  for (; done < iters; ++done) enqueue_batch_iteration(T);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventRecord(T->ev_done, T->s1));
+  HIPCHK(hipStreamWaitEvent(T->user, T->ev_done, 0));
+  return PFK_OK;
+}
+
+// Collect the members' states and act on them as a single solve's host loop
+// does: a recurred convergence gets its true-residual check, a GMRES cycle end
+// or a breakdown/residual gap a restart from x (restarts and iterations
+// bounded), anything final ends the member.  Synchronises the batch stream.
+extern "C" int pfk_batch_poll(pfk_batch T, int* finished, int cap, int* nfinished, int* nrunning) {
+  if (!T) return fail(PFK_ERR_ARG, "null batch");
+  if (nfinished) *nfinished = 0;
+  if (T->dirty) {
+    int rc = batch_rebuild(T);
+    if (rc) return rc;
+  }
+  const int n = (int)T->rows.size();
+  int nf = 0, nr = 0;
+  if (n > 0) {
+    LAUNCH(kb_gather_status, (n + kBlock - 1) / kBlock, T->s1, (const BSys*)T->d_sys, n, T->d_stat);
+    HIPCHK(hipMemcpyAsync(T->h_stat, T->d_stat, sizeof(int) * 2 * n, hipMemcpyDeviceToHost, T->s1));
+    HIPCHK(hipStreamSynchronize(T->s1));
+  }
+  for (int r = 0; r < n; ++r) {
+    auto& mb = T->mem[T->rows[r]];
+    pfk_session_s* S = mb.S;
+    const int status = T->h_stat[2 * r], it = T->h_stat[2 * r + 1];
+    bool ended = false;
+    int code = PFK_NOT_CONVERGED;
+    switch (status) {
+      case kRunning: break;
+      case kConverged: enqueue_true_check(S, T->s1); break;
+      case kDone: ended = true; code = PFK_OK; break;
+      case kMaxit: ended = true; break;
+      case kNonfinite: ended = true; code = PFK_ERR_NONFINITE; break;
+      case kBreakdown0: ended = true; code = PFK_ERR_BREAKDOWN; break;
+      case kCycleEnd:
+        if (it >= S->maxit) ended = true;
+        else enqueue_start(S, T->s1);
+        break;
+      case kBreakdown:
+      case kGap:
+        if (it >= S->maxit) {
+          ended = true;
+        } else if (++S->restarts > S->opts.max_restarts) {
+          ended = true;
+          code = status == kBreakdown ? PFK_ERR_BREAKDOWN : PFK_NOT_CONVERGED;
+        } else {
+          enqueue_start(S, T->s1);
+        }
+        break;
+      default: ended = true; break;
+    }
+    if (ended) {
+      // the true residual at exit (already known after a converged check)
+      if (status != kDone) enqueue_true_check(S, T->s1);
+      mb.state = 2;
+      mb.code = code;
+      T->dirty = true;
+      if (finished && nf < cap) finished[nf] = T->rows[r];
+      ++nf;
+      continue;
+    }
+    ++nr;
+  }
+  HIPCHK(hipGetLastError());
+  if (nfinished) *nfinished = nf;
+  if (nrunning) *nrunning = nr;
+  return PFK_OK;
+}
+
+extern "C" int pfk_batch_info(pfk_batch T, int slot, pfk_solve_info* info) {
+  if (!T || slot < 0 || slot >= (int)T->mem.size() || T->mem[slot].state == 0)
+    return fail(PFK_ERR_ARG, "no such member");
+  auto& mb = T->mem[slot];
+  int rc = read_state(mb.S);
+  if (rc) return rc;
+  const int code = mb.state == 2 ? mb.code : PFK_NOT_CONVERGED;
+  fill_info(mb.S, code, info);
+  if (info) info->converged = (mb.state == 2 && code == PFK_OK) ? 1 : 0;
+  return mb.state == 2 ? code : PFK_NOT_CONVERGED;
+}
+
+extern "C" int pfk_batch_remove(pfk_batch T, int slot) {
+  if (!T || slot < 0 || slot >= (int)T->mem.size() || T->mem[slot].state == 0)
+    return fail(PFK_ERR_ARG, "no such member");
+  HIPCHK(hipStreamSynchronize(T->s1));
+  pfk_session_destroy(T->mem[slot].S);
+  T->mem[slot] = pfk_batch_s::Member{};
+  T->dirty = true;
+  bool any = false;
+  for (auto& m : T->mem) any = any || m.state != 0;
+  if (!any) { T->pc_kind = -1; T->fp32 = -1; T->dim = 0; }
+  return PFK_OK;
+}
+
+extern "C" size_t pfk_batch_workspace_bytes(pfk_operator A, pfk_precond B, pfk_method method, int mmax, int maxit) {
+  return pfk_workspace_bytes(A, B, method, mmax, maxit);
+}
+
+extern "C" int pfk_solve_batched(int count, const pfk_operator* A, const pfk_precond* B, pfk_method method,
+                                 const double* const* b, double* const* x, const double* rtol, int maxit, int mmax,
+                                 void* stream, const pfk_solve_opts* opts, pfk_solve_info* infos) {
+  if (count < 1 || !A || !B || !b || !x || !rtol) return fail(PFK_ERR_ARG, "null argument");
+  pfk_batch T = nullptr;
+  int rc = pfk_batch_create(method, mmax, count, stream, opts, &T);
+  if (rc) return rc;
+  std::vector<int> slot(count, -1);
+  for (int i = 0; i < count && !rc; ++i)
+    rc = pfk_batch_add(T, A[i], B[i], b[i], x[i], rtol[i], maxit, nullptr, 0, &slot[i]);
+  int running = count;
+  const int gi = T->opts.graph_iters;
+  while (!rc && running > 0) {
+    rc = pfk_batch_step(T, gi);
+    if (!rc) rc = pfk_batch_poll(T, nullptr, 0, nullptr, &running);
+  }
+  int worst = PFK_OK;
+  for (int i = 0; !rc && i < count; ++i) {
+    const int c = pfk_batch_info(T, slot[i], infos ? &infos[i] : nullptr);
+    if (c < 0 && worst >= 0) worst = c;
+    else if (c > 0 && worst == PFK_OK) worst = c;
+  }
+  if (!rc) HIPCHK(hipEventRecord(T->ev_done, T->s1));
+  if (!rc) HIPCHK(hipStreamWaitEvent(T->user, T->ev_done, 0));
+  pfk_batch_destroy(T);
+  return rc ? rc : worst;
+}
+
+// ---------------------------------------------------------------------------
+// serving: a request queue in front of continuously refilled batches
+// ---------------------------------------------------------------------------
+namespace {
+
+// Device memory for admitted requests' workspaces: freed blocks are kept and
+// reused for a request of the same or slightly smaller size (within 2x).
+struct WsPool {
+  std::vector<std::pair<size_t, void*>> free_blocks;
+  size_t held = 0;   // bytes allocated from the device (in use or cached)
+  void* get(size_t bytes, size_t budget, size_t in_use) {
+    int best = -1;
+    for (int i = 0; i < (int)free_blocks.size(); ++i) {
+      const size_t sz = free_blocks[i].first;
+      if (sz >= bytes && sz <= 2 * bytes && (best < 0 || sz < free_blocks[best].first)) best = i;
+    }
+    if (best >= 0) {
+      void* p = free_blocks[best].second;
+      free_blocks.erase(free_blocks.begin() + best);
+      return p;
+    }
+    // release cached blocks while a fresh allocation would exceed the budget
+    while (!free_blocks.empty() && held + bytes > budget + 0 && held > in_use) {
+      (void)hipFree(free_blocks.back().second);
+      held -= free_blocks.back().first;
+      free_blocks.pop_back();
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    held += bytes;
+    return p;
+  }
+  void put(void* p, size_t bytes) { free_blocks.push_back({bytes, p}); }
+  void release_all() {
+    for (auto& b : free_blocks) (void)hipFree(b.second);
+    free_blocks.clear();
+  }
+};
+
+}  // namespace
+
+struct pfk_server_s {
+  pfk_server_config cfg{};
+  void* stream = nullptr;
+  struct Req {
+    pfk_operator A = nullptr;
+    pfk_precond B = nullptr;
+    int method = 0;
+    const double* b = nullptr;
+    double* x = nullptr;
+    double rtol = 0.0;
+    int maxit = 0;
+    size_t bytes = 0;       // workspace size (counts against the budget while active)
+    int state = 0;          // 0 queued, 1 active, 2 finished
+    int batch = -1, slot = -1;
+    void* ws = nullptr;
+    int code = PFK_NOT_CONVERGED;
+    pfk_solve_info info{};
+    std::vector<double> hist;
+  };
+  std::vector<Req> reqs;                      // index = request id
+  std::vector<long long> queue;               // FIFO of queued ids
+  size_t qhead = 0;
+  struct Bt {
+    int method, kind, fp32, dim;
+    pfk_batch T;
+    std::vector<long long> owner;             // request id per slot (-1 free)
+    int active;
+  };
+  std::vector<Bt> batches;
+  size_t used = 0;
+  long long completed = 0;
+  WsPool pool;
+};
+
+extern "C" void pfk_server_destroy(pfk_server S) {
+  if (!S) return;
+  for (auto& bt : S->batches) pfk_batch_destroy(bt.T);
+  for (auto& r : S->reqs)
+    if (r.ws) S->pool.put(r.ws, r.bytes);
+  S->pool.release_all();
+  delete S;
+}
+
+extern "C" int pfk_server_create(const pfk_server_config* cfg, void* stream, pfk_server* out) {
+  if (!out || !cfg) return fail(PFK_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (cfg->max_active < 1 || cfg->max_active > 4096) return fail(PFK_ERR_ARG, "max_active must be 1..4096");
+  if (cfg->step_iters < 1) return fail(PFK_ERR_ARG, "step_iters must be >= 1");
+  if (cfg->mmax < 1 || cfg->mmax > kNuMax) return fail(PFK_ERR_ARG, "mmax must be 1..64");
+  if (cfg->hbm_budget == 0) return fail(PFK_ERR_ARG, "hbm_budget must be positive");
+  auto* S = new (std::nothrow) pfk_server_s();
+  if (!S) return fail(PFK_ERR_OOM, "host allocation");
+  S->cfg = *cfg;
+  S->stream = stream;
+  *out = S;
+  return PFK_OK;
+}
+
+extern "C" int pfk_server_submit(pfk_server S, pfk_operator A, pfk_precond B, pfk_method method, const double* b,
+                                 double* x, double rtol, int maxit, long long* id) {
+  if (!S || !A || !B || !b || !x || !id) return fail(PFK_ERR_ARG, "null argument");
+  if (!batch_method_ok(method)) return fail(PFK_ERR_ARG, "requests run PIPEFCG, FCG or PIPEFGMRES");
+  if (B->A != A) return fail(PFK_ERR_ARG, "preconditioner was made for another operator");
+  if (B->kind != kPcNone && B->kind != kPcJacobi && B->kind != kPcBlockPcg)
+    return fail(PFK_ERR_ARG, "requests take the NONE, JACOBI or BLOCK_JACOBI_PCG preconditioner");
+  if (maxit < 0 || !(rtol >= 0.0)) return fail(PFK_ERR_ARG, "bad rtol or maxit");
+  pfk_server_s::Req r;
+  r.A = A; r.B = B; r.method = method; r.b = b; r.x = x; r.rtol = rtol; r.maxit = maxit;
+  r.bytes = pfk_workspace_bytes(A, B, method, S->cfg.mmax, maxit);
+  if (r.bytes == 0) return fail(PFK_ERR_ARG, "workspace size");
+  if (r.bytes > S->cfg.hbm_budget) return fail(PFK_ERR_ARG, "request larger than the whole budget");
+  *id = (long long)S->reqs.size();
+  S->reqs.push_back(std::move(r));
+  S->queue.push_back(*id);
+  return PFK_OK;
+}
+
+// One scheduling round: admit queued requests in arrival order while each fits
+// a batch slot and the memory budget, advance every batch with running members
+// by step_iters iterations (batches run on their own streams, so their work
+// overlaps), poll, and retire what ended (workspace back to the pool).
+extern "C" int pfk_server_progress(pfk_server S, long long* completed, int cap, int* ncompleted) {
+  if (!S) return fail(PFK_ERR_ARG, "null server");
+  if (ncompleted) *ncompleted = 0;
+  // admission
+  while (S->qhead < S->queue.size()) {
+    auto& r = S->reqs[S->queue[S->qhead]];
+    const int fp32 = r.B->kind == kPcBlockPcg && r.B->prec == PFK_FP32_BF16COEF;
+    int bi = -1;
+    for (int i = 0; i < (int)S->batches.size() && bi < 0; ++i) {
+      const auto& bt = S->batches[i];
+      if (bt.method == r.method && bt.kind == r.B->kind && bt.fp32 == fp32 && bt.dim == r.A->dim) bi = i;
+    }
+    if (bi < 0) {
+      pfk_solve_opts o;
+      pfk_default_opts(&o);
+      o.graph_iters = S->cfg.step_iters;
+      pfk_server_s::Bt bt{r.method, r.B->kind, fp32, r.A->dim, nullptr, {}, 0};
+      int rc = pfk_batch_create((pfk_method)r.method, S->cfg.mmax, S->cfg.max_active, S->stream, &o, &bt.T);
+      if (rc) return rc;
+      bt.owner.assign(S->cfg.max_active, -1);
+      S->batches.push_back(std::move(bt));
+      bi = (int)S->batches.size() - 1;
+    }
+    auto& bt = S->batches[bi];
+    if (bt.active >= S->cfg.max_active) break;            // arrival order: the head waits
+    if (S->used + r.bytes > S->cfg.hbm_budget) break;
+    void* ws = S->pool.get(r.bytes, S->cfg.hbm_budget, S->used);
+    if (!ws) break;                                        // out of device memory: wait for retirements
+    int slot = -1;
+    int rc = pfk_batch_add(bt.T, r.A, r.B, r.b, r.x, r.rtol, r.maxit, ws, r.bytes, &slot);
+    if (rc) {
+      S->pool.put(ws, r.bytes);
+      return rc;
+    }
+    r.ws = ws;
+    r.state = 1;
+    r.batch = bi;
+    r.slot = slot;
+    bt.owner[slot] = S->queue[S->qhead];
+    ++bt.active;
+    S->used += r.bytes;
+    ++S->qhead;
+  }
+  // advance
+  for (auto& bt : S->batches)
+    if (bt.active > 0) {
+      int rc = pfk_batch_step(bt.T, S->cfg.step_iters);
+      if (rc) return rc;
+    }
+  // retire
+  int nc = 0;
+  std::vector<int> fin;
+  for (auto& bt : S->batches) {
+    if (bt.active == 0) continue;
+    fin.assign(S->cfg.max_active, -1);
+    int nf = 0, nr = 0;
+    int rc = pfk_batch_poll(bt.T, fin.data(), (int)fin.size(), &nf, &nr);
+    if (rc) return rc;
+    for (int k = 0; k < nf; ++k) {
+      const int slot = fin[k];
+      const long long id = bt.owner[slot];
+      auto& r = S->reqs[id];
+      r.hist.assign((size_t)r.maxit + 1, 0.0);
+      r.info.history = r.hist.data();
+      r.info.history_cap = r.maxit + 1;
+      r.code = pfk_batch_info(bt.T, slot, &r.info);
+      rc = pfk_batch_remove(bt.T, slot);
+      if (rc) return rc;
+      S->pool.put(r.ws, r.bytes);
+      r.ws = nullptr;
+      S->used -= r.bytes;
+      r.state = 2;
+      bt.owner[slot] = -1;
+      --bt.active;
+      ++S->completed;
+      if (completed && nc < cap) completed[nc] = id;
+      ++nc;
+    }
+  }
+  if (ncompleted) *ncompleted = nc;
+  return PFK_OK;
+}
+
+extern "C" int pfk_server_result(pfk_server S, long long id, pfk_solve_info* info) {
+  if (!S || id < 0 || id >= (long long)S->reqs.size()) return fail(PFK_ERR_ARG, "no such request");
+  const auto& r = S->reqs[id];
+  if (r.state != 2) return fail(PFK_ERR_ARG, "request not finished");
+  if (info) {
+    double* h = info->history;
+    const int cap = info->history_cap;
+    *info = r.info;
+    info->history = h;
+    info->history_cap = cap;
+    info->history_len = 0;
+    if (h && cap > 0) {
+      const int n = std::min(cap, r.info.history_len);
+      std::memcpy(h, r.hist.data(), sizeof(double) * n);
+      info->history_len = n;
+    }
+  }
+  return r.code;
+}
+
+extern "C" int pfk_server_stats(pfk_server S, pfk_server_status* st) {
+  if (!S || !st) return fail(PFK_ERR_ARG, "null argument");
+  st->queued = (long long)(S->queue.size() - S->qhead);
+  st->active = 0;
+  for (const auto& bt : S->batches) st->active += bt.active;
+  st->completed = S->completed;
+  st->bytes_in_use = S->used;
+  st->bytes_held = S->pool.held;
   return PFK_OK;
 }

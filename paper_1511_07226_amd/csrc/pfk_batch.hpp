@@ -1,0 +1,168 @@
+// Batched kernels: one launch advances one phase of an outer iteration for
+// every system of a batch.
+//
+// Each system keeps its own operator, preconditioner, workspace and device
+// SolveState (exactly those of a single solve); a device table of BSys
+// records holds the pointers and launch geometry of each.  A phase's launch
+// is the concatenation of every system's own launch of that phase: system s
+// owns workgroups [off[s], off[s+1]) (ranges start at multiples of 8, so the
+// XCD-aware tile order of the stencil engine carries over), finds its record
+// by binary search and runs the same device body as the single-system kernel
+// with its index inside the range.  Systems of different sizes therefore
+// share launches without any per-system kernel boundary, and a system that
+// has stopped (converged, failed, or waiting for a host decision) returns at
+// once in every phase.
+#pragma once
+#include "pfk_gmres.hpp"
+
+namespace pfk {
+
+// Per-system arguments of the batched phases.
+struct BSys {
+  long long N;
+  Grid g;                 // outer operator
+  GridM gm;               // inner operator of the mixed-precision block preconditioner
+  StencilGeom sg;         // the system's stencil launch geometry
+  int Pv, Ps;             // its vector / stencil workgroup counts
+  int bj_wx, bj_wy, bj_n; // its block-preconditioner launch (workgroups along x, y; total)
+  int pc_k;               // inner iterations
+  PcOutDesc pd;           // where B(v) comes from (input vectors and the block solve's output)
+  Window P, S, Q, Z;      // direction windows (method-dependent roles, as in a single solve)
+  double *x, *r, *u, *w, *m, *n, *z, *x0;
+  double *part_main, *part_a, *part_b;
+  SolveState* st;
+  double* hist;
+};
+
+// Phases: workgroup-range tables, one per launch shape.
+enum BPhase { kBpVec = 0, kBpSten = 1, kBpBlk = 2, kBpOne = 3, kBpCount = 4 };
+
+// System owning workgroup b: the largest s with off[s] <= b.
+__device__ __forceinline__ int batch_find(const int* off, int nsys, int b) {
+  int lo = 0, hi = nsys - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---- PIPEFCG ------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) kb_pipefcg_update(const BSys* sys, const int* off, int nsys) {
+  const int s = batch_find(off, nsys, (int)blockIdx.x);
+  const BSys& d = sys[s];
+  const Blk bk{(int)blockIdx.x - off[s], d.Pv};
+  if (bk.id >= bk.n) return;   // padding of the range
+  pipefcg_update_body(bk, d.N, d.P, d.S, d.Q, d.Z, d.x, d.r, d.u, d.w, d.m, d.n, d.part_main, d.st);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_pipefcg_scalars(const BSys* sys) {
+  const BSys& d = sys[blockIdx.x];
+  pipefcg_scalars_body(Blk{0, 1}, d.part_main, d.Pv, d.st, d.hist);
+}
+
+// m = u + B(w - r), n = A m (PIPEFCG); wbar = A B(zbar) (PIPEFGMRES, O unused)
+__global__ void __launch_bounds__(kBlock) kb_apply_pc_out(const BSys* sys, const int* off, int nsys, int pipefcg) {
+  const int s = batch_find(off, nsys, (int)blockIdx.x);
+  const BSys& d = sys[s];
+  const Blk bk{(int)blockIdx.x - off[s], d.Ps};
+  if (bk.id >= bk.n) return;   // padding of the range
+  if (pipefcg)
+    apply_pc_out_body(bk, d.g, d.sg, d.pd, d.u, 1.0, d.m, d.n, 0, nullptr, d.part_b, d.st);
+  else
+    apply_pc_out_body(bk, d.g, d.sg, d.pd, nullptr, 0.0, nullptr, d.z, 0, nullptr, d.part_b, d.st);
+}
+
+// ---- the block-Jacobi inner solve of every system -----------------------------
+template <class T, int D3>
+__global__ void __launch_bounds__(kBlock) kb_block_pcg(const BSys* sys, const int* off, int nsys) {
+  const int s = batch_find(off, nsys, (int)blockIdx.x);
+  const BSys& d = sys[s];
+  const Blk bk{(int)blockIdx.x - off[s], d.bj_n};
+  if (bk.id >= bk.n) return;   // padding of the range
+  const PcOutDesc& pd = d.pd;
+  if constexpr (sizeof(T) == 4)
+    block_pcg_body<float, GridM, D3>(bk, d.gm, d.bj_wx, d.bj_wy, d.pc_k, pd.X1, pd.c1, pd.X2, pd.c2,
+                                     (float*)const_cast<void*>(pd.y), d.st);
+  else
+    block_pcg_body<double, Grid, D3>(bk, d.g, d.bj_wx, d.bj_wy, d.pc_k, pd.X1, pd.c1, pd.X2, pd.c2,
+                                     (double*)const_cast<void*>(pd.y), d.st);
+}
+
+// ---- FCG ----------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) kb_fcg_xr(const BSys* sys, const int* off, int nsys) {
+  const int s = batch_find(off, nsys, (int)blockIdx.x);
+  const BSys& d = sys[s];
+  const Blk bk{(int)blockIdx.x - off[s], d.Pv};
+  if (bk.id >= bk.n) return;   // padding of the range
+  fcg_xr_body(bk, d.N, d.P, d.S, d.x, d.r, d.st);
+}
+
+// u = B(r) with the first reduction (<u,r>, <u,u>, <r,r>, <u, s_d>)
+__global__ void __launch_bounds__(kBlock) kb_fcg_multidot(const BSys* sys, const int* off, int nsys) {
+  const int s = batch_find(off, nsys, (int)blockIdx.x);
+  const BSys& d = sys[s];
+  const Blk bk{(int)blockIdx.x - off[s], d.Pv};
+  if (bk.id >= bk.n) return;   // padding of the range
+  multidot_body(bk, d.N, 0, 1, d.pd, nullptr, d.u, d.r, d.S, d.part_main, d.st);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_cg_scalars1(const BSys* sys) {
+  const BSys& d = sys[blockIdx.x];
+  cg_scalars1_body(Blk{0, 1}, 0, d.part_main, d.Pv, d.st, d.hist);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_fcg_maxpy(const BSys* sys, const int* off, int nsys) {
+  const int s = batch_find(off, nsys, (int)blockIdx.x);
+  const BSys& d = sys[s];
+  const Blk bk{(int)blockIdx.x - off[s], d.Pv};
+  if (bk.id >= bk.n) return;   // padding of the range
+  fcg_maxpy_body(bk, d.N, d.P, d.u, d.st);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_fcg_apply(const BSys* sys, const int* off, int nsys) {
+  const int s = batch_find(off, nsys, (int)blockIdx.x);
+  const BSys& d = sys[s];
+  const Blk bk{(int)blockIdx.x - off[s], d.Ps};
+  if (bk.id >= bk.n) return;   // padding of the range
+  fcg_apply_body(bk, d.g, d.sg, d.P, d.S, d.part_a, d.st);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_cg_scalars2(const BSys* sys) {
+  const BSys& d = sys[blockIdx.x];
+  cg_scalars2_body(Blk{0, 1}, 0, 0, d.part_a, d.Ps, d.st);
+}
+
+// ---- PIPEFGMRES ---------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) kb_pgm_update(const BSys* sys, const int* off, int nsys) {
+  const int s = batch_find(off, nsys, (int)blockIdx.x);
+  const BSys& d = sys[s];
+  const Blk bk{(int)blockIdx.x - off[s], d.Pv};
+  if (bk.id >= bk.n) return;   // padding of the range
+  // P: basis p, S: u~, Q: zbar; qbar = B(zbar) of the previous column from d.pd
+  pgm_update_body(bk, d.N, d.P, d.S, d.Q, d.pd, d.z, d.m, d.part_main, d.st);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_pgm_scalars(const BSys* sys) {
+  const BSys& d = sys[blockIdx.x];
+  pgm_scalars_body(Blk{0, 1}, d.part_main, d.Pv, d.st, d.hist);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_gm_update_x(const BSys* sys, const int* off, int nsys) {
+  const int s = batch_find(off, nsys, (int)blockIdx.x);
+  const BSys& d = sys[s];
+  const Blk bk{(int)blockIdx.x - off[s], d.Pv};
+  if (bk.id >= bk.n) return;   // padding of the range
+  gm_update_x_body(bk, d.N, d.S, d.x0, d.x, d.st);
+}
+
+// ---- status of every system in one copy ----------------------------------------
+__global__ void __launch_bounds__(kBlock) kb_gather_status(const BSys* sys, int nsys, int* out) {
+  for (int s = blockIdx.x * kBlock + threadIdx.x; s < nsys; s += gridDim.x * kBlock) {
+    out[2 * s] = read_status(sys[s].st);
+    out[2 * s + 1] = sys[s].st->it;
+  }
+}
+
+}  // namespace pfk

@@ -80,8 +80,7 @@ k_apply(Grid g, StencilGeom sg, const double* __restrict__ x, double* __restrict
 // O = c3*X3 + B(v) at every node, N = A O.  With `dots`: partials <O, R>, <O, N>.
 // Used for u_0/w_0 and m_0/n_0 of PIPEFCG's start-up and for m_i, n_i in its
 // loop (m_i = u_i + B(w_i - r_i), n_i = A m_i).
-__global__ void __launch_bounds__(kBlock)
-k_apply_pc_out(Grid g, StencilGeom sg, PcOutDesc pd, const double* X3, double c3,
+__device__ __forceinline__ void apply_pc_out_body(Blk bk, Grid g, StencilGeom sg, PcOutDesc pd, const double* X3, double c3,
                double* __restrict__ O, double* __restrict__ Nout,
                int dots, const double* __restrict__ R, double* part, SolveState* st) {
   if (read_status(st) != kRunning) return;
@@ -96,8 +95,14 @@ k_apply_pc_out(Grid g, StencilGeom sg, PcOutDesc pd, const double* X3, double c3
       acc[1] += mc * nv;
     }
   };
-  stencil_march<double>(g, sg, in, sink);
-  if (dots) block_partials<2>(acc, 2, part, sg.blocks());
+  stencil_march<double>(g, sg, bk.id, in, sink);
+  if (dots) block_partials<2>(acc, 2, part, sg.blocks(), bk.id);
+}
+__global__ void __launch_bounds__(kBlock)
+k_apply_pc_out(Grid g, StencilGeom sg, PcOutDesc pd, const double* X3, double c3,
+               double* __restrict__ O, double* __restrict__ Nout,
+               int dots, const double* __restrict__ R, double* part, SolveState* st) {
+  apply_pc_out_body(this_blk(), g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
 }
 
 // True-residual verdict after a recurred convergence: kDone or kGap.
@@ -156,8 +161,7 @@ __device__ __forceinline__ void st2(double* p, long long e, double2 v, bool full
 // consecutive nodes (16-byte accesses); the per-direction dot is summed over
 // the wave at once and accumulated in LDS, so the register footprint does not
 // grow with the window.  Vectors must be 16-byte aligned.
-__global__ void __launch_bounds__(kBlock)
-k_pipefcg_update(long long N, Window P, Window S, Window Q, Window Z,
+__device__ __forceinline__ void pipefcg_update_body(Blk bk, long long N, Window P, Window S, Window Q, Window Z,
                  double* __restrict__ x, double* __restrict__ r, double* __restrict__ u,
                  double* __restrict__ w, const double* __restrict__ m, const double* __restrict__ n,
                  double* part, const SolveState* st) {
@@ -183,7 +187,7 @@ k_pipefcg_update(long long N, Window P, Window S, Window Q, Window Z,
   const long long npair = (N + 1) / 2;
   // the trip count is uniform per wave (the in-loop wave sums need every lane);
   // lanes past the end compute on element 0 and contribute nothing
-  for (long long qw = gtid() - lane; qw < npair; qw += gstride()) {
+  for (long long qw = bk.gtid() - lane; qw < npair; qw += bk.gstride()) {
     const bool act = qw + lane < npair;
     const long long e = act ? 2 * (qw + lane) : 0;
     const bool full = act && e + 1 < N;
@@ -247,15 +251,21 @@ k_pipefcg_update(long long N, Window P, Window S, Window Q, Window Z,
     double acc = 0.0;
 #pragma unroll
     for (int wv = 0; wv < kWaves; ++wv) acc += s_dot[wv][src];
-    part[(long long)c * gridDim.x + blockIdx.x] = acc;
+    part[(long long)c * bk.n + bk.id] = acc;
   }
+}
+__global__ void __launch_bounds__(kBlock)
+k_pipefcg_update(long long N, Window P, Window S, Window Q, Window Z,
+                 double* __restrict__ x, double* __restrict__ r, double* __restrict__ u,
+                 double* __restrict__ w, const double* __restrict__ m, const double* __restrict__ n,
+                 double* part, const SolveState* st) {
+  pipefcg_update_body(this_blk(), N, P, S, Q, Z, x, r, u, w, m, n, part, st);
 }
 
 // Scalars of iteration j+1 from the fused reduction: iteration count,
 // history, convergence test, beta_{j+1,d} = -<u,s_d>/eta_d,
 // eta_{j+1} = delta - sum beta^2 eta_d (breakdown if not positive), alpha.
-__global__ void __launch_bounds__(kBlock)
-k_pipefcg_scalars(const double* part, int P, SolveState* st, double* hist) {
+__device__ __forceinline__ void pipefcg_scalars_body(Blk bk, const double* part, int P, SolveState* st, double* hist) {
   __shared__ double col[kNuMax + 3];
   if (read_status(st) != kRunning) return;
   const int j1 = st->j + 1;
@@ -288,23 +298,31 @@ k_pipefcg_scalars(const double* part, int P, SolveState* st, double* hist) {
   st->alpha = col[0] / eta;
   if (it >= st->maxit) st->status = kMaxit;
 }
+__global__ void __launch_bounds__(kBlock)
+k_pipefcg_scalars(const double* part, int P, SolveState* st, double* hist) {
+  pipefcg_scalars_body(this_blk(), part, P, st, hist);
+}
 
 // ---------------------------------------------------------------------------
 // FCG and GCR (two blocking reductions per iteration)
 // ---------------------------------------------------------------------------
 // x += alpha p_j, r -= alpha s_j for the newest direction j = st->j.
-__global__ void __launch_bounds__(kBlock)
-k_fcg_xr(long long N, Window P, Window S, double* __restrict__ x, double* __restrict__ r,
+__device__ __forceinline__ void fcg_xr_body(Blk bk, long long N, Window P, Window S, double* __restrict__ x, double* __restrict__ r,
          const SolveState* st) {
   if (read_status(st) != kRunning) return;
   const int slot = st->j % st->nu_max;
   const double alpha = st->alpha;
   const double* p = P.slot(slot);
   const double* s = S.slot(slot);
-  for (long long e = gtid(); e < N; e += gstride()) {
+  for (long long e = bk.gtid(); e < N; e += bk.gstride()) {
     x[e] += alpha * p[e];
     r[e] -= alpha * s[e];
   }
+}
+__global__ void __launch_bounds__(kBlock)
+k_fcg_xr(long long N, Window P, Window S, double* __restrict__ x, double* __restrict__ r,
+         const SolveState* st) {
+  fcg_xr_body(this_blk(), N, P, S, x, r, st);
 }
 
 // The multi-dot of one vector V against R, itself and the window:
@@ -314,8 +332,7 @@ k_fcg_xr(long long N, Window P, Window S, double* __restrict__ x, double* __rest
 //   FCG:     V = u = B(r), R = r  (gamma = <u,r>, the test on <r,r>, <u,s_d>)
 //   GCR:     V = t = A u,  R = r  (the test on <r,r>, <t,s_d>)
 //   PIPEGCR: V = w = A u,  R = r  (gamma, delta, rho, <w,s_d>: its single reduction)
-__global__ void __launch_bounds__(kBlock)
-k_multidot(long long N, int init, int from_pc, PcOutDesc pd, const double* __restrict__ Vin,
+__device__ __forceinline__ void multidot_body(Blk bk, long long N, int init, int from_pc, PcOutDesc pd, const double* __restrict__ Vin,
            double* __restrict__ Vout, const double* __restrict__ R, Window S, double* part, SolveState* st) {
   if (read_status(st) != kRunning) return;
   PcOut pc{};
@@ -330,9 +347,9 @@ k_multidot(long long N, int init, int from_pc, PcOutDesc pd, const double* __res
   for (int t = threadIdx.x; t < kWaves * (kNuMax + 3); t += kBlock) (&s_dot[0][0])[t] = 0.0;
   __syncthreads();
   double vr = 0.0, vv = 0.0, rr = 0.0;
-  const long long step = 2LL * gstride();
+  const long long step = 2LL * bk.gstride();
   // wave-uniform trip count (wave sums inside); lanes past the end contribute 0
-  for (long long w0 = 2LL * blockIdx.x * kBlock + threadIdx.x - lane; w0 < N; w0 += step) {
+  for (long long w0 = 2LL * bk.id * kBlock + threadIdx.x - lane; w0 < N; w0 += step) {
     const long long e0 = w0 + lane;
     const bool h0 = e0 < N;
     const long long e1 = e0 + kBlock;
@@ -380,15 +397,19 @@ k_multidot(long long N, int init, int from_pc, PcOutDesc pd, const double* __res
     double acc = 0.0;
 #pragma unroll
     for (int wv = 0; wv < kWaves; ++wv) acc += s_dot[wv][c];
-    part[(long long)c * gridDim.x + blockIdx.x] = acc;
+    part[(long long)c * bk.n + bk.id] = acc;
   }
+}
+__global__ void __launch_bounds__(kBlock)
+k_multidot(long long N, int init, int from_pc, PcOutDesc pd, const double* __restrict__ Vin,
+           double* __restrict__ Vout, const double* __restrict__ R, Window S, double* part, SolveState* st) {
+  multidot_body(this_blk(), N, init, from_pc, pd, Vin, Vout, R, S, part, st);
 }
 
 // First-reduction scalars of FCG/GCR from k_multidot's columns: the
 // iteration count, history and test on ||r||, beta_d = -<V,s_d>/eta_d, and
 // (FCG) gamma = <u, r>.  With `init` only j = 0 and gamma are set.
-__global__ void __launch_bounds__(kBlock)
-k_cg_scalars1(int init, const double* part, int P, SolveState* st, double* hist) {
+__device__ __forceinline__ void cg_scalars1_body(Blk bk, int init, const double* part, int P, SolveState* st, double* hist) {
   __shared__ double col[kNuMax + 3];
   if (read_status(st) != kRunning) return;
   const int j1 = init ? 0 : st->j + 1;
@@ -411,10 +432,13 @@ k_cg_scalars1(int init, const double* part, int P, SolveState* st, double* hist)
     st->beta[t] = -col[3 + t] / st->eta_ring[d % numax];
   }
 }
+__global__ void __launch_bounds__(kBlock)
+k_cg_scalars1(int init, const double* part, int P, SolveState* st, double* hist) {
+  cg_scalars1_body(this_blk(), init, part, P, st, hist);
+}
 
 // p_j = u + sum beta p_d into slot j (FCG).
-__global__ void __launch_bounds__(kBlock)
-k_fcg_maxpy(long long N, Window P, const double* __restrict__ u, const SolveState* st) {
+__device__ __forceinline__ void fcg_maxpy_body(Blk bk, long long N, Window P, const double* __restrict__ u, const SolveState* st) {
   if (read_status(st) != kRunning) return;
   __shared__ double s_beta[kNuMax];
   __shared__ long long s_off[kNuMax];
@@ -426,7 +450,7 @@ k_fcg_maxpy(long long N, Window P, const double* __restrict__ u, const SolveStat
   __syncthreads();
   double* pn = P.slot(j % numax);
   const long long npair = (N + 1) / 2;
-  for (long long qi = gtid(); qi < npair; qi += gstride()) {
+  for (long long qi = bk.gtid(); qi < npair; qi += bk.gstride()) {
     const long long e = 2 * qi;
     const bool full = e + 1 < N;
     double2 p = ld2(u, e, full);
@@ -444,6 +468,10 @@ k_fcg_maxpy(long long N, Window P, const double* __restrict__ u, const SolveStat
     }
     st2(pn, e, p, full);
   }
+}
+__global__ void __launch_bounds__(kBlock)
+k_fcg_maxpy(long long N, Window P, const double* __restrict__ u, const SolveState* st) {
+  fcg_maxpy_body(this_blk(), N, P, u, st);
 }
 
 // GCR: p_j = u + sum beta p_d, s_j = t + sum beta s_d into slot j, partials
@@ -483,8 +511,7 @@ k_gcr_maxpy(long long N, Window P, Window S, const double* __restrict__ u, const
 }
 
 // s_j = A p_j, partial eta_j = <p_j, s_j> (FCG).
-__global__ void __launch_bounds__(kBlock)
-k_fcg_apply(Grid g, StencilGeom sg, Window P, Window S, double* part, const SolveState* st) {
+__device__ __forceinline__ void fcg_apply_body(Blk bk, Grid g, StencilGeom sg, Window P, Window S, double* part, const SolveState* st) {
   if (read_status(st) != kRunning) return;
   const int slot = st->j % st->nu_max;
   const double* p = P.slot(slot);
@@ -495,14 +522,17 @@ k_fcg_apply(Grid g, StencilGeom sg, Window P, Window S, double* part, const Solv
     s[idx] = sv;
     acc[0] += pc * sv;
   };
-  stencil_march<double>(g, sg, in, sink);
-  block_partials<1>(acc, 1, part, sg.blocks());
+  stencil_march<double>(g, sg, bk.id, in, sink);
+  block_partials<1>(acc, 1, part, sg.blocks(), bk.id);
+}
+__global__ void __launch_bounds__(kBlock)
+k_fcg_apply(Grid g, StencilGeom sg, Window P, Window S, double* part, const SolveState* st) {
+  fcg_apply_body(this_blk(), g, sg, P, S, part, st);
 }
 
 // Second-reduction scalars: eta_j (FCG: <p,s>; GCR: <s,s> with gamma = <r,s>),
 // breakdown check, alpha_j.
-__global__ void __launch_bounds__(kBlock)
-k_cg_scalars2(int gcr, int init, const double* part, int P, SolveState* st) {
+__device__ __forceinline__ void cg_scalars2_body(Blk bk, int gcr, int init, const double* part, int P, SolveState* st) {
   if (read_status(st) != kRunning) return;
   const double c0 = block_sum_column(part, P, 0);
   const double c1 = gcr ? block_sum_column(part, P, 1) : 0.0;
@@ -521,6 +551,10 @@ k_cg_scalars2(int gcr, int init, const double* part, int P, SolveState* st) {
   st->eta_ring[j % st->nu_max] = eta;
   st->alpha = st->gamma / eta;
   if (st->it >= st->maxit) st->status = kMaxit;
+}
+__global__ void __launch_bounds__(kBlock)
+k_cg_scalars2(int gcr, int init, const double* part, int P, SolveState* st) {
+  cg_scalars2_body(this_blk(), gcr, init, part, P, st);
 }
 
 // Start-up test on ||r_0|| (history[0]).

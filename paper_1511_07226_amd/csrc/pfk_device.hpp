@@ -268,7 +268,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // blockIdx.x goes to part[c*P + blockIdx.x] for c < nc.  Every thread of the
 // workgroup must call this (it synchronises).
 template <int NC>
-__device__ __forceinline__ void block_partials(double (&acc)[NC], int nc, double* part, int P) {
+__device__ __forceinline__ void block_partials(double (&acc)[NC], int nc, double* part, int P, int bid) {
   __shared__ double sh[kWaves][NC];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -283,8 +283,12 @@ __device__ __forceinline__ void block_partials(double (&acc)[NC], int nc, double
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) s += sh[w][c];
-    part[(long long)c * P + blockIdx.x] = s;
+    part[(long long)c * P + bid] = s;
   }
+}
+template <int NC>
+__device__ __forceinline__ void block_partials(double (&acc)[NC], int nc, double* part, int P) {
+  block_partials<NC>(acc, nc, part, P, (int)blockIdx.x);
 }
 
 // Sum column c of P partials with the whole workgroup (fixed order); the
@@ -323,6 +327,16 @@ __device__ __forceinline__ void block_sum_columns(const double* part, int P, int
   }
   __syncthreads();
 }
+
+// A workgroup's place in its launch.  A single-system kernel is a launch of
+// its own (id = blockIdx.x, n = gridDim.x); a batched kernel gives every
+// system its own contiguous range of workgroups.
+struct Blk {
+  int id, n;
+  __device__ __forceinline__ long long gtid() const { return (long long)id * kBlock + threadIdx.x; }
+  __device__ __forceinline__ long long gstride() const { return (long long)n * kBlock; }
+};
+__device__ __forceinline__ Blk this_blk() { return Blk{(int)blockIdx.x, (int)gridDim.x}; }
 
 // Grid-stride geometry for pointwise kernels.
 __device__ __forceinline__ long long gtid() { return (long long)blockIdx.x * kBlock + threadIdx.x; }

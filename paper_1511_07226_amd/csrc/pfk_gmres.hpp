@@ -92,18 +92,21 @@ k_gm_scale(long long N, const double* src, int from_window, Window P, double* __
 }
 
 // x = x0 + sum_j y_j U[j] once a cycle has ended (idempotent).
-__global__ void __launch_bounds__(kBlock)
-k_gm_update_x(long long N, Window U, const double* __restrict__ x0, double* __restrict__ x, const SolveState* st) {
+__device__ __forceinline__ void gm_update_x_body(Blk bk, long long N, Window U, const double* __restrict__ x0, double* __restrict__ x, const SolveState* st) {
   if (!st->pend) return;
   __shared__ double s_y[kNuMax];
   const int n = st->ycols;
   for (int t = threadIdx.x; t < n; t += kBlock) s_y[t] = st->y[t];
   __syncthreads();
-  for (long long e = gtid(); e < N; e += gstride()) {
+  for (long long e = bk.gtid(); e < N; e += bk.gstride()) {
     double v = x0[e];
     for (int j = 0; j < n; ++j) v += s_y[j] * U.base[(long long)j * U.ld + e];
     x[e] = v;
   }
+}
+__global__ void __launch_bounds__(kBlock)
+k_gm_update_x(long long N, Window U, const double* __restrict__ x0, double* __restrict__ x, const SolveState* st) {
+  gm_update_x_body(this_blk(), N, U, x0, x, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -238,8 +241,7 @@ k_pgm_apply0(Grid g, StencilGeom sg, PcOutDesc pd, Window U, Window P, Window ZB
 // t = ||zbar_c||^2 - sum hbar_j^2 (t < 0: norm breakdown -> finish with the
 // columns so far and restart), h_{c,c} = hbar_c + sigma, h_{c+1,c} = sqrt(t),
 // Givens, history, test, cycle end.
-__global__ void __launch_bounds__(kBlock)
-k_pgm_scalars(const double* part, int P, SolveState* st, double* hist) {
+__device__ __forceinline__ void pgm_scalars_body(Blk bk, const double* part, int P, SolveState* st, double* hist) {
   __shared__ double col[kNuMax + 2];
   if (read_status(st) != kRunning) return;
   const int c = st->col;
@@ -274,6 +276,10 @@ k_pgm_scalars(const double* part, int P, SolveState* st, double* hist) {
   st->inv_hn = 1.0 / hn;
   st->col = c + 1;
 }
+__global__ void __launch_bounds__(kBlock)
+k_pgm_scalars(const double* part, int P, SolveState* st, double* hist) {
+  pgm_scalars_body(this_blk(), part, P, st, hist);
+}
 
 // Column n = st->col (after the scalars of column n-1):
 //   p_n   = (zbar_{n-1} - sum_j hbar_j p_j) / h
@@ -281,8 +287,7 @@ k_pgm_scalars(const double* part, int P, SolveState* st, double* hist) {
 //   zbar_n = (wbar_{n-1} - sigma zbar_{n-1} - sum_j hbar_j zbar_j) / h
 // into slot n (zbar_n also to zin), and the next single reduction:
 // <p_j, zbar_n> for j <= n and ||zbar_n||^2.
-__global__ void __launch_bounds__(kBlock)
-k_pgm_update(long long N, Window P, Window U, Window ZB, PcOutDesc pd, const double* __restrict__ wb,
+__device__ __forceinline__ void pgm_update_body(Blk bk, long long N, Window P, Window U, Window ZB, PcOutDesc pd, const double* __restrict__ wb,
              double* __restrict__ zin, double* part, SolveState* st) {
   if (read_status(st) != kRunning) return;
   const PcOut pc = make_pc_out(pd, &st->pc);
@@ -302,7 +307,7 @@ k_pgm_update(long long N, Window P, Window U, Window ZB, PcOutDesc pd, const dou
   double dp = 0.0, zz = 0.0;
   // wave-uniform trip count (wave sums inside); lanes past the end use
   // element 0, contribute 0 and store nothing
-  for (long long ew = gtid() - lane; ew < N; ew += gstride()) {
+  for (long long ew = bk.gtid() - lane; ew < N; ew += bk.gstride()) {
     const bool act = ew + lane < N;
     const long long e = act ? ew + lane : 0;
     double z = wb[e] - sigma * zprev[e];
@@ -337,8 +342,13 @@ k_pgm_update(long long N, Window P, Window U, Window ZB, PcOutDesc pd, const dou
     double acc = 0.0;
 #pragma unroll
     for (int wv = 0; wv < kWaves; ++wv) acc += s_dot[wv][c];
-    part[(long long)c * gridDim.x + blockIdx.x] = acc;
+    part[(long long)c * bk.n + bk.id] = acc;
   }
+}
+__global__ void __launch_bounds__(kBlock)
+k_pgm_update(long long N, Window P, Window U, Window ZB, PcOutDesc pd, const double* __restrict__ wb,
+             double* __restrict__ zin, double* part, SolveState* st) {
+  pgm_update_body(this_blk(), N, P, U, ZB, pd, wb, zin, part, st);
 }
 
 // ---------------------------------------------------------------------------

@@ -447,8 +447,7 @@ __device__ __forceinline__ void bj_coeffs(const G& g, int i, int j, int k, int l
 // yout (T).  Workgroups: wx * wy * wz, with wx = ceil(nx / (BPW * 8)),
 // wy = ceil(ny / 8), wz = ceil(nz / 8) (1 in 2D).
 template <class T, class G, int D3>
-__global__ void __launch_bounds__(kBlock)
-k_block_pcg(G g, int wx, int wy, int k, const double* X1, double c1, const double* X2, double c2,
+__device__ __forceinline__ void block_pcg_body(Blk bk, G g, int wx, int wy, int k, const double* X1, double c1, const double* X2, double c2,
             T* __restrict__ yout, const SolveState* st) {
   using Sh = BjShape<D3>;
   constexpr int NPT = Sh::NPT, WPB = Sh::WPB, BPW = Sh::BPW, ZL = Sh::ZL;
@@ -458,7 +457,7 @@ k_block_pcg(G g, int wx, int wy, int k, const double* X1, double c1, const doubl
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lx = lane & 7, ly = lane >> 3;
   const int blk = wave / WPB, zh = wave % WPB;
-  const int b = blockIdx.x;
+  const int b = bk.id;
   const int gx = b % wx, gy = (b / wx) % wy, gz = b / (wx * wy);
   const int i = (gx * BPW + blk) * kBjEdge + lx;
   const int j = gy * kBjEdge + ly;
@@ -555,6 +554,12 @@ k_block_pcg(G g, int wx, int wy, int k, const double* X1, double c1, const doubl
 #pragma unroll
   for (int n = 0; n < NPT; ++n)
     if (valid[n]) yout[vec_index(g, i, j, gz * ZL + zh * NPT + n)] = y[n];
+}
+template <class T, class G, int D3>
+__global__ void __launch_bounds__(kBlock)
+k_block_pcg(G g, int wx, int wy, int k, const double* X1, double c1, const double* X2, double c2,
+            T* __restrict__ yout, const SolveState* st) {
+  block_pcg_body<T, G, D3>(this_blk(), g, wx, wy, k, X1, c1, X2, c2, yout, st);
 }
 
 }  // namespace pfk
