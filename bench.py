@@ -16,6 +16,8 @@ from __future__ import annotations
 import argparse
 import json
 import math
+
+import numpy as np
 import os
 import sys
 import time
@@ -125,6 +127,188 @@ def time_to_solution(pfk, torch, A, B, method, b, rtol, maxit, mmax, **opts):
             "solves_per_s": round(1.0 / dt, 4)}, x
 
 
+def size_sweep(pfk, torch, steps=40):
+    """PIPEFCG against FCG per outer iteration on single systems of growing size
+    (block-Jacobi inner solve, FP64, nu_max 30): where the one device-side
+    reduction per iteration matters more than the pipelined method's extra
+    window traffic."""
+    import gen
+    out = {}
+    for dim, n in ((2, 64), (3, 16), (3, 32), (3, 64), (3, 128)):
+        p = gen.make_problem(dim, n, 8 if dim == 2 else 20, 3.0 if dim == 2 else 4.0, seed=0)
+        A = pfk.Operator(dim, n, p.eta)
+        B = pfk.Precond(A, "block_jacobi_pcg", INNER, block=8)
+        b = torch.as_tensor(p.b).cuda()
+        row = {}
+        for method in ("pipefcg", "fcg"):
+            S, dt = time_steps(pfk, torch, A, B, method, b, steps, NU + 2)
+            S.close()
+            row[method] = round(steps / dt, 1)
+        row["pipelined_over_unpipelined"] = round(row["pipefcg"] / row["fcg"], 3)
+        out[f"{dim}d_n{n}"] = row
+    return out
+
+
+def batched_bench(pfk, torch, steps, warmup, count=64):
+    """Configuration 4: 64 uneven SPD systems (edge 32..96, contrast 1e2..1e4),
+    PIPEFCG nu_max 20 with the block-Jacobi inner solve (4 steps, FP32 on BF16
+    viscosity), advanced by shared launches.  Tiling per size from the
+    autotuner.  Reports steady-state batch iterations/s (every system advances
+    one iteration), the same for FCG and for the systems stepped one at a time,
+    and the time to solve all of them to rtol 1e-8."""
+    import gen
+    NU4, K4 = 20, 4
+    probs = gen.batched_problems(count, seed=0)
+    mem = []
+    for p in probs:
+        A = pfk.Operator(3, p.n, p.eta)
+        B = pfk.Precond(A, "block_jacobi_pcg", K4, precision=pfk.FP32_BF16COEF, block=8)
+        mem.append((p, A, B))
+    tuning = {}
+    for p, A, B in mem:
+        if p.n not in tuning:
+            tuning[p.n] = A.autotune(B, "pipefcg", mmax=NU4, reps=5)
+    for p, A, B in mem:
+        t = tuning[p.n]
+        A.set_tiling(t["tile_x"], t["stencil_target"], t["vector_blocks"])
+    total_n = sum(A.N for _, A, _ in mem)
+    bs = [torch.as_tensor(p.b).cuda() for p, _, _ in mem]
+    out = {"workload": f"{count} SPD sinker systems, edge in {{32,48,64,80,96}}, {total_n} unknowns; "
+                       f"nu_max {NU4}, block-Jacobi PCG ({K4} steps, FP32/BF16), outer FP64",
+           "sizes": {str(n): sum(1 for p, _, _ in mem if p.n == n) for n in sorted(tuning)},
+           "autotuned": {str(n): {k: v for k, v in t.items()} for n, t in tuning.items()}}
+
+    def steady(method):
+        T = pfk.Batch(method, mmax=NU4, capacity=count, graph_iters=10)
+        xs = [torch.zeros_like(b) for b in bs]
+        for (p, A, B), b, x in zip(mem, bs, xs):
+            T.add(A, B, b, x, rtol=0.0, maxit=warmup + steps + 50)
+        T.step(max(warmup, NU4 + 2))
+        T.poll()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        T.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        _, running = T.poll()
+        T.close()
+        if running != count:
+            raise RuntimeError(f"batched {method}: {count - running} systems stopped during timing")
+        return steps / dt
+
+    for method in ("pipefcg", "fcg"):
+        log(f"batched {method}: timing {steps} steps")
+        r = steady(method)
+        out[f"{method}_batch_iters_per_s"] = round(r, 2)
+        out[f"{method}_unknown_iters_per_s"] = round(r * total_n, 1)
+    # the same systems stepped one session at a time (one per size, scaled by count)
+    seq_ms = 0.0
+    for n in sorted(tuning):
+        p, A, B = next(m for m in mem if m[0].n == n)
+        S, dt = time_steps(pfk, torch, A, B, "pipefcg", torch.as_tensor(p.b).cuda(), steps, warmup, mmax=NU4)
+        S.close()
+        seq_ms += dt / steps * 1e3 * out["sizes"][str(n)]
+    out["pipefcg_one_at_a_time_iters_per_s"] = round(1e3 / seq_ms, 2)
+    out["batching_speedup"] = round(out["pipefcg_batch_iters_per_s"] * seq_ms / 1e3, 3)
+    # bytes of one batched PIPEFCG iteration: window update (4 nu + 14 vectors), the
+    # block solve (v in: 2 vectors, eta 2 B, y out 4 B), m, n (u, y, eta in; m, n out)
+    per_unknown = (4 * NU4 + 14) * 8 + (2 * 8 + 2 + 4) + (8 + 4 + 2 + 2 * 8)
+    out["algorithmic_GBps_pipefcg"] = round(per_unknown * total_n * out["pipefcg_batch_iters_per_s"] / 1e9, 1)
+    out["algorithmic_bytes_per_unknown_iteration"] = per_unknown
+    log("batched pipefcg: solving all systems to rtol 1e-8")
+    xs = [torch.zeros_like(b) for b in bs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    code, infos = pfk.solve_batched([A for _, A, _ in mem], [B for _, _, B in mem], "pipefcg", bs, xs,
+                                    rtol=1e-8, maxit=4000, mmax=NU4, graph_iters=10)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    its = [i.iterations for i in infos]
+    out["time_to_solution"] = {"seconds": round(dt, 3), "solves_per_s": round(count / dt, 2),
+                               "converged": sum(1 for i in infos if i.converged),
+                               "iterations_min_median_max": [min(its), sorted(its)[len(its) // 2], max(its)],
+                               "max_true_rel_resid": max(i.true_rel_resid for i in infos)}
+    return out
+
+
+def serving_bench(pfk, torch, nreq=160, seed=0, loads=(0.5, 0.9)):
+    """Configuration 5: Poisson arrivals of PIPEFCG / PIPEFGMRES requests (50/50)
+    on 3D sinker grids, edge lognormal (median 40, sigma_ln 0.5) clipped to
+    16..128, contrast 10^U(1,4), rtol 1e-6 or 1e-8, admitted by a memory
+    budget into continuously refilled batches.  Both methods use the
+    block-Jacobi inner solve (4 steps, FP32/BF16).  The capacity is measured
+    with every request arriving at once; Poisson streams then offer a fraction
+    of it.  Latency = completion seen by the serving loop minus arrival."""
+    import gen
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(nreq):
+        n = int(np.clip(round(float(rng.lognormal(math.log(40.0), 0.5))), 16, 128))
+        method = "pipefcg" if rng.random() < 0.5 else "pipefgmres"
+        rtol = 1e-6 if rng.random() < 0.5 else 1e-8
+        p = gen.make_problem(3, n, 20, (1.0, 4.0), seed=10000 + i)
+        A = pfk.Operator(3, n, p.eta)
+        B = pfk.Precond(A, "block_jacobi_pcg", 4, precision=pfk.FP32_BF16COEF, block=8)
+        reqs.append(dict(A=A, B=B, b=torch.as_tensor(p.b).cuda(), method=method, rtol=rtol, n=n))
+    budget = 48 << 30
+    MAXIT = 4000
+
+    def run(arrivals):
+        srv = pfk.Server(hbm_budget=budget, max_active=64, step_iters=8, mmax=NU)
+        xs = [torch.zeros_like(r["b"]) for r in reqs]
+        ids, lat, conv = {}, [], 0
+        by_method, failed = {}, []
+        t0 = time.perf_counter()
+        k, done = 0, 0
+        while done < len(reqs):
+            now = time.perf_counter() - t0
+            while k < len(reqs) and arrivals[k] <= now:
+                r = reqs[k]
+                ids[srv.submit(r["A"], r["B"], r["method"], r["b"], xs[k], rtol=r["rtol"], maxit=MAXIT)] = k
+                k += 1
+            st = srv.stats()
+            if st["active"] == 0 and st["queued"] == 0:
+                if k < len(reqs):
+                    time.sleep(max(0.0, min(0.002, arrivals[k] - now)))
+                continue
+            fin = srv.progress()
+            t = time.perf_counter() - t0
+            for rid in fin:
+                lat.append(t - arrivals[ids[rid]])
+                info = srv.result(rid)
+                conv += int(info.converged)
+                r = reqs[ids[rid]]
+                key = f"{r['method']}_rtol{r['rtol']:.0e}"
+                bym = by_method.setdefault(key, [0, 0])
+                bym[0] += 1
+                bym[1] += int(info.converged)
+                if not info.converged and len(failed) < 12:
+                    failed.append({"n": r["n"], "method": r["method"], "rtol": r["rtol"],
+                                   "iterations": info.iterations, "status": info.status_name,
+                                   "true_rel": float(f"{info.true_rel_resid:.3e}")})
+                done += 1
+        total = time.perf_counter() - t0
+        srv.close()
+        lat = np.sort(np.array(lat))
+        return {"requests": len(reqs), "seconds": round(total, 3), "solves_per_s": round(len(reqs) / total, 2),
+                "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2), "converged": conv,
+                "served_converged_by_kind": by_method, "not_converged_sample": failed}
+
+    log(f"serving: {nreq} requests arriving at once (capacity)")
+    cap = run(np.zeros(nreq))
+    out = {"workload": f"{nreq} requests, edge lognormal(40, 0.5) in 16..128, PIPEFCG/PIPEFGMRES 50/50, "
+                       f"rtol 1e-6/1e-8, window/restart {NU}, maxit {MAXIT}, block-Jacobi PCG (4, FP32/BF16), "
+                       "budget 48 GiB, 64 per batch",
+           "edge_median": int(np.median([r["n"] for r in reqs])), "burst": cap, "poisson": {}}
+    for f in loads:
+        rate = f * cap["solves_per_s"]
+        arr = np.cumsum(np.random.default_rng(seed + 1).exponential(1.0 / rate, size=nreq))
+        log(f"serving: Poisson arrivals at {rate:.1f}/s ({f} x capacity)")
+        out["poisson"][f"{f}x"] = {"offered_per_s": round(rate, 2), **run(arr)}
+    return out
+
+
 def cpu_baseline(prob, method):
     """The FP64 oracle on the host: one outer iteration of the same workload,
     timed as (start-up + 1 iteration) minus (start-up alone), one thread."""
@@ -200,6 +384,8 @@ def main():
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the FP64 PIPEFCG/FCG pair (for profiler runs)")
     ap.add_argument("--profile-iters", type=int, default=10)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -313,6 +499,17 @@ def main():
             conv[method] = {"it_per_s": round(args.steps / dt, 3), "ms_per_step": round(dt / args.steps * 1e3, 4)}
         extra["conv_diff_256"] = conv
         del A3, B3, b3
+
+    if not args.headline_only:
+        log("size sweep: PIPEFCG vs FCG per iteration")
+        extra["size_sweep_it_per_s"] = size_sweep(pfk, torch)
+    if not args.headline_only and not args.no_batched:
+        log("batched workload (64 uneven systems)")
+        extra["batched_64"] = batched_bench(pfk, torch, args.steps, args.warmup)
+        torch.cuda.empty_cache()
+    if not args.headline_only and not args.no_serving:
+        log("serving workload")
+        extra["serving"] = serving_bench(pfk, torch)
 
     cpu = None
     if not args.no_cpu_baseline:

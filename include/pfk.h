@@ -166,6 +166,7 @@ int pfk_operator_get_tiling(pfk_operator A, int* tile_x, int* stencil_blocks, in
 
 typedef struct {
   int tile_x;               /* chosen stencil tile width                          */
+  int stencil_target;       /* the stencil_target that gives the chosen geometry  */
   int stencil_blocks;       /* chosen workgroups per stencil launch               */
   int vector_blocks;        /* chosen workgroups per vector launch                */
   double ms_per_iteration;  /* best measured time of one outer iteration          */

@@ -43,7 +43,8 @@ EXPORTED = [
 
 
 class Tuning(C.Structure):
-    _fields_ = [("tile_x", C.c_int), ("stencil_blocks", C.c_int), ("vector_blocks", C.c_int),
+    _fields_ = [("tile_x", C.c_int), ("stencil_target", C.c_int), ("stencil_blocks", C.c_int),
+                ("vector_blocks", C.c_int),
                 ("ms_per_iteration", C.c_double), ("ms_default", C.c_double), ("candidates", C.c_int)]
 
     def as_dict(self) -> dict:

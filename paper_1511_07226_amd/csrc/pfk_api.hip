@@ -127,6 +127,7 @@ struct pfk_operator_s {
   long long npad = 0;
   StencilGeom sg{};
   int pv_blocks = 0;       // workgroups of pointwise kernels
+  int stencil_target = 2048;  // the workgroup target sg was made for
   // mixed-precision inner operator (made when a mixed preconditioner is created)
   __hip_bfloat16* eta_bf16 = nullptr;
   float* vel_f32 = nullptr;
@@ -1251,6 +1252,7 @@ extern "C" int pfk_operator_set_tiling(pfk_operator A, int tile_x, int stencil_t
   const StencilGeom sg = make_geom(A->dim, (int)A->n[0], (int)A->n[1], (int)A->n[2], tile_x, stencil_target);
   if (sg.blocks() > kMaxLaunchBlocks) return fail(PFK_ERR_ARG, "stencil launch too large");
   A->sg = sg;
+  A->stencil_target = stencil_target;
   A->pv_blocks = vector_blocks;
   return PFK_OK;
 }
@@ -1278,12 +1280,16 @@ extern "C" int pfk_operator_autotune(pfk_operator A, pfk_precond B, pfk_method m
   const int nx = (int)A->n[0], ny = (int)A->n[1], nz = (int)A->n[2];
   // candidates
   std::vector<StencilGeom> geoms;
+  std::vector<int> targets;
   for (int tx : {64, 32})
     for (int target : {512, 1024, 2048, 4096}) {
       const StencilGeom g = make_geom(A->dim, nx, ny, nz, tx, target);
       bool dup = false;
       for (const auto& h : geoms) dup = dup || (h.tx == g.tx && h.zc == g.zc);
-      if (!dup && g.blocks() <= kMaxLaunchBlocks) geoms.push_back(g);
+      if (!dup && g.blocks() <= kMaxLaunchBlocks) {
+        geoms.push_back(g);
+        targets.push_back(target);
+      }
     }
   std::vector<int> pvs;
   const int pv_cap = std::max(1, std::min(kMaxLaunchBlocks, ceil_div(A->N, 2LL * kBlock)));
@@ -1377,13 +1383,14 @@ extern "C" int pfk_operator_autotune(pfk_operator A, pfk_precond B, pfk_method m
     rc = time_iters(&dflt);   // the geometry the operator had
   }
   StencilGeom best_sg = sg0;
+  int best_target = A->stencil_target;
   int best_pv = pv0;
   best = dflt;
   for (size_t c = 0; !rc && c < geoms.size(); ++c) {
     S->sg = geoms[c];
     double t = 0.0;
     rc = time_iters(&t);
-    if (!rc && t < best) { best = t; best_sg = geoms[c]; }
+    if (!rc && t < best) { best = t; best_sg = geoms[c]; best_target = targets[c]; }
   }
   S->sg = best_sg;
   for (size_t c = 0; !rc && c < pvs.size(); ++c) {
@@ -1396,9 +1403,11 @@ extern "C" int pfk_operator_autotune(pfk_operator A, pfk_precond B, pfk_method m
   cleanup();
   if (rc) return rc;
   A->sg = best_sg;
+  A->stencil_target = best_target;
   A->pv_blocks = best_pv;
   if (out) {
     out->tile_x = best_sg.tx;
+    out->stencil_target = best_target;
     out->stencil_blocks = best_sg.blocks();
     out->vector_blocks = best_pv;
     out->ms_per_iteration = best;

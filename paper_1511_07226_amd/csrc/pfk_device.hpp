@@ -161,18 +161,22 @@ __device__ __forceinline__ void for_tile_nodes(const G& g, const StencilGeom& sg
 }
 
 // The hot stencil engine, in arithmetic type T.  A workgroup walks its tile
-// up the z-axis.  Each node's input value u = in(flat index) is formed once:
-// z-neighbours stay in registers (three planes), in-plane neighbours come from
-// an LDS copy of the current plane with a one-node halo (halo values are
-// formed by the first 2(TX+TY) threads).  Values outside the domain are 0
-// (Dirichlet).  For every interior node the engine calls
-// sink(flat index, u, (A u)).
+// up the z-axis.  Each node's input value u = in(flat index) is formed once.
+// z-neighbours stay in registers; in-plane neighbours of u and of the
+// viscosity come from LDS copies of the current plane with a one-node halo
+// (halo values are formed by the first 2(TX+TY) threads).  Every global load
+// is issued one plane step before its value is used: while plane k is
+// computed, plane k+2 (centre column) and the halo of plane k+1 are in
+// flight, so a plane step never waits on its own loads.  Values outside the
+// domain are 0 (Dirichlet); viscosities are read on the whole padded grid.
+// For every interior node the engine calls sink(flat index, u, (A u)).
 template <int TX, class T, class G, class In, class Sink>
 __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& sg, int bid, const In& in,
                                                 Sink& sink) {
   using S = TileShape<TX>;
   constexpr int TY = S::TY;
   __shared__ T su[TY + 2][TX + 2];
+  __shared__ T se[TY + 2][TX + 2];
   const int L = xcd_tile(bid, sg.blocks());
   const int tx = L % sg.tiles_x;
   const int ty = (L / sg.tiles_x) % sg.tiles_y;
@@ -185,14 +189,16 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
   const int k0 = tz * sg.zc;
   const int k1 = min(g.nz, k0 + sg.zc);
   const bool d3 = g.dim == 3;
+  const int kmax = d3 ? g.nz : 0;          // last padded z-plane index minus 1
   const T zero = T(0);
   int jr[2], row[2];
-  bool valid[2];
+  bool valid[2], evalid[2];
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
     row[r] = r0 + r * (TY / 2);
     jr[r] = j0 + row[r];
     valid[r] = i < g.nx && jr[r] < g.ny;
+    evalid[r] = i <= g.nx && jr[r] <= g.ny;   // on the padded grid (boundary ring included)
   }
   // this thread's halo node (if any) and its LDS slot
   const int t = threadIdx.x;
@@ -203,43 +209,68 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
   else if (t < S::HALO) { hi = i0 + TX; hj = j0 + t - 2 * TX - TY; hr = hj - j0 + 1; hc = TX + 1; }
   const bool has_halo = t < S::HALO;
   const bool hvalid = has_halo && hi >= 0 && hi < g.nx && hj >= 0 && hj < g.ny;
+  const bool hevalid = has_halo && hi >= -1 && hi <= g.nx && hj >= -1 && hj <= g.ny;
 
+  auto U = [&](int r, int k) { return (valid[r] && k >= 0 && k < g.nz) ? in(vec_index(g, i, jr[r], k)) : zero; };
+  auto E = [&](int r, int k) {
+    return (evalid[r] && k >= -1 && k <= kmax) ? T(to_real(g.eta[padded_index(g, i, jr[r], k)])) : zero;
+  };
+  auto HU = [&](int k) { return (hvalid && k < g.nz) ? in(vec_index(g, hi, hj, k)) : zero; };
+  auto HE = [&](int k) { return (hevalid && k <= kmax) ? T(to_real(g.eta[padded_index(g, hi, hj, k)])) : zero; };
+
+  // register window: m = k-1, c = k, p = k+1 (u and eta of the centre column)
   T um[2], uc[2], up[2], em[2], ec[2], ep[2];
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
-    um[r] = (valid[r] && d3 && k0 > 0) ? in(vec_index(g, i, jr[r], k0 - 1)) : zero;
-    uc[r] = (valid[r] && k0 < k1) ? in(vec_index(g, i, jr[r], k0)) : zero;
-    em[r] = (valid[r] && d3) ? T(to_real(g.eta[padded_index(g, i, jr[r], k0 - 1)])) : zero;
-    ec[r] = valid[r] ? T(to_real(g.eta[padded_index(g, i, jr[r], k0)])) : zero;
+    um[r] = d3 ? U(r, k0 - 1) : zero;
+    uc[r] = k0 < k1 ? U(r, k0) : zero;
+    up[r] = d3 ? U(r, k0 + 1) : zero;
+    em[r] = d3 ? E(r, k0 - 1) : zero;
+    ec[r] = E(r, k0);
+    ep[r] = d3 ? E(r, k0 + 1) : zero;
   }
+  T hu = HU(k0), he = HE(k0);
   for (int k = k0; k < k1; ++k) {
+    // in flight during this step: plane k+2 of the column, the halo of plane k+1
+    T upp[2], epp[2];
+    const bool more = k + 1 < k1;
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-      up[r] = (valid[r] && k + 1 < g.nz) ? in(vec_index(g, i, jr[r], k + 1)) : zero;
-      ep[r] = (valid[r] && d3) ? T(to_real(g.eta[padded_index(g, i, jr[r], k + 1)])) : zero;
+      upp[r] = (d3 && more) ? U(r, k + 2) : zero;
+      epp[r] = (d3 && more) ? E(r, k + 2) : zero;
     }
-    const T hv = hvalid ? in(vec_index(g, hi, hj, k)) : zero;
+    const T hu_n = more ? HU(k + 1) : zero;
+    const T he_n = more ? HE(k + 1) : zero;
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 2; ++r) su[row[r] + 1][xo + 1] = uc[r];
-    if (has_halo) su[hr][hc] = hv;
+    for (int r = 0; r < 2; ++r) {
+      su[row[r] + 1][xo + 1] = uc[r];
+      se[row[r] + 1][xo + 1] = ec[r];
+    }
+    if (has_halo) {
+      su[hr][hc] = hu;
+      se[hr][hc] = he;
+    }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
       if (valid[r]) {
         const int rr = row[r] + 1;
         const long long pc = padded_index(g, i, jr[r], k);
-        const T Au = apply_faces<T>(g, pc, uc[r], ec[r], T(to_real(g.eta[pc + 1])), T(to_real(g.eta[pc - 1])),
-                                    T(to_real(g.eta[pc + g.sy])), T(to_real(g.eta[pc - g.sy])), ep[r], em[r],
-                                    su[rr][xo + 2], su[rr][xo], su[rr + 1][xo + 1], su[rr - 1][xo + 1], up[r],
-                                    um[r]);
+        const T Au = apply_faces<T>(g, pc, uc[r], ec[r], se[rr][xo + 2], se[rr][xo], se[rr + 1][xo + 1],
+                                    se[rr - 1][xo + 1], ep[r], em[r], su[rr][xo + 2], su[rr][xo],
+                                    su[rr + 1][xo + 1], su[rr - 1][xo + 1], up[r], um[r]);
         sink(vec_index(g, i, jr[r], k), uc[r], Au);
       }
       um[r] = uc[r];
       uc[r] = up[r];
+      up[r] = upp[r];
       em[r] = ec[r];
       ec[r] = ep[r];
+      ep[r] = epp[r];
     }
+    hu = hu_n;
+    he = he_n;
   }
 }
 
