@@ -31,6 +31,29 @@ NU = 30
 INNER = 5
 
 
+# HBM traffic of one steady-state k_pipefcg_update launch (256^3, nu = 30):
+# the per-dispatch means of two rocprofv3 --pmc runs (FETCH_SIZE, then
+# WRITE_SIZE, KiB), each scaled by what the same counter reads for a 2 GiB
+# device-to-device copy (FETCH_SIZE reads 1,048,588 KiB for 2,097,152 KiB
+# moved: x2.000; WRITE_SIZE reads 2,097,152: x1.000).  Valid only for the
+# kernel source it was measured on (digest of its device body).
+UPDATE_TRAFFIC = {"body_sha1": "9ab0a32992c5f042", "fetch_kib": 8261065.0, "fetch_scale": 2.0,
+                  "write_kib": 1050810.0, "write_scale": 1.0}
+
+
+def update_traffic_bytes():
+    """Measured bytes per launch of k_pipefcg_update, or None when its source
+    has changed since the counters were taken."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_1511_07226_amd", "csrc", "pfk_cg.hpp")).read()
+    i = src.index("void pipefcg_update_body(")
+    j = src.index("k_pipefcg_update(", i)
+    if hashlib.sha1(src[i:j].encode()).hexdigest()[:16] != UPDATE_TRAFFIC["body_sha1"]:
+        return None
+    t = UPDATE_TRAFFIC
+    return round((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0)
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -366,7 +389,30 @@ def trace_summary(trace_csv: str, kernel: str, skip: int) -> str:
     return "\n".join(lines)
 
 
+def pmc_summary(csv_path: str) -> str:
+    """Mean value per dispatch of each hardware counter, per kernel, from a
+    rocprofv3 --pmc counter-collection CSV."""
+    import csv
+    acc = {}
+    with open(csv_path, newline="") as f:
+        for r in csv.DictReader(f):
+            key = (_short_kernel_name(r["Kernel_Name"]), r["Counter_Name"])
+            a = acc.setdefault(key, [0, 0.0, set()])
+            a[1] += float(r["Counter_Value"])
+            a[2].add(r["Dispatch_Id"])
+    lines = [f"{'kernel':48s} {'counter':12s} {'dispatches':>10s} {'mean per dispatch':>18s}"]
+    for (k, c), (_, tot, ids) in sorted(acc.items(), key=lambda kv: -kv[1][1]):
+        lines.append(f"{k[:48]:48s} {c:12s} {len(ids):10d} {tot / max(len(ids), 1):18.1f}")
+    return "\n".join(lines)
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--pmc-summary":
+        sp = argparse.ArgumentParser()
+        sp.add_argument("--pmc-summary", required=True, help="rocprofv3 *_counter_collection.csv")
+        a = sp.parse_args()
+        print(pmc_summary(a.pmc_summary))
+        return
     if len(sys.argv) > 1 and sys.argv[1] == "--trace-summary":
         sp = argparse.ArgumentParser()
         sp.add_argument("--trace-summary", required=True, help="rocprofv3 *_kernel_trace.csv")
@@ -384,6 +430,9 @@ def main():
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the FP64 PIPEFCG/FCG pair (for profiler runs)")
     ap.add_argument("--profile-iters", type=int, default=10)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a 2 GiB device-to-device copy three times (the reference kernel "
+                         "for calibrating hardware byte counters)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
@@ -397,6 +446,14 @@ def main():
     import paper_1511_07226_amd as pfk
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        src = torch.full((1 << 28,), 1.0, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
     log("generating the 256^3 sinker workload")
     prob = gen.config_problem("cfgM", seed=0)
     N = prob.N
@@ -534,7 +591,8 @@ def main():
                                f"7-point FP64, nu_max={NU}, B = {INNER}-step Jacobi-PCG (global), rtol=0 steady state",
                    "unknowns": N, "method": main_m, "nu_max": NU, "inner_its": INNER},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": update_traffic_bytes() if main_m == "pipefcg" else None,
                      "kernel": upd_name, "avg_ms": round(avg_ms, 4),
                      "algorithmic_bytes_per_launch": upd_bytes},
         "cpu_baseline": cpu,
