@@ -105,6 +105,9 @@ typedef struct {
                               (a blocking reduction); turns graphs off               */
   int max_restarts;        /* breakdown / residual-gap restarts allowed               */
   int force_breakdown_at;  /* test hook: force a breakdown at this iteration (-1 off) */
+  int persistent;          /* batches only: 1 runs each pfk_batch_step as one cooperative
+                              launch whose phases are separated by grid barriers (no
+                              kernel boundaries); 0 one launch per phase (default)    */
 } pfk_solve_opts;
 
 typedef struct {

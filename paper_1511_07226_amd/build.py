@@ -23,6 +23,9 @@ FLAGS = [
     "-shared",
     # packed FP32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit multiply-add contraction: every kernel that shares a device
+    # body (single, batched, persistent) then rounds identically
+    "-ffp-contract=off",
     "-I" + os.path.join(ROOT, "include"),
     "-Wall",
     "-Wno-unused-function",

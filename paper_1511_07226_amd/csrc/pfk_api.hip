@@ -201,6 +201,7 @@ extern "C" void pfk_default_opts(pfk_solve_opts* o) {
   o->host_sync = 0;
   o->max_restarts = 10;
   o->force_breakdown_at = -1;
+  o->persistent = 0;
 }
 
 extern "C" int pfk_operator_create(int dim, const int64_t n[3], const double* eta, const double* face_vel,
@@ -1442,6 +1443,8 @@ struct pfk_batch_s {
   int tot[kBpCount] = {};
   bool dirty = true;
   hipGraphExec_t graph = nullptr;
+  GridBarrier* bar = nullptr;             // persistent form: grid barrier state
+  int coop_grid = 0;                      // its workgroup count (0: not yet sized)
 };
 
 namespace {
@@ -1590,6 +1593,51 @@ void enqueue_batch_iteration(pfk_batch_s* T) {
   }
 }
 
+// The persistent kernel for this batch's method / inner solve / dimension.
+using KpFn = void (*)(const BSys*, const int*, int, int, int, int, int, GridBarrier*);
+template <int M>
+KpFn kp_pick(int pc, int d3) {
+  if (pc == 0) return d3 ? (KpFn)kp_batch<M, 0, 1> : (KpFn)kp_batch<M, 0, 0>;
+  if (pc == 1) return d3 ? (KpFn)kp_batch<M, 1, 1> : (KpFn)kp_batch<M, 1, 0>;
+  return d3 ? (KpFn)kp_batch<M, 2, 1> : (KpFn)kp_batch<M, 2, 0>;
+}
+
+KpFn kp_kernel(const pfk_batch_s* T) {
+  const int pc = T->pc_kind == kPcBlockPcg ? (T->fp32 ? 2 : 1) : 0;
+  const int d3 = T->dim == 3;
+  if (T->method == PFK_PIPEFCG) return kp_pick<PFK_PIPEFCG>(pc, d3);
+  if (T->method == PFK_FCG) return kp_pick<PFK_FCG>(pc, d3);
+  return kp_pick<PFK_PIPEFGMRES>(pc, d3);
+}
+
+// `iters` iterations of every running member in one cooperative launch.  The
+// grid holds as many workgroups as can be resident at once (a multiple of 8,
+// so a work item and its workgroup sit on the same XCD), capped by the work.
+int batch_persistent(pfk_batch_s* T, int iters) {
+  KpFn fn = kp_kernel(T);
+  if (!T->bar) {
+    HIPCHK(hipMalloc(&T->bar, sizeof(GridBarrier)));
+  }
+  int dev = 0, ncu = 0, per_cu = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, kBlock, 0));
+  const int most = std::max(T->tot[kBpVec], std::max(T->tot[kBpSten], T->tot[kBpBlk]));
+  int G = std::min(per_cu * ncu, std::max(8, (most + 7) / 8 * 8));
+  G = G / 8 * 8;
+  if (G < 8) return fail(PFK_ERR_HIP, "persistent launch: no resident workgroups");
+  T->coop_grid = G;
+  HIPCHK(hipMemsetAsync(T->bar, 0, sizeof(GridBarrier), T->s1));
+  const int n = (int)T->rows.size();
+  const BSys* sys = T->d_sys;
+  const int* off = T->d_off;
+  int tv = T->tot[kBpVec], ts = T->tot[kBpSten], tb = T->tot[kBpBlk];
+  void* args[] = {(void*)&sys, (void*)&off, (void*)&n, (void*)&tv, (void*)&ts, (void*)&tb, (void*)&iters,
+                  (void*)&T->bar};
+  HIPCHK(hipLaunchCooperativeKernel((const void*)fn, dim3(G), dim3(kBlock), args, 0, T->s1));
+  return PFK_OK;
+}
+
 }  // namespace
 
 extern "C" void pfk_batch_destroy(pfk_batch T) {
@@ -1602,6 +1650,7 @@ extern "C" void pfk_batch_destroy(pfk_batch T) {
   if (T->d_off) (void)hipFree(T->d_off);
   if (T->d_stat) (void)hipFree(T->d_stat);
   if (T->h_stat) (void)hipHostFree(T->h_stat);
+  if (T->bar) (void)hipFree(T->bar);
   for (hipEvent_t e : {T->ev_fork, T->ev_join, T->ev_user, T->ev_done})
     if (e) (void)hipEventDestroy(e);
   if (T->s1) (void)hipStreamDestroy(T->s1);
@@ -1691,6 +1740,13 @@ extern "C" int pfk_batch_step(pfk_batch T, int iters) {
   if (T->rows.empty()) return PFK_OK;
   HIPCHK(hipEventRecord(T->ev_user, T->user));
   HIPCHK(hipStreamWaitEvent(T->s1, T->ev_user, 0));
+  if (T->opts.persistent) {
+    int rc = batch_persistent(T, iters);
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(T->ev_done, T->s1));
+    HIPCHK(hipStreamWaitEvent(T->user, T->ev_done, 0));
+    return PFK_OK;
+  }
   const int gi = T->opts.graph_iters;
   int done = 0;
   if (T->opts.use_graph && iters >= gi) {
@@ -1729,6 +1785,11 @@ extern "C" int pfk_batch_poll(pfk_batch T, int* finished, int cap, int* nfinishe
     LAUNCH(kb_gather_status, (n + kBlock - 1) / kBlock, T->s1, (const BSys*)T->d_sys, n, T->d_stat);
     HIPCHK(hipMemcpyAsync(T->h_stat, T->d_stat, sizeof(int) * 2 * n, hipMemcpyDeviceToHost, T->s1));
     HIPCHK(hipStreamSynchronize(T->s1));
+  }
+  if (T->bar) {
+    GridBarrier hb{};
+    HIPCHK(hipMemcpy(&hb, T->bar, sizeof(GridBarrier), hipMemcpyDeviceToHost));
+    if (hb.abort) return fail(PFK_ERR_HIP, "persistent launch: a grid barrier timed out");
   }
   for (int r = 0; r < n; ++r) {
     auto& mb = T->mem[T->rows[r]];

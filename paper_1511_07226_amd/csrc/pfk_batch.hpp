@@ -166,3 +166,177 @@ __global__ void __launch_bounds__(kBlock) kb_gather_status(const BSys* sys, int 
 }
 
 }  // namespace pfk
+
+namespace pfk {
+
+// ---- persistent form ----------------------------------------------------------
+// One cooperative launch runs `iters` outer iterations of every member: the
+// phases are separated by a grid barrier instead of kernel boundaries, and
+// inside a phase the workgroups take the phase's work items (the concatenated
+// per-member ranges of the phased form) round robin.  The reduction finish of
+// the PIPE methods shares a phase with the preconditioner, so it costs no
+// barrier of its own; FCG's two finishes each sit between two barriers.
+//
+// Barrier: two-level arrival (one counter per XCD slot, workgroup b arriving
+// on slot b mod 8, whose last arrival arrives at the top counter) and a
+// generation word in device memory.  Stores of the phase are ordered before
+// the arrival by the workgroup barrier (which waits for each wave's stores)
+// and an agent-scope release fence; the waiting side polls the generation
+// with relaxed loads (no cache invalidation per poll, so waiting workgroups do
+// not disturb the ones still working) and acquires once it changes.  The wait
+// is bounded: a workgroup that polls longer than kBarrierSpins sets `abort`,
+// and every workgroup that sees it leaves the kernel, so every wave exits.
+struct GridBarrier {
+  unsigned slot[8][16];   // arrival counters, one 64-byte line each
+  unsigned top;
+  unsigned gen;
+  int abort;
+  int pad;
+};
+constexpr long long kBarrierSpins = 1LL << 24;   // ~1 s with the 64-cycle sleep
+
+__device__ __forceinline__ bool grid_barrier(GridBarrier* b, unsigned nblocks) {
+  __shared__ int s_ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    const unsigned g = __hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned lane = blockIdx.x & 7u;
+    // workgroups in this slot: those b < nblocks with b mod 8 == lane (nblocks is a multiple of 8)
+    const unsigned per_slot = nblocks / 8u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // the phase's stores, before arriving
+    bool last = false;
+    const unsigned a = __hip_atomic_fetch_add(&b->slot[lane][0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+    if (a == per_slot) {
+      __hip_atomic_store(&b->slot[lane][0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned t = __hip_atomic_fetch_add(&b->top, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+      last = (t == 8u);
+    }
+    if (last) {
+      __hip_atomic_store(&b->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&b->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      long long spins = 0;
+      while (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        if (__hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || ++spins > kBarrierSpins) {
+          __hip_atomic_store(&b->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the other workgroups' stores of the phase
+    if (__hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+    s_ok = ok;
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+
+// PC: 0 = no inner-solve kernel (NONE, JACOBI), 1 = block PCG in FP64, 2 = in FP32.
+template <int PC, int D3>
+__device__ __forceinline__ void kp_block_items(const BSys* sys, const int* off, int nsys, int tot, int first,
+                                               int stride) {
+  if constexpr (PC != 0) {
+    for (int it = first; it < tot; it += stride) {
+      const int s = batch_find(off, nsys, it);
+      const BSys& d = sys[s];
+      const Blk bk{it - off[s], d.bj_n};
+      if (bk.id >= bk.n) continue;
+      const PcOutDesc& pd = d.pd;
+      if constexpr (PC == 2)
+        block_pcg_body<float, GridM, D3>(bk, d.gm, d.bj_wx, d.bj_wy, d.pc_k, pd.X1, pd.c1, pd.X2, pd.c2,
+                                         (float*)const_cast<void*>(pd.y), d.st);
+      else
+        block_pcg_body<double, Grid, D3>(bk, d.g, d.bj_wx, d.bj_wy, d.pc_k, pd.X1, pd.c1, pd.X2, pd.c2,
+                                         (double*)const_cast<void*>(pd.y), d.st);
+    }
+  }
+}
+
+// Apply F(d, bk) to every work item of a phase this workgroup owns.
+template <class F>
+__device__ __forceinline__ void kp_items(const BSys* sys, const int* off, int nsys, int tot, int which, F&& f) {
+  for (int it = (int)blockIdx.x; it < tot; it += (int)gridDim.x) {
+    const int s = batch_find(off, nsys, it);
+    const BSys& d = sys[s];
+    const int count = which == kBpVec ? d.Pv : d.Ps;
+    const Blk bk{it - off[s], count};
+    if (bk.id >= bk.n) continue;
+    f(d, bk);
+  }
+}
+
+template <int M, int PC, int D3>
+__global__ void __launch_bounds__(kBlock)
+kp_batch(const BSys* sys, const int* offs, int nsys, int tot_vec, int tot_sten, int tot_blk, int iters,
+         GridBarrier* bar) {
+  const int* ov = offs + kBpVec * (nsys + 1);
+  const int* os = offs + kBpSten * (nsys + 1);
+  const int* ob = offs + kBpBlk * (nsys + 1);
+  const unsigned G = gridDim.x;
+  for (int k = 0; k < iters; ++k) {
+    if constexpr (M == PFK_PIPEFCG) {
+      kp_items(sys, ov, nsys, tot_vec, kBpVec, [&](const BSys& d, Blk bk) {
+        pipefcg_update_body(bk, d.N, d.P, d.S, d.Q, d.Z, d.x, d.r, d.u, d.w, d.m, d.n, d.part_main, d.st);
+      });
+      if (!grid_barrier(bar, G)) return;
+      // the reduction finish of every member beside the inner solves
+      for (int s = (int)blockIdx.x; s < nsys; s += (int)G)
+        pipefcg_scalars_body(Blk{0, 1}, sys[s].part_main, sys[s].Pv, sys[s].st, sys[s].hist);
+      kp_block_items<PC, D3>(sys, ob, nsys, tot_blk, (int)((blockIdx.x + G - (unsigned)(nsys % (int)G)) % G), (int)G);
+      if (!grid_barrier(bar, G)) return;
+      kp_items(sys, os, nsys, tot_sten, kBpSten, [&](const BSys& d, Blk bk) {
+        apply_pc_out_body(bk, d.g, d.sg, d.pd, d.u, 1.0, d.m, d.n, 0, nullptr, d.part_b, d.st);
+      });
+      if (!grid_barrier(bar, G)) return;
+    } else if constexpr (M == PFK_FCG) {
+      kp_items(sys, ov, nsys, tot_vec, kBpVec, [&](const BSys& d, Blk bk) {
+        fcg_xr_body(bk, d.N, d.P, d.S, d.x, d.r, d.st);
+      });
+      if (!grid_barrier(bar, G)) return;
+      if constexpr (PC != 0) {
+        kp_block_items<PC, D3>(sys, ob, nsys, tot_blk, (int)blockIdx.x, (int)G);
+        if (!grid_barrier(bar, G)) return;
+      }
+      kp_items(sys, ov, nsys, tot_vec, kBpVec, [&](const BSys& d, Blk bk) {
+        multidot_body(bk, d.N, 0, 1, d.pd, nullptr, d.u, d.r, d.S, d.part_main, d.st);
+      });
+      if (!grid_barrier(bar, G)) return;
+      for (int s = (int)blockIdx.x; s < nsys; s += (int)G)
+        cg_scalars1_body(Blk{0, 1}, 0, sys[s].part_main, sys[s].Pv, sys[s].st, sys[s].hist);
+      if (!grid_barrier(bar, G)) return;
+      kp_items(sys, ov, nsys, tot_vec, kBpVec, [&](const BSys& d, Blk bk) {
+        fcg_maxpy_body(bk, d.N, d.P, d.u, d.st);
+      });
+      if (!grid_barrier(bar, G)) return;
+      kp_items(sys, os, nsys, tot_sten, kBpSten, [&](const BSys& d, Blk bk) {
+        fcg_apply_body(bk, d.g, d.sg, d.P, d.S, d.part_a, d.st);
+      });
+      if (!grid_barrier(bar, G)) return;
+      for (int s = (int)blockIdx.x; s < nsys; s += (int)G)
+        cg_scalars2_body(Blk{0, 1}, 0, 0, sys[s].part_a, sys[s].Ps, sys[s].st);
+      if (!grid_barrier(bar, G)) return;
+    } else {   // PIPEFGMRES
+      kp_items(sys, ov, nsys, tot_vec, kBpVec, [&](const BSys& d, Blk bk) {
+        pgm_update_body(bk, d.N, d.P, d.S, d.Q, d.pd, d.z, d.m, d.part_main, d.st);
+      });
+      if (!grid_barrier(bar, G)) return;
+      for (int s = (int)blockIdx.x; s < nsys; s += (int)G)
+        pgm_scalars_body(Blk{0, 1}, sys[s].part_main, sys[s].Pv, sys[s].st, sys[s].hist);
+      kp_block_items<PC, D3>(sys, ob, nsys, tot_blk, (int)((blockIdx.x + G - (unsigned)(nsys % (int)G)) % G), (int)G);
+      if (!grid_barrier(bar, G)) return;
+      kp_items(sys, os, nsys, tot_sten, kBpSten, [&](const BSys& d, Blk bk) {
+        apply_pc_out_body(bk, d.g, d.sg, d.pd, nullptr, 0.0, nullptr, d.z, 0, nullptr, d.part_b, d.st);
+      });
+      if (!grid_barrier(bar, G)) return;
+      kp_items(sys, ov, nsys, tot_vec, kBpVec, [&](const BSys& d, Blk bk) {
+        gm_update_x_body(bk, d.N, d.S, d.x0, d.x, d.st);
+      });
+      if (!grid_barrier(bar, G)) return;
+    }
+  }
+}
+
+}  // namespace pfk

@@ -63,10 +63,11 @@ CASES = [("pipefcg", "block_jacobi_pcg", 0, False), ("pipefcg", "block_jacobi_pc
          ("pipefgmres", "block_jacobi_pcg", 1, True), ("fcg", "none", 0, False)]
 
 
+@pytest.mark.parametrize("persistent", [0, 1], ids=["phased", "persistent"])
 @pytest.mark.parametrize("case", CASES, ids=[f"{m}-{k}-{'mixed' if p else 'fp64'}" for m, k, p, _ in CASES])
-def test_members_identical_to_single_solves(pfk, case):
+def test_members_identical_to_single_solves(pfk, case, persistent):
     method, kind, prec, conv = case
-    _say("batch identity", case)
+    _say("batch identity", case, "persistent" if persistent else "phased")
     mem = _members(pfk, kind, prec, conv, tilings=[(64, 2048, 32), (32, 64, 7), (64, 5, 100)])
     sig = {}
     if method == "pipefgmres":
@@ -79,7 +80,7 @@ def test_members_identical_to_single_solves(pfk, case):
         singles.append((info, _host(x)))
     # PIPEFGMRES members estimate their own shift when they are added (the
     # same estimate pfk.estimate_sigma makes)
-    T = pfk.Batch(method, mmax=20, capacity=8, graph_iters=5)
+    T = pfk.Batch(method, mmax=20, capacity=8, graph_iters=5, persistent=persistent)
     xs, slots = {}, {}
     for i in range(len(mem)):
         p, A, B = mem[i]
@@ -168,7 +169,8 @@ def test_batch_edge_cases(pfk):
         pfk.Batch("gcr", mmax=10, capacity=2)
 
 
-def test_solve_batched_uneven_systems(pfk):
+@pytest.mark.parametrize("persistent", [0, 1], ids=["phased", "persistent"])
+def test_solve_batched_uneven_systems(pfk, persistent):
     # (a grid of one or two blocks per axis with strong contrast makes the block
     # solve nearly the global few-step CG, under which PIPEFCG stagnates in the
     # oracle too, e.g. n = 8 or 11 with 15 inclusions; FP32 inner sweeps push
@@ -180,7 +182,7 @@ def test_solve_batched_uneven_systems(pfk):
     bs = [_dev(p.b) for p, _, _ in mem]
     xs = [_dev(np.zeros(A.N)) for _, A, _ in mem]
     code, infos = pfk.solve_batched([A for _, A, _ in mem], [B for _, _, B in mem], "pipefcg", bs, xs,
-                                    rtol=1e-8, maxit=2000, mmax=20)
+                                    rtol=1e-8, maxit=2000, mmax=20, persistent=persistent)
     for n, info in zip(sizes, infos):
         print(f"  n={n}: {info.status_name} its {info.iterations} restarts {info.restarts} "
               f"true rel {info.true_rel_resid:.2e}")
