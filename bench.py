@@ -150,11 +150,32 @@ def time_to_solution(pfk, torch, A, B, method, b, rtol, maxit, mmax, **opts):
             "solves_per_s": round(1.0 / dt, 4)}, x
 
 
+def persistent_rate(pfk, torch, A, B, method, b, steps, warmup):
+    """Steady-state iterations/s of one system run by the persistent batched
+    form (one cooperative launch per step, grid barriers between phases)."""
+    T = pfk.Batch(method, mmax=NU, capacity=1, persistent=1)
+    x = torch.zeros_like(b)
+    T.add(A, B, b, x, rtol=0.0, maxit=warmup + steps + 50)
+    T.step(warmup)
+    T.poll()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    _, running = T.poll()
+    T.close()
+    if running != 1:
+        raise RuntimeError(f"persistent {method}: the system stopped during timing")
+    return steps / dt
+
+
 def size_sweep(pfk, torch, steps=40):
     """PIPEFCG against FCG per outer iteration on single systems of growing size
-    (block-Jacobi inner solve, FP64, nu_max 30): where the one device-side
-    reduction per iteration matters more than the pipelined method's extra
-    window traffic."""
+    (block-Jacobi inner solve, FP64, nu_max 30), in the graph-launched form and
+    in the persistent form (grid barriers instead of kernel boundaries): where
+    the one device-side reduction per iteration matters more than the
+    pipelined method's extra window traffic."""
     import gen
     out = {}
     for dim, n in ((2, 64), (3, 16), (3, 32), (3, 64), (3, 128)):
@@ -167,7 +188,9 @@ def size_sweep(pfk, torch, steps=40):
             S, dt = time_steps(pfk, torch, A, B, method, b, steps, NU + 2)
             S.close()
             row[method] = round(steps / dt, 1)
+            row[method + "_persistent"] = round(persistent_rate(pfk, torch, A, B, method, b, steps, NU + 2), 1)
         row["pipelined_over_unpipelined"] = round(row["pipefcg"] / row["fcg"], 3)
+        row["pipelined_over_unpipelined_persistent"] = round(row["pipefcg_persistent"] / row["fcg_persistent"], 3)
         out[f"{dim}d_n{n}"] = row
     return out
 

@@ -23,9 +23,10 @@ FLAGS = [
     "-shared",
     # packed FP32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    # no implicit multiply-add contraction: every kernel that shares a device
-    # body (single, batched, persistent) then rounds identically
-    "-ffp-contract=off",
+    # multiply-adds are fused only inside a source expression (a*b + c), never
+    # across statements after inlining: every kernel that shares a device body
+    # (single, batched, persistent) then rounds identically
+    "-ffp-contract=on",
     "-I" + os.path.join(ROOT, "include"),
     "-Wall",
     "-Wno-unused-function",
