@@ -381,7 +381,7 @@ def _short_kernel_name(name: str) -> str:
     return head.split("::")[-1] + (("<" + tmpl.replace("pfk::", "")) if sep else "")
 
 
-def trace_summary(trace_csv: str, kernel: str, skip: int) -> str:
+def trace_summary(trace_csv: str, kernel: str, skip: int, last: int = 0) -> str:
     """Per-kernel statistics from a rocprofv3 kernel trace (CSV), plus the
     steady-state mean of `kernel`: its dispatches after the first `skip` (the
     window fills during the first nu iterations of a solve, so the early
@@ -402,27 +402,37 @@ def trace_summary(trace_csv: str, kernel: str, skip: int) -> str:
     for name, (c, tot) in sorted(stats.items(), key=lambda kv: -kv[1][1])[:20]:
         lines.append(f"{name[:48]:48s} {c:7d} {tot / c / 1e6:10.4f} {tot / 1e6:10.2f}")
     durs = [ns for _, name, ns in rows if name == kernel]
-    steady = durs[skip:]
+    steady = durs[-last:] if last > 0 else durs[skip:]
+    what = f"the last {last}" if last > 0 else f"dispatch {skip + 1} on"
     if steady:
         steady_sorted = sorted(steady)
-        lines.append(f"\n{kernel}: {len(durs)} dispatches; steady state (dispatch {skip + 1} on): "
+        lines.append(f"\n{kernel}: {len(durs)} dispatches; steady state ({what}): "
                      f"{len(steady)} dispatches, mean {sum(steady) / len(steady) / 1e6:.4f} ms, "
                      f"median {steady_sorted[len(steady) // 2] / 1e6:.4f} ms, "
                      f"min {steady_sorted[0] / 1e6:.4f} ms, max {steady_sorted[-1] / 1e6:.4f} ms")
     return "\n".join(lines)
 
 
-def pmc_summary(csv_path: str) -> str:
+def pmc_summary(csv_path: str, kernel: str = "", last: int = 0) -> str:
     """Mean value per dispatch of each hardware counter, per kernel, from a
-    rocprofv3 --pmc counter-collection CSV."""
+    rocprofv3 --pmc counter-collection CSV; for `kernel`, only its last `last`
+    dispatches when last > 0 (the steady-state ones of the profiled run)."""
     import csv
-    acc = {}
+    rows = []
     with open(csv_path, newline="") as f:
         for r in csv.DictReader(f):
-            key = (_short_kernel_name(r["Kernel_Name"]), r["Counter_Name"])
-            a = acc.setdefault(key, [0, 0.0, set()])
-            a[1] += float(r["Counter_Value"])
-            a[2].add(r["Dispatch_Id"])
+            rows.append((int(r["Dispatch_Id"]), _short_kernel_name(r["Kernel_Name"]), r["Counter_Name"],
+                         float(r["Counter_Value"])))
+    rows.sort()
+    if kernel and last > 0:
+        ids = sorted({d for d, k, _, _ in rows if k == kernel})[-last:]
+        keep = set(ids)
+        rows = [r for r in rows if r[1] != kernel or r[0] in keep]
+    acc = {}
+    for d, k, c, v in rows:
+        a = acc.setdefault((k, c), [0, 0.0, set()])
+        a[1] += v
+        a[2].add(d)
     lines = [f"{'kernel':48s} {'counter':12s} {'dispatches':>10s} {'mean per dispatch':>18s}"]
     for (k, c), (_, tot, ids) in sorted(acc.items(), key=lambda kv: -kv[1][1]):
         lines.append(f"{k[:48]:48s} {c:12s} {len(ids):10d} {tot / max(len(ids), 1):18.1f}")
@@ -433,16 +443,19 @@ def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--pmc-summary":
         sp = argparse.ArgumentParser()
         sp.add_argument("--pmc-summary", required=True, help="rocprofv3 *_counter_collection.csv")
+        sp.add_argument("--kernel", default="")
+        sp.add_argument("--last", type=int, default=0)
         a = sp.parse_args()
-        print(pmc_summary(a.pmc_summary))
+        print(pmc_summary(a.pmc_summary, a.kernel, a.last))
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--trace-summary":
         sp = argparse.ArgumentParser()
         sp.add_argument("--trace-summary", required=True, help="rocprofv3 *_kernel_trace.csv")
         sp.add_argument("--kernel", default="k_pipefcg_update")
         sp.add_argument("--skip", type=int, default=NU + 1)
+        sp.add_argument("--last", type=int, default=0, help="use the last N dispatches instead of --skip")
         a = sp.parse_args()
-        print(trace_summary(a.trace_summary, a.kernel, a.skip))
+        print(trace_summary(a.trace_summary, a.kernel, a.skip, a.last))
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -456,6 +469,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a 2 GiB device-to-device copy three times (the reference kernel "
                          "for calibrating hardware byte counters)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch geometry")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="time only the batched workload (after the headline pair)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
@@ -483,13 +499,24 @@ def main():
     A = pfk.Operator(prob.dim, prob.n, prob.eta)
     B = pfk.Precond(A, "jacobi_pcg", INNER)
     b = torch.as_tensor(prob.b).cuda()
+    tuning = {}
+
+    def tune(method):
+        # each method is timed with the launch geometry tuned for it
+        if not args.no_autotune:
+            tuning[method] = A.autotune(B, method, mmax=NU, reps=3)
+            log(f"{method} tiling: {tuning[method]}")
 
     def rate(method, Bx, **opts):
+        t = tuning.get(method)
+        if t is not None:
+            A.set_tiling(t["tile_x"], t["stencil_target"], t["vector_blocks"])
         S, dt = time_steps(pfk, torch, A, Bx, method, b, args.steps, args.warmup, **opts)
         return S, {"it_per_s": round(args.steps / dt, 3), "ms_per_step": round(dt / args.steps * 1e3, 4)}
 
     results, sessions = {}, {}
     for method in ("pipefcg", "fcg"):
+        tune(method)
         log(f"timing {method}: {args.warmup} warm-up + {args.steps} steps")
         sessions[method], results[method] = rate(method, B)
         log(f"{method}: {results[method]['it_per_s']:.1f} it/s")
@@ -513,6 +540,9 @@ def main():
     eff = {m: it_bytes[m] * results[m]["it_per_s"] / 1e9 for m in results}
 
     extra = {}
+    if args.batched_only:
+        args.headline_only = True
+        extra["batched_64"] = batched_bench(pfk, torch, args.steps, args.warmup)
     if not args.headline_only:
         # unpipelined baseline with a blocking (host-synchronised) reduction
         log("timing fcg host-sync")
@@ -612,7 +642,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{main_m.upper()} 256^3 variable-viscosity sinker (20 spheres, eta 1e4/1), "
                                f"7-point FP64, nu_max={NU}, B = {INNER}-step Jacobi-PCG (global), rtol=0 steady state",
-                   "unknowns": N, "method": main_m, "nu_max": NU, "inner_its": INNER},
+                   "unknowns": N, "method": main_m, "nu_max": NU, "inner_its": INNER,
+                   "launch_geometry": tuning.get(main_m, "default")},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": update_traffic_bytes() if main_m == "pipefcg" else None,

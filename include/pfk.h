@@ -269,16 +269,25 @@ int pfk_batch_poll(pfk_batch T, int* finished, int cap, int* nfinished, int* nru
 /* A member's pfk_solve_info (synchronising); returns its final pfk_status, or
  * PFK_NOT_CONVERGED while it still runs. */
 int pfk_batch_info(pfk_batch T, int slot, pfk_solve_info* info);
+/* Test hook for the persistent form: the number of polls after which a
+ * workgroup waiting at a grid barrier gives up and aborts the launch (default
+ * about a second's worth).  An aborted launch leaves every member's state
+ * undefined and makes the next pfk_batch_poll return PFK_ERR_HIP; the batch
+ * should then be destroyed. */
+int pfk_batch_set_barrier_limit(pfk_batch T, long long polls);
 /* Release a member (its slot becomes free; its x keeps the last iterate). */
 int pfk_batch_remove(pfk_batch T, int slot);
 /* Workspace bytes of one member (the same as pfk_workspace_bytes). */
 size_t pfk_batch_workspace_bytes(pfk_operator A, pfk_precond B, pfk_method method, int mmax, int maxit);
 /* Solve `count` systems as one batch until every one has ended; infos[i] (may
- * be NULL) receives each system's info.  Returns PFK_OK if all converged, else
- * the first error or PFK_NOT_CONVERGED. */
+ * be NULL) receives each system's info.  workspace: NULL (the library allocates)
+ * or one device buffer holding every member's workspace in order, each
+ * pfk_workspace_bytes(A[i], B[i], method, mmax, maxit) rounded up to 256 bytes.
+ * Returns PFK_OK if all converged, else the first error or PFK_NOT_CONVERGED. */
 int pfk_solve_batched(int count, const pfk_operator* A, const pfk_precond* B, pfk_method method,
                       const double* const* b, double* const* x, const double* rtol, int maxit, int mmax,
-                      void* stream, const pfk_solve_opts* opts, pfk_solve_info* infos);
+                      void* workspace, size_t ws_bytes, void* stream, const pfk_solve_opts* opts,
+                      pfk_solve_info* infos);
 
 /* ---- serving -------------------------------------------------------------
  * A request queue in front of continuously refilled batches (no paper

@@ -37,6 +37,7 @@ EXPORTED = [
     "pfk_operator_set_tiling", "pfk_operator_get_tiling", "pfk_operator_autotune",
     "pfk_batch_create", "pfk_batch_destroy", "pfk_batch_add", "pfk_batch_step", "pfk_batch_poll",
     "pfk_batch_info", "pfk_batch_remove", "pfk_batch_workspace_bytes", "pfk_solve_batched",
+    "pfk_batch_set_barrier_limit",
     "pfk_server_create", "pfk_server_destroy", "pfk_server_submit", "pfk_server_progress",
     "pfk_server_result", "pfk_server_stats",
 ]
@@ -142,6 +143,7 @@ def lib():
         "pfk_batch_poll": (C.c_int, [vp, C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
         "pfk_batch_info": (C.c_int, [vp, C.c_int, C.POINTER(_Info)]),
         "pfk_batch_remove": (C.c_int, [vp, C.c_int]),
+        "pfk_batch_set_barrier_limit": (C.c_int, [vp, C.c_longlong]),
         "pfk_batch_workspace_bytes": (C.c_size_t, [vp, vp, C.c_int, C.c_int, C.c_int]),
         "pfk_server_create": (C.c_int, [C.POINTER(ServerConfig), vp, C.POINTER(vp)]),
         "pfk_server_destroy": (None, [vp]),
@@ -151,8 +153,8 @@ def lib():
         "pfk_server_result": (C.c_int, [vp, C.c_longlong, C.POINTER(_Info)]),
         "pfk_server_stats": (C.c_int, [vp, C.POINTER(ServerStatus)]),
         "pfk_solve_batched": (C.c_int, [C.c_int, C.POINTER(vp), C.POINTER(vp), C.c_int, C.POINTER(vp),
-                                        C.POINTER(vp), C.POINTER(C.c_double), C.c_int, C.c_int, vp,
-                                        C.POINTER(SolveOpts), C.POINTER(_Info)]),
+                                        C.POINTER(vp), C.POINTER(C.c_double), C.c_int, C.c_int, vp, C.c_size_t,
+                                        vp, C.POINTER(SolveOpts), C.POINTER(_Info)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -419,6 +421,10 @@ class Batch:
         _check(code, allow_positive=True)
         return _to_info(code, info, hist)
 
+    def set_barrier_limit(self, polls: int):
+        """Test hook: polls before a persistent launch's grid barrier gives up."""
+        _check(lib().pfk_batch_set_barrier_limit(self._h, int(polls)))
+
     def remove(self, slot: int):
         _check(lib().pfk_batch_remove(self._h, int(slot)))
         self._keep.pop(slot, None)
@@ -437,8 +443,8 @@ class Batch:
             pass
 
 
-def solve_batched(As, Bs, method: str, bs, xs, rtol=1e-8, maxit: int = 500, mmax: int = 30, stream=None,
-                  **opts):
+def solve_batched(As, Bs, method: str, bs, xs, rtol=1e-8, maxit: int = 500, mmax: int = 30, workspace=None,
+                  stream=None, **opts):
     """Solve every system (lists of operators, preconditioners, b and x tensors)
     in one batch.  Returns (status code, [SolveInfo])."""
     n = len(As)
@@ -456,8 +462,11 @@ def solve_batched(As, Bs, method: str, bs, xs, rtol=1e-8, maxit: int = 500, mmax
         infos[i].history = hist.ctypes.data_as(C.POINTER(C.c_double))
         infos[i].history_cap = maxit + 1
         hists.append(hist)
+    wsp, wsb = (None, 0)
+    if workspace is not None:
+        wsp, wsb = workspace.data_ptr(), workspace.numel() * workspace.element_size()
     code = lib().pfk_solve_batched(n, arrA, arrB, METHODS[method], arrb, arrx, arrr, int(maxit), int(mmax),
-                                   _stream_ptr(stream), C.byref(o), infos)
+                                   wsp, wsb, _stream_ptr(stream), C.byref(o), infos)
     _check(code, allow_positive=True)
     return code, [_to_info(infos[i].status, infos[i], hists[i]) for i in range(n)]
 

@@ -1444,6 +1444,8 @@ struct pfk_batch_s {
   bool dirty = true;
   hipGraphExec_t graph = nullptr;
   GridBarrier* bar = nullptr;             // persistent form: grid barrier state
+  GridBarrier* h_bar = nullptr;           // pinned initial value of it
+  long long barrier_limit = kBarrierSpins;
   int coop_grid = 0;                      // its workgroup count (0: not yet sized)
 };
 
@@ -1617,6 +1619,7 @@ int batch_persistent(pfk_batch_s* T, int iters) {
   KpFn fn = kp_kernel(T);
   if (!T->bar) {
     HIPCHK(hipMalloc(&T->bar, sizeof(GridBarrier)));
+    HIPCHK(hipHostMalloc(&T->h_bar, sizeof(GridBarrier), hipHostMallocDefault));
   }
   int dev = 0, ncu = 0, per_cu = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -1627,7 +1630,10 @@ int batch_persistent(pfk_batch_s* T, int iters) {
   G = G / 8 * 8;
   if (G < 8) return fail(PFK_ERR_HIP, "persistent launch: no resident workgroups");
   T->coop_grid = G;
-  HIPCHK(hipMemsetAsync(T->bar, 0, sizeof(GridBarrier), T->s1));
+  HIPCHK(hipStreamSynchronize(T->s1));   // the pinned initial value is reused by every launch
+  std::memset(T->h_bar, 0, sizeof(GridBarrier));
+  T->h_bar->limit = T->barrier_limit;
+  HIPCHK(hipMemcpyAsync(T->bar, T->h_bar, sizeof(GridBarrier), hipMemcpyHostToDevice, T->s1));
   const int n = (int)T->rows.size();
   const BSys* sys = T->d_sys;
   const int* off = T->d_off;
@@ -1651,6 +1657,7 @@ extern "C" void pfk_batch_destroy(pfk_batch T) {
   if (T->d_stat) (void)hipFree(T->d_stat);
   if (T->h_stat) (void)hipHostFree(T->h_stat);
   if (T->bar) (void)hipFree(T->bar);
+  if (T->h_bar) (void)hipHostFree(T->h_bar);
   for (hipEvent_t e : {T->ev_fork, T->ev_join, T->ev_user, T->ev_done})
     if (e) (void)hipEventDestroy(e);
   if (T->s1) (void)hipStreamDestroy(T->s1);
@@ -1851,6 +1858,12 @@ extern "C" int pfk_batch_info(pfk_batch T, int slot, pfk_solve_info* info) {
   return mb.state == 2 ? code : PFK_NOT_CONVERGED;
 }
 
+extern "C" int pfk_batch_set_barrier_limit(pfk_batch T, long long polls) {
+  if (!T || polls < 0) return fail(PFK_ERR_ARG, "bad argument");
+  T->barrier_limit = polls;
+  return PFK_OK;
+}
+
 extern "C" int pfk_batch_remove(pfk_batch T, int slot) {
   if (!T || slot < 0 || slot >= (int)T->mem.size() || T->mem[slot].state == 0)
     return fail(PFK_ERR_ARG, "no such member");
@@ -1870,14 +1883,30 @@ extern "C" size_t pfk_batch_workspace_bytes(pfk_operator A, pfk_precond B, pfk_m
 
 extern "C" int pfk_solve_batched(int count, const pfk_operator* A, const pfk_precond* B, pfk_method method,
                                  const double* const* b, double* const* x, const double* rtol, int maxit, int mmax,
-                                 void* stream, const pfk_solve_opts* opts, pfk_solve_info* infos) {
+                                 void* workspace, size_t ws_bytes, void* stream, const pfk_solve_opts* opts,
+                                 pfk_solve_info* infos) {
   if (count < 1 || !A || !B || !b || !x || !rtol) return fail(PFK_ERR_ARG, "null argument");
+  // member i's part of a caller workspace: its own workspace size, 256-byte aligned, in order
+  std::vector<size_t> part((size_t)count, 0);
+  size_t need = 0;
+  for (int i = 0; i < count; ++i) {
+    if (!A[i] || !B[i]) return fail(PFK_ERR_ARG, "null operator or preconditioner");
+    part[i] = align_up(pfk_workspace_bytes(A[i], B[i], method, mmax, maxit));
+    if (part[i] == 0) return fail(PFK_ERR_ARG, "workspace size");
+    need += part[i];
+  }
+  if (workspace && ws_bytes < need)
+    return fail(PFK_ERR_ARG, "workspace too small: need " + std::to_string(need) + " bytes");
   pfk_batch T = nullptr;
   int rc = pfk_batch_create(method, mmax, count, stream, opts, &T);
   if (rc) return rc;
   std::vector<int> slot(count, -1);
-  for (int i = 0; i < count && !rc; ++i)
-    rc = pfk_batch_add(T, A[i], B[i], b[i], x[i], rtol[i], maxit, nullptr, 0, &slot[i]);
+  size_t off = 0;
+  for (int i = 0; i < count && !rc; ++i) {
+    void* w = workspace ? (void*)((char*)workspace + off) : nullptr;
+    rc = pfk_batch_add(T, A[i], B[i], b[i], x[i], rtol[i], maxit, w, workspace ? part[i] : 0, &slot[i]);
+    off += part[i];
+  }
   int running = count;
   const int gi = T->opts.graph_iters;
   while (!rc && running > 0) {

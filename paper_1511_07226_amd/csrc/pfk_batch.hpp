@@ -184,7 +184,7 @@ namespace pfk {
 // and an agent-scope release fence; the waiting side polls the generation
 // with relaxed loads (no cache invalidation per poll, so waiting workgroups do
 // not disturb the ones still working) and acquires once it changes.  The wait
-// is bounded: a workgroup that polls longer than kBarrierSpins sets `abort`,
+// is bounded: a workgroup that polls more than `limit` times sets `abort`,
 // and every workgroup that sees it leaves the kernel, so every wave exits.
 struct GridBarrier {
   unsigned slot[8][16];   // arrival counters, one 64-byte line each
@@ -192,6 +192,7 @@ struct GridBarrier {
   unsigned gen;
   int abort;
   int pad;
+  long long limit;        // polls before a wait gives up
 };
 constexpr long long kBarrierSpins = 1LL << 24;   // ~1 s with the 64-cycle sleep
 
@@ -218,7 +219,7 @@ __device__ __forceinline__ bool grid_barrier(GridBarrier* b, unsigned nblocks) {
     } else {
       long long spins = 0;
       while (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
-        if (__hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || ++spins > kBarrierSpins) {
+        if (__hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || ++spins > b->limit) {
           __hip_atomic_store(&b->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           ok = 0;
           break;

@@ -80,12 +80,13 @@ k_apply(Grid g, StencilGeom sg, const double* __restrict__ x, double* __restrict
 // O = c3*X3 + B(v) at every node, N = A O.  With `dots`: partials <O, R>, <O, N>.
 // Used for u_0/w_0 and m_0/n_0 of PIPEFCG's start-up and for m_i, n_i in its
 // loop (m_i = u_i + B(w_i - r_i), n_i = A m_i).
-__device__ __forceinline__ void apply_pc_out_body(Blk bk, Grid g, StencilGeom sg, PcOutDesc pd, const double* X3, double c3,
-               double* __restrict__ O, double* __restrict__ Nout,
-               int dots, const double* __restrict__ R, double* part, SolveState* st) {
-  if (read_status(st) != kRunning) return;
+template <int K, int F32>
+__device__ __forceinline__ void apply_pc_out_t(Blk bk, const Grid& g, const StencilGeom& sg, const PcOutDesc& pd,
+                                               const double* X3, double c3, double* __restrict__ O,
+                                               double* __restrict__ Nout, int dots, const double* __restrict__ R,
+                                               double* part, SolveState* st) {
   const PcOut pc = make_pc_out(pd, &st->pc);
-  auto in = [&](long long t) { double v = pc(t); if (X3 != nullptr) v += c3 * X3[t]; return v; };
+  auto in = [&](long long t) { double v = pc.at<K, F32>(t); if (X3 != nullptr) v += c3 * X3[t]; return v; };
   double acc[2] = {0.0, 0.0};
   auto sink = [&](long long idx, double mc, double nv) {
     if (O != nullptr) O[idx] = mc;
@@ -97,6 +98,23 @@ __device__ __forceinline__ void apply_pc_out_body(Blk bk, Grid g, StencilGeom sg
   };
   stencil_march<double>(g, sg, bk.id, in, sink);
   if (dots) block_partials<2>(acc, 2, part, sg.blocks(), bk.id);
+}
+// The inner solve's output kind and storage are fixed per instantiation for
+// the two inner-CG forms (the hot cases); the others decide at run time.
+__device__ __forceinline__ void apply_pc_out_body(Blk bk, Grid g, StencilGeom sg, PcOutDesc pd, const double* X3,
+                                                  double c3, double* __restrict__ O, double* __restrict__ Nout,
+                                                  int dots, const double* __restrict__ R, double* part,
+                                                  SolveState* st) {
+  if (read_status(st) != kRunning) return;
+  if (pd.kind == kPcBlockPcg) {
+    if (pd.fp32) apply_pc_out_t<kPcBlockPcg, 1>(bk, g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
+    else apply_pc_out_t<kPcBlockPcg, 0>(bk, g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
+  } else if (pd.kind == kPcJacobiPcg) {
+    if (pd.fp32) apply_pc_out_t<kPcJacobiPcg, 1>(bk, g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
+    else apply_pc_out_t<kPcJacobiPcg, 0>(bk, g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
+  } else {
+    apply_pc_out_t<-1, 0>(bk, g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
+  }
 }
 __global__ void __launch_bounds__(kBlock)
 k_apply_pc_out(Grid g, StencilGeom sg, PcOutDesc pd, const double* X3, double c3,

@@ -170,13 +170,23 @@ __device__ __forceinline__ void for_tile_nodes(const G& g, const StencilGeom& sg
 // flight, so a plane step never waits on its own loads.  Values outside the
 // domain are 0 (Dirichlet); viscosities are read on the whole padded grid.
 // For every interior node the engine calls sink(flat index, u, (A u)).
+// LDS of the stencil engine: one buffer shared by every instantiation (tile
+// widths, arithmetic types, callers) -- a static in a non-template function is
+// a single object, so a kernel holds it once however many variants it uses.
+constexpr int kStencilLds = 2 * (TileShape<64>::TY + 2) * (64 + 2) * 8;
+static_assert(kStencilLds >= 2 * (TileShape<32>::TY + 2) * (32 + 2) * 8, "LDS sized for the widest tile");
+__device__ __forceinline__ char* stencil_lds() {
+  __shared__ __attribute__((aligned(16))) char buf[kStencilLds];
+  return buf;
+}
+
 template <int TX, class T, class G, class In, class Sink>
 __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& sg, int bid, const In& in,
                                                 Sink& sink) {
   using S = TileShape<TX>;
   constexpr int TY = S::TY;
-  __shared__ T su[TY + 2][TX + 2];
-  __shared__ T se[TY + 2][TX + 2];
+  T (*su)[TX + 2] = reinterpret_cast<T (*)[TX + 2]>(stencil_lds());
+  T (*se)[TX + 2] = reinterpret_cast<T (*)[TX + 2]>(stencil_lds() + sizeof(T) * (TY + 2) * (TX + 2));
   const int L = xcd_tile(bid, sg.blocks());
   const int tx = L % sg.tiles_x;
   const int ty = (L / sg.tiles_x) % sg.tiles_y;
@@ -351,8 +361,16 @@ __device__ __forceinline__ double block_sum_column(const double* part, int P, in
 __device__ __forceinline__ void block_sum_columns(const double* part, int P, int ncol, double* out) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int c = wid; c < ncol; c += kWaves) {
-    double s = 0.0;
-    for (int b = lane; b < P; b += 64) s += part[(long long)c * P + b];
+    // eight independent partial sums per lane keep eight loads in flight
+    const double* col = part + (long long)c * P;
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int b = lane;
+    for (; b + 7 * 64 < P; b += 8 * 64) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[q] += col[b + q * 64];
+    }
+    for (; b < P; b += 64) a[0] += col[b];
+    double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     s = wave_sum(s);
     if (lane == 0) out[c] = s;
   }

@@ -104,6 +104,21 @@ struct PcOut {
       }
     }
   }
+  // The same value with the kind K and the inner storage type fixed at
+  // compile time (K < 0: decided at run time); the arithmetic is that of
+  // operator(), so every caller rounds alike.
+  template <int K, int F32>
+  __device__ __forceinline__ double at(long long t) const {
+    if constexpr (K == kPcBlockPcg) {
+      return F32 ? ldw<float>(y, t) : ldw<double>(y, t);
+    } else if constexpr (K == kPcJacobiPcg) {
+      double r = use_y ? (F32 ? ldw<float>(y, t) : ldw<double>(y, t)) : 0.0;
+      if (add_p) r += alpha * (F32 ? ldw<float>(pk, t) : ldw<double>(pk, t));
+      return r;
+    } else {
+      return (*this)(t);
+    }
+  }
 };
 
 // Finish the inner solve (PCG: alpha_k from the last A_k partials; GMRES:

@@ -1,0 +1,65 @@
+"""Host-side logic of bench.py that needs no GPU: the multi-GPU refusal, the
+byte models, and the rocprofv3 CSV summaries (on small hand-made files)."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stdout + r.stderr
+
+
+def test_update_bytes_model():
+    # (4 nu + 14) vectors of 8 bytes per unknown: the window MAXPYs (4 nu reads),
+    # u, w, m, n, r, x reads and p, s, q, z, x, r, u, w writes
+    assert bench.window_update_bytes("pipefcg", 30, 1000) == (4 * 30 + 14) * 8 * 1000
+    assert bench.iteration_bytes("pipefcg", 30, 5, 10) > bench.iteration_bytes("fcg", 30, 5, 10)
+
+
+def test_traffic_guard_matches_current_kernel_source():
+    # the stored counter reading belongs to the update kernel as it is
+    assert bench.update_traffic_bytes() == pytest.approx(17.99e9, rel=1e-3)
+
+
+def _write(path, header, rows):
+    with open(path, "w") as f:
+        f.write(",".join(f'"{h}"' for h in header) + "\n")
+        for r in rows:
+            f.write(",".join(f'"{v}"' if isinstance(v, str) else str(v) for v in r) + "\n")
+
+
+def test_trace_summary_steady_state(tmp_path):
+    header = ["Kind", "Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"]
+    rows = []
+    t = 0
+    for d in range(1, 11):        # ramp: 5 short dispatches, then 5 long ones
+        dur = 1000 if d <= 5 else 3000
+        rows.append(["KERNEL_DISPATCH", d, "pfk::k_pipefcg_update(long long, double*)", t, t + dur])
+        t += dur + 10
+    rows.append(["KERNEL_DISPATCH", 11, "void pfk::k_pcg_a<double, pfk::GridT<double, double> >(int)", t, t + 500])
+    p = tmp_path / "trace.csv"
+    _write(p, header, rows)
+    out = bench.trace_summary(str(p), "k_pipefcg_update", 5)
+    assert "k_pipefcg_update" in out and "k_pcg_a<double, GridT<double, double> >" in out
+    assert "5 dispatches, mean 0.0030 ms" in out
+
+
+def test_pmc_summary_means(tmp_path):
+    header = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    rows = [[1, "pfk::k_pipefcg_update(long long)", "FETCH_SIZE", 100.0],
+            [2, "pfk::k_pipefcg_update(long long)", "FETCH_SIZE", 300.0],
+            [3, "__amd_rocclr_copyBuffer", "FETCH_SIZE", 50.0]]
+    p = tmp_path / "pmc.csv"
+    _write(p, header, rows)
+    out = bench.pmc_summary(str(p))
+    line = next(l for l in out.splitlines() if l.startswith("k_pipefcg_update"))
+    assert line.split()[-2:] == ["2", "200.0"]

@@ -191,3 +191,38 @@ def test_solve_batched_uneven_systems(pfk, persistent):
         Ao = oracle.StencilOperator(3, p.n, p.eta)
         xh = _host(x)
         assert info.converged and np.linalg.norm(p.b - Ao.apply(xh)) <= 1e-8 * np.linalg.norm(p.b)
+
+
+def test_persistent_barrier_timeout_is_reported(pfk):
+    # a grid barrier that may not poll gives up at the first wait: the launch must
+    # end (every workgroup leaves) and the next poll must report the failure
+    _say("persistent barrier timeout")
+    mem = _members(pfk, "block_jacobi_pcg", 0, sizes=[24, 32])
+    T = pfk.Batch("pipefcg", mmax=20, capacity=2, persistent=1)
+    for p, A, B in mem:
+        T.add(A, B, _dev(p.b), _dev(np.zeros(A.N)), rtol=1e-8, maxit=100)
+    T.set_barrier_limit(0)
+    T.step(3)
+    with pytest.raises(RuntimeError):
+        T.poll()
+    T.close()
+
+
+def test_solve_batched_caller_workspace(pfk):
+    _say("solve_batched caller workspace")
+    import torch
+    mem = _members(pfk, "block_jacobi_pcg", 0, sizes=[12, 20, 16])
+    As, Bs = [A for _, A, _ in mem], [B for _, _, B in mem]
+    bs = [_dev(p.b) for p, _, _ in mem]
+    sizes = [(pfk.workspace_bytes(A, B, "pipefcg", 20, 300) + 255) // 256 * 256 for A, B in zip(As, Bs)]
+    ws = torch.empty(sum(sizes), dtype=torch.uint8, device="cuda")
+    xa = [_dev(np.zeros(A.N)) for A in As]
+    xb = [_dev(np.zeros(A.N)) for A in As]
+    ca, ia = pfk.solve_batched(As, Bs, "pipefcg", bs, xa, rtol=1e-8, maxit=300, mmax=20, workspace=ws)
+    cb, ib = pfk.solve_batched(As, Bs, "pipefcg", bs, xb, rtol=1e-8, maxit=300, mmax=20)
+    assert ca == cb == 0
+    for u, v, p, q in zip(xa, xb, ia, ib):
+        assert np.array_equal(_host(u), _host(v)) and np.array_equal(p.history, q.history)
+    small = torch.empty(sum(sizes) - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(RuntimeError):
+        pfk.solve_batched(As, Bs, "pipefcg", bs, xa, rtol=1e-8, maxit=300, mmax=20, workspace=small)
