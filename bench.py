@@ -31,14 +31,14 @@ NU = 30
 INNER = 5
 
 
-# HBM traffic of one steady-state k_pipefcg_update launch (256^3, nu = 30):
-# the per-dispatch means of two rocprofv3 --pmc runs (FETCH_SIZE, then
-# WRITE_SIZE, KiB), each scaled by what the same counter reads for a 2 GiB
+# HBM traffic of one steady-state k_pipefcg_update launch (256^3, nu = 30,
+# autotuned geometry): the per-dispatch means over the last 7 dispatches of
+# two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB), each scaled by what the same counter reads for a 2 GiB
 # device-to-device copy (FETCH_SIZE reads 1,048,588 KiB for 2,097,152 KiB
 # moved: x2.000; WRITE_SIZE reads 2,097,152: x1.000).  Valid only for the
 # kernel source it was measured on (digest of its device body).
-UPDATE_TRAFFIC = {"body_sha1": "9ab0a32992c5f042", "fetch_kib": 8261065.0, "fetch_scale": 2.0,
-                  "write_kib": 1050810.0, "write_scale": 1.0}
+UPDATE_TRAFFIC = {"body_sha1": "9ab0a32992c5f042", "fetch_kib": 8260449.7, "fetch_scale": 2.0,
+                  "write_kib": 1050804.5, "write_scale": 1.0}
 
 
 def update_traffic_bytes():
@@ -257,8 +257,9 @@ def batched_bench(pfk, torch, steps, warmup, count=64):
     out["pipefcg_one_at_a_time_iters_per_s"] = round(1e3 / seq_ms, 2)
     out["batching_speedup"] = round(out["pipefcg_batch_iters_per_s"] * seq_ms / 1e3, 3)
     # bytes of one batched PIPEFCG iteration: window update (4 nu + 14 vectors), the
-    # block solve (v in: 2 vectors, eta 2 B, y out 4 B), m, n (u, y, eta in; m, n out)
-    per_unknown = (4 * NU4 + 14) * 8 + (2 * 8 + 2 + 4) + (8 + 4 + 2 + 2 * 8)
+    # block solve (v in: 2 vectors, BF16 eta 2 B, FP32 y out 4 B), m, n (u, FP32 y,
+    # FP64 eta in; m, n out)
+    per_unknown = (4 * NU4 + 14) * 8 + (2 * 8 + 2 + 4) + (8 + 4 + 8 + 2 * 8)
     out["algorithmic_GBps_pipefcg"] = round(per_unknown * total_n * out["pipefcg_batch_iters_per_s"] / 1e9, 1)
     out["algorithmic_bytes_per_unknown_iteration"] = per_unknown
     log("batched pipefcg: solving all systems to rtol 1e-8")
@@ -381,7 +382,7 @@ def _short_kernel_name(name: str) -> str:
     return head.split("::")[-1] + (("<" + tmpl.replace("pfk::", "")) if sep else "")
 
 
-def trace_summary(trace_csv: str, kernel: str, skip: int, last: int = 0) -> str:
+def trace_summary(trace_csv: str, kernel: str, skip: int, last: int = 0, count: int = 0) -> str:
     """Per-kernel statistics from a rocprofv3 kernel trace (CSV), plus the
     steady-state mean of `kernel`: its dispatches after the first `skip` (the
     window fills during the first nu iterations of a solve, so the early
@@ -402,8 +403,12 @@ def trace_summary(trace_csv: str, kernel: str, skip: int, last: int = 0) -> str:
     for name, (c, tot) in sorted(stats.items(), key=lambda kv: -kv[1][1])[:20]:
         lines.append(f"{name[:48]:48s} {c:7d} {tot / c / 1e6:10.4f} {tot / 1e6:10.2f}")
     durs = [ns for _, name, ns in rows if name == kernel]
-    steady = durs[-last:] if last > 0 else durs[skip:]
-    what = f"the last {last}" if last > 0 else f"dispatch {skip + 1} on"
+    if last > 0:
+        steady, what = durs[-last:], f"the last {last}"
+    elif count > 0:
+        steady, what = durs[skip:skip + count], f"dispatches {skip + 1}..{skip + count}"
+    else:
+        steady, what = durs[skip:], f"dispatch {skip + 1} on"
     if steady:
         steady_sorted = sorted(steady)
         lines.append(f"\n{kernel}: {len(durs)} dispatches; steady state ({what}): "
@@ -454,8 +459,9 @@ def main():
         sp.add_argument("--kernel", default="k_pipefcg_update")
         sp.add_argument("--skip", type=int, default=NU + 1)
         sp.add_argument("--last", type=int, default=0, help="use the last N dispatches instead of --skip")
+        sp.add_argument("--count", type=int, default=0, help="with --skip: only this many dispatches")
         a = sp.parse_args()
-        print(trace_summary(a.trace_summary, a.kernel, a.skip, a.last))
+        print(trace_summary(a.trace_summary, a.kernel, a.skip, a.last, a.count))
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
