@@ -37,8 +37,8 @@ INNER = 5
 # device-to-device copy (FETCH_SIZE reads 1,048,588 KiB for 2,097,152 KiB
 # moved: x2.000; WRITE_SIZE reads 2,097,152: x1.000).  Valid only for the
 # kernel source it was measured on (digest of its device body).
-UPDATE_TRAFFIC = {"body_sha1": "9ab0a32992c5f042", "fetch_kib": 8260449.7, "fetch_scale": 2.0,
-                  "write_kib": 1050804.5, "write_scale": 1.0}
+UPDATE_TRAFFIC = {"body_sha1": "64540aeaf4544d08", "fetch_kib": 8261903.9, "fetch_scale": 2.0,
+                  "write_kib": 1050801.9, "write_scale": 1.0}
 
 
 def update_traffic_bytes():
@@ -608,7 +608,7 @@ def main():
             opts = {"shift_sigma": sigma} if method == "pipefgmres" else {}
             dt = time_cycles(pfk, torch, A3, B3, method, b3, cycles, NU, **opts)
             conv[method] = {"it_per_s": round(cycles * NU / dt, 3), "ms_per_step": round(dt / (cycles * NU) * 1e3, 4)}
-        for method in ("pipegcr", "gcr"):
+        for method in ("pipegcr", "pipegcr_w", "gcr"):
             log(f"timing {method}")
             S, dt = time_steps(pfk, torch, A3, B3, method, b3, args.steps, args.warmup)
             S.close()

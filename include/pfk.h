@@ -62,7 +62,9 @@ typedef enum {
   PFK_GCR = 2,        /* Alg. 9                                                */
   PFK_PIPEGCR = 3,    /* Alg. 11: one reduction, overlapped with B             */
   PFK_FGMRES = 4,     /* Alg. 13                                               */
-  PFK_PIPEFGMRES = 5  /* Alg. 15: one reduction, overlapped with B and A       */
+  PFK_PIPEFGMRES = 5, /* Alg. 15: one reduction, overlapped with B and A       */
+  PFK_PIPEGCR_W = 6   /* Alg. 12: PIPEGCR with w = A u recurred (a fourth window,
+                         no A u per iteration), overlapped with B and A         */
 } pfk_method;
 
 typedef enum {

@@ -17,8 +17,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(HERE, "libpfk.so")
 
 FCG, PIPEFCG, GCR, PIPEGCR, FGMRES, PIPEFGMRES = range(6)
+PIPEGCR_W = 6
 METHODS = {"fcg": FCG, "pipefcg": PIPEFCG, "gcr": GCR, "pipegcr": PIPEGCR,
-           "fgmres": FGMRES, "pipefgmres": PIPEFGMRES}
+           "fgmres": FGMRES, "pipefgmres": PIPEFGMRES, "pipegcr_w": PIPEGCR_W}
 PC_NONE, PC_JACOBI, PC_JACOBI_PCG, PC_JACOBI_GMRES, PC_BLOCK_JACOBI_PCG = range(5)
 PC_KINDS = {"none": PC_NONE, "jacobi": PC_JACOBI, "jacobi_pcg": PC_JACOBI_PCG,
             "jacobi_gmres": PC_JACOBI_GMRES, "block_jacobi_pcg": PC_BLOCK_JACOBI_PCG}

@@ -405,7 +405,7 @@ void window_slots(int method, int mmax, int* slots) {
   switch (method) {
     case PFK_FCG: case PFK_GCR: slots[W_P] = slots[W_S] = mmax; break;
     case PFK_PIPEGCR: slots[W_P] = slots[W_S] = slots[W_Q] = mmax; break;
-    case PFK_PIPEFCG: slots[W_P] = slots[W_S] = slots[W_Q] = slots[W_Z] = mmax; break;
+    case PFK_PIPEFCG: case PFK_PIPEGCR_W: slots[W_P] = slots[W_S] = slots[W_Q] = slots[W_Z] = mmax; break;
     case PFK_FGMRES: slots[W_P] = mmax + 1; slots[W_S] = mmax; break;
     case PFK_PIPEFGMRES: slots[W_P] = slots[W_S] = slots[W_Q] = mmax + 1; break;
     default: break;
@@ -687,10 +687,13 @@ void enqueue_start(pfk_session_s* S, hipStream_t s) {
       LAUNCH(k_init_test, 1, s, S->part(PT_A), S->Ps(), S->st, S->hist);
       enqueue_cg_body(S, s, 1);
       break;
-    case PFK_PIPEFCG: {
-      // u_0 = B(r_0), w_0 = A u_0, gamma_0 = <u_0,r_0>, delta_0 = <u_0,w_0>
+    case PFK_PIPEFCG:
+    case PFK_PIPEGCR_W: {
+      // u_0 = B(r_0), w_0 = A u_0; PIPEFCG: gamma_0 = <u_0,r_0>, eta_0 = <u_0,w_0>;
+      // PIPEGCR_w (p_0 = u_0, s_0 = w_0): gamma_0 = <r_0,s_0>, eta_0 = <s_0,s_0>
+      const int dots = S->method == PFK_PIPEGCR_W ? 2 : 1;
       PcOutDesc pd = enqueue_pc(S, s, S->vec(V_R), 1.0, nullptr, 0.0);
-      LAUNCH(k_apply_pc_out, S->Ps(), s, g, S->sg, pd, (const double*)nullptr, 0.0, S->vec(V_U), S->vec(V_W), 1,
+      LAUNCH(k_apply_pc_out, S->Ps(), s, g, S->sg, pd, (const double*)nullptr, 0.0, S->vec(V_U), S->vec(V_W), dots,
              (const double*)S->vec(V_R), S->part(PT_B), S->st);
       // m_0 = B(w_0), n_0 = A m_0
       pd = enqueue_pc(S, s, S->vec(V_W), 1.0, nullptr, 0.0);
@@ -749,10 +752,11 @@ void enqueue_iteration(pfk_session_s* S) {
       LAUNCH(k_fcg_xr, S->Pv(), s1, A->N, S->win(W_P), S->win(W_S), S->x, S->vec(V_R), (const SolveState*)S->st);
       enqueue_cg_body(S, s1, 0);
       break;
-    case PFK_PIPEFCG: {
+    case PFK_PIPEFCG:
+    case PFK_PIPEGCR_W: {
       LAUNCH(k_pipefcg_update, S->Pv(), s1, A->N, S->win(W_P), S->win(W_S), S->win(W_Q), S->win(W_Z), S->x,
              S->vec(V_R), S->vec(V_U), S->vec(V_W), (const double*)S->vec(V_M), (const double*)S->vec(V_N),
-             S->part(PT_MAIN), (const SolveState*)S->st);
+             S->part(PT_MAIN), (const SolveState*)S->st, S->method == PFK_PIPEGCR_W ? 1 : 0);
       // fork: finish the reduction on s2 while s1 applies B and A
       (void)hipEventRecord(S->ev_fork, s1);
       (void)hipStreamWaitEvent(s2, S->ev_fork, 0);
@@ -922,7 +926,7 @@ static int session_make(pfk_operator A, pfk_precond B, pfk_method method, const 
   *out = nullptr;
   if (!A || !B || !b || !x) return fail(PFK_ERR_ARG, "null argument");
   if (B->A != A) return fail(PFK_ERR_ARG, "preconditioner was made for another operator");
-  if (method < PFK_FCG || method > PFK_PIPEFGMRES) return fail(PFK_ERR_ARG, "unknown method");
+  if (method < PFK_FCG || method > PFK_PIPEGCR_W) return fail(PFK_ERR_ARG, "unknown method");
   if (mmax < 1 || mmax > kNuMax) return fail(PFK_ERR_ARG, "mmax must be 1..64");
   if (maxit < 0) return fail(PFK_ERR_ARG, "maxit must be >= 0");
   if (!(rtol >= 0.0)) return fail(PFK_ERR_ARG, "rtol must be >= 0");
@@ -1275,7 +1279,7 @@ extern "C" int pfk_operator_autotune(pfk_operator A, pfk_precond B, pfk_method m
                                      void* stream, pfk_tuning* out) {
   if (!A || !B) return fail(PFK_ERR_ARG, "null argument");
   if (B->A != A) return fail(PFK_ERR_ARG, "preconditioner was made for another operator");
-  if (method < PFK_FCG || method > PFK_PIPEFGMRES) return fail(PFK_ERR_ARG, "unknown method");
+  if (method < PFK_FCG || method > PFK_PIPEGCR_W) return fail(PFK_ERR_ARG, "unknown method");
   if (mmax < 1 || mmax > kNuMax) return fail(PFK_ERR_ARG, "mmax must be 1..64");
   if (reps < 1) reps = 5;
   const int nx = (int)A->n[0], ny = (int)A->n[1], nz = (int)A->n[2];

@@ -54,7 +54,7 @@ __global__ void __launch_bounds__(kBlock) kb_pipefcg_update(const BSys* sys, con
   const BSys& d = sys[s];
   const Blk bk{(int)blockIdx.x - off[s], d.Pv};
   if (bk.id >= bk.n) return;   // padding of the range
-  pipefcg_update_body(bk, d.N, d.P, d.S, d.Q, d.Z, d.x, d.r, d.u, d.w, d.m, d.n, d.part_main, d.st);
+  pipefcg_update_body(bk, d.N, d.P, d.S, d.Q, d.Z, d.x, d.r, d.u, d.w, d.m, d.n, d.part_main, d.st, 0);
 }
 
 __global__ void __launch_bounds__(kBlock) kb_pipefcg_scalars(const BSys* sys) {
@@ -280,7 +280,7 @@ kp_batch(const BSys* sys, const int* offs, int nsys, int tot_vec, int tot_sten, 
   for (int k = 0; k < iters; ++k) {
     if constexpr (M == PFK_PIPEFCG) {
       kp_items(sys, ov, nsys, tot_vec, kBpVec, [&](const BSys& d, Blk bk) {
-        pipefcg_update_body(bk, d.N, d.P, d.S, d.Q, d.Z, d.x, d.r, d.u, d.w, d.m, d.n, d.part_main, d.st);
+        pipefcg_update_body(bk, d.N, d.P, d.S, d.Q, d.Z, d.x, d.r, d.u, d.w, d.m, d.n, d.part_main, d.st, 0);
       });
       if (!grid_barrier(bar, G)) return;
       // the reduction finish of every member beside the inner solves

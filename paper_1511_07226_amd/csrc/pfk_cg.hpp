@@ -77,7 +77,8 @@ k_apply(Grid g, StencilGeom sg, const double* __restrict__ x, double* __restrict
   stencil_march<double>(g, sg, in, sink);
 }
 
-// O = c3*X3 + B(v) at every node, N = A O.  With `dots`: partials <O, R>, <O, N>.
+// O = c3*X3 + B(v) at every node, N = A O.  With dots = 1: partials <O, R>,
+// <O, N>; with dots = 2: <N, R>, <N, N>.
 // Used for u_0/w_0 and m_0/n_0 of PIPEFCG's start-up and for m_i, n_i in its
 // loop (m_i = u_i + B(w_i - r_i), n_i = A m_i).
 template <int K, int F32>
@@ -91,9 +92,12 @@ __device__ __forceinline__ void apply_pc_out_t(Blk bk, const Grid& g, const Sten
   auto sink = [&](long long idx, double mc, double nv) {
     if (O != nullptr) O[idx] = mc;
     Nout[idx] = nv;
-    if (dots) {
+    if (dots == 1) {            // <O, R>, <O, N>
       acc[0] += mc * R[idx];
       acc[1] += mc * nv;
+    } else if (dots == 2) {     // <N, R>, <N, N>
+      acc[0] += nv * R[idx];
+      acc[1] += nv * nv;
     }
   };
   stencil_march<double>(g, sg, bk.id, in, sink);
@@ -174,7 +178,10 @@ __device__ __forceinline__ void st2(double* p, long long e, double2 v, bool full
 //   q_j = m_j + sum beta q_d,  z_j = n_j + sum beta z_d      (written to slot j)
 //   x += alpha p_j, r -= alpha s_j, u -= alpha q_j, w -= alpha z_j
 // and the single reduction of iteration j+1 on the updated vectors:
-//   gamma = <u,r>, delta = <u,w>, rho = <r,r>, <u, s_d> for d in window(j+1).
+//   gamma = <u,r>, delta = <u,w>, rho = <r,r>, <u, s_d> for d in window(j+1)
+// (PIPEFCG), or with w in place of u (red_w: PIPEGCR_w, Alg. 12, whose
+// vectors and windows are PIPEFCG's with w recurred: gamma = <r,w>,
+// delta = <w,w>, <w, s_d>).
 // The window dots reuse the s_d loads of the MAXPY.  Each lane owns two
 // consecutive nodes (16-byte accesses); the per-direction dot is summed over
 // the wave at once and accumulated in LDS, so the register footprint does not
@@ -182,7 +189,7 @@ __device__ __forceinline__ void st2(double* p, long long e, double2 v, bool full
 __device__ __forceinline__ void pipefcg_update_body(Blk bk, long long N, Window P, Window S, Window Q, Window Z,
                  double* __restrict__ x, double* __restrict__ r, double* __restrict__ u,
                  double* __restrict__ w, const double* __restrict__ m, const double* __restrict__ n,
-                 double* part, const SolveState* st) {
+                 double* part, const SolveState* st, int red_w) {
   if (read_status(st) != kRunning) return;
   __shared__ double s_beta[kNuMax];
   __shared__ long long s_off[kNuMax];
@@ -220,9 +227,10 @@ __device__ __forceinline__ void pipefcg_update_body(Blk bk, long long N, Window 
       q.x += b * qv.x; q.y += b * qv.y;
       z.x += b * zv.x; z.y += b * zv.y;
     }
-    double2 un = make_double2(u0.x - alpha * q.x, u0.y - alpha * q.y);
+    const double2 un = make_double2(u0.x - alpha * q.x, u0.y - alpha * q.y);
     const double2 wn = make_double2(w0.x - alpha * z.x, w0.y - alpha * z.y);
-    if (!act) un = make_double2(0.0, 0.0);
+    double2 a = red_w ? wn : un;                 // the reduction's first operand
+    if (!act) a = make_double2(0.0, 0.0);
     double2 sv = w0;
 #pragma unroll 4
     for (int t = 0; t < nu; ++t) {
@@ -230,7 +238,7 @@ __device__ __forceinline__ void pipefcg_update_body(Blk bk, long long N, Window 
       const double2 sd = ld2(S.base, s_off[t] + e, full);
       sv.x += b * sd.x; sv.y += b * sd.y;
       if (t >= shift) {
-        const double d = wave_sum(un.x * sd.x + un.y * sd.y);
+        const double d = wave_sum(a.x * sd.x + a.y * sd.y);
         if (lane == 0) s_dot[wid][t - shift] += d;
       }
     }
@@ -247,10 +255,10 @@ __device__ __forceinline__ void pipefcg_update_body(Blk bk, long long N, Window 
     st2(u, e, un, full);
     st2(w, e, wn, full);
     st2(r, e, rn, full);
-    gam += un.x * rn.x + un.y * rn.y;
-    del += un.x * wn.x + un.y * wn.y;
+    gam += a.x * rn.x + a.y * rn.y;
+    del += a.x * wn.x + a.y * wn.y;
     rho += rn.x * rn.x + rn.y * rn.y;
-    dnew += un.x * sv.x + un.y * sv.y;
+    dnew += a.x * sv.x + a.y * sv.y;
   }
   // columns: gamma, delta, rho, then <u, s_d> for d = j+1-nu1 .. j (the last is s_j)
   const int ncol = 3 + nu1;
@@ -276,8 +284,8 @@ __global__ void __launch_bounds__(kBlock)
 k_pipefcg_update(long long N, Window P, Window S, Window Q, Window Z,
                  double* __restrict__ x, double* __restrict__ r, double* __restrict__ u,
                  double* __restrict__ w, const double* __restrict__ m, const double* __restrict__ n,
-                 double* part, const SolveState* st) {
-  pipefcg_update_body(this_blk(), N, P, S, Q, Z, x, r, u, w, m, n, part, st);
+                 double* part, const SolveState* st, int red_w) {
+  pipefcg_update_body(this_blk(), N, P, S, Q, Z, x, r, u, w, m, n, part, st, red_w);
 }
 
 // Scalars of iteration j+1 from the fused reduction: iteration count,

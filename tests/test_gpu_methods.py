@@ -183,3 +183,37 @@ def test_host_sync_rejected_for_pipelined(pfk):
     Bg = pfk.Precond(Ag, "jacobi", 1)
     with pytest.raises(RuntimeError):
         pfk.solve(Ag, Bg, "pipefcg", _dev(prob.b), _dev(np.zeros(256)), host_sync=1)
+
+
+W_CASES = [("conv20", "jacobi", 1), ("conv20", "jacobi_gmres", 5), ("conv20", "block_jacobi_pcg", 4),
+           ("cfg1", "jacobi_pcg", 2)]
+
+
+@pytest.mark.parametrize("case", W_CASES, ids=[f"{c[0]}-{c[1]}" for c in W_CASES])
+def test_pipegcr_w_history_parity_first_20(pfk, case):
+    # Alg. 12: PIPEGCR with w recurred; the same windows as PIPEFCG, reductions on w
+    name, kind, k = case
+    prob = gen.config_problem("cfg1", seed=0) if name == "cfg1" else _conv(20, seed=1)
+    _say("pipegcr_w history", name, kind, k)
+    Ao = oracle.StencilOperator(prob.dim, prob.n, prob.eta, prob.vel)
+    Bo = oracle.make_pc(kind, Ao, k, block=8)
+    ref = oracle.solve("pipegcr_w", Ao, Bo, prob.b, rtol=0.0, maxit=20, nu_max=30)
+    Ag = pfk.Operator(prob.dim, prob.n, prob.eta, prob.vel)
+    Bg = pfk.Precond(Ag, kind, k, block=8)
+    x = _dev(np.zeros(Ao.N))
+    info = pfk.solve(Ag, Bg, "pipegcr_w", _dev(prob.b), x, rtol=0.0, maxit=20, mmax=30)
+    h, hr = info.history, np.array(ref.history)
+    assert len(h) == len(hr) == 21
+    assert (np.abs(h - hr) / np.abs(hr)).max() <= 1e-9
+
+
+def test_pipegcr_w_full_solve_and_ragged(pfk):
+    prob = _conv(20, seed=4)
+    _say("pipegcr_w full solve")
+    ref, info, x, Ao = _parity(pfk, "pipegcr_w", prob, "jacobi", 1, 30, 3000, rtol=1e-8)
+    assert ref.converged and info.converged and info.status == 0
+    assert abs(info.iterations - ref.iterations) <= max(3, ref.iterations // 5)
+    assert np.linalg.norm(prob.b - Ao.apply(x)) <= 1e-8 * np.linalg.norm(prob.b)
+    conv = gen.make_problem(3, 13, 3, 2.0, seed=6, convection=True)     # N = 2197
+    ref, info, x, _ = _parity(pfk, "pipegcr_w", conv, "jacobi_gmres", 3, 30, 15)
+    assert np.allclose(info.history, ref.history, rtol=1e-9)
