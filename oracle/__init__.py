@@ -16,6 +16,9 @@ Everything here is numpy in float64, written from the paper
 * ``precond``  -- Jacobi, k-step Jacobi-PCG and k-step right-Jacobi GMRES
   inner solves (the flexible, nonlinear preconditioners B), plus the noisy
   preconditioner of the section 2.2.1 toy study;
+* ``noise``    -- the counter-based Gaussian generator (Philox4x64-10 and
+  Box-Muller) behind the seeded noisy preconditioner that a GPU solve can
+  reproduce draw for draw;
 * ``krylov``   -- FCG (Alg. 2), PCG (Alg. 3), naive PIPEFCG (Alg. 7),
   PIPEFCG (Alg. 8), GCR (Alg. 9), PIPEGCR (Alg. 11), PIPEGCR_w (Alg. 12),
   FGMRES (Alg. 13) and PIPEFGMRES (Alg. 15), with the truncation rules and
@@ -29,6 +32,7 @@ from .precond import (  # noqa: F401
     identity_pc, jacobi_pc, jacobi_pcg, jacobi_gmres, block_jacobi_pcg, block_operator,
     noisy_pc, make_pc,
 )
+from .noise import philox4x64, box_muller, gauss, CounterNoisyPC  # noqa: F401
 from .krylov import (  # noqa: F401
     Result, truncation_nu, givens_lstsq, solve, estimate_sigma, METHODS,
 )
