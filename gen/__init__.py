@@ -41,6 +41,7 @@ __all__ = [
     "config_problem",
     "batched_problems",
     "toy_diagonal",
+    "study_problem",
     "CONFIGS",
 ]
 
@@ -247,3 +248,22 @@ def toy_diagonal(n: int = 100, cond: float = 5.0):
     lam = 1.0 + (cond - 1.0) * np.arange(n, dtype=np.float64) / (n - 1)
     b = np.ones(n) / math.sqrt(n)
     return lam, b
+
+
+def study_problem(dim: int, n: int, seed: int = 0) -> Problem:
+    """Stencil system for the noisy-preconditioner stagnation study at scale.
+
+    The Figure 1 toy (section 2.2.1) pairs B(r) = r + noise with a spectrum of
+    order one.  Constant viscosity eta = h^2 cancels the stencil's 1/h^2, so
+    the operator is the unscaled Dirichlet graph Laplacian (spectrum inside
+    (0, 4*dim]) and the noise of B(w - r) stays comparable to that of B(r).
+    Returns the system with ``b`` a standard-normal right-hand side and the
+    seeded exact solution ``x_star`` (standard normal) in ``meta``; a caller
+    that needs A x_star = b forms b with its own operator.
+    """
+    g_geo, g_rhs, _ = streams(seed)
+    h = 1.0 / (n + 1)
+    eta = np.full((n + 2,) * dim, h * h, dtype=np.float64)
+    b = rhs(dim, n, g_rhs)
+    x_star = g_geo.standard_normal(n ** dim)
+    return Problem(dim, n, eta, b, None, dict(seed=seed, x_star=x_star, study=True))

@@ -63,8 +63,11 @@ typedef enum {
   PFK_PIPEGCR = 3,    /* Alg. 11: one reduction, overlapped with B             */
   PFK_FGMRES = 4,     /* Alg. 13                                               */
   PFK_PIPEFGMRES = 5, /* Alg. 15: one reduction, overlapped with B and A       */
-  PFK_PIPEGCR_W = 6   /* Alg. 12: PIPEGCR with w = A u recurred (a fourth window,
+  PFK_PIPEGCR_W = 6,  /* Alg. 12: PIPEGCR with w = A u recurred (a fourth window,
                          no A u per iteration), overlapped with B and A         */
+  PFK_PIPEFCG_NAIVE = 7 /* Alg. 7: PIPEFCG with the unstabilised m = B(w) in place
+                         of u + B(w - r); stagnates near a nonlinear B's noise
+                         level (section 2.2.1).  For studying that effect.      */
 } pfk_method;
 
 typedef enum {
@@ -72,10 +75,13 @@ typedef enum {
   PFK_PC_JACOBI = 1,            /* B(v) = D^-1 v, D = diag(A) (linear)               */
   PFK_PC_JACOBI_PCG = 2,        /* k iterations of Jacobi-PCG on A y = v from y = 0  */
   PFK_PC_JACOBI_GMRES = 3,      /* one GMRES(k) cycle on A D^-1 t = v from 0, y = D^-1 t */
-  PFK_PC_BLOCK_JACOBI_PCG = 4   /* k Jacobi-PCG iterations inside every cubic block of
+  PFK_PC_BLOCK_JACOBI_PCG = 4,  /* k Jacobi-PCG iterations inside every cubic block of
                                    `block` nodes per axis (square in 2D), on the block's
                                    principal submatrix with its own scalars: the block
                                    Jacobi of the experiments (section 6.2)             */
+  PFK_PC_NOISY = 5              /* B(v) = v + eta ||v|| g/||g||, g seeded Gaussian noise:
+                                   the toy of section 2.2.1; made by
+                                   pfk_precond_create_noisy only                      */
 } pfk_pc_kind;
 
 typedef enum {
@@ -154,6 +160,21 @@ int pfk_operator_diag_inv(pfk_operator A, double* dinv, void* stream);
  * PFK_ERR_HIP. */
 int pfk_precond_create(pfk_operator A, pfk_pc_kind kind, int inner_its, pfk_precision prec,
                        int block, pfk_precond* out);
+/* The noisy preconditioner of the stagnation study (section 2.2.1, Figure 1):
+ * B(v) = v + eta ||v|| g / ||g|| (v unchanged when ||v|| = 0), with g standard
+ * normal from a counter-based stream: node e of draw d is Box-Muller on
+ * words 0 and 1 of Philox4x64-10 at counter (e, d, 0, 0) and key (seed, 0)
+ * (u1 = (word0 >> 11) + 1, u2 = word1 >> 11, both times 2^-53;
+ * g = sqrt(-2 ln u1) cos(2 pi u2)).  Inside a solve the draws are 0, 1, 2, ...
+ * for the applications the method goes on to use, in its order (start-up
+ * included, counting on across restarts; an application made concurrently
+ * with the reduction that ends the solve by convergence does not count, and
+ * reuses the next index).  PIPEFGMRES's shift estimate, when the library
+ * makes it, draws 0, 1, ... of its own before the solve's count starts.
+ * Standalone pfk_precond_apply calls use the handle's own count, 0, 1, 2, ...
+ * FP64 only; not accepted by batches or the server.
+ * Errors: PFK_ERR_ARG (eta negative or not finite, null pointers), PFK_ERR_OOM. */
+int pfk_precond_create_noisy(pfk_operator A, double eta, uint64_t seed, pfk_precond* out);
 void pfk_precond_destroy(pfk_precond B);
 /* y = B(v) for device vectors (synchronous w.r.t. stream completion of the call). */
 int pfk_precond_apply(pfk_precond B, const double* v, double* y, void* stream);

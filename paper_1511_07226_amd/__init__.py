@@ -7,8 +7,8 @@ streams.  The library must have been built (``python -m
 paper_1511_07226_amd.build``); importing the binding without it raises.
 """
 from .binding import (  # noqa: F401
-    FCG, PIPEFCG, GCR, PIPEGCR, FGMRES, PIPEFGMRES, PIPEGCR_W, METHODS,
-    PC_NONE, PC_JACOBI, PC_JACOBI_PCG, PC_JACOBI_GMRES, PC_BLOCK_JACOBI_PCG, PC_KINDS,
+    FCG, PIPEFCG, GCR, PIPEGCR, FGMRES, PIPEFGMRES, PIPEGCR_W, PIPEFCG_NAIVE, METHODS,
+    PC_NONE, PC_JACOBI, PC_JACOBI_PCG, PC_JACOBI_GMRES, PC_BLOCK_JACOBI_PCG, PC_NOISY, PC_KINDS,
     FP64, FP32_BF16COEF,
     PfkError, Operator, Precond, Session, SolveInfo, SolveOpts, Batch, Tuning, Server,
     solve, solve_batched, workspace_bytes, estimate_sigma, lib, lib_path, EXPORTED,

@@ -18,11 +18,13 @@ _LIB_PATH = os.path.join(HERE, "libpfk.so")
 
 FCG, PIPEFCG, GCR, PIPEGCR, FGMRES, PIPEFGMRES = range(6)
 PIPEGCR_W = 6
+PIPEFCG_NAIVE = 7
 METHODS = {"fcg": FCG, "pipefcg": PIPEFCG, "gcr": GCR, "pipegcr": PIPEGCR,
-           "fgmres": FGMRES, "pipefgmres": PIPEFGMRES, "pipegcr_w": PIPEGCR_W}
-PC_NONE, PC_JACOBI, PC_JACOBI_PCG, PC_JACOBI_GMRES, PC_BLOCK_JACOBI_PCG = range(5)
+           "fgmres": FGMRES, "pipefgmres": PIPEFGMRES, "pipegcr_w": PIPEGCR_W,
+           "pipefcg_naive": PIPEFCG_NAIVE}
+PC_NONE, PC_JACOBI, PC_JACOBI_PCG, PC_JACOBI_GMRES, PC_BLOCK_JACOBI_PCG, PC_NOISY = range(6)
 PC_KINDS = {"none": PC_NONE, "jacobi": PC_JACOBI, "jacobi_pcg": PC_JACOBI_PCG,
-            "jacobi_gmres": PC_JACOBI_GMRES, "block_jacobi_pcg": PC_BLOCK_JACOBI_PCG}
+            "jacobi_gmres": PC_JACOBI_GMRES, "block_jacobi_pcg": PC_BLOCK_JACOBI_PCG, "noisy": PC_NOISY}
 FP64, FP32_BF16COEF = 0, 1
 
 STATUS_NAMES = {0: "ok", 1: "not_converged", -1: "err_arg", -2: "err_oom", -3: "err_hip",
@@ -31,7 +33,8 @@ STATUS_NAMES = {0: "ok", 1: "not_converged", -1: "err_arg", -2: "err_oom", -3: "
 # every symbol include/pfk.h declares
 EXPORTED = [
     "pfk_default_opts", "pfk_operator_create", "pfk_operator_destroy", "pfk_operator_size",
-    "pfk_operator_apply", "pfk_operator_diag_inv", "pfk_precond_create", "pfk_precond_destroy",
+    "pfk_operator_apply", "pfk_operator_diag_inv", "pfk_precond_create", "pfk_precond_create_noisy",
+    "pfk_precond_destroy",
     "pfk_precond_apply", "pfk_workspace_bytes", "pfk_solve", "pfk_session_create",
     "pfk_session_start", "pfk_session_iterate", "pfk_session_sync", "pfk_session_destroy",
     "pfk_session_profile", "pfk_estimate_sigma", "pfk_last_error",
@@ -118,6 +121,7 @@ def lib():
         "pfk_operator_apply": (C.c_int, [vp, vp, vp, vp]),
         "pfk_operator_diag_inv": (C.c_int, [vp, vp, vp]),
         "pfk_precond_create": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(vp)]),
+        "pfk_precond_create_noisy": (C.c_int, [vp, C.c_double, C.c_uint64, C.POINTER(vp)]),
         "pfk_precond_destroy": (None, [vp]),
         "pfk_precond_apply": (C.c_int, [vp, vp, vp, vp]),
         "pfk_workspace_bytes": (C.c_size_t, [vp, vp, C.c_int, C.c_int, C.c_int]),
@@ -260,15 +264,23 @@ class Operator:
 
 
 class Precond:
-    """Flexible preconditioner B of the given kind on operator A."""
+    """Flexible preconditioner B of the given kind on operator A.
+
+    kind "noisy" is the seeded Gaussian-noise preconditioner of the section
+    2.2.1 study (``eta``, ``seed``; the other arguments are ignored).
+    """
 
     def __init__(self, A: Operator, kind: str = "jacobi_pcg", inner_its: int = 5,
-                 precision: int = FP64, block: int = 8):
+                 precision: int = FP64, block: int = 8, eta: float = 0.0, seed: int = 0):
         h = C.c_void_p()
-        _check(lib().pfk_precond_create(A.handle, PC_KINDS[kind], inner_its, precision, block, C.byref(h)))
+        if kind == "noisy":
+            _check(lib().pfk_precond_create_noisy(A.handle, float(eta), int(seed), C.byref(h)))
+        else:
+            _check(lib().pfk_precond_create(A.handle, PC_KINDS[kind], inner_its, precision, block, C.byref(h)))
         self._h = h
         self.A = A
         self.kind, self.inner_its, self.precision, self.block = kind, inner_its, precision, block
+        self.eta, self.seed = eta, seed
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -25,6 +25,7 @@
 
 #include "../../include/pfk.h"
 #include "pfk_batch.hpp"
+#include "pfk_noise.hpp"
 
 using namespace pfk;
 
@@ -110,7 +111,10 @@ k_pc_write(long long N, PcOutDesc pd, double* __restrict__ y, SolveState* st) {
 }
 
 __global__ void k_set_running(SolveState* st) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) st->status = kRunning;
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->status = kRunning;
+    st->pc.ndraws = 0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -167,6 +171,9 @@ struct pfk_precond_s {
   int k = 1;
   int prec = 0;
   int block = 8;
+  double noise_eta = 0.0;        // noisy kind: noise magnitude relative to ||v||
+  unsigned long long seed = 0;   // noisy kind: generator key
+  long long draws = 0;           // noisy kind: standalone applications so far
   // private buffers for pfk_precond_apply
   char* scratch = nullptr;
   size_t scratch_bytes = 0;
@@ -339,6 +346,7 @@ extern "C" int pfk_precond_create(pfk_operator A, pfk_pc_kind kind, int inner_it
                                   int block, pfk_precond* out) {
   if (!out || !A) return fail(PFK_ERR_ARG, "null argument");
   *out = nullptr;
+  if (kind == PFK_PC_NOISY) return fail(PFK_ERR_ARG, "the noisy preconditioner is made by pfk_precond_create_noisy");
   if (kind < PFK_PC_NONE || kind > PFK_PC_BLOCK_JACOBI_PCG) return fail(PFK_ERR_ARG, "unknown preconditioner");
   if ((kind == PFK_PC_JACOBI_PCG || kind == PFK_PC_JACOBI_GMRES || kind == PFK_PC_BLOCK_JACOBI_PCG) &&
       (inner_its < 1 || inner_its > kMaxInner))
@@ -360,6 +368,22 @@ extern "C" int pfk_precond_create(pfk_operator A, pfk_pc_kind kind, int inner_it
   B->k = (kind == PFK_PC_NONE || kind == PFK_PC_JACOBI) ? 1 : inner_its;
   B->prec = prec;
   B->block = block;
+  *out = B;
+  return PFK_OK;
+}
+
+extern "C" int pfk_precond_create_noisy(pfk_operator A, double eta, uint64_t seed, pfk_precond* out) {
+  if (!out || !A) return fail(PFK_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (!(eta >= 0.0) || !std::isfinite(eta)) return fail(PFK_ERR_ARG, "eta must be finite and non-negative");
+  auto* B = new (std::nothrow) pfk_precond_s();
+  if (!B) return fail(PFK_ERR_OOM, "host allocation");
+  B->A = A;
+  B->kind = PFK_PC_NOISY;
+  B->k = 1;
+  B->prec = PFK_FP64;
+  B->noise_eta = eta;
+  B->seed = (unsigned long long)seed;
   *out = B;
   return PFK_OK;
 }
@@ -405,7 +429,9 @@ void window_slots(int method, int mmax, int* slots) {
   switch (method) {
     case PFK_FCG: case PFK_GCR: slots[W_P] = slots[W_S] = mmax; break;
     case PFK_PIPEGCR: slots[W_P] = slots[W_S] = slots[W_Q] = mmax; break;
-    case PFK_PIPEFCG: case PFK_PIPEGCR_W: slots[W_P] = slots[W_S] = slots[W_Q] = slots[W_Z] = mmax; break;
+    case PFK_PIPEFCG: case PFK_PIPEGCR_W: case PFK_PIPEFCG_NAIVE:
+      slots[W_P] = slots[W_S] = slots[W_Q] = slots[W_Z] = mmax;
+      break;
     case PFK_FGMRES: slots[W_P] = mmax + 1; slots[W_S] = mmax; break;
     case PFK_PIPEFGMRES: slots[W_P] = slots[W_S] = slots[W_Q] = mmax + 1; break;
     default: break;
@@ -486,6 +512,8 @@ struct pfk_session_s {
   int pv = 0;
   int Ps() const { return sg.blocks(); }
   int Pv() const { return pv; }
+  long long noise_draw = -1;          // noisy PC: fixed draw index (standalone apply), or -1
+  int noise_apps = 0;                 // noisy PC: applications enqueued in the current phase
 };
 
 namespace {
@@ -537,6 +565,16 @@ PcOutDesc pc_out_desc(const pfk_session_s* S, const double* X1, double c1, const
   PcOutDesc d{};
   d.kind = S->B->kind;
   d.k = S->B->k;
+  if (d.kind == PFK_PC_NOISY) {
+    // the noisy output is stored whole; consumers read it as block PCG's
+    d.kind = kPcBlockPcg;
+    d.fp32 = 0;
+    d.X1 = X1; d.c1 = c1; d.X2 = X2; d.c2 = c2;
+    d.dinv = S->A->dinv;
+    d.dinv_in = S->A->dinv;
+    d.y = S->vec(V_PC_Y);
+    return d;
+  }
   d.fp32 = S->B->prec == PFK_FP32_BF16COEF &&
            (d.kind == kPcJacobiPcg || d.kind == kPcJacobiGmres || d.kind == kPcBlockPcg);
   d.X1 = X1; d.c1 = c1; d.X2 = X2; d.c2 = c2;
@@ -622,9 +660,28 @@ void enqueue_pc_kernels(pfk_session_s* S, hipStream_t s, const PcOutDesc& d, con
 PcOutDesc enqueue_pc(pfk_session_s* S, hipStream_t s, const double* X1, double c1, const double* X2,
                      double c2) {
   const PcOutDesc d = pc_out_desc(S, X1, c1, X2, c2);
+  if (S->B->kind == PFK_PC_NOISY) {
+    const long long N = S->A->N;
+    const int off = S->noise_apps++;
+    LAUNCH(k_noise_norms, S->Pv(), s, N, X1, c1, X2, c2, S->B->seed, S->noise_draw, off, S->part(PT_PC0),
+           (const SolveState*)S->st);
+    LAUNCH(k_noise_apply, S->Pv(), s, N, X1, c1, X2, c2, S->B->seed, S->noise_draw, off, S->B->noise_eta,
+           (const double*)S->part(PT_PC0), S->Pv(), S->vec(V_PC_Y), (const SolveState*)S->st);
+    return d;
+  }
   if (d.fp32) enqueue_pc_kernels<float>(S, s, d, S->A->grid_mixed(), (const float*)S->A->dinv_f32);
   else enqueue_pc_kernels<double>(S, s, d, S->grid(), (const double*)S->A->dinv);
   return d;
+}
+
+// Phase bracket of the noisy preconditioner's draw count (no-ops otherwise).
+void noise_begin(pfk_session_s* S, hipStream_t s) {
+  S->noise_apps = 0;
+  if (S->B->kind == PFK_PC_NOISY) LAUNCH(k_noise_mark, 1, s, S->st);
+}
+void noise_end(pfk_session_s* S, hipStream_t s) {
+  if (S->B->kind == PFK_PC_NOISY && S->noise_apps > 0) LAUNCH(k_noise_advance, 1, s, S->st, S->noise_apps);
+  S->noise_apps = 0;
 }
 
 void enqueue_multidot(pfk_session_s* S, hipStream_t s, int init, int from_pc, const PcOutDesc& pd,
@@ -679,6 +736,7 @@ void enqueue_start(pfk_session_s* S, hipStream_t s) {
   const Grid g = S->grid();
   const bool gm = S->method == PFK_FGMRES || S->method == PFK_PIPEFGMRES;
   LAUNCH(k_restart, 1, s, S->st);
+  noise_begin(S, s);
   LAUNCH(k_residual, S->Ps(), s, g, S->sg, S->b, (const double*)S->x, S->vec(V_R), S->part(PT_A),
          gm ? S->vec(V_X0) : nullptr);
   switch (S->method) {
@@ -688,6 +746,7 @@ void enqueue_start(pfk_session_s* S, hipStream_t s) {
       enqueue_cg_body(S, s, 1);
       break;
     case PFK_PIPEFCG:
+    case PFK_PIPEFCG_NAIVE:
     case PFK_PIPEGCR_W: {
       // u_0 = B(r_0), w_0 = A u_0; PIPEFCG: gamma_0 = <u_0,r_0>, eta_0 = <u_0,w_0>;
       // PIPEGCR_w (p_0 = u_0, s_0 = w_0): gamma_0 = <r_0,s_0>, eta_0 = <s_0,s_0>
@@ -739,6 +798,7 @@ void enqueue_start(pfk_session_s* S, hipStream_t s) {
     default:
       break;
   }
+  noise_end(S, s);
 }
 
 // One iteration.
@@ -746,6 +806,7 @@ void enqueue_iteration(pfk_session_s* S) {
   const pfk_operator_s* A = S->A;
   const Grid g = S->grid();
   hipStream_t s1 = S->s1, s2 = S->s2;
+  noise_begin(S, s1);
   switch (S->method) {
     case PFK_FCG:
     case PFK_GCR:
@@ -753,6 +814,7 @@ void enqueue_iteration(pfk_session_s* S) {
       enqueue_cg_body(S, s1, 0);
       break;
     case PFK_PIPEFCG:
+    case PFK_PIPEFCG_NAIVE:
     case PFK_PIPEGCR_W: {
       LAUNCH(k_pipefcg_update, S->Pv(), s1, A->N, S->win(W_P), S->win(W_S), S->win(W_Q), S->win(W_Z), S->x,
              S->vec(V_R), S->vec(V_U), S->vec(V_W), (const double*)S->vec(V_M), (const double*)S->vec(V_N),
@@ -762,9 +824,12 @@ void enqueue_iteration(pfk_session_s* S) {
       (void)hipStreamWaitEvent(s2, S->ev_fork, 0);
       LAUNCH(k_pipefcg_scalars, 1, s2, S->part(PT_MAIN), S->Pv(), S->st, S->hist);
       (void)hipEventRecord(S->ev_join, s2);
-      PcOutDesc pd = enqueue_pc(S, s1, S->vec(V_W), 1.0, S->vec(V_R), -1.0);
-      LAUNCH(k_apply_pc_out, S->Ps(), s1, g, S->sg, pd, (const double*)S->vec(V_U), 1.0, S->vec(V_M),
-             S->vec(V_N), 0, (const double*)nullptr, S->part(PT_B), S->st);
+      // m = u + B(w - r) (Alg. 8, 12); the naive form (Alg. 7) takes m = B(w)
+      const bool naive = S->method == PFK_PIPEFCG_NAIVE;
+      PcOutDesc pd = naive ? enqueue_pc(S, s1, S->vec(V_W), 1.0, nullptr, 0.0)
+                           : enqueue_pc(S, s1, S->vec(V_W), 1.0, S->vec(V_R), -1.0);
+      LAUNCH(k_apply_pc_out, S->Ps(), s1, g, S->sg, pd, naive ? (const double*)nullptr : (const double*)S->vec(V_U),
+             naive ? 0.0 : 1.0, S->vec(V_M), S->vec(V_N), 0, (const double*)nullptr, S->part(PT_B), S->st);
       (void)hipStreamWaitEvent(s1, S->ev_join, 0);
       break;
     }
@@ -820,10 +885,10 @@ void enqueue_iteration(pfk_session_s* S) {
     default:
       break;
   }
+  noise_end(S, s1);
 }
 
 void enqueue_true_check(pfk_session_s* S, hipStream_t s) {
-  const pfk_operator_s* A = S->A;
   LAUNCH(k_residual, S->Ps(), s, S->grid(), S->sg, S->b, (const double*)S->x, S->vec(V_R), S->part(PT_A),
          (double*)nullptr);
   LAUNCH(k_true_check, 1, s, S->part(PT_A), S->Ps(), S->st);
@@ -836,6 +901,7 @@ void enqueue_sigma_estimate(pfk_session_s* S, hipStream_t s, int its) {
   double* v = S->vec(V_VIN);
   double* w = S->vec(V_Z);
   LAUNCH(k_set_running, 1, s, S->st);
+  noise_begin(S, s);
   LAUNCH(k_fill, S->Pv(), s, A->N, v, 1.0 / std::sqrt((double)A->N));
   for (int i = 0; i < its; ++i) {
     PcOutDesc pd = enqueue_pc(S, s, v, 1.0, nullptr, 0.0);
@@ -844,6 +910,7 @@ void enqueue_sigma_estimate(pfk_session_s* S, hipStream_t s, int its) {
     LAUNCH(k_dot2, S->Pv(), s, A->N, (const double*)v, (const double*)w, S->part(PT_MAIN));
     LAUNCH(k_power_step, S->Pv(), s, A->N, (const double*)S->part(PT_MAIN), S->Pv(), v, (const double*)w, S->st);
   }
+  noise_end(S, s);
 }
 
 int capture(pfk_session_s* S, hipGraphExec_t* out, int what, int iters) {
@@ -926,7 +993,7 @@ static int session_make(pfk_operator A, pfk_precond B, pfk_method method, const 
   *out = nullptr;
   if (!A || !B || !b || !x) return fail(PFK_ERR_ARG, "null argument");
   if (B->A != A) return fail(PFK_ERR_ARG, "preconditioner was made for another operator");
-  if (method < PFK_FCG || method > PFK_PIPEGCR_W) return fail(PFK_ERR_ARG, "unknown method");
+  if (method < PFK_FCG || method > PFK_PIPEFCG_NAIVE) return fail(PFK_ERR_ARG, "unknown method");
   if (mmax < 1 || mmax > kNuMax) return fail(PFK_ERR_ARG, "mmax must be 1..64");
   if (maxit < 0) return fail(PFK_ERR_ARG, "maxit must be >= 0");
   if (!(rtol >= 0.0)) return fail(PFK_ERR_ARG, "rtol must be >= 0");
@@ -1167,6 +1234,7 @@ extern "C" int pfk_precond_apply(pfk_precond B, const double* v, double* y, void
   S.A = A; S.B = B; S.ws = B->scratch; S.L = L; S.mmax = 1;
   S.sg = A->sg; S.pv = A->pv_blocks;
   S.st = (SolveState*)(S.ws + L.state);
+  if (B->kind == PFK_PC_NOISY) S.noise_draw = B->draws++;
   hipStream_t s = (hipStream_t)stream;
   LAUNCH(k_set_running, 1, s, S.st);
   PcOutDesc pd = enqueue_pc(&S, s, v, 1.0, nullptr, 0.0);
@@ -1279,7 +1347,7 @@ extern "C" int pfk_operator_autotune(pfk_operator A, pfk_precond B, pfk_method m
                                      void* stream, pfk_tuning* out) {
   if (!A || !B) return fail(PFK_ERR_ARG, "null argument");
   if (B->A != A) return fail(PFK_ERR_ARG, "preconditioner was made for another operator");
-  if (method < PFK_FCG || method > PFK_PIPEGCR_W) return fail(PFK_ERR_ARG, "unknown method");
+  if (method < PFK_FCG || method > PFK_PIPEFCG_NAIVE) return fail(PFK_ERR_ARG, "unknown method");
   if (mmax < 1 || mmax > kNuMax) return fail(PFK_ERR_ARG, "mmax must be 1..64");
   if (reps < 1) reps = 5;
   const int nx = (int)A->n[0], ny = (int)A->n[1], nz = (int)A->n[2];

@@ -41,6 +41,8 @@ __global__ void k_setup(SolveState* st, double tol, int maxit, int nu_max, int t
   st->col = 0;
   st->bzero = 0;
   st->bnorm = 0.0;
+  st->pc.ndraws = 0;
+  st->pc.noise_live = 0;
 }
 
 // Start (or restart) a cycle from the current x: the pipeline is flushed.

@@ -31,6 +31,10 @@ struct PcScalars {                 // one inner solve's scalars, indexed by inne
   double vs[kMaxInner + 1];
   double beta0;
   int ncol;
+  // noisy preconditioner: applications of B this solve has used so far, and
+  // whether the current phase runs
+  unsigned long long ndraws;
+  int noise_live;
 };
 
 constexpr int kMaxInnerGmres = 8;  // inner GMRES steps supported
