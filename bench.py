@@ -356,6 +356,76 @@ def serving_bench(pfk, torch, nreq=160, seed=0, loads=(0.5, 0.9)):
     return out
 
 
+def stagnation_study(pfk, torch):
+    """Section 2.2.1 (Figure 1) at scale: FCG, PIPEFCG and naive PIPEFCG
+    (Alg. 7) with the seeded noisy preconditioner B(r) = r + eta ||r|| g/||g||
+    on the unit-scaled Dirichlet Laplacian (eta = h^2, the stencil's 1/h^2
+    cancelled so that the spectrum is of order one as in the toy), b = A x*.
+    Each method runs as a full solve (true-residual check, breakdown
+    restarts) to rtol 1e-10 or maxit, and reports its relative error
+    ||x - x*|| / ||x*||.  Naive PIPEFCG also reports its error along one
+    cycle (up to its first breakdown) at iterations 5, 10, ..., 50, then
+    every 50.  Both truncation rules at 128^3; the standard one at 256^3 for
+    eta = 1e-2."""
+    import gen
+    out = {"workload": "unit-scaled 7-point Laplacian, b = A x* (x* ~ N(0,1)), noisy B (seed 1), nu_max 30, "
+                       "rtol 1e-10"}
+    marks = list(range(5, 50, 5)) + list(range(50, 2001, 50))
+    plan = ((128, (1e-1, 1e-2, 1e-3), (0, 1), 1000), (256, (1e-2,), (0,), 1500))
+    for n, etas, truncs, maxit in plan:
+        p = gen.study_problem(3, n, seed=0)
+        A = pfk.Operator(3, n, p.eta)
+        xs = torch.as_tensor(p.meta["x_star"]).cuda()
+        b = A.apply(xs)
+        xn = float(torch.linalg.vector_norm(xs))
+        del p
+
+        def rel_err(x):
+            return float(f"{float(torch.linalg.vector_norm(x - xs)) / xn:.3g}")
+
+        for trunc in truncs:
+            for eta in etas:
+                for method in ("fcg", "pipefcg", "pipefcg_naive"):
+                    key = f"{n}^3/{'notay' if trunc else 'standard'}/eta={eta:g}/{method}"
+                    B = pfk.Precond(A, "noisy", eta=eta, seed=1)
+                    x = torch.zeros_like(b)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    info = pfk.solve(A, B, method, b, x, rtol=1e-10, maxit=maxit, mmax=NU, truncation=trunc,
+                                     graph_iters=10)
+                    torch.cuda.synchronize()
+                    dt = time.perf_counter() - t0
+                    r = {"iterations": info.iterations, "restarts": info.restarts, "converged": info.converged,
+                         "status": info.status_name, "rel_error": rel_err(x),
+                         "true_rel_resid": float(f"{info.true_rel_resid:.3g}"),
+                         "ms_per_iteration": round(dt / max(info.iterations, 1) * 1e3, 4)}
+                    if method == "pipefcg_naive":
+                        r["plateau_over_eta"] = round(r["rel_error"] / eta, 3)
+                        # the error along one cycle, sampled
+                        x.zero_()
+                        S = pfk.Session(A, pfk.Precond(A, "noisy", eta=eta, seed=1), method, b, x, rtol=1e-10,
+                                        maxit=maxit, mmax=NU, truncation=trunc, graph_iters=10)
+                        S.start()
+                        curve, it = [], 0
+                        for stop in marks:
+                            if stop > maxit:
+                                break
+                            S.iterate(stop - it)
+                            reached = S.sync().iterations
+                            curve.append([reached, rel_err(x)])
+                            if reached < stop:
+                                break
+                            it = reached
+                        S.close()
+                        r["cycle_rel_error_at"] = curve
+                    out[key] = r
+                    log(f"stagnation {key}: {info.iterations} its, {info.restarts} restarts, "
+                        f"rel error {r['rel_error']:.3g}")
+        del A, xs, b
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(prob, method):
     """The FP64 oracle on the host: one outer iteration of the same workload,
     timed as (start-up + 1 iteration) minus (start-up alone), one thread."""
@@ -480,6 +550,9 @@ def main():
                     help="time only the batched workload (after the headline pair)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-stagnation", action="store_true")
+    ap.add_argument("--stagnation-only", action="store_true",
+                    help="headline plus the noisy-preconditioner stagnation study")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -549,6 +622,9 @@ def main():
     if args.batched_only:
         args.headline_only = True
         extra["batched_64"] = batched_bench(pfk, torch, args.steps, args.warmup)
+    if args.stagnation_only:
+        args.headline_only = True
+        extra["stagnation_study"] = stagnation_study(pfk, torch)
     if not args.headline_only:
         # unpipelined baseline with a blocking (host-synchronised) reduction
         log("timing fcg host-sync")
@@ -616,6 +692,9 @@ def main():
         extra["conv_diff_256"] = conv
         del A3, B3, b3
 
+    if not args.headline_only and not args.no_stagnation:
+        log("stagnation study (section 2.2.1 at scale)")
+        extra["stagnation_study"] = stagnation_study(pfk, torch)
     if not args.headline_only:
         log("size sweep: PIPEFCG vs FCG per iteration")
         extra["size_sweep_it_per_s"] = size_sweep(pfk, torch)
