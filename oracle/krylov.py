@@ -17,6 +17,17 @@ and the listings omit.  Conventions shared with the GPU path:
 * Convergence: the first i with history[i] <= rtol*||b||_2.  The true
   residual ||b - A x|| is then checked; if it is above the tolerance the
   method restarts from x (a "gap" restart).
+* Natural norm (section 5, implementation remarks: the one residual norm a
+  pipelined CG/CR method has without an extra reduction): sqrt|gamma_i|,
+  gamma = <u, r> for CG types and <r, A u> for CR types (u = B(r) or its
+  recurrence).  ``natural[0]`` comes from the first start-up, ``natural[i]``
+  from iteration i, whenever the method forms that gamma (FCG and GCR form
+  it only after their 2-norm test, so the iteration that converges in the
+  2-norm has none).  With ``norm="natural"`` the test is
+  natural[i] <= rtol*natural[0], B is applied before the test, and the
+  converged iterate is accepted without the 2-norm true-residual check.
+  GMRES types have no natural norm and always test |g_i| (PCG, kept as
+  FCG's pin, tests the 2-norm only).
 * Window: the last nu_i directions, nu_i from ``truncation_nu`` with j the
   number of iterations since the last (re)start.
 * Breakdown (section 5): eta_i <= 0 or non-finite for CG/CR types,
@@ -161,16 +172,40 @@ class Result:
     status: str                 # 'converged' | 'maxit' | 'breakdown'
     true_rel_resid: float
     trace: dict = field(default_factory=dict)
+    natural: list = field(default_factory=list)
 
 
 class _State:
-    def __init__(self, maxit, force_breakdown_at, record):
+    def __init__(self, maxit, force_breakdown_at, record, norm="2", rtol=0.0):
         self.it = 0
         self.history = []
+        self.natural = []
         self.maxit = maxit
         self.force = force_breakdown_at
         self.record = record
         self.trace = {}
+        self.norm = norm
+        self.rtol = rtol
+        self.ntol = 0.0
+
+    @property
+    def natural_test(self) -> bool:
+        return self.norm == "natural"
+
+    def start_natural(self, gamma):
+        """natural[0] and the natural-norm tolerance, from the first start-up only."""
+        if not self.natural:
+            self.natural.append(math.sqrt(abs(gamma)))
+            self.ntol = self.rtol * self.natural[0]
+
+    def log_natural(self, gamma):
+        self.natural.append(math.sqrt(abs(gamma)))
+
+    def converged(self, tol) -> bool:
+        """The convergence test of the chosen norm on the newest entries."""
+        if self.natural_test:
+            return self.natural[-1] <= self.ntol
+        return self.history[-1] <= tol
 
     def forced(self, it=None) -> bool:
         """True once, at iteration ``force_breakdown_at`` (test hook)."""
@@ -183,14 +218,17 @@ class _State:
 
 def solve(method: str, A, B, b, x0=None, rtol=1e-8, maxit=500, nu_max=30,
           truncation="standard", sigma=None, max_restarts=10,
-          force_breakdown_at=-1, record=False) -> Result:
+          force_breakdown_at=-1, record=False, norm="2") -> Result:
     """Solve A x = b with the named method.
 
     ``A`` is a callable (or an object with ``apply``), ``B`` a callable
     preconditioner.  ``nu_max`` is the window length for CG/CR types and the
     restart length m for GMRES types.  ``sigma`` is PIPEFGMRES's constant
-    shift (default: ``estimate_sigma``).
+    shift (default: ``estimate_sigma``).  ``norm`` is "2" or "natural" (the
+    convergence measure of CG/CR types, see the module docstring).
     """
+    if norm not in ("2", "natural"):
+        raise ValueError("norm must be '2' or 'natural'")
     Aop = A.apply if hasattr(A, "apply") else A
     b = np.asarray(b, dtype=np.float64)
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
@@ -202,13 +240,14 @@ def solve(method: str, A, B, b, x0=None, rtol=1e-8, maxit=500, nu_max=30,
     kw = dict(nu_max=nu_max, trunc=truncation)
     if method == "pipefgmres":
         kw["sigma"] = estimate_sigma(Aop, B, b.shape[0]) if sigma is None else float(sigma)
-    st = _State(maxit, force_breakdown_at, record)
+    no_natural = method in ("pcg", "fgmres", "pipefgmres")
+    st = _State(maxit, force_breakdown_at, record, "2" if no_natural else norm, rtol)
     restarts = 0
     status = "maxit"
     while True:
         reason = cycle(Aop, B, b, x, st, tol, **kw)
         if reason == "converged":
-            if _norm(b - Aop(x)) <= tol:
+            if st.natural_test or _norm(b - Aop(x)) <= tol:
                 status = "converged"
                 break
             reason = "gap"
@@ -228,7 +267,8 @@ def solve(method: str, A, B, b, x0=None, rtol=1e-8, maxit=500, nu_max=30,
             status = "maxit"
             break
     true_rel = _norm(b - Aop(x)) / bnorm
-    return Result(x, st.history, st.it, restarts, status == "converged", status, true_rel, st.trace)
+    return Result(x, st.history, st.it, restarts, status == "converged", status, true_rel, st.trace,
+                  st.natural)
 
 
 def _start(Aop, b, x, st, tol):
@@ -290,6 +330,7 @@ def _fcg_cycle(Aop, B, b, x, st, tol, nu_max, trunc):
     P = [u.copy()]
     S = [Aop(P[0])]
     gamma = _dot(u, r)
+    st.start_natural(gamma)
     ETA = [_dot(P[0], S[0])]
     if not _finite_pos(ETA[0]):
         return "breakdown0"
@@ -303,12 +344,15 @@ def _fcg_cycle(Aop, B, b, x, st, tol, nu_max, trunc):
         x += alpha * P[-1]
         r -= alpha * S[-1]
         st.history.append(_norm(r))
-        if st.history[-1] <= tol:
+        if not st.natural_test and st.converged(tol):
             return "converged"
         u = B(r)
+        gamma = _dot(u, r)
+        st.log_natural(gamma)
+        if st.natural_test and st.converged(tol):
+            return "converged"
         nu = truncation_nu(trunc, j, nu_max)
         win = _window(P, nu)
-        gamma = _dot(u, r)
         beta = {k: -_dot(u, S[k]) / ETA[k] for k in win}
         p = u.copy()
         for k in win:
@@ -343,6 +387,7 @@ def _pipefcg_cycle(Aop, B, b, x, st, tol, nu_max, trunc, naive=False):
     n = Aop(m)
     gamma = _dot(u, r)
     delta = _dot(u, w)
+    st.start_natural(gamma)
     P, S, Q, Z = [u.copy()], [w.copy()], [m.copy()], [n.copy()]
     ETA = [delta]
     if not _finite_pos(delta):
@@ -366,7 +411,8 @@ def _pipefcg_cycle(Aop, B, b, x, st, tol, nu_max, trunc, naive=False):
         dks = {k: _dot(u, S[k]) for k in win}
         rho = _dot(r, r)
         st.history.append(math.sqrt(rho))
-        if st.history[-1] <= tol:
+        st.log_natural(gamma)
+        if st.converged(tol):
             return "converged"
         # overlapped with the reduction
         m = B(w) if naive else u + B(w - r)
@@ -414,6 +460,7 @@ def _gcr_cycle(Aop, B, b, x, st, tol, nu_max, trunc):
     P = [u.copy()]
     S = [Aop(P[0])]
     gamma = _dot(r, S[0])
+    st.start_natural(gamma)
     ETA = [_dot(S[0], S[0])]
     if not _finite_pos(ETA[0]):
         return "breakdown0"
@@ -427,10 +474,13 @@ def _gcr_cycle(Aop, B, b, x, st, tol, nu_max, trunc):
         x += alpha * P[-1]
         r -= alpha * S[-1]
         st.history.append(_norm(r))
-        if st.history[-1] <= tol:
+        if not st.natural_test and st.converged(tol):
             return "converged"
         u = B(r)
         t = Aop(u)
+        st.log_natural(_dot(r, t))
+        if st.natural_test and st.converged(tol):
+            return "converged"
         nu = truncation_nu(trunc, j, nu_max)
         win = _window(P, nu)
         beta = {k: -_dot(t, S[k]) / ETA[k] for k in win}
@@ -467,6 +517,7 @@ def _pipegcr_cycle(Aop, B, b, x, st, tol, nu_max, trunc, recur_w=False):
     Zw = [Aop(Q[0])] if recur_w else None
     w = S[0].copy() if recur_w else None
     gamma = _dot(r, S[0])
+    st.start_natural(gamma)
     ETA = [_dot(S[0], S[0])]
     if not _finite_pos(ETA[0]):
         return "breakdown0"
@@ -491,7 +542,8 @@ def _pipegcr_cycle(Aop, B, b, x, st, tol, nu_max, trunc, recur_w=False):
         dks = {k: _dot(w, S[k]) for k in win}
         rho = _dot(r, r)
         st.history.append(math.sqrt(rho))
-        if st.history[-1] <= tol:
+        st.log_natural(gamma)
+        if st.converged(tol):
             return "converged"
         m = u + B(w - r)
         nn = Aop(m) if recur_w else None

@@ -219,3 +219,48 @@ def test_fig1_toy_stagnation():
             err[m] = np.linalg.norm(r.x - xs) / np.linalg.norm(xs)
         assert lo * eta <= err["pipefcg_naive"] <= hi * eta, (eta, err)
         assert err["fcg"] < g["converged_error_below"] and err["pipefcg"] < g["converged_error_below"], err
+
+
+# ---------------------------------------------------------------------------
+# natural norm (section 5, implementation remarks)
+# ---------------------------------------------------------------------------
+def _dense_natural(method, A, Dinv, b, its, nu):
+    """sqrt|gamma| recomputed from the true residual of the iterate after each
+    of the first ``its`` iterations (separate solves stopped by maxit):
+    sqrt(r D^-1 r) for CG types, sqrt|r A D^-1 r| for CR types."""
+    out = []
+    for i in range(its + 1):
+        x = solve(method, A, lambda v: Dinv * v, b, rtol=0.0, maxit=i, nu_max=nu).x
+        r = b - A.apply(x)
+        g = r @ (Dinv * r) if method in ("fcg", "pipefcg") else r @ A.apply(Dinv * r)
+        out.append(math.sqrt(abs(g)))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("method", ["fcg", "pipefcg", "gcr", "pipegcr", "pipegcr_w"])
+def test_natural_norm_is_the_b_norm_of_the_true_residual(method):
+    conv = method in ("gcr", "pipegcr", "pipegcr_w")
+    A, b = _tiny(3, 7, 2.0, seed=5, conv=conv)
+    Dinv = 1.0 / A.diagonal()
+    ref = solve(method, A, lambda v: Dinv * v, b, rtol=0.0, maxit=8, nu_max=30)
+    assert len(ref.natural) == 9
+    np.testing.assert_allclose(ref.natural, _dense_natural(method, A, Dinv, b, 8, 30), rtol=1e-8)
+
+
+@pytest.mark.parametrize("method", ["fcg", "pipefcg", "gcr", "pipegcr"])
+def test_natural_norm_stopping(method):
+    conv = method in ("gcr", "pipegcr")
+    A, b = _tiny(2, 12, 2.0, seed=6, conv=False) if not conv else _tiny(3, 8, 2.0, seed=6, conv=True)
+    B = make_pc("jacobi_pcg", A, 2)
+    rtol = 1e-6
+    full = solve(method, A, B, b, rtol=0.0, maxit=200, nu_max=30)
+    nat = np.array(full.natural)
+    first = int(np.argmax(nat <= rtol * nat[0]))
+    assert nat[first] <= rtol * nat[0] and first > 0
+    res = solve(method, A, B, b, rtol=rtol, maxit=200, nu_max=30, norm="natural")
+    assert res.converged and res.iterations == first
+    assert np.array_equal(res.natural, nat[:first + 1])
+    # the 2-norm mode logs the same natural norms (FCG/GCR up to the converging iteration)
+    two = solve(method, A, B, b, rtol=rtol, maxit=200, nu_max=30)
+    n = len(two.natural)
+    assert n >= two.iterations and np.array_equal(two.natural, nat[:n])
