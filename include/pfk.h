@@ -116,6 +116,15 @@ typedef struct {
   int persistent;          /* batches only: 1 runs each pfk_batch_step as one cooperative
                               launch whose phases are separated by grid barriers (no
                               kernel boundaries); 0 one launch per phase (default)    */
+  int norm;                /* convergence measure of the CG/CR types: 0 the recurred
+                              ||r_i||_2 <= rtol ||b||_2, then the true-residual check
+                              (default); 1 the natural norm sqrt|gamma_i| <= rtol times
+                              that of the first start-up, gamma = <u, r> (CG types) or
+                              <r, A u> (CR types), the one norm these methods have
+                              without an extra reduction (section 5); the iterate is
+                              then accepted without the 2-norm check (true_rel_resid
+                              still reports it).  GMRES types ignore it (they test the
+                              Givens estimate of the preconditioned residual).       */
 } pfk_solve_opts;
 
 typedef struct {
@@ -129,10 +138,15 @@ typedef struct {
                               the Givens estimate for GMRES), history[0] = ||r_0||    */
   int history_cap;         /* entries available in history                            */
   int history_len;         /* entries written (iterations + 1, capped)                */
+  double* natural_history; /* caller buffer (host, history_cap entries) or NULL: the
+                              natural norm sqrt|gamma_i| of every iteration, [0] from
+                              the first start-up (CG/CR types; logged in either norm
+                              mode).  The server does not keep it.                   */
+  int natural_len;         /* entries written (0 for GMRES types)                     */
 } pfk_solve_info;
 
 /* Defaults: standard truncation, sigma estimated, graph_iters 8, graphs on,
- * no host sync, 10 restarts, no forced breakdown. */
+ * no host sync, 10 restarts, no forced breakdown, phased batches, 2-norm test. */
 void pfk_default_opts(pfk_solve_opts* opts);
 
 /* Operator A of dimension 2 or 3 with n[0..dim) interior nodes per axis (x, y, z;

@@ -74,13 +74,14 @@ class PfkError(RuntimeError):
 class SolveOpts(C.Structure):
     _fields_ = [("truncation", C.c_int), ("shift_sigma", C.c_double), ("graph_iters", C.c_int),
                 ("use_graph", C.c_int), ("host_sync", C.c_int), ("max_restarts", C.c_int),
-                ("force_breakdown_at", C.c_int), ("persistent", C.c_int)]
+                ("force_breakdown_at", C.c_int), ("persistent", C.c_int), ("norm", C.c_int)]
 
 
 class _Info(C.Structure):
     _fields_ = [("iterations", C.c_int), ("restarts", C.c_int), ("converged", C.c_int),
                 ("status", C.c_int), ("true_rel_resid", C.c_double),
-                ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int), ("history_len", C.c_int)]
+                ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int), ("history_len", C.c_int),
+                ("natural_history", C.POINTER(C.c_double)), ("natural_len", C.c_int)]
 
 
 @dataclass
@@ -91,6 +92,7 @@ class SolveInfo:
     converged: bool
     true_rel_resid: float
     history: np.ndarray
+    natural: np.ndarray = None      # sqrt|gamma_i| per iteration (CG/CR types), else empty
 
     @property
     def status_name(self) -> str:
@@ -312,17 +314,20 @@ def estimate_sigma(A: Operator, B: Precond, its: int = 10, stream=None) -> float
     return sig.value
 
 
-def _info_struct(cap: int):
-    info = _Info()
-    hist = np.zeros(max(cap, 1), dtype=np.float64)
-    info.history = hist.ctypes.data_as(C.POINTER(C.c_double))
+def _info_struct(cap: int, info=None):
+    """An info record with host buffers for both histories (row 0: the
+    residual measure, row 1: the natural norm)."""
+    info = _Info() if info is None else info
+    hist = np.zeros((2, max(cap, 1)), dtype=np.float64)
+    info.history = hist[0].ctypes.data_as(C.POINTER(C.c_double))
+    info.natural_history = hist[1].ctypes.data_as(C.POINTER(C.c_double))
     info.history_cap = cap
     return info, hist
 
 
 def _to_info(code: int, info: _Info, hist: np.ndarray) -> SolveInfo:
     return SolveInfo(code, info.iterations, info.restarts, bool(info.converged), info.true_rel_resid,
-                     hist[: info.history_len].copy())
+                     hist[0, : info.history_len].copy(), hist[1, : info.natural_len].copy())
 
 
 def solve(A: Operator, B: Precond, method: str, b, x, rtol: float = 1e-8, maxit: int = 500,
@@ -469,12 +474,7 @@ def solve_batched(As, Bs, method: str, bs, xs, rtol=1e-8, maxit: int = 500, mmax
     arrx = (C.c_void_p * n)(*[_dev_ptr(v, a.N, "x") for v, a in zip(xs, As)])
     arrr = (C.c_double * n)(*rt)
     infos = (_Info * n)()
-    hists = []
-    for i in range(n):
-        hist = np.zeros(maxit + 1, dtype=np.float64)
-        infos[i].history = hist.ctypes.data_as(C.POINTER(C.c_double))
-        infos[i].history_cap = maxit + 1
-        hists.append(hist)
+    hists = [_info_struct(maxit + 1, infos[i])[1] for i in range(n)]
     wsp, wsb = (None, 0)
     if workspace is not None:
         wsp, wsb = workspace.data_ptr(), workspace.numel() * workspace.element_size()

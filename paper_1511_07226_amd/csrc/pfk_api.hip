@@ -88,6 +88,7 @@ k_setup_tol(const double* part, int P, double rtol, SolveState* st, double* hist
   const double bb = block_sum_column(part, P, 0);
   if (threadIdx.x != 0) return;
   st->bnorm = sqrt(bb);
+  st->rtol = rtol;
   st->tol = rtol * st->bnorm;
   if (bb == 0.0) {
     st->bzero = 1;
@@ -209,6 +210,7 @@ extern "C" void pfk_default_opts(pfk_solve_opts* o) {
   o->max_restarts = 10;
   o->force_breakdown_at = -1;
   o->persistent = 0;
+  o->norm = 0;
 }
 
 extern "C" int pfk_operator_create(int dim, const int64_t n[3], const double* eta, const double* face_vel,
@@ -412,7 +414,7 @@ enum Win { W_P, W_S, W_Q, W_Z, W_PCV, W_COUNT };  // W_PCV: inner GMRES basis
 enum Part { PT_MAIN, PT_A, PT_B, PT_PC0, PT_PC1, PT_COUNT };
 
 struct Layout {
-  size_t state = 0, hist = 0;
+  size_t state = 0, hist = 0, nhist = 0;
   size_t vec[V_COUNT] = {};
   size_t win[W_COUNT] = {};
   int slots[W_COUNT] = {};
@@ -447,6 +449,8 @@ Layout make_layout(const pfk_operator_s* A, const pfk_precond_s* B, int method, 
   L.state = off;
   off = align_up(off + sizeof(SolveState));
   L.hist = off;
+  off = align_up(off + sizeof(double) * (size_t)(maxit + 2));
+  L.nhist = off;
   off = align_up(off + sizeof(double) * (size_t)(maxit + 2));
   L.ld = (A->N + 31) / 32 * 32;
   const size_t vbytes = align_up(sizeof(double) * (size_t)L.ld);
@@ -498,6 +502,7 @@ struct pfk_session_s {
   hipGraphExec_t g_start = nullptr, g_iter = nullptr, g_one = nullptr;
   SolveState* st = nullptr;
   double* hist = nullptr;
+  double* nhist = nullptr;
   SolveState* host_state = nullptr;   // pinned
   int restarts = 0;
   bool owns_streams = true;           // false for members of a batch (the batch's streams)
@@ -1009,6 +1014,10 @@ static int session_make(pfk_operator A, pfk_precond B, pfk_method method, const 
     delete S;
     return fail(PFK_ERR_ARG, "truncation must be 0, 1 or 2");
   }
+  if (S->opts.norm < 0 || S->opts.norm > 1) {
+    delete S;
+    return fail(PFK_ERR_ARG, "norm must be 0 (2-norm) or 1 (natural)");
+  }
   if (S->opts.host_sync) {
     if (method != PFK_FCG && method != PFK_GCR && method != PFK_FGMRES) {
       delete S;
@@ -1034,6 +1043,7 @@ static int session_make(pfk_operator A, pfk_precond B, pfk_method method, const 
   }
   S->st = (SolveState*)(S->ws + S->L.state);
   S->hist = (double*)(S->ws + S->L.hist);
+  S->nhist = (double*)(S->ws + S->L.nhist);
   S->user = (hipStream_t)stream;
   if (bs1) {
     S->owns_streams = false;
@@ -1090,8 +1100,9 @@ static int session_setup(pfk_session_s* S) {
   } else {
     S->sigma = std::isnan(S->opts.shift_sigma) ? 0.0 : S->opts.shift_sigma;
   }
+  const bool gm = S->method == PFK_FGMRES || S->method == PFK_PIPEFGMRES;
   LAUNCH(k_setup, 1, S->s1, S->st, 0.0, S->maxit, S->mmax, S->opts.truncation, S->opts.force_breakdown_at,
-         S->sigma);
+         S->sigma, gm ? 0 : S->opts.norm, S->nhist);
   LAUNCH(k_dot, S->Pv(), S->s1, S->A->N, S->b, S->b, S->part(PT_A));
   LAUNCH(k_setup_tol, 1, S->s1, S->part(PT_A), S->Pv(), S->rtol, S->st, S->hist);
   LAUNCH(k_zero_if_done, S->Pv(), S->s1, S->A->N, S->x, S->st);
@@ -1137,6 +1148,13 @@ static int fill_info(pfk_session_s* S, int rc, pfk_solve_info* info) {
   bn = h.bnorm;
   info->true_rel_resid = bn > 0.0 ? h.true_res / bn : 0.0;
   info->history_len = 0;
+  info->natural_len = 0;
+  if (info->natural_history && info->history_cap > 0) {
+    const int n = std::min(info->history_cap, h.nat_started ? h.it + 1 : 0);
+    if (n > 0 && hipMemcpy(info->natural_history, S->nhist, sizeof(double) * n, hipMemcpyDeviceToHost) ==
+                     hipSuccess)
+      info->natural_len = n;
+  }
   if (info->history && info->history_cap > 0) {
     const int n = std::min(info->history_cap, h.hist_started ? h.it + 1 : 0);
     if (n > 0 && hipMemcpy(info->history, S->hist, sizeof(double) * n, hipMemcpyDeviceToHost) == hipSuccess)
@@ -1417,6 +1435,7 @@ extern "C" int pfk_operator_autotune(pfk_operator A, pfk_precond B, pfk_method m
   }
   S->st = (SolveState*)(S->ws + S->L.state);
   S->hist = (double*)(S->ws + S->L.hist);
+  S->nhist = (double*)(S->ws + S->L.nhist);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   double best = 0.0, dflt = 0.0;
   int count = 0;
@@ -2208,9 +2227,12 @@ extern "C" int pfk_server_result(pfk_server S, long long id, pfk_solve_info* inf
   if (r.state != 2) return fail(PFK_ERR_ARG, "request not finished");
   if (info) {
     double* h = info->history;
+    double* nh = info->natural_history;
     const int cap = info->history_cap;
     *info = r.info;
     info->history = h;
+    info->natural_history = nh;
+    info->natural_len = 0;
     info->history_cap = cap;
     info->history_len = 0;
     if (h && cap > 0) {

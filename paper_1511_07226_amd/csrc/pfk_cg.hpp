@@ -23,7 +23,7 @@ struct Window {
 // Shared kernels
 // ---------------------------------------------------------------------------
 __global__ void k_setup(SolveState* st, double tol, int maxit, int nu_max, int trunc, int force_it,
-                        double sigma) {
+                        double sigma, int norm, double* nhist) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   st->status = kRunning;
   st->it = 0;
@@ -43,6 +43,32 @@ __global__ void k_setup(SolveState* st, double tol, int maxit, int nu_max, int t
   st->bnorm = 0.0;
   st->pc.ndraws = 0;
   st->pc.noise_live = 0;
+  st->norm = norm;
+  st->nat_started = 0;
+  st->rtol = 0.0;
+  st->ntol = 0.0;
+  st->nhist = nhist;
+}
+
+// Natural norm sqrt|gamma| (section 5: the residual norm CG/CR types have
+// without an extra reduction; gamma = <u, r> or <r, A u>).  The first
+// start-up records entry 0 and the tolerance rtol * entry 0; every iteration
+// logs its entry, and natural_test says whether it passes.
+__device__ __forceinline__ void natural_start(SolveState* st, double gamma) {
+  if (st->nat_started) return;
+  st->nat_started = 1;
+  const double v = sqrt(fabs(gamma));
+  if (st->nhist) st->nhist[0] = v;
+  st->ntol = st->rtol * v;
+}
+__device__ __forceinline__ double natural_log(SolveState* st, int it, double gamma) {
+  const double v = sqrt(fabs(gamma));
+  if (st->nhist) st->nhist[it] = v;
+  return v;
+}
+// The convergence test of the chosen norm (res = recurred ||r||_2).
+__device__ __forceinline__ bool converged_test(const SolveState* st, double res, double nat) {
+  return st->norm ? nat <= st->ntol : res <= st->tol;
 }
 
 // Start (or restart) a cycle from the current x: the pipeline is flushed.
@@ -136,7 +162,8 @@ k_true_check(const double* part, int P, SolveState* st) {
   if (threadIdx.x == 0) {
     const double res = sqrt(rr);
     st->true_res = res;
-    st->status = (res <= st->tol) ? kDone : kGap;
+    // a natural-norm test accepts its iterate; the 2-norm is only reported
+    st->status = (res <= st->tol || st->norm) ? kDone : kGap;
   }
 }
 
@@ -156,6 +183,7 @@ k_pipefcg_init_scalars(const double* part_r, int P_r, const double* part_ud, int
   if (!st->hist_started) { hist[0] = res; st->hist_started = 1; }
   if (!isfinite(res)) { st->status = kNonfinite; return; }
   if (res <= st->tol) { st->status = kConverged; return; }
+  natural_start(st, gamma);
   if (!(delta > 0.0) || !isfinite(delta)) { st->status = kBreakdown0; return; }
   st->eta_ring[0] = delta;
   st->alpha = gamma / delta;
@@ -305,8 +333,9 @@ __device__ __forceinline__ void pipefcg_scalars_body(Blk bk, const double* part,
   st->j = j1;
   const double res = sqrt(col[2]);
   hist[it] = res;
+  const double nat = natural_log(st, it, col[0]);
   if (!isfinite(res)) { st->status = kNonfinite; return; }
-  if (res <= st->tol) { st->status = kConverged; return; }
+  if (converged_test(st, res, nat)) { st->status = kConverged; return; }
   const int numax = st->nu_max;
   double eta = col[1];
   for (int t = 0; t < nu1; ++t) {
@@ -447,13 +476,17 @@ __device__ __forceinline__ void cg_scalars1_body(Blk bk, int init, const double*
   st->gamma = col[0];
   st->nu = nu;
   st->j = j1;
-  if (init) return;
+  if (init) {
+    natural_start(st, col[0]);
+    return;
+  }
   const int it = st->it + 1;
   st->it = it;
   const double res = sqrt(col[2]);
   hist[it] = res;
+  const double nat = natural_log(st, it, col[0]);
   if (!isfinite(res)) { st->status = kNonfinite; return; }
-  if (res <= st->tol) { st->status = kConverged; return; }
+  if (converged_test(st, res, nat)) { st->status = kConverged; return; }
   const int numax = st->nu_max;
   for (int t = 0; t < nu; ++t) {
     const int d = j1 - nu + t;
@@ -609,6 +642,7 @@ k_pipegcr_init_scalars(const double* part, int P, SolveState* st) {
   const double gamma = block_sum_column(part, P, 0);
   const double eta = block_sum_column(part, P, 1);
   if (threadIdx.x != 0) return;
+  natural_start(st, gamma);
   if (!(eta > 0.0) || !isfinite(eta)) { st->status = kBreakdown0; return; }
   st->eta_ring[0] = eta;
   st->alpha = gamma / eta;

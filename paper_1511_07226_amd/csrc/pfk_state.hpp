@@ -56,6 +56,11 @@ struct SolveState {
   double sigma;      // PIPEFGMRES shift
   double true_res;
   double bnorm;      // ||b||_2
+  int norm;          // CG/CR types: 1 tests the natural norm sqrt|gamma| instead of ||r||_2
+  int nat_started;   // natural-norm history entry 0 recorded (first start-up)
+  double rtol;
+  double ntol;       // rtol * natural norm of the first start-up
+  double* nhist;     // natural-norm history (device), or null
   double eta_ring[kNuMax];   // eta of direction d at slot d mod nu_max
   double beta[kNuMax];       // beta of the current update, window order (oldest first)
   // GMRES family (restart length m <= kNuMax)

@@ -1,0 +1,95 @@
+"""GPU parity for the natural residual norm (section 5, implementation remarks).
+
+The CG/CR types log sqrt|gamma_i| every iteration (gamma = <u, r> or
+<r, A u>, a column of the reduction they already make) and can stop on it.
+Bar: the logged norms match the oracle's within 1e-9 relative over the first
+20 iterations; a natural-norm solve stops at the oracle's iteration and
+accepts its iterate.  Each case prints its name before touching the GPU.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pfk():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1511_07226_amd as pfk
+    pfk.lib()
+    return pfk
+
+
+def _dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+CASES = [("fcg", "spd", "jacobi_pcg", 2), ("pipefcg", "spd", "jacobi_pcg", 2),
+         ("gcr", "conv", "jacobi_gmres", 3), ("pipegcr", "conv", "jacobi_gmres", 3),
+         ("pipegcr_w", "conv", "jacobi", 1), ("pipefcg", "spd", "block_jacobi_pcg", 3)]
+
+
+def _problem(kind):
+    return gen.config_problem("cfg1", seed=1) if kind == "spd" else gen.make_problem(3, 18, 4, 2.0, 2,
+                                                                                      convection=True)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{m}-{p}-{k}" for m, _, p, k in CASES])
+def test_natural_history_parity(pfk, case):
+    method, kind, pc, k = case
+    _say("natural history", method, kind, pc, k)
+    p = _problem(kind)
+    Ao = oracle.StencilOperator(p.dim, p.n, p.eta, p.vel)
+    ref = oracle.solve(method, Ao, oracle.make_pc(pc, Ao, k, block=8), p.b, rtol=0.0, maxit=20, nu_max=30)
+    Ag = pfk.Operator(p.dim, p.n, p.eta, p.vel)
+    info = pfk.solve(Ag, pfk.Precond(Ag, pc, k, block=8), method, _dev(p.b), _dev(np.zeros(Ao.N)), rtol=0.0,
+                     maxit=20, mmax=30)
+    nr = np.array(ref.natural)
+    assert len(info.natural) == len(nr) == 21
+    assert (np.abs(info.natural - nr) / nr).max() <= 1e-9
+
+
+@pytest.mark.parametrize("case", CASES[:4], ids=[c[0] for c in CASES[:4]])
+def test_natural_norm_stopping(pfk, case):
+    method, kind, pc, k = case
+    _say("natural stopping", method)
+    p = _problem(kind)
+    Ao = oracle.StencilOperator(p.dim, p.n, p.eta, p.vel)
+    ref = oracle.solve(method, Ao, oracle.make_pc(pc, Ao, k), p.b, rtol=1e-6, maxit=800, nu_max=30,
+                       norm="natural")
+    Ag = pfk.Operator(p.dim, p.n, p.eta, p.vel)
+    for use_graph in (1, 0):
+        info = pfk.solve(Ag, pfk.Precond(Ag, pc, k), method, _dev(p.b), _dev(np.zeros(Ao.N)), rtol=1e-6,
+                         maxit=800, mmax=30, norm=1, use_graph=use_graph)
+        assert ref.converged and info.converged and info.status == 0
+        assert info.iterations == ref.iterations
+        assert info.natural[-1] <= 1e-6 * info.natural[0] < info.natural[-2]
+        assert abs(info.true_rel_resid - ref.true_rel_resid) <= 1e-6 * ref.true_rel_resid
+
+
+def test_natural_norm_edges(pfk):
+    _say("natural edges")
+    p = gen.make_problem(3, 12, 3, 2.0, 3, convection=True)
+    Ag = pfk.Operator(3, 12, p.eta, p.vel)
+    B = pfk.Precond(Ag, "jacobi", 1)
+    # GMRES types have no natural norm and ignore the option
+    info = pfk.solve(Ag, B, "fgmres", _dev(p.b), _dev(np.zeros(Ag.N)), rtol=1e-8, maxit=300, mmax=30, norm=1)
+    assert info.converged and len(info.natural) == 0 and info.true_rel_resid <= 1e-8
+    with pytest.raises(pfk.PfkError):
+        pfk.solve(Ag, B, "gcr", _dev(p.b), _dev(np.zeros(Ag.N)), norm=2)
+    # a zero right-hand side finishes at once with no natural norm
+    info = pfk.solve(Ag, B, "pipegcr", _dev(np.zeros(Ag.N)), _dev(np.zeros(Ag.N)), norm=1)
+    assert info.converged and info.iterations == 0 and len(info.natural) == 0
