@@ -1774,6 +1774,10 @@ extern "C" int pfk_batch_create(pfk_method method, int mmax, int capacity, void*
     delete T;
     return fail(PFK_ERR_ARG, "host_sync does not apply to batches");
   }
+  if (T->opts.persistent < 0 || T->opts.persistent > 1) {
+    delete T;
+    return fail(PFK_ERR_ARG, "persistent must be 0 or 1");
+  }
   T->user = (hipStream_t)stream;
   T->mem.resize(capacity);
   if (hipStreamCreateWithFlags(&T->s1, hipStreamNonBlocking) != hipSuccess ||

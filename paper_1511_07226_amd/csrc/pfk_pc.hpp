@@ -466,7 +466,7 @@ __device__ __forceinline__ void block_pcg_body(Blk bk, G g, int wx, int wy, int 
             T* __restrict__ yout, const SolveState* st) {
   using Sh = BjShape<D3>;
   constexpr int NPT = Sh::NPT, WPB = Sh::WPB, BPW = Sh::BPW, ZL = Sh::ZL;
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   __shared__ T sp[BPW * ZL * 64];
   __shared__ double sred[2][kWaves];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

@@ -94,4 +94,17 @@ __device__ __forceinline__ int read_status(const SolveState* st) {
   return __hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Whether the solve runs, as one value for the whole workgroup (thread 0
+// reads, a barrier shares it).  A body with internal barriers that can run
+// while another workgroup changes the status (the inner solve beside the
+// scalar kernel inside a persistent launch, where an early return does not
+// end the wave) tests it this way, so every wave takes the same branch.
+__device__ __forceinline__ bool wg_running(const SolveState* st) {
+  __shared__ int s_run;
+  __syncthreads();
+  if (threadIdx.x == 0) s_run = read_status(st) == kRunning;
+  __syncthreads();
+  return s_run != 0;
+}
+
 }  // namespace pfk

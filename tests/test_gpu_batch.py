@@ -63,11 +63,14 @@ CASES = [("pipefcg", "block_jacobi_pcg", 0, False), ("pipefcg", "block_jacobi_pc
          ("pipefgmres", "block_jacobi_pcg", 1, True), ("fcg", "none", 0, False)]
 
 
-@pytest.mark.parametrize("persistent", [0, 1], ids=["phased", "persistent"])
+FORMS = {0: "phased", 1: "persistent"}
+
+
+@pytest.mark.parametrize("persistent", [0, 1], ids=[FORMS[f] for f in (0, 1)])
 @pytest.mark.parametrize("case", CASES, ids=[f"{m}-{k}-{'mixed' if p else 'fp64'}" for m, k, p, _ in CASES])
 def test_members_identical_to_single_solves(pfk, case, persistent):
     method, kind, prec, conv = case
-    _say("batch identity", case, "persistent" if persistent else "phased")
+    _say("batch identity", case, FORMS[persistent])
     mem = _members(pfk, kind, prec, conv, tilings=[(64, 2048, 32), (32, 64, 7), (64, 5, 100)])
     sig = {}
     if method == "pipefgmres":
@@ -169,7 +172,7 @@ def test_batch_edge_cases(pfk):
         pfk.Batch("gcr", mmax=10, capacity=2)
 
 
-@pytest.mark.parametrize("persistent", [0, 1], ids=["phased", "persistent"])
+@pytest.mark.parametrize("persistent", [0, 1], ids=[FORMS[f] for f in (0, 1)])
 def test_solve_batched_uneven_systems(pfk, persistent):
     # (a grid of one or two blocks per axis with strong contrast makes the block
     # solve nearly the global few-step CG, under which PIPEFCG stagnates in the
@@ -206,6 +209,21 @@ def test_persistent_barrier_timeout_is_reported(pfk):
     with pytest.raises(RuntimeError):
         T.poll()
     T.close()
+
+
+@pytest.mark.skip(reason="a persistent form driven by per-system completion counters (work items "
+                         "from one ticket counter) did not finish its first launch on the GPU; the "
+                         "cause was not found, so the form was taken out and the library refuses "
+                         "persistent = 2")
+def test_members_identical_dataflow_form(pfk):
+    _say("batch identity dataflow")
+    raise AssertionError("not built")
+
+
+def test_unknown_persistent_form_is_refused(pfk):
+    _say("persistent form 2 refused")
+    with pytest.raises(RuntimeError):
+        pfk.Batch("pipefcg", mmax=20, capacity=2, persistent=2)
 
 
 def test_solve_batched_caller_workspace(pfk):
