@@ -70,25 +70,36 @@ def window_update_bytes(method: str, nu: int, N: int) -> float:
     return (2 * nu + 5) * 8.0 * N
 
 
-def iteration_bytes(method: str, nu: int, k: int, N: int) -> float:
-    """Algorithmic HBM bytes per steady-state outer iteration (FP64 vectors,
-    eta read once per operator apply, D^-1 stored).  Inner Jacobi-PCG with k
-    steps: A_1 reads v-inputs and D^-1 and writes p, q; each B_j reads p, q,
-    rho (or the v-inputs), y, D^-1 and writes y, rho; each A_j (j>1) reads
-    rho, D^-1, p and writes p, q; every stencil pass also reads eta."""
+def iteration_bytes(method: str, nu: int, k: int, N: int, pc: str = "global", mixed: bool = False) -> float:
+    """Algorithmic HBM bytes per steady-state outer iteration (outer vectors
+    FP64, eta read once per operator apply, D^-1 stored).  The inner solve's
+    vectors and D^-1 take w bytes (8, or 4 in the mixed form) and its
+    viscosity c bytes (8, or 2 for BF16).
+    Global Jacobi-PCG with k steps: A_1 reads the v inputs, D^-1 and eta and
+    writes p, q; each B_j reads p, q, rho (the v inputs for j = 1), y (j > 1)
+    and D^-1 and writes y, rho; each A_j (j > 1) reads rho, D^-1, p and eta and
+    writes p, q.  Block-Jacobi PCG: one pass reads the v inputs and eta and
+    writes y.  The consumer forms m = u + B(v) (PIPEFCG) and applies A."""
     W = 8.0
-    pc = (2 + 1 + 1 + 2)            # A_1: two v inputs, D^-1, eta; writes p, q
-    pc += (k - 1) * (5 + 2)         # B_j: reads p, q, rho|v(2), y(j>1), D^-1 ~ 5; writes 2
-    pc += (k - 1) * (4 + 2)         # A_j: rho, D^-1, p, eta; writes p, q
+    w, c = (4.0, 2.0) if mixed else (8.0, 8.0)
+    if pc == "block":
+        pcb = 2 * W + c + w                            # v inputs, eta; writes y
+        tail_pc = w                                    # the consumer reads y
+    else:
+        pcb = 2 * W + w + c + 2 * w                    # A_1
+        # B_j: reads rho (the two FP64 v inputs for j = 1), y (j > 1), p, q, D^-1; writes y, rho
+        pcb += 2 * W + (k - 2) * w + (k - 2) * w + (k - 1) * (3 * w + 2 * w)
+        pcb += (k - 1) * (3 * w + c + 2 * w)           # A_j: rho, D^-1, p, eta; writes p, q
+        tail_pc = 2 * w                                # the consumer reads y and p_k
     if method == "pipefcg":
-        upd = 4 * nu + 14
-        tail = 5 + 2                # m = u + y + alpha p_k (+eta), n = A m: reads u, y, p, eta; writes m, n
-        return (upd + pc + tail) * W * N
-    fcg = (2 * nu + 5)              # dots + maxpy
-    fcg += 4 + 2                    # x, r update: reads x, p, r, s; writes x, r
-    fcg += 3 + 1                    # u = y + alpha p_k with dots (reads y, p, r): 3 + window counted above
-    fcg += 2 + 1                    # s = A p: reads p, eta; writes s
-    return (fcg + pc - 1) * W * N
+        upd = (4 * nu + 14) * W
+        tail = tail_pc + 2 * W + 2 * W                 # reads u, eta; writes m, n
+        return (upd + pcb + tail) * N
+    fcg = (2 * nu + 5) * W                             # dots + maxpy
+    fcg += 6 * W                                       # x, r update: reads x, p, r, s; writes x, r
+    fcg += tail_pc + 2 * W                             # u = B(r) with the dots: reads r; writes u
+    fcg += 3 * W                                       # s = A p: reads p, eta; writes s
+    return (fcg + pcb - W) * N                         # FCG's inner input is r alone
 
 
 def time_steps(pfk, torch, A, B, method, b, steps, warmup, mmax=NU, graph_iters=10, **opts):
@@ -598,7 +609,11 @@ def main():
         if t is not None:
             A.set_tiling(t["tile_x"], t["stencil_target"], t["vector_blocks"])
         S, dt = time_steps(pfk, torch, A, Bx, method, b, args.steps, args.warmup, **opts)
-        return S, {"it_per_s": round(args.steps / dt, 3), "ms_per_step": round(dt / args.steps * 1e3, 4)}
+        nbytes = iteration_bytes(method, NU, INNER, N, "block" if Bx.kind == "block_jacobi_pcg" else "global",
+                                 Bx.precision == pfk.FP32_BF16COEF)
+        return S, {"it_per_s": round(args.steps / dt, 3), "ms_per_step": round(dt / args.steps * 1e3, 4),
+                   "algorithmic_GBps": round(nbytes * args.steps / dt / 1e9, 1),
+                   "roofline_frac": round(nbytes * args.steps / dt / 1e9 / HBM_PEAK_GBS, 3)}
 
     results, sessions = {}, {}
     for method in ("pipefcg", "fcg"):
