@@ -186,6 +186,35 @@ def persistent_rate(pfk, torch, A, B, method, b, steps, warmup):
     return steps / dt
 
 
+def conv_diff_bench(pfk, torch, steps, warmup):
+    """Configuration 3: 256^3 convection-diffusion sinker, outer FP64, inner
+    GMRES(5) in FP32 on BF16 viscosity.  The GMRES types are timed over whole
+    restart cycles (each followed by its restart's start-up), the CR types
+    over steady-state iterations."""
+    import gen
+    log("generating the 256^3 convection-diffusion workload")
+    p3 = gen.config_problem("cfg3", seed=0)
+    A3 = pfk.Operator(p3.dim, p3.n, p3.eta, p3.vel)
+    B3 = pfk.Precond(A3, "jacobi_gmres", INNER, precision=pfk.FP32_BF16COEF)
+    b3 = torch.as_tensor(p3.b).cuda()
+    del p3
+    sigma = pfk.estimate_sigma(A3, B3)
+    cycles = max(1, math.ceil(steps / NU))
+    conv = {"workload": "256^3 conv-diff sinker (cell Peclet 5), outer FP64, B = GMRES(5) FP32/BF16",
+            "sigma": sigma}
+    for method in ("pipefgmres", "fgmres"):
+        log(f"timing {method}: {cycles} cycles of {NU}")
+        opts = {"shift_sigma": sigma} if method == "pipefgmres" else {}
+        dt = time_cycles(pfk, torch, A3, B3, method, b3, cycles, NU, **opts)
+        conv[method] = {"it_per_s": round(cycles * NU / dt, 3), "ms_per_step": round(dt / (cycles * NU) * 1e3, 4)}
+    for method in ("pipegcr", "pipegcr_w", "gcr"):
+        log(f"timing {method}")
+        S, dt = time_steps(pfk, torch, A3, B3, method, b3, steps, warmup)
+        S.close()
+        conv[method] = {"it_per_s": round(steps / dt, 3), "ms_per_step": round(dt / steps * 1e3, 4)}
+    return conv
+
+
 def size_sweep(pfk, torch, steps=40):
     """PIPEFCG against FCG per outer iteration on single systems of growing size
     (block-Jacobi inner solve, FP64, nu_max 30), in the graph-launched form and
@@ -569,6 +598,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-stagnation", action="store_true")
+    ap.add_argument("--conv-diff-only", action="store_true",
+                    help="headline plus the 256^3 convection-diffusion comparison")
     ap.add_argument("--stagnation-only", action="store_true",
                     help="headline plus the noisy-preconditioner stagnation study")
     args = ap.parse_args()
@@ -647,6 +678,9 @@ def main():
     if args.stagnation_only:
         args.headline_only = True
         extra["stagnation_study"] = stagnation_study(pfk, torch)
+    if args.conv_diff_only:
+        args.headline_only = True
+        extra["conv_diff_256"] = conv_diff_bench(pfk, torch, args.steps, args.warmup)
     if not args.headline_only:
         # unpipelined baseline with a blocking (host-synchronised) reduction
         log("timing fcg host-sync")
@@ -690,29 +724,7 @@ def main():
         extra["time_to_solution_rtol1e-8"] = tts
         del xs, A2, b2, p2
 
-        # config 3: 256^3 convection-diffusion, GMRES(5) inner solve in FP32 on BF16 viscosity
-        log("generating the 256^3 convection-diffusion workload")
-        p3 = gen.config_problem("cfg3", seed=0)
-        A3 = pfk.Operator(p3.dim, p3.n, p3.eta, p3.vel)
-        B3 = pfk.Precond(A3, "jacobi_gmres", INNER, precision=pfk.FP32_BF16COEF)
-        b3 = torch.as_tensor(p3.b).cuda()
-        del p3
-        sigma = pfk.estimate_sigma(A3, B3)
-        cycles = max(1, math.ceil(args.steps / NU))
-        conv = {"workload": "256^3 conv-diff sinker (cell Peclet 5), outer FP64, B = GMRES(5) FP32/BF16",
-                "sigma": sigma}
-        for method in ("pipefgmres", "fgmres"):
-            log(f"timing {method}: {cycles} cycles of {NU}")
-            opts = {"shift_sigma": sigma} if method == "pipefgmres" else {}
-            dt = time_cycles(pfk, torch, A3, B3, method, b3, cycles, NU, **opts)
-            conv[method] = {"it_per_s": round(cycles * NU / dt, 3), "ms_per_step": round(dt / (cycles * NU) * 1e3, 4)}
-        for method in ("pipegcr", "pipegcr_w", "gcr"):
-            log(f"timing {method}")
-            S, dt = time_steps(pfk, torch, A3, B3, method, b3, args.steps, args.warmup)
-            S.close()
-            conv[method] = {"it_per_s": round(args.steps / dt, 3), "ms_per_step": round(dt / args.steps * 1e3, 4)}
-        extra["conv_diff_256"] = conv
-        del A3, B3, b3
+        extra["conv_diff_256"] = conv_diff_bench(pfk, torch, args.steps, args.warmup)
 
     if not args.headline_only and not args.no_stagnation:
         log("stagnation study (section 2.2.1 at scale)")
