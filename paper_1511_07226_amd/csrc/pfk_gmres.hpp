@@ -287,6 +287,9 @@ k_pgm_scalars(const double* part, int P, SolveState* st, double* hist) {
 //   zbar_n = (wbar_{n-1} - sigma zbar_{n-1} - sum_j hbar_j zbar_j) / h
 // into slot n (zbar_n also to zin), and the next single reduction:
 // <p_j, zbar_n> for j <= n and ||zbar_n||^2.
+// As in PIPEFCG's update, each lane owns two consecutive nodes (16-byte
+// accesses) and the window loops are unrolled so that several independent
+// loads are in flight; the dot with p_j reuses the p_j load.
 __device__ __forceinline__ void pgm_update_body(Blk bk, long long N, Window P, Window U, Window ZB, PcOutDesc pd, const double* __restrict__ wb,
              double* __restrict__ zin, double* part, SolveState* st) {
   if (read_status(st) != kRunning) return;
@@ -305,33 +308,54 @@ __device__ __forceinline__ void pgm_update_body(Blk bk, long long N, Window P, W
   double* un = U.slot(n);
   double* zn = ZB.slot(n);
   double dp = 0.0, zz = 0.0;
+  const long long npair = (N + 1) / 2;
   // wave-uniform trip count (wave sums inside); lanes past the end use
   // element 0, contribute 0 and store nothing
-  for (long long ew = bk.gtid() - lane; ew < N; ew += bk.gstride()) {
-    const bool act = ew + lane < N;
-    const long long e = act ? ew + lane : 0;
-    double z = wb[e] - sigma * zprev[e];
-    for (int j = 0; j < n; ++j) z -= s_h[j] * ZB.base[(long long)j * ZB.ld + e];
-    z *= inv;
-    if (!act) z = 0.0;
-    double p = zprev[e];
+  for (long long qw = bk.gtid() - lane; qw < npair; qw += bk.gstride()) {
+    const bool act = qw + lane < npair;
+    const long long e = act ? 2 * (qw + lane) : 0;
+    const bool full = act && e + 1 < N;
+    const double2 zp = ld2(zprev, e, full), wv = ld2(wb, e, full);
+    double2 z = make_double2(wv.x - sigma * zp.x, wv.y - sigma * zp.y);
+#pragma unroll 4
     for (int j = 0; j < n; ++j) {
-      const double pj = P.base[(long long)j * P.ld + e];
-      p -= s_h[j] * pj;
-      const double d = wave_sum(pj * z);
+      const double h = s_h[j];
+      const double2 zj = ld2(ZB.base, (long long)j * ZB.ld + e, full);
+      z.x -= h * zj.x;
+      z.y -= h * zj.y;
+    }
+    z.x *= inv;
+    z.y *= inv;
+    if (!act) z = make_double2(0.0, 0.0);
+    double2 p = zp;
+#pragma unroll 4
+    for (int j = 0; j < n; ++j) {
+      const double h = s_h[j];
+      const double2 pj = ld2(P.base, (long long)j * P.ld + e, full);
+      p.x -= h * pj.x;
+      p.y -= h * pj.y;
+      const double d = wave_sum(pj.x * z.x + pj.y * z.y);
       if (lane == 0) s_dot[wid][j] += d;
     }
-    p *= inv;
-    double u = pc(e);
-    for (int j = 0; j < n; ++j) u -= s_h[j] * U.base[(long long)j * U.ld + e];
-    u *= inv;
+    p.x *= inv;
+    p.y *= inv;
+    double2 u = make_double2(pc(e), full ? pc(e + 1) : 0.0);
+#pragma unroll 4
+    for (int j = 0; j < n; ++j) {
+      const double h = s_h[j];
+      const double2 uj = ld2(U.base, (long long)j * U.ld + e, full);
+      u.x -= h * uj.x;
+      u.y -= h * uj.y;
+    }
+    u.x *= inv;
+    u.y *= inv;
     if (!act) continue;
-    pn[e] = p;
-    un[e] = u;
-    zn[e] = z;
-    zin[e] = z;
-    dp += p * z;
-    zz += z * z;
+    st2(pn, e, p, full);
+    st2(un, e, u, full);
+    st2(zn, e, z, full);
+    st2(zin, e, z, full);
+    dp += p.x * z.x + p.y * z.y;
+    zz += z.x * z.x + z.y * z.y;
   }
   {
     const double a0 = wave_sum(dp), a1 = wave_sum(zz);
