@@ -594,7 +594,7 @@ PcOutDesc pc_out_desc(const pfk_session_s* S, const double* X1, double c1, const
   } else if (d.kind == kPcBlockPcg) {
     d.y = S->vec(V_PC_Y);
   } else if (d.kind == kPcJacobiGmres) {
-    // G0, (GA_j, GO_j): every GO_j writes PC0
+    // G0 and every GO_j write PC0: the final norm the consumer reads
     d.part = S->part(PT_PC0);
     d.P = S->Pv();
     d.vbase = S->win(W_PCV).base;
@@ -645,17 +645,14 @@ void enqueue_pc_kernels(pfk_session_s* S, hipStream_t s, const PcOutDesc& d, con
     T* V = (T*)S->win(W_PCV).base;
     const long long ldv = S->L.ld;
     T* w = (T*)S->vec(V_PC_Q);
+    // G0 and every GO_j write PC0 (the norm GA_j reads); every GD_j writes PC1
     LAUNCH((k_gmpc_start<T>), S->Pv(), s, A->N, d.k, X1, c1, X2, c2, V, part[0], S->st);
-    int t = 1, Pprev = S->Pv();
     for (int j = 0; j < d.k; ++j) {
-      LAUNCH((k_gmpc_apply<T, G>), S->Ps(), s, j, g, S->sg, dinv, (const T*)V, ldv, w,
-             (const double*)part[(t - 1) & 1], Pprev, part[t & 1], S->st);
-      Pprev = S->Ps();
-      ++t;
-      LAUNCH((k_gmpc_orth<T>), S->Pv(), s, j, d.k, A->N, V, ldv, (const T*)w, (const double*)part[(t - 1) & 1],
-             Pprev, part[t & 1], S->st);
-      Pprev = S->Pv();
-      ++t;
+      LAUNCH((k_gmpc_apply<T, G>), S->Ps(), s, j, g, S->sg, dinv, (const T*)V, ldv, w, (const double*)part[0],
+             S->Pv(), S->st);
+      LAUNCH((k_gmpc_dots<T>), S->Pv(), s, j, A->N, (const T*)V, ldv, (const T*)w, part[1], S->st);
+      LAUNCH((k_gmpc_orth<T>), S->Pv(), s, j, d.k, A->N, V, ldv, (const T*)w, (const double*)part[1], S->Pv(),
+             part[0], S->st);
     }
   }
 }
