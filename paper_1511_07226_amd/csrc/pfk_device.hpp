@@ -63,27 +63,54 @@ __device__ __forceinline__ T harmonic(T a, T b) { return T(2) * a * b / (a + b);
 // (if g.vel): first-order upwind flux h^-1 sum_f (max(v_f,0) u_c +
 // min(v_f,0) u_nb) with v_f the outward normal velocity.  Faces are taken in
 // the order x+, x-, y+, y-, z+, z-.
+// (A u) at a node from its value uc, its six neighbour values (0 on the
+// Dirichlet boundary) and the viscosities at the node and its neighbours, in
+// arithmetic type T.  Diffusion: h^-2 sum_f k_f (u_c - u_nb) with k_f the
+// harmonic mean of eta; convection (if the operator has face velocities):
+// first-order upwind flux h^-1 sum_f (max(v_f,0) u_c + min(v_f,0) u_nb) with
+// v_f the outward normal velocity.  Faces are taken in the order x+, x-, y+,
+// y-, z+, z-.  The two parts are separate so that every form of the operator
+// (velocities loaded here or ahead of use) rounds alike.
 template <class T, class G>
-__device__ __forceinline__ T apply_faces(const G& g, long long pc, T uc, T ec, T exp_, T exm, T eyp, T eym,
-                                         T ezp, T ezm, T uxp, T uxm, T uyp, T uym, T uzp, T uzm) {
+__device__ __forceinline__ T faces_diffusion(const G& g, T uc, T ec, T exp_, T exm, T eyp, T eym, T ezp, T ezm,
+                                             T uxp, T uxm, T uyp, T uym, T uzp, T uzm) {
   T acc = harmonic(ec, exp_) * (uc - uxp) + harmonic(ec, exm) * (uc - uxm) +
           harmonic(ec, eyp) * (uc - uyp) + harmonic(ec, eym) * (uc - uym);
   if (g.dim == 3) acc += harmonic(ec, ezp) * (uc - uzp) + harmonic(ec, ezm) * (uc - uzm);
-  acc *= T(g.h2inv);
+  return acc * T(g.h2inv);
+}
+// The upwind sum (before the h^-1 factor) from the node's face velocities
+// vx(p), vx(p - e_x), vy(p), vy(p - e_y), vz(p), vz(p - e_z).
+template <class T, class G>
+__device__ __forceinline__ T faces_convection(const G& g, T uc, T uxp, T uxm, T uyp, T uym, T uzp, T uzm, T vxp,
+                                              T vxm, T vyp, T vym, T vzp, T vzm) {
+  const T zero = T(0);
+  T c = zero, v;
+  v = vxp;   c += fmax(v, zero) * uc + fmin(v, zero) * uxp;
+  v = -vxm;  c += fmax(v, zero) * uc + fmin(v, zero) * uxm;
+  v = vyp;   c += fmax(v, zero) * uc + fmin(v, zero) * uyp;
+  v = -vym;  c += fmax(v, zero) * uc + fmin(v, zero) * uym;
+  if (g.dim == 3) {
+    v = vzp;   c += fmax(v, zero) * uc + fmin(v, zero) * uzp;
+    v = -vzm;  c += fmax(v, zero) * uc + fmin(v, zero) * uzm;
+  }
+  return c;
+}
+
+// The whole operator at the node with padded index pc, velocities (if any)
+// loaded here.
+template <class T, class G>
+__device__ __forceinline__ T apply_faces(const G& g, long long pc, T uc, T ec, T exp_, T exm, T eyp, T eym,
+                                         T ezp, T ezm, T uxp, T uxm, T uyp, T uym, T uzp, T uzm) {
+  T acc = faces_diffusion<T>(g, uc, ec, exp_, exm, eyp, eym, ezp, ezm, uxp, uxm, uyp, uym, uzp, uzm);
   if (g.vel != nullptr) {
     const auto* vx = g.vel;
     const auto* vy = g.vel + g.vstride;
     const auto* vz = g.vel + 2 * g.vstride;
-    const T zero = T(0);
-    T c = zero, v;
-    v = T(to_real(vx[pc]));            c += fmax(v, zero) * uc + fmin(v, zero) * uxp;
-    v = -T(to_real(vx[pc - 1]));       c += fmax(v, zero) * uc + fmin(v, zero) * uxm;
-    v = T(to_real(vy[pc]));            c += fmax(v, zero) * uc + fmin(v, zero) * uyp;
-    v = -T(to_real(vy[pc - g.sy]));    c += fmax(v, zero) * uc + fmin(v, zero) * uym;
-    if (g.dim == 3) {
-      v = T(to_real(vz[pc]));          c += fmax(v, zero) * uc + fmin(v, zero) * uzp;
-      v = -T(to_real(vz[pc - g.sz]));  c += fmax(v, zero) * uc + fmin(v, zero) * uzm;
-    }
+    const bool d3 = g.dim == 3;
+    const T c = faces_convection<T>(g, uc, uxp, uxm, uyp, uym, uzp, uzm, T(to_real(vx[pc])),
+                                    T(to_real(vx[pc - 1])), T(to_real(vy[pc])), T(to_real(vy[pc - g.sy])),
+                                    d3 ? T(to_real(vz[pc])) : T(0), d3 ? T(to_real(vz[pc - g.sz])) : T(0));
     acc += T(g.hinv) * c;
   }
   return acc;
@@ -180,7 +207,13 @@ __device__ __forceinline__ char* stencil_lds() {
   return buf;
 }
 
-template <int TX, class T, class G, class In, class Sink>
+// CV: the operator has face velocities, and they are loaded one plane step
+// ahead into registers like the column's u and eta (the z- face of a plane is
+// the z+ face of the one below, kept from the previous step).  Without CV a
+// convective operator still works: apply_faces then loads the velocities
+// when it needs them.  CV kernels are separate instantiations, so the
+// diffusion kernels do not carry the extra registers.
+template <int TX, bool CV, class T, class G, class In, class Sink>
 __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& sg, int bid, const In& in,
                                                 Sink& sink) {
   using S = TileShape<TX>;
@@ -240,6 +273,30 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
     ep[r] = d3 ? E(r, k0 + 1) : zero;
   }
   T hu = HU(k0), he = HE(k0);
+  // face velocities of the centre column (CV): x+, x-, y+, y-, z+ of the
+  // current plane, of the next one in flight, and z- of the current plane
+  T vc[2][5], vn[2][5], vzm[2];
+  auto VL = [&](int r, int k, T (&v)[5]) {
+    const T zero_ = T(0);
+#pragma unroll
+    for (int f = 0; f < 5; ++f) v[f] = zero_;
+    if (valid[r]) {
+      const long long pc = padded_index(g, i, jr[r], k);
+      v[0] = T(to_real(g.vel[pc]));
+      v[1] = T(to_real(g.vel[pc - 1]));
+      v[2] = T(to_real(g.vel[g.vstride + pc]));
+      v[3] = T(to_real(g.vel[g.vstride + pc - g.sy]));
+      if (d3) v[4] = T(to_real(g.vel[2 * g.vstride + pc]));
+    }
+  };
+  if constexpr (CV) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      if (k0 < k1) VL(r, k0, vc[r]);
+      vzm[r] = (d3 && valid[r] && k0 < k1) ? T(to_real(g.vel[2 * g.vstride + padded_index(g, i, jr[r], k0) - g.sz]))
+                                           : zero;
+    }
+  }
   for (int k = k0; k < k1; ++k) {
     // in flight during this step: plane k+2 of the column, the halo of plane k+1
     T upp[2], epp[2];
@@ -251,6 +308,12 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
     }
     const T hu_n = more ? HU(k + 1) : zero;
     const T he_n = more ? HE(k + 1) : zero;
+    if constexpr (CV) {
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        if (more) VL(r, k + 1, vn[r]);
+      }
+    }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
@@ -266,11 +329,25 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
     for (int r = 0; r < 2; ++r) {
       if (valid[r]) {
         const int rr = row[r] + 1;
-        const long long pc = padded_index(g, i, jr[r], k);
-        const T Au = apply_faces<T>(g, pc, uc[r], ec[r], se[rr][xo + 2], se[rr][xo], se[rr + 1][xo + 1],
-                                    se[rr - 1][xo + 1], ep[r], em[r], su[rr][xo + 2], su[rr][xo],
-                                    su[rr + 1][xo + 1], su[rr - 1][xo + 1], up[r], um[r]);
+        T Au;
+        if constexpr (CV) {
+          const T uxp = su[rr][xo + 2], uxm = su[rr][xo], uyp = su[rr + 1][xo + 1], uym = su[rr - 1][xo + 1];
+          Au = faces_diffusion<T>(g, uc[r], ec[r], se[rr][xo + 2], se[rr][xo], se[rr + 1][xo + 1],
+                                  se[rr - 1][xo + 1], ep[r], em[r], uxp, uxm, uyp, uym, up[r], um[r]);
+          Au += T(g.hinv) * faces_convection<T>(g, uc[r], uxp, uxm, uyp, uym, up[r], um[r], vc[r][0], vc[r][1],
+                                                vc[r][2], vc[r][3], vc[r][4], vzm[r]);
+        } else {
+          const long long pc = padded_index(g, i, jr[r], k);
+          Au = apply_faces<T>(g, pc, uc[r], ec[r], se[rr][xo + 2], se[rr][xo], se[rr + 1][xo + 1],
+                              se[rr - 1][xo + 1], ep[r], em[r], su[rr][xo + 2], su[rr][xo], su[rr + 1][xo + 1],
+                              su[rr - 1][xo + 1], up[r], um[r]);
+        }
         sink(vec_index(g, i, jr[r], k), uc[r], Au);
+      }
+      if constexpr (CV) {
+        vzm[r] = vc[r][4];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) vc[r][f] = vn[r][f];
       }
       um[r] = uc[r];
       uc[r] = up[r];
@@ -284,14 +361,14 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
   }
 }
 
-template <class T, class G, class In, class Sink>
+template <class T, bool CV = false, class G, class In, class Sink>
 __device__ __forceinline__ void stencil_march(const G& g, const StencilGeom& sg, int bid, const In& in, Sink& sink) {
-  if (sg.tx == 32) stencil_march_t<32, T>(g, sg, bid, in, sink);
-  else stencil_march_t<64, T>(g, sg, bid, in, sink);
+  if (sg.tx == 32) stencil_march_t<32, CV, T>(g, sg, bid, in, sink);
+  else stencil_march_t<64, CV, T>(g, sg, bid, in, sink);
 }
-template <class T, class G, class In, class Sink>
+template <class T, bool CV = false, class G, class In, class Sink>
 __device__ __forceinline__ void stencil_march(const G& g, const StencilGeom& sg, const In& in, Sink& sink) {
-  stencil_march<T>(g, sg, (int)blockIdx.x, in, sink);
+  stencil_march<T, CV>(g, sg, (int)blockIdx.x, in, sink);
 }
 
 // ---------------------------------------------------------------------------

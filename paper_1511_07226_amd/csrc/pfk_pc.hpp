@@ -314,7 +314,7 @@ k_gmpc_start(long long N, int k, const double* X1, double c1, const double* X2, 
 // GA_j: scale of V_j from the previous norm (a zero norm ends the cycle:
 // beta = 0 gives B(v) = 0, a zero subdiagonal is a happy breakdown), then
 // w = A D^-1 V_j and partials <stored V_i, w> for i <= j.
-template <class T, class G>
+template <class T, class G, bool CV = false>
 __global__ void __launch_bounds__(kBlock)
 k_gmpc_apply(int jstep, G g, StencilGeom sg, const T* __restrict__ dinv, const T* Vbase,
              long long ldv, T* __restrict__ w, const double* part_in, int P_in, SolveState* st) {
@@ -333,7 +333,7 @@ k_gmpc_apply(int jstep, G g, StencilGeom sg, const T* __restrict__ dinv, const T
   const T* Vj = Vbase + (long long)jstep * ldv;
   auto in = [&](long long t) { return dinv[t] * (sj * Vj[t]); };
   auto sink = [&](long long idx, T, T Au) { w[idx] = Au; };
-  stencil_march<T>(g, sg, in, sink);
+  stencil_march<T, CV>(g, sg, in, sink);
 }
 
 // GD_j: partials <stored V_i, w> for i <= j.  A streaming pass of its own:
