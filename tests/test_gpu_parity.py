@@ -216,3 +216,53 @@ def test_deterministic_and_graph_equals_direct(pfk):
         hs.append(info.history)
     for h in hs[1:]:
         assert np.array_equal(h, hs[0])
+
+
+@pytest.mark.parametrize("dim,n", [(3, 1), (3, 2), (2, 1), (2, 3), (3, 9)])
+@pytest.mark.parametrize("method", ["fcg", "pipefcg", "gcr", "pipegcr", "fgmres", "pipefgmres"])
+def test_tiny_grids(pfk, dim, n, method):
+    # degenerate sizes: one node, a single ragged tile, fewer nodes than a wave
+    _say("tiny grid", dim, n, method)
+    prob = gen.make_problem(dim, n, 2, 2.0, seed=n, convection=(dim == 3 and method in ("gcr", "pipegcr",
+                                                                                          "fgmres", "pipefgmres")))
+    for kind, k in (("jacobi", 1), ("block_jacobi_pcg", 3)):
+        Ao = oracle.StencilOperator(prob.dim, n, prob.eta, prob.vel)
+        sigma = None
+        Bo = oracle.make_pc(kind, Ao, k, block=8)
+        if method == "pipefgmres":
+            sigma = oracle.estimate_sigma(Ao.apply, Bo, Ao.N)
+        ref = oracle.solve(method, Ao, Bo, prob.b, rtol=1e-10, maxit=400, nu_max=30, sigma=sigma)
+        Ag = pfk.Operator(prob.dim, n, prob.eta, prob.vel)
+        Bg = pfk.Precond(Ag, kind, k, block=8)
+        x = _dev(np.zeros(Ao.N))
+        opts = {"shift_sigma": float(sigma)} if sigma is not None else {}
+        info = pfk.solve(Ag, Bg, method, _dev(prob.b), x, rtol=1e-10, maxit=400, mmax=30, **opts)
+        assert ref.converged and info.converged, (kind, info, ref.status)
+        # when the Krylov space is exhausted (iteration N), whether a pipelined
+        # method sees a breakdown (a restart) or converges is decided by the sign
+        # of a rounding-level quantity (PIPEFGMRES's t); iteration counts are
+        # compared only when both sides took the same path
+        if info.restarts == ref.restarts:
+            assert abs(info.iterations - ref.iterations) <= 2, (kind, info.iterations, ref.iterations)
+        # histories agree to 1e-8, or to 1e3 times the oracle's own change under
+        # a rounding-level perturbation of b where that is larger: as a tiny
+        # system's Krylov space runs out, the pipelined recurrences cancel
+        # (PIPEFGMRES's t = zeta - sum hbar^2 above all) and a step can amplify
+        # rounding by many orders; beyond that point only rounding noise is left
+        m = min(len(info.history), len(ref.history), 21)
+        hr = np.array(ref.history)[:m]
+        sens = np.zeros(m)
+        rng = np.random.default_rng(0)
+        keep = hr > 1e-6 * hr[0]          # exact zeros (one-node grids) are left out
+        safe = np.where(keep, hr, 1.0)
+        for _ in range(3):
+            b1 = prob.b * (1.0 + 1e-15 * rng.standard_normal(prob.b.shape))
+            h1 = np.array(oracle.solve(method, Ao, Bo, b1, rtol=1e-10, maxit=400, nu_max=30,
+                                       sigma=sigma).history)[:m]
+            k = min(len(h1), m)
+            sens[:k] = np.maximum(sens[:k], np.abs(h1[:k] - hr[:k]) / safe[:k])
+        rel = np.abs(info.history[:m] - hr) / safe
+        assert np.all((rel <= np.maximum(1e-8, 1e3 * sens))[keep]), (rel, sens)
+        xs = np.linalg.solve(np.array([Ao.apply(e) for e in np.eye(Ao.N)]).T, prob.b)
+        assert np.linalg.norm(_host(x) - xs) <= 1e-8 * np.linalg.norm(xs) * max(1.0, np.linalg.cond(
+            np.array([Ao.apply(e) for e in np.eye(Ao.N)]).T))
