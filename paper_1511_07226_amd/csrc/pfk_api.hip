@@ -732,7 +732,7 @@ void enqueue_cg_body(pfk_session_s* S, hipStream_t s, int init) {
     LAUNCH(k_cg_scalars2, 1, s, 0, init, S->part(PT_A), S->Ps(), S->st);
     host_wait(S, s);
   } else {
-    LAUNCH_OP(S->A, k_apply_pc_out, S->Ps(), s, g, S->sg, pd, (const double*)nullptr, 0.0, S->vec(V_U), S->vec(V_W), 0,
+    LAUNCH(k_apply_pc_out, S->Ps(), s, g, S->sg, pd, (const double*)nullptr, 0.0, S->vec(V_U), S->vec(V_W), 0,
            (const double*)nullptr, S->part(PT_B), S->st);
     enqueue_multidot(S, s, init, 0, pd, S->vec(V_W), nullptr);
     LAUNCH(k_cg_scalars1, 1, s, init, S->part(PT_MAIN), S->Pv(), S->st, S->hist);
@@ -766,11 +766,11 @@ void enqueue_start(pfk_session_s* S, hipStream_t s) {
       // PIPEGCR_w (p_0 = u_0, s_0 = w_0): gamma_0 = <r_0,s_0>, eta_0 = <s_0,s_0>
       const int dots = S->method == PFK_PIPEGCR_W ? 2 : 1;
       PcOutDesc pd = enqueue_pc(S, s, S->vec(V_R), 1.0, nullptr, 0.0);
-      LAUNCH_OP(S->A, k_apply_pc_out, S->Ps(), s, g, S->sg, pd, (const double*)nullptr, 0.0, S->vec(V_U), S->vec(V_W), dots,
+      LAUNCH(k_apply_pc_out, S->Ps(), s, g, S->sg, pd, (const double*)nullptr, 0.0, S->vec(V_U), S->vec(V_W), dots,
              (const double*)S->vec(V_R), S->part(PT_B), S->st);
       // m_0 = B(w_0), n_0 = A m_0
       pd = enqueue_pc(S, s, S->vec(V_W), 1.0, nullptr, 0.0);
-      LAUNCH_OP(S->A, k_apply_pc_out, S->Ps(), s, g, S->sg, pd, (const double*)nullptr, 0.0, S->vec(V_M), S->vec(V_N), 0,
+      LAUNCH(k_apply_pc_out, S->Ps(), s, g, S->sg, pd, (const double*)nullptr, 0.0, S->vec(V_M), S->vec(V_N), 0,
              (const double*)nullptr, S->part(PT_B), S->st);
       LAUNCH(k_pipefcg_init_scalars, 1, s, S->part(PT_A), S->Ps(), S->part(PT_B), S->Ps(), S->st, S->hist);
       break;
@@ -779,7 +779,7 @@ void enqueue_start(pfk_session_s* S, hipStream_t s) {
       LAUNCH(k_init_test, 1, s, S->part(PT_A), S->Ps(), S->st, S->hist);
       // u_0 = B(r_0), s_0 = A u_0 (kept in w), gamma_0 = <r_0,s_0>, eta_0 = <s_0,s_0>
       PcOutDesc pd = enqueue_pc(S, s, S->vec(V_R), 1.0, nullptr, 0.0);
-      LAUNCH_OP(S->A, k_apply_pc_out, S->Ps(), s, g, S->sg, pd, (const double*)nullptr, 0.0, S->vec(V_U), S->vec(V_W), 0,
+      LAUNCH(k_apply_pc_out, S->Ps(), s, g, S->sg, pd, (const double*)nullptr, 0.0, S->vec(V_U), S->vec(V_W), 0,
              (const double*)nullptr, S->part(PT_B), S->st);
       enqueue_multidot(S, s, 1, 0, pd, S->vec(V_W), nullptr);
       // q_0 = B(s_0), consumed by the first update
@@ -802,7 +802,7 @@ void enqueue_start(pfk_session_s* S, hipStream_t s) {
              S->part(PT_MAIN), S->st);
       // qbar_0 = B(zbar_0), wbar_0 = A qbar_0
       pd = enqueue_pc(S, s, S->vec(V_M), 1.0, nullptr, 0.0);
-      LAUNCH_OP(S->A, k_apply_pc_out, S->Ps(), s, g, S->sg, pd, (const double*)nullptr, 0.0, (double*)nullptr,
+      LAUNCH(k_apply_pc_out, S->Ps(), s, g, S->sg, pd, (const double*)nullptr, 0.0, (double*)nullptr,
              S->vec(V_Z), 0, (const double*)nullptr, S->part(PT_B), S->st);
       LAUNCH(k_pgm_scalars, 1, s, S->part(PT_MAIN), S->Ps(), S->st, S->hist);   // partials of k_pgm_apply0
       LAUNCH(k_gm_update_x, S->Pv(), s, A->N, S->win(W_S), (const double*)S->vec(V_X0), S->x,
@@ -842,7 +842,7 @@ void enqueue_iteration(pfk_session_s* S) {
       const bool naive = S->method == PFK_PIPEFCG_NAIVE;
       PcOutDesc pd = naive ? enqueue_pc(S, s1, S->vec(V_W), 1.0, nullptr, 0.0)
                            : enqueue_pc(S, s1, S->vec(V_W), 1.0, S->vec(V_R), -1.0);
-      LAUNCH_OP(S->A, k_apply_pc_out, S->Ps(), s1, g, S->sg, pd, naive ? (const double*)nullptr : (const double*)S->vec(V_U),
+      LAUNCH(k_apply_pc_out, S->Ps(), s1, g, S->sg, pd, naive ? (const double*)nullptr : (const double*)S->vec(V_U),
              naive ? 0.0 : 1.0, S->vec(V_M), S->vec(V_N), 0, (const double*)nullptr, S->part(PT_B), S->st);
       (void)hipStreamWaitEvent(s1, S->ev_join, 0);
       break;
@@ -864,7 +864,7 @@ void enqueue_iteration(pfk_session_s* S) {
     }
     case PFK_FGMRES: {
       PcOutDesc pd = enqueue_pc(S, s1, S->vec(V_VIN), 1.0, nullptr, 0.0);
-      LAUNCH_OP(S->A, k_fgm_apply, S->Ps(), s1, g, S->sg, pd, S->win(W_S), S->vec(V_Z), S->st);
+      LAUNCH(k_fgm_apply, S->Ps(), s1, g, S->sg, pd, S->win(W_S), S->vec(V_Z), S->st);
       LAUNCH(k_fgm_dots, S->Pv(), s1, A->N, S->win(W_P), (const double*)S->vec(V_Z), S->part(PT_MAIN),
              (const SolveState*)S->st);
       LAUNCH(k_gm_hbar, 1, s1, S->part(PT_MAIN), S->Pv(), S->st);
@@ -889,7 +889,7 @@ void enqueue_iteration(pfk_session_s* S) {
       LAUNCH(k_pgm_scalars, 1, s2, S->part(PT_MAIN), S->Pv(), S->st, S->hist);
       (void)hipEventRecord(S->ev_join, s2);
       PcOutDesc pd = enqueue_pc(S, s1, S->vec(V_M), 1.0, nullptr, 0.0);
-      LAUNCH_OP(S->A, k_apply_pc_out, S->Ps(), s1, g, S->sg, pd, (const double*)nullptr, 0.0, (double*)nullptr,
+      LAUNCH(k_apply_pc_out, S->Ps(), s1, g, S->sg, pd, (const double*)nullptr, 0.0, (double*)nullptr,
              S->vec(V_Z), 0, (const double*)nullptr, S->part(PT_B), S->st);
       (void)hipStreamWaitEvent(s1, S->ev_join, 0);
       LAUNCH(k_gm_update_x, S->Pv(), s1, A->N, S->win(W_S), (const double*)S->vec(V_X0), S->x,
@@ -919,7 +919,7 @@ void enqueue_sigma_estimate(pfk_session_s* S, hipStream_t s, int its) {
   LAUNCH(k_fill, S->Pv(), s, A->N, v, 1.0 / std::sqrt((double)A->N));
   for (int i = 0; i < its; ++i) {
     PcOutDesc pd = enqueue_pc(S, s, v, 1.0, nullptr, 0.0);
-    LAUNCH_OP(S->A, k_apply_pc_out, S->Ps(), s, S->grid(), S->sg, pd, (const double*)nullptr, 0.0, (double*)nullptr, w, 0,
+    LAUNCH(k_apply_pc_out, S->Ps(), s, S->grid(), S->sg, pd, (const double*)nullptr, 0.0, (double*)nullptr, w, 0,
            (const double*)nullptr, S->part(PT_B), S->st);
     LAUNCH(k_dot2, S->Pv(), s, A->N, (const double*)v, (const double*)w, S->part(PT_MAIN));
     LAUNCH(k_power_step, S->Pv(), s, A->N, (const double*)S->part(PT_MAIN), S->Pv(), v, (const double*)w, S->st);

@@ -96,9 +96,9 @@ k_residual(Grid g, StencilGeom sg, const double* __restrict__ b, const double* _
   block_partials<1>(acc, 1, part, sg.blocks());
 }
 
-// y = A x (operator checks; PIPEGCR's w = A u when st is given).  The _cv
-// kernels here and below are the same bodies for operators with face
-// velocities, which the stencil then loads ahead of use.
+// y = A x (operator checks; PIPEGCR's w = A u when st is given).  k_apply_cv
+// is the same body for operators with face velocities, which the stencil
+// then loads ahead of use.
 template <bool CV>
 __device__ __forceinline__ void apply_body(const Grid& g, const StencilGeom& sg, const double* __restrict__ x,
                                            double* __restrict__ y, const SolveState* st) {
@@ -120,7 +120,7 @@ k_apply_cv(Grid g, StencilGeom sg, const double* __restrict__ x, double* __restr
 // <O, N>; with dots = 2: <N, R>, <N, N>.
 // Used for u_0/w_0 and m_0/n_0 of PIPEFCG's start-up and for m_i, n_i in its
 // loop (m_i = u_i + B(w_i - r_i), n_i = A m_i).
-template <int K, int F32, bool CV = false>
+template <int K, int F32>
 __device__ __forceinline__ void apply_pc_out_t(Blk bk, const Grid& g, const StencilGeom& sg, const PcOutDesc& pd,
                                                const double* X3, double c3, double* __restrict__ O,
                                                double* __restrict__ Nout, int dots, const double* __restrict__ R,
@@ -139,38 +139,31 @@ __device__ __forceinline__ void apply_pc_out_t(Blk bk, const Grid& g, const Sten
       acc[1] += nv * nv;
     }
   };
-  stencil_march<double, CV>(g, sg, bk.id, in, sink);
+  stencil_march<double>(g, sg, bk.id, in, sink);
   if (dots) block_partials<2>(acc, 2, part, sg.blocks(), bk.id);
 }
 // The inner solve's output kind and storage are fixed per instantiation for
 // the two inner-CG forms (the hot cases); the others decide at run time.
-template <bool CV = false>
 __device__ __forceinline__ void apply_pc_out_body(Blk bk, Grid g, StencilGeom sg, PcOutDesc pd, const double* X3,
                                                   double c3, double* __restrict__ O, double* __restrict__ Nout,
                                                   int dots, const double* __restrict__ R, double* part,
                                                   SolveState* st) {
   if (read_status(st) != kRunning) return;
   if (pd.kind == kPcBlockPcg) {
-    if (pd.fp32) apply_pc_out_t<kPcBlockPcg, 1, CV>(bk, g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
-    else apply_pc_out_t<kPcBlockPcg, 0, CV>(bk, g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
+    if (pd.fp32) apply_pc_out_t<kPcBlockPcg, 1>(bk, g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
+    else apply_pc_out_t<kPcBlockPcg, 0>(bk, g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
   } else if (pd.kind == kPcJacobiPcg) {
-    if (pd.fp32) apply_pc_out_t<kPcJacobiPcg, 1, CV>(bk, g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
-    else apply_pc_out_t<kPcJacobiPcg, 0, CV>(bk, g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
+    if (pd.fp32) apply_pc_out_t<kPcJacobiPcg, 1>(bk, g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
+    else apply_pc_out_t<kPcJacobiPcg, 0>(bk, g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
   } else {
-    apply_pc_out_t<-1, 0, CV>(bk, g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
+    apply_pc_out_t<-1, 0>(bk, g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
   }
 }
 __global__ void __launch_bounds__(kBlock)
 k_apply_pc_out(Grid g, StencilGeom sg, PcOutDesc pd, const double* X3, double c3,
                double* __restrict__ O, double* __restrict__ Nout,
                int dots, const double* __restrict__ R, double* part, SolveState* st) {
-  apply_pc_out_body<false>(this_blk(), g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
-}
-__global__ void __launch_bounds__(kBlock)
-k_apply_pc_out_cv(Grid g, StencilGeom sg, PcOutDesc pd, const double* X3, double c3,
-                  double* __restrict__ O, double* __restrict__ Nout,
-                  int dots, const double* __restrict__ R, double* part, SolveState* st) {
-  apply_pc_out_body<true>(this_blk(), g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
+  apply_pc_out_body(this_blk(), g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
 }
 
 // True-residual verdict after a recurred convergence: kDone or kGap.

@@ -113,9 +113,8 @@ k_gm_update_x(long long N, Window U, const double* __restrict__ x0, double* __re
 // FGMRES
 // ---------------------------------------------------------------------------
 // u_c = B(p_c) into U[c] and z = A u_c (c = st->col).
-template <bool CV>
-__device__ __forceinline__ void fgm_apply_body(const Grid& g, const StencilGeom& sg, const PcOutDesc& pd, Window U,
-                                               double* __restrict__ z, SolveState* st) {
+__global__ void __launch_bounds__(kBlock)
+k_fgm_apply(Grid g, StencilGeom sg, PcOutDesc pd, Window U, double* __restrict__ z, SolveState* st) {
   if (read_status(st) != kRunning) return;
   const PcOut pc = make_pc_out(pd, &st->pc);
   double* uc = U.slot(st->col);
@@ -124,15 +123,7 @@ __device__ __forceinline__ void fgm_apply_body(const Grid& g, const StencilGeom&
     uc[idx] = u;
     z[idx] = Au;
   };
-  stencil_march<double, CV>(g, sg, in, sink);
-}
-__global__ void __launch_bounds__(kBlock)
-k_fgm_apply(Grid g, StencilGeom sg, PcOutDesc pd, Window U, double* __restrict__ z, SolveState* st) {
-  fgm_apply_body<false>(g, sg, pd, U, z, st);
-}
-__global__ void __launch_bounds__(kBlock)
-k_fgm_apply_cv(Grid g, StencilGeom sg, PcOutDesc pd, Window U, double* __restrict__ z, SolveState* st) {
-  fgm_apply_body<true>(g, sg, pd, U, z, st);
+  stencil_march<double>(g, sg, in, sink);
 }
 
 // First reduction: <p_j, z> for j <= c.
