@@ -414,46 +414,69 @@ __device__ __forceinline__ void multidot_body(Blk bk, long long N, int init, int
   for (int t = threadIdx.x; t < nu; t += kBlock) s_off[t] = (long long)((j1 - nu + t) % numax) * S.ld;
   for (int t = threadIdx.x; t < kWaves * (kNuMax + 3); t += kBlock) (&s_dot[0][0])[t] = 0.0;
   __syncthreads();
+  // Windows of up to kDotRegs directions (the configurations' 20 and 30)
+  // keep one accumulator per direction in registers and sum over the wave
+  // once at the end; longer windows sum every direction's products over the
+  // wave inside the loop.
+  constexpr int kDotRegs = 32;
+  const bool regs = nu <= kDotRegs;
+  double acc[kDotRegs];
+#pragma unroll
+  for (int t = 0; t < kDotRegs; ++t) acc[t] = 0.0;
   double vr = 0.0, vv = 0.0, rr = 0.0;
-  const long long step = 2LL * bk.gstride();
-  // wave-uniform trip count (wave sums inside); lanes past the end contribute 0
-  for (long long w0 = 2LL * bk.id * kBlock + threadIdx.x - lane; w0 < N; w0 += step) {
-    const long long e0 = w0 + lane;
-    const bool h0 = e0 < N;
-    const long long e1 = e0 + kBlock;
-    const bool h1 = e1 < N;
-    double v0 = 0.0, v1 = 0.0;
+  const long long npair = (N + 1) / 2;
+  // wave-uniform trip count (the long-window path sums over the wave inside);
+  // lanes past the end use element 0 and contribute nothing.  Each lane owns
+  // two consecutive nodes (16-byte accesses).
+  for (long long qw = bk.gtid() - lane; qw < npair; qw += bk.gstride()) {
+    const bool act = qw + lane < npair;
+    const long long e = act ? 2 * (qw + lane) : 0;
+    const bool full = act && e + 1 < N;
+    double2 v = make_double2(0.0, 0.0);
     if (from_pc) {
-      if (h0) v0 = pc(e0);
-      if (h1) v1 = pc(e1);
-      if (h0) Vout[e0] = v0;
-      if (h1) Vout[e1] = v1;
+      if (act) {
+        v.x = pc(e);
+        if (full) v.y = pc(e + 1);
+        st2(Vout, e, v, full);
+      }
+    } else if (act) {
+      v = ld2(Vin, e, full);
+    }
+    const double2 r = act ? ld2(R, e, full) : make_double2(0.0, 0.0);
+    vr += v.x * r.x + v.y * r.y;
+    vv += v.x * v.x + v.y * v.y;
+    rr += r.x * r.x + r.y * r.y;
+    if (regs) {
+      // eight directions at a time: their loads in flight together, the
+      // compiler kept from hoisting the next group's (registers)
+#pragma unroll
+      for (int c = 0; c < kDotRegs; c += 8) {
+        if (c < nu) {
+#pragma unroll
+          for (int t = c; t < c + 8; ++t) {
+            if (t < nu) {
+              const double2 sd = ld2(S.base, s_off[t] + e, full);
+              acc[t] += v.x * sd.x + v.y * sd.y;
+            }
+          }
+        }
+        asm volatile("" ::: "memory");
+      }
     } else {
-      if (h0) v0 = Vin[e0];
-      if (h1) v1 = Vin[e1];
-    }
-    const double r0 = h0 ? R[e0] : 0.0, r1 = h1 ? R[e1] : 0.0;
-    vr += v0 * r0 + v1 * r1;
-    vv += v0 * v0 + v1 * v1;
-    rr += r0 * r0 + r1 * r1;
-    int t = 0;
-    for (; t + 4 <= nu; t += 4) {
-      double a[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const long long o = s_off[t + q];
-        a[q] = (h0 ? v0 * S.base[o + e0] : 0.0) + (h1 ? v1 * S.base[o + e1] : 0.0);
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const double d = wave_sum(a[q]);
-        if (lane == 0) s_dot[wid][3 + t + q] += d;
+      for (int t = 0; t < nu; ++t) {
+        const double2 sd = ld2(S.base, s_off[t] + e, full);
+        const double d = wave_sum(v.x * sd.x + v.y * sd.y);
+        if (lane == 0) s_dot[wid][3 + t] += d;
       }
     }
-    for (; t < nu; ++t) {
-      const long long o = s_off[t];
-      const double d = wave_sum((h0 ? v0 * S.base[o + e0] : 0.0) + (h1 ? v1 * S.base[o + e1] : 0.0));
-      if (lane == 0) s_dot[wid][3 + t] += d;
+  }
+  if (regs) {
+#pragma unroll
+    for (int t = 0; t < kDotRegs; ++t) {
+      if (t < nu) {
+        const double d = wave_sum(acc[t]);
+        if (lane == 0) s_dot[wid][3 + t] = d;
+      }
     }
   }
   {
@@ -462,10 +485,10 @@ __device__ __forceinline__ void multidot_body(Blk bk, long long N, int init, int
   }
   __syncthreads();
   for (int c = threadIdx.x; c < 3 + nu; c += kBlock) {
-    double acc = 0.0;
+    double a = 0.0;
 #pragma unroll
-    for (int wv = 0; wv < kWaves; ++wv) acc += s_dot[wv][c];
-    part[(long long)c * bk.n + bk.id] = acc;
+    for (int wv = 0; wv < kWaves; ++wv) a += s_dot[wv][c];
+    part[(long long)c * bk.n + bk.id] = a;
   }
 }
 __global__ void __launch_bounds__(kBlock)
