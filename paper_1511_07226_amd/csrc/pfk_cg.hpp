@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(kBlock)
 k_residual(Grid g, StencilGeom sg, const double* __restrict__ b, const double* __restrict__ x,
            double* __restrict__ r, double* part, double* __restrict__ x0) {
   double acc[1] = {0.0};
-  auto in = [&](long long t) { return x[t]; };
+  const auto in = stencil_in([&](long long t) { return x[t]; });
   auto sink = [&](long long idx, double xc, double Au) {
     if (x0 != nullptr) x0[idx] = xc;
     const double rv = b[idx] - Au;
@@ -103,7 +103,7 @@ template <bool CV>
 __device__ __forceinline__ void apply_body(const Grid& g, const StencilGeom& sg, const double* __restrict__ x,
                                            double* __restrict__ y, const SolveState* st) {
   if (st != nullptr && read_status(st) != kRunning) return;
-  auto in = [&](long long t) { return x[t]; };
+  const auto in = stencil_in([&](long long t) { return x[t]; });
   auto sink = [&](long long idx, double, double Au) { y[idx] = Au; };
   stencil_march<double, CV>(g, sg, in, sink);
 }
@@ -126,7 +126,6 @@ __device__ __forceinline__ void apply_pc_out_t(Blk bk, const Grid& g, const Sten
                                                double* __restrict__ Nout, int dots, const double* __restrict__ R,
                                                double* part, SolveState* st) {
   const PcOut pc = make_pc_out(pd, &st->pc);
-  auto in = [&](long long t) { double v = pc.at<K, F32>(t); if (X3 != nullptr) v += c3 * X3[t]; return v; };
   double acc[2] = {0.0, 0.0};
   auto sink = [&](long long idx, double mc, double nv) {
     if (O != nullptr) O[idx] = mc;
@@ -139,7 +138,38 @@ __device__ __forceinline__ void apply_pc_out_t(Blk bk, const Grid& g, const Sten
       acc[1] += nv * nv;
     }
   };
-  stencil_march<double>(g, sg, bk.id, in, sink);
+  if constexpr (K == kPcBlockPcg || K == kPcJacobiPcg) {
+    // the inner solve's stored output (and X3) are loaded ahead; the value is
+    // PcOut::at's arithmetic, plus c3*X3
+    using W = typename std::conditional<F32 != 0, float, double>::type;
+    struct RawPc { W y, p; double x3; };
+    const W* yw = static_cast<const W*>(pc.y);
+    const W* pw = static_cast<const W*>(pc.pk);
+    const bool ly = K == kPcBlockPcg || pc.use_y;
+    const bool lp = K == kPcJacobiPcg && pc.add_p;
+    const double alpha = pc.alpha;
+    auto load = [&](long long t) {
+      RawPc q{};
+      if (ly) q.y = yw[t];
+      if (lp) q.p = pw[t];
+      if (X3 != nullptr) q.x3 = X3[t];
+      return q;
+    };
+    auto value = [&](const RawPc& q) {
+      double r = ly ? (double)q.y : 0.0;
+      if (lp) r += alpha * (double)q.p;
+      if (X3 != nullptr) r += c3 * q.x3;
+      return r;
+    };
+    stencil_march<double>(g, sg, bk.id, stencil_in(load, value), sink);
+  } else {
+    const auto in = stencil_in([&](long long t) {
+      double v = pc.at<K, F32>(t);
+      if (X3 != nullptr) v += c3 * X3[t];
+      return v;
+    });
+    stencil_march<double>(g, sg, bk.id, in, sink);
+  }
   if (dots) block_partials<2>(acc, 2, part, sg.blocks(), bk.id);
 }
 // The inner solve's output kind and storage are fixed per instantiation for
@@ -612,7 +642,7 @@ __device__ __forceinline__ void fcg_apply_body(Blk bk, Grid g, StencilGeom sg, W
   const double* p = P.slot(slot);
   double* s = S.slot(slot);
   double acc[1] = {0.0};
-  auto in = [&](long long t) { return p[t]; };
+  const auto in = stencil_in([&](long long t) { return p[t]; });
   auto sink = [&](long long idx, double pc, double sv) {
     s[idx] = sv;
     acc[0] += pc * sv;

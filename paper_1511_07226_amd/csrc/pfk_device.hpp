@@ -15,6 +15,8 @@
 #include <hip/hip_bf16.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace pfk {
 
 constexpr int kBlock = 256;        // threads per workgroup: four 64-wide waves
@@ -187,8 +189,30 @@ __device__ __forceinline__ void for_tile_nodes(const G& g, const StencilGeom& sg
   else for_tile_nodes_t<64>(g, sg, blockIdx.x, body);
 }
 
+// Input of the stencil engine: load(t) issues the global loads of flat node t
+// and nothing else (its result is a value, or a struct of loaded values);
+// value(raw) forms the node's input u from them.  The engine issues loads one
+// plane step ahead and forms values only when their plane is reached, so no
+// arithmetic on loaded data makes a plane step wait for its own prefetch.
+template <class LoadF, class ValueF>
+struct StencilIn {
+  LoadF load;
+  ValueF value;
+};
+template <class LoadF, class ValueF>
+__device__ __forceinline__ StencilIn<LoadF, ValueF> stencil_in(LoadF load, ValueF value) {
+  return StencilIn<LoadF, ValueF>{load, value};
+}
+// An input formed where it is loaded (a plain load, or a combination the
+// caller evaluates at once).
+template <class LoadF>
+__device__ __forceinline__ auto stencil_in(LoadF load) {
+  return stencil_in(load, [](auto v) { return v; });
+}
+
 // The hot stencil engine, in arithmetic type T.  A workgroup walks its tile
-// up the z-axis.  Each node's input value u = in(flat index) is formed once.
+// up the z-axis.  Each node's input value u = in.value(in.load(flat index)) is
+// formed once.
 // z-neighbours stay in registers; in-plane neighbours of u and of the
 // viscosity come from LDS copies of the current plane with a one-node halo
 // (halo values are formed by the first 2(TX+TY) threads).  Every global load
@@ -254,12 +278,21 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
   const bool hvalid = has_halo && hi >= 0 && hi < g.nx && hj >= 0 && hj < g.ny;
   const bool hevalid = has_halo && hi >= -1 && hi <= g.nx && hj >= -1 && hj <= g.ny;
 
-  auto U = [&](int r, int k) { return (valid[r] && k >= 0 && k < g.nz) ? in(vec_index(g, i, jr[r], k)) : zero; };
-  auto E = [&](int r, int k) {
-    return (evalid[r] && k >= -1 && k <= kmax) ? T(to_real(g.eta[padded_index(g, i, jr[r], k)])) : zero;
+  // raw loads (R suffix) and the values formed from them
+  using Raw = decltype(in.load(0LL));
+  using ES = typename std::remove_cv<typename std::remove_pointer<decltype(g.eta)>::type>::type;
+  const ES ez = ES(0.0f);
+  auto UOK = [&](int r, int k) { return valid[r] && k >= 0 && k < g.nz; };
+  auto UR = [&](int r, int k) { return UOK(r, k) ? in.load(vec_index(g, i, jr[r], k)) : Raw{}; };
+  auto U = [&](int r, int k) { return UOK(r, k) ? T(in.value(UR(r, k))) : zero; };
+  auto ER = [&](int r, int k) {
+    return (evalid[r] && k >= -1 && k <= kmax) ? g.eta[padded_index(g, i, jr[r], k)] : ez;
   };
-  auto HU = [&](int k) { return (hvalid && k < g.nz) ? in(vec_index(g, hi, hj, k)) : zero; };
-  auto HE = [&](int k) { return (hevalid && k <= kmax) ? T(to_real(g.eta[padded_index(g, hi, hj, k)])) : zero; };
+  auto E = [&](int r, int k) { return T(to_real(ER(r, k))); };
+  auto HOK = [&](int k) { return hvalid && k < g.nz; };
+  auto HU = [&](int k) { return HOK(k) ? T(in.value(in.load(vec_index(g, hi, hj, k)))) : zero; };
+  auto HER = [&](int k) { return (hevalid && k <= kmax) ? g.eta[padded_index(g, hi, hj, k)] : ez; };
+  auto HE = [&](int k) { return T(to_real(HER(k))); };
 
   // register window: m = k-1, c = k, p = k+1 (u and eta of the centre column)
   T um[2], uc[2], up[2], em[2], ec[2], ep[2];
@@ -299,15 +332,19 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
   }
   for (int k = k0; k < k1; ++k) {
     // in flight during this step: plane k+2 of the column, the halo of plane k+1
-    T upp[2], epp[2];
+    Raw uppR[2];
+    ES eppR[2];
+    bool uppOK[2];
     const bool more = k + 1 < k1;
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-      upp[r] = (d3 && more) ? U(r, k + 2) : zero;
-      epp[r] = (d3 && more) ? E(r, k + 2) : zero;
+      uppOK[r] = d3 && more && UOK(r, k + 2);
+      uppR[r] = uppOK[r] ? in.load(vec_index(g, i, jr[r], k + 2)) : Raw{};
+      eppR[r] = (d3 && more) ? ER(r, k + 2) : ez;
     }
-    const T hu_n = more ? HU(k + 1) : zero;
-    const T he_n = more ? HE(k + 1) : zero;
+    const bool hok_n = more && HOK(k + 1);
+    const Raw huR_n = hok_n ? in.load(vec_index(g, hi, hj, k + 1)) : Raw{};
+    const ES heR_n = more ? HER(k + 1) : ez;
     if constexpr (CV) {
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
@@ -351,13 +388,13 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
       }
       um[r] = uc[r];
       uc[r] = up[r];
-      up[r] = upp[r];
+      up[r] = uppOK[r] ? T(in.value(uppR[r])) : zero;
       em[r] = ec[r];
       ec[r] = ep[r];
-      ep[r] = epp[r];
+      ep[r] = T(to_real(eppR[r]));
     }
-    hu = hu_n;
-    he = he_n;
+    hu = hok_n ? T(in.value(huR_n)) : zero;
+    he = T(to_real(heR_n));
   }
 }
 

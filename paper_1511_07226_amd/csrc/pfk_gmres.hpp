@@ -118,7 +118,7 @@ k_fgm_apply(Grid g, StencilGeom sg, PcOutDesc pd, Window U, double* __restrict__
   if (read_status(st) != kRunning) return;
   const PcOut pc = make_pc_out(pd, &st->pc);
   double* uc = U.slot(st->col);
-  auto in = [&](long long t) { return pc(t); };
+  const auto in = stencil_in([&](long long t) { return pc(t); });
   auto sink = [&](long long idx, double u, double Au) {
     uc[idx] = u;
     z[idx] = Au;
@@ -223,7 +223,7 @@ k_pgm_apply0(Grid g, StencilGeom sg, PcOutDesc pd, Window U, Window P, Window ZB
   const double* p0 = P.slot(0);
   double* z0 = ZB.slot(0);
   double acc[2] = {0.0, 0.0};
-  auto in = [&](long long t) { return pc(t); };
+  const auto in = stencil_in([&](long long t) { return pc(t); });
   auto sink = [&](long long idx, double u, double Au) {
     const double pv = p0[idx];
     const double zb = Au - sigma * pv;

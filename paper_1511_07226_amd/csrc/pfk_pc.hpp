@@ -206,7 +206,20 @@ k_pcg_a1(G g, StencilGeom sg, const T* __restrict__ dinv,
   if (read_status(st) != kRunning) return;
   double acc[2] = {0.0, 0.0};
   auto V = [&](long long t) { double r = c1 * X1[t]; if (X2 != nullptr) r += c2 * X2[t]; return T(r); };
-  auto in = [&](long long t) { return dinv[t] * V(t); };
+  struct Raw { T d; double x1, x2; };
+  auto load = [&](long long t) {
+    Raw q{};
+    q.d = dinv[t];
+    q.x1 = X1[t];
+    if (X2 != nullptr) q.x2 = X2[t];
+    return q;
+  };
+  auto value = [&](const Raw& q) {        // dinv * V, V's arithmetic
+    double r = c1 * q.x1;
+    if (X2 != nullptr) r += c2 * q.x2;
+    return q.d * T(r);
+  };
+  const auto in = stencil_in(load, value);
   auto sink = [&](long long idx, T pc, T q) {
     pout[idx] = pc;
     qout[idx] = q;
@@ -282,7 +295,9 @@ k_pcg_a(int jstep, G g, StencilGeom sg, const T* __restrict__ dinv,
   const T beta = T((stopped || gprev == 0.0) ? 0.0 : gj / gprev);
   if (blockIdx.x == 0 && threadIdx.x == 0) pcs->gamma[jstep] = gj;
   double acc[1] = {0.0};
-  auto in = [&](long long t) { return dinv[t] * rho[t] + beta * pprev[t]; };
+  struct Raw { T d, r, p; };
+  const auto in = stencil_in([&](long long t) { return Raw{dinv[t], rho[t], pprev[t]}; },
+                             [&](const Raw& q) { return q.d * q.r + beta * q.p; });
   auto sink = [&](long long idx, T pc, T q) {
     pout[idx] = pc;
     qout[idx] = q;
@@ -331,7 +346,9 @@ k_gmpc_apply(int jstep, G g, StencilGeom sg, const T* __restrict__ dinv, const T
   if (nrm == 0.0) return;
   const T sj = T(1.0 / nrm);
   const T* Vj = Vbase + (long long)jstep * ldv;
-  auto in = [&](long long t) { return dinv[t] * (sj * Vj[t]); };
+  struct Raw { T d, v; };
+  const auto in = stencil_in([&](long long t) { return Raw{dinv[t], Vj[t]}; },
+                             [&](const Raw& q) { return q.d * (sj * q.v); });
   auto sink = [&](long long idx, T, T Au) { w[idx] = Au; };
   stencil_march<T, CV>(g, sg, in, sink);
 }
