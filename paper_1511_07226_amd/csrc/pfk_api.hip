@@ -570,6 +570,20 @@ thread_local KernelProfiler* g_prof = nullptr;
     else LAUNCH(kernel, blocks, stream, __VA_ARGS__);                                    \
   } while (0)
 
+// k_apply_pc_out in the instantiation for the descriptor's output kind.
+#define LAUNCH_PC_OUT(pd, blocks, stream, ...)                                                      \
+  do {                                                                                              \
+    if ((pd).kind == kPcBlockPcg) {                                                                 \
+      if ((pd).fp32) LAUNCH((k_apply_pc_out<kPcBlockPcg, 1>), blocks, stream, __VA_ARGS__);         \
+      else LAUNCH((k_apply_pc_out<kPcBlockPcg, 0>), blocks, stream, __VA_ARGS__);                   \
+    } else if ((pd).kind == kPcJacobiPcg) {                                                         \
+      if ((pd).fp32) LAUNCH((k_apply_pc_out<kPcJacobiPcg, 1>), blocks, stream, __VA_ARGS__);        \
+      else LAUNCH((k_apply_pc_out<kPcJacobiPcg, 0>), blocks, stream, __VA_ARGS__);                  \
+    } else {                                                                                        \
+      LAUNCH((k_apply_pc_out<-1, 0>), blocks, stream, __VA_ARGS__);                                 \
+    }                                                                                               \
+  } while (0)
+
 // Enqueue the inner solve B(v), v = c1*X1 + c2*X2; returns how the consumer
 // evaluates B(v).
 // How a consumer evaluates B(v) after enqueue_pc(v): which buffers hold the
@@ -732,7 +746,7 @@ void enqueue_cg_body(pfk_session_s* S, hipStream_t s, int init) {
     LAUNCH(k_cg_scalars2, 1, s, 0, init, S->part(PT_A), S->Ps(), S->st);
     host_wait(S, s);
   } else {
-    LAUNCH(k_apply_pc_out, S->Ps(), s, g, S->sg, pd, (const double*)nullptr, 0.0, S->vec(V_U), S->vec(V_W), 0,
+    LAUNCH_PC_OUT(pd, S->Ps(), s, g, S->sg, pd, (const double*)nullptr, 0.0, S->vec(V_U), S->vec(V_W), 0,
            (const double*)nullptr, S->part(PT_B), S->st);
     enqueue_multidot(S, s, init, 0, pd, S->vec(V_W), nullptr);
     LAUNCH(k_cg_scalars1, 1, s, init, S->part(PT_MAIN), S->Pv(), S->st, S->hist);
@@ -766,11 +780,11 @@ void enqueue_start(pfk_session_s* S, hipStream_t s) {
       // PIPEGCR_w (p_0 = u_0, s_0 = w_0): gamma_0 = <r_0,s_0>, eta_0 = <s_0,s_0>
       const int dots = S->method == PFK_PIPEGCR_W ? 2 : 1;
       PcOutDesc pd = enqueue_pc(S, s, S->vec(V_R), 1.0, nullptr, 0.0);
-      LAUNCH(k_apply_pc_out, S->Ps(), s, g, S->sg, pd, (const double*)nullptr, 0.0, S->vec(V_U), S->vec(V_W), dots,
+      LAUNCH_PC_OUT(pd, S->Ps(), s, g, S->sg, pd, (const double*)nullptr, 0.0, S->vec(V_U), S->vec(V_W), dots,
              (const double*)S->vec(V_R), S->part(PT_B), S->st);
       // m_0 = B(w_0), n_0 = A m_0
       pd = enqueue_pc(S, s, S->vec(V_W), 1.0, nullptr, 0.0);
-      LAUNCH(k_apply_pc_out, S->Ps(), s, g, S->sg, pd, (const double*)nullptr, 0.0, S->vec(V_M), S->vec(V_N), 0,
+      LAUNCH_PC_OUT(pd, S->Ps(), s, g, S->sg, pd, (const double*)nullptr, 0.0, S->vec(V_M), S->vec(V_N), 0,
              (const double*)nullptr, S->part(PT_B), S->st);
       LAUNCH(k_pipefcg_init_scalars, 1, s, S->part(PT_A), S->Ps(), S->part(PT_B), S->Ps(), S->st, S->hist);
       break;
@@ -779,7 +793,7 @@ void enqueue_start(pfk_session_s* S, hipStream_t s) {
       LAUNCH(k_init_test, 1, s, S->part(PT_A), S->Ps(), S->st, S->hist);
       // u_0 = B(r_0), s_0 = A u_0 (kept in w), gamma_0 = <r_0,s_0>, eta_0 = <s_0,s_0>
       PcOutDesc pd = enqueue_pc(S, s, S->vec(V_R), 1.0, nullptr, 0.0);
-      LAUNCH(k_apply_pc_out, S->Ps(), s, g, S->sg, pd, (const double*)nullptr, 0.0, S->vec(V_U), S->vec(V_W), 0,
+      LAUNCH_PC_OUT(pd, S->Ps(), s, g, S->sg, pd, (const double*)nullptr, 0.0, S->vec(V_U), S->vec(V_W), 0,
              (const double*)nullptr, S->part(PT_B), S->st);
       enqueue_multidot(S, s, 1, 0, pd, S->vec(V_W), nullptr);
       // q_0 = B(s_0), consumed by the first update
@@ -802,7 +816,7 @@ void enqueue_start(pfk_session_s* S, hipStream_t s) {
              S->part(PT_MAIN), S->st);
       // qbar_0 = B(zbar_0), wbar_0 = A qbar_0
       pd = enqueue_pc(S, s, S->vec(V_M), 1.0, nullptr, 0.0);
-      LAUNCH(k_apply_pc_out, S->Ps(), s, g, S->sg, pd, (const double*)nullptr, 0.0, (double*)nullptr,
+      LAUNCH_PC_OUT(pd, S->Ps(), s, g, S->sg, pd, (const double*)nullptr, 0.0, (double*)nullptr,
              S->vec(V_Z), 0, (const double*)nullptr, S->part(PT_B), S->st);
       LAUNCH(k_pgm_scalars, 1, s, S->part(PT_MAIN), S->Ps(), S->st, S->hist);   // partials of k_pgm_apply0
       LAUNCH(k_gm_update_x, S->Pv(), s, A->N, S->win(W_S), (const double*)S->vec(V_X0), S->x,
@@ -842,7 +856,7 @@ void enqueue_iteration(pfk_session_s* S) {
       const bool naive = S->method == PFK_PIPEFCG_NAIVE;
       PcOutDesc pd = naive ? enqueue_pc(S, s1, S->vec(V_W), 1.0, nullptr, 0.0)
                            : enqueue_pc(S, s1, S->vec(V_W), 1.0, S->vec(V_R), -1.0);
-      LAUNCH(k_apply_pc_out, S->Ps(), s1, g, S->sg, pd, naive ? (const double*)nullptr : (const double*)S->vec(V_U),
+      LAUNCH_PC_OUT(pd, S->Ps(), s1, g, S->sg, pd, naive ? (const double*)nullptr : (const double*)S->vec(V_U),
              naive ? 0.0 : 1.0, S->vec(V_M), S->vec(V_N), 0, (const double*)nullptr, S->part(PT_B), S->st);
       (void)hipStreamWaitEvent(s1, S->ev_join, 0);
       break;
@@ -889,7 +903,7 @@ void enqueue_iteration(pfk_session_s* S) {
       LAUNCH(k_pgm_scalars, 1, s2, S->part(PT_MAIN), S->Pv(), S->st, S->hist);
       (void)hipEventRecord(S->ev_join, s2);
       PcOutDesc pd = enqueue_pc(S, s1, S->vec(V_M), 1.0, nullptr, 0.0);
-      LAUNCH(k_apply_pc_out, S->Ps(), s1, g, S->sg, pd, (const double*)nullptr, 0.0, (double*)nullptr,
+      LAUNCH_PC_OUT(pd, S->Ps(), s1, g, S->sg, pd, (const double*)nullptr, 0.0, (double*)nullptr,
              S->vec(V_Z), 0, (const double*)nullptr, S->part(PT_B), S->st);
       (void)hipStreamWaitEvent(s1, S->ev_join, 0);
       LAUNCH(k_gm_update_x, S->Pv(), s1, A->N, S->win(W_S), (const double*)S->vec(V_X0), S->x,
@@ -919,7 +933,7 @@ void enqueue_sigma_estimate(pfk_session_s* S, hipStream_t s, int its) {
   LAUNCH(k_fill, S->Pv(), s, A->N, v, 1.0 / std::sqrt((double)A->N));
   for (int i = 0; i < its; ++i) {
     PcOutDesc pd = enqueue_pc(S, s, v, 1.0, nullptr, 0.0);
-    LAUNCH(k_apply_pc_out, S->Ps(), s, S->grid(), S->sg, pd, (const double*)nullptr, 0.0, (double*)nullptr, w, 0,
+    LAUNCH_PC_OUT(pd, S->Ps(), s, S->grid(), S->sg, pd, (const double*)nullptr, 0.0, (double*)nullptr, w, 0,
            (const double*)nullptr, S->part(PT_B), S->st);
     LAUNCH(k_dot2, S->Pv(), s, A->N, (const double*)v, (const double*)w, S->part(PT_MAIN));
     LAUNCH(k_power_step, S->Pv(), s, A->N, (const double*)S->part(PT_MAIN), S->Pv(), v, (const double*)w, S->st);

@@ -119,8 +119,10 @@ k_apply_cv(Grid g, StencilGeom sg, const double* __restrict__ x, double* __restr
 // O = c3*X3 + B(v) at every node, N = A O.  With dots = 1: partials <O, R>,
 // <O, N>; with dots = 2: <N, R>, <N, N>.
 // Used for u_0/w_0 and m_0/n_0 of PIPEFCG's start-up and for m_i, n_i in its
-// loop (m_i = u_i + B(w_i - r_i), n_i = A m_i).
-template <int K, int F32>
+// loop (m_i = u_i + B(w_i - r_i), n_i = A m_i).  K: the inner solve's
+// output kind fixed at compile time (K < 0: decided at run time); GM: the
+// run-time path loads an FP32 inner GMRES output ahead (gm_raw_in).
+template <int K, int F32, bool GM = false>
 __device__ __forceinline__ void apply_pc_out_t(Blk bk, const Grid& g, const StencilGeom& sg, const PcOutDesc& pd,
                                                const double* X3, double c3, double* __restrict__ O,
                                                double* __restrict__ Nout, int dots, const double* __restrict__ R,
@@ -163,12 +165,21 @@ __device__ __forceinline__ void apply_pc_out_t(Blk bk, const Grid& g, const Sten
     };
     stencil_march<double>(g, sg, bk.id, stencil_in(load, value), sink);
   } else {
-    const auto in = stencil_in([&](long long t) {
-      double v = pc.at<K, F32>(t);
-      if (X3 != nullptr) v += c3 * X3[t];
-      return v;
-    });
-    stencil_march<double>(g, sg, bk.id, in, sink);
+    bool done = false;
+    if constexpr (GM) {
+      if (gm_raw_ok(pc)) {
+        stencil_march<double>(g, sg, bk.id, gm_raw_in(pc, X3, c3), sink);
+        done = true;
+      }
+    }
+    if (!done) {
+      const auto in = stencil_in([&](long long t) {
+        double v = pc.at<K, F32>(t);
+        if (X3 != nullptr) v += c3 * X3[t];
+        return v;
+      });
+      stencil_march<double>(g, sg, bk.id, in, sink);
+    }
   }
   if (dots) block_partials<2>(acc, 2, part, sg.blocks(), bk.id);
 }
@@ -189,11 +200,16 @@ __device__ __forceinline__ void apply_pc_out_body(Blk bk, Grid g, StencilGeom sg
     apply_pc_out_t<-1, 0>(bk, g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
   }
 }
+// The single-system kernel: one instantiation per output kind and storage
+// (the host picks it from the descriptor), so each carries only its own
+// registers.
+template <int K, int F32>
 __global__ void __launch_bounds__(kBlock)
 k_apply_pc_out(Grid g, StencilGeom sg, PcOutDesc pd, const double* X3, double c3,
                double* __restrict__ O, double* __restrict__ Nout,
                int dots, const double* __restrict__ R, double* part, SolveState* st) {
-  apply_pc_out_body(this_blk(), g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
+  if (read_status(st) != kRunning) return;
+  apply_pc_out_t<K, F32, true>(this_blk(), g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
 }
 
 // True-residual verdict after a recurred convergence: kDone or kGap.

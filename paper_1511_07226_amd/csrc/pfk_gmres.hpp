@@ -123,7 +123,8 @@ k_fgm_apply(Grid g, StencilGeom sg, PcOutDesc pd, Window U, double* __restrict__
     uc[idx] = u;
     z[idx] = Au;
   };
-  stencil_march<double>(g, sg, in, sink);
+  if (gm_raw_ok(pc)) stencil_march<double>(g, sg, gm_raw_in(pc, nullptr, 0.0), sink);
+  else stencil_march<double>(g, sg, in, sink);
 }
 
 // First reduction: <p_j, z> for j <= c.
@@ -233,7 +234,8 @@ k_pgm_apply0(Grid g, StencilGeom sg, PcOutDesc pd, Window U, Window P, Window ZB
     acc[0] += pv * zb;
     acc[1] += zb * zb;
   };
-  stencil_march<double>(g, sg, in, sink);
+  if (gm_raw_ok(pc)) stencil_march<double>(g, sg, gm_raw_in(pc, nullptr, 0.0), sink);
+  else stencil_march<double>(g, sg, in, sink);
   block_partials<2>(acc, 2, part, sg.blocks());
 }
 

@@ -196,6 +196,46 @@ __device__ __forceinline__ PcOut make_pc_out(const PcOutDesc& d, PcScalars* pcs)
   return o;
 }
 
+// B(v) + c3*X3 as a stencil input for an inner GMRES output with FP32 storage
+// and at most kGmRaw basis vectors (gm_raw_ok): the basis values, D^-1 and
+// X3 are loaded ahead and combined with PcOut's arithmetic when their plane
+// is reached.
+constexpr int kGmRaw = 8;
+__device__ __forceinline__ bool gm_raw_ok(const PcOut& pc) {
+  return pc.kind == kPcJacobiGmres && pc.fp32 && pc.nv <= kGmRaw;
+}
+struct GmRaw {
+  float d;
+  float v[kGmRaw];
+  double x3;
+};
+__device__ __forceinline__ auto gm_raw_in(const PcOut& pc, const double* X3, double c3) {
+  const float* V = static_cast<const float*>(pc.vbase);
+  const float* D = static_cast<const float*>(pc.dinv_in);
+  const int nv = pc.nv;
+  const long long ldv = pc.ldv;
+  const double* cf = pc.cf;
+  auto load = [=](long long t) {
+    GmRaw q{};
+    q.d = D[t];
+#pragma unroll
+    for (int j = 0; j < kGmRaw; ++j)
+      if (j < nv) q.v[j] = V[(long long)j * ldv + t];
+    if (X3 != nullptr) q.x3 = X3[t];
+    return q;
+  };
+  auto value = [=](const GmRaw& q) {
+    double r = 0.0;
+#pragma unroll
+    for (int j = 0; j < kGmRaw; ++j)
+      if (j < nv) r += cf[j] * (double)q.v[j];
+    double v = (double)q.d * r;
+    if (X3 != nullptr) v += c3 * q.x3;
+    return v;
+  };
+  return stencil_in(load, value);
+}
+
 // ---- A_1: p_1 = D^-1 v, q = A p_1 -------------------------------------------
 template <class T, class G>
 __global__ void __launch_bounds__(kBlock)
