@@ -250,14 +250,26 @@ k_pipefcg_init_scalars(const double* part_r, int P_r, const double* part_ud, int
 }
 
 // Two consecutive doubles per lane: one 16-byte access (the scalar tail of
-// an odd N reads/writes only .x).
+// an odd N reads/writes only .x).  The window and vector kernels stream
+// vectors far larger than the caches, so their accesses are nontemporal
+// (measured on the PIPEFCG update at 256^3: 3.66 -> 3.46 ms).
+typedef double pfk_d2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ double2 ld2(const double* p, long long e, bool full) {
-  if (full) return *reinterpret_cast<const double2*>(p + e);
-  return make_double2(p[e], 0.0);
+  if (full) {
+    const pfk_d2v v = __builtin_nontemporal_load(reinterpret_cast<const pfk_d2v*>(p + e));
+    return make_double2(v.x, v.y);
+  }
+  return make_double2(__builtin_nontemporal_load(p + e), 0.0);
 }
 __device__ __forceinline__ void st2(double* p, long long e, double2 v, bool full) {
-  if (full) *reinterpret_cast<double2*>(p + e) = v;
-  else p[e] = v.x;
+  if (full) {
+    pfk_d2v t;
+    t.x = v.x;
+    t.y = v.y;
+    __builtin_nontemporal_store(t, reinterpret_cast<pfk_d2v*>(p + e));
+  } else {
+    __builtin_nontemporal_store(v.x, p + e);
+  }
 }
 
 // One fused pass for direction j (= st->j):

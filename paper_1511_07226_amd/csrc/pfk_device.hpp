@@ -189,6 +189,17 @@ __device__ __forceinline__ void for_tile_nodes(const G& g, const StencilGeom& sg
   else for_tile_nodes_t<64>(g, sg, blockIdx.x, body);
 }
 
+// Nontemporal element access for kernels that stream vectors much larger
+// than the caches.
+template <class T>
+__device__ __forceinline__ T ldnt(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+template <class T>
+__device__ __forceinline__ void stnt(T* p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
+
 // Input of the stencil engine: load(t) issues the global loads of flat node t
 // and nothing else (its result is a value, or a struct of loaded values);
 // value(raw) forms the node's input u from them.  The engine issues loads one

@@ -301,21 +301,21 @@ k_pcg_b(int jstep, long long N, const T* __restrict__ dinv,
     T r;
     T yv;
     if (jstep == 1) {
-      double rv = c1 * X1[e];
-      if (X2 != nullptr) rv += c2 * X2[e];
+      double rv = c1 * ldnt(X1 + e);
+      if (X2 != nullptr) rv += c2 * ldnt(X2 + e);
       r = T(rv);
       yv = T(0);
     } else {
-      r = rho[e];
-      yv = y[e];
+      r = ldnt(rho + e);
+      yv = ldnt(y + e);
     }
     if (!stopped) {
-      yv += alpha * p[e];
-      r -= alpha * q[e];
+      yv += alpha * ldnt(p + e);
+      r -= alpha * ldnt(q + e);
     }
-    y[e] = yv;
-    rho[e] = r;
-    acc[0] += (double)r * (double)(dinv[e] * r);
+    stnt(y + e, yv);
+    stnt(rho + e, r);
+    acc[0] += (double)r * (double)(ldnt(dinv + e) * r);
   }
   block_partials<1>(acc, 1, part_out, gridDim.x);
 }
@@ -406,10 +406,10 @@ k_gmpc_dots(int jstep, long long N, const T* Vbase, long long ldv, const T* __re
 #pragma unroll
   for (int q = 0; q < kMaxInnerGmres; ++q) acc[q] = 0.0;
   for (long long e = gtid(); e < N; e += gstride()) {
-    const double wv = (double)w[e];
+    const double wv = (double)ldnt(w + e);
 #pragma unroll
     for (int q = 0; q < kMaxInnerGmres; ++q)
-      if (q <= jstep) acc[q] += (double)Vbase[(long long)q * ldv + e] * wv;
+      if (q <= jstep) acc[q] += (double)ldnt(Vbase + (long long)q * ldv + e) * wv;
   }
   block_partials<kMaxInnerGmres>(acc, jstep + 1, part_out, gridDim.x);
 }
@@ -436,9 +436,9 @@ k_gmpc_orth(int jstep, int k, long long N, T* Vbase, long long ldv, const T* __r
   T* Vn = Vbase + (long long)(jstep + 1) * ldv;
   double acc[1] = {0.0};
   for (long long e = gtid(); e < N; e += gstride()) {
-    T v = w[e];
-    for (int q = 0; q <= jstep; ++q) v -= T(coef[q]) * Vbase[(long long)q * ldv + e];
-    if (store) Vn[e] = v;
+    T v = ldnt(w + e);
+    for (int q = 0; q <= jstep; ++q) v -= T(coef[q]) * ldnt(Vbase + (long long)q * ldv + e);
+    if (store) stnt(Vn + e, v);
     acc[0] += (double)v * (double)v;
   }
   block_partials<1>(acc, 1, part_out, gridDim.x);
