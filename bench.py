@@ -36,7 +36,8 @@ INNER = 5
 # two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB), each scaled by what the same counter reads for a 2 GiB
 # device-to-device copy (FETCH_SIZE reads 1,048,588 KiB for 2,097,152 KiB
 # moved: x2.000; WRITE_SIZE reads 2,097,152: x1.000).  Valid only for the
-# kernel source it was measured on (digest of its device body).
+# kernel source it was measured on (digest of its device body and of the
+# load/store helpers it uses).
 UPDATE_TRAFFIC = {"body_sha1": "64540aeaf4544d08", "fetch_kib": 8261903.9, "fetch_scale": 2.0,
                   "write_kib": 1050801.9, "write_scale": 1.0}
 
@@ -46,7 +47,7 @@ def update_traffic_bytes():
     has changed since the counters were taken."""
     import hashlib
     src = open(os.path.join(ROOT, "paper_1511_07226_amd", "csrc", "pfk_cg.hpp")).read()
-    i = src.index("void pipefcg_update_body(")
+    i = src.index("__device__ __forceinline__ double2 ld2(")
     j = src.index("k_pipefcg_update(", i)
     if hashlib.sha1(src[i:j].encode()).hexdigest()[:16] != UPDATE_TRAFFIC["body_sha1"]:
         return None

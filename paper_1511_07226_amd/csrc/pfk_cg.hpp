@@ -130,8 +130,8 @@ __device__ __forceinline__ void apply_pc_out_t(Blk bk, const Grid& g, const Sten
   const PcOut pc = make_pc_out(pd, &st->pc);
   double acc[2] = {0.0, 0.0};
   auto sink = [&](long long idx, double mc, double nv) {
-    if (O != nullptr) O[idx] = mc;
-    Nout[idx] = nv;
+    if (O != nullptr) stnt(O + idx, mc);
+    stnt(Nout + idx, nv);
     if (dots == 1) {            // <O, R>, <O, N>
       acc[0] += mc * R[idx];
       acc[1] += mc * nv;
