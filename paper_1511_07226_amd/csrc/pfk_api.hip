@@ -484,6 +484,11 @@ extern "C" size_t pfk_workspace_bytes(pfk_operator A, pfk_precond B, pfk_method 
 // ---------------------------------------------------------------------------
 // sessions
 // ---------------------------------------------------------------------------
+// Unknowns (times the batch capacity for batch members) from which the
+// vector kernels stream with nontemporal accesses: below it the L2 and the
+// Infinity Cache keep a solve's vectors between kernels.
+constexpr double kNtMinUnknowns = 1 << 20;
+
 struct pfk_session_s {
   pfk_operator A = nullptr;
   pfk_precond B = nullptr;
@@ -494,6 +499,7 @@ struct pfk_session_s {
   int maxit = 0, mmax = 0;
   double sigma = 0.0;
   pfk_solve_opts opts{};
+  int nt_scale = 1;                 // batch members: the batch capacity
   char* ws = nullptr;
   bool ws_owned = false;
   Layout L;
@@ -1124,8 +1130,11 @@ static int session_setup(pfk_session_s* S) {
     S->sigma = std::isnan(S->opts.shift_sigma) ? 0.0 : S->opts.shift_sigma;
   }
   const bool gm = S->method == PFK_FGMRES || S->method == PFK_PIPEFGMRES;
+  // nontemporal vector accesses once the solve's working set (the members of
+  // a batch together) is far beyond the caches
+  const int nt = (double)S->A->N * S->nt_scale >= kNtMinUnknowns;
   LAUNCH(k_setup, 1, S->s1, S->st, 0.0, S->maxit, S->mmax, S->opts.truncation, S->opts.force_breakdown_at,
-         S->sigma, gm ? 0 : S->opts.norm, S->nhist);
+         S->sigma, gm ? 0 : S->opts.norm, S->nhist, nt);
   LAUNCH(k_dot, S->Pv(), S->s1, S->A->N, S->b, S->b, S->part(PT_A));
   LAUNCH(k_setup_tol, 1, S->s1, S->part(PT_A), S->Pv(), S->rtol, S->st, S->hist);
   LAUNCH(k_zero_if_done, S->Pv(), S->s1, S->A->N, S->x, S->st);
@@ -1834,6 +1843,7 @@ extern "C" int pfk_batch_add(pfk_batch T, pfk_operator A, pfk_precond B, const d
   int rc = session_make(A, B, (pfk_method)T->method, b, x, rtol, maxit, T->mmax, workspace, ws_bytes, T->user,
                         &T->opts, T->s1, T->s2, &S);
   if (rc) return rc;
+  S->nt_scale = (int)T->mem.size();
   // order after the caller's queued work, then the set-up and the start-up
   HIPCHK(hipEventRecord(T->ev_user, T->user));
   HIPCHK(hipStreamWaitEvent(T->s1, T->ev_user, 0));

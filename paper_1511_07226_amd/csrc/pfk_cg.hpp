@@ -23,8 +23,9 @@ struct Window {
 // Shared kernels
 // ---------------------------------------------------------------------------
 __global__ void k_setup(SolveState* st, double tol, int maxit, int nu_max, int trunc, int force_it,
-                        double sigma, int norm, double* nhist) {
+                        double sigma, int norm, double* nhist, int nt) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  st->nt = nt;
   st->status = kRunning;
   st->it = 0;
   st->j = 0;
@@ -128,10 +129,16 @@ __device__ __forceinline__ void apply_pc_out_t(Blk bk, const Grid& g, const Sten
                                                double* __restrict__ Nout, int dots, const double* __restrict__ R,
                                                double* part, SolveState* st) {
   const PcOut pc = make_pc_out(pd, &st->pc);
+  const bool nt = st->nt != 0;
   double acc[2] = {0.0, 0.0};
   auto sink = [&](long long idx, double mc, double nv) {
-    if (O != nullptr) stnt(O + idx, mc);
-    stnt(Nout + idx, nv);
+    if (nt) {
+      if (O != nullptr) stnt(O + idx, mc);
+      stnt(Nout + idx, nv);
+    } else {
+      if (O != nullptr) O[idx] = mc;
+      Nout[idx] = nv;
+    }
     if (dots == 1) {            // <O, R>, <O, N>
       acc[0] += mc * R[idx];
       acc[1] += mc * nv;
@@ -250,25 +257,38 @@ k_pipefcg_init_scalars(const double* part_r, int P_r, const double* part_ud, int
 }
 
 // Two consecutive doubles per lane: one 16-byte access (the scalar tail of
-// an odd N reads/writes only .x).  The window and vector kernels stream
-// vectors far larger than the caches, so their accesses are nontemporal
-// (measured on the PIPEFCG update at 256^3: 3.66 -> 3.46 ms).
+// an odd N reads/writes only .x).  NT: nontemporal accesses, for solves whose
+// vectors are far larger than the caches (SolveState::nt; measured on the
+// PIPEFCG update at 256^3: 3.66 -> 3.46 ms); small systems keep ordinary
+// accesses, whose data the L2 and the Infinity Cache hold between kernels.
 typedef double pfk_d2v __attribute__((ext_vector_type(2)));
+template <bool NT>
 __device__ __forceinline__ double2 ld2(const double* p, long long e, bool full) {
-  if (full) {
-    const pfk_d2v v = __builtin_nontemporal_load(reinterpret_cast<const pfk_d2v*>(p + e));
-    return make_double2(v.x, v.y);
-  }
-  return make_double2(__builtin_nontemporal_load(p + e), 0.0);
-}
-__device__ __forceinline__ void st2(double* p, long long e, double2 v, bool full) {
-  if (full) {
-    pfk_d2v t;
-    t.x = v.x;
-    t.y = v.y;
-    __builtin_nontemporal_store(t, reinterpret_cast<pfk_d2v*>(p + e));
+  if constexpr (NT) {
+    if (full) {
+      const pfk_d2v v = __builtin_nontemporal_load(reinterpret_cast<const pfk_d2v*>(p + e));
+      return make_double2(v.x, v.y);
+    }
+    return make_double2(__builtin_nontemporal_load(p + e), 0.0);
   } else {
-    __builtin_nontemporal_store(v.x, p + e);
+    if (full) return *reinterpret_cast<const double2*>(p + e);
+    return make_double2(p[e], 0.0);
+  }
+}
+template <bool NT>
+__device__ __forceinline__ void st2(double* p, long long e, double2 v, bool full) {
+  if constexpr (NT) {
+    if (full) {
+      pfk_d2v t;
+      t.x = v.x;
+      t.y = v.y;
+      __builtin_nontemporal_store(t, reinterpret_cast<pfk_d2v*>(p + e));
+    } else {
+      __builtin_nontemporal_store(v.x, p + e);
+    }
+  } else {
+    if (full) *reinterpret_cast<double2*>(p + e) = v;
+    else p[e] = v.x;
   }
 }
 
@@ -285,7 +305,8 @@ __device__ __forceinline__ void st2(double* p, long long e, double2 v, bool full
 // consecutive nodes (16-byte accesses); the per-direction dot is summed over
 // the wave at once and accumulated in LDS, so the register footprint does not
 // grow with the window.  Vectors must be 16-byte aligned.
-__device__ __forceinline__ void pipefcg_update_body(Blk bk, long long N, Window P, Window S, Window Q, Window Z,
+template <bool NT>
+__device__ __forceinline__ void pipefcg_update_body_t(Blk bk, long long N, Window P, Window S, Window Q, Window Z,
                  double* __restrict__ x, double* __restrict__ r, double* __restrict__ u,
                  double* __restrict__ w, const double* __restrict__ m, const double* __restrict__ n,
                  double* part, const SolveState* st, int red_w) {
@@ -315,13 +336,13 @@ __device__ __forceinline__ void pipefcg_update_body(Blk bk, long long N, Window 
     const bool act = qw + lane < npair;
     const long long e = act ? 2 * (qw + lane) : 0;
     const bool full = act && e + 1 < N;
-    const double2 u0 = ld2(u, e, full), w0 = ld2(w, e, full);
-    double2 p = u0, q = ld2(m, e, full), z = ld2(n, e, full);
+    const double2 u0 = ld2<NT>(u, e, full), w0 = ld2<NT>(w, e, full);
+    double2 p = u0, q = ld2<NT>(m, e, full), z = ld2<NT>(n, e, full);
 #pragma unroll 4
     for (int t = 0; t < nu; ++t) {
       const double b = s_beta[t];
       const long long o = s_off[t] + e;
-      const double2 pv = ld2(P.base, o, full), qv = ld2(Q.base, o, full), zv = ld2(Z.base, o, full);
+      const double2 pv = ld2<NT>(P.base, o, full), qv = ld2<NT>(Q.base, o, full), zv = ld2<NT>(Z.base, o, full);
       p.x += b * pv.x; p.y += b * pv.y;
       q.x += b * qv.x; q.y += b * qv.y;
       z.x += b * zv.x; z.y += b * zv.y;
@@ -334,7 +355,7 @@ __device__ __forceinline__ void pipefcg_update_body(Blk bk, long long N, Window 
 #pragma unroll 4
     for (int t = 0; t < nu; ++t) {
       const double b = s_beta[t];
-      const double2 sd = ld2(S.base, s_off[t] + e, full);
+      const double2 sd = ld2<NT>(S.base, s_off[t] + e, full);
       sv.x += b * sd.x; sv.y += b * sd.y;
       if (t >= shift) {
         const double d = wave_sum(a.x * sd.x + a.y * sd.y);
@@ -342,18 +363,18 @@ __device__ __forceinline__ void pipefcg_update_body(Blk bk, long long N, Window 
       }
     }
     if (!act) continue;
-    const double2 r0 = ld2(r, e, full);
+    const double2 r0 = ld2<NT>(r, e, full);
     const double2 rn = make_double2(r0.x - alpha * sv.x, r0.y - alpha * sv.y);
-    double2 x0 = ld2(x, e, full);
+    double2 x0 = ld2<NT>(x, e, full);
     x0.x += alpha * p.x; x0.y += alpha * p.y;
-    st2(x, e, x0, full);
-    st2(P.base, ns + e, p, full);
-    st2(S.base, ns + e, sv, full);
-    st2(Q.base, ns + e, q, full);
-    st2(Z.base, ns + e, z, full);
-    st2(u, e, un, full);
-    st2(w, e, wn, full);
-    st2(r, e, rn, full);
+    st2<NT>(x, e, x0, full);
+    st2<NT>(P.base, ns + e, p, full);
+    st2<NT>(S.base, ns + e, sv, full);
+    st2<NT>(Q.base, ns + e, q, full);
+    st2<NT>(Z.base, ns + e, z, full);
+    st2<NT>(u, e, un, full);
+    st2<NT>(w, e, wn, full);
+    st2<NT>(r, e, rn, full);
     gam += a.x * rn.x + a.y * rn.y;
     del += a.x * wn.x + a.y * wn.y;
     rho += rn.x * rn.x + rn.y * rn.y;
@@ -378,6 +399,13 @@ __device__ __forceinline__ void pipefcg_update_body(Blk bk, long long N, Window 
     for (int wv = 0; wv < kWaves; ++wv) acc += s_dot[wv][src];
     part[(long long)c * bk.n + bk.id] = acc;
   }
+}
+__device__ __forceinline__ void pipefcg_update_body(Blk bk, long long N, Window P, Window S, Window Q, Window Z,
+                 double* __restrict__ x, double* __restrict__ r, double* __restrict__ u,
+                 double* __restrict__ w, const double* __restrict__ m, const double* __restrict__ n,
+                 double* part, const SolveState* st, int red_w) {
+  if (st->nt) pipefcg_update_body_t<true>(bk, N, P, S, Q, Z, x, r, u, w, m, n, part, st, red_w);
+  else pipefcg_update_body_t<false>(bk, N, P, S, Q, Z, x, r, u, w, m, n, part, st, red_w);
 }
 __global__ void __launch_bounds__(kBlock)
 k_pipefcg_update(long long N, Window P, Window S, Window Q, Window Z,
@@ -458,7 +486,8 @@ k_fcg_xr(long long N, Window P, Window S, double* __restrict__ x, double* __rest
 //   FCG:     V = u = B(r), R = r  (gamma = <u,r>, the test on <r,r>, <u,s_d>)
 //   GCR:     V = t = A u,  R = r  (the test on <r,r>, <t,s_d>)
 //   PIPEGCR: V = w = A u,  R = r  (gamma, delta, rho, <w,s_d>: its single reduction)
-__device__ __forceinline__ void multidot_body(Blk bk, long long N, int init, int from_pc, PcOutDesc pd, const double* __restrict__ Vin,
+template <bool NT>
+__device__ __forceinline__ void multidot_body_t(Blk bk, long long N, int init, int from_pc, PcOutDesc pd, const double* __restrict__ Vin,
            double* __restrict__ Vout, const double* __restrict__ R, Window S, double* part, SolveState* st) {
   if (read_status(st) != kRunning) return;
   PcOut pc{};
@@ -495,12 +524,12 @@ __device__ __forceinline__ void multidot_body(Blk bk, long long N, int init, int
       if (act) {
         v.x = pc(e);
         if (full) v.y = pc(e + 1);
-        st2(Vout, e, v, full);
+        st2<NT>(Vout, e, v, full);
       }
     } else if (act) {
-      v = ld2(Vin, e, full);
+      v = ld2<NT>(Vin, e, full);
     }
-    const double2 r = act ? ld2(R, e, full) : make_double2(0.0, 0.0);
+    const double2 r = act ? ld2<NT>(R, e, full) : make_double2(0.0, 0.0);
     vr += v.x * r.x + v.y * r.y;
     vv += v.x * v.x + v.y * v.y;
     rr += r.x * r.x + r.y * r.y;
@@ -513,7 +542,7 @@ __device__ __forceinline__ void multidot_body(Blk bk, long long N, int init, int
 #pragma unroll
           for (int t = c; t < c + 8; ++t) {
             if (t < nu) {
-              const double2 sd = ld2(S.base, s_off[t] + e, full);
+              const double2 sd = ld2<NT>(S.base, s_off[t] + e, full);
               acc[t] += v.x * sd.x + v.y * sd.y;
             }
           }
@@ -522,7 +551,7 @@ __device__ __forceinline__ void multidot_body(Blk bk, long long N, int init, int
       }
     } else {
       for (int t = 0; t < nu; ++t) {
-        const double2 sd = ld2(S.base, s_off[t] + e, full);
+        const double2 sd = ld2<NT>(S.base, s_off[t] + e, full);
         const double d = wave_sum(v.x * sd.x + v.y * sd.y);
         if (lane == 0) s_dot[wid][3 + t] += d;
       }
@@ -548,6 +577,11 @@ __device__ __forceinline__ void multidot_body(Blk bk, long long N, int init, int
     for (int wv = 0; wv < kWaves; ++wv) a += s_dot[wv][c];
     part[(long long)c * bk.n + bk.id] = a;
   }
+}
+__device__ __forceinline__ void multidot_body(Blk bk, long long N, int init, int from_pc, PcOutDesc pd, const double* __restrict__ Vin,
+           double* __restrict__ Vout, const double* __restrict__ R, Window S, double* part, SolveState* st) {
+  if (st->nt) multidot_body_t<true>(bk, N, init, from_pc, pd, Vin, Vout, R, S, part, st);
+  else multidot_body_t<false>(bk, N, init, from_pc, pd, Vin, Vout, R, S, part, st);
 }
 __global__ void __launch_bounds__(kBlock)
 k_multidot(long long N, int init, int from_pc, PcOutDesc pd, const double* __restrict__ Vin,
@@ -591,7 +625,8 @@ k_cg_scalars1(int init, const double* part, int P, SolveState* st, double* hist)
 }
 
 // p_j = u + sum beta p_d into slot j (FCG).
-__device__ __forceinline__ void fcg_maxpy_body(Blk bk, long long N, Window P, const double* __restrict__ u, const SolveState* st) {
+template <bool NT>
+__device__ __forceinline__ void fcg_maxpy_body_t(Blk bk, long long N, Window P, const double* __restrict__ u, const SolveState* st) {
   if (read_status(st) != kRunning) return;
   __shared__ double s_beta[kNuMax];
   __shared__ long long s_off[kNuMax];
@@ -606,21 +641,25 @@ __device__ __forceinline__ void fcg_maxpy_body(Blk bk, long long N, Window P, co
   for (long long qi = bk.gtid(); qi < npair; qi += bk.gstride()) {
     const long long e = 2 * qi;
     const bool full = e + 1 < N;
-    double2 p = ld2(u, e, full);
+    double2 p = ld2<NT>(u, e, full);
     int t = 0;
     for (; t + 4 <= nu; t += 4) {
       double2 v[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) v[q] = ld2(P.base, s_off[t + q] + e, full);
+      for (int q = 0; q < 4; ++q) v[q] = ld2<NT>(P.base, s_off[t + q] + e, full);
 #pragma unroll
       for (int q = 0; q < 4; ++q) { p.x += s_beta[t + q] * v[q].x; p.y += s_beta[t + q] * v[q].y; }
     }
     for (; t < nu; ++t) {
-      const double2 v = ld2(P.base, s_off[t] + e, full);
+      const double2 v = ld2<NT>(P.base, s_off[t] + e, full);
       p.x += s_beta[t] * v.x; p.y += s_beta[t] * v.y;
     }
-    st2(pn, e, p, full);
+    st2<NT>(pn, e, p, full);
   }
+}
+__device__ __forceinline__ void fcg_maxpy_body(Blk bk, long long N, Window P, const double* __restrict__ u, const SolveState* st) {
+  if (st->nt) fcg_maxpy_body_t<true>(bk, N, P, u, st);
+  else fcg_maxpy_body_t<false>(bk, N, P, u, st);
 }
 __global__ void __launch_bounds__(kBlock)
 k_fcg_maxpy(long long N, Window P, const double* __restrict__ u, const SolveState* st) {
@@ -629,9 +668,10 @@ k_fcg_maxpy(long long N, Window P, const double* __restrict__ u, const SolveStat
 
 // GCR: p_j = u + sum beta p_d, s_j = t + sum beta s_d into slot j, partials
 // <r, s_j>, <s_j, s_j> (gamma and eta of the second reduction).
-__global__ void __launch_bounds__(kBlock)
-k_gcr_maxpy(long long N, Window P, Window S, const double* __restrict__ u, const double* __restrict__ t_,
-            const double* __restrict__ r, double* part, const SolveState* st) {
+template <bool NT>
+__device__ __forceinline__ void gcr_maxpy_t(long long N, Window P, Window S, const double* __restrict__ u,
+                                            const double* __restrict__ t_, const double* __restrict__ r,
+                                            double* part, const SolveState* st) {
   if (read_status(st) != kRunning) return;
   __shared__ double s_beta[kNuMax];
   __shared__ long long s_off[kNuMax];
@@ -647,20 +687,26 @@ k_gcr_maxpy(long long N, Window P, Window S, const double* __restrict__ u, const
   for (long long qi = gtid(); qi < npair; qi += gstride()) {
     const long long e = 2 * qi;
     const bool full = e + 1 < N;
-    double2 p = ld2(u, e, full), s = ld2(t_, e, full);
+    double2 p = ld2<NT>(u, e, full), s = ld2<NT>(t_, e, full);
     for (int t = 0; t < nu; ++t) {
       const double b = s_beta[t];
-      const double2 pv = ld2(P.base, s_off[t] + e, full), sv = ld2(S.base, s_off[t] + e, full);
+      const double2 pv = ld2<NT>(P.base, s_off[t] + e, full), sv = ld2<NT>(S.base, s_off[t] + e, full);
       p.x += b * pv.x; p.y += b * pv.y;
       s.x += b * sv.x; s.y += b * sv.y;
     }
-    st2(P.base, ns + e, p, full);
-    st2(S.base, ns + e, s, full);
-    const double2 rv = ld2(r, e, full);
+    st2<NT>(P.base, ns + e, p, full);
+    st2<NT>(S.base, ns + e, s, full);
+    const double2 rv = ld2<NT>(r, e, full);
     acc[0] += rv.x * s.x + rv.y * s.y;
     acc[1] += s.x * s.x + s.y * s.y;
   }
   block_partials<2>(acc, 2, part, gridDim.x);
+}
+__global__ void __launch_bounds__(kBlock)
+k_gcr_maxpy(long long N, Window P, Window S, const double* __restrict__ u, const double* __restrict__ t_,
+            const double* __restrict__ r, double* part, const SolveState* st) {
+  if (st->nt) gcr_maxpy_t<true>(N, P, S, u, t_, r, part, st);
+  else gcr_maxpy_t<false>(N, P, S, u, t_, r, part, st);
 }
 
 // s_j = A p_j, partial eta_j = <p_j, s_j> (FCG).

@@ -292,7 +292,8 @@ k_pgm_scalars(const double* part, int P, SolveState* st, double* hist) {
 // As in PIPEFCG's update, each lane owns two consecutive nodes (16-byte
 // accesses) and the window loops are unrolled so that several independent
 // loads are in flight; the dot with p_j reuses the p_j load.
-__device__ __forceinline__ void pgm_update_body(Blk bk, long long N, Window P, Window U, Window ZB, PcOutDesc pd, const double* __restrict__ wb,
+template <bool NT>
+__device__ __forceinline__ void pgm_update_body_t(Blk bk, long long N, Window P, Window U, Window ZB, PcOutDesc pd, const double* __restrict__ wb,
              double* __restrict__ zin, double* part, SolveState* st) {
   if (read_status(st) != kRunning) return;
   const PcOut pc = make_pc_out(pd, &st->pc);
@@ -317,12 +318,12 @@ __device__ __forceinline__ void pgm_update_body(Blk bk, long long N, Window P, W
     const bool act = qw + lane < npair;
     const long long e = act ? 2 * (qw + lane) : 0;
     const bool full = act && e + 1 < N;
-    const double2 zp = ld2(zprev, e, full), wv = ld2(wb, e, full);
+    const double2 zp = ld2<NT>(zprev, e, full), wv = ld2<NT>(wb, e, full);
     double2 z = make_double2(wv.x - sigma * zp.x, wv.y - sigma * zp.y);
 #pragma unroll 4
     for (int j = 0; j < n; ++j) {
       const double h = s_h[j];
-      const double2 zj = ld2(ZB.base, (long long)j * ZB.ld + e, full);
+      const double2 zj = ld2<NT>(ZB.base, (long long)j * ZB.ld + e, full);
       z.x -= h * zj.x;
       z.y -= h * zj.y;
     }
@@ -333,7 +334,7 @@ __device__ __forceinline__ void pgm_update_body(Blk bk, long long N, Window P, W
 #pragma unroll 4
     for (int j = 0; j < n; ++j) {
       const double h = s_h[j];
-      const double2 pj = ld2(P.base, (long long)j * P.ld + e, full);
+      const double2 pj = ld2<NT>(P.base, (long long)j * P.ld + e, full);
       p.x -= h * pj.x;
       p.y -= h * pj.y;
       const double d = wave_sum(pj.x * z.x + pj.y * z.y);
@@ -345,17 +346,17 @@ __device__ __forceinline__ void pgm_update_body(Blk bk, long long N, Window P, W
 #pragma unroll 4
     for (int j = 0; j < n; ++j) {
       const double h = s_h[j];
-      const double2 uj = ld2(U.base, (long long)j * U.ld + e, full);
+      const double2 uj = ld2<NT>(U.base, (long long)j * U.ld + e, full);
       u.x -= h * uj.x;
       u.y -= h * uj.y;
     }
     u.x *= inv;
     u.y *= inv;
     if (!act) continue;
-    st2(pn, e, p, full);
-    st2(un, e, u, full);
-    st2(zn, e, z, full);
-    st2(zin, e, z, full);
+    st2<NT>(pn, e, p, full);
+    st2<NT>(un, e, u, full);
+    st2<NT>(zn, e, z, full);
+    st2<NT>(zin, e, z, full);
     dp += p.x * z.x + p.y * z.y;
     zz += z.x * z.x + z.y * z.y;
   }
@@ -370,6 +371,11 @@ __device__ __forceinline__ void pgm_update_body(Blk bk, long long N, Window P, W
     for (int wv = 0; wv < kWaves; ++wv) acc += s_dot[wv][c];
     part[(long long)c * bk.n + bk.id] = acc;
   }
+}
+__device__ __forceinline__ void pgm_update_body(Blk bk, long long N, Window P, Window U, Window ZB, PcOutDesc pd, const double* __restrict__ wb,
+             double* __restrict__ zin, double* part, SolveState* st) {
+  if (st->nt) pgm_update_body_t<true>(bk, N, P, U, ZB, pd, wb, zin, part, st);
+  else pgm_update_body_t<false>(bk, N, P, U, ZB, pd, wb, zin, part, st);
 }
 __global__ void __launch_bounds__(kBlock)
 k_pgm_update(long long N, Window P, Window U, Window ZB, PcOutDesc pd, const double* __restrict__ wb,

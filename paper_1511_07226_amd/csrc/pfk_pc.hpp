@@ -297,26 +297,40 @@ k_pcg_b(int jstep, long long N, const T* __restrict__ dinv,
     pcs->stopped[jstep] = stopped;
   }
   double acc[1] = {0.0};
-  for (long long e = gtid(); e < N; e += gstride()) {
-    T r;
-    T yv;
-    if (jstep == 1) {
-      double rv = c1 * ldnt(X1 + e);
-      if (X2 != nullptr) rv += c2 * ldnt(X2 + e);
-      r = T(rv);
-      yv = T(0);
-    } else {
-      r = ldnt(rho + e);
-      yv = ldnt(y + e);
+  // nontemporal accesses for vectors far larger than the caches (st->nt)
+  auto sweep = [&](auto ntc) {
+    constexpr bool NT = decltype(ntc)::value;
+    auto ld = [](const auto* a) {
+      if constexpr (NT) return ldnt(a);
+      else return *a;
+    };
+    auto sto = [](T* a, T v) {
+      if constexpr (NT) stnt(a, v);
+      else *a = v;
+    };
+    for (long long e = gtid(); e < N; e += gstride()) {
+      T r;
+      T yv;
+      if (jstep == 1) {
+        double rv = c1 * ld(X1 + e);
+        if (X2 != nullptr) rv += c2 * ld(X2 + e);
+        r = T(rv);
+        yv = T(0);
+      } else {
+        r = ld(rho + e);
+        yv = ld(y + e);
+      }
+      if (!stopped) {
+        yv += alpha * ld(p + e);
+        r -= alpha * ld(q + e);
+      }
+      sto(y + e, yv);
+      sto(rho + e, r);
+      acc[0] += (double)r * (double)(ld(dinv + e) * r);
     }
-    if (!stopped) {
-      yv += alpha * ldnt(p + e);
-      r -= alpha * ldnt(q + e);
-    }
-    stnt(y + e, yv);
-    stnt(rho + e, r);
-    acc[0] += (double)r * (double)(ldnt(dinv + e) * r);
-  }
+  };
+  if (st->nt) sweep(std::true_type{});
+  else sweep(std::false_type{});
   block_partials<1>(acc, 1, part_out, gridDim.x);
 }
 
@@ -406,10 +420,10 @@ k_gmpc_dots(int jstep, long long N, const T* Vbase, long long ldv, const T* __re
 #pragma unroll
   for (int q = 0; q < kMaxInnerGmres; ++q) acc[q] = 0.0;
   for (long long e = gtid(); e < N; e += gstride()) {
-    const double wv = (double)ldnt(w + e);
+    const double wv = (double)w[e];
 #pragma unroll
     for (int q = 0; q < kMaxInnerGmres; ++q)
-      if (q <= jstep) acc[q] += (double)ldnt(Vbase + (long long)q * ldv + e) * wv;
+      if (q <= jstep) acc[q] += (double)Vbase[(long long)q * ldv + e] * wv;
   }
   block_partials<kMaxInnerGmres>(acc, jstep + 1, part_out, gridDim.x);
 }
@@ -436,9 +450,9 @@ k_gmpc_orth(int jstep, int k, long long N, T* Vbase, long long ldv, const T* __r
   T* Vn = Vbase + (long long)(jstep + 1) * ldv;
   double acc[1] = {0.0};
   for (long long e = gtid(); e < N; e += gstride()) {
-    T v = ldnt(w + e);
-    for (int q = 0; q <= jstep; ++q) v -= T(coef[q]) * ldnt(Vbase + (long long)q * ldv + e);
-    if (store) stnt(Vn + e, v);
+    T v = w[e];
+    for (int q = 0; q <= jstep; ++q) v -= T(coef[q]) * Vbase[(long long)q * ldv + e];
+    if (store) Vn[e] = v;
     acc[0] += (double)v * (double)v;
   }
   block_partials<1>(acc, 1, part_out, gridDim.x);

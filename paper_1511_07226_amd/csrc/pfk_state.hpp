@@ -58,6 +58,7 @@ struct SolveState {
   double bnorm;      // ||b||_2
   int norm;          // CG/CR types: 1 tests the natural norm sqrt|gamma| instead of ||r||_2
   int nat_started;   // natural-norm history entry 0 recorded (first start-up)
+  int nt;            // vector kernels use nontemporal accesses (working set far beyond the caches)
   double rtol;
   double ntol;       // rtol * natural norm of the first start-up
   double* nhist;     // natural-norm history (device), or null
