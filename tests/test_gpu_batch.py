@@ -66,11 +66,15 @@ CASES = [("pipefcg", "block_jacobi_pcg", 0, False), ("pipefcg", "block_jacobi_pc
 FORMS = {0: "phased", 1: "persistent"}
 
 
+# capacity 256: members from 13^3 up stream with nontemporal accesses (N times
+# the capacity >= 2^20) while the single solves of these sizes do not; the
+# access hint must not change a bit of the arithmetic
+@pytest.mark.parametrize("capacity", [8, 256], ids=["cap8", "cap256"])
 @pytest.mark.parametrize("persistent", [0, 1], ids=[FORMS[f] for f in (0, 1)])
 @pytest.mark.parametrize("case", CASES, ids=[f"{m}-{k}-{'mixed' if p else 'fp64'}" for m, k, p, _ in CASES])
-def test_members_identical_to_single_solves(pfk, case, persistent):
+def test_members_identical_to_single_solves(pfk, case, persistent, capacity):
     method, kind, prec, conv = case
-    _say("batch identity", case, FORMS[persistent])
+    _say("batch identity", case, FORMS[persistent], "capacity", capacity)
     mem = _members(pfk, kind, prec, conv, tilings=[(64, 2048, 32), (32, 64, 7), (64, 5, 100)])
     sig = {}
     if method == "pipefgmres":
@@ -83,7 +87,7 @@ def test_members_identical_to_single_solves(pfk, case, persistent):
         singles.append((info, _host(x)))
     # PIPEFGMRES members estimate their own shift when they are added (the
     # same estimate pfk.estimate_sigma makes)
-    T = pfk.Batch(method, mmax=20, capacity=8, graph_iters=5, persistent=persistent)
+    T = pfk.Batch(method, mmax=20, capacity=capacity, graph_iters=5, persistent=persistent)
     xs, slots = {}, {}
     for i in range(len(mem)):
         p, A, B = mem[i]
