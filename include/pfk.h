@@ -233,8 +233,8 @@ size_t pfk_workspace_bytes(pfk_operator A, pfk_precond B, pfk_method method, int
  * measure is <= rtol * ||b||_2 and whose true residual confirms it, or after
  * maxit iterations.  mmax: window length nu_max (FCG/GCR types) or restart
  * length m (FGMRES types).  workspace: device memory of ws_bytes >=
- * pfk_workspace_bytes(...), or NULL to let the library allocate it for the
- * call.  opts may be NULL (defaults); info may be NULL.  Returns PFK_OK,
+ * pfk_workspace_bytes(...), 256-byte aligned, or NULL to let the library
+ * allocate it for the call.  opts may be NULL (defaults); info may be NULL.  Returns PFK_OK,
  * PFK_NOT_CONVERGED or an error.  b == 0 returns x = 0 after 0 iterations. */
 int pfk_solve(pfk_operator A, pfk_precond B, pfk_method method, const double* b, double* x,
               double rtol, int maxit, int mmax, void* workspace, size_t ws_bytes, void* stream,

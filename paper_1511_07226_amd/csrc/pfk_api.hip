@@ -1058,6 +1058,10 @@ static int session_make(pfk_operator A, pfk_precond B, pfk_method method, const 
   S->sg = A->sg;
   S->pv = A->pv_blocks;
   if (workspace) {
+    if ((uintptr_t)workspace % kAlign != 0) {
+      delete S;
+      return fail(PFK_ERR_ARG, "workspace must be 256-byte aligned");
+    }
     if (ws_bytes < S->L.total) {
       delete S;
       return fail(PFK_ERR_ARG, "workspace too small: need " + std::to_string(S->L.total) + " bytes");

@@ -104,3 +104,21 @@ def test_refuses_bad_sizes(pfk):
     assert pfk.workspace_bytes(A, B, "pipefcg", 0, 10) == 0
     assert pfk.workspace_bytes(A, B, "pipefcg", 10, -1) == 0
     assert pfk.workspace_bytes(A, B, "pipefcg", 10, 0) > 0
+
+
+def test_caller_workspace_alignment(pfk):
+    # a caller's workspace must be 256-byte aligned (the vectors inside it are
+    # accessed 16 bytes at a time); an offset view is refused before any launch
+    import torch
+    print("[case] storage workspace alignment", flush=True)
+    p = gen.study_problem(3, 12, seed=4)
+    A = pfk.Operator(3, 12, p.eta, None)
+    B = pfk.Precond(A, "jacobi_pcg", 3)
+    need = pfk.workspace_bytes(A, B, "pipefcg", 8, 50)
+    buf = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    b = torch.as_tensor(p.b).cuda()
+    x = torch.zeros_like(b)
+    with pytest.raises(pfk.PfkError):
+        pfk.solve(A, B, "pipefcg", b, x, rtol=1e-8, maxit=50, mmax=8, workspace=buf[8:8 + need])
+    info = pfk.solve(A, B, "pipefcg", b, x, rtol=1e-8, maxit=50, mmax=8, workspace=buf[256:256 + need])
+    assert info.iterations > 0
