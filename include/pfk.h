@@ -190,7 +190,8 @@ int pfk_precond_create(pfk_operator A, pfk_pc_kind kind, int inner_its, pfk_prec
  * Errors: PFK_ERR_ARG (eta negative or not finite, null pointers), PFK_ERR_OOM. */
 int pfk_precond_create_noisy(pfk_operator A, double eta, uint64_t seed, pfk_precond* out);
 void pfk_precond_destroy(pfk_precond B);
-/* y = B(v) for device vectors (synchronous w.r.t. stream completion of the call). */
+/* y = B(v) for device vectors, 16-byte aligned (synchronous w.r.t. stream
+ * completion of the call). */
 int pfk_precond_apply(pfk_precond B, const double* v, double* y, void* stream);
 
 /* Launch geometry of A's kernels (performance only; results do not depend

@@ -111,10 +111,11 @@ k_pc_write(long long N, PcOutDesc pd, double* __restrict__ y, SolveState* st) {
   for (long long e = gtid(); e < N; e += gstride()) y[e] = pc(e);
 }
 
-__global__ void k_set_running(SolveState* st) {
+__global__ void k_set_running(SolveState* st, int nt) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     st->status = kRunning;
     st->pc.ndraws = 0;
+    st->nt = nt;
   }
 }
 
@@ -527,6 +528,12 @@ struct pfk_session_s {
   int noise_apps = 0;                 // noisy PC: applications enqueued in the current phase
 };
 
+// Nontemporal vector accesses once the solve's working set (the members of a
+// batch together) is far beyond the caches.
+inline int session_nt(const pfk_session_s* S) {
+  return (double)S->A->N * S->nt_scale >= kNtMinUnknowns ? 1 : 0;
+}
+
 namespace {
 
 // Optional per-kernel timing (pfk_session_profile): HIP events recorded on
@@ -934,7 +941,7 @@ void enqueue_sigma_estimate(pfk_session_s* S, hipStream_t s, int its) {
   const pfk_operator_s* A = S->A;
   double* v = S->vec(V_VIN);
   double* w = S->vec(V_Z);
-  LAUNCH(k_set_running, 1, s, S->st);
+  LAUNCH(k_set_running, 1, s, S->st, session_nt(S));
   noise_begin(S, s);
   LAUNCH(k_fill, S->Pv(), s, A->N, v, 1.0 / std::sqrt((double)A->N));
   for (int i = 0; i < its; ++i) {
@@ -1134,9 +1141,7 @@ static int session_setup(pfk_session_s* S) {
     S->sigma = std::isnan(S->opts.shift_sigma) ? 0.0 : S->opts.shift_sigma;
   }
   const bool gm = S->method == PFK_FGMRES || S->method == PFK_PIPEFGMRES;
-  // nontemporal vector accesses once the solve's working set (the members of
-  // a batch together) is far beyond the caches
-  const int nt = (double)S->A->N * S->nt_scale >= kNtMinUnknowns;
+  const int nt = session_nt(S);
   LAUNCH(k_setup, 1, S->s1, S->st, 0.0, S->maxit, S->mmax, S->opts.truncation, S->opts.force_breakdown_at,
          S->sigma, gm ? 0 : S->opts.norm, S->nhist, nt);
   LAUNCH(k_dot, S->Pv(), S->s1, S->A->N, S->b, S->b, S->part(PT_A));
@@ -1276,6 +1281,7 @@ extern "C" int pfk_solve(pfk_operator A, pfk_precond B, pfk_method method, const
 
 extern "C" int pfk_precond_apply(pfk_precond B, const double* v, double* y, void* stream) {
   if (!B || !v || !y) return fail(PFK_ERR_ARG, "null argument");
+  if (((uintptr_t)v | (uintptr_t)y) % 16 != 0) return fail(PFK_ERR_ARG, "v and y must be 16-byte aligned");
   pfk_operator A = B->A;
   Layout L = make_layout(A, B, PFK_FCG, 1, 1);
   if (!B->scratch || B->scratch_bytes < L.total) {
@@ -1290,7 +1296,7 @@ extern "C" int pfk_precond_apply(pfk_precond B, const double* v, double* y, void
   S.st = (SolveState*)(S.ws + L.state);
   if (B->kind == PFK_PC_NOISY) S.noise_draw = B->draws++;
   hipStream_t s = (hipStream_t)stream;
-  LAUNCH(k_set_running, 1, s, S.st);
+  LAUNCH(k_set_running, 1, s, S.st, session_nt(&S));
   PcOutDesc pd = enqueue_pc(&S, s, v, 1.0, nullptr, 0.0);
   LAUNCH(k_pc_write, A->pv_blocks, s, A->N, pd, y, S.st);
   HIPCHK(hipGetLastError());

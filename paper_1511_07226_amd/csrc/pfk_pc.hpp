@@ -297,20 +297,69 @@ k_pcg_b(int jstep, long long N, const T* __restrict__ dinv,
     pcs->stopped[jstep] = stopped;
   }
   double acc[1] = {0.0};
-  // nontemporal accesses for vectors far larger than the caches (st->nt)
+  // VW nodes per lane (16-byte accesses to the T vectors; all vectors start
+  // 16-byte aligned), the scalar tail after; nontemporal accesses for vectors
+  // far larger than the caches (st->nt).  The arithmetic per node is the same.
+  constexpr int VW = 16 / sizeof(T);
+  typedef T tv_t __attribute__((ext_vector_type(VW)));
+  typedef double dv_t __attribute__((ext_vector_type(VW), aligned(16)));   // X1, X2 16-byte aligned
   auto sweep = [&](auto ntc) {
     constexpr bool NT = decltype(ntc)::value;
     auto ld = [](const auto* a) {
       if constexpr (NT) return ldnt(a);
       else return *a;
     };
-    auto sto = [](T* a, T v) {
+    auto sto = [](auto* a, auto v) {
       if constexpr (NT) stnt(a, v);
       else *a = v;
     };
-    for (long long e = gtid(); e < N; e += gstride()) {
-      T r;
-      T yv;
+    auto node = [&](T r, T yv, T pv, T qv, T dv, T& ro, T& yo) {
+      if (!stopped) {
+        yv += alpha * pv;
+        r -= alpha * qv;
+      }
+      yo = yv;
+      ro = r;
+      acc[0] += (double)r * (double)(dv * r);
+    };
+    const long long nv = N / VW;
+    for (long long qv = gtid(); qv < nv; qv += gstride()) {
+      const long long e = qv * VW;
+      tv_t r, yv;
+      if (jstep == 1) {
+        const dv_t x1 = ld(reinterpret_cast<const dv_t*>(X1 + e));
+        dv_t x2 = {};
+        if (X2 != nullptr) x2 = ld(reinterpret_cast<const dv_t*>(X2 + e));
+#pragma unroll
+        for (int l = 0; l < VW; ++l) {
+          double rv = c1 * x1[l];
+          if (X2 != nullptr) rv += c2 * x2[l];
+          r[l] = T(rv);
+          yv[l] = T(0);
+        }
+      } else {
+        r = ld(reinterpret_cast<const tv_t*>(rho + e));
+        yv = ld(reinterpret_cast<const tv_t*>(y + e));
+      }
+      tv_t pv = {}, qv4 = {};
+      if (!stopped) {
+        pv = ld(reinterpret_cast<const tv_t*>(p + e));
+        qv4 = ld(reinterpret_cast<const tv_t*>(q + e));
+      }
+      const tv_t dv = ld(reinterpret_cast<const tv_t*>(dinv + e));
+      tv_t ro, yo;
+#pragma unroll
+      for (int l = 0; l < VW; ++l) {
+        T rl, yl;
+        node(r[l], yv[l], pv[l], qv4[l], dv[l], rl, yl);
+        ro[l] = rl;
+        yo[l] = yl;
+      }
+      sto(reinterpret_cast<tv_t*>(y + e), yo);
+      sto(reinterpret_cast<tv_t*>(rho + e), ro);
+    }
+    for (long long e = nv * VW + gtid(); e < N; e += gstride()) {
+      T r, yv;
       if (jstep == 1) {
         double rv = c1 * ld(X1 + e);
         if (X2 != nullptr) rv += c2 * ld(X2 + e);
@@ -320,13 +369,12 @@ k_pcg_b(int jstep, long long N, const T* __restrict__ dinv,
         r = ld(rho + e);
         yv = ld(y + e);
       }
-      if (!stopped) {
-        yv += alpha * ld(p + e);
-        r -= alpha * ld(q + e);
-      }
-      sto(y + e, yv);
-      sto(rho + e, r);
-      acc[0] += (double)r * (double)(ld(dinv + e) * r);
+      const T pv = stopped ? T(0) : ld(p + e);
+      const T qv = stopped ? T(0) : ld(q + e);
+      T ro, yo;
+      node(r, yv, pv, qv, ld(dinv + e), ro, yo);
+      sto(y + e, yo);
+      sto(rho + e, ro);
     }
   };
   if (st->nt) sweep(std::true_type{});
