@@ -579,19 +579,62 @@ __device__ __forceinline__ double wave_allsum(double v) {
 // plane within the block.  (A_bb u)_c = d u_c - sum_f o_f u_f, faces in the
 // order x+, x-, y+, y-, z+, z-; o_f = 0 for a neighbour outside the block or
 // on the boundary.
-template <class T, class G>
-__device__ __forceinline__ void bj_coeffs(const G& g, int i, int j, int k, int lx, int ly, int zl, T& d,
-                                          T (&o)[6]) {
+// The global loads of one node's block coefficients (viscosity at the node
+// and its six neighbours; face velocities when the operator has them) and of
+// its input X1, X2: loads only, so every plane's loads are in flight at once.
+template <class EC, class VC>
+struct BjRaw {
+  EC e[7];
+  VC v[6];
+  double x1, x2;
+};
+template <class G, class EC, class VC>
+__device__ __forceinline__ void bj_load(const G& g, int i, int j, int k, const double* X1, const double* X2,
+                                        BjRaw<EC, VC>& r) {
   const long long pc = padded_index(g, i, j, k);
   const bool d3 = g.dim == 3;
-  const T ec = T(to_real(g.eta[pc]));
+  r.e[0] = g.eta[pc];
+  r.e[1] = g.eta[pc + 1];
+  r.e[2] = g.eta[pc - 1];
+  r.e[3] = g.eta[pc + g.sy];
+  r.e[4] = g.eta[pc - g.sy];
+  if (d3) {
+    r.e[5] = g.eta[pc + g.sz];
+    r.e[6] = g.eta[pc - g.sz];
+  }
+  if (g.vel != nullptr) {
+    const auto* vx = g.vel;
+    const auto* vy = g.vel + g.vstride;
+    const auto* vz = g.vel + 2 * g.vstride;
+    r.v[0] = vx[pc];
+    r.v[1] = vx[pc - 1];
+    r.v[2] = vy[pc];
+    r.v[3] = vy[pc - g.sy];
+    if (d3) {
+      r.v[4] = vz[pc];
+      r.v[5] = vz[pc - g.sz];
+    }
+  }
+  const long long e = vec_index(g, i, j, k);
+  r.x1 = X1[e];
+  if (X2 != nullptr) r.x2 = X2[e];
+}
+
+// A node's row of its block's matrix A_bb from the loaded values: diagonal d
+// (of A, kept whole) and the in-block off-diagonal magnitudes o (x+, x-, y+,
+// y-, z+, z-; zero where the neighbour is outside the block or the domain).
+template <class T, class G, class EC, class VC>
+__device__ __forceinline__ void bj_coeffs(const G& g, const BjRaw<EC, VC>& r, int i, int j, int k, int lx, int ly,
+                                          int zl, T& d, T (&o)[6]) {
+  const bool d3 = g.dim == 3;
+  const T ec = T(to_real(r.e[0]));
   T kf[6];
-  kf[0] = harmonic(ec, T(to_real(g.eta[pc + 1])));
-  kf[1] = harmonic(ec, T(to_real(g.eta[pc - 1])));
-  kf[2] = harmonic(ec, T(to_real(g.eta[pc + g.sy])));
-  kf[3] = harmonic(ec, T(to_real(g.eta[pc - g.sy])));
-  kf[4] = d3 ? harmonic(ec, T(to_real(g.eta[pc + g.sz]))) : T(0);
-  kf[5] = d3 ? harmonic(ec, T(to_real(g.eta[pc - g.sz]))) : T(0);
+  kf[0] = harmonic(ec, T(to_real(r.e[1])));
+  kf[1] = harmonic(ec, T(to_real(r.e[2])));
+  kf[2] = harmonic(ec, T(to_real(r.e[3])));
+  kf[3] = harmonic(ec, T(to_real(r.e[4])));
+  kf[4] = d3 ? harmonic(ec, T(to_real(r.e[5]))) : T(0);
+  kf[5] = d3 ? harmonic(ec, T(to_real(r.e[6]))) : T(0);
   const bool in[6] = {lx + 1 < kBjEdge && i + 1 < g.nx, lx > 0,
                       ly + 1 < kBjEdge && j + 1 < g.ny, ly > 0,
                       d3 && zl + 1 < kBjEdge && k + 1 < g.nz, d3 && zl > 0};
@@ -602,16 +645,13 @@ __device__ __forceinline__ void bj_coeffs(const G& g, int i, int j, int k, int l
   dd *= h2;
   T vn[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
   if (g.vel != nullptr) {
-    const auto* vx = g.vel;
-    const auto* vy = g.vel + g.vstride;
-    const auto* vz = g.vel + 2 * g.vstride;
-    vn[0] = T(to_real(vx[pc]));
-    vn[1] = -T(to_real(vx[pc - 1]));
-    vn[2] = T(to_real(vy[pc]));
-    vn[3] = -T(to_real(vy[pc - g.sy]));
+    vn[0] = T(to_real(r.v[0]));
+    vn[1] = -T(to_real(r.v[1]));
+    vn[2] = T(to_real(r.v[2]));
+    vn[3] = -T(to_real(r.v[3]));
     if (d3) {
-      vn[4] = T(to_real(vz[pc]));
-      vn[5] = -T(to_real(vz[pc - g.sz]));
+      vn[4] = T(to_real(r.v[4]));
+      vn[5] = -T(to_real(r.v[5]));
     }
     T up = T(0);
 #pragma unroll
@@ -647,19 +687,28 @@ __device__ __forceinline__ void block_pcg_body(Blk bk, G g, int wx, int wy, int 
   int slot[NPT];
   bool valid[NPT];
   double acc = 0.0;
+  // every plane's loads first, then the arithmetic on them
+  using EC = typename std::remove_cv<typename std::remove_pointer<decltype(g.eta)>::type>::type;
+  using VC = typename std::remove_cv<typename std::remove_pointer<decltype(g.vel)>::type>::type;
+  BjRaw<EC, VC> raw[NPT];
 #pragma unroll
   for (int n = 0; n < NPT; ++n) {
     const int zl = zh * NPT + n;
     const int kz = gz * ZL + zl;
     slot[n] = ((blk * ZL + zl) * kBjEdge + ly) * kBjEdge + lx;
     valid[n] = col && kz < g.nz;
+    if (valid[n]) bj_load(g, i, j, kz, X1, X2, raw[n]);
+  }
+#pragma unroll
+  for (int n = 0; n < NPT; ++n) {
+    const int zl = zh * NPT + n;
+    const int kz = gz * ZL + zl;
     y[n] = T(0);
     if (valid[n]) {
-      bj_coeffs<T>(g, i, j, kz, lx, ly, zl, dg[n], o[n]);
+      bj_coeffs<T>(g, raw[n], i, j, kz, lx, ly, zl, dg[n], o[n]);
       dinv[n] = T(1) / dg[n];
-      const long long e = vec_index(g, i, j, kz);
-      double v = c1 * X1[e];
-      if (X2 != nullptr) v += c2 * X2[e];
+      double v = c1 * raw[n].x1;
+      if (X2 != nullptr) v += c2 * raw[n].x2;
       r[n] = T(v);
     } else {
 #pragma unroll
