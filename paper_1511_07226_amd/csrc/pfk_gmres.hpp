@@ -311,6 +311,9 @@ __device__ __forceinline__ void pgm_update_body_t(Blk bk, long long N, Window P,
   double* un = U.slot(n);
   double* zn = ZB.slot(n);
   double dp = 0.0, zz = 0.0;
+  const bool gm2 = gm_raw_ok(pc);
+  const float* gmV = static_cast<const float*>(pc.vbase);
+  const float* gmD = static_cast<const float*>(pc.dinv_in);
   const long long npair = (N + 1) / 2;
   // wave-uniform trip count (wave sums inside); lanes past the end use
   // element 0, contribute 0 and store nothing
@@ -342,7 +345,24 @@ __device__ __forceinline__ void pgm_update_body_t(Blk bk, long long N, Window P,
     }
     p.x *= inv;
     p.y *= inv;
-    double2 u = make_double2(pc(e), full ? pc(e + 1) : 0.0);
+    double2 u;
+    if (gm2 && full) {
+      // B(zbar) from an FP32 inner GMRES output, both nodes per 8-byte load
+      // (PcOut's arithmetic: dinv * sum cf_q V_q)
+      const float2 dv = *reinterpret_cast<const float2*>(gmD + e);
+      double r0 = 0.0, r1 = 0.0;
+#pragma unroll
+      for (int q = 0; q < kGmRaw; ++q) {
+        if (q < pc.nv) {
+          const float2 vq = *reinterpret_cast<const float2*>(gmV + (long long)q * pc.ldv + e);
+          r0 += pc.cf[q] * (double)vq.x;
+          r1 += pc.cf[q] * (double)vq.y;
+        }
+      }
+      u = make_double2((double)dv.x * r0, (double)dv.y * r1);
+    } else {
+      u = make_double2(pc(e), full ? pc(e + 1) : 0.0);
+    }
 #pragma unroll 4
     for (int j = 0; j < n; ++j) {
       const double h = s_h[j];
