@@ -112,3 +112,30 @@ def test_mixed_solves_reach_tolerance(pfk, method, kind, k, conv):
         return
     assert info.converged and true_rel <= 1e-8
     assert sol_err <= 1e-5
+
+
+@pytest.mark.parametrize("n", [21, 20], ids=["odd-N", "even-N"])
+def test_mixed_pipefgmres_history_follows_rounded_oracle(pfk, n):
+    # PIPEFGMRES with the FP32 inner GMRES: the update evaluates B(zbar) from
+    # the inner basis two nodes per load (an odd N leaves a one-node tail).
+    # Its residual history follows the FP64 oracle whose inner solve runs on
+    # the BF16-rounded viscosity and FP32 velocities; the remaining difference
+    # is the inner solve's FP32 arithmetic (about 1e-6 relative per
+    # application), so the bar is 1e-4 over the first 12 iterations -- a wrong
+    # basis vector, coefficient or node would differ at order one.
+    _say("mixed pipefgmres history", n)
+    p = gen.make_problem(3, n, 4, 2.0, seed=7, convection=True)
+    Ao = oracle.StencilOperator(3, n, p.eta, p.vel)
+    Ar = oracle.StencilOperator(3, n, bf16_round(p.eta), p.vel.astype(np.float32).astype(np.float64))
+    Bo = oracle.make_pc("jacobi_gmres", Ar, 5)
+    sigma = oracle.estimate_sigma(Ao.apply, Bo, Ao.N)
+    ref = oracle.solve("pipefgmres", Ao, Bo, p.b, rtol=0.0, maxit=12, nu_max=30, sigma=sigma)
+    Ag = pfk.Operator(3, n, p.eta, p.vel)
+    Bg = pfk.Precond(Ag, "jacobi_gmres", 5, precision=pfk.FP32_BF16COEF)
+    x = _dev(np.zeros(Ao.N))
+    info = pfk.solve(Ag, Bg, "pipefgmres", _dev(p.b), x, rtol=0.0, maxit=12, mmax=30, shift_sigma=float(sigma))
+    h, hr = info.history, np.array(ref.history)
+    assert len(h) == len(hr) == 13
+    rel = np.abs(h - hr) / np.abs(hr)
+    print(f"  max relative history difference {rel.max():.2e}")
+    assert rel.max() <= 1e-4, rel
