@@ -74,7 +74,8 @@ class PfkError(RuntimeError):
 class SolveOpts(C.Structure):
     _fields_ = [("truncation", C.c_int), ("shift_sigma", C.c_double), ("graph_iters", C.c_int),
                 ("use_graph", C.c_int), ("host_sync", C.c_int), ("max_restarts", C.c_int),
-                ("force_breakdown_at", C.c_int), ("persistent", C.c_int), ("norm", C.c_int)]
+                ("force_breakdown_at", C.c_int), ("persistent", C.c_int), ("norm", C.c_int),
+                ("side_delay", C.c_int)]
 
 
 class _Info(C.Structure):

@@ -111,6 +111,12 @@ k_pc_write(long long N, PcOutDesc pd, double* __restrict__ y, SolveState* st) {
   for (long long e = gtid(); e < N; e += gstride()) y[e] = pc(e);
 }
 
+// Test hook: one wave sleeps `rounds` times (s_sleep 127 each), a fixed,
+// bounded delay on the stream it is launched on.
+__global__ void k_delay(int rounds) {
+  for (int r = 0; r < rounds; ++r) __builtin_amdgcn_s_sleep(127);
+}
+
 __global__ void k_set_running(SolveState* st, int nt) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     st->status = kRunning;
@@ -212,6 +218,7 @@ extern "C" void pfk_default_opts(pfk_solve_opts* o) {
   o->force_breakdown_at = -1;
   o->persistent = 0;
   o->norm = 0;
+  o->side_delay = 0;
 }
 
 extern "C" int pfk_operator_create(int dim, const int64_t n[3], const double* eta, const double* face_vel,
@@ -842,6 +849,11 @@ void enqueue_start(pfk_session_s* S, hipStream_t s) {
   noise_end(S, s);
 }
 
+// The stream-join test hook (opts.side_delay): a bounded delay on stream s.
+void side_delay(const pfk_session_s* S, hipStream_t s) {
+  if (S->opts.side_delay > 0) LAUNCH(k_delay, 1, s, S->opts.side_delay);
+}
+
 // One iteration.
 void enqueue_iteration(pfk_session_s* S) {
   const pfk_operator_s* A = S->A;
@@ -863,6 +875,7 @@ void enqueue_iteration(pfk_session_s* S) {
       // fork: finish the reduction on s2 while s1 applies B and A
       (void)hipEventRecord(S->ev_fork, s1);
       (void)hipStreamWaitEvent(s2, S->ev_fork, 0);
+      side_delay(S, s2);
       LAUNCH(k_pipefcg_scalars, 1, s2, S->part(PT_MAIN), S->Pv(), S->st, S->hist);
       (void)hipEventRecord(S->ev_join, s2);
       // m = u + B(w - r) (Alg. 8, 12); the naive form (Alg. 7) takes m = B(w)
@@ -883,6 +896,7 @@ void enqueue_iteration(pfk_session_s* S) {
       enqueue_multidot(S, s1, 0, 0, pd_prev, S->vec(V_W), nullptr);
       (void)hipEventRecord(S->ev_fork, s1);
       (void)hipStreamWaitEvent(s2, S->ev_fork, 0);
+      side_delay(S, s2);
       LAUNCH(k_pipefcg_scalars, 1, s2, S->part(PT_MAIN), S->Pv(), S->st, S->hist);
       (void)hipEventRecord(S->ev_join, s2);
       enqueue_pc(S, s1, S->vec(V_W), 1.0, S->vec(V_R), -1.0);
@@ -913,6 +927,7 @@ void enqueue_iteration(pfk_session_s* S) {
              (const double*)S->vec(V_Z), S->vec(V_M), S->part(PT_MAIN), S->st);
       (void)hipEventRecord(S->ev_fork, s1);
       (void)hipStreamWaitEvent(s2, S->ev_fork, 0);
+      side_delay(S, s2);
       LAUNCH(k_pgm_scalars, 1, s2, S->part(PT_MAIN), S->Pv(), S->st, S->hist);
       (void)hipEventRecord(S->ev_join, s2);
       PcOutDesc pd = enqueue_pc(S, s1, S->vec(V_M), 1.0, nullptr, 0.0);
@@ -1053,6 +1068,10 @@ static int session_make(pfk_operator A, pfk_precond B, pfk_method method, const 
   if (S->opts.norm < 0 || S->opts.norm > 1) {
     delete S;
     return fail(PFK_ERR_ARG, "norm must be 0 (2-norm) or 1 (natural)");
+  }
+  if (S->opts.side_delay < 0 || S->opts.side_delay > 10000) {
+    delete S;
+    return fail(PFK_ERR_ARG, "side_delay must be 0..10000");
   }
   if (S->opts.host_sync) {
     if (method != PFK_FCG && method != PFK_GCR && method != PFK_FGMRES) {
