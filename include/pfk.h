@@ -125,7 +125,8 @@ typedef struct {
                               then accepted without the 2-norm check (true_rel_resid
                               still reports it).  GMRES types ignore it (they test the
                               Givens estimate of the preconditioned residual).       */
-  int side_delay;          /* test hook: before each reduction finish on the second
+  int side_delay;          /* test hook (single solves and sessions; batches ignore it):
+                              before each reduction finish on the second
                               stream, a one-workgroup kernel sleeps this many rounds
                               of s_sleep 127 (about 3.4 us each; 0..10000, 0 off), so
                               a missing join between the streams would show in the
