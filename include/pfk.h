@@ -125,6 +125,11 @@ typedef struct {
                               then accepted without the 2-norm check (true_rel_resid
                               still reports it).  GMRES types ignore it (they test the
                               Givens estimate of the preconditioned residual).       */
+  int timestamps;          /* 1: record the device clock at every history entry (the
+                              scalar kernel that logs it reads the GPU's constant-rate
+                              wall clock); returned as iter_time_us (single solves,
+                              sessions and batch members; the server does not keep
+                              it)                                                    */
   int side_delay;          /* test hook (single solves and sessions; batches ignore it):
                               before each reduction finish on the second
                               stream, a one-workgroup kernel sleeps this many rounds
@@ -149,6 +154,10 @@ typedef struct {
                               the first start-up (CG/CR types; logged in either norm
                               mode).  The server does not keep it.                   */
   int natural_len;         /* entries written (0 for GMRES types)                     */
+  double* iter_time_us;    /* caller buffer (host, history_cap entries) or NULL: with
+                              opts.timestamps, microseconds from history entry 0 to
+                              entry i on the device clock                             */
+  int iter_time_len;       /* entries written (0 without opts.timestamps)             */
 } pfk_solve_info;
 
 /* Defaults: standard truncation, sigma estimated, graph_iters 8, graphs on,

@@ -75,14 +75,15 @@ class SolveOpts(C.Structure):
     _fields_ = [("truncation", C.c_int), ("shift_sigma", C.c_double), ("graph_iters", C.c_int),
                 ("use_graph", C.c_int), ("host_sync", C.c_int), ("max_restarts", C.c_int),
                 ("force_breakdown_at", C.c_int), ("persistent", C.c_int), ("norm", C.c_int),
-                ("side_delay", C.c_int)]
+                ("timestamps", C.c_int), ("side_delay", C.c_int)]
 
 
 class _Info(C.Structure):
     _fields_ = [("iterations", C.c_int), ("restarts", C.c_int), ("converged", C.c_int),
                 ("status", C.c_int), ("true_rel_resid", C.c_double),
                 ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int), ("history_len", C.c_int),
-                ("natural_history", C.POINTER(C.c_double)), ("natural_len", C.c_int)]
+                ("natural_history", C.POINTER(C.c_double)), ("natural_len", C.c_int),
+                ("iter_time_us", C.POINTER(C.c_double)), ("iter_time_len", C.c_int)]
 
 
 @dataclass
@@ -94,6 +95,7 @@ class SolveInfo:
     true_rel_resid: float
     history: np.ndarray
     natural: np.ndarray = None      # sqrt|gamma_i| per iteration (CG/CR types), else empty
+    iter_time_us: np.ndarray = None  # device time of each history entry (opts timestamps=1), else empty
 
     @property
     def status_name(self) -> str:
@@ -316,19 +318,21 @@ def estimate_sigma(A: Operator, B: Precond, its: int = 10, stream=None) -> float
 
 
 def _info_struct(cap: int, info=None):
-    """An info record with host buffers for both histories (row 0: the
-    residual measure, row 1: the natural norm)."""
+    """An info record with host buffers for the histories (row 0: the
+    residual measure, row 1: the natural norm, row 2: device timestamps)."""
     info = _Info() if info is None else info
-    hist = np.zeros((2, max(cap, 1)), dtype=np.float64)
+    hist = np.zeros((3, max(cap, 1)), dtype=np.float64)
     info.history = hist[0].ctypes.data_as(C.POINTER(C.c_double))
     info.natural_history = hist[1].ctypes.data_as(C.POINTER(C.c_double))
+    info.iter_time_us = hist[2].ctypes.data_as(C.POINTER(C.c_double))
     info.history_cap = cap
     return info, hist
 
 
 def _to_info(code: int, info: _Info, hist: np.ndarray) -> SolveInfo:
     return SolveInfo(code, info.iterations, info.restarts, bool(info.converged), info.true_rel_resid,
-                     hist[0, : info.history_len].copy(), hist[1, : info.natural_len].copy())
+                     hist[0, : info.history_len].copy(), hist[1, : info.natural_len].copy(),
+                     hist[2, : info.iter_time_len].copy())
 
 
 def solve(A: Operator, B: Precond, method: str, b, x, rtol: float = 1e-8, maxit: int = 500,

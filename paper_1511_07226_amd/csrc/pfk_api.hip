@@ -218,6 +218,7 @@ extern "C" void pfk_default_opts(pfk_solve_opts* o) {
   o->force_breakdown_at = -1;
   o->persistent = 0;
   o->norm = 0;
+  o->timestamps = 0;
   o->side_delay = 0;
 }
 
@@ -422,7 +423,7 @@ enum Win { W_P, W_S, W_Q, W_Z, W_PCV, W_COUNT };  // W_PCV: inner GMRES basis
 enum Part { PT_MAIN, PT_A, PT_B, PT_PC0, PT_PC1, PT_COUNT };
 
 struct Layout {
-  size_t state = 0, hist = 0, nhist = 0;
+  size_t state = 0, hist = 0, nhist = 0, tstamp = 0;
   size_t vec[V_COUNT] = {};
   size_t win[W_COUNT] = {};
   int slots[W_COUNT] = {};
@@ -460,6 +461,8 @@ Layout make_layout(const pfk_operator_s* A, const pfk_precond_s* B, int method, 
   off = align_up(off + sizeof(double) * (size_t)(maxit + 2));
   L.nhist = off;
   off = align_up(off + sizeof(double) * (size_t)(maxit + 2));
+  L.tstamp = off;
+  off = align_up(off + sizeof(unsigned long long) * (size_t)(maxit + 2));
   L.ld = (A->N + 31) / 32 * 32;
   const size_t vbytes = align_up(sizeof(double) * (size_t)L.ld);
   for (int v = 0; v < V_COUNT; ++v) {
@@ -517,6 +520,7 @@ struct pfk_session_s {
   SolveState* st = nullptr;
   double* hist = nullptr;
   double* nhist = nullptr;
+  unsigned long long* tstamp = nullptr;
   SolveState* host_state = nullptr;   // pinned
   int restarts = 0;
   bool owns_streams = true;           // false for members of a batch (the batch's streams)
@@ -1069,6 +1073,10 @@ static int session_make(pfk_operator A, pfk_precond B, pfk_method method, const 
     delete S;
     return fail(PFK_ERR_ARG, "norm must be 0 (2-norm) or 1 (natural)");
   }
+  if (S->opts.timestamps < 0 || S->opts.timestamps > 1) {
+    delete S;
+    return fail(PFK_ERR_ARG, "timestamps must be 0 or 1");
+  }
   if (S->opts.side_delay < 0 || S->opts.side_delay > 10000) {
     delete S;
     return fail(PFK_ERR_ARG, "side_delay must be 0..10000");
@@ -1103,6 +1111,7 @@ static int session_make(pfk_operator A, pfk_precond B, pfk_method method, const 
   S->st = (SolveState*)(S->ws + S->L.state);
   S->hist = (double*)(S->ws + S->L.hist);
   S->nhist = (double*)(S->ws + S->L.nhist);
+  S->tstamp = (unsigned long long*)(S->ws + S->L.tstamp);
   S->user = (hipStream_t)stream;
   if (bs1) {
     S->owns_streams = false;
@@ -1162,7 +1171,7 @@ static int session_setup(pfk_session_s* S) {
   const bool gm = S->method == PFK_FGMRES || S->method == PFK_PIPEFGMRES;
   const int nt = session_nt(S);
   LAUNCH(k_setup, 1, S->s1, S->st, 0.0, S->maxit, S->mmax, S->opts.truncation, S->opts.force_breakdown_at,
-         S->sigma, gm ? 0 : S->opts.norm, S->nhist, nt);
+         S->sigma, gm ? 0 : S->opts.norm, S->nhist, nt, S->opts.timestamps ? S->tstamp : nullptr);
   LAUNCH(k_dot, S->Pv(), S->s1, S->A->N, S->b, S->b, S->part(PT_A));
   LAUNCH(k_setup_tol, 1, S->s1, S->part(PT_A), S->Pv(), S->rtol, S->st, S->hist);
   LAUNCH(k_zero_if_done, S->Pv(), S->s1, S->A->N, S->x, S->st);
@@ -1209,6 +1218,19 @@ static int fill_info(pfk_session_s* S, int rc, pfk_solve_info* info) {
   info->true_rel_resid = bn > 0.0 ? h.true_res / bn : 0.0;
   info->history_len = 0;
   info->natural_len = 0;
+  info->iter_time_len = 0;
+  if (info->iter_time_us && info->history_cap > 0 && S->opts.timestamps) {
+    // device clock ticks -> microseconds from entry 0 (the clock's rate in kHz)
+    const int n = std::min(info->history_cap, h.hist_started ? h.it + 1 : 0);
+    int dev = 0, khz = 0;
+    std::vector<unsigned long long> t((size_t)std::max(n, 0));
+    if (n > 0 && hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0 &&
+        hipMemcpy(t.data(), S->tstamp, sizeof(unsigned long long) * n, hipMemcpyDeviceToHost) == hipSuccess) {
+      for (int i = 0; i < n; ++i) info->iter_time_us[i] = (double)(long long)(t[i] - t[0]) * 1e3 / khz;
+      info->iter_time_len = n;
+    }
+  }
   if (info->natural_history && info->history_cap > 0) {
     const int n = std::min(info->history_cap, h.nat_started ? h.it + 1 : 0);
     if (n > 0 && hipMemcpy(info->natural_history, S->nhist, sizeof(double) * n, hipMemcpyDeviceToHost) ==
@@ -1497,6 +1519,7 @@ extern "C" int pfk_operator_autotune(pfk_operator A, pfk_precond B, pfk_method m
   S->st = (SolveState*)(S->ws + S->L.state);
   S->hist = (double*)(S->ws + S->L.hist);
   S->nhist = (double*)(S->ws + S->L.nhist);
+  S->tstamp = (unsigned long long*)(S->ws + S->L.tstamp);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   double best = 0.0, dflt = 0.0;
   int count = 0;
@@ -2294,11 +2317,14 @@ extern "C" int pfk_server_result(pfk_server S, long long id, pfk_solve_info* inf
   if (info) {
     double* h = info->history;
     double* nh = info->natural_history;
+    double* tu = info->iter_time_us;
     const int cap = info->history_cap;
     *info = r.info;
     info->history = h;
     info->natural_history = nh;
     info->natural_len = 0;
+    info->iter_time_us = tu;
+    info->iter_time_len = 0;
     info->history_cap = cap;
     info->history_len = 0;
     if (h && cap > 0) {

@@ -23,7 +23,7 @@ struct Window {
 // Shared kernels
 // ---------------------------------------------------------------------------
 __global__ void k_setup(SolveState* st, double tol, int maxit, int nu_max, int trunc, int force_it,
-                        double sigma, int norm, double* nhist, int nt) {
+                        double sigma, int norm, double* nhist, int nt, unsigned long long* tstamp) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   st->nt = nt;
   st->status = kRunning;
@@ -49,6 +49,7 @@ __global__ void k_setup(SolveState* st, double tol, int maxit, int nu_max, int t
   st->rtol = 0.0;
   st->ntol = 0.0;
   st->nhist = nhist;
+  st->tstamp = tstamp;
 }
 
 // Natural norm sqrt|gamma| (section 5: the residual norm CG/CR types have
@@ -244,7 +245,7 @@ k_pipefcg_init_scalars(const double* part_r, int P_r, const double* part_ud, int
   const double delta = block_sum_column(part_ud, P_ud, 1);
   if (threadIdx.x != 0) return;
   const double res = sqrt(rr);
-  if (!st->hist_started) { hist[0] = res; st->hist_started = 1; }
+  if (!st->hist_started) { hist[0] = res; log_time(st, 0); st->hist_started = 1; }
   if (!isfinite(res)) { st->status = kNonfinite; return; }
   if (res <= st->tol) { st->status = kConverged; return; }
   natural_start(st, gamma);
@@ -430,6 +431,7 @@ __device__ __forceinline__ void pipefcg_scalars_body(Blk bk, const double* part,
   st->j = j1;
   const double res = sqrt(col[2]);
   hist[it] = res;
+  log_time(st, it);
   const double nat = natural_log(st, it, col[0]);
   if (!isfinite(res)) { st->status = kNonfinite; return; }
   if (converged_test(st, res, nat)) { st->status = kConverged; return; }
@@ -610,6 +612,7 @@ __device__ __forceinline__ void cg_scalars1_body(Blk bk, int init, const double*
   st->it = it;
   const double res = sqrt(col[2]);
   hist[it] = res;
+  log_time(st, it);
   const double nat = natural_log(st, it, col[0]);
   if (!isfinite(res)) { st->status = kNonfinite; return; }
   if (converged_test(st, res, nat)) { st->status = kConverged; return; }
@@ -763,7 +766,7 @@ k_init_test(const double* part, int P, SolveState* st, double* hist) {
   const double rr = block_sum_column(part, P, 0);
   if (threadIdx.x != 0) return;
   const double res = sqrt(rr);
-  if (!st->hist_started) { hist[0] = res; st->hist_started = 1; }
+  if (!st->hist_started) { hist[0] = res; log_time(st, 0); st->hist_started = 1; }
   if (!isfinite(res)) { st->status = kNonfinite; return; }
   if (res <= st->tol) st->status = kConverged;
   else if (st->it >= st->maxit) st->status = kMaxit;

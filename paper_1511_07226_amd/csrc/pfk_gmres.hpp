@@ -63,7 +63,7 @@ k_gm_cycle_start(const double* part, int P, SolveState* st, double* hist) {
   const double rr = block_sum_column(part, P, 0);
   if (threadIdx.x != 0) return;
   const double beta = sqrt(rr);
-  if (!st->hist_started) { hist[0] = beta; st->hist_started = 1; }
+  if (!st->hist_started) { hist[0] = beta; log_time(st, 0); st->hist_started = 1; }
   st->col = 0;
   st->pend = 0;
   st->ycols = 0;
@@ -201,6 +201,7 @@ k_fgm_column(const double* part, int P, SolveState* st, double* hist) {
   const int it = st->it + 1;
   st->it = it;
   hist[it] = res;
+  log_time(st, it);
   st->hn = hn;
   if (res <= st->tol || hn == 0.0) { gm_finish_cycle(st, c + 1); st->status = kConverged; return; }
   if (c + 1 == st->nu_max) { gm_finish_cycle(st, c + 1); st->status = kCycleEnd; return; }
@@ -271,6 +272,7 @@ __device__ __forceinline__ void pgm_scalars_body(Blk bk, const double* part, int
   const double res = gm_add_column(st, c, h, hn);
   st->it = nxt;
   hist[nxt] = res;
+  log_time(st, nxt);
   st->hn = hn;
   if (res <= st->tol || hn == 0.0) { gm_finish_cycle(st, c + 1); st->status = kConverged; return; }
   if (c + 1 == st->nu_max) { gm_finish_cycle(st, c + 1); st->status = kCycleEnd; return; }

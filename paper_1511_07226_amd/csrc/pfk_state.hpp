@@ -62,6 +62,7 @@ struct SolveState {
   double rtol;
   double ntol;       // rtol * natural norm of the first start-up
   double* nhist;     // natural-norm history (device), or null
+  unsigned long long* tstamp;   // device clock per history entry, or null
   double eta_ring[kNuMax];   // eta of direction d at slot d mod nu_max
   double beta[kNuMax];       // beta of the current update, window order (oldest first)
   // GMRES family (restart length m <= kNuMax)
@@ -89,6 +90,11 @@ __host__ __device__ inline int trunc_nu(int rule, int j, int numax) {
     return m < j ? m : j;
   }
   return j < numax ? j : numax;
+}
+
+// The device's constant-rate wall clock at history entry i (opts.timestamps).
+__device__ __forceinline__ void log_time(SolveState* st, int i) {
+  if (st->tstamp) st->tstamp[i] = wall_clock64();
 }
 
 __device__ __forceinline__ int read_status(const SolveState* st) {

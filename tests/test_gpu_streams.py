@@ -89,3 +89,35 @@ def test_side_delay_range_is_checked(pfk):
         with pytest.raises(pfk.PfkError):
             pfk.solve(A, B, "pipefcg", _dev(p.b), _dev(np.zeros(A.N)), rtol=1e-8, maxit=5, mmax=4,
                       side_delay=bad)
+
+
+@pytest.mark.parametrize("method", ["pipefcg", "fcg", "pipefgmres"])
+def test_device_timestamps(pfk, method):
+    # opts.timestamps: the device clock at every history entry, in us from
+    # entry 0; non-decreasing, one per entry, spanning about the solve's time
+    # (here stretched by the side-stream delay for the pipelined methods)
+    _say("timestamps", method)
+    p = gen.make_problem(3, 14, 4, 2.0, seed=12, convection=method == "pipefgmres")
+    A = pfk.Operator(3, 14, p.eta, p.vel)
+    B = pfk.Precond(A, "jacobi_gmres" if method == "pipefgmres" else "jacobi_pcg", 3)
+    extra = {"shift_sigma": float(pfk.estimate_sigma(A, B))} if method == "pipefgmres" else {}
+    x = _dev(np.zeros(A.N))
+    b = _dev(p.b)
+    off = pfk.solve(A, B, method, b, x, rtol=0.0, maxit=20, mmax=10, **extra)
+    assert off.iter_time_us.size == 0
+    x = _dev(np.zeros(A.N))
+    delay = 0 if method == "fcg" else 100
+    t0 = time.perf_counter()
+    info = pfk.solve(A, B, method, b, x, rtol=0.0, maxit=20, mmax=10, timestamps=1, side_delay=delay, **extra)
+    wall_us = (time.perf_counter() - t0) * 1e6
+    ts = info.iter_time_us
+    print(f"  {len(ts)} stamps, last {ts[-1]:.0f} us, host wall {wall_us:.0f} us")
+    assert len(ts) == len(info.history) == 21
+    assert ts[0] == 0.0 and np.all(np.diff(ts) >= 0.0)
+    assert ts[-1] <= wall_us
+    if delay:
+        # 20 iterations, each holding back the reduction finish by >= 100 us
+        assert ts[-1] >= 20 * 100 * 1.0
+    assert np.array_equal(info.history, off.history)
+    with pytest.raises(pfk.PfkError):
+        pfk.solve(A, B, method, b, x, rtol=0.0, maxit=5, mmax=10, timestamps=2, **extra)
