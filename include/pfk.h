@@ -374,7 +374,7 @@ void pfk_server_destroy(pfk_server S);
 int pfk_server_submit(pfk_server S, pfk_operator A, pfk_precond B, pfk_method method, const double* b,
                       double* x, double rtol, int maxit, long long* id);
 /* One scheduling round (admit, advance every batch by step_iters iterations,
- * poll, retire); the ids that completed in this round go to
+ * poll, retire); the ids that completed in this call go to
  * completed[0..cap) (*ncompleted of them).  Synchronises the batch streams. */
 int pfk_server_progress(pfk_server S, long long* completed, int cap, int* ncompleted);
 /* Info of a completed request (history copied into info->history up to
