@@ -373,7 +373,7 @@ void pfk_server_destroy(pfk_server S);
  * (method or preconditioner not batched, a request larger than the budget). */
 int pfk_server_submit(pfk_server S, pfk_operator A, pfk_precond B, pfk_method method, const double* b,
                       double* x, double rtol, int maxit, long long* id);
-/* One scheduling round (admit, advance every batch by step_iters iterations,
+/* One scheduling pass (admit, advance every batch by step_iters iterations,
  * poll, retire); the ids that completed in this call go to
  * completed[0..cap) (*ncompleted of them).  Synchronises the batch streams. */
 int pfk_server_progress(pfk_server S, long long* completed, int cap, int* ncompleted);
