@@ -500,12 +500,19 @@ def _gcr_cycle(Aop, B, b, x, st, tol, nu_max, trunc):
             del P[0], S[0], ETA[0]
 
 
-def _pipegcr_cycle(Aop, B, b, x, st, tol, nu_max, trunc, recur_w=False):
+def _pipegcr_cycle(Aop, B, b, x, st, tol, nu_max, trunc, recur_w=False, naive=False):
     """PIPEGCR (Alg. 11); with ``recur_w`` PIPEGCR_w (Alg. 12).
 
     Initialisation reads gamma_0 = <r_0, s_0>, eta_0 = <s_0, s_0>, q_0 = B(s_0)
     (and z_0 = A q_0, w_0 = s_0 for the recurred-w variant); the tilde-u of
     the listing is the recurred u throughout.
+
+    ``naive`` replaces the stabilised m_i = u_i + B(w_i - r_i) of section
+    2.2.2 by m_i = B(w_i), the CR counterpart of the naive pipelining that
+    Alg. 7 shows for FCG (identical for linear B).  It exists so a test can
+    show that the stabilised form is the one written here: with a noisy B
+    the naive cycle stalls near the noise level while PIPEGCR converges.
+    Pinned by that contrast (tests/test_oracle_krylov.py).
     """
     r, done = _start(Aop, b, x, st, tol)
     if done:
@@ -545,7 +552,7 @@ def _pipegcr_cycle(Aop, B, b, x, st, tol, nu_max, trunc, recur_w=False):
         st.log_natural(gamma)
         if st.converged(tol):
             return "converged"
-        m = u + B(w - r)
+        m = B(w) if naive else u + B(w - r)
         nn = Aop(m) if recur_w else None
         beta = {k: -dks[k] / ETA[k] for k in win}
         p, s, q = u.copy(), w.copy(), m.copy()
@@ -573,6 +580,14 @@ def _pipegcr_cycle(Aop, B, b, x, st, tol, nu_max, trunc, recur_w=False):
 
 def _pipegcr_w_cycle(*a, **k):
     return _pipegcr_cycle(*a, recur_w=True, **k)
+
+
+def _naive_pipegcr_cycle(*a, **k):
+    return _pipegcr_cycle(*a, naive=True, **k)
+
+
+def _naive_pipegcr_w_cycle(*a, **k):
+    return _pipegcr_cycle(*a, recur_w=True, naive=True, **k)
 
 
 # ---------------------------------------------------------------------------
@@ -696,8 +711,14 @@ def estimate_sigma(Aop, B, N: int, its: int = 10) -> float:
 
     The paper sets sigma to a constant approximating the largest eigenvalue
     of the (right-)preconditioned operator (sections 4.4 and 5); the start
-    vector is the normalised all-ones vector.  Parity unpinned as an
-    estimate; the parity tests pass sigma explicitly.
+    vector is the normalised all-ones vector.  The parity tests of the
+    methods pass sigma explicitly.
+
+    Pins (tests/test_oracle_krylov.py): for diagonal A and B the estimate is
+    the closed form sum(mu^(2k-1)) / sum(mu^(2k-2)) over the eigenvalues mu
+    of A B (k = its, equal start weights), it approaches max(mu) within the
+    power-iteration bound, and on a small stencil operator with Jacobi B it
+    converges to the largest eigenvalue of A D^-1 from a dense solver.
     """
     v = np.ones(N) / math.sqrt(N)
     lam = 0.0
@@ -719,6 +740,8 @@ METHODS = {
     "gcr": _gcr_cycle,
     "pipegcr": _pipegcr_cycle,
     "pipegcr_w": _pipegcr_w_cycle,
+    "pipegcr_naive": _naive_pipegcr_cycle,
+    "pipegcr_w_naive": _naive_pipegcr_w_cycle,
     "fgmres": _fgmres_cycle,
     "pipefgmres": _pipefgmres_cycle,
 }

@@ -264,3 +264,106 @@ def test_natural_norm_stopping(method):
     two = solve(method, A, B, b, rtol=rtol, maxit=200, nu_max=30)
     n = len(two.natural)
     assert n >= two.iterations and np.array_equal(two.natural, nat[:n])
+
+
+# ---------------------------------------------------------------------------
+# PIPEGCR's stabilised m_i = u_i + B(w_i - r_i) (section 2.2.2, Alg. 11/12)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("nu_max", [100, 30])
+def test_pipegcr_stabilised_m_with_noisy_pc(nu_max):
+    """With B(r) = r + noise (the section 2.2.1 toy), GCR and both PIPEGCR
+    forms converge while the same cycle with m_i = B(w_i) stalls near the
+    noise level.  For linear B the two m agree exactly, so only a nonlinear B
+    shows which one the oracle computes."""
+    g = json.load(open(os.path.join(GOLDEN, "fig1_toy.json")))
+    lam, b = gen.toy_diagonal(g["problem"]["n"], g["problem"]["condition_number"])
+    xs = b / lam
+    lo, hi = g["plateau_band"]
+    for eta in g["noise_levels"]:
+        err = {}
+        for m in ("gcr", "pipegcr", "pipegcr_w", "pipegcr_naive", "pipegcr_w_naive"):
+            B = noisy_pc(eta, np.random.default_rng(1))
+            r = solve(m, lambda v: lam * v, B, b, rtol=1e-15, maxit=g["check_at_iteration"], nu_max=nu_max)
+            err[m] = np.linalg.norm(r.x - xs) / np.linalg.norm(xs)
+        for m in ("pipegcr_naive", "pipegcr_w_naive"):
+            assert lo * eta <= err[m] <= hi * eta, (eta, err)
+        for m in ("gcr", "pipegcr", "pipegcr_w"):
+            assert err[m] < g["converged_error_below"], (eta, err)
+
+
+def test_pipegcr_stabilised_m_on_a_stencil_with_counter_noise():
+    """The same contrast on the unit-scaled 3D Laplacian of the study at scale,
+    with the seeded counter-based noise the GPU path also draws."""
+    from oracle import CounterNoisyPC
+    p = gen.study_problem(3, 10, seed=0)
+    A = StencilOperator(3, 10, p.eta, None)
+    xs = p.meta["x_star"]
+    b = A.apply(xs)
+    eta = 1e-2
+    err = {}
+    for m in ("gcr", "pipegcr", "pipegcr_naive"):
+        r = solve(m, A, CounterNoisyPC(eta, 3), b, rtol=1e-12, maxit=150, nu_max=30)
+        err[m] = np.linalg.norm(r.x - xs) / np.linalg.norm(xs)
+    assert err["gcr"] < 1e-9 and err["pipegcr"] < 1e-9, err
+    assert 0.3 * eta <= err["pipegcr_naive"] <= 10 * eta, err
+
+
+def test_naive_and_stabilised_pipegcr_agree_for_linear_pc():
+    A, b = _tiny(3, 5, 1.0, seed=7, conv=True)
+    B = jacobi_pc(1.0 / A.diagonal())
+    for stab, naive in (("pipegcr", "pipegcr_naive"), ("pipegcr_w", "pipegcr_w_naive")):
+        h0 = solve(stab, A, B, b, rtol=1e-14, maxit=10, nu_max=30).history
+        h1 = solve(naive, A, B, b, rtol=1e-14, maxit=10, nu_max=30).history
+        assert np.allclose(h0, h1, rtol=1e-8)
+
+
+# ---------------------------------------------------------------------------
+# PIPEFGMRES shift sigma (sections 4.4 and 5): power-iteration estimate
+# ---------------------------------------------------------------------------
+def _closed_form_rayleigh(mu, its):
+    """Rayleigh quotient after ``its`` power steps on diag(mu) from equal weights:
+    v_{its-1} is proportional to mu^(its-1), so R = sum mu^(2 its-1) / sum mu^(2 its-2)."""
+    mu = np.asarray(mu, dtype=np.float64)
+    s = mu / mu.max()                                    # scaled powers (no overflow)
+    return mu.max() * np.sum(s ** (2 * its - 1)) / np.sum(s ** (2 * its - 2))
+
+
+@pytest.mark.parametrize("its", [1, 2, 10, 25])
+def test_estimate_sigma_closed_form_for_diagonal_operators(its):
+    from oracle import estimate_sigma
+    rng = np.random.default_rng(3)
+    lam = np.linspace(1.0, 9.0, 40)
+    d = rng.uniform(0.2, 1.5, 40)                        # B = diag(d): A B != A in order and scale
+    mu = lam * d
+    est = estimate_sigma(lambda v: lam * v, lambda v: d * v, 40, its=its)
+    assert est == pytest.approx(_closed_form_rayleigh(mu, its), rel=1e-12)
+    # the operator order matters: A alone (no B) gives another value
+    assert abs(_closed_form_rayleigh(lam, its) - est) > 1e-3 * est
+
+
+def test_estimate_sigma_power_iteration_bound():
+    """max(mu) - R_k <= (max - min) tan^2(theta_0) (mu_2/mu_1)^(2k-2) for a symmetric
+    A B with a simple top eigenvalue, equal start weights (tan^2 theta_0 = N - 1)."""
+    from oracle import estimate_sigma
+    mu = np.concatenate([np.linspace(0.5, 3.0, 31), [6.0]])
+    N = mu.size
+    for its in (5, 10, 20):
+        est = estimate_sigma(lambda v: mu * v, lambda v: v.copy(), N, its=its)
+        gap = (mu.max() - mu.min()) * (N - 1) * (3.0 / 6.0) ** (2 * its - 2)
+        assert est <= mu.max() * (1 + 1e-15)
+        assert mu.max() - est <= gap, (its, est)
+    assert estimate_sigma(lambda v: mu * v, lambda v: v.copy(), N, its=60) == pytest.approx(6.0, rel=1e-12)
+
+
+def test_estimate_sigma_reaches_largest_eigenvalue_of_jacobi_preconditioned_stencil():
+    from oracle import estimate_sigma
+    A, _ = _tiny(2, 4, 2.0, seed=1)
+    Dinv = 1.0 / A.diagonal()
+    ev = np.linalg.eigvals(_dense(A) * Dinv[None, :])    # A D^-1: the right-preconditioned operator
+    top = float(np.max(ev.real))
+    est = estimate_sigma(A.apply, jacobi_pc(Dinv), A.N, its=400)
+    assert est == pytest.approx(top, rel=1e-8)
+    # with B = I the same routine finds the top of A's own spectrum instead
+    est_a = estimate_sigma(A.apply, lambda v: v.copy(), A.N, its=400)
+    assert est_a == pytest.approx(float(np.max(np.linalg.eigvalsh(_dense(A)))), rel=1e-8)
+    assert abs(est_a - top) > 1e-2 * top
