@@ -317,8 +317,9 @@ def batched_bench(pfk, torch, steps, warmup, count=64):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     its = [i.iterations for i in infos]
-    out["time_to_solution"] = {"seconds": round(dt, 3), "solves_per_s": round(count / dt, 2),
-                               "converged": sum(1 for i in infos if i.converged),
+    nconv = sum(1 for i in infos if i.converged)
+    out["time_to_solution"] = {"seconds": round(dt, 3), "converged_solves_per_s": round(nconv / dt, 2),
+                               "converged": nconv,
                                "iterations_min_median_max": [min(its), sorted(its)[len(its) // 2], max(its)],
                                "max_true_rel_resid": max(i.true_rel_resid for i in infos)}
     return out
@@ -383,7 +384,8 @@ def serving_bench(pfk, torch, nreq=160, seed=0, loads=(0.25, 0.5, 0.75, 0.9, 1.1
         total = time.perf_counter() - t0
         srv.close()
         lat = np.sort(np.array(lat))
-        return {"requests": len(reqs), "seconds": round(total, 3), "solves_per_s": round(len(reqs) / total, 2),
+        return {"requests": len(reqs), "seconds": round(total, 3),
+                "converged_solves_per_s": round(conv / total, 2), "served_per_s": round(len(reqs) / total, 2),
                 "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
                 "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2), "converged": conv,
                 "served_converged_by_kind": by_method, "not_converged_sample": failed}
@@ -395,7 +397,7 @@ def serving_bench(pfk, torch, nreq=160, seed=0, loads=(0.25, 0.5, 0.75, 0.9, 1.1
                        "budget 48 GiB, 64 per batch",
            "edge_median": int(np.median([r["n"] for r in reqs])), "burst": cap, "poisson": {}}
     for f in loads:
-        rate = f * cap["solves_per_s"]
+        rate = f * cap["converged_solves_per_s"]
         arr = np.cumsum(np.random.default_rng(seed + 1).exponential(1.0 / rate, size=nreq))
         log(f"serving: Poisson arrivals at {rate:.1f}/s ({f} x capacity)")
         out["poisson"][f"{f}x"] = {"offered_per_s": round(rate, 2), **run(arr)}
@@ -472,26 +474,65 @@ def stagnation_study(pfk, torch):
     return out
 
 
-def cpu_baseline(prob, method):
-    """The FP64 oracle on the host: one outer iteration of the same workload,
-    timed as (start-up + 1 iteration) minus (start-up alone), one thread."""
+def cpu_baseline(method, n=96, steady=6):
+    """The FP64 oracle on the host, at steady state: the same recipe as the
+    256^3 workload (20 spheres, eta 1e4/1, nu_max 30, global 5-step
+    Jacobi-PCG) at n = 96, which the oracle fills and times in about half a
+    minute (at 128^3 a steady oracle iteration takes about 2 s and the fill
+    alone over a minute).  One solve runs nu_max + 1 + 2 steady iterations; each iteration
+    applies B once, so the times between successive B calls are outer
+    iterations.  Iterations [nu, nu + steady) run on one thread, the next
+    `steady` on every host core (threadpoolctl; numpy's elementwise and
+    slicing work stays on one core either way, only its BLAS dots spread).
+    The rate is reported per n^3 iteration and scaled by n^3 / 256^3 to the
+    256^3 unit (every step of an iteration is linear in N)."""
     import oracle
+    import gen
     from threadpoolctl import threadpool_limits
-    A = oracle.StencilOperator(prob.dim, prob.n, prob.eta)
-    with threadpool_limits(1):
-        B = oracle.make_pc("jacobi_pcg", A, INNER)
-        t = time.perf_counter()
-        oracle.solve(method, A, B, prob.b, rtol=0.0, maxit=0, nu_max=NU)
-        t_start = time.perf_counter() - t
-        t = time.perf_counter()
-        oracle.solve(method, A, B, prob.b, rtol=0.0, maxit=1, nu_max=NU)
-        t_one = time.perf_counter() - t
-    per_it = max(t_one - t_start, 1e-9)
-    gbps = iteration_bytes(method, NU, INNER, prob.N) / per_it / 1e9
-    return {"value": 1.0 / per_it, "unit": "outer_iters/s", "cores": 1, "kind": "oracle",
-            "algorithmic_GBps": round(gbps, 3),
-            "sample": f"256^3 {method.upper()} workload: start-up + 1 outer iteration ({t_one:.1f} s) minus "
-                      f"start-up alone ({t_start:.1f} s), numpy FP64, 1 thread"}
+    p = gen.config_problem("cfgM", seed=0, n=n)
+    A = oracle.StencilOperator(p.dim, p.n, p.eta)
+    Bpc = oracle.make_pc("jacobi_pcg", A, INNER)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    # B call c belongs to iteration c - 1 for PIPEFCG (its start-up applies B
+    # twice) and to iteration c for FCG: start timing at iteration nu + 1
+    first = NU + 2 if method == "pipefcg" else NU + 1
+    stamps = []
+    lim = {}
+
+    def B(v):
+        c = len(stamps)
+        if c == first:
+            lim["one"] = threadpool_limits(1)
+        elif c == first + steady:
+            lim["one"].restore_original_limits()
+            lim["all"] = threadpool_limits(cores)
+        stamps.append(time.perf_counter())
+        return Bpc(v)
+
+    t0 = time.perf_counter()
+    oracle.solve(method, A, B, p.b, rtol=0.0, maxit=NU + 1 + 2 * steady, nu_max=NU)
+    total = time.perf_counter() - t0
+    if "all" in lim:
+        lim["all"].restore_original_limits()
+    st = np.array(stamps)
+    one = float(np.mean(np.diff(st[first:first + steady + 1])))
+    allc = float(np.mean(np.diff(st[first + steady:first + 2 * steady + 1])))
+    best, best_cores = (allc, cores) if allc < one else (one, 1)
+    N = p.N
+    scale = N / float(256 ** 3)
+    nbytes = iteration_bytes(method, NU, INNER, N)
+    return {"value": round(scale / best, 5), "unit": "outer_iters/s", "cores": best_cores, "kind": "oracle",
+            "sample": f"{method.upper()} steady-state iterations {NU + 1}..{NU + steady} (1 thread) and "
+                      f"{NU + steady + 1}..{NU + 2 * steady} ({cores} threads) of the same recipe at {n}^3, "
+                      f"numpy FP64, {total:.0f} s in all; value = the faster {n}^3 rate x {scale:g} (256^3 unit)",
+            f"it_per_s_{n}cube": {"1_thread": round(1.0 / one, 4), f"{cores}_threads": round(1.0 / allc, 4)},
+            "algorithmic_GBps": {"1_thread": round(nbytes / one / 1e9, 3),
+                                 f"{cores}_threads": round(nbytes / allc / 1e9, 3)},
+            "host": {"nproc": cores, "os_cpu_count": os.cpu_count(),
+                     "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}}
 
 
 def _short_kernel_name(name: str) -> str:
@@ -587,6 +628,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--method", default="pipefcg", choices=["pipefcg", "fcg"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--detail-out", default=os.path.join("gpurun_out", "bench_detail.json"),
+                    help="file for the full record (empty: stderr only)")
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the FP64 PIPEFCG/FCG pair (for profiler runs)")
     ap.add_argument("--profile-iters", type=int, default=10)
@@ -743,8 +786,16 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle, 1 thread; about a minute)")
-        cpu = cpu_baseline(prob, main_m)
+        log("cpu baseline (oracle at 96^3, steady state, 1 thread then all host threads; about 30 s)")
+        cpu = cpu_baseline(main_m)
+        # the GPU at the oracle's sample size, same recipe and launch defaults
+        pc = gen.config_problem("cfgM", seed=0, n=96)
+        Ac = pfk.Operator(pc.dim, pc.n, pc.eta)
+        Sx, dt = time_steps(pfk, torch, Ac, pfk.Precond(Ac, "jacobi_pcg", INNER), main_m,
+                            torch.as_tensor(pc.b).cuda(), args.steps, args.warmup)
+        Sx.close()
+        cpu["gpu_it_per_s_96cube"] = round(args.steps / dt, 1)
+        del pc, Ac
 
     value = results[main_m]["it_per_s"]
     out = {
@@ -779,7 +830,75 @@ def main():
         },
         "kernels": kernels,
     }
-    print(json.dumps(out), flush=True)
+    # everything goes to the detail record (a file and one stderr line); stdout
+    # ends with the compact headline line
+    detail = json.dumps(out)
+    path = args.detail_out
+    if path:
+        os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+        with open(path, "w") as f:
+            f.write(detail + "\n")
+        log(f"detail record written to {path}")
+    print("[bench] detail " + detail, file=sys.stderr, flush=True)
+    head = {k: out[k] for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                                "higher_is_better", "scaling", "vs_baseline", "dtype", "data")}
+    head["config"] = {k: out["config"][k] for k in ("workload", "unknowns", "method", "nu_max", "inner_its")}
+    head["roofline"] = out["roofline"]
+    head["cpu_baseline"] = compact_cpu(cpu)
+    head["compare"] = compact_compare(out["compare"], other)
+    print(json.dumps(head, separators=(",", ":")), flush=True)
+
+
+def compact_cpu(cpu):
+    if cpu is None:
+        return None
+    keep = ("value", "unit", "cores", "kind", "sample", "gpu_it_per_s_96cube")
+    c = {k: cpu[k] for k in keep if k in cpu}
+    c["it_per_s_96cube"] = next((v for k, v in cpu.items() if k.startswith("it_per_s_")), None)
+    c["nproc"] = cpu.get("host", {}).get("nproc")
+    return c
+
+
+def compact_compare(cmp, other):
+    """The headline comparisons in a few hundred bytes: rates, ratios,
+    convergence counts and latencies (the full record is the detail line)."""
+    def rate(d):
+        return d.get("it_per_s") if isinstance(d, dict) else None
+
+    c = {f"{other}_it_per_s": rate(cmp[other]), "pipelined_over_unpipelined": cmp["pipelined_over_unpipelined"],
+         "GBps_whole_iteration": cmp["algorithmic_GBps_whole_iteration"]}
+    for k in ("fcg_host_sync", "pipefcg_mixed", "fcg_mixed", "pipefcg_block", "fcg_block",
+              "pipefcg_block_mixed", "fcg_block_mixed"):
+        if k in cmp:
+            c[k] = rate(cmp[k])
+    cd = cmp.get("conv_diff_256")
+    if cd:
+        c["conv_diff_256_it_per_s"] = {m: rate(cd[m]) for m in ("pipefgmres", "fgmres", "pipegcr", "pipegcr_w", "gcr")
+                                       if m in cd}
+    tts = cmp.get("time_to_solution_rtol1e-8")
+    if tts:
+        c["tts_128_s_its"] = {k: [v["seconds"], v["iterations"], int(v["converged"])] for k, v in tts.items()
+                              if isinstance(v, dict)}
+    bt = cmp.get("batched_64")
+    if bt:
+        t = bt.get("time_to_solution", {})
+        c["batched_64"] = {"pipefcg_batch_it_per_s": bt.get("pipefcg_batch_iters_per_s"),
+                           "fcg_batch_it_per_s": bt.get("fcg_batch_iters_per_s"),
+                           "speedup_vs_one_at_a_time": bt.get("batching_speedup"),
+                           "solve_s": t.get("seconds"), "converged": t.get("converged"),
+                           "max_true_rel": t.get("max_true_rel_resid")}
+    sv = cmp.get("serving")
+    if sv:
+        row = {"capacity": {k: sv["burst"][k] for k in ("converged_solves_per_s", "p50_ms", "p99_ms", "converged",
+                                                        "requests")}}
+        for f, r in sv.get("poisson", {}).items():
+            row[f] = {k: r[k] for k in ("converged_solves_per_s", "p50_ms", "p99_ms", "converged")}
+        c["serving"] = row
+    sw = cmp.get("size_sweep_it_per_s")
+    if sw:
+        c["size_sweep_pipe_over_unpipe"] = {k: [v["pipelined_over_unpipelined"],
+                                                v["pipelined_over_unpipelined_persistent"]] for k, v in sw.items()}
+    return c
 
 
 if __name__ == "__main__":

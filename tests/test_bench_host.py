@@ -66,3 +66,27 @@ def test_pmc_summary_means(tmp_path):
     out = bench.pmc_summary(str(p))
     line = next(l for l in out.splitlines() if l.startswith("k_pipefcg_update"))
     assert line.split()[-2:] == ["2", "200.0"]
+
+
+def test_cpu_baseline_steady_state_sample():
+    # the oracle timing reaches the full window before it times, and reports
+    # per-thread-count rates scaled to the 256^3 unit
+    r = bench.cpu_baseline("pipefcg", n=16, steady=2)
+    assert r["kind"] == "oracle" and r["unit"] == "outer_iters/s"
+    assert r["cores"] >= 1 and r["host"]["nproc"] >= 1
+    rates = r["it_per_s_16cube"]
+    assert len(rates) == 2 and all(v > 0 for v in rates.values())
+    assert r["value"] == pytest.approx(max(rates.values()) * 16 ** 3 / 256 ** 3, rel=1e-3)
+    assert "31..32" in r["sample"]
+
+
+def test_compact_line_is_short():
+    cmp = {"fcg": {"it_per_s": 300.0}, "pipelined_over_unpipelined": 0.64,
+           "algorithmic_GBps_whole_iteration": {"pipefcg": 5000.0, "fcg": 5400.0},
+           "serving": {"burst": {"converged_solves_per_s": 25.0, "p50_ms": 1.0, "p99_ms": 2.0, "converged": 10,
+                                 "requests": 10, "not_converged_sample": [{"n": 1}] * 50},
+                       "poisson": {"0.5x": {"converged_solves_per_s": 12.0, "p50_ms": 1.0, "p99_ms": 3.0,
+                                            "converged": 10, "not_converged_sample": [{"n": 1}] * 50}}}}
+    c = bench.compact_compare(cmp, "fcg")
+    assert "not_converged_sample" not in str(c)
+    assert c["serving"]["0.5x"]["converged_solves_per_s"] == 12.0
