@@ -25,7 +25,12 @@ and the listings omit.  Conventions shared with the GPU path:
   it only after their 2-norm test, so the iteration that converges in the
   2-norm has none).  With ``norm="natural"`` the test is
   natural[i] <= rtol*natural[0], B is applied before the test, and the
-  converged iterate is accepted without the 2-norm true-residual check.
+  converged iterate is confirmed in the same norm of the true residual,
+  sqrt|<B(r), r>| (CG) or sqrt|<r, A B(r)>| (CR) with r = b - A x, one more
+  application of B ("other norms ... should be used to assess convergence",
+  section 5); above the tolerance it is a gap restart.  If the first
+  start-up already meets the 2-norm tolerance no natural tolerance exists
+  and the 2-norm check decides.
   GMRES types have no natural norm and always test |g_i| (PCG, kept as
   FCG's pin, tests the 2-norm only).
 * Window: the last nu_i directions, nu_i from ``truncation_nu`` with j the
@@ -244,10 +249,15 @@ def solve(method: str, A, B, b, x0=None, rtol=1e-8, maxit=500, nu_max=30,
     st = _State(maxit, force_breakdown_at, record, "2" if no_natural else norm, rtol)
     restarts = 0
     status = "maxit"
+    cr = method in _CR_TYPES
     while True:
         reason = cycle(Aop, B, b, x, st, tol, **kw)
         if reason == "converged":
-            if st.natural_test or _norm(b - Aop(x)) <= tol:
+            if st.natural_test and st.natural:
+                ok = _true_natural(Aop, B, b, x, cr) <= st.ntol
+            else:
+                ok = _norm(b - Aop(x)) <= tol
+            if ok:
                 status = "converged"
                 break
             reason = "gap"
@@ -269,6 +279,20 @@ def solve(method: str, A, B, b, x0=None, rtol=1e-8, maxit=500, nu_max=30,
     true_rel = _norm(b - Aop(x)) / bnorm
     return Result(x, st.history, st.it, restarts, status == "converged", status, true_rel, st.trace,
                   st.natural)
+
+
+_CR_TYPES = ("gcr", "pipegcr", "pipegcr_w", "pipegcr_naive", "pipegcr_w_naive")
+
+
+def _true_natural(Aop, B, b, x, cr):
+    """The natural norm of the true residual r = b - A x: sqrt|<B(r), r>| for
+    CG types, sqrt|<r, A B(r)>| for CR types (one more application of B).
+    Section 5 advises checking convergence in other norms as well; a
+    natural-norm test on the recurred quantities is confirmed with it."""
+    r = b - Aop(x)
+    u = B(r)
+    g = _dot(r, Aop(u)) if cr else _dot(u, r)
+    return math.sqrt(abs(g))
 
 
 def _start(Aop, b, x, st, tol):

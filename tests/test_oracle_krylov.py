@@ -258,8 +258,19 @@ def test_natural_norm_stopping(method):
     first = int(np.argmax(nat <= rtol * nat[0]))
     assert nat[first] <= rtol * nat[0] and first > 0
     res = solve(method, A, B, b, rtol=rtol, maxit=200, nu_max=30, norm="natural")
-    assert res.converged and res.iterations == first
-    assert np.array_equal(res.natural, nat[:first + 1])
+    assert res.converged
+    # the accepted iterate meets the tolerance in the natural norm of its true residual
+    r = b - A.apply(res.x)
+    g = r @ A.apply(B(r)) if conv else B(r) @ r
+    assert math.sqrt(abs(g)) <= rtol * nat[0]
+    if res.restarts == 0:
+        # it stopped at the first recurred crossing
+        assert res.iterations == first
+        assert np.array_equal(res.natural, nat[:first + 1])
+    else:
+        # that iterate failed the true-residual check: a gap restart, then a later stop
+        assert res.iterations > first
+        assert np.array_equal(res.natural[:first + 1], nat[:first + 1])
     # the 2-norm mode logs the same natural norms (FCG/GCR up to the converging iteration)
     two = solve(method, A, B, b, rtol=rtol, maxit=200, nu_max=30)
     n = len(two.natural)
@@ -367,3 +378,21 @@ def test_estimate_sigma_reaches_largest_eigenvalue_of_jacobi_preconditioned_sten
     est_a = estimate_sigma(A.apply, lambda v: v.copy(), A.N, its=400)
     assert est_a == pytest.approx(float(np.max(np.linalg.eigvalsh(_dense(A)))), rel=1e-8)
     assert abs(est_a - top) > 1e-2 * top
+
+
+def test_natural_norm_check_rejects_a_stagnated_iterate():
+    """PIPEFCG with the global 2-step inner CG on config 1 stagnates in the true
+    residual while its recurred natural norm keeps falling (section 2.2.2: the
+    pipelined CG needs a faithful preconditioner).  The natural-norm test must
+    not accept such an iterate: every recurred crossing is checked against the
+    natural norm of the true residual, and fails, so the solve restarts and
+    ends unconverged."""
+    p = gen.config_problem("cfg1", seed=0)
+    A = StencilOperator(2, 64, p.eta)
+    B = make_pc("jacobi_pcg", A, 2)
+    r = solve("pipefcg", A, B, p.b, rtol=1e-6, maxit=300, nu_max=30, norm="natural", max_restarts=3)
+    assert not r.converged
+    assert r.restarts >= 1
+    rt = p.b - A.apply(r.x)
+    assert math.sqrt(abs(B(rt) @ rt)) > 1e-6 * r.natural[0]
+    assert r.true_rel_resid > 1e-3
