@@ -42,6 +42,7 @@ __all__ = [
     "batched_problems",
     "toy_diagonal",
     "study_problem",
+    "graded_problem",
     "CONFIGS",
 ]
 
@@ -267,3 +268,21 @@ def study_problem(dim: int, n: int, seed: int = 0) -> Problem:
     b = rhs(dim, n, g_rhs)
     x_star = g_geo.standard_normal(n ** dim)
     return Problem(dim, n, eta, b, None, dict(seed=seed, x_star=x_star, study=True))
+
+
+def graded_problem(dim: int, n: int, log10_range=(0.0, 4.0), seed: int = 0,
+                   convection: bool = False) -> Problem:
+    """System whose viscosity varies from node to node: log10(eta) drawn
+    U(lo, hi) independently at every padded node, f ~ N(0, 1).
+
+    The sinker fields take two values, so their reduced-precision copies are
+    checked at two numbers only; here almost every node's value sits between
+    two BF16 numbers, which makes a coefficient-rounding rule visible (the
+    sinker and this field exercise the same operator).
+    """
+    g_geo, g_rhs, g_vel = streams(seed)
+    lo, hi = log10_range
+    eta = 10.0 ** g_geo.uniform(lo, hi, size=(n + 2,) * dim)
+    b = rhs(dim, n, g_rhs)
+    vel = divfree_face_velocity(n, g_vel) if convection else None
+    return Problem(dim, n, eta, b, vel, dict(seed=seed, graded=tuple(log10_range), convection=convection))

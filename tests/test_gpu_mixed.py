@@ -108,10 +108,32 @@ def test_mixed_solves_reach_tolerance(pfk, method, kind, k, conv):
     print(f"  {method}: its {info.iterations} (FP64 oracle {ref.iterations}), true rel {true_rel:.2e}, "
           f"error vs FP64 solution {sol_err:.2e}")
     if method == "pipefcg":
-        # global inner CG: the pipelined CG variant stagnates in every precision (see the FP64 tests)
+        # global inner CG: the pipelined CG variant stagnates in every precision
+        # (test_mixed_pipefcg_global_pc_stagnates_like_rounded_oracle)
+        assert not info.converged
         return
     assert info.converged and true_rel <= 1e-8
     assert sol_err <= 1e-5
+
+
+def test_mixed_pipefcg_global_pc_stagnates_like_rounded_oracle(pfk):
+    # The mixed global 2-step inner CG is not a faithful preconditioner either:
+    # PIPEFCG plateaus.  The FP64 oracle whose inner solve runs on the
+    # BF16-rounded viscosity (outer operator exact) plateaus at the same level.
+    _say("mixed pipefcg plateau")
+    p = gen.make_problem(3, 20, 6, 3.0, seed=3)
+    Ao = oracle.StencilOperator(3, 20, p.eta)
+    Ar = oracle.StencilOperator(3, 20, bf16_round(p.eta))
+    ref = oracle.solve("pipefcg", Ao, oracle.make_pc("jacobi_pcg", Ar, 2), p.b, rtol=1e-8, maxit=300, nu_max=30)
+    Ag = pfk.Operator(3, 20, p.eta)
+    Bg = pfk.Precond(Ag, "jacobi_pcg", 2, precision=pfk.FP32_BF16COEF)
+    info = pfk.solve(Ag, Bg, "pipefcg", _dev(p.b), _dev(np.zeros(Ao.N)), rtol=1e-8, maxit=300, mmax=30)
+    h, hr = info.history, np.array(ref.history)
+    print(f"  plateau: GPU {h[-1] / h[0]:.2e}, rounded oracle {hr[-1] / hr[0]:.2e}")
+    assert not ref.converged and info.status == 1 and info.iterations == 300
+    assert np.abs(np.log10(h[-50:]) - np.log10(hr[-50:])).max() < 0.5
+    # early on, before the plateau, the two follow each other closely
+    assert np.abs(h[:11] - hr[:11]).max() <= 1e-4 * hr[0]
 
 
 @pytest.mark.parametrize("n", [21, 20], ids=["odd-N", "even-N"])
