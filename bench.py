@@ -474,12 +474,12 @@ def stagnation_study(pfk, torch):
     return out
 
 
-def cpu_baseline(method, n=96, steady=6):
+def cpu_baseline(method, n=128, steady=6):
     """The FP64 oracle on the host, at steady state: the same recipe as the
     256^3 workload (20 spheres, eta 1e4/1, nu_max 30, global 5-step
-    Jacobi-PCG) at n = 96, which the oracle fills and times in about half a
-    minute (at 128^3 a steady oracle iteration takes about 2 s and the fill
-    alone over a minute).  One solve runs nu_max + 1 + 2 steady iterations; each iteration
+    Jacobi-PCG) at n = 128 (config 2's size), which the oracle fills and times
+    in 20-100 s depending on the host (at 256^3 the fill alone would take
+    several minutes).  One solve runs nu_max + 1 + 2 steady iterations; each iteration
     applies B once, so the times between successive B calls are outer
     iterations.  Iterations [nu, nu + steady) run on one thread, the next
     `steady` on every host core (threadpoolctl; numpy's elementwise and
@@ -786,15 +786,15 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle at 96^3, steady state, 1 thread then all host threads; about 30 s)")
+        log("cpu baseline (oracle at 128^3, steady state, 1 thread then all host threads)")
         cpu = cpu_baseline(main_m)
         # the GPU at the oracle's sample size, same recipe and launch defaults
-        pc = gen.config_problem("cfgM", seed=0, n=96)
+        pc = gen.config_problem("cfgM", seed=0, n=128)
         Ac = pfk.Operator(pc.dim, pc.n, pc.eta)
         Sx, dt = time_steps(pfk, torch, Ac, pfk.Precond(Ac, "jacobi_pcg", INNER), main_m,
                             torch.as_tensor(pc.b).cuda(), args.steps, args.warmup)
         Sx.close()
-        cpu["gpu_it_per_s_96cube"] = round(args.steps / dt, 1)
+        cpu["gpu_it_per_s_128cube"] = round(args.steps / dt, 1)
         del pc, Ac
 
     value = results[main_m]["it_per_s"]
@@ -852,9 +852,9 @@ def main():
 def compact_cpu(cpu):
     if cpu is None:
         return None
-    keep = ("value", "unit", "cores", "kind", "sample", "gpu_it_per_s_96cube")
+    keep = ("value", "unit", "cores", "kind", "sample", "gpu_it_per_s_128cube")
     c = {k: cpu[k] for k in keep if k in cpu}
-    c["it_per_s_96cube"] = next((v for k, v in cpu.items() if k.startswith("it_per_s_")), None)
+    c["it_per_s_128cube"] = next((v for k, v in cpu.items() if k.startswith("it_per_s_")), None)
     c["nproc"] = cpu.get("host", {}).get("nproc")
     return c
 
@@ -877,8 +877,7 @@ def compact_compare(cmp, other):
                                        if m in cd}
     tts = cmp.get("time_to_solution_rtol1e-8")
     if tts:
-        c["tts_128_s_its"] = {k: [v["seconds"], v["iterations"], int(v["converged"])] for k, v in tts.items()
-                              if isinstance(v, dict)}
+        c["tts_128_s"] = {k: v["seconds"] for k, v in tts.items() if isinstance(v, dict)}
     bt = cmp.get("batched_64")
     if bt:
         t = bt.get("time_to_solution", {})
@@ -892,12 +891,11 @@ def compact_compare(cmp, other):
         row = {"capacity": {k: sv["burst"][k] for k in ("converged_solves_per_s", "p50_ms", "p99_ms", "converged",
                                                         "requests")}}
         for f, r in sv.get("poisson", {}).items():
-            row[f] = {k: r[k] for k in ("converged_solves_per_s", "p50_ms", "p99_ms", "converged")}
+            row[f] = [r[k] for k in ("converged_solves_per_s", "p50_ms", "p99_ms")]
         c["serving"] = row
     sw = cmp.get("size_sweep_it_per_s")
     if sw:
-        c["size_sweep_pipe_over_unpipe"] = {k: [v["pipelined_over_unpipelined"],
-                                                v["pipelined_over_unpipelined_persistent"]] for k, v in sw.items()}
+        c["size_sweep_pipe_over_unpipe"] = {k: v["pipelined_over_unpipelined"] for k, v in sw.items()}
     return c
 
 

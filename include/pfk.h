@@ -122,9 +122,12 @@ typedef struct {
                               that of the first start-up, gamma = <u, r> (CG types) or
                               <r, A u> (CR types), the one norm these methods have
                               without an extra reduction (section 5); the iterate is
-                              then accepted without the 2-norm check (true_rel_resid
-                              still reports it).  GMRES types ignore it (they test the
-                              Givens estimate of the preconditioned residual).       */
+                              then confirmed in the natural norm of its true residual
+                              r = b - A x, sqrt|<B(r), r>| (CG) or sqrt|<r, A B(r)>|
+                              (CR), one more application of B, and restarted from
+                              if above the tolerance (true_rel_resid reports the
+                              2-norm).  GMRES types ignore it (they test the Givens
+                              estimate of the preconditioned residual).              */
   int timestamps;          /* 1: record the device clock at every history entry (the
                               scalar kernel that logs it reads the GPU's constant-rate
                               wall clock); returned as iter_time_us (single solves,
@@ -299,7 +302,9 @@ const char* pfk_last_error(void);
  * Preconditioners: NONE, JACOBI, BLOCK_JACOBI_PCG; all members of a batch share
  * the dimension, the preconditioner kind and its precision.  opts as for
  * pfk_solve except host_sync (rejected); graph_iters iterations are captured
- * per graph (recaptured when the set of running members changes).
+ * per graph (recaptured when members are added or removed, or when members
+ * that ended hold half of the vector workgroups; until then an ended member's
+ * launches return at once, its status being final).
  * Ownership: b, x and the workspace (or the library's allocation when NULL)
  * must stay valid while the member is in the batch. */
 int pfk_batch_create(pfk_method method, int mmax, int capacity, void* stream, const pfk_solve_opts* opts,
@@ -348,15 +353,22 @@ int pfk_solve_batched(int count, const pfk_operator* A, const pfk_precond* B, pf
  * batch slot and the device-memory budget (each holds its workspace,
  * pfk_workspace_bytes, from admission to retirement; workspaces come from a
  * pool that keeps freed blocks).  Requests of one method, preconditioner kind,
- * precision and dimension share a batch; batches run on their own streams, so
- * a PIPEFCG batch and a PIPEFGMRES batch overlap on the device.  A request's
- * result is bit-identical to a single pfk_solve of it, whatever else is being
- * served. */
+ * precision and dimension share a batch; batches run on their own streams and
+ * are stepped without waiting for each other, so a PIPEFCG batch and a
+ * PIPEFGMRES batch overlap on the device.  A request's result is
+ * bit-identical to a single pfk_solve of it, whatever else is being served.
+ * Streams: admission orders a request's work after what the server's stream
+ * (the `stream` of pfk_server_create) holds at that moment; the server's
+ * stream is not made to wait for the batches -- a request's x is final when
+ * pfk_server_progress reports it (that call synchronises the batch streams). */
 typedef struct {
   size_t hbm_budget;   /* bytes of workspace the admitted requests may hold       */
   int max_active;      /* members per batch (1..4096)                             */
   int step_iters;      /* outer iterations per scheduling round (graph length)    */
   int mmax;            /* window / restart length of every request                */
+  int launch_direct;   /* 1: batches launch their kernels directly instead of
+                          replaying captured graphs (same results; for tools that
+                          trace individual launches); 0: graphs (default)        */
 } pfk_server_config;
 
 typedef struct {

@@ -57,7 +57,8 @@ class Tuning(C.Structure):
 
 
 class ServerConfig(C.Structure):
-    _fields_ = [("hbm_budget", C.c_size_t), ("max_active", C.c_int), ("step_iters", C.c_int), ("mmax", C.c_int)]
+    _fields_ = [("hbm_budget", C.c_size_t), ("max_active", C.c_int), ("step_iters", C.c_int), ("mmax", C.c_int),
+                ("launch_direct", C.c_int)]
 
 
 class ServerStatus(C.Structure):
@@ -493,8 +494,9 @@ class Server:
     """Request queue in front of continuously refilled batches:
     submit(), progress() -> completed ids, result(id), stats()."""
 
-    def __init__(self, hbm_budget: int, max_active: int = 64, step_iters: int = 10, mmax: int = 30, stream=None):
-        cfg = ServerConfig(int(hbm_budget), int(max_active), int(step_iters), int(mmax))
+    def __init__(self, hbm_budget: int, max_active: int = 64, step_iters: int = 10, mmax: int = 30, stream=None,
+                 launch_direct: bool = False):
+        cfg = ServerConfig(int(hbm_budget), int(max_active), int(step_iters), int(mmax), int(bool(launch_direct)))
         h = C.c_void_p()
         _check(lib().pfk_server_create(C.byref(cfg), _stream_ptr(stream), C.byref(h)))
         self._h = h

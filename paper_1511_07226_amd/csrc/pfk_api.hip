@@ -106,7 +106,7 @@ k_zero_if_done(long long N, double* __restrict__ x, const SolveState* st) {
 
 __global__ void __launch_bounds__(kBlock)
 k_pc_write(long long N, PcOutDesc pd, double* __restrict__ y, SolveState* st) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   const PcOut pc = make_pc_out(pd, &st->pc);
   for (long long e = gtid(); e < N; e += gstride()) y[e] = pc(e);
 }
@@ -948,10 +948,46 @@ void enqueue_iteration(pfk_session_s* S) {
   noise_end(S, s1);
 }
 
+// Whether the solve tests the natural norm (CG/CR types with opts.norm = 1).
+bool natural_mode(const pfk_session_s* S) {
+  const bool gm = S->method == PFK_FGMRES || S->method == PFK_PIPEFGMRES;
+  return S->opts.norm == 1 && !gm;
+}
+bool cr_type(int method) { return method == PFK_GCR || method == PFK_PIPEGCR || method == PFK_PIPEGCR_W; }
+
+// The verdict after a recurred convergence (status kConverged): r = b - A x,
+// then in the 2-norm mode ||r|| <= tol, in the natural-norm mode
+// sqrt|<B(r), r>| (CR types sqrt|<r, A B(r)>|) <= rtol times the natural norm
+// of the first start-up -- unless the first start-up met the 2-norm
+// tolerance before any natural norm existed, when the 2-norm decides.
 void enqueue_true_check(pfk_session_s* S, hipStream_t s) {
   LAUNCH(k_residual, S->Ps(), s, S->grid(), S->sg, S->b, (const double*)S->x, S->vec(V_R), S->part(PT_A),
          (double*)nullptr);
-  LAUNCH(k_true_check, 1, s, S->part(PT_A), S->Ps(), S->st);
+  if (!natural_mode(S)) {
+    LAUNCH(k_true_check, 1, s, S->part(PT_A), S->Ps(), (const double*)nullptr, 0, S->st);
+    return;
+  }
+  const long long N = S->A->N;
+  LAUNCH(k_check_open, 1, s, S->st);
+  noise_begin(S, s);
+  const PcOutDesc pd = enqueue_pc(S, s, S->vec(V_R), 1.0, nullptr, 0.0);
+  LAUNCH(k_pc_write, S->Pv(), s, N, pd, S->vec(V_U), S->st);
+  noise_end(S, s);
+  if (cr_type(S->method)) {
+    LAUNCH_OP(S->A, k_apply, S->Ps(), s, S->grid(), S->sg, (const double*)S->vec(V_U), S->vec(V_W),
+              (const SolveState*)S->st);
+    LAUNCH(k_dot, S->Pv(), s, N, (const double*)S->vec(V_R), (const double*)S->vec(V_W), S->part(PT_B));
+  } else {
+    LAUNCH(k_dot, S->Pv(), s, N, (const double*)S->vec(V_U), (const double*)S->vec(V_R), S->part(PT_B));
+  }
+  LAUNCH(k_true_check, 1, s, S->part(PT_A), S->Ps(), (const double*)S->part(PT_B), S->Pv(), S->st);
+}
+
+// ||b - A x|| at exit, for the report (status unchanged).
+void enqueue_true_residual(pfk_session_s* S, hipStream_t s) {
+  LAUNCH(k_residual, S->Ps(), s, S->grid(), S->sg, S->b, (const double*)S->x, S->vec(V_R), S->part(PT_A),
+         (double*)nullptr);
+  LAUNCH(k_true_report, 1, s, S->part(PT_A), S->Ps(), S->st);
 }
 
 // sigma of PIPEFGMRES: Rayleigh quotient of v -> A B(v) after `its` power steps
@@ -1305,7 +1341,7 @@ extern "C" int pfk_solve(pfk_operator A, pfk_precond B, pfk_method method, const
   }
   if (rc == PFK_OK) {
     // the true residual at exit (also after maxit)
-    if (!S->host_state->bzero) enqueue_true_check(S, S->s1);
+    if (!S->host_state->bzero) enqueue_true_residual(S, S->s1);
     rc = read_state(S);
   }
   if (rc == PFK_OK) {
@@ -1616,6 +1652,7 @@ struct pfk_batch_s {
   int* h_stat = nullptr;                  // pinned copy
   int cap_rows = 0;
   int tot[kBpCount] = {};
+  int stale = 0;                          // vector workgroups of table rows whose member ended
   bool dirty = true;
   hipGraphExec_t graph = nullptr;
   GridBarrier* bar = nullptr;             // persistent form: grid barrier state
@@ -1712,6 +1749,7 @@ int batch_rebuild(pfk_batch_s* T) {
     HIPCHK(hipMemcpy(T->d_sys, sys.data(), sizeof(BSys) * n, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(T->d_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice));
   }
+  T->stale = 0;
   T->dirty = false;
   return PFK_OK;
 }
@@ -1917,21 +1955,32 @@ extern "C" int pfk_batch_add(pfk_batch T, pfk_operator A, pfk_precond B, const d
   return PFK_OK;
 }
 
-extern "C" int pfk_batch_step(pfk_batch T, int iters) {
-  if (!T) return fail(PFK_ERR_ARG, "null batch");
+namespace {
+
+// `iters` iterations of every running member.  With `join` the batch stream
+// first waits for the caller's stream and the caller's stream then waits for
+// the batch (the ordering every stream-taking call of the ABI gives); the
+// server steps its batches without it, so batches of different methods run
+// side by side instead of each waiting for the previous one through the
+// caller's stream.
+int batch_step(pfk_batch_s* T, int iters, bool join) {
   if (iters <= 0) return PFK_OK;
   if (T->dirty) {
     int rc = batch_rebuild(T);
     if (rc) return rc;
   }
   if (T->rows.empty()) return PFK_OK;
-  HIPCHK(hipEventRecord(T->ev_user, T->user));
-  HIPCHK(hipStreamWaitEvent(T->s1, T->ev_user, 0));
+  if (join) {
+    HIPCHK(hipEventRecord(T->ev_user, T->user));
+    HIPCHK(hipStreamWaitEvent(T->s1, T->ev_user, 0));
+  }
   if (T->opts.persistent) {
     int rc = batch_persistent(T, iters);
     if (rc) return rc;
-    HIPCHK(hipEventRecord(T->ev_done, T->s1));
-    HIPCHK(hipStreamWaitEvent(T->user, T->ev_done, 0));
+    if (join) {
+      HIPCHK(hipEventRecord(T->ev_done, T->s1));
+      HIPCHK(hipStreamWaitEvent(T->user, T->ev_done, 0));
+    }
     return PFK_OK;
   }
   const int gi = T->opts.graph_iters;
@@ -1950,9 +1999,18 @@ extern "C" int pfk_batch_step(pfk_batch T, int iters) {
   }
   for (; done < iters; ++done) enqueue_batch_iteration(T);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipEventRecord(T->ev_done, T->s1));
-  HIPCHK(hipStreamWaitEvent(T->user, T->ev_done, 0));
+  if (join) {
+    HIPCHK(hipEventRecord(T->ev_done, T->s1));
+    HIPCHK(hipStreamWaitEvent(T->user, T->ev_done, 0));
+  }
   return PFK_OK;
+}
+
+}  // namespace
+
+extern "C" int pfk_batch_step(pfk_batch T, int iters) {
+  if (!T) return fail(PFK_ERR_ARG, "null batch");
+  return batch_step(T, iters, true);
 }
 
 // Collect the members' states and act on them as a single solve's host loop
@@ -1980,6 +2038,7 @@ extern "C" int pfk_batch_poll(pfk_batch T, int* finished, int cap, int* nfinishe
   }
   for (int r = 0; r < n; ++r) {
     auto& mb = T->mem[T->rows[r]];
+    if (mb.state != 1) continue;   // ended at an earlier poll; its row waits for the next rebuild
     pfk_session_s* S = mb.S;
     const int status = T->h_stat[2 * r], it = T->h_stat[2 * r + 1];
     bool ended = false;
@@ -2010,10 +2069,16 @@ extern "C" int pfk_batch_poll(pfk_batch T, int* finished, int cap, int* nfinishe
     }
     if (ended) {
       // the true residual at exit (already known after a converged check)
-      if (status != kDone) enqueue_true_check(S, T->s1);
+      if (status != kDone) enqueue_true_residual(S, T->s1);
       mb.state = 2;
       mb.code = code;
-      T->dirty = true;
+      // Its device status is final (not kRunning), so every later launch
+      // returns at once for its row: the tables and the captured graph stay
+      // valid.  They are rebuilt once ended rows hold half of the vector
+      // workgroups, not at every retirement (a rebuild synchronises the batch
+      // and re-instantiates its graph).
+      T->stale += (S->Pv() + 7) / 8 * 8;
+      if (2 * T->stale >= T->tot[kBpVec]) T->dirty = true;
       if (finished && nf < cap) finished[nf] = T->rows[r];
       ++nf;
       continue;
@@ -2243,6 +2308,7 @@ extern "C" int pfk_server_progress(pfk_server S, long long* completed, int cap, 
       pfk_solve_opts o;
       pfk_default_opts(&o);
       o.graph_iters = S->cfg.step_iters;
+      o.use_graph = S->cfg.launch_direct ? 0 : 1;
       pfk_server_s::Bt bt{r.method, r.B->kind, fp32, r.A->dim, nullptr, {}, 0};
       int rc = pfk_batch_create((pfk_method)r.method, S->cfg.mmax, S->cfg.max_active, S->stream, &o, &bt.T);
       if (rc) return rc;
@@ -2270,10 +2336,10 @@ extern "C" int pfk_server_progress(pfk_server S, long long* completed, int cap, 
     S->used += r.bytes;
     ++S->qhead;
   }
-  // advance
+  // advance: every batch on its own streams, none waiting for another
   for (auto& bt : S->batches)
     if (bt.active > 0) {
-      int rc = pfk_batch_step(bt.T, S->cfg.step_iters);
+      int rc = batch_step(bt.T, S->cfg.step_iters, false);
       if (rc) return rc;
     }
   // retire

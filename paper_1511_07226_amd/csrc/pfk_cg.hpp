@@ -104,7 +104,7 @@ k_residual(Grid g, StencilGeom sg, const double* __restrict__ b, const double* _
 template <bool CV>
 __device__ __forceinline__ void apply_body(const Grid& g, const StencilGeom& sg, const double* __restrict__ x,
                                            double* __restrict__ y, const SolveState* st) {
-  if (st != nullptr && read_status(st) != kRunning) return;
+  if (st != nullptr && !wg_running(st)) return;
   const auto in = stencil_in([&](long long t) { return x[t]; });
   auto sink = [&](long long idx, double, double Au) { y[idx] = Au; };
   stencil_march<double, CV>(g, sg, in, sink);
@@ -197,7 +197,7 @@ __device__ __forceinline__ void apply_pc_out_body(Blk bk, Grid g, StencilGeom sg
                                                   double c3, double* __restrict__ O, double* __restrict__ Nout,
                                                   int dots, const double* __restrict__ R, double* part,
                                                   SolveState* st) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   if (pd.kind == kPcBlockPcg) {
     if (pd.fp32) apply_pc_out_t<kPcBlockPcg, 1>(bk, g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
     else apply_pc_out_t<kPcBlockPcg, 0>(bk, g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
@@ -216,20 +216,40 @@ __global__ void __launch_bounds__(kBlock)
 k_apply_pc_out(Grid g, StencilGeom sg, PcOutDesc pd, const double* X3, double c3,
                double* __restrict__ O, double* __restrict__ Nout,
                int dots, const double* __restrict__ R, double* part, SolveState* st) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   apply_pc_out_t<K, F32, true>(this_blk(), g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
 }
 
-// True-residual verdict after a recurred convergence: kDone or kGap.
+// True-residual verdict after a recurred convergence: kDone or kGap.  part
+// holds the partials of ||b - A x||^2; part_nat (natural-norm test) those of
+// the true residual's gamma, <B(r), r> or <r, A B(r)>, which then decides
+// against the natural tolerance (section 5: other norms confirm it).
 __global__ void __launch_bounds__(kBlock)
-k_true_check(const double* part, int P, SolveState* st) {
+k_true_check(const double* part, int P, const double* part_nat, int Pn, SolveState* st) {
   const double rr = block_sum_column(part, P, 0);
+  const double gg = part_nat != nullptr ? block_sum_column(part_nat, Pn, 0) : 0.0;
   if (threadIdx.x == 0) {
     const double res = sqrt(rr);
     st->true_res = res;
-    // a natural-norm test accepts its iterate; the 2-norm is only reported
-    st->status = (res <= st->tol || st->norm) ? kDone : kGap;
+    // before the first start-up's natural norm exists (x0 met the 2-norm
+    // tolerance at once) the 2-norm decides
+    const bool nat = part_nat != nullptr && st->nat_started;
+    const bool ok = nat ? sqrt(fabs(gg)) <= st->ntol : res <= st->tol;
+    st->status = ok ? kDone : kGap;
   }
+}
+
+// The natural-norm check applies B to the true residual: its kernels run only
+// while the status is kRunning, so the check reopens a recurred convergence.
+__global__ void k_check_open(SolveState* st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && st->status == kConverged) st->status = kRunning;
+}
+
+// ||b - A x|| at exit, reported only (the status is left as it is).
+__global__ void __launch_bounds__(kBlock)
+k_true_report(const double* part, int P, SolveState* st) {
+  const double rr = block_sum_column(part, P, 0);
+  if (threadIdx.x == 0) st->true_res = sqrt(rr);
 }
 
 // ---------------------------------------------------------------------------
@@ -239,7 +259,7 @@ k_true_check(const double* part, int P, SolveState* st) {
 __global__ void __launch_bounds__(kBlock)
 k_pipefcg_init_scalars(const double* part_r, int P_r, const double* part_ud, int P_ud,
                        SolveState* st, double* hist) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   const double rr = block_sum_column(part_r, P_r, 0);
   const double gamma = block_sum_column(part_ud, P_ud, 0);
   const double delta = block_sum_column(part_ud, P_ud, 1);
@@ -311,7 +331,7 @@ __device__ __forceinline__ void pipefcg_update_body_t(Blk bk, long long N, Windo
                  double* __restrict__ x, double* __restrict__ r, double* __restrict__ u,
                  double* __restrict__ w, const double* __restrict__ m, const double* __restrict__ n,
                  double* part, const SolveState* st, int red_w) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   __shared__ double s_beta[kNuMax];
   __shared__ long long s_off[kNuMax];
   __shared__ double s_dot[kWaves][kNuMax + 4];
@@ -421,7 +441,7 @@ k_pipefcg_update(long long N, Window P, Window S, Window Q, Window Z,
 // eta_{j+1} = delta - sum beta^2 eta_d (breakdown if not positive), alpha.
 __device__ __forceinline__ void pipefcg_scalars_body(Blk bk, const double* part, int P, SolveState* st, double* hist) {
   __shared__ double col[kNuMax + 3];
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   const int j1 = st->j + 1;
   const int nu1 = trunc_nu(st->trunc, j1, st->nu_max);
   block_sum_columns(part, P, 3 + nu1, col);
@@ -465,7 +485,7 @@ k_pipefcg_scalars(const double* part, int P, SolveState* st, double* hist) {
 // x += alpha p_j, r -= alpha s_j for the newest direction j = st->j.
 __device__ __forceinline__ void fcg_xr_body(Blk bk, long long N, Window P, Window S, double* __restrict__ x, double* __restrict__ r,
          const SolveState* st) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   const int slot = st->j % st->nu_max;
   const double alpha = st->alpha;
   const double* p = P.slot(slot);
@@ -491,7 +511,7 @@ k_fcg_xr(long long N, Window P, Window S, double* __restrict__ x, double* __rest
 template <bool NT>
 __device__ __forceinline__ void multidot_body_t(Blk bk, long long N, int init, int from_pc, PcOutDesc pd, const double* __restrict__ Vin,
            double* __restrict__ Vout, const double* __restrict__ R, Window S, double* part, SolveState* st) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   PcOut pc{};
   if (from_pc) pc = make_pc_out(pd, &st->pc);
   __shared__ long long s_off[kNuMax];
@@ -596,7 +616,7 @@ k_multidot(long long N, int init, int from_pc, PcOutDesc pd, const double* __res
 // (FCG) gamma = <u, r>.  With `init` only j = 0 and gamma are set.
 __device__ __forceinline__ void cg_scalars1_body(Blk bk, int init, const double* part, int P, SolveState* st, double* hist) {
   __shared__ double col[kNuMax + 3];
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   const int j1 = init ? 0 : st->j + 1;
   const int nu = init ? 0 : trunc_nu(st->trunc, j1, st->nu_max);
   block_sum_columns(part, P, 3 + nu, col);
@@ -630,7 +650,7 @@ k_cg_scalars1(int init, const double* part, int P, SolveState* st, double* hist)
 // p_j = u + sum beta p_d into slot j (FCG).
 template <bool NT>
 __device__ __forceinline__ void fcg_maxpy_body_t(Blk bk, long long N, Window P, const double* __restrict__ u, const SolveState* st) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   __shared__ double s_beta[kNuMax];
   __shared__ long long s_off[kNuMax];
   const int j = st->j, nu = st->nu, numax = st->nu_max;
@@ -675,7 +695,7 @@ template <bool NT>
 __device__ __forceinline__ void gcr_maxpy_t(long long N, Window P, Window S, const double* __restrict__ u,
                                             const double* __restrict__ t_, const double* __restrict__ r,
                                             double* part, const SolveState* st) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   __shared__ double s_beta[kNuMax];
   __shared__ long long s_off[kNuMax];
   const int j = st->j, nu = st->nu, numax = st->nu_max;
@@ -714,7 +734,7 @@ k_gcr_maxpy(long long N, Window P, Window S, const double* __restrict__ u, const
 
 // s_j = A p_j, partial eta_j = <p_j, s_j> (FCG).
 __device__ __forceinline__ void fcg_apply_body(Blk bk, Grid g, StencilGeom sg, Window P, Window S, double* part, const SolveState* st) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   const int slot = st->j % st->nu_max;
   const double* p = P.slot(slot);
   double* s = S.slot(slot);
@@ -735,7 +755,7 @@ k_fcg_apply(Grid g, StencilGeom sg, Window P, Window S, double* part, const Solv
 // Second-reduction scalars: eta_j (FCG: <p,s>; GCR: <s,s> with gamma = <r,s>),
 // breakdown check, alpha_j.
 __device__ __forceinline__ void cg_scalars2_body(Blk bk, int gcr, int init, const double* part, int P, SolveState* st) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   const double c0 = block_sum_column(part, P, 0);
   const double c1 = gcr ? block_sum_column(part, P, 1) : 0.0;
   if (threadIdx.x != 0) return;
@@ -762,7 +782,7 @@ k_cg_scalars2(int gcr, int init, const double* part, int P, SolveState* st) {
 // Start-up test on ||r_0|| (history[0]).
 __global__ void __launch_bounds__(kBlock)
 k_init_test(const double* part, int P, SolveState* st, double* hist) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   const double rr = block_sum_column(part, P, 0);
   if (threadIdx.x != 0) return;
   const double res = sqrt(rr);
@@ -779,7 +799,7 @@ k_init_test(const double* part, int P, SolveState* st, double* hist) {
 // R = r_0): gamma_0 = <r_0, s_0>, eta_0 = <s_0, s_0>, alpha_0.
 __global__ void __launch_bounds__(kBlock)
 k_pipegcr_init_scalars(const double* part, int P, SolveState* st) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   const double gamma = block_sum_column(part, P, 0);
   const double eta = block_sum_column(part, P, 1);
   if (threadIdx.x != 0) return;
@@ -799,7 +819,7 @@ k_pipegcr_init_scalars(const double* part, int P, SolveState* st) {
 __global__ void __launch_bounds__(kBlock)
 k_pipegcr_update(long long N, Window P, Window S, Window Q, double* __restrict__ x, double* __restrict__ r,
                  double* __restrict__ u, const double* __restrict__ w, PcOutDesc pd, SolveState* st) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   __shared__ double s_beta[kNuMax];
   __shared__ long long s_off[kNuMax];
   const int j = st->j;

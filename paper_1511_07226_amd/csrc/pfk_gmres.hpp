@@ -59,7 +59,7 @@ __device__ inline void gm_finish_cycle(SolveState* st, int ncol) {
 // ||r_0||, g = beta_0 e_0, the scale 1/beta_0 of p_0.
 __global__ void __launch_bounds__(kBlock)
 k_gm_cycle_start(const double* part, int P, SolveState* st, double* hist) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   const double rr = block_sum_column(part, P, 0);
   if (threadIdx.x != 0) return;
   const double beta = sqrt(rr);
@@ -80,7 +80,7 @@ k_gm_cycle_start(const double* part, int P, SolveState* st, double* hist) {
 __global__ void __launch_bounds__(kBlock)
 k_gm_scale(long long N, const double* src, int from_window, Window P, double* __restrict__ vin,
            const SolveState* st) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   const double sc = st->inv_hn;
   double* dst = P.slot(st->col);
   const double* s = from_window ? dst : src;
@@ -115,7 +115,7 @@ k_gm_update_x(long long N, Window U, const double* __restrict__ x0, double* __re
 // u_c = B(p_c) into U[c] and z = A u_c (c = st->col).
 __global__ void __launch_bounds__(kBlock)
 k_fgm_apply(Grid g, StencilGeom sg, PcOutDesc pd, Window U, double* __restrict__ z, SolveState* st) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   const PcOut pc = make_pc_out(pd, &st->pc);
   double* uc = U.slot(st->col);
   const auto in = stencil_in([&](long long t) { return pc(t); });
@@ -130,7 +130,7 @@ k_fgm_apply(Grid g, StencilGeom sg, PcOutDesc pd, Window U, double* __restrict__
 // First reduction: <p_j, z> for j <= c.
 __global__ void __launch_bounds__(kBlock)
 k_fgm_dots(long long N, Window P, const double* __restrict__ z, double* part, const SolveState* st) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   __shared__ double s_dot[kWaves][kNuMax + 1];
   const int nc = st->col + 1;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -163,7 +163,7 @@ k_fgm_dots(long long N, Window P, const double* __restrict__ z, double* part, co
 __global__ void __launch_bounds__(kBlock)
 k_gm_hbar(const double* part, int P, SolveState* st) {
   __shared__ double col[kNuMax + 1];
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   const int nc = st->col + 1;
   block_sum_columns(part, P, nc, col);
   for (int c = threadIdx.x; c < nc; c += kBlock) st->hbar[c] = col[c];
@@ -172,7 +172,7 @@ k_gm_hbar(const double* part, int P, SolveState* st) {
 // p-bar = z - sum_j h_j p_j into P[c+1] (unnormalised), partial ||p-bar||^2.
 __global__ void __launch_bounds__(kBlock)
 k_fgm_orth(long long N, Window P, const double* __restrict__ z, double* part, const SolveState* st) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   __shared__ double s_h[kNuMax + 1];
   const int nc = st->col + 1;
   for (int t = threadIdx.x; t < nc; t += kBlock) s_h[t] = st->hbar[t];
@@ -191,7 +191,7 @@ k_fgm_orth(long long N, Window P, const double* __restrict__ z, double* part, co
 // Second reduction: h_{c+1,c} = ||p-bar||, Givens, history, test, cycle end.
 __global__ void __launch_bounds__(kBlock)
 k_fgm_column(const double* part, int P, SolveState* st, double* hist) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   const double nn = block_sum_column(part, P, 0);
   if (threadIdx.x != 0) return;
   const int c = st->col;
@@ -218,7 +218,7 @@ k_fgm_column(const double* part, int P, SolveState* st, double* hist) {
 __global__ void __launch_bounds__(kBlock)
 k_pgm_apply0(Grid g, StencilGeom sg, PcOutDesc pd, Window U, Window P, Window ZB, double* __restrict__ zin,
              double* part, SolveState* st) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   const PcOut pc = make_pc_out(pd, &st->pc);
   const double sigma = st->sigma;
   double* u0 = U.slot(0);
@@ -246,7 +246,7 @@ k_pgm_apply0(Grid g, StencilGeom sg, PcOutDesc pd, Window U, Window P, Window ZB
 // Givens, history, test, cycle end.
 __device__ __forceinline__ void pgm_scalars_body(Blk bk, const double* part, int P, SolveState* st, double* hist) {
   __shared__ double col[kNuMax + 2];
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   const int c = st->col;
   block_sum_columns(part, P, c + 2, col);
   if (threadIdx.x != 0) return;
@@ -297,7 +297,7 @@ k_pgm_scalars(const double* part, int P, SolveState* st, double* hist) {
 template <bool NT>
 __device__ __forceinline__ void pgm_update_body_t(Blk bk, long long N, Window P, Window U, Window ZB, PcOutDesc pd, const double* __restrict__ wb,
              double* __restrict__ zin, double* part, SolveState* st) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   const PcOut pc = make_pc_out(pd, &st->pc);
   __shared__ double s_h[kNuMax + 1];
   __shared__ double s_dot[kWaves][kNuMax + 2];

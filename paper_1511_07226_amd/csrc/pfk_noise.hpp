@@ -78,7 +78,7 @@ __global__ void k_noise_advance(SolveState* st, int count) {
 __global__ void __launch_bounds__(kBlock)
 k_noise_norms(long long N, const double* __restrict__ X1, double c1, const double* __restrict__ X2, double c2,
               unsigned long long seed, long long fixed, int offset, double* part, const SolveState* st) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   const unsigned long long d = noise_draw(st, fixed, offset);
   double acc[2] = {0.0, 0.0};
   for (long long e = gtid(); e < N; e += gstride()) {
@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(kBlock)
 k_noise_apply(long long N, const double* __restrict__ X1, double c1, const double* __restrict__ X2, double c2,
               unsigned long long seed, long long fixed, int offset, double eta, const double* part, int P,
               double* __restrict__ y, const SolveState* st) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   const double vv = block_sum_column(part, P, 0);
   const double gg = block_sum_column(part, P, 1);
   const double s = (vv > 0.0 && gg > 0.0) ? eta * sqrt(vv) / sqrt(gg) : 0.0;

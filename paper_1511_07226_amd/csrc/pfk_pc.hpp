@@ -243,7 +243,7 @@ k_pcg_a1(G g, StencilGeom sg, const T* __restrict__ dinv,
          const double* X1, double c1, const double* X2, double c2,
          T* __restrict__ pout, T* __restrict__ qout,
          double* part, const SolveState* st) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   double acc[2] = {0.0, 0.0};
   auto V = [&](long long t) { double r = c1 * X1[t]; if (X2 != nullptr) r += c2 * X2[t]; return T(r); };
   struct Raw { T d; double x1, x2; };
@@ -278,7 +278,7 @@ k_pcg_b(int jstep, long long N, const T* __restrict__ dinv,
         const T* __restrict__ p, const T* __restrict__ q,
         T* __restrict__ rho, T* __restrict__ y,
         const double* part_in, int P_in, double* part_out, SolveState* st) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   PcScalars* pcs = &st->pc;
   const double pq = block_sum_column(part_in, P_in, 0);
   double gj;
@@ -389,7 +389,7 @@ k_pcg_a(int jstep, G g, StencilGeom sg, const T* __restrict__ dinv,
         const T* __restrict__ rho, const T* __restrict__ pprev,
         T* __restrict__ pout, T* __restrict__ qout,
         const double* part_in, int P_in, double* part_out, SolveState* st) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   PcScalars* pcs = &st->pc;
   const double gj = block_sum_column(part_in, P_in, 0);
   const double gprev = pcs->gamma[jstep - 1];
@@ -415,7 +415,7 @@ template <class T>
 __global__ void __launch_bounds__(kBlock)
 k_gmpc_start(long long N, int k, const double* X1, double c1, const double* X2, double c2,
              T* __restrict__ V0, double* part_out, SolveState* st) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) st->pc.ncol = k;
   double acc[1] = {0.0};
   for (long long e = gtid(); e < N; e += gstride()) {
@@ -435,7 +435,7 @@ template <class T, class G, bool CV = false>
 __global__ void __launch_bounds__(kBlock)
 k_gmpc_apply(int jstep, G g, StencilGeom sg, const T* __restrict__ dinv, const T* Vbase,
              long long ldv, T* __restrict__ w, const double* part_in, int P_in, SolveState* st) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   PcScalars* pcs = &st->pc;
   if (jstep >= pcs->ncol) return;
   const double nrm = sqrt(block_sum_column(part_in, P_in, 0));
@@ -462,7 +462,7 @@ template <class T>
 __global__ void __launch_bounds__(kBlock)
 k_gmpc_dots(int jstep, long long N, const T* Vbase, long long ldv, const T* __restrict__ w, double* part_out,
             SolveState* st) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   if (jstep >= st->pc.ncol) return;
   double acc[kMaxInnerGmres];
 #pragma unroll
@@ -499,7 +499,7 @@ template <class T>
 __global__ void __launch_bounds__(kBlock)
 k_gmpc_orth(int jstep, int k, long long N, T* Vbase, long long ldv, const T* __restrict__ w,
             const double* part_in, int P_in, double* part_out, SolveState* st) {
-  if (read_status(st) != kRunning) return;
+  if (!wg_running(st)) return;
   PcScalars* pcs = &st->pc;
   if (jstep >= pcs->ncol) return;
   __shared__ double coef[kMaxInnerGmres];

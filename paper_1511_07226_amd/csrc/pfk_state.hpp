@@ -102,10 +102,12 @@ __device__ __forceinline__ int read_status(const SolveState* st) {
 }
 
 // Whether the solve runs, as one value for the whole workgroup (thread 0
-// reads, a barrier shares it).  A body with internal barriers that can run
-// while another workgroup changes the status (the inner solve beside the
-// scalar kernel inside a persistent launch, where an early return does not
-// end the wave) tests it this way, so every wave takes the same branch.
+// reads, a barrier shares it).  Every kernel and device body tests the status
+// this way on entry: the preconditioner and operator kernels of a pipelined
+// method run on one stream while the scalar kernel on the other may change
+// the status, and a per-thread read could send the waves of one workgroup to
+// different sides of the body's barriers (inside a persistent launch an early
+// return does not even end the wave).
 __device__ __forceinline__ bool wg_running(const SolveState* st) {
   __shared__ int s_run;
   __syncthreads();
