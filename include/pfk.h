@@ -259,6 +259,26 @@ int pfk_solve(pfk_operator A, pfk_precond B, pfk_method method, const double* b,
               double rtol, int maxit, int mmax, void* workspace, size_t ws_bytes, void* stream,
               const pfk_solve_opts* opts, pfk_solve_info* info);
 
+/* pfk_solve for callers that cannot allocate memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  The same
+ * solve, arguments and results as pfk_solve with these differences:
+ *   - the workspace is a fixed device array inside the library, 256 MiB
+ *     (268,435,456 bytes) on each GPU the library runs on, held until the
+ *     process ends; a solve whose pfk_workspace_bytes(A, B, method, mmax,
+ *     maxit) exceeds it is refused with PFK_ERR_ARG (PIPEFCG with mmax 30
+ *     fits up to about 240,000 unknowns, FCG about 450,000);
+ *   - every kernel runs on `stream` (the pipelined methods' second-stream
+ *     work is ordered on it too; the arithmetic is the same), launched
+ *     directly: no streams, events, graphs, host or device allocations;
+ *   - opts->timestamps must be 0.
+ * The call synchronises `stream` (the host reads the solve's status).  Every
+ * call on one GPU uses that GPU's one array, which keeps the last call's
+ * contents (the call clears what must start at zero): calls that overlap on
+ * one GPU, from several threads or streams, race and must not be made. */
+int pfk_solve_noalloc(pfk_operator A, pfk_precond B, pfk_method method, const double* b, double* x,
+                      double rtol, int maxit, int mmax, void* stream, const pfk_solve_opts* opts,
+                      pfk_solve_info* info);
+
 /* Sessions split pfk_solve into asynchronous steps (for timing and serving):
  * create binds the buffers, start enqueues the set-up and start-up phase,
  * iterate enqueues `iters` more iterations without waiting, sync waits and

@@ -11,5 +11,5 @@ from .binding import (  # noqa: F401
     PC_NONE, PC_JACOBI, PC_JACOBI_PCG, PC_JACOBI_GMRES, PC_BLOCK_JACOBI_PCG, PC_NOISY, PC_KINDS,
     FP64, FP32_BF16COEF,
     PfkError, Operator, Precond, Session, SolveInfo, SolveOpts, Batch, Tuning, Server,
-    solve, solve_batched, workspace_bytes, estimate_sigma, lib, lib_path, EXPORTED,
+    solve, solve_noalloc, solve_batched, workspace_bytes, estimate_sigma, lib, lib_path, EXPORTED,
 )

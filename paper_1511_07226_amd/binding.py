@@ -35,7 +35,7 @@ EXPORTED = [
     "pfk_default_opts", "pfk_operator_create", "pfk_operator_destroy", "pfk_operator_size",
     "pfk_operator_apply", "pfk_operator_diag_inv", "pfk_precond_create", "pfk_precond_create_noisy",
     "pfk_precond_destroy",
-    "pfk_precond_apply", "pfk_workspace_bytes", "pfk_solve", "pfk_session_create",
+    "pfk_precond_apply", "pfk_workspace_bytes", "pfk_solve", "pfk_solve_noalloc", "pfk_session_create",
     "pfk_session_start", "pfk_session_iterate", "pfk_session_sync", "pfk_session_destroy",
     "pfk_session_profile", "pfk_estimate_sigma", "pfk_last_error",
     "pfk_operator_set_tiling", "pfk_operator_get_tiling", "pfk_operator_autotune",
@@ -133,6 +133,8 @@ def lib():
         "pfk_workspace_bytes": (C.c_size_t, [vp, vp, C.c_int, C.c_int, C.c_int]),
         "pfk_solve": (C.c_int, [vp, vp, C.c_int, vp, vp, C.c_double, C.c_int, C.c_int, vp, C.c_size_t,
                                 vp, C.POINTER(SolveOpts), C.POINTER(_Info)]),
+        "pfk_solve_noalloc": (C.c_int, [vp, vp, C.c_int, vp, vp, C.c_double, C.c_int, C.c_int, vp,
+                                        C.POINTER(SolveOpts), C.POINTER(_Info)]),
         "pfk_session_create": (C.c_int, [vp, vp, C.c_int, vp, vp, C.c_double, C.c_int, C.c_int, vp,
                                          C.c_size_t, vp, C.POINTER(SolveOpts), C.POINTER(vp)]),
         "pfk_session_start": (C.c_int, [vp]),
@@ -347,6 +349,19 @@ def solve(A: Operator, B: Precond, method: str, b, x, rtol: float = 1e-8, maxit:
     code = lib().pfk_solve(A.handle, B.handle, METHODS[method], _dev_ptr(b, A.N, "b"), _dev_ptr(x, A.N, "x"),
                            float(rtol), int(maxit), int(mmax), wsp, wsb, _stream_ptr(stream), C.byref(o),
                            C.byref(info))
+    _check(code, allow_positive=True)
+    return _to_info(code, info, hist)
+
+
+def solve_noalloc(A: Operator, B: Precond, method: str, b, x, rtol: float = 1e-8, maxit: int = 500,
+                  mmax: int = 30, stream=None, **opts) -> SolveInfo:
+    """solve() through pfk_solve_noalloc: the library's fixed device workspace,
+    one stream, no allocation (for callers that cannot allocate)."""
+    o = default_opts(**opts)
+    info, hist = _info_struct(maxit + 1)
+    code = lib().pfk_solve_noalloc(A.handle, B.handle, METHODS[method], _dev_ptr(b, A.N, "b"),
+                                   _dev_ptr(x, A.N, "x"), float(rtol), int(maxit), int(mmax), _stream_ptr(stream),
+                                   C.byref(o), C.byref(info))
     _check(code, allow_positive=True)
     return _to_info(code, info, hist)
 

@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -853,6 +854,21 @@ void enqueue_start(pfk_session_s* S, hipStream_t s) {
   noise_end(S, s);
 }
 
+// The second stream's branch of a pipelined iteration: fork it off s1, mark
+// its end, join it back.  A session that runs on one stream (s1 == s2) has
+// no events and orders the same kernels in one queue (same results).
+void side_fork(pfk_session_s* S) {
+  if (S->s2 == S->s1) return;
+  (void)hipEventRecord(S->ev_fork, S->s1);
+  (void)hipStreamWaitEvent(S->s2, S->ev_fork, 0);
+}
+void side_end(pfk_session_s* S) {
+  if (S->s2 != S->s1) (void)hipEventRecord(S->ev_join, S->s2);
+}
+void side_join(pfk_session_s* S) {
+  if (S->s2 != S->s1) (void)hipStreamWaitEvent(S->s1, S->ev_join, 0);
+}
+
 // The stream-join test hook (opts.side_delay): a bounded delay on stream s.
 void side_delay(const pfk_session_s* S, hipStream_t s) {
   if (S->opts.side_delay > 0) LAUNCH(k_delay, 1, s, S->opts.side_delay);
@@ -877,18 +893,17 @@ void enqueue_iteration(pfk_session_s* S) {
              S->vec(V_R), S->vec(V_U), S->vec(V_W), (const double*)S->vec(V_M), (const double*)S->vec(V_N),
              S->part(PT_MAIN), (const SolveState*)S->st, S->method == PFK_PIPEGCR_W ? 1 : 0);
       // fork: finish the reduction on s2 while s1 applies B and A
-      (void)hipEventRecord(S->ev_fork, s1);
-      (void)hipStreamWaitEvent(s2, S->ev_fork, 0);
+      side_fork(S);
       side_delay(S, s2);
       LAUNCH(k_pipefcg_scalars, 1, s2, S->part(PT_MAIN), S->Pv(), S->st, S->hist);
-      (void)hipEventRecord(S->ev_join, s2);
+      side_end(S);
       // m = u + B(w - r) (Alg. 8, 12); the naive form (Alg. 7) takes m = B(w)
       const bool naive = S->method == PFK_PIPEFCG_NAIVE;
       PcOutDesc pd = naive ? enqueue_pc(S, s1, S->vec(V_W), 1.0, nullptr, 0.0)
                            : enqueue_pc(S, s1, S->vec(V_W), 1.0, S->vec(V_R), -1.0);
       LAUNCH_PC_OUT(pd, S->Ps(), s1, g, S->sg, pd, naive ? (const double*)nullptr : (const double*)S->vec(V_U),
              naive ? 0.0 : 1.0, S->vec(V_M), S->vec(V_N), 0, (const double*)nullptr, S->part(PT_B), S->st);
-      (void)hipStreamWaitEvent(s1, S->ev_join, 0);
+      side_join(S);
       break;
     }
     case PFK_PIPEGCR: {
@@ -898,13 +913,12 @@ void enqueue_iteration(pfk_session_s* S) {
              S->vec(V_U), (const double*)S->vec(V_W), pd_prev, S->st);
       LAUNCH_OP(S->A, k_apply, S->Ps(), s1, g, S->sg, (const double*)S->vec(V_U), S->vec(V_W), (const SolveState*)S->st);
       enqueue_multidot(S, s1, 0, 0, pd_prev, S->vec(V_W), nullptr);
-      (void)hipEventRecord(S->ev_fork, s1);
-      (void)hipStreamWaitEvent(s2, S->ev_fork, 0);
+      side_fork(S);
       side_delay(S, s2);
       LAUNCH(k_pipefcg_scalars, 1, s2, S->part(PT_MAIN), S->Pv(), S->st, S->hist);
-      (void)hipEventRecord(S->ev_join, s2);
+      side_end(S);
       enqueue_pc(S, s1, S->vec(V_W), 1.0, S->vec(V_R), -1.0);
-      (void)hipStreamWaitEvent(s1, S->ev_join, 0);
+      side_join(S);
       break;
     }
     case PFK_FGMRES: {
@@ -929,15 +943,14 @@ void enqueue_iteration(pfk_session_s* S) {
       const PcOutDesc pd_prev = pc_out_desc(S, S->vec(V_M), 1.0, nullptr, 0.0);
       LAUNCH(k_pgm_update, S->Pv(), s1, A->N, S->win(W_P), S->win(W_S), S->win(W_Q), pd_prev,
              (const double*)S->vec(V_Z), S->vec(V_M), S->part(PT_MAIN), S->st);
-      (void)hipEventRecord(S->ev_fork, s1);
-      (void)hipStreamWaitEvent(s2, S->ev_fork, 0);
+      side_fork(S);
       side_delay(S, s2);
       LAUNCH(k_pgm_scalars, 1, s2, S->part(PT_MAIN), S->Pv(), S->st, S->hist);
-      (void)hipEventRecord(S->ev_join, s2);
+      side_end(S);
       PcOutDesc pd = enqueue_pc(S, s1, S->vec(V_M), 1.0, nullptr, 0.0);
       LAUNCH_PC_OUT(pd, S->Ps(), s1, g, S->sg, pd, (const double*)nullptr, 0.0, (double*)nullptr,
              S->vec(V_Z), 0, (const double*)nullptr, S->part(PT_B), S->st);
-      (void)hipStreamWaitEvent(s1, S->ev_join, 0);
+      side_join(S);
       LAUNCH(k_gm_update_x, S->Pv(), s1, A->N, S->win(W_S), (const double*)S->vec(V_X0), S->x,
              (const SolveState*)S->st);
       break;
@@ -1294,16 +1307,13 @@ extern "C" int pfk_session_sync(pfk_session S, pfk_solve_info* info) {
   return fill_info(S, code, info);
 }
 
-// The full solve: start, iterate in graph chunks, check the true residual on
-// convergence, restart on breakdown or residual gap.
-extern "C" int pfk_solve(pfk_operator A, pfk_precond B, pfk_method method, const double* b, double* x,
-                         double rtol, int maxit, int mmax, void* workspace, size_t ws_bytes, void* stream,
-                         const pfk_solve_opts* opts, pfk_solve_info* info) {
-  pfk_session S = nullptr;
-  int rc = pfk_session_create(A, B, method, b, x, rtol, maxit, mmax, workspace, ws_bytes, stream, opts, &S);
-  if (rc) return rc;
-  rc = pfk_session_start(S);
+// The host loop of a full solve after its start-up has been enqueued:
+// iterate in graph chunks (or direct launches), check the true residual on
+// convergence, restart on breakdown or residual gap; then the true residual
+// at exit.  Returns a HIP/argument error (rc) or PFK_OK with *code set.
+static int solve_loop(pfk_session_s* S, int* code_out) {
   int code = PFK_NOT_CONVERGED;
+  int rc = PFK_OK;
   const int max_restarts = S->opts.max_restarts;
   while (rc == PFK_OK) {
     rc = read_state(S);
@@ -1344,6 +1354,20 @@ extern "C" int pfk_solve(pfk_operator A, pfk_precond B, pfk_method method, const
     if (!S->host_state->bzero) enqueue_true_residual(S, S->s1);
     rc = read_state(S);
   }
+  *code_out = code;
+  return rc;
+}
+
+// The full solve: start, then the host loop above.
+extern "C" int pfk_solve(pfk_operator A, pfk_precond B, pfk_method method, const double* b, double* x,
+                         double rtol, int maxit, int mmax, void* workspace, size_t ws_bytes, void* stream,
+                         const pfk_solve_opts* opts, pfk_solve_info* info) {
+  pfk_session S = nullptr;
+  int rc = pfk_session_create(A, B, method, b, x, rtol, maxit, mmax, workspace, ws_bytes, stream, opts, &S);
+  if (rc) return rc;
+  rc = pfk_session_start(S);
+  int code = PFK_NOT_CONVERGED;
+  if (rc == PFK_OK) rc = solve_loop(S, &code);
   if (rc == PFK_OK) {
     fill_info(S, code, info);
     if (info) info->converged = (code == PFK_OK) ? 1 : 0;
@@ -1353,6 +1377,107 @@ extern "C" int pfk_solve(pfk_operator A, pfk_precond B, pfk_method method, const
   (void)hipEventRecord(S->ev_done, S->s1);
   (void)hipStreamWaitEvent(S->user, S->ev_done, 0);
   pfk_session_destroy(S);
+  return rc ? rc : code;
+}
+
+// ---------------------------------------------------------------------------
+// the solve for callers that cannot allocate
+// ---------------------------------------------------------------------------
+// pfk_solve_noalloc's workspace: a fixed array in device memory, one copy on
+// every GPU the library runs on, held until the process ends.  Host code
+// never uses the symbol's name as an address: the device address comes from
+// hipGetSymbolAddress, looked up once per device with that device current.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// The current device's address of `scratch`.
+int scratch_address(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(PFK_ERR_ARG, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(PFK_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PFK_OK;
+}
+
+// Zero n 8-byte words (a kernel, so the call can also be recorded in a graph).
+__global__ void __launch_bounds__(kBlock) k_zero_words(unsigned long long* __restrict__ p, long long n) {
+  for (long long e = gtid(); e < n; e += gstride()) p[e] = 0ull;
+}
+
+}  // namespace
+
+extern "C" int pfk_solve_noalloc(pfk_operator A, pfk_precond B, pfk_method method, const double* b, double* x,
+                                 double rtol, int maxit, int mmax, void* stream, const pfk_solve_opts* opts,
+                                 pfk_solve_info* info) {
+  if (!A || !B || !b || !x) return fail(PFK_ERR_ARG, "null argument");
+  if (B->A != A) return fail(PFK_ERR_ARG, "preconditioner was made for another operator");
+  if (method < PFK_FCG || method > PFK_PIPEFCG_NAIVE) return fail(PFK_ERR_ARG, "unknown method");
+  if (mmax < 1 || mmax > kNuMax) return fail(PFK_ERR_ARG, "mmax must be 1..64");
+  if (maxit < 0) return fail(PFK_ERR_ARG, "maxit must be >= 0");
+  if (!(rtol >= 0.0)) return fail(PFK_ERR_ARG, "rtol must be >= 0");
+  if (((uintptr_t)b | (uintptr_t)x) % 16 != 0) return fail(PFK_ERR_ARG, "b and x must be 16-byte aligned");
+  pfk_session_s S;   // on the stack: no host or device allocation
+  pfk_default_opts(&S.opts);
+  if (opts) S.opts = *opts;
+  if (S.opts.graph_iters < 1) S.opts.graph_iters = 1;
+  if (S.opts.truncation < 0 || S.opts.truncation > 2) return fail(PFK_ERR_ARG, "truncation must be 0, 1 or 2");
+  if (S.opts.norm < 0 || S.opts.norm > 1) return fail(PFK_ERR_ARG, "norm must be 0 (2-norm) or 1 (natural)");
+  if (S.opts.side_delay < 0 || S.opts.side_delay > 10000) return fail(PFK_ERR_ARG, "side_delay must be 0..10000");
+  if (S.opts.timestamps)
+    return fail(PFK_ERR_ARG, "timestamps are not available in the no-allocation solve (use pfk_solve)");
+  if (S.opts.host_sync && method != PFK_FCG && method != PFK_GCR && method != PFK_FGMRES)
+    return fail(PFK_ERR_ARG, "host_sync applies to FCG, GCR and FGMRES only");
+  S.opts.use_graph = 0;   // instantiating a graph allocates: kernels are launched directly
+  S.L = make_layout(A, B, method, mmax, maxit);
+  if (S.L.total > kScratchBytes)
+    return fail(PFK_ERR_ARG, "this solve needs " + std::to_string(S.L.total) +
+                                 " bytes of workspace; the no-allocation solve has " +
+                                 std::to_string(kScratchBytes) + " (use pfk_solve with a workspace)");
+  void* ws = nullptr;
+  int rc = scratch_address(&ws);
+  if (rc) return rc;
+  SolveState host_state{};   // the host's copy of the device state, also on the stack
+  S.A = A; S.B = B; S.method = method; S.b = b; S.x = x; S.rtol = rtol;
+  S.maxit = maxit; S.mmax = mmax;
+  S.sg = A->sg;
+  S.pv = A->pv_blocks;
+  S.ws = (char*)ws;
+  S.ws_owned = false;
+  S.st = (SolveState*)(S.ws + S.L.state);
+  S.hist = (double*)(S.ws + S.L.hist);
+  S.nhist = (double*)(S.ws + S.L.nhist);
+  S.tstamp = (unsigned long long*)(S.ws + S.L.tstamp);
+  // one stream, the caller's: the second stream's branch runs in order on it
+  S.user = S.s1 = S.s2 = (hipStream_t)stream;
+  S.owns_streams = false;
+  S.host_state = &host_state;
+  // the array keeps the previous call's contents: the state and the histories
+  // start from zero (every other part is written before it is read)
+  LAUNCH(k_zero_words, 64, S.s1, (unsigned long long*)S.ws, (long long)(S.L.vec[0] / 8));
+  HIPCHK(hipGetLastError());
+  rc = session_setup(&S);
+  if (rc == PFK_OK) rc = launch_start(&S);
+  int code = PFK_NOT_CONVERGED;
+  if (rc == PFK_OK) rc = solve_loop(&S, &code);
+  if (rc == PFK_OK) {
+    fill_info(&S, code, info);
+    if (info) info->converged = (code == PFK_OK) ? 1 : 0;
+  } else if (info) {
+    info->status = rc;
+  }
   return rc ? rc : code;
 }
 
