@@ -319,8 +319,11 @@ const char* pfk_last_error(void);
  * computes exactly what a single pfk_solve with the same arguments computes.
  *
  * Methods: PIPEFCG, FCG, PIPEFGMRES (mmax = window or restart length).
- * Preconditioners: NONE, JACOBI, BLOCK_JACOBI_PCG; all members of a batch share
- * the dimension, the preconditioner kind and its precision.  opts as for
+ * Preconditioners: every kind but NOISY; all members of a batch share the
+ * dimension, the preconditioner kind and its precision, and for the global
+ * inner solves (JACOBI_PCG, JACOBI_GMRES) the number of inner steps: each of
+ * their phases is one launch over all members.  The persistent form takes
+ * NONE, JACOBI and BLOCK_JACOBI_PCG only.  opts as for
  * pfk_solve except host_sync (rejected); graph_iters iterations are captured
  * per graph (recaptured when members are added or removed, or when members
  * that ended hold half of the vector workgroups; until then an ended member's

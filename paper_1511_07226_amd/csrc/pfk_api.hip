@@ -1763,6 +1763,7 @@ struct pfk_batch_s {
   hipStream_t user = nullptr, s1 = nullptr, s2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_user = nullptr, ev_done = nullptr;
   int dim = 0, fp32 = -1, pc_kind = -1;   // shared by every member (fixed by the first one added)
+  int pc_k = -1;                          // inner steps, shared when the inner solve is global
   struct Member {
     pfk_session S = nullptr;
     int state = 0;     // 0 free, 1 running, 2 finished
@@ -1818,6 +1819,12 @@ BSys make_bsys(const pfk_session_s* S) {
   d.S = S->win(W_S);
   d.Q = S->win(W_Q);
   d.Z = S->win(W_Z);
+  d.pc_p0 = S->vec(V_PC_P0);
+  d.pc_p1 = S->vec(V_PC_P1);
+  d.pc_q = S->vec(V_PC_Q);
+  d.pc_rho = S->vec(V_PC_RHO);
+  d.part_pc0 = S->part(PT_PC0);
+  d.part_pc1 = S->part(PT_PC1);
   d.x = S->x;
   d.r = S->vec(V_R);
   d.u = S->vec(V_U);
@@ -1886,6 +1893,28 @@ void batch_block_pc(pfk_batch_s* Tb, const int* off, int n) {
   else LAUNCH((kb_block_pcg<T, 0>), Tb->tot[kBpBlk], s1, Tb->d_sys, off, n);
 }
 
+// The global inner solves of every member, phase by phase as a single solve
+// launches them (os: stencil ranges, ov: vector ranges).
+template <class T>
+void batch_inner_pcg(pfk_batch_s* Tb, const int* os, const int* ov, int n) {
+  hipStream_t s1 = Tb->s1;
+  LAUNCH((kb_pcg_a1<T>), Tb->tot[kBpSten], s1, Tb->d_sys, os, n);
+  for (int j = 1; j < Tb->pc_k; ++j) {
+    LAUNCH((kb_pcg_b<T>), Tb->tot[kBpVec], s1, Tb->d_sys, ov, n, j);
+    LAUNCH((kb_pcg_a<T>), Tb->tot[kBpSten], s1, Tb->d_sys, os, n, j);
+  }
+}
+template <class T>
+void batch_inner_gmres(pfk_batch_s* Tb, const int* os, const int* ov, int n) {
+  hipStream_t s1 = Tb->s1;
+  LAUNCH((kb_gmpc_start<T>), Tb->tot[kBpVec], s1, Tb->d_sys, ov, n);
+  for (int j = 0; j < Tb->pc_k; ++j) {
+    LAUNCH((kb_gmpc_apply<T>), Tb->tot[kBpSten], s1, Tb->d_sys, os, n, j);
+    LAUNCH((kb_gmpc_dots<T>), Tb->tot[kBpVec], s1, Tb->d_sys, ov, n, j);
+    LAUNCH((kb_gmpc_orth<T>), Tb->tot[kBpVec], s1, Tb->d_sys, ov, n, j);
+  }
+}
+
 // One outer iteration of every running member.
 void enqueue_batch_iteration(pfk_batch_s* T) {
   const int n = (int)T->rows.size();
@@ -1893,11 +1922,23 @@ void enqueue_batch_iteration(pfk_batch_s* T) {
   const int* os = T->d_off + kBpSten * (n + 1);
   const int* ob = T->d_off + kBpBlk * (n + 1);
   hipStream_t s1 = T->s1, s2 = T->s2;
-  const bool blockpc = T->pc_kind == kPcBlockPcg;
   auto pc = [&]() {
-    if (!blockpc) return;
-    if (T->fp32) batch_block_pc<float>(T, ob, n);
-    else batch_block_pc<double>(T, ob, n);
+    switch (T->pc_kind) {
+      case kPcBlockPcg:
+        if (T->fp32) batch_block_pc<float>(T, ob, n);
+        else batch_block_pc<double>(T, ob, n);
+        break;
+      case kPcJacobiPcg:
+        if (T->fp32) batch_inner_pcg<float>(T, os, ov, n);
+        else batch_inner_pcg<double>(T, os, ov, n);
+        break;
+      case kPcJacobiGmres:
+        if (T->fp32) batch_inner_gmres<float>(T, os, ov, n);
+        else batch_inner_gmres<double>(T, os, ov, n);
+        break;
+      default:
+        break;   // NONE, JACOBI: B(v) is evaluated by its consumer
+    }
   };
   switch (T->method) {
     case PFK_PIPEFCG:
@@ -2045,11 +2086,15 @@ extern "C" int pfk_batch_add(pfk_batch T, pfk_operator A, pfk_precond B, const d
   if (!T || !A || !B || !slot) return fail(PFK_ERR_ARG, "null argument");
   *slot = -1;
   const int kind = B->kind;
-  if (kind != kPcNone && kind != kPcJacobi && kind != kPcBlockPcg)
-    return fail(PFK_ERR_ARG, "batches take the NONE, JACOBI or BLOCK_JACOBI_PCG preconditioner");
-  const int fp32 = kind == kPcBlockPcg && B->prec == PFK_FP32_BF16COEF;
+  if (kind == PFK_PC_NOISY) return fail(PFK_ERR_ARG, "batches do not take the noisy preconditioner");
+  const bool global_inner = kind == kPcJacobiPcg || kind == kPcJacobiGmres;
+  if (global_inner && T->opts.persistent)
+    return fail(PFK_ERR_ARG, "the persistent form takes the NONE, JACOBI or BLOCK_JACOBI_PCG preconditioner");
+  const int fp32 = (kind == kPcBlockPcg || global_inner) && B->prec == PFK_FP32_BF16COEF;
   if (T->pc_kind >= 0 && (T->pc_kind != kind || T->fp32 != fp32 || T->dim != A->dim))
     return fail(PFK_ERR_ARG, "every member of a batch has the same dimension, preconditioner kind and precision");
+  if (global_inner && T->pc_kind >= 0 && T->pc_k != B->k)
+    return fail(PFK_ERR_ARG, "every member of a batch has the same number of inner steps");
   int s = -1;
   for (int i = 0; i < (int)T->mem.size() && s < 0; ++i)
     if (T->mem[i].state == 0) s = i;
@@ -2072,6 +2117,7 @@ extern "C" int pfk_batch_add(pfk_batch T, pfk_operator A, pfk_precond B, const d
   T->pc_kind = kind;
   T->fp32 = fp32;
   T->dim = A->dim;
+  T->pc_k = B->k;
   T->mem[s].S = S;
   T->mem[s].state = 1;
   T->mem[s].code = PFK_NOT_CONVERGED;
@@ -2243,7 +2289,7 @@ extern "C" int pfk_batch_remove(pfk_batch T, int slot) {
   T->dirty = true;
   bool any = false;
   for (auto& m : T->mem) any = any || m.state != 0;
-  if (!any) { T->pc_kind = -1; T->fp32 = -1; T->dim = 0; }
+  if (!any) { T->pc_kind = -1; T->fp32 = -1; T->dim = 0; T->pc_k = -1; }
   return PFK_OK;
 }
 
@@ -2359,7 +2405,7 @@ struct pfk_server_s {
   std::vector<long long> queue;               // FIFO of queued ids
   size_t qhead = 0;
   struct Bt {
-    int method, kind, fp32, dim;
+    int method, kind, fp32, dim, k;
     pfk_batch T;
     std::vector<long long> owner;             // request id per slot (-1 free)
     int active;
@@ -2399,8 +2445,7 @@ extern "C" int pfk_server_submit(pfk_server S, pfk_operator A, pfk_precond B, pf
   if (!S || !A || !B || !b || !x || !id) return fail(PFK_ERR_ARG, "null argument");
   if (!batch_method_ok(method)) return fail(PFK_ERR_ARG, "requests run PIPEFCG, FCG or PIPEFGMRES");
   if (B->A != A) return fail(PFK_ERR_ARG, "preconditioner was made for another operator");
-  if (B->kind != kPcNone && B->kind != kPcJacobi && B->kind != kPcBlockPcg)
-    return fail(PFK_ERR_ARG, "requests take the NONE, JACOBI or BLOCK_JACOBI_PCG preconditioner");
+  if (B->kind == PFK_PC_NOISY) return fail(PFK_ERR_ARG, "requests do not take the noisy preconditioner");
   if (maxit < 0 || !(rtol >= 0.0)) return fail(PFK_ERR_ARG, "bad rtol or maxit");
   pfk_server_s::Req r;
   r.A = A; r.B = B; r.method = method; r.b = b; r.x = x; r.rtol = rtol; r.maxit = maxit;
@@ -2423,18 +2468,21 @@ extern "C" int pfk_server_progress(pfk_server S, long long* completed, int cap, 
   // admission
   while (S->qhead < S->queue.size()) {
     auto& r = S->reqs[S->queue[S->qhead]];
-    const int fp32 = r.B->kind == kPcBlockPcg && r.B->prec == PFK_FP32_BF16COEF;
+    const int fp32 = r.B->kind >= kPcJacobiPcg && r.B->kind <= kPcBlockPcg && r.B->prec == PFK_FP32_BF16COEF;
     int bi = -1;
     for (int i = 0; i < (int)S->batches.size() && bi < 0; ++i) {
       const auto& bt = S->batches[i];
-      if (bt.method == r.method && bt.kind == r.B->kind && bt.fp32 == fp32 && bt.dim == r.A->dim) bi = i;
+      const bool global_inner = r.B->kind == kPcJacobiPcg || r.B->kind == kPcJacobiGmres;
+      if (bt.method == r.method && bt.kind == r.B->kind && bt.fp32 == fp32 && bt.dim == r.A->dim &&
+          (!global_inner || bt.k == r.B->k))
+        bi = i;
     }
     if (bi < 0) {
       pfk_solve_opts o;
       pfk_default_opts(&o);
       o.graph_iters = S->cfg.step_iters;
       o.use_graph = S->cfg.launch_direct ? 0 : 1;
-      pfk_server_s::Bt bt{r.method, r.B->kind, fp32, r.A->dim, nullptr, {}, 0};
+      pfk_server_s::Bt bt{r.method, r.B->kind, fp32, r.A->dim, r.B->k, nullptr, {}, 0};
       int rc = pfk_batch_create((pfk_method)r.method, S->cfg.mmax, S->cfg.max_active, S->stream, &o, &bt.T);
       if (rc) return rc;
       bt.owner.assign(S->cfg.max_active, -1);

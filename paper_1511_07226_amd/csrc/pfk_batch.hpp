@@ -26,7 +26,10 @@ struct BSys {
   int Pv, Ps;             // its vector / stencil workgroup counts
   int bj_wx, bj_wy, bj_n; // its block-preconditioner launch (workgroups along x, y; total)
   int pc_k;               // inner iterations
-  PcOutDesc pd;           // where B(v) comes from (input vectors and the block solve's output)
+  PcOutDesc pd;           // where B(v) comes from (input vectors, the inner solve's buffers)
+  void *pc_p0, *pc_p1;    // global inner solves' work vectors (arithmetic type of the inner sweeps):
+  void *pc_q, *pc_rho;    //   PCG directions, A p, residual; GMRES: pc_q holds w = A D^-1 V_j
+  double *part_pc0, *part_pc1;   // their partial sums
   Window P, S, Q, Z;      // direction windows (method-dependent roles, as in a single solve)
   double *x, *r, *u, *w, *m, *n, *z, *x0;
   double *part_main, *part_a, *part_b;
@@ -69,9 +72,114 @@ __global__ void __launch_bounds__(kBlock) kb_apply_pc_out(const BSys* sys, const
   const Blk bk{(int)blockIdx.x - off[s], d.Ps};
   if (bk.id >= bk.n) return;   // padding of the range
   if (pipefcg)
-    apply_pc_out_body(bk, d.g, d.sg, d.pd, d.u, 1.0, d.m, d.n, 0, nullptr, d.part_b, d.st);
+    apply_pc_out_body<true>(bk, d.g, d.sg, d.pd, d.u, 1.0, d.m, d.n, 0, nullptr, d.part_b, d.st);
   else
-    apply_pc_out_body(bk, d.g, d.sg, d.pd, nullptr, 0.0, nullptr, d.z, 0, nullptr, d.part_b, d.st);
+    apply_pc_out_body<true>(bk, d.g, d.sg, d.pd, nullptr, 0.0, nullptr, d.z, 0, nullptr, d.part_b, d.st);
+}
+
+// ---- the global inner solves of every system ----------------------------------
+// The same phases a single solve launches (pfk_pc.hpp), each over all members:
+// k-step Jacobi-PCG as A_1, then (B_j, A_{j+1}) for j < k; k-step right-Jacobi
+// GMRES as G0, then (GA_j, GD_j, GO_j) for j < k.  Every member of a batch has
+// the same inner kind, precision and step count k.  T: the inner arithmetic
+// (FP32 sweeps run on the BF16 viscosity copy).
+template <class T, class F>
+__device__ __forceinline__ void with_inner_grid(const BSys& d, F&& f) {
+  if constexpr (sizeof(T) == 4) f(d.gm);
+  else f(d.g);
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) kb_pcg_a1(const BSys* sys, const int* off, int nsys) {
+  const int s = batch_find(off, nsys, (int)blockIdx.x);
+  const BSys& d = sys[s];
+  const Blk bk{(int)blockIdx.x - off[s], d.Ps};
+  if (bk.id >= bk.n) return;   // padding of the range
+  const PcOutDesc& pd = d.pd;
+  with_inner_grid<T>(d, [&](const auto& g) {
+    pcg_a1_body<T>(bk, g, d.sg, (const T*)pd.dinv_in, pd.X1, pd.c1, pd.X2, pd.c2, (T*)d.pc_p0, (T*)d.pc_q,
+                   d.part_pc0, d.st);
+  });
+}
+
+// B_j: y += alpha p_j, rho -= alpha q (reads A_j's partials, PC0; writes PC1)
+template <class T>
+__global__ void __launch_bounds__(kBlock) kb_pcg_b(const BSys* sys, const int* off, int nsys, int j) {
+  const int s = batch_find(off, nsys, (int)blockIdx.x);
+  const BSys& d = sys[s];
+  const Blk bk{(int)blockIdx.x - off[s], d.Pv};
+  if (bk.id >= bk.n) return;   // padding of the range
+  const PcOutDesc& pd = d.pd;
+  const T* pj = (const T*)((j - 1) & 1 ? d.pc_p1 : d.pc_p0);
+  pcg_b_body<T>(bk, j, d.N, (const T*)pd.dinv_in, pd.X1, pd.c1, pd.X2, pd.c2, pj, (const T*)d.pc_q,
+                (T*)d.pc_rho, (T*)const_cast<void*>(pd.y), d.part_pc0, d.Ps, d.part_pc1, d.st);
+}
+
+// A_{j+1}: p_{j+1} = D^-1 rho + beta p_j, q = A p_{j+1} (reads PC1, writes PC0)
+template <class T>
+__global__ void __launch_bounds__(kBlock) kb_pcg_a(const BSys* sys, const int* off, int nsys, int j) {
+  const int s = batch_find(off, nsys, (int)blockIdx.x);
+  const BSys& d = sys[s];
+  const Blk bk{(int)blockIdx.x - off[s], d.Ps};
+  if (bk.id >= bk.n) return;   // padding of the range
+  const PcOutDesc& pd = d.pd;
+  const T* pj = (const T*)((j - 1) & 1 ? d.pc_p1 : d.pc_p0);
+  T* pn = (T*)(j & 1 ? d.pc_p1 : d.pc_p0);
+  with_inner_grid<T>(d, [&](const auto& g) {
+    pcg_a_body<T>(bk, j + 1, g, d.sg, (const T*)pd.dinv_in, (const T*)d.pc_rho, pj, pn, (T*)d.pc_q,
+                  d.part_pc1, d.Pv, d.part_pc0, d.st);
+  });
+}
+
+// G0: V_0 = v, partial ||v||^2 (PC0)
+template <class T>
+__global__ void __launch_bounds__(kBlock) kb_gmpc_start(const BSys* sys, const int* off, int nsys) {
+  const int s = batch_find(off, nsys, (int)blockIdx.x);
+  const BSys& d = sys[s];
+  const Blk bk{(int)blockIdx.x - off[s], d.Pv};
+  if (bk.id >= bk.n) return;   // padding of the range
+  const PcOutDesc& pd = d.pd;
+  gmpc_start_body<T>(bk, d.N, pd.k, pd.X1, pd.c1, pd.X2, pd.c2, (T*)const_cast<void*>(pd.vbase), d.part_pc0,
+                     d.st);
+}
+
+// GA_j: w = A D^-1 V_j (reads PC0).  Velocities are loaded where used in every
+// member (the load-ahead form of a single solve rounds alike).
+template <class T>
+__global__ void __launch_bounds__(kBlock) kb_gmpc_apply(const BSys* sys, const int* off, int nsys, int j) {
+  const int s = batch_find(off, nsys, (int)blockIdx.x);
+  const BSys& d = sys[s];
+  const Blk bk{(int)blockIdx.x - off[s], d.Ps};
+  if (bk.id >= bk.n) return;   // padding of the range
+  const PcOutDesc& pd = d.pd;
+  with_inner_grid<T>(d, [&](const auto& g) {
+    gmpc_apply_body<T, std::decay_t<decltype(g)>, false>(bk, j, g, d.sg, (const T*)pd.dinv_in,
+                                                        (const T*)pd.vbase, pd.ldv, (T*)d.pc_q, d.part_pc0,
+                                                        d.Pv, d.st);
+  });
+}
+
+// GD_j: partials <V_i, w> (PC1)
+template <class T>
+__global__ void __launch_bounds__(kBlock) kb_gmpc_dots(const BSys* sys, const int* off, int nsys, int j) {
+  const int s = batch_find(off, nsys, (int)blockIdx.x);
+  const BSys& d = sys[s];
+  const Blk bk{(int)blockIdx.x - off[s], d.Pv};
+  if (bk.id >= bk.n) return;   // padding of the range
+  const PcOutDesc& pd = d.pd;
+  gmpc_dots_body<T>(bk, j, d.N, (const T*)pd.vbase, pd.ldv, (const T*)d.pc_q, d.part_pc1, d.st);
+}
+
+// GO_j: V_{j+1} = w - sum h V_i, partial ||V_{j+1}||^2 (reads PC1, writes PC0)
+template <class T>
+__global__ void __launch_bounds__(kBlock) kb_gmpc_orth(const BSys* sys, const int* off, int nsys, int j) {
+  const int s = batch_find(off, nsys, (int)blockIdx.x);
+  const BSys& d = sys[s];
+  const Blk bk{(int)blockIdx.x - off[s], d.Pv};
+  if (bk.id >= bk.n) return;   // padding of the range
+  const PcOutDesc& pd = d.pd;
+  gmpc_orth_body<T>(bk, j, pd.k, d.N, (T*)const_cast<void*>(pd.vbase), pd.ldv, (const T*)d.pc_q, d.part_pc1,
+                    d.Pv, d.part_pc0, d.st);
 }
 
 // ---- the block-Jacobi inner solve of every system -----------------------------

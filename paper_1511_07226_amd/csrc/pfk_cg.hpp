@@ -193,6 +193,9 @@ __device__ __forceinline__ void apply_pc_out_t(Blk bk, const Grid& g, const Sten
 }
 // The inner solve's output kind and storage are fixed per instantiation for
 // the two inner-CG forms (the hot cases); the others decide at run time.
+// GM: the run-time branch also carries the FP32 inner-GMRES load-ahead path
+// (more registers; the phased batched kernel takes it, the persistent one not).
+template <bool GM = false>
 __device__ __forceinline__ void apply_pc_out_body(Blk bk, Grid g, StencilGeom sg, PcOutDesc pd, const double* X3,
                                                   double c3, double* __restrict__ O, double* __restrict__ Nout,
                                                   int dots, const double* __restrict__ R, double* part,
@@ -205,7 +208,7 @@ __device__ __forceinline__ void apply_pc_out_body(Blk bk, Grid g, StencilGeom sg
     if (pd.fp32) apply_pc_out_t<kPcJacobiPcg, 1>(bk, g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
     else apply_pc_out_t<kPcJacobiPcg, 0>(bk, g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
   } else {
-    apply_pc_out_t<-1, 0>(bk, g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
+    apply_pc_out_t<-1, 0, GM>(bk, g, sg, pd, X3, c3, O, Nout, dots, R, part, st);
   }
 }
 // The single-system kernel: one instantiation per output kind and storage

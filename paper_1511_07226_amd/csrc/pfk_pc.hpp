@@ -238,8 +238,7 @@ __device__ __forceinline__ auto gm_raw_in(const PcOut& pc, const double* X3, dou
 
 // ---- A_1: p_1 = D^-1 v, q = A p_1 -------------------------------------------
 template <class T, class G>
-__global__ void __launch_bounds__(kBlock)
-k_pcg_a1(G g, StencilGeom sg, const T* __restrict__ dinv,
+__device__ __forceinline__ void pcg_a1_body(Blk bk, G g, StencilGeom sg, const T* __restrict__ dinv,
          const double* X1, double c1, const double* X2, double c2,
          T* __restrict__ pout, T* __restrict__ qout,
          double* part, const SolveState* st) {
@@ -266,14 +265,21 @@ k_pcg_a1(G g, StencilGeom sg, const T* __restrict__ dinv,
     acc[0] += (double)pc * (double)q;
     acc[1] += (double)V(idx) * (double)pc;
   };
-  stencil_march<T>(g, sg, in, sink);
-  block_partials<2>(acc, 2, part, sg.blocks());
+  stencil_march<T>(g, sg, bk.id, in, sink);
+  block_partials<2>(acc, 2, part, bk.n, bk.id);
+}
+template <class T, class G>
+__global__ void __launch_bounds__(kBlock)
+k_pcg_a1(G g, StencilGeom sg, const T* __restrict__ dinv,
+         const double* X1, double c1, const double* X2, double c2,
+         T* __restrict__ pout, T* __restrict__ qout,
+         double* part, const SolveState* st) {
+  pcg_a1_body(this_blk(), g, sg, dinv, X1, c1, X2, c2, pout, qout, part, st);
 }
 
 // ---- B_j (1 <= j < k): y += alpha p, rho -= alpha q, partial <rho, D^-1 rho> --
 template <class T>
-__global__ void __launch_bounds__(kBlock)
-k_pcg_b(int jstep, long long N, const T* __restrict__ dinv,
+__device__ __forceinline__ void pcg_b_body(Blk bk, int jstep, long long N, const T* __restrict__ dinv,
         const double* X1, double c1, const double* X2, double c2,
         const T* __restrict__ p, const T* __restrict__ q,
         T* __restrict__ rho, T* __restrict__ y,
@@ -292,7 +298,7 @@ k_pcg_b(int jstep, long long N, const T* __restrict__ dinv,
   }
   stopped = stopped || !(pq > 0.0);
   const T alpha = T(stopped ? 0.0 : gj / pq);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (bk.id == 0 && threadIdx.x == 0) {
     if (jstep == 1) pcs->gamma[1] = gj;
     pcs->stopped[jstep] = stopped;
   }
@@ -323,7 +329,7 @@ k_pcg_b(int jstep, long long N, const T* __restrict__ dinv,
       acc[0] += (double)r * (double)(dv * r);
     };
     const long long nv = N / VW;
-    for (long long qv = gtid(); qv < nv; qv += gstride()) {
+    for (long long qv = bk.gtid(); qv < nv; qv += bk.gstride()) {
       const long long e = qv * VW;
       tv_t r, yv;
       if (jstep == 1) {
@@ -358,7 +364,7 @@ k_pcg_b(int jstep, long long N, const T* __restrict__ dinv,
       sto(reinterpret_cast<tv_t*>(y + e), yo);
       sto(reinterpret_cast<tv_t*>(rho + e), ro);
     }
-    for (long long e = nv * VW + gtid(); e < N; e += gstride()) {
+    for (long long e = nv * VW + bk.gtid(); e < N; e += bk.gstride()) {
       T r, yv;
       if (jstep == 1) {
         double rv = c1 * ld(X1 + e);
@@ -379,13 +385,21 @@ k_pcg_b(int jstep, long long N, const T* __restrict__ dinv,
   };
   if (st->nt) sweep(std::true_type{});
   else sweep(std::false_type{});
-  block_partials<1>(acc, 1, part_out, gridDim.x);
+  block_partials<1>(acc, 1, part_out, bk.n, bk.id);
+}
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+k_pcg_b(int jstep, long long N, const T* __restrict__ dinv,
+        const double* X1, double c1, const double* X2, double c2,
+        const T* __restrict__ p, const T* __restrict__ q,
+        T* __restrict__ rho, T* __restrict__ y,
+        const double* part_in, int P_in, double* part_out, SolveState* st) {
+  pcg_b_body(this_blk(), jstep, N, dinv, X1, c1, X2, c2, p, q, rho, y, part_in, P_in, part_out, st);
 }
 
 // ---- A_j (2 <= j <= k): p_j = D^-1 rho + beta p_{j-1}, q = A p_j -------------
 template <class T, class G>
-__global__ void __launch_bounds__(kBlock)
-k_pcg_a(int jstep, G g, StencilGeom sg, const T* __restrict__ dinv,
+__device__ __forceinline__ void pcg_a_body(Blk bk, int jstep, G g, StencilGeom sg, const T* __restrict__ dinv,
         const T* __restrict__ rho, const T* __restrict__ pprev,
         T* __restrict__ pout, T* __restrict__ qout,
         const double* part_in, int P_in, double* part_out, SolveState* st) {
@@ -395,7 +409,7 @@ k_pcg_a(int jstep, G g, StencilGeom sg, const T* __restrict__ dinv,
   const double gprev = pcs->gamma[jstep - 1];
   const int stopped = pcs->stopped[jstep - 1];
   const T beta = T((stopped || gprev == 0.0) ? 0.0 : gj / gprev);
-  if (blockIdx.x == 0 && threadIdx.x == 0) pcs->gamma[jstep] = gj;
+  if (bk.id == 0 && threadIdx.x == 0) pcs->gamma[jstep] = gj;
   double acc[1] = {0.0};
   struct Raw { T d, r, p; };
   const auto in = stencil_in([&](long long t) { return Raw{dinv[t], rho[t], pprev[t]}; },
@@ -405,41 +419,53 @@ k_pcg_a(int jstep, G g, StencilGeom sg, const T* __restrict__ dinv,
     qout[idx] = q;
     acc[0] += (double)pc * (double)q;
   };
-  stencil_march<T>(g, sg, in, sink);
-  block_partials<1>(acc, 1, part_out, sg.blocks());
+  stencil_march<T>(g, sg, bk.id, in, sink);
+  block_partials<1>(acc, 1, part_out, bk.n, bk.id);
+}
+template <class T, class G>
+__global__ void __launch_bounds__(kBlock)
+k_pcg_a(int jstep, G g, StencilGeom sg, const T* __restrict__ dinv,
+        const T* __restrict__ rho, const T* __restrict__ pprev,
+        T* __restrict__ pout, T* __restrict__ qout,
+        const double* part_in, int P_in, double* part_out, SolveState* st) {
+  pcg_a_body(this_blk(), jstep, g, sg, dinv, rho, pprev, pout, qout, part_in, P_in, part_out, st);
 }
 
 // ---- inner GMRES -----------------------------------------------------------
 // G0: V_0 = v (stored unnormalised), partial ||v||^2.
 template <class T>
-__global__ void __launch_bounds__(kBlock)
-k_gmpc_start(long long N, int k, const double* X1, double c1, const double* X2, double c2,
+__device__ __forceinline__ void gmpc_start_body(Blk bk, long long N, int k, const double* X1, double c1, const double* X2, double c2,
              T* __restrict__ V0, double* part_out, SolveState* st) {
   if (!wg_running(st)) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) st->pc.ncol = k;
+  if (bk.id == 0 && threadIdx.x == 0) st->pc.ncol = k;
   double acc[1] = {0.0};
-  for (long long e = gtid(); e < N; e += gstride()) {
+  for (long long e = bk.gtid(); e < N; e += bk.gstride()) {
     double v = c1 * X1[e];
     if (X2 != nullptr) v += c2 * X2[e];
     const T vt = T(v);
     V0[e] = vt;
     acc[0] += (double)vt * (double)vt;
   }
-  block_partials<1>(acc, 1, part_out, gridDim.x);
+  block_partials<1>(acc, 1, part_out, bk.n, bk.id);
+}
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+k_gmpc_start(long long N, int k, const double* X1, double c1, const double* X2, double c2,
+             T* __restrict__ V0, double* part_out, SolveState* st) {
+  gmpc_start_body(this_blk(), N, k, X1, c1, X2, c2, V0, part_out, st);
 }
 
 // GA_j: scale of V_j from the previous norm (a zero norm ends the cycle:
 // beta = 0 gives B(v) = 0, a zero subdiagonal is a happy breakdown), then
 // w = A D^-1 V_j and partials <stored V_i, w> for i <= j.
 template <class T, class G, bool CV = false>
-__global__ void __launch_bounds__(kBlock)
-k_gmpc_apply(int jstep, G g, StencilGeom sg, const T* __restrict__ dinv, const T* Vbase,
+__device__ __forceinline__ void gmpc_apply_body(Blk bk, int jstep, G g, StencilGeom sg, const T* __restrict__ dinv, const T* Vbase,
              long long ldv, T* __restrict__ w, const double* part_in, int P_in, SolveState* st) {
   if (!wg_running(st)) return;
   PcScalars* pcs = &st->pc;
   if (jstep >= pcs->ncol) return;
   const double nrm = sqrt(block_sum_column(part_in, P_in, 0));
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (bk.id == 0 && threadIdx.x == 0) {
     if (jstep == 0) pcs->beta0 = nrm;
     else pcs->h[(jstep - 1) * (kMaxInner + 1) + jstep] = nrm;
     pcs->vs[jstep] = nrm == 0.0 ? 0.0 : 1.0 / nrm;
@@ -452,15 +478,20 @@ k_gmpc_apply(int jstep, G g, StencilGeom sg, const T* __restrict__ dinv, const T
   const auto in = stencil_in([&](long long t) { return Raw{dinv[t], Vj[t]}; },
                              [&](const Raw& q) { return q.d * (sj * q.v); });
   auto sink = [&](long long idx, T, T Au) { w[idx] = Au; };
-  stencil_march<T, CV>(g, sg, in, sink);
+  stencil_march<T, CV>(g, sg, bk.id, in, sink);
+}
+template <class T, class G, bool CV = false>
+__global__ void __launch_bounds__(kBlock)
+k_gmpc_apply(int jstep, G g, StencilGeom sg, const T* __restrict__ dinv, const T* Vbase,
+             long long ldv, T* __restrict__ w, const double* part_in, int P_in, SolveState* st) {
+  gmpc_apply_body<T, G, CV>(this_blk(), jstep, g, sg, dinv, Vbase, ldv, w, part_in, P_in, st);
 }
 
 // GD_j: partials <stored V_i, w> for i <= j.  A streaming pass of its own:
 // taken in the stencil's sink these loads would sit outside the stencil's
 // one-plane-ahead prefetch (measured: 2.1 TB/s for the fused kernel).
 template <class T>
-__global__ void __launch_bounds__(kBlock)
-k_gmpc_dots(int jstep, long long N, const T* Vbase, long long ldv, const T* __restrict__ w, double* part_out,
+__device__ __forceinline__ void gmpc_dots_body(Blk bk, int jstep, long long N, const T* Vbase, long long ldv, const T* __restrict__ w, double* part_out,
             SolveState* st) {
   if (!wg_running(st)) return;
   if (jstep >= st->pc.ncol) return;
@@ -472,7 +503,7 @@ k_gmpc_dots(int jstep, long long N, const T* Vbase, long long ldv, const T* __re
   constexpr int VW = 16 / sizeof(T);
   typedef T vec_t __attribute__((ext_vector_type(VW)));
   const long long nv = N / VW;
-  for (long long qv = gtid(); qv < nv; qv += gstride()) {
+  for (long long qv = bk.gtid(); qv < nv; qv += bk.gstride()) {
     const long long e = qv * VW;
     const vec_t wv = *reinterpret_cast<const vec_t*>(w + e);
 #pragma unroll
@@ -484,20 +515,25 @@ k_gmpc_dots(int jstep, long long N, const T* Vbase, long long ldv, const T* __re
       }
     }
   }
-  for (long long e = nv * VW + gtid(); e < N; e += gstride()) {
+  for (long long e = nv * VW + bk.gtid(); e < N; e += bk.gstride()) {
     const double wv = (double)w[e];
 #pragma unroll
     for (int q = 0; q < kMaxInnerGmres; ++q)
       if (q <= jstep) acc[q] += (double)Vbase[(long long)q * ldv + e] * wv;
   }
-  block_partials<kMaxInnerGmres>(acc, jstep + 1, part_out, gridDim.x);
+  block_partials<kMaxInnerGmres>(acc, jstep + 1, part_out, bk.n, bk.id);
+}
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+k_gmpc_dots(int jstep, long long N, const T* Vbase, long long ldv, const T* __restrict__ w, double* part_out,
+            SolveState* st) {
+  gmpc_dots_body(this_blk(), jstep, N, Vbase, ldv, w, part_out, st);
 }
 
 // GO_j: h_ij = <V_i, w> (classical Gram-Schmidt), V_{j+1} = w - sum h_ij V_i
 // stored unnormalised (not stored for the last step), partial ||V_{j+1}||^2.
 template <class T>
-__global__ void __launch_bounds__(kBlock)
-k_gmpc_orth(int jstep, int k, long long N, T* Vbase, long long ldv, const T* __restrict__ w,
+__device__ __forceinline__ void gmpc_orth_body(Blk bk, int jstep, int k, long long N, T* Vbase, long long ldv, const T* __restrict__ w,
             const double* part_in, int P_in, double* part_out, SolveState* st) {
   if (!wg_running(st)) return;
   PcScalars* pcs = &st->pc;
@@ -507,7 +543,7 @@ k_gmpc_orth(int jstep, int k, long long N, T* Vbase, long long ldv, const T* __r
     const double hq = pcs->vs[q] * block_sum_column(part_in, P_in, q);
     if (threadIdx.x == 0) {
       coef[q] = hq * pcs->vs[q];
-      if (blockIdx.x == 0) pcs->h[jstep * (kMaxInner + 1) + q] = hq;
+      if (bk.id == 0) pcs->h[jstep * (kMaxInner + 1) + q] = hq;
     }
   }
   __syncthreads();
@@ -518,7 +554,7 @@ k_gmpc_orth(int jstep, int k, long long N, T* Vbase, long long ldv, const T* __r
   constexpr int VW = 16 / sizeof(T);
   typedef T vec_t __attribute__((ext_vector_type(VW)));
   const long long nv = N / VW;
-  for (long long qv = gtid(); qv < nv; qv += gstride()) {
+  for (long long qv = bk.gtid(); qv < nv; qv += bk.gstride()) {
     const long long e = qv * VW;
     vec_t v = *reinterpret_cast<const vec_t*>(w + e);
     for (int q = 0; q <= jstep; ++q) {
@@ -531,13 +567,19 @@ k_gmpc_orth(int jstep, int k, long long N, T* Vbase, long long ldv, const T* __r
 #pragma unroll
     for (int l = 0; l < VW; ++l) acc[0] += (double)v[l] * (double)v[l];
   }
-  for (long long e = nv * VW + gtid(); e < N; e += gstride()) {
+  for (long long e = nv * VW + bk.gtid(); e < N; e += bk.gstride()) {
     T v = w[e];
     for (int q = 0; q <= jstep; ++q) v -= T(coef[q]) * Vbase[(long long)q * ldv + e];
     if (store) Vn[e] = v;
     acc[0] += (double)v * (double)v;
   }
-  block_partials<1>(acc, 1, part_out, gridDim.x);
+  block_partials<1>(acc, 1, part_out, bk.n, bk.id);
+}
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+k_gmpc_orth(int jstep, int k, long long N, T* Vbase, long long ldv, const T* __restrict__ w,
+            const double* part_in, int P_in, double* part_out, SolveState* st) {
+  gmpc_orth_body(this_blk(), jstep, k, N, Vbase, ldv, w, part_in, P_in, part_out, st);
 }
 
 // ---- block-Jacobi PCG ------------------------------------------------------

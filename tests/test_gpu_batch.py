@@ -110,20 +110,62 @@ def test_members_identical_to_single_solves(pfk, case, persistent, capacity):
     T.close()
 
 
-@pytest.mark.parametrize("method,conv", [("pipefcg", False), ("fcg", False), ("pipefgmres", True)])
-def test_batch_member_follows_oracle(pfk, method, conv):
-    _say("batch oracle", method)
+# the global inner solves (Jacobi-PCG, Jacobi-GMRES) run phase by phase over
+# all members, in the phased form only
+GLOBAL_CASES = [("pipefgmres", "jacobi_gmres", 1, True), ("pipefgmres", "jacobi_gmres", 0, True),
+                ("pipefcg", "jacobi_pcg", 0, False), ("fcg", "jacobi_pcg", 1, False),
+                ("fcg", "jacobi_gmres", 1, False)]
+
+
+@pytest.mark.parametrize("case", GLOBAL_CASES,
+                         ids=[f"{m}-{k}-{'mixed' if p else 'fp64'}" for m, k, p, _ in GLOBAL_CASES])
+def test_global_inner_members_identical_to_single_solves(pfk, case):
+    method, kind, prec, conv = case
+    _say("batch identity, global inner solve", case)
+    mem = _members(pfk, kind, prec, conv, tilings=[(64, 2048, 32), (32, 64, 7), (64, 5, 100)])
+    singles = []
+    for p, A, B in mem:
+        x = _dev(np.zeros(A.N))
+        info = pfk.solve(A, B, method, _dev(p.b), x, rtol=1e-8, maxit=600, mmax=20)
+        singles.append((info, _host(x)))
+    T = pfk.Batch(method, mmax=20, capacity=8, graph_iters=5)
+    xs, slots = {}, {}
+    for i, (p, A, B) in enumerate(mem):
+        xs[i] = _dev(np.zeros(A.N))
+        slots[i] = T.add(A, B, _dev(p.b), xs[i], rtol=1e-8, maxit=600)
+    running, steps = len(slots), 0
+    while running:
+        T.step(5)
+        _, running = T.poll()
+        steps += 1
+        assert steps < 1000
+    for i, s in slots.items():
+        info = T.info(s)
+        ref, xref = singles[i]
+        assert info.status == ref.status and info.iterations == ref.iterations, (i, info, ref)
+        assert np.array_equal(info.history, ref.history), i
+        assert np.array_equal(_host(xs[i]), xref), i
+    T.close()
+
+
+@pytest.mark.parametrize("method,conv,kind,k", [("pipefcg", False, "block_jacobi_pcg", 4),
+                                                ("fcg", False, "block_jacobi_pcg", 4),
+                                                ("pipefgmres", True, "block_jacobi_pcg", 4),
+                                                ("pipefgmres", True, "jacobi_gmres", 5),
+                                                ("fcg", False, "jacobi_pcg", 4)])
+def test_batch_member_follows_oracle(pfk, method, conv, kind, k):
+    _say("batch oracle", method, kind, k)
     p = gen.make_problem(3, 19, 6, 3.0, seed=9, convection=conv)
     Ao = oracle.StencilOperator(3, 19, p.eta, p.vel)
-    Bo = oracle.make_pc("block_jacobi_pcg", Ao, 4, block=8)
+    Bo = oracle.make_pc(kind, Ao, k, block=8)
     sigma = oracle.estimate_sigma(Ao.apply, Bo, Ao.N) if method == "pipefgmres" else None
     ref = oracle.solve(method, Ao, Bo, p.b, rtol=0.0, maxit=20, nu_max=20, sigma=sigma)
     other = gen.make_problem(3, 11, 2, 2.0, seed=3, convection=conv)
     T = pfk.Batch(method, mmax=20, capacity=4, **({"shift_sigma": float(sigma)} if sigma else {}))
     A = pfk.Operator(3, 19, p.eta, p.vel)
-    B = pfk.Precond(A, "block_jacobi_pcg", 4, block=8)
+    B = pfk.Precond(A, kind, k, block=8)
     A2 = pfk.Operator(3, 11, other.eta, other.vel)
-    B2 = pfk.Precond(A2, "block_jacobi_pcg", 4, block=8)
+    B2 = pfk.Precond(A2, kind, k, block=8)
     x, x2 = _dev(np.zeros(A.N)), _dev(np.zeros(A2.N))
     s = T.add(A, B, _dev(p.b), x, rtol=0.0, maxit=20)
     T.add(A2, B2, _dev(other.b), x2, rtol=0.0, maxit=20)
@@ -145,9 +187,20 @@ def test_batch_edge_cases(pfk):
     B = pfk.Precond(A, "block_jacobi_pcg", 4, block=8)
     Bm = pfk.Precond(A, "block_jacobi_pcg", 4, precision=pfk.FP32_BF16COEF, block=8)
     Bg = pfk.Precond(A, "jacobi_pcg", 4)
+    Bg3 = pfk.Precond(A, "jacobi_pcg", 3)
+    Bn = pfk.Precond(A, "noisy", eta=0.1, seed=1)
+    Tp = pfk.Batch("pipefcg", mmax=10, capacity=2, persistent=1)
+    with pytest.raises(RuntimeError):
+        Tp.add(A, Bg, _dev(p.b), _dev(np.zeros(A.N)))         # the persistent form has no global inner solve
+    Tp.close()
+    Tg = pfk.Batch("pipefcg", mmax=10, capacity=2)
+    Tg.add(A, Bg, _dev(p.b), _dev(np.zeros(A.N)), rtol=1e-8)
+    with pytest.raises(RuntimeError):
+        Tg.add(A, Bg3, _dev(p.b), _dev(np.zeros(A.N)))        # another inner step count
+    Tg.close()
     T = pfk.Batch("pipefcg", mmax=10, capacity=2)
     with pytest.raises(RuntimeError):
-        T.add(A, Bg, _dev(p.b), _dev(np.zeros(A.N)))          # global inner CG is not batched
+        T.add(A, Bn, _dev(p.b), _dev(np.zeros(A.N)))          # the noisy preconditioner is not batched
     x0 = _dev(np.ones(A.N))
     s0 = T.add(A, B, _dev(np.zeros(A.N)), x0, rtol=1e-8)      # b = 0: x = 0 at once
     with pytest.raises(RuntimeError):

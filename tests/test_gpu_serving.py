@@ -39,7 +39,10 @@ def _host(t):
     return t.cpu().numpy()
 
 
-def _requests(pfk, count, seed=0):
+def _requests(pfk, count, seed=0, mix="block"):
+    # mix "block": both methods with the block-Jacobi PCG (4 steps); mix
+    # "gmres": PIPEFGMRES requests with the global right-Jacobi GMRES(5)
+    # inner solve, as in the serving configuration; all FP32/BF16 inner sweeps
     rng = np.random.default_rng(seed)
     out = []
     for i in range(count):
@@ -47,15 +50,20 @@ def _requests(pfk, count, seed=0):
         method = "pipefcg" if i % 2 == 0 else "pipefgmres"
         p = gen.make_problem(3, n, 6, (1.0, 4.0), seed=500 + i)
         A = pfk.Operator(3, n, p.eta)
-        B = pfk.Precond(A, "block_jacobi_pcg", 4, precision=pfk.FP32_BF16COEF, block=8)
+        if mix == "gmres" and method == "pipefgmres":
+            B = pfk.Precond(A, "jacobi_gmres", 5, precision=pfk.FP32_BF16COEF)
+        else:
+            B = pfk.Precond(A, "block_jacobi_pcg", 4, precision=pfk.FP32_BF16COEF, block=8)
         rtol = 1e-6 if rng.random() < 0.5 else 1e-8
         out.append(dict(p=p, A=A, B=B, method=method, rtol=rtol))
     return out
 
 
-def test_alone_vs_mix_identical(pfk):
-    _say("serving alone vs mix")
-    reqs = _requests(pfk, 12)
+@pytest.mark.parametrize("mix,direct", [("block", False), ("gmres", False), ("gmres", True)],
+                         ids=["block", "gmres", "gmres-direct"])
+def test_alone_vs_mix_identical(pfk, mix, direct):
+    _say("serving alone vs mix", mix, "direct launches" if direct else "graphs")
+    reqs = _requests(pfk, 12, mix=mix)
     alone = []
     for r in reqs:
         x = _dev(np.zeros(r["A"].N))
@@ -65,7 +73,7 @@ def test_alone_vs_mix_identical(pfk):
     import paper_1511_07226_amd as m
     per = [m.workspace_bytes(r["A"], r["B"], r["method"], 20, 1500) for r in reqs]
     budget = 3 * max(per)
-    srv = pfk.Server(hbm_budget=budget, max_active=4, step_iters=5, mmax=20)
+    srv = pfk.Server(hbm_budget=budget, max_active=4, step_iters=5, mmax=20, launch_direct=direct)
     xs, ids, done = {}, {}, set()
     max_active = 0
     # arrivals: half up front, the rest one per round
@@ -111,5 +119,5 @@ def test_submit_errors(pfk):
     with pytest.raises(RuntimeError):
         srv.submit(A, B, "gcr", _dev(p.b), _dev(np.zeros(A.N)))
     with pytest.raises(RuntimeError):
-        srv.submit(A, pfk.Precond(A, "jacobi_pcg", 3), "pipefcg", _dev(p.b), _dev(np.zeros(A.N)))
+        srv.submit(A, pfk.Precond(A, "noisy", eta=0.1, seed=1), "pipefcg", _dev(p.b), _dev(np.zeros(A.N)))
     srv.close()
