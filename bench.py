@@ -347,7 +347,7 @@ def batched_bench(pfk, torch, steps, warmup, count=64):
     return out
 
 
-def serving_bench(pfk, torch, nreq=400, seed=0, loads=(0.5, 0.9)):
+def serving_bench(pfk, torch, nreq=400, seed=0, loads=(0.5, 0.9), direct=False, per_batch=64):
     """Configuration 5: Poisson arrivals of PIPEFCG / PIPEFGMRES requests (50/50)
     on 3D sinker grids, edge lognormal (median 40, sigma_ln 0.5) clipped to
     16..128, contrast 10^U(1,4), rtol 1e-6 or 1e-8, admitted by a memory
@@ -381,7 +381,7 @@ def serving_bench(pfk, torch, nreq=400, seed=0, loads=(0.5, 0.9)):
     NU_SERVE = 60
 
     def run(arrivals):
-        srv = pfk.Server(hbm_budget=budget, max_active=64, step_iters=8, mmax=NU_SERVE)
+        srv = pfk.Server(hbm_budget=budget, max_active=per_batch, step_iters=8, mmax=NU_SERVE, launch_direct=direct)
         xs = [torch.zeros_like(r["b"]) for r in reqs]
         ids, lat, conv = {}, [], 0
         by_method, failed = {}, []
@@ -414,6 +414,8 @@ def serving_bench(pfk, torch, nreq=400, seed=0, loads=(0.5, 0.9)):
                                    "iterations": info.iterations, "status": info.status_name,
                                    "true_rel": float(f"{info.true_rel_resid:.3e}")})
                 done += 1
+                if done % 250 == 0:
+                    log(f"serving: {done} of {len(reqs)} requests done at {t:.1f} s")
         total = time.perf_counter() - t0
         srv.close()
         lat = np.sort(np.array(lat))
@@ -427,7 +429,8 @@ def serving_bench(pfk, torch, nreq=400, seed=0, loads=(0.5, 0.9)):
     cap = run(np.zeros(nreq))
     out = {"workload": f"{nreq} requests, edge lognormal(40, 0.5) in 16..128, PIPEFCG/PIPEFGMRES 50/50, "
                        f"rtol 1e-6/1e-8, window/restart {NU_SERVE}, maxit {MAXIT}; PIPEFGMRES: GMRES(5), PIPEFCG: "
-                       "block-Jacobi PCG (4), FP32/BF16 inner; budget 48 GiB, 64 per batch",
+                       f"block-Jacobi PCG (4), FP32/BF16 inner; budget 48 GiB, {per_batch} per batch" +
+                       (", direct launches" if direct else ", graphs"),
            "edge_median": int(np.median([r["n"] for r in reqs])), "burst": cap, "poisson": {}}
     for f in loads:
         rate = f * cap["converged_solves_per_s"]
@@ -679,6 +682,9 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=400)
     ap.add_argument("--serving-loads", default="0.5,0.9",
                     help="Poisson offered loads as fractions of the measured capacity")
+    ap.add_argument("--serving-per-batch", type=int, default=64, help="members per serving batch")
+    ap.add_argument("--serving-direct", action="store_true",
+                    help="serving batches launch kernels directly instead of replaying graphs")
     ap.add_argument("--no-stagnation", action="store_true")
     ap.add_argument("--conv-diff-only", action="store_true",
                     help="headline plus the 256^3 convection-diffusion comparison")
@@ -766,7 +772,8 @@ def main():
     loads = tuple(float(v) for v in args.serving_loads.split(",") if v)
     if args.serving_only:
         args.headline_only = True
-        extra["serving"] = serving_bench(pfk, torch, nreq=args.serving_requests, loads=loads)
+        extra["serving"] = serving_bench(pfk, torch, nreq=args.serving_requests, loads=loads,
+                                         direct=args.serving_direct, per_batch=args.serving_per_batch)
     if not args.headline_only:
         # unpipelined baseline with a blocking (host-synchronised) reduction
         log("timing fcg host-sync")
@@ -824,7 +831,8 @@ def main():
         torch.cuda.empty_cache()
     if not args.headline_only and not args.no_serving:
         log("serving workload")
-        extra["serving"] = serving_bench(pfk, torch, nreq=args.serving_requests, loads=loads)
+        extra["serving"] = serving_bench(pfk, torch, nreq=args.serving_requests, loads=loads,
+                                         direct=args.serving_direct, per_batch=args.serving_per_batch)
 
     cpu = None
     if not args.no_cpu_baseline:
