@@ -241,7 +241,7 @@ def size_sweep(pfk, torch, steps=40):
     return out
 
 
-def batched_bench(pfk, torch, steps, warmup, count=64):
+def batched_bench(pfk, torch, steps, warmup, count=64, solve=True):
     """Configuration 4: 64 uneven SPD systems (edge 32..96, contrast 1e2..1e4),
     PIPEFCG nu_max 20 with the block-Jacobi inner solve (4 steps, FP32 on BF16
     viscosity), advanced by shared launches.  Tiling per size from the
@@ -255,6 +255,7 @@ def batched_bench(pfk, torch, steps, warmup, count=64):
     # residual stalls near 1e-7 with FP32 inner sweeps until a residual-gap
     # restart) reach the tolerance
     MAXIT4 = 20000
+    STALL4 = 200        # stagnation restarts, as for serving
     probs = gen.batched_problems(count, seed=0)
     mem = []
     for p in probs:
@@ -318,12 +319,15 @@ def batched_bench(pfk, torch, steps, warmup, count=64):
     per_unknown = (4 * NU4 + 14) * 8 + (2 * 8 + 2 + 4) + (8 + 4 + 8 + 2 * 8)
     out["algorithmic_GBps_pipefcg"] = round(per_unknown * total_n * out["pipefcg_batch_iters_per_s"] / 1e9, 1)
     out["algorithmic_bytes_per_unknown_iteration"] = per_unknown
+    if not solve:
+        return out
     log("batched pipefcg: solving all systems to rtol 1e-8")
     xs = [torch.zeros_like(b) for b in bs]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     code, infos = pfk.solve_batched([A for _, A, _ in mem], [B for _, _, B in mem], "pipefcg", bs, xs,
-                                    rtol=1e-8, maxit=MAXIT4, mmax=NU4, graph_iters=10)
+                                    rtol=1e-8, maxit=MAXIT4, mmax=NU4, graph_iters=10, stall_window=STALL4,
+                                    max_restarts=100)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     its = [i.iterations for i in infos]
@@ -333,7 +337,8 @@ def batched_bench(pfk, torch, steps, warmup, count=64):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, infp = pfk.solve_batched([A for _, A, _ in mem], [B for _, _, B in mem], "pipefcg", bs, xp,
-                                rtol=1e-8, maxit=MAXIT4, mmax=NU4, graph_iters=10, persistent=1)
+                                rtol=1e-8, maxit=MAXIT4, mmax=NU4, graph_iters=10, persistent=1,
+                                stall_window=STALL4, max_restarts=100)
     torch.cuda.synchronize()
     dtp = time.perf_counter() - t0
     out["time_to_solution_persistent"] = {"seconds": round(dtp, 3),
@@ -379,9 +384,15 @@ def serving_bench(pfk, torch, nreq=400, seed=0, loads=(0.5, 0.9), direct=False, 
     # PIPEFCG with the FP32 inner sweeps and a full 30-direction window -- while
     # 60 converges them (measured per request against 10, 20, 40, 50)
     NU_SERVE = 60
+    # stagnation restarts (window 200): PIPEFCG with the FP32 inner sweeps can
+    # stall at a floor that scales with ||A|| ||B|| on high-contrast requests
+    # (section 2.2.1's noise effect, the noise being FP32 rounding); a restart
+    # from the current x rebuilds the recurrences there
+    STALL = 200
 
     def run(arrivals):
-        srv = pfk.Server(hbm_budget=budget, max_active=per_batch, step_iters=8, mmax=NU_SERVE, launch_direct=direct)
+        srv = pfk.Server(hbm_budget=budget, max_active=per_batch, step_iters=8, mmax=NU_SERVE, launch_direct=direct,
+                         stall_window=STALL, max_restarts=100)
         xs = [torch.zeros_like(r["b"]) for r in reqs]
         ids, lat, conv = {}, [], 0
         by_method, failed = {}, []
@@ -428,7 +439,8 @@ def serving_bench(pfk, torch, nreq=400, seed=0, loads=(0.5, 0.9), direct=False, 
     log(f"serving: {nreq} requests arriving at once (capacity)")
     cap = run(np.zeros(nreq))
     out = {"workload": f"{nreq} requests, edge lognormal(40, 0.5) in 16..128, PIPEFCG/PIPEFGMRES 50/50, "
-                       f"rtol 1e-6/1e-8, window/restart {NU_SERVE}, maxit {MAXIT}; PIPEFGMRES: GMRES(5), PIPEFCG: "
+                       f"rtol 1e-6/1e-8, window/restart {NU_SERVE}, maxit {MAXIT}, stagnation restarts (window "
+                       f"{STALL}); PIPEFGMRES: GMRES(5), PIPEFCG: "
                        f"block-Jacobi PCG (4), FP32/BF16 inner; budget 48 GiB, {per_batch} per batch" +
                        (", direct launches" if direct else ", graphs"),
            "edge_median": int(np.median([r["n"] for r in reqs])), "burst": cap, "poisson": {}}
@@ -676,6 +688,8 @@ def main():
     ap.add_argument("--batched-only", action="store_true",
                     help="time only the batched workload (after the headline pair)")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-batched-solve", action="store_true",
+                    help="with --batched-only: steady-state timing only, no solve to tolerance")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-only", action="store_true",
                     help="headline pair plus the serving workload (with --serving-requests / --serving-loads)")
@@ -762,7 +776,7 @@ def main():
     extra = {}
     if args.batched_only:
         args.headline_only = True
-        extra["batched_64"] = batched_bench(pfk, torch, args.steps, args.warmup)
+        extra["batched_64"] = batched_bench(pfk, torch, args.steps, args.warmup, solve=not args.no_batched_solve)
     if args.stagnation_only:
         args.headline_only = True
         extra["stagnation_study"] = stagnation_study(pfk, torch)

@@ -133,6 +133,14 @@ typedef struct {
                               wall clock); returned as iter_time_us (single solves,
                               sessions and batch members; the server does not keep
                               it)                                                    */
+  int stall_window;        /* CG/CR types: 0 off (default); K > 0 restarts from x
+                              (like a residual gap, counted with max_restarts) at an
+                              iteration at least K after the (re)start whose recurred
+                              ||r|| is above half of that K iterations earlier.  A
+                              pipelined method with an inexact B can stall at a noise
+                              floor scaling with ||A|| ||B|| (section 2.2.1); the
+                              restart rebuilds its recurrences from the current x.
+                              GMRES types ignore it.                                 */
   int side_delay;          /* test hook (single solves and sessions; batches ignore it):
                               before each reduction finish on the second
                               stream, a one-workgroup kernel sleeps this many rounds
@@ -392,6 +400,8 @@ typedef struct {
   int launch_direct;   /* 1: batches launch their kernels directly instead of
                           replaying captured graphs (same results; for tools that
                           trace individual launches); 0: graphs (default)        */
+  int stall_window;    /* the requests' pfk_solve_opts.stall_window (0 off)       */
+  int max_restarts;    /* the requests' pfk_solve_opts.max_restarts (0: default)  */
 } pfk_server_config;
 
 typedef struct {

@@ -35,6 +35,13 @@ and the listings omit.  Conventions shared with the GPU path:
   FCG's pin, tests the 2-norm only).
 * Window: the last nu_i directions, nu_i from ``truncation_nu`` with j the
   number of iterations since the last (re)start.
+* Stagnation restart (option ``stall_window`` K, CG/CR types, 0 = off): once
+  K iterations have passed since the (re)start, an iteration whose recurred
+  residual is above half the one K iterations earlier restarts from x as a
+  residual gap does (counted with the restarts).  Section 5's restarts flush
+  the pipeline on a breakdown; a pipelined CG/CR method with an inexact B
+  can instead stall at a noise floor that scales with ||A|| ||B|| (section
+  2.2.1), and a restart from the current x rebuilds its recurrences there.
 * Breakdown (section 5): eta_i <= 0 or non-finite for CG/CR types,
   t < 0 for PIPEFGMRES; restart from the current x, flushing the pipeline.
   A breakdown of the initial eta_0 is unrecoverable, as is exceeding
@@ -181,7 +188,8 @@ class Result:
 
 
 class _State:
-    def __init__(self, maxit, force_breakdown_at, record, norm="2", rtol=0.0):
+    def __init__(self, maxit, force_breakdown_at, record, norm="2", rtol=0.0, stall_window=0):
+        self.stall = stall_window
         self.it = 0
         self.history = []
         self.natural = []
@@ -212,6 +220,11 @@ class _State:
             return self.natural[-1] <= self.ntol
         return self.history[-1] <= tol
 
+    def stalled(self, j) -> bool:
+        """Stagnation: at least ``stall`` iterations since the (re)start and the
+        newest recurred residual above half the one ``stall`` iterations back."""
+        return self.stall > 0 and j >= self.stall and self.history[-1] > 0.5 * self.history[-1 - self.stall]
+
     def forced(self, it=None) -> bool:
         """True once, at iteration ``force_breakdown_at`` (test hook)."""
         it = self.it if it is None else it
@@ -223,7 +236,7 @@ class _State:
 
 def solve(method: str, A, B, b, x0=None, rtol=1e-8, maxit=500, nu_max=30,
           truncation="standard", sigma=None, max_restarts=10,
-          force_breakdown_at=-1, record=False, norm="2") -> Result:
+          force_breakdown_at=-1, record=False, norm="2", stall_window=0) -> Result:
     """Solve A x = b with the named method.
 
     ``A`` is a callable (or an object with ``apply``), ``B`` a callable
@@ -246,7 +259,8 @@ def solve(method: str, A, B, b, x0=None, rtol=1e-8, maxit=500, nu_max=30,
     if method == "pipefgmres":
         kw["sigma"] = estimate_sigma(Aop, B, b.shape[0]) if sigma is None else float(sigma)
     no_natural = method in ("pcg", "fgmres", "pipefgmres")
-    st = _State(maxit, force_breakdown_at, record, "2" if no_natural else norm, rtol)
+    st = _State(maxit, force_breakdown_at, record, "2" if no_natural else norm, rtol,
+                0 if method in ("pcg", "fgmres", "pipefgmres") else stall_window)
     restarts = 0
     status = "maxit"
     cr = method in _CR_TYPES
@@ -370,11 +384,15 @@ def _fcg_cycle(Aop, B, b, x, st, tol, nu_max, trunc):
         st.history.append(_norm(r))
         if not st.natural_test and st.converged(tol):
             return "converged"
+        if not st.natural_test and st.stalled(j):
+            return "gap"
         u = B(r)
         gamma = _dot(u, r)
         st.log_natural(gamma)
         if st.natural_test and st.converged(tol):
             return "converged"
+        if st.natural_test and st.stalled(j):
+            return "gap"
         nu = truncation_nu(trunc, j, nu_max)
         win = _window(P, nu)
         beta = {k: -_dot(u, S[k]) / ETA[k] for k in win}
@@ -438,6 +456,8 @@ def _pipefcg_cycle(Aop, B, b, x, st, tol, nu_max, trunc, naive=False):
         st.log_natural(gamma)
         if st.converged(tol):
             return "converged"
+        if st.stalled(j):
+            return "gap"
         # overlapped with the reduction
         m = B(w) if naive else u + B(w - r)
         n = Aop(m)
@@ -500,11 +520,15 @@ def _gcr_cycle(Aop, B, b, x, st, tol, nu_max, trunc):
         st.history.append(_norm(r))
         if not st.natural_test and st.converged(tol):
             return "converged"
+        if not st.natural_test and st.stalled(j):
+            return "gap"
         u = B(r)
         t = Aop(u)
         st.log_natural(_dot(r, t))
         if st.natural_test and st.converged(tol):
             return "converged"
+        if st.natural_test and st.stalled(j):
+            return "gap"
         nu = truncation_nu(trunc, j, nu_max)
         win = _window(P, nu)
         beta = {k: -_dot(t, S[k]) / ETA[k] for k in win}
@@ -576,6 +600,8 @@ def _pipegcr_cycle(Aop, B, b, x, st, tol, nu_max, trunc, recur_w=False, naive=Fa
         st.log_natural(gamma)
         if st.converged(tol):
             return "converged"
+        if st.stalled(j):
+            return "gap"
         m = B(w) if naive else u + B(w - r)
         nn = Aop(m) if recur_w else None
         beta = {k: -dks[k] / ETA[k] for k in win}

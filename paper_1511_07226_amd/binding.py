@@ -58,7 +58,7 @@ class Tuning(C.Structure):
 
 class ServerConfig(C.Structure):
     _fields_ = [("hbm_budget", C.c_size_t), ("max_active", C.c_int), ("step_iters", C.c_int), ("mmax", C.c_int),
-                ("launch_direct", C.c_int)]
+                ("launch_direct", C.c_int), ("stall_window", C.c_int), ("max_restarts", C.c_int)]
 
 
 class ServerStatus(C.Structure):
@@ -76,7 +76,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("truncation", C.c_int), ("shift_sigma", C.c_double), ("graph_iters", C.c_int),
                 ("use_graph", C.c_int), ("host_sync", C.c_int), ("max_restarts", C.c_int),
                 ("force_breakdown_at", C.c_int), ("persistent", C.c_int), ("norm", C.c_int),
-                ("timestamps", C.c_int), ("side_delay", C.c_int)]
+                ("timestamps", C.c_int), ("stall_window", C.c_int), ("side_delay", C.c_int)]
 
 
 class _Info(C.Structure):
@@ -510,8 +510,9 @@ class Server:
     submit(), progress() -> completed ids, result(id), stats()."""
 
     def __init__(self, hbm_budget: int, max_active: int = 64, step_iters: int = 10, mmax: int = 30, stream=None,
-                 launch_direct: bool = False):
-        cfg = ServerConfig(int(hbm_budget), int(max_active), int(step_iters), int(mmax), int(bool(launch_direct)))
+                 launch_direct: bool = False, stall_window: int = 0, max_restarts: int = 0):
+        cfg = ServerConfig(int(hbm_budget), int(max_active), int(step_iters), int(mmax), int(bool(launch_direct)),
+                           int(stall_window), int(max_restarts))
         h = C.c_void_p()
         _check(lib().pfk_server_create(C.byref(cfg), _stream_ptr(stream), C.byref(h)))
         self._h = h

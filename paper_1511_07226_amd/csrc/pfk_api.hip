@@ -221,6 +221,7 @@ extern "C" void pfk_default_opts(pfk_solve_opts* o) {
   o->norm = 0;
   o->timestamps = 0;
   o->side_delay = 0;
+  o->stall_window = 0;
 }
 
 extern "C" int pfk_operator_create(int dim, const int64_t n[3], const double* eta, const double* face_vel,
@@ -1130,6 +1131,10 @@ static int session_make(pfk_operator A, pfk_precond B, pfk_method method, const 
     delete S;
     return fail(PFK_ERR_ARG, "side_delay must be 0..10000");
   }
+  if (S->opts.stall_window < 0) {
+    delete S;
+    return fail(PFK_ERR_ARG, "stall_window must be >= 0");
+  }
   if (S->opts.host_sync) {
     if (method != PFK_FCG && method != PFK_GCR && method != PFK_FGMRES) {
       delete S;
@@ -1220,7 +1225,8 @@ static int session_setup(pfk_session_s* S) {
   const bool gm = S->method == PFK_FGMRES || S->method == PFK_PIPEFGMRES;
   const int nt = session_nt(S);
   LAUNCH(k_setup, 1, S->s1, S->st, 0.0, S->maxit, S->mmax, S->opts.truncation, S->opts.force_breakdown_at,
-         S->sigma, gm ? 0 : S->opts.norm, S->nhist, nt, S->opts.timestamps ? S->tstamp : nullptr);
+         S->sigma, gm ? 0 : S->opts.norm, S->nhist, nt, S->opts.timestamps ? S->tstamp : nullptr,
+         gm ? 0 : S->opts.stall_window);
   LAUNCH(k_dot, S->Pv(), S->s1, S->A->N, S->b, S->b, S->part(PT_A));
   LAUNCH(k_setup_tol, 1, S->s1, S->part(PT_A), S->Pv(), S->rtol, S->st, S->hist);
   LAUNCH(k_zero_if_done, S->Pv(), S->s1, S->A->N, S->x, S->st);
@@ -1338,11 +1344,12 @@ static int solve_loop(pfk_session_s* S, int* code_out) {
     if (status == kNonfinite) { code = PFK_ERR_NONFINITE; break; }
     if (status == kBreakdown0) { code = PFK_ERR_BREAKDOWN; break; }
     if (status == kBreakdown || status == kGap) {
-      if (S->host_state->it >= S->maxit) { code = PFK_NOT_CONVERGED; break; }
+      // the restart is counted first, also when maxit ends the solve here
       if (++S->restarts > max_restarts) {
         code = status == kBreakdown ? PFK_ERR_BREAKDOWN : PFK_NOT_CONVERGED;
         break;
       }
+      if (S->host_state->it >= S->maxit) { code = PFK_NOT_CONVERGED; break; }
       rc = launch_start(S);
       continue;
     }
@@ -1436,6 +1443,7 @@ extern "C" int pfk_solve_noalloc(pfk_operator A, pfk_precond B, pfk_method metho
   if (S.opts.truncation < 0 || S.opts.truncation > 2) return fail(PFK_ERR_ARG, "truncation must be 0, 1 or 2");
   if (S.opts.norm < 0 || S.opts.norm > 1) return fail(PFK_ERR_ARG, "norm must be 0 (2-norm) or 1 (natural)");
   if (S.opts.side_delay < 0 || S.opts.side_delay > 10000) return fail(PFK_ERR_ARG, "side_delay must be 0..10000");
+  if (S.opts.stall_window < 0) return fail(PFK_ERR_ARG, "stall_window must be >= 0");
   if (S.opts.timestamps)
     return fail(PFK_ERR_ARG, "timestamps are not available in the no-allocation solve (use pfk_solve)");
   if (S.opts.host_sync && method != PFK_FCG && method != PFK_GCR && method != PFK_FGMRES)
@@ -2227,11 +2235,12 @@ extern "C" int pfk_batch_poll(pfk_batch T, int* finished, int cap, int* nfinishe
         break;
       case kBreakdown:
       case kGap:
-        if (it >= S->maxit) {
-          ended = true;
-        } else if (++S->restarts > S->opts.max_restarts) {
+        // the restart is counted first, also when maxit ends the member here
+        if (++S->restarts > S->opts.max_restarts) {
           ended = true;
           code = status == kBreakdown ? PFK_ERR_BREAKDOWN : PFK_NOT_CONVERGED;
+        } else if (it >= S->maxit) {
+          ended = true;
         } else {
           enqueue_start(S, T->s1);
         }
@@ -2432,6 +2441,8 @@ extern "C" int pfk_server_create(const pfk_server_config* cfg, void* stream, pfk
   if (cfg->step_iters < 1) return fail(PFK_ERR_ARG, "step_iters must be >= 1");
   if (cfg->mmax < 1 || cfg->mmax > kNuMax) return fail(PFK_ERR_ARG, "mmax must be 1..64");
   if (cfg->hbm_budget == 0) return fail(PFK_ERR_ARG, "hbm_budget must be positive");
+  if (cfg->stall_window < 0 || cfg->max_restarts < 0)
+    return fail(PFK_ERR_ARG, "stall_window and max_restarts must be >= 0");
   auto* S = new (std::nothrow) pfk_server_s();
   if (!S) return fail(PFK_ERR_OOM, "host allocation");
   S->cfg = *cfg;
@@ -2482,6 +2493,8 @@ extern "C" int pfk_server_progress(pfk_server S, long long* completed, int cap, 
       pfk_default_opts(&o);
       o.graph_iters = S->cfg.step_iters;
       o.use_graph = S->cfg.launch_direct ? 0 : 1;
+      o.stall_window = S->cfg.stall_window;
+      if (S->cfg.max_restarts > 0) o.max_restarts = S->cfg.max_restarts;
       pfk_server_s::Bt bt{r.method, r.B->kind, fp32, r.A->dim, r.B->k, nullptr, {}, 0};
       int rc = pfk_batch_create((pfk_method)r.method, S->cfg.mmax, S->cfg.max_active, S->stream, &o, &bt.T);
       if (rc) return rc;

@@ -23,7 +23,7 @@ struct Window {
 // Shared kernels
 // ---------------------------------------------------------------------------
 __global__ void k_setup(SolveState* st, double tol, int maxit, int nu_max, int trunc, int force_it,
-                        double sigma, int norm, double* nhist, int nt, unsigned long long* tstamp) {
+                        double sigma, int norm, double* nhist, int nt, unsigned long long* tstamp, int stall) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   st->nt = nt;
   st->status = kRunning;
@@ -50,6 +50,7 @@ __global__ void k_setup(SolveState* st, double tol, int maxit, int nu_max, int t
   st->ntol = 0.0;
   st->nhist = nhist;
   st->tstamp = tstamp;
+  st->stall = stall;
 }
 
 // Natural norm sqrt|gamma| (section 5: the residual norm CG/CR types have
@@ -458,6 +459,7 @@ __device__ __forceinline__ void pipefcg_scalars_body(Blk bk, const double* part,
   const double nat = natural_log(st, it, col[0]);
   if (!isfinite(res)) { st->status = kNonfinite; return; }
   if (converged_test(st, res, nat)) { st->status = kConverged; return; }
+  if (stalled(st, hist, it, j1, res)) { st->status = kGap; return; }
   const int numax = st->nu_max;
   double eta = col[1];
   for (int t = 0; t < nu1; ++t) {
@@ -639,6 +641,7 @@ __device__ __forceinline__ void cg_scalars1_body(Blk bk, int init, const double*
   const double nat = natural_log(st, it, col[0]);
   if (!isfinite(res)) { st->status = kNonfinite; return; }
   if (converged_test(st, res, nat)) { st->status = kConverged; return; }
+  if (stalled(st, hist, it, j1, res)) { st->status = kGap; return; }
   const int numax = st->nu_max;
   for (int t = 0; t < nu; ++t) {
     const int d = j1 - nu + t;

@@ -57,6 +57,7 @@ struct SolveState {
   double true_res;
   double bnorm;      // ||b||_2
   int norm;          // CG/CR types: 1 tests the natural norm sqrt|gamma| instead of ||r||_2
+  int stall;         // CG/CR types: stagnation restart window K (0 off)
   int nat_started;   // natural-norm history entry 0 recorded (first start-up)
   int nt;            // vector kernels use nontemporal accesses (working set far beyond the caches)
   double rtol;
@@ -95,6 +96,13 @@ __host__ __device__ inline int trunc_nu(int rule, int j, int numax) {
 // The device's constant-rate wall clock at history entry i (opts.timestamps).
 __device__ __forceinline__ void log_time(SolveState* st, int i) {
   if (st->tstamp) st->tstamp[i] = wall_clock64();
+}
+
+// Stagnation (option stall_window K, CG/CR types): at least K iterations since
+// the (re)start and the newest recurred residual above half of the one K
+// iterations back; the solve then restarts from x as after a residual gap.
+__device__ __forceinline__ bool stalled(const SolveState* st, const double* hist, int it, int j, double res) {
+  return st->stall > 0 && j >= st->stall && res > 0.5 * hist[it - st->stall];
 }
 
 __device__ __forceinline__ int read_status(const SolveState* st) {

@@ -396,3 +396,40 @@ def test_natural_norm_check_rejects_a_stagnated_iterate():
     rt = p.b - A.apply(r.x)
     assert math.sqrt(abs(B(rt) @ rt)) > 1e-6 * r.natural[0]
     assert r.true_rel_resid > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# stagnation restart (option stall_window)
+# ---------------------------------------------------------------------------
+def test_stall_restart_fires_at_the_rule():
+    """The restart comes at the first iteration i >= K (since the start) whose
+    recurred residual is above half of entry i - K, and not before."""
+    p = gen.config_problem("cfg1", seed=0)
+    A = StencilOperator(2, 64, p.eta)
+    B = make_pc("jacobi_pcg", A, 2)
+    h = solve("pipefcg", A, B, p.b, rtol=0.0, maxit=120, nu_max=30).history
+    K = 20
+    i = next(i for i in range(K, len(h)) if h[i] > 0.5 * h[i - K])
+    before = solve("pipefcg", A, B, p.b, rtol=0.0, maxit=i - 1, nu_max=30, stall_window=K)
+    at = solve("pipefcg", A, B, p.b, rtol=0.0, maxit=i, nu_max=30, stall_window=K)
+    assert before.restarts == 0 and at.restarts == 1
+    assert at.history == h[:i + 1]
+    # GMRES types ignore the option
+    g0 = solve("fgmres", A, jacobi_pc(1.0 / A.diagonal()), p.b, rtol=0.0, maxit=40, nu_max=30)
+    g1 = solve("fgmres", A, jacobi_pc(1.0 / A.diagonal()), p.b, rtol=0.0, maxit=40, nu_max=30, stall_window=5)
+    assert g0.history == g1.history and g1.restarts == 0
+
+
+def test_stall_restarts_lift_the_noise_floor():
+    """Naive PIPEFCG on the section 2.2.1 toy stalls near the noise level; a
+    restart from the current x rebuilds its recurrences there, so with
+    stagnation restarts it goes far below the plateau."""
+    lam, b = gen.toy_diagonal(100, 5.0)
+    xs = b / lam
+    err = {}
+    for K in (0, 20):
+        B = noisy_pc(0.1, np.random.default_rng(1))
+        r = solve("pipefcg_naive", lambda v: lam * v, B, b, rtol=1e-15, maxit=200, nu_max=100,
+                  stall_window=K, max_restarts=50)
+        err[K] = np.linalg.norm(r.x - xs) / np.linalg.norm(xs)
+    assert err[0] > 1e-4 and err[20] < 1e-7, err
