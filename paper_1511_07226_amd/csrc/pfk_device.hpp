@@ -58,13 +58,6 @@ __device__ __forceinline__ long long vec_index(const G& g, int i, int j, int k) 
 template <class T>
 __device__ __forceinline__ T harmonic(T a, T b) { return T(2) * a * b / (a + b); }
 
-// (A u) at the node with padded index pc from its value uc, its six
-// neighbour values (0 on the Dirichlet boundary) and the viscosities at the
-// node and its neighbours, in arithmetic type T.  Diffusion:
-// h^-2 sum_f k_f (u_c - u_nb) with k_f the harmonic mean of eta; convection
-// (if g.vel): first-order upwind flux h^-1 sum_f (max(v_f,0) u_c +
-// min(v_f,0) u_nb) with v_f the outward normal velocity.  Faces are taken in
-// the order x+, x-, y+, y-, z+, z-.
 // (A u) at a node from its value uc, its six neighbour values (0 on the
 // Dirichlet boundary) and the viscosities at the node and its neighbours, in
 // arithmetic type T.  Diffusion: h^-2 sum_f k_f (u_c - u_nb) with k_f the
@@ -225,20 +218,31 @@ __device__ __forceinline__ auto stencil_in(LoadF load) {
 // up the z-axis.  Each node's input value u = in.value(in.load(flat index)) is
 // formed once.
 // z-neighbours stay in registers; in-plane neighbours of u and of the
-// viscosity come from LDS copies of the current plane with a one-node halo
-// (halo values are formed by the first 2(TX+TY) threads).  Every global load
-// is issued one plane step before its value is used: while plane k is
-// computed, plane k+2 (centre column) and the halo of plane k+1 are in
-// flight, so a plane step never waits on its own loads.  Values outside the
-// domain are 0 (Dirichlet); viscosities are read on the whole padded grid.
+// viscosity come from LDS copies of the plane with a one-node halo (halo
+// values are formed by the first 2(TX+TY) threads).  While plane k is
+// computed, the loads of plane k+2 are in flight, for the centre column and
+// for the halo alike: a tile's halo rows are interior rows of its neighbours,
+// which those load in the same plane step, so the second request finds the
+// line in (or on its way into) the XCD's L2 instead of fetching it again
+// from HBM.  Column values are formed at the end of the step and kept in
+// registers; halo values are formed at the end of the step straight into the
+// LDS buffer of their plane (three plane buffers in a ring: k being read,
+// k+1 complete, k+2 receiving its halo), so no halo value is held in a
+// register across a step.  Values outside the domain are 0 (Dirichlet);
+// viscosities are read on the whole padded grid.
 // For every interior node the engine calls sink(flat index, u, (A u)).
-// LDS of the stencil engine: one buffer shared by every instantiation (tile
-// widths, arithmetic types, callers) -- a static in a non-template function is
-// a single object, so a kernel holds it once however many variants it uses.
-constexpr int kStencilLds = 2 * (TileShape<64>::TY + 2) * (64 + 2) * 8;
-static_assert(kStencilLds >= 2 * (TileShape<32>::TY + 2) * (32 + 2) * 8, "LDS sized for the widest tile");
+//
+// LDS of the stencil engine: kStencilSlots plane buffers of u and of the
+// viscosity, sized for the larger tile (64x8 and 32x16 tiles with their
+// halo); one buffer per word size, shared by every tile width and caller of
+// that size -- a static in a function is a single object per instantiation,
+// so a kernel holds it once however many variants it uses.
+constexpr int kStencilSlots = 3;
+constexpr int kStencilPlane = (TileShape<64>::TY + 2) * (64 + 2);
+static_assert(kStencilPlane >= (TileShape<32>::TY + 2) * (32 + 2), "LDS sized for the larger tile");
+template <int B>
 __device__ __forceinline__ char* stencil_lds() {
-  __shared__ __attribute__((aligned(16))) char buf[kStencilLds];
+  __shared__ __attribute__((aligned(16))) char buf[kStencilSlots * 2 * kStencilPlane * B];
   return buf;
 }
 
@@ -253,8 +257,11 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
                                                 Sink& sink) {
   using S = TileShape<TX>;
   constexpr int TY = S::TY;
-  T (*su)[TX + 2] = reinterpret_cast<T (*)[TX + 2]>(stencil_lds());
-  T (*se)[TX + 2] = reinterpret_cast<T (*)[TX + 2]>(stencil_lds() + sizeof(T) * (TY + 2) * (TX + 2));
+  constexpr int PL = (TY + 2) * (TX + 2);
+  T* const lds = reinterpret_cast<T*>(stencil_lds<sizeof(T)>());
+  // plane buffer of ring slot s: u at lds + 2 s PL, the viscosity after it
+  auto SU = [&](int s) { return reinterpret_cast<T (*)[TX + 2]>(lds + 2 * s * PL); };
+  auto SE = [&](int s) { return reinterpret_cast<T (*)[TX + 2]>(lds + (2 * s + 1) * PL); };
   const int L = xcd_tile(bid, sg.blocks());
   const int tx = L % sg.tiles_x;
   const int ty = (L / sg.tiles_x) % sg.tiles_y;
@@ -301,10 +308,10 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
   };
   auto E = [&](int r, int k) { return T(to_real(ER(r, k))); };
   auto HOK = [&](int k) { return hvalid && k < g.nz; };
-  auto HU = [&](int k) { return HOK(k) ? T(in.value(in.load(vec_index(g, hi, hj, k)))) : zero; };
   auto HER = [&](int k) { return (hevalid && k <= kmax) ? g.eta[padded_index(g, hi, hj, k)] : ez; };
-  auto HE = [&](int k) { return T(to_real(HER(k))); };
 
+  // a previous march of this workgroup may still be reading the buffers
+  __syncthreads();
   // register window: m = k-1, c = k, p = k+1 (u and eta of the centre column)
   T um[2], uc[2], up[2], em[2], ec[2], ep[2];
 #pragma unroll
@@ -316,7 +323,18 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
     ec[r] = E(r, k0);
     ep[r] = d3 ? E(r, k0 + 1) : zero;
   }
-  T hu = HU(k0), he = HE(k0);
+  // halo of planes k0 and k0+1 into ring slots 0 and 1
+  if (has_halo) {
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const int kk = k0 + d;
+      if (kk < k1) {
+        SU(d)[hr][hc] = HOK(kk) ? T(in.value(in.load(vec_index(g, hi, hj, kk)))) : zero;
+        SE(d)[hr][hc] = T(to_real(HER(kk)));
+      }
+    }
+  }
+  int slot = 0;   // ring slot of plane k
   // face velocities of the centre column (CV): x+, x-, y+, y-, z+ of the
   // current plane, of the next one in flight, and z- of the current plane
   T vc[2][5], vn[2][5], vzm[2];
@@ -342,7 +360,7 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
     }
   }
   for (int k = k0; k < k1; ++k) {
-    // in flight during this step: plane k+2 of the column, the halo of plane k+1
+    // in flight during this step: plane k+2 of the column and of the halo
     Raw uppR[2];
     ES eppR[2];
     bool uppOK[2];
@@ -353,24 +371,23 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
       uppR[r] = uppOK[r] ? in.load(vec_index(g, i, jr[r], k + 2)) : Raw{};
       eppR[r] = (d3 && more) ? ER(r, k + 2) : ez;
     }
-    const bool hok_n = more && HOK(k + 1);
-    const Raw huR_n = hok_n ? in.load(vec_index(g, hi, hj, k + 1)) : Raw{};
-    const ES heR_n = more ? HER(k + 1) : ez;
+    const bool h2 = has_halo && k + 2 < k1;
+    const bool h2ok = h2 && HOK(k + 2);
+    const Raw huR = h2ok ? in.load(vec_index(g, hi, hj, k + 2)) : Raw{};
+    const ES heR = h2 ? HER(k + 2) : ez;
     if constexpr (CV) {
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
         if (more) VL(r, k + 1, vn[r]);
       }
     }
+    T (*const su)[TX + 2] = SU(slot);
+    T (*const se)[TX + 2] = SE(slot);
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
       su[row[r] + 1][xo + 1] = uc[r];
       se[row[r] + 1][xo + 1] = ec[r];
-    }
-    if (has_halo) {
-      su[hr][hc] = hu;
-      se[hr][hc] = he;
     }
     __syncthreads();
 #pragma unroll
@@ -404,8 +421,14 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
       ec[r] = ep[r];
       ep[r] = T(to_real(eppR[r]));
     }
-    hu = hok_n ? T(in.value(huR_n)) : zero;
-    he = T(to_real(heR_n));
+    // the halo of plane k+2 into the slot plane k-1 used (every thread has
+    // passed this step's barriers, so none still reads it)
+    const int s2 = slot == 0 ? kStencilSlots - 1 : slot - 1;
+    if (h2) {
+      SU(s2)[hr][hc] = h2ok ? T(in.value(huR)) : zero;
+      SE(s2)[hr][hc] = T(to_real(heR));
+    }
+    slot = slot == kStencilSlots - 1 ? 0 : slot + 1;
   }
 }
 
