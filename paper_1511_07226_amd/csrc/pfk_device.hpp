@@ -219,17 +219,22 @@ __device__ __forceinline__ auto stencil_in(LoadF load) {
 // formed once.
 // z-neighbours stay in registers; in-plane neighbours of u and of the
 // viscosity come from LDS copies of the plane with a one-node halo (halo
-// values are formed by the first 2(TX+TY) threads).  While plane k is
-// computed, the loads of plane k+2 are in flight, for the centre column and
-// for the halo alike: a tile's halo rows are interior rows of its neighbours,
-// which those load in the same plane step, so the second request finds the
-// line in (or on its way into) the XCD's L2 instead of fetching it again
-// from HBM.  Column values are formed at the end of the step and kept in
-// registers; halo values are formed at the end of the step straight into the
-// LDS buffer of their plane (three plane buffers in a ring: k being read,
-// k+1 complete, k+2 receiving its halo), so no halo value is held in a
-// register across a step.  Values outside the domain are 0 (Dirichlet);
-// viscosities are read on the whole padded grid.
+// values are formed by the first 2(TX+TY) threads).  Loads run PD plane
+// steps ahead: while plane k is computed, the loads of planes k+2 .. k+1+PD
+// are in flight, for the centre column and for the halo alike.  A tile's halo
+// rows are interior rows of its neighbours, which those load in the same
+// plane step, so the second request finds the line in (or on its way into)
+// the XCD's L2 instead of fetching it again from HBM.  At the end of step k
+// the values of plane k+2 are formed: the column's into registers, the
+// halo's straight into the LDS buffer of their plane (three plane buffers in
+// a ring: k being read, k+1 complete, k+2 receiving its halo), so no formed
+// halo value is held in a register across a step.  PD = 1 waits at the end
+// of a step for loads issued at its start; PD = 2 keeps a second plane of raw
+// loads in registers and waits for loads a whole step old -- worth it where
+// the extra registers cost no occupancy step (the FP32 inner GMRES apply at
+// 256^3: 0.160 -> 0.133 ms), not where they do (the FP64 inner PCG kernels
+// lose one and slow down 3-10%).  Values outside the domain are 0
+// (Dirichlet); viscosities are read on the whole padded grid.
 // For every interior node the engine calls sink(flat index, u, (A u)).
 //
 // LDS of the stencil engine: kStencilSlots plane buffers of u and of the
@@ -252,9 +257,10 @@ __device__ __forceinline__ char* stencil_lds() {
 // convective operator still works: apply_faces then loads the velocities
 // when it needs them.  CV kernels are separate instantiations, so the
 // diffusion kernels do not carry the extra registers.
-template <int TX, bool CV, class T, class G, class In, class Sink>
+template <int TX, bool CV, int PD, class T, class G, class In, class Sink>
 __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& sg, int bid, const In& in,
                                                 Sink& sink) {
+  static_assert(PD >= 1 && PD <= 3, "prefetch depth 1..3 plane steps");
   using S = TileShape<TX>;
   constexpr int TY = S::TY;
   constexpr int PL = (TY + 2) * (TX + 2);
@@ -334,6 +340,47 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
       }
     }
   }
+  // raw loads of one plane p: the column's (needed while plane p-1 is
+  // computed, i.e. if p-1 < k1) and the halo's (needed if p < k1)
+  struct ColRaw {
+    Raw u[2];
+    ES e[2];
+    bool ok[2];
+  };
+  struct HaloRaw {
+    Raw u;
+    ES e;
+    bool h, ok;
+  };
+  auto issue_col = [&](int p) {
+    ColRaw c;
+    const bool need = d3 && p - 1 < k1;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      c.ok[r] = need && UOK(r, p);
+      c.u[r] = c.ok[r] ? in.load(vec_index(g, i, jr[r], p)) : Raw{};
+      c.e[r] = need ? ER(r, p) : ez;
+    }
+    return c;
+  };
+  auto issue_halo = [&](int p) {
+    HaloRaw h;
+    h.h = has_halo && p < k1;
+    h.ok = h.h && HOK(p);
+    h.u = h.ok ? in.load(vec_index(g, hi, hj, p)) : Raw{};
+    h.e = h.h ? HER(p) : ez;
+    return h;
+  };
+  // planes k0+2 .. k0+PD in flight before the first step (PD > 1)
+  ColRaw cq[PD > 1 ? PD - 1 : 1];
+  HaloRaw hq[PD > 1 ? PD - 1 : 1];
+  if constexpr (PD > 1) {
+#pragma unroll
+    for (int d = 0; d < PD - 1; ++d) {
+      cq[d] = issue_col(k0 + 2 + d);
+      hq[d] = issue_halo(k0 + 2 + d);
+    }
+  }
   int slot = 0;   // ring slot of plane k
   // face velocities of the centre column (CV): x+, x-, y+, y-, z+ of the
   // current plane, of the next one in flight, and z- of the current plane
@@ -360,21 +407,10 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
     }
   }
   for (int k = k0; k < k1; ++k) {
-    // in flight during this step: plane k+2 of the column and of the halo
-    Raw uppR[2];
-    ES eppR[2];
-    bool uppOK[2];
+    // issued this step: plane k+1+PD of the column and of the halo
+    const ColRaw cn = issue_col(k + 1 + PD);
+    const HaloRaw hn = issue_halo(k + 1 + PD);
     const bool more = k + 1 < k1;
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      uppOK[r] = d3 && more && UOK(r, k + 2);
-      uppR[r] = uppOK[r] ? in.load(vec_index(g, i, jr[r], k + 2)) : Raw{};
-      eppR[r] = (d3 && more) ? ER(r, k + 2) : ez;
-    }
-    const bool h2 = has_halo && k + 2 < k1;
-    const bool h2ok = h2 && HOK(k + 2);
-    const Raw huR = h2ok ? in.load(vec_index(g, hi, hj, k + 2)) : Raw{};
-    const ES heR = h2 ? HER(k + 2) : ez;
     if constexpr (CV) {
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
@@ -390,6 +426,9 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
       se[row[r] + 1][xo + 1] = ec[r];
     }
     __syncthreads();
+    // the raw loads of plane k+2, formed at the end of this step
+    const ColRaw& c2 = PD > 1 ? cq[0] : cn;
+    const HaloRaw& h2 = PD > 1 ? hq[0] : hn;
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
       if (valid[r]) {
@@ -416,30 +455,39 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
       }
       um[r] = uc[r];
       uc[r] = up[r];
-      up[r] = uppOK[r] ? T(in.value(uppR[r])) : zero;
+      up[r] = c2.ok[r] ? T(in.value(c2.u[r])) : zero;
       em[r] = ec[r];
       ec[r] = ep[r];
-      ep[r] = T(to_real(eppR[r]));
+      ep[r] = T(to_real(c2.e[r]));
     }
     // the halo of plane k+2 into the slot plane k-1 used (every thread has
     // passed this step's barriers, so none still reads it)
     const int s2 = slot == 0 ? kStencilSlots - 1 : slot - 1;
-    if (h2) {
-      SU(s2)[hr][hc] = h2ok ? T(in.value(huR)) : zero;
-      SE(s2)[hr][hc] = T(to_real(heR));
+    if (h2.h) {
+      SU(s2)[hr][hc] = h2.ok ? T(in.value(h2.u)) : zero;
+      SE(s2)[hr][hc] = T(to_real(h2.e));
+    }
+    if constexpr (PD > 1) {
+#pragma unroll
+      for (int d = 0; d + 1 < PD - 1; ++d) {
+        cq[d] = cq[d + 1];
+        hq[d] = hq[d + 1];
+      }
+      cq[PD - 2] = cn;
+      hq[PD - 2] = hn;
     }
     slot = slot == kStencilSlots - 1 ? 0 : slot + 1;
   }
 }
 
-template <class T, bool CV = false, class G, class In, class Sink>
+template <class T, bool CV = false, int PD = 1, class G, class In, class Sink>
 __device__ __forceinline__ void stencil_march(const G& g, const StencilGeom& sg, int bid, const In& in, Sink& sink) {
-  if (sg.tx == 32) stencil_march_t<32, CV, T>(g, sg, bid, in, sink);
-  else stencil_march_t<64, CV, T>(g, sg, bid, in, sink);
+  if (sg.tx == 32) stencil_march_t<32, CV, PD, T>(g, sg, bid, in, sink);
+  else stencil_march_t<64, CV, PD, T>(g, sg, bid, in, sink);
 }
-template <class T, bool CV = false, class G, class In, class Sink>
+template <class T, bool CV = false, int PD = 1, class G, class In, class Sink>
 __device__ __forceinline__ void stencil_march(const G& g, const StencilGeom& sg, const In& in, Sink& sink) {
-  stencil_march<T, CV>(g, sg, (int)blockIdx.x, in, sink);
+  stencil_march<T, CV, PD>(g, sg, (int)blockIdx.x, in, sink);
 }
 
 // ---------------------------------------------------------------------------

@@ -123,8 +123,9 @@ k_fgm_apply(Grid g, StencilGeom sg, PcOutDesc pd, Window U, double* __restrict__
     uc[idx] = u;
     z[idx] = Au;
   };
-  if (gm_raw_ok(pc)) stencil_march<double>(g, sg, gm_raw_in(pc, nullptr, 0.0), sink);
-  else stencil_march<double>(g, sg, in, sink);
+  // loads two plane steps ahead (no occupancy step lost)
+  if (gm_raw_ok(pc)) stencil_march<double, false, 2>(g, sg, gm_raw_in(pc, nullptr, 0.0), sink);
+  else stencil_march<double, false, 2>(g, sg, in, sink);
 }
 
 // First reduction: <p_j, z> for j <= c.

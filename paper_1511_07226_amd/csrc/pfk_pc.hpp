@@ -478,7 +478,8 @@ __device__ __forceinline__ void gmpc_apply_body(Blk bk, int jstep, G g, StencilG
   const auto in = stencil_in([&](long long t) { return Raw{dinv[t], Vj[t]}; },
                              [&](const Raw& q) { return q.d * (sj * q.v); });
   auto sink = [&](long long idx, T, T Au) { w[idx] = Au; };
-  stencil_march<T, CV>(g, sg, bk.id, in, sink);
+  // FP32: loads two plane steps ahead (the registers fit the same occupancy)
+  stencil_march<T, CV, sizeof(T) == 4 ? 2 : 1>(g, sg, bk.id, in, sink);
 }
 template <class T, class G, bool CV = false>
 __global__ void __launch_bounds__(kBlock)
