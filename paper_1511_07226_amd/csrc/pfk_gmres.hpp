@@ -293,8 +293,12 @@ k_pgm_scalars(const double* part, int P, SolveState* st, double* hist) {
 // into slot n (zbar_n also to zin), and the next single reduction:
 // <p_j, zbar_n> for j <= n and ||zbar_n||^2.
 // As in PIPEFCG's update, each lane owns two consecutive nodes (16-byte
-// accesses) and the window loops are unrolled so that several independent
-// loads are in flight; the dot with p_j reuses the p_j load.
+// accesses).  Two window passes per node pair, each keeping eight loads in
+// flight: zbar first (its loop unrolled by eight), then p and u~ together
+// (by four), since the dots with p_j need the finished zbar_n and reuse the
+// p_j loads.  The inner solve's output is loaded before the zbar pass and
+// combined after it, so its loads overlap that pass.  Each vector subtracts
+// its terms in order j = 0, 1, ..., as the method writes them.
 template <bool NT>
 __device__ __forceinline__ void pgm_update_body_t(Blk bk, long long N, Window P, Window U, Window ZB, PcOutDesc pd, const double* __restrict__ wb,
              double* __restrict__ zin, double* part, SolveState* st) {
@@ -325,8 +329,18 @@ __device__ __forceinline__ void pgm_update_body_t(Blk bk, long long N, Window P,
     const long long e = act ? 2 * (qw + lane) : 0;
     const bool full = act && e + 1 < N;
     const double2 zp = ld2<NT>(zprev, e, full), wv = ld2<NT>(wb, e, full);
+    // B(zbar) from an FP32 inner GMRES output, both nodes per 8-byte load
+    // (PcOut's arithmetic: dinv * sum cf_q V_q), loads issued here
+    const bool gmf = gm2 && full;
+    float2 dv = make_float2(0.f, 0.f), vq[kGmRaw];
+#pragma unroll
+    for (int q = 0; q < kGmRaw; ++q) {
+      vq[q] = make_float2(0.f, 0.f);
+      if (gmf && q < pc.nv) vq[q] = *reinterpret_cast<const float2*>(gmV + (long long)q * pc.ldv + e);
+    }
+    if (gmf) dv = *reinterpret_cast<const float2*>(gmD + e);
     double2 z = make_double2(wv.x - sigma * zp.x, wv.y - sigma * zp.y);
-#pragma unroll 4
+#pragma unroll 8
     for (int j = 0; j < n; ++j) {
       const double h = s_h[j];
       const double2 zj = ld2<NT>(ZB.base, (long long)j * ZB.ld + e, full);
@@ -336,43 +350,36 @@ __device__ __forceinline__ void pgm_update_body_t(Blk bk, long long N, Window P,
     z.x *= inv;
     z.y *= inv;
     if (!act) z = make_double2(0.0, 0.0);
-    double2 p = zp;
-#pragma unroll 4
-    for (int j = 0; j < n; ++j) {
-      const double h = s_h[j];
-      const double2 pj = ld2<NT>(P.base, (long long)j * P.ld + e, full);
-      p.x -= h * pj.x;
-      p.y -= h * pj.y;
-      const double d = wave_sum(pj.x * z.x + pj.y * z.y);
-      if (lane == 0) s_dot[wid][j] += d;
-    }
-    p.x *= inv;
-    p.y *= inv;
     double2 u;
-    if (gm2 && full) {
-      // B(zbar) from an FP32 inner GMRES output, both nodes per 8-byte load
-      // (PcOut's arithmetic: dinv * sum cf_q V_q)
-      const float2 dv = *reinterpret_cast<const float2*>(gmD + e);
+    if (gmf) {
       double r0 = 0.0, r1 = 0.0;
 #pragma unroll
       for (int q = 0; q < kGmRaw; ++q) {
         if (q < pc.nv) {
-          const float2 vq = *reinterpret_cast<const float2*>(gmV + (long long)q * pc.ldv + e);
-          r0 += pc.cf[q] * (double)vq.x;
-          r1 += pc.cf[q] * (double)vq.y;
+          r0 += pc.cf[q] * (double)vq[q].x;
+          r1 += pc.cf[q] * (double)vq[q].y;
         }
       }
       u = make_double2((double)dv.x * r0, (double)dv.y * r1);
     } else {
       u = make_double2(pc(e), full ? pc(e + 1) : 0.0);
     }
+    double2 p = zp;
 #pragma unroll 4
     for (int j = 0; j < n; ++j) {
       const double h = s_h[j];
+      const long long oj = (long long)j * P.ld + e;
+      const double2 pj = ld2<NT>(P.base, oj, full);
       const double2 uj = ld2<NT>(U.base, (long long)j * U.ld + e, full);
+      p.x -= h * pj.x;
+      p.y -= h * pj.y;
       u.x -= h * uj.x;
       u.y -= h * uj.y;
+      const double d = wave_sum(pj.x * z.x + pj.y * z.y);
+      if (lane == 0) s_dot[wid][j] += d;
     }
+    p.x *= inv;
+    p.y *= inv;
     u.x *= inv;
     u.y *= inv;
     if (!act) continue;
