@@ -651,6 +651,32 @@ PcOutDesc pc_out_desc(const pfk_session_s* S, const double* X1, double c1, const
   return d;
 }
 
+// GF_j of the inner GMRES: one instantiation per basis length up to
+// kGfFixed (their raw loads fixed at compile time), one for longer bases.
+template <class T, class G, bool CV>
+void launch_gmpc_fused_cv(pfk_session_s* S, hipStream_t s, int j, int k, const G& g, const T* dinv,
+                          const double* X1, double c1, const double* X2, double c2, T* V, long long ldv,
+                          const T* wp, T* wo, const double* pin, int Pin, double* pout) {
+#define PFK_GF(J) LAUNCH((k_gmpc_fused<T, G, CV, J>), S->Ps(), s, j, k, g, S->sg, dinv, X1, c1, X2, c2, V, ldv, wp, \
+                         wo, pin, Pin, pout, S->st)
+  switch (j) {
+    case 0: PFK_GF(0); break;
+    case 1: PFK_GF(1); break;
+    case 2: PFK_GF(2); break;
+    case 3: PFK_GF(3); break;
+    case 4: PFK_GF(4); break;
+    default: PFK_GF(kGfFixed + 1); break;
+  }
+#undef PFK_GF
+}
+template <class T, class G>
+void launch_gmpc_fused(pfk_session_s* S, hipStream_t s, bool cv, int j, int k, const G& g, const T* dinv,
+                       const double* X1, double c1, const double* X2, double c2, T* V, long long ldv,
+                       const T* wp, T* wo, const double* pin, int Pin, double* pout) {
+  if (cv) launch_gmpc_fused_cv<T, G, true>(S, s, j, k, g, dinv, X1, c1, X2, c2, V, ldv, wp, wo, pin, Pin, pout);
+  else launch_gmpc_fused_cv<T, G, false>(S, s, j, k, g, dinv, X1, c1, X2, c2, V, ldv, wp, wo, pin, Pin, pout);
+}
+
 // The inner solve's kernels in arithmetic type T on operator description G
 // (FP64 on the outer operator, or FP32 on the BF16 one).  Its work vectors
 // are the session's inner vectors viewed as T.
@@ -692,20 +718,19 @@ void enqueue_pc_kernels(pfk_session_s* S, hipStream_t s, const PcOutDesc& d, con
   } else if (d.kind == kPcJacobiGmres) {
     T* V = (T*)S->win(W_PCV).base;
     const long long ldv = S->L.ld;
-    T* w = (T*)S->vec(V_PC_Q);
-    // G0 and every GO_j write PC0 (the norm GA_j reads); every GD_j writes PC1
-    LAUNCH((k_gmpc_start<T>), S->Pv(), s, A->N, d.k, X1, c1, X2, c2, V, part[0], S->st);
+    // w~ alternates between the inner vector and the basis window's last slot
+    T* w[2] = {(T*)S->vec(V_PC_Q), V + (long long)d.k * ldv};
+    const bool cv = A->vel != nullptr;
     for (int j = 0; j < d.k; ++j) {
-      if (A->vel != nullptr)
-        LAUNCH((k_gmpc_apply<T, G, true>), S->Ps(), s, j, g, S->sg, dinv, (const T*)V, ldv, w,
-               (const double*)part[0], S->Pv(), S->st);
-      else
-        LAUNCH((k_gmpc_apply<T, G, false>), S->Ps(), s, j, g, S->sg, dinv, (const T*)V, ldv, w,
-               (const double*)part[0], S->Pv(), S->st);
-      LAUNCH((k_gmpc_dots<T>), S->Pv(), s, j, A->N, (const T*)V, ldv, (const T*)w, part[1], S->st);
-      LAUNCH((k_gmpc_orth<T>), S->Pv(), s, j, d.k, A->N, V, ldv, (const T*)w, (const double*)part[1], S->Pv(),
-             part[0], S->st);
+      // GF_j reads GD_{j-1}'s partials (PC1), writes PC0; GD_j reads PC0, writes PC1
+      const T* wp = j > 0 ? (const T*)w[(j - 1) & 1] : nullptr;
+      launch_gmpc_fused<T, G>(S, s, cv, j, d.k, g, dinv, X1, c1, X2, c2, V, ldv, wp, w[j & 1],
+                              (const double*)part[1], S->Pv(), part[0]);
+      LAUNCH((k_gmpc_dots<T>), S->Pv(), s, j, A->N, (const T*)V, ldv, (const T*)w[j & 1],
+             (const double*)part[0], S->Ps(), part[1], S->st);
     }
+    LAUNCH((k_gmpc_norm<T>), S->Pv(), s, d.k - 1, A->N, (const T*)V, ldv, (const T*)w[(d.k - 1) & 1],
+           (const double*)part[1], S->Pv(), part[0], S->st);
   }
 }
 
@@ -1915,12 +1940,18 @@ void batch_inner_pcg(pfk_batch_s* Tb, const int* os, const int* ov, int n) {
 template <class T>
 void batch_inner_gmres(pfk_batch_s* Tb, const int* os, const int* ov, int n) {
   hipStream_t s1 = Tb->s1;
-  LAUNCH((kb_gmpc_start<T>), Tb->tot[kBpVec], s1, Tb->d_sys, ov, n);
   for (int j = 0; j < Tb->pc_k; ++j) {
-    LAUNCH((kb_gmpc_apply<T>), Tb->tot[kBpSten], s1, Tb->d_sys, os, n, j);
+    switch (j) {
+      case 0: LAUNCH((kb_gmpc_fused<T, 0>), Tb->tot[kBpSten], s1, Tb->d_sys, os, n, j); break;
+      case 1: LAUNCH((kb_gmpc_fused<T, 1>), Tb->tot[kBpSten], s1, Tb->d_sys, os, n, j); break;
+      case 2: LAUNCH((kb_gmpc_fused<T, 2>), Tb->tot[kBpSten], s1, Tb->d_sys, os, n, j); break;
+      case 3: LAUNCH((kb_gmpc_fused<T, 3>), Tb->tot[kBpSten], s1, Tb->d_sys, os, n, j); break;
+      case 4: LAUNCH((kb_gmpc_fused<T, 4>), Tb->tot[kBpSten], s1, Tb->d_sys, os, n, j); break;
+      default: LAUNCH((kb_gmpc_fused<T, kGfFixed + 1>), Tb->tot[kBpSten], s1, Tb->d_sys, os, n, j); break;
+    }
     LAUNCH((kb_gmpc_dots<T>), Tb->tot[kBpVec], s1, Tb->d_sys, ov, n, j);
-    LAUNCH((kb_gmpc_orth<T>), Tb->tot[kBpVec], s1, Tb->d_sys, ov, n, j);
   }
+  LAUNCH((kb_gmpc_norm<T>), Tb->tot[kBpVec], s1, Tb->d_sys, ov, n, Tb->pc_k - 1);
 }
 
 // One outer iteration of every running member.

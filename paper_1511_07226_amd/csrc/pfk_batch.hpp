@@ -131,35 +131,32 @@ __global__ void __launch_bounds__(kBlock) kb_pcg_a(const BSys* sys, const int* o
   });
 }
 
-// G0: V_0 = v, partial ||v||^2 (PC0)
+// The inner GMRES of every member (GF_j, GD_j, GN as in a single solve; w~
+// alternates between the inner vector and the basis window's slot k).
+// Velocities are loaded where used in every member (the load-ahead form of
+// a single solve rounds alike).
 template <class T>
-__global__ void __launch_bounds__(kBlock) kb_gmpc_start(const BSys* sys, const int* off, int nsys) {
-  const int s = batch_find(off, nsys, (int)blockIdx.x);
-  const BSys& d = sys[s];
-  const Blk bk{(int)blockIdx.x - off[s], d.Pv};
-  if (bk.id >= bk.n) return;   // padding of the range
+__device__ __forceinline__ T* batch_gm_w(const BSys& d, int j) {
   const PcOutDesc& pd = d.pd;
-  gmpc_start_body<T>(bk, d.N, pd.k, pd.X1, pd.c1, pd.X2, pd.c2, (T*)const_cast<void*>(pd.vbase), d.part_pc0,
-                     d.st);
+  return (j & 1) ? (T*)const_cast<void*>(pd.vbase) + (long long)pd.k * pd.ldv : (T*)d.pc_q;
 }
-
-// GA_j: w = A D^-1 V_j (reads PC0).  Velocities are loaded where used in every
-// member (the load-ahead form of a single solve rounds alike).
-template <class T>
-__global__ void __launch_bounds__(kBlock) kb_gmpc_apply(const BSys* sys, const int* off, int nsys, int j) {
+// GF_j: reads PC1 (GD_{j-1}), writes PC0
+template <class T, int J>
+__global__ void __launch_bounds__(kBlock) kb_gmpc_fused(const BSys* sys, const int* off, int nsys, int j) {
   const int s = batch_find(off, nsys, (int)blockIdx.x);
   const BSys& d = sys[s];
   const Blk bk{(int)blockIdx.x - off[s], d.Ps};
   if (bk.id >= bk.n) return;   // padding of the range
   const PcOutDesc& pd = d.pd;
+  const T* wp = j > 0 ? batch_gm_w<T>(d, j - 1) : nullptr;
   with_inner_grid<T>(d, [&](const auto& g) {
-    gmpc_apply_body<T, std::decay_t<decltype(g)>, false>(bk, j, g, d.sg, (const T*)pd.dinv_in,
-                                                        (const T*)pd.vbase, pd.ldv, (T*)d.pc_q, d.part_pc0,
-                                                        d.Pv, d.st);
+    gmpc_fused_body<T, std::decay_t<decltype(g)>, false, J>(
+        bk, j, pd.k, g, d.sg, (const T*)pd.dinv_in, pd.X1, pd.c1, pd.X2, pd.c2, (T*)const_cast<void*>(pd.vbase),
+        pd.ldv, wp, batch_gm_w<T>(d, j), d.part_pc1, d.Pv, d.part_pc0, d.st);
   });
 }
 
-// GD_j: partials <V_i, w> (PC1)
+// GD_j: reads PC0 (GF_j's norm partials, one per stencil workgroup), writes PC1
 template <class T>
 __global__ void __launch_bounds__(kBlock) kb_gmpc_dots(const BSys* sys, const int* off, int nsys, int j) {
   const int s = batch_find(off, nsys, (int)blockIdx.x);
@@ -167,19 +164,20 @@ __global__ void __launch_bounds__(kBlock) kb_gmpc_dots(const BSys* sys, const in
   const Blk bk{(int)blockIdx.x - off[s], d.Pv};
   if (bk.id >= bk.n) return;   // padding of the range
   const PcOutDesc& pd = d.pd;
-  gmpc_dots_body<T>(bk, j, d.N, (const T*)pd.vbase, pd.ldv, (const T*)d.pc_q, d.part_pc1, d.st);
+  gmpc_dots_body<T>(bk, j, d.N, (const T*)pd.vbase, pd.ldv, batch_gm_w<T>(d, j), d.part_pc0, d.Ps,
+                    d.part_pc1, d.st);
 }
 
-// GO_j: V_{j+1} = w - sum h V_i, partial ||V_{j+1}||^2 (reads PC1, writes PC0)
+// GN: reads PC1, writes PC0 (the norm the consumer's least squares reads)
 template <class T>
-__global__ void __launch_bounds__(kBlock) kb_gmpc_orth(const BSys* sys, const int* off, int nsys, int j) {
+__global__ void __launch_bounds__(kBlock) kb_gmpc_norm(const BSys* sys, const int* off, int nsys, int j) {
   const int s = batch_find(off, nsys, (int)blockIdx.x);
   const BSys& d = sys[s];
   const Blk bk{(int)blockIdx.x - off[s], d.Pv};
   if (bk.id >= bk.n) return;   // padding of the range
   const PcOutDesc& pd = d.pd;
-  gmpc_orth_body<T>(bk, j, pd.k, d.N, (T*)const_cast<void*>(pd.vbase), pd.ldv, (const T*)d.pc_q, d.part_pc1,
-                    d.Pv, d.part_pc0, d.st);
+  gmpc_norm_body<T>(bk, j, d.N, (const T*)pd.vbase, pd.ldv, batch_gm_w<T>(d, j), d.part_pc1, d.Pv,
+                    d.part_pc0, d.st);
 }
 
 // ---- the block-Jacobi inner solve of every system -----------------------------

@@ -195,17 +195,29 @@ __device__ __forceinline__ void stnt(T* p, T v) {
 
 // Input of the stencil engine: load(t) issues the global loads of flat node t
 // and nothing else (its result is a value, or a struct of loaded values);
-// value(raw) forms the node's input u from them.  The engine issues loads one
-// plane step ahead and forms values only when their plane is reached, so no
-// arithmetic on loaded data makes a plane step wait for its own prefetch.
-template <class LoadF, class ValueF>
+// value(raw) forms the node's input u from them.  The engine issues loads
+// ahead and forms values only when their plane is reached, so no arithmetic
+// on loaded data makes a plane step wait for its own prefetch.  keep(t, raw)
+// is called once for every node the workgroup owns (never for its halo), with
+// the raw loads its value is formed from: a caller that also stores a value
+// derived from the input (the next inner basis vector, say) does it there.
+struct NoKeep {
+  template <class R>
+  __device__ __forceinline__ void operator()(long long, const R&) const {}
+};
+template <class LoadF, class ValueF, class KeepF = NoKeep>
 struct StencilIn {
   LoadF load;
   ValueF value;
+  KeepF keep;
 };
 template <class LoadF, class ValueF>
 __device__ __forceinline__ StencilIn<LoadF, ValueF> stencil_in(LoadF load, ValueF value) {
-  return StencilIn<LoadF, ValueF>{load, value};
+  return StencilIn<LoadF, ValueF>{load, value, NoKeep{}};
+}
+template <class LoadF, class ValueF, class KeepF>
+__device__ __forceinline__ StencilIn<LoadF, ValueF, KeepF> stencil_in(LoadF load, ValueF value, KeepF keep) {
+  return StencilIn<LoadF, ValueF, KeepF>{load, value, keep};
 }
 // An input formed where it is loaded (a plain load, or a combination the
 // caller evaluates at once).
@@ -323,8 +335,20 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
     um[r] = d3 ? U(r, k0 - 1) : zero;
-    uc[r] = k0 < k1 ? U(r, k0) : zero;
-    up[r] = d3 ? U(r, k0 + 1) : zero;
+    uc[r] = zero;
+    if (k0 < k1 && UOK(r, k0)) {
+      const long long t0 = vec_index(g, i, jr[r], k0);
+      const Raw q = in.load(t0);
+      uc[r] = T(in.value(q));
+      in.keep(t0, q);
+    }
+    up[r] = zero;
+    if (d3 && UOK(r, k0 + 1)) {
+      const long long t1 = vec_index(g, i, jr[r], k0 + 1);
+      const Raw q = in.load(t1);
+      up[r] = T(in.value(q));
+      if (k0 + 1 < k1) in.keep(t1, q);
+    }
     em[r] = d3 ? E(r, k0 - 1) : zero;
     ec[r] = E(r, k0);
     ep[r] = d3 ? E(r, k0 + 1) : zero;
@@ -456,6 +480,7 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
       um[r] = uc[r];
       uc[r] = up[r];
       up[r] = c2.ok[r] ? T(in.value(c2.u[r])) : zero;
+      if (c2.ok[r] && k + 2 < k1) in.keep(vec_index(g, i, jr[r], k + 2), c2.u[r]);
       em[r] = ec[r];
       ec[r] = ep[r];
       ep[r] = T(to_real(c2.e[r]));

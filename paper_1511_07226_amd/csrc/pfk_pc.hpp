@@ -432,39 +432,147 @@ k_pcg_a(int jstep, G g, StencilGeom sg, const T* __restrict__ dinv,
 }
 
 // ---- inner GMRES -----------------------------------------------------------
-// G0: V_0 = v (stored unnormalised), partial ||v||^2.
+// Right-Jacobi GMRES(k) from x = 0 (Arnoldi with classical Gram-Schmidt).
+// The basis is stored unnormalised: stored vector q is nu_q V_q with
+// nu_q = ||stored q|| (vs[q] = 1/nu_q), and the operator is applied to the
+// stored vector, w~_j = A D^-1 (stored j) = nu_j A D^-1 V_j.  Per step j two
+// passes:
+//   GF_j (stencil): the stored vector j is formed at every node from the
+//     previous step's data -- j = 0: v = c1 X1 + c2 X2; j >= 1:
+//     vs[j-1] w~_{j-1} - sum_{q<j} h(q,j-1) vs[q] (stored q), which is
+//     w_{j-1} - sum h(q,j-1) V_q -- stored, its squared norm summed, and
+//     w~_j = A D^-1 (stored j) computed from it in the same pass;
+//   GD_j (streaming): nu_j from GF_j's partials (beta0 for j = 0, else the
+//     subdiagonal h(j,j-1)), then <stored q, w~_j> for q <= j, from which
+//     GF_{j+1} takes h(q,j) = vs[q] vs[j] <stored q, w~_j>.
+// A final streaming pass GN forms step k-1's vector only for its norm
+// h(k,k-1), which the consumer's least squares reads (PC0).  A zero norm nu_j
+// ends the cycle at j columns (beta0 = 0 gives B(v) = 0, a zero subdiagonal
+// is a happy breakdown).  w~ alternates between two buffers (GF_j reads one
+// at halo nodes while writing the other).  Partial buffers: GF_j and GN
+// write PC0, GD_j writes PC1.
+
+// Column `col` of the Hessenberg from GD_col's partials: h(q,col) into the
+// scalars (workgroup 0), and the coefficients of the next stored vector,
+// cw = vs[col] for w~_col and c[q] = h(q,col) vs[q].  Every thread calls it.
+__device__ __forceinline__ double gm_column(Blk bk, int col, const double* part, int P, PcScalars* pcs,
+                                            double* c) {
+  const double sc = pcs->vs[col];
+  for (int q = 0; q <= col; ++q) {
+    const double hq = pcs->vs[q] * sc * block_sum_column(part, P, q);
+    if (threadIdx.x == 0) {
+      c[q] = hq * pcs->vs[q];
+      if (bk.id == 0) pcs->h[col * (kMaxInner + 1) + q] = hq;
+    }
+  }
+  __syncthreads();
+  return sc;
+}
+
+// Raw loads of GF_J at a node: D^-1 and, for J >= 1, w~_{J-1} and the first
+// RJ stored vectors (RJ = J for J <= kGfFixed, else kMaxInnerGmres - 1 with
+// the count taken at run time); for J = 0 the outer input v.
+constexpr int kGfFixed = 4;
+template <class T, int J>
+struct GfRaw {
+  static constexpr int RJ = J <= kGfFixed ? J : kMaxInnerGmres - 1;
+  T d, w;
+  T v[RJ > 0 ? RJ : 1];
+};
 template <class T>
-__device__ __forceinline__ void gmpc_start_body(Blk bk, long long N, int k, const double* X1, double c1, const double* X2, double c2,
-             T* __restrict__ V0, double* part_out, SolveState* st) {
+struct GfRaw<T, 0> {
+  T d;
+  double x1, x2;
+};
+
+template <class T, class G, bool CV, int J>
+__device__ __forceinline__ void gmpc_fused_body(Blk bk, int jstep, int k, G g, StencilGeom sg,
+                                                const T* __restrict__ dinv, const double* X1, double c1,
+                                                const double* X2, double c2, T* Vbase, long long ldv,
+                                                const T* wprev, T* __restrict__ wout, const double* part_in,
+                                                int P_in, double* part_out, SolveState* st) {
   if (!wg_running(st)) return;
-  if (bk.id == 0 && threadIdx.x == 0) st->pc.ncol = k;
+  PcScalars* pcs = &st->pc;
+  using R = GfRaw<T, J>;
   double acc[1] = {0.0};
-  for (long long e = bk.gtid(); e < N; e += bk.gstride()) {
-    double v = c1 * X1[e];
-    if (X2 != nullptr) v += c2 * X2[e];
-    const T vt = T(v);
-    V0[e] = vt;
-    acc[0] += (double)vt * (double)vt;
+  T* Vj = Vbase + (long long)jstep * ldv;
+  auto sink = [&](long long idx, T, T Au) { wout[idx] = Au; };
+  // FP32 with up to two basis terms: loads two plane steps ahead; longer
+  // bases take one step (the second plane of raw loads would cost an
+  // occupancy step: at 256^3, J = 3 and 4 ran 1-4% faster with one)
+  constexpr int PD = (sizeof(T) == 4 && J <= 2) ? 2 : 1;
+  if constexpr (J == 0) {
+    if (bk.id == 0 && threadIdx.x == 0) pcs->ncol = k;
+    auto load = [&](long long t) {
+      R q;
+      q.d = dinv[t];
+      q.x1 = X1[t];
+      q.x2 = X2 != nullptr ? X2[t] : 0.0;
+      return q;
+    };
+    auto form = [&](const R& q) {
+      double v = c1 * q.x1;
+      if (X2 != nullptr) v += c2 * q.x2;
+      return T(v);
+    };
+    auto value = [&](const R& q) { return q.d * form(q); };
+    auto keep = [&](long long t, const R& q) {
+      const T v = form(q);
+      Vj[t] = v;
+      acc[0] += (double)v * (double)v;
+    };
+    stencil_march<T, CV, PD>(g, sg, bk.id, stencil_in(load, value, keep), sink);
+  } else {
+    if (jstep >= pcs->ncol) return;     // an earlier step ended the cycle
+    __shared__ double s_c[kMaxInnerGmres];
+    const T cw = T(gm_column(bk, jstep - 1, part_in, P_in, pcs, s_c));
+    T c[R::RJ > 0 ? R::RJ : 1];
+#pragma unroll
+    for (int q = 0; q < R::RJ; ++q) c[q] = q < jstep ? T(s_c[q]) : T(0);
+    auto load = [&](long long t) {
+      R q;
+      q.d = dinv[t];
+      q.w = wprev[t];
+#pragma unroll
+      for (int p = 0; p < R::RJ; ++p) q.v[p] = (J <= kGfFixed || p < jstep) ? Vbase[(long long)p * ldv + t] : T(0);
+      return q;
+    };
+    auto form = [&](const R& q) {
+      T v = cw * q.w;
+#pragma unroll
+      for (int p = 0; p < R::RJ; ++p)
+        if (J <= kGfFixed || p < jstep) v -= c[p] * q.v[p];
+      return v;
+    };
+    auto value = [&](const R& q) { return q.d * form(q); };
+    auto keep = [&](long long t, const R& q) {
+      const T v = form(q);
+      Vj[t] = v;
+      acc[0] += (double)v * (double)v;
+    };
+    stencil_march<T, CV, PD>(g, sg, bk.id, stencil_in(load, value, keep), sink);
   }
   block_partials<1>(acc, 1, part_out, bk.n, bk.id);
 }
-template <class T>
+template <class T, class G, bool CV, int J>
 __global__ void __launch_bounds__(kBlock)
-k_gmpc_start(long long N, int k, const double* X1, double c1, const double* X2, double c2,
-             T* __restrict__ V0, double* part_out, SolveState* st) {
-  gmpc_start_body(this_blk(), N, k, X1, c1, X2, c2, V0, part_out, st);
+k_gmpc_fused(int jstep, int k, G g, StencilGeom sg, const T* __restrict__ dinv, const double* X1, double c1,
+             const double* X2, double c2, T* Vbase, long long ldv, const T* wprev, T* __restrict__ wout,
+             const double* part_in, int P_in, double* part_out, SolveState* st) {
+  gmpc_fused_body<T, G, CV, J>(this_blk(), jstep, k, g, sg, dinv, X1, c1, X2, c2, Vbase, ldv, wprev, wout,
+                               part_in, P_in, part_out, st);
 }
 
-// GA_j: scale of V_j from the previous norm (a zero norm ends the cycle:
-// beta = 0 gives B(v) = 0, a zero subdiagonal is a happy breakdown), then
-// w = A D^-1 V_j and partials <stored V_i, w> for i <= j.
-template <class T, class G, bool CV = false>
-__device__ __forceinline__ void gmpc_apply_body(Blk bk, int jstep, G g, StencilGeom sg, const T* __restrict__ dinv, const T* Vbase,
-             long long ldv, T* __restrict__ w, const double* part_in, int P_in, SolveState* st) {
+// GD_j: nu_j from GF_j's partials (PC0), then partials <stored q, w~_j> for
+// q <= j (PC1).
+template <class T>
+__device__ __forceinline__ void gmpc_dots_body(Blk bk, int jstep, long long N, const T* Vbase, long long ldv,
+                                               const T* __restrict__ w, const double* part_norm, int P_norm,
+                                               double* part_out, SolveState* st) {
   if (!wg_running(st)) return;
   PcScalars* pcs = &st->pc;
   if (jstep >= pcs->ncol) return;
-  const double nrm = sqrt(block_sum_column(part_in, P_in, 0));
+  const double nrm = sqrt(block_sum_column(part_norm, P_norm, 0));
   if (bk.id == 0 && threadIdx.x == 0) {
     if (jstep == 0) pcs->beta0 = nrm;
     else pcs->h[(jstep - 1) * (kMaxInner + 1) + jstep] = nrm;
@@ -472,30 +580,6 @@ __device__ __forceinline__ void gmpc_apply_body(Blk bk, int jstep, G g, StencilG
     if (nrm == 0.0) pcs->ncol = jstep;
   }
   if (nrm == 0.0) return;
-  const T sj = T(1.0 / nrm);
-  const T* Vj = Vbase + (long long)jstep * ldv;
-  struct Raw { T d, v; };
-  const auto in = stencil_in([&](long long t) { return Raw{dinv[t], Vj[t]}; },
-                             [&](const Raw& q) { return q.d * (sj * q.v); });
-  auto sink = [&](long long idx, T, T Au) { w[idx] = Au; };
-  // FP32: loads two plane steps ahead (the registers fit the same occupancy)
-  stencil_march<T, CV, sizeof(T) == 4 ? 2 : 1>(g, sg, bk.id, in, sink);
-}
-template <class T, class G, bool CV = false>
-__global__ void __launch_bounds__(kBlock)
-k_gmpc_apply(int jstep, G g, StencilGeom sg, const T* __restrict__ dinv, const T* Vbase,
-             long long ldv, T* __restrict__ w, const double* part_in, int P_in, SolveState* st) {
-  gmpc_apply_body<T, G, CV>(this_blk(), jstep, g, sg, dinv, Vbase, ldv, w, part_in, P_in, st);
-}
-
-// GD_j: partials <stored V_i, w> for i <= j.  A streaming pass of its own:
-// taken in the stencil's sink these loads would sit outside the stencil's
-// one-plane-ahead prefetch (measured: 2.1 TB/s for the fused kernel).
-template <class T>
-__device__ __forceinline__ void gmpc_dots_body(Blk bk, int jstep, long long N, const T* Vbase, long long ldv, const T* __restrict__ w, double* part_out,
-            SolveState* st) {
-  if (!wg_running(st)) return;
-  if (jstep >= st->pc.ncol) return;
   double acc[kMaxInnerGmres];
 #pragma unroll
   for (int q = 0; q < kMaxInnerGmres; ++q) acc[q] = 0.0;
@@ -526,61 +610,55 @@ __device__ __forceinline__ void gmpc_dots_body(Blk bk, int jstep, long long N, c
 }
 template <class T>
 __global__ void __launch_bounds__(kBlock)
-k_gmpc_dots(int jstep, long long N, const T* Vbase, long long ldv, const T* __restrict__ w, double* part_out,
-            SolveState* st) {
-  gmpc_dots_body(this_blk(), jstep, N, Vbase, ldv, w, part_out, st);
+k_gmpc_dots(int jstep, long long N, const T* Vbase, long long ldv, const T* __restrict__ w,
+            const double* part_norm, int P_norm, double* part_out, SolveState* st) {
+  gmpc_dots_body(this_blk(), jstep, N, Vbase, ldv, w, part_norm, P_norm, part_out, st);
 }
 
-// GO_j: h_ij = <V_i, w> (classical Gram-Schmidt), V_{j+1} = w - sum h_ij V_i
-// stored unnormalised (not stored for the last step), partial ||V_{j+1}||^2.
+// GN: column j = k-1 of the Hessenberg from GD_j's partials (PC1) and the
+// partial squared norm of vs[j] w~_j - sum h(q,j) vs[q] (stored q), the
+// subdiagonal h(k,k-1) (PC0).  The vector itself is not stored.
 template <class T>
-__device__ __forceinline__ void gmpc_orth_body(Blk bk, int jstep, int k, long long N, T* Vbase, long long ldv, const T* __restrict__ w,
-            const double* part_in, int P_in, double* part_out, SolveState* st) {
+__device__ __forceinline__ void gmpc_norm_body(Blk bk, int jstep, long long N, const T* Vbase, long long ldv,
+                                               const T* __restrict__ w, const double* part_in, int P_in,
+                                               double* part_out, SolveState* st) {
   if (!wg_running(st)) return;
   PcScalars* pcs = &st->pc;
   if (jstep >= pcs->ncol) return;
-  __shared__ double coef[kMaxInnerGmres];
-  for (int q = 0; q <= jstep; ++q) {
-    const double hq = pcs->vs[q] * block_sum_column(part_in, P_in, q);
-    if (threadIdx.x == 0) {
-      coef[q] = hq * pcs->vs[q];
-      if (bk.id == 0) pcs->h[jstep * (kMaxInner + 1) + q] = hq;
-    }
-  }
-  __syncthreads();
-  const bool store = jstep + 1 < k;
-  T* Vn = Vbase + (long long)(jstep + 1) * ldv;
+  __shared__ double s_c[kMaxInnerGmres];
+  const T cw = T(gm_column(bk, jstep, part_in, P_in, pcs, s_c));
   double acc[1] = {0.0};
-  // 16-byte accesses as in k_gmpc_dots, the same arithmetic per node
+  // 16-byte accesses as in k_gmpc_dots; the arithmetic per node is GF's
   constexpr int VW = 16 / sizeof(T);
   typedef T vec_t __attribute__((ext_vector_type(VW)));
   const long long nv = N / VW;
   for (long long qv = bk.gtid(); qv < nv; qv += bk.gstride()) {
     const long long e = qv * VW;
-    vec_t v = *reinterpret_cast<const vec_t*>(w + e);
+    const vec_t wv = *reinterpret_cast<const vec_t*>(w + e);
+    vec_t v;
+#pragma unroll
+    for (int l = 0; l < VW; ++l) v[l] = cw * wv[l];
     for (int q = 0; q <= jstep; ++q) {
       const vec_t vq = *reinterpret_cast<const vec_t*>(Vbase + (long long)q * ldv + e);
-      const T cq = T(coef[q]);
+      const T cq = T(s_c[q]);
 #pragma unroll
       for (int l = 0; l < VW; ++l) v[l] -= cq * vq[l];
     }
-    if (store) *reinterpret_cast<vec_t*>(Vn + e) = v;
 #pragma unroll
     for (int l = 0; l < VW; ++l) acc[0] += (double)v[l] * (double)v[l];
   }
   for (long long e = nv * VW + bk.gtid(); e < N; e += bk.gstride()) {
-    T v = w[e];
-    for (int q = 0; q <= jstep; ++q) v -= T(coef[q]) * Vbase[(long long)q * ldv + e];
-    if (store) Vn[e] = v;
+    T v = cw * w[e];
+    for (int q = 0; q <= jstep; ++q) v -= T(s_c[q]) * Vbase[(long long)q * ldv + e];
     acc[0] += (double)v * (double)v;
   }
   block_partials<1>(acc, 1, part_out, bk.n, bk.id);
 }
 template <class T>
 __global__ void __launch_bounds__(kBlock)
-k_gmpc_orth(int jstep, int k, long long N, T* Vbase, long long ldv, const T* __restrict__ w,
+k_gmpc_norm(int jstep, long long N, const T* Vbase, long long ldv, const T* __restrict__ w,
             const double* part_in, int P_in, double* part_out, SolveState* st) {
-  gmpc_orth_body(this_blk(), jstep, k, N, Vbase, ldv, w, part_in, P_in, part_out, st);
+  gmpc_norm_body(this_blk(), jstep, N, Vbase, ldv, w, part_in, P_in, part_out, st);
 }
 
 // ---- block-Jacobi PCG ------------------------------------------------------
