@@ -605,6 +605,8 @@ thread_local KernelProfiler* g_prof = nullptr;
     } else if ((pd).kind == kPcJacobiPcg) {                                                         \
       if ((pd).fp32) LAUNCH((k_apply_pc_out<kPcJacobiPcg, 1>), blocks, stream, __VA_ARGS__);        \
       else LAUNCH((k_apply_pc_out<kPcJacobiPcg, 0>), blocks, stream, __VA_ARGS__);                  \
+    } else if ((pd).kind == kPcJacobiGmres && (pd).fp32 && (pd).k <= kGmRaw) {                      \
+      LAUNCH((k_apply_pc_out<kPcJacobiGmres, 1>), blocks, stream, __VA_ARGS__);                     \
     } else {                                                                                        \
       LAUNCH((k_apply_pc_out<-1, 0>), blocks, stream, __VA_ARGS__);                                 \
     }                                                                                               \

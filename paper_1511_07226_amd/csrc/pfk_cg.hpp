@@ -173,6 +173,12 @@ __device__ __forceinline__ void apply_pc_out_t(Blk bk, const Grid& g, const Sten
       return r;
     };
     stencil_march<double>(g, sg, bk.id, stencil_in(load, value), sink);
+  } else if constexpr (K == kPcJacobiGmres) {
+    // FP32 inner GMRES output with at most kGmRaw columns (checked by the
+    // host); a convective operator's velocities are issued at the start of
+    // their plane step (the registers leave no room to load them a step ahead)
+    if (g.vel != nullptr) stencil_march<double, 2>(g, sg, bk.id, gm_raw_in(pc, X3, c3), sink);
+    else stencil_march<double>(g, sg, bk.id, gm_raw_in(pc, X3, c3), sink);
   } else {
     bool done = false;
     if constexpr (GM) {

@@ -263,13 +263,15 @@ __device__ __forceinline__ char* stencil_lds() {
   return buf;
 }
 
-// CV: the operator has face velocities, and they are loaded one plane step
-// ahead into registers like the column's u and eta (the z- face of a plane is
-// the z+ face of the one below, kept from the previous step).  Without CV a
-// convective operator still works: apply_faces then loads the velocities
-// when it needs them.  CV kernels are separate instantiations, so the
-// diffusion kernels do not carry the extra registers.
-template <int TX, bool CV, int PD, class T, class G, class In, class Sink>
+// CV: how the face velocities of a convective operator are loaded.
+// 0: where they are used (apply_faces; any operator), 1: one plane step
+// ahead into registers like the column's u and eta, 2: at the start of their
+// own plane step, so they are in flight during the step's barriers and LDS
+// exchange -- for kernels whose registers leave no room for a second plane of
+// velocities.  With 1 and 2 the z- face of a plane is the z+ face of the one
+// below, kept from the previous step.  CV kernels are separate
+// instantiations, so the diffusion kernels do not carry the extra registers.
+template <int TX, int CV, int PD, class T, class G, class In, class Sink>
 __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& sg, int bid, const In& in,
                                                 Sink& sink) {
   static_assert(PD >= 1 && PD <= 3, "prefetch depth 1..3 plane steps");
@@ -422,10 +424,10 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
       if (d3) v[4] = T(to_real(g.vel[2 * g.vstride + pc]));
     }
   };
-  if constexpr (CV) {
+  if constexpr (CV != 0) {
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-      if (k0 < k1) VL(r, k0, vc[r]);
+      if (CV == 1 && k0 < k1) VL(r, k0, vc[r]);
       vzm[r] = (d3 && valid[r] && k0 < k1) ? T(to_real(g.vel[2 * g.vstride + padded_index(g, i, jr[r], k0) - g.sz]))
                                            : zero;
     }
@@ -435,11 +437,14 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
     const ColRaw cn = issue_col(k + 1 + PD);
     const HaloRaw hn = issue_halo(k + 1 + PD);
     const bool more = k + 1 < k1;
-    if constexpr (CV) {
+    if constexpr (CV == 1) {
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
         if (more) VL(r, k + 1, vn[r]);
       }
+    } else if constexpr (CV == 2) {
+#pragma unroll
+      for (int r = 0; r < 2; ++r) VL(r, k, vc[r]);
     }
     T (*const su)[TX + 2] = SU(slot);
     T (*const se)[TX + 2] = SE(slot);
@@ -458,7 +463,7 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
       if (valid[r]) {
         const int rr = row[r] + 1;
         T Au;
-        if constexpr (CV) {
+        if constexpr (CV != 0) {
           const T uxp = su[rr][xo + 2], uxm = su[rr][xo], uyp = su[rr + 1][xo + 1], uym = su[rr - 1][xo + 1];
           Au = faces_diffusion<T>(g, uc[r], ec[r], se[rr][xo + 2], se[rr][xo], se[rr + 1][xo + 1],
                                   se[rr - 1][xo + 1], ep[r], em[r], uxp, uxm, uyp, uym, up[r], um[r]);
@@ -472,8 +477,8 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
         }
         sink(vec_index(g, i, jr[r], k), uc[r], Au);
       }
-      if constexpr (CV) {
-        vzm[r] = vc[r][4];
+      if constexpr (CV != 0) vzm[r] = vc[r][4];
+      if constexpr (CV == 1) {
 #pragma unroll
         for (int f = 0; f < 5; ++f) vc[r][f] = vn[r][f];
       }
@@ -505,12 +510,12 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
   }
 }
 
-template <class T, bool CV = false, int PD = 1, class G, class In, class Sink>
+template <class T, int CV = 0, int PD = 1, class G, class In, class Sink>
 __device__ __forceinline__ void stencil_march(const G& g, const StencilGeom& sg, int bid, const In& in, Sink& sink) {
   if (sg.tx == 32) stencil_march_t<32, CV, PD, T>(g, sg, bid, in, sink);
   else stencil_march_t<64, CV, PD, T>(g, sg, bid, in, sink);
 }
-template <class T, bool CV = false, int PD = 1, class G, class In, class Sink>
+template <class T, int CV = 0, int PD = 1, class G, class In, class Sink>
 __device__ __forceinline__ void stencil_march(const G& g, const StencilGeom& sg, const In& in, Sink& sink) {
   stencil_march<T, CV, PD>(g, sg, (int)blockIdx.x, in, sink);
 }
