@@ -644,9 +644,8 @@ PcOutDesc pc_out_desc(const pfk_session_s* S, const double* X1, double c1, const
   } else if (d.kind == kPcBlockPcg) {
     d.y = S->vec(V_PC_Y);
   } else if (d.kind == kPcJacobiGmres) {
-    // G0 and every GO_j write PC0: the final norm the consumer reads
-    d.part = S->part(PT_PC0);
-    d.P = S->Pv();
+    // the inner solve's end (k_gmpc_finish) leaves the coefficients in the
+    // solve's scalars
     d.vbase = S->win(W_PCV).base;
     d.ldv = S->L.ld;
   }
@@ -728,11 +727,10 @@ void enqueue_pc_kernels(pfk_session_s* S, hipStream_t s, const PcOutDesc& d, con
       const T* wp = j > 0 ? (const T*)w[(j - 1) & 1] : nullptr;
       launch_gmpc_fused<T, G>(S, s, cv, j, d.k, g, dinv, X1, c1, X2, c2, V, ldv, wp, w[j & 1],
                               (const double*)part[1], S->Pv(), part[0]);
-      LAUNCH((k_gmpc_dots<T>), S->Pv(), s, j, A->N, (const T*)V, ldv, (const T*)w[j & 1],
+      LAUNCH((k_gmpc_dots<T>), S->Pv(), s, j, d.k, A->N, (const T*)V, ldv, (const T*)w[j & 1],
              (const double*)part[0], S->Ps(), part[1], S->st);
     }
-    LAUNCH((k_gmpc_norm<T>), S->Pv(), s, d.k - 1, A->N, (const T*)V, ldv, (const T*)w[(d.k - 1) & 1],
-           (const double*)part[1], S->Pv(), part[0], S->st);
+    LAUNCH(k_gmpc_finish, 1, s, d.k, (const double*)part[1], S->Pv(), S->st);
   }
 }
 
@@ -1953,7 +1951,7 @@ void batch_inner_gmres(pfk_batch_s* Tb, const int* os, const int* ov, int n) {
     }
     LAUNCH((kb_gmpc_dots<T>), Tb->tot[kBpVec], s1, Tb->d_sys, ov, n, j);
   }
-  LAUNCH((kb_gmpc_norm<T>), Tb->tot[kBpVec], s1, Tb->d_sys, ov, n, Tb->pc_k - 1);
+  LAUNCH(kb_gmpc_finish, n, s1, Tb->d_sys, n);
 }
 
 // One outer iteration of every running member.

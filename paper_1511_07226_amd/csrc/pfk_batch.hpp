@@ -131,7 +131,7 @@ __global__ void __launch_bounds__(kBlock) kb_pcg_a(const BSys* sys, const int* o
   });
 }
 
-// The inner GMRES of every member (GF_j, GD_j, GN as in a single solve; w~
+// The inner GMRES of every member (GF_j, GD_j, GE as in a single solve; w~
 // alternates between the inner vector and the basis window's slot k).
 // Velocities are loaded where used in every member (the load-ahead form of
 // a single solve rounds alike).
@@ -164,20 +164,14 @@ __global__ void __launch_bounds__(kBlock) kb_gmpc_dots(const BSys* sys, const in
   const Blk bk{(int)blockIdx.x - off[s], d.Pv};
   if (bk.id >= bk.n) return;   // padding of the range
   const PcOutDesc& pd = d.pd;
-  gmpc_dots_body<T>(bk, j, d.N, (const T*)pd.vbase, pd.ldv, batch_gm_w<T>(d, j), d.part_pc0, d.Ps,
+  gmpc_dots_body<T>(bk, j, pd.k, d.N, (const T*)pd.vbase, pd.ldv, batch_gm_w<T>(d, j), d.part_pc0, d.Ps,
                     d.part_pc1, d.st);
 }
 
-// GN: reads PC1, writes PC0 (the norm the consumer's least squares reads)
-template <class T>
-__global__ void __launch_bounds__(kBlock) kb_gmpc_norm(const BSys* sys, const int* off, int nsys, int j) {
-  const int s = batch_find(off, nsys, (int)blockIdx.x);
-  const BSys& d = sys[s];
-  const Blk bk{(int)blockIdx.x - off[s], d.Pv};
-  if (bk.id >= bk.n) return;   // padding of the range
-  const PcOutDesc& pd = d.pd;
-  gmpc_norm_body<T>(bk, j, d.N, (const T*)pd.vbase, pd.ldv, batch_gm_w<T>(d, j), d.part_pc1, d.Pv,
-                    d.part_pc0, d.st);
+// GE: one workgroup per member (reads PC1)
+__global__ void __launch_bounds__(kBlock) kb_gmpc_finish(const BSys* sys, int nsys) {
+  const BSys& d = sys[blockIdx.x];
+  gmpc_finish_body(d.pd.k, d.part_pc1, d.Pv, d.st);
 }
 
 // ---- the block-Jacobi inner solve of every system -----------------------------

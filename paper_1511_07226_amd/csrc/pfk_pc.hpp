@@ -51,8 +51,7 @@ struct PcOutDesc {
   const void* dinv_in;          // D^-1 of the inner sweeps (T)
   const void* y;                // inner iterate (PCG), or final output (block PCG) (T)
   const void* pk;               // last inner direction (PCG) (T)
-  const double* part;           // partials of the last inner kernel (PCG: <p_k,q>; A_1 also <v,p_1>;
-                                //   GMRES: ||V_k||^2)
+  const double* part;           // partials of the last inner kernel (PCG: <p_k,q>; A_1 also <v,p_1>)
   int P;
   const void* vbase;            // inner GMRES basis (k+1 stored vectors, ldv apart) (T)
   long long ldv;
@@ -79,7 +78,7 @@ struct PcOut {
   const void* vbase;            // inner GMRES: B(v) = dinv * sum cf_j V_j
   long long ldv;
   int nv;
-  const double* cf;             // nv coefficients (in LDS)
+  const double* cf;             // nv coefficients (the solve's scalars)
   __device__ __forceinline__ double v(long long t) const {
     double r = c1 * X1[t];
     if (X2 != nullptr) r += c2 * X2[t];
@@ -150,47 +149,13 @@ __device__ __forceinline__ PcOut make_pc_out(const PcOutDesc& d, PcScalars* pcs)
   o.nv = 0;
   o.cf = nullptr;
   if (d.kind == kPcJacobiGmres) {
-    // least squares min || beta0 e_0 - H c || over the active columns (Givens)
+    // the least squares was solved once, at the end of the inner solve; its
+    // coefficients are copied to LDS (the per-node loops read them there)
     __shared__ double s_cf[kMaxInnerGmres];
-    __shared__ double H[(kMaxInnerGmres + 1) * kMaxInnerGmres];
-    __shared__ double g[kMaxInnerGmres + 1], cs[kMaxInnerGmres], sn[kMaxInnerGmres], yv[kMaxInnerGmres];
-    __shared__ int s_nv;
-    const int nc = pcs->ncol;
-    const double hk = (nc == d.k) ? sqrt(block_sum_column(d.part, d.P, 0)) : 0.0;
-    if (threadIdx.x == 0) {
-      constexpr int L = kMaxInner + 1, M = kMaxInnerGmres + 1;
-      for (int jj = 0; jj < nc; ++jj)
-        for (int ii = 0; ii <= jj + 1; ++ii) H[jj * M + ii] = pcs->h[jj * L + ii];
-      if (nc == d.k && nc > 0) H[(nc - 1) * M + nc] = hk;
-      for (int ii = 0; ii <= nc; ++ii) g[ii] = 0.0;
-      g[0] = pcs->beta0;
-      for (int jj = 0; jj < nc; ++jj) {
-        double* col = &H[jj * M];
-        for (int ii = 0; ii < jj; ++ii) {
-          const double a = col[ii], b = col[ii + 1];
-          col[ii] = cs[ii] * a + sn[ii] * b;
-          col[ii + 1] = -sn[ii] * a + cs[ii] * b;
-        }
-        const double a = col[jj], b = col[jj + 1];
-        const double dd = hypot(a, b);
-        cs[jj] = dd == 0.0 ? 1.0 : a / dd;
-        sn[jj] = dd == 0.0 ? 0.0 : b / dd;
-        col[jj] = dd;
-        col[jj + 1] = 0.0;
-        const double gi = g[jj];
-        g[jj] = cs[jj] * gi;
-        g[jj + 1] = -sn[jj] * gi;
-      }
-      for (int ii = nc - 1; ii >= 0; --ii) {
-        double acc = g[ii];
-        for (int jj = ii + 1; jj < nc; ++jj) acc -= H[jj * M + ii] * yv[jj];
-        yv[ii] = acc / H[ii * M + ii];
-      }
-      for (int ii = 0; ii < nc; ++ii) s_cf[ii] = yv[ii] * pcs->vs[ii];
-      s_nv = nc;
-    }
+    const int nv = pcs->nv;
+    if (threadIdx.x < nv) s_cf[threadIdx.x] = pcs->cf[threadIdx.x];
     __syncthreads();
-    o.nv = s_nv;
+    o.nv = nv;
     o.cf = s_cf;
   }
   return o;
@@ -445,12 +410,12 @@ k_pcg_a(int jstep, G g, StencilGeom sg, const T* __restrict__ dinv,
 //   GD_j (streaming): nu_j from GF_j's partials (beta0 for j = 0, else the
 //     subdiagonal h(j,j-1)), then <stored q, w~_j> for q <= j, from which
 //     GF_{j+1} takes h(q,j) = vs[q] vs[j] <stored q, w~_j>.
-// A final streaming pass GN forms step k-1's vector only for its norm
-// h(k,k-1), which the consumer's least squares reads (PC0).  A zero norm nu_j
+// GE (one workgroup) finishes: column k-1, its subdiagonal h(k,k-1) and the
+// least squares, whose coefficients the consumers read.  A zero norm nu_j
 // ends the cycle at j columns (beta0 = 0 gives B(v) = 0, a zero subdiagonal
 // is a happy breakdown).  w~ alternates between two buffers (GF_j reads one
-// at halo nodes while writing the other).  Partial buffers: GF_j and GN
-// write PC0, GD_j writes PC1.
+// at halo nodes while writing the other).  Partial buffers: GF_j writes PC0,
+// GD_j PC1.
 
 // Column `col` of the Hessenberg from GD_col's partials: h(q,col) into the
 // scalars (workgroup 0), and the coefficients of the next stored vector,
@@ -565,24 +530,15 @@ k_gmpc_fused(int jstep, int k, G g, StencilGeom sg, const T* __restrict__ dinv, 
 
 // GD_j: nu_j from GF_j's partials (PC0), then partials <stored q, w~_j> for
 // q <= j (PC1).
-template <class T>
-__device__ __forceinline__ void gmpc_dots_body(Blk bk, int jstep, long long N, const T* Vbase, long long ldv,
-                                               const T* __restrict__ w, const double* part_norm, int P_norm,
-                                               double* part_out, SolveState* st) {
-  if (!wg_running(st)) return;
-  PcScalars* pcs = &st->pc;
-  if (jstep >= pcs->ncol) return;
-  const double nrm = sqrt(block_sum_column(part_norm, P_norm, 0));
-  if (bk.id == 0 && threadIdx.x == 0) {
-    if (jstep == 0) pcs->beta0 = nrm;
-    else pcs->h[(jstep - 1) * (kMaxInner + 1) + jstep] = nrm;
-    pcs->vs[jstep] = nrm == 0.0 ? 0.0 : 1.0 / nrm;
-    if (nrm == 0.0) pcs->ncol = jstep;
-  }
-  if (nrm == 0.0) return;
+template <class T, bool WW>
+__device__ __forceinline__ void gmpc_dots_t(Blk bk, int jstep, long long N, const T* Vbase, long long ldv,
+                                            const T* __restrict__ w, double* part_out) {
+  // columns q <= j: <stored q, w~_j>; with WW (the last step) also column
+  // j+1: ||w~_j||^2, from which the last subdiagonal comes
   double acc[kMaxInnerGmres];
 #pragma unroll
   for (int q = 0; q < kMaxInnerGmres; ++q) acc[q] = 0.0;
+  double ww[1] = {0.0};
   // 16-byte accesses (four FP32 or two FP64 nodes per lane); vectors start
   // 256-byte aligned and ldv is a multiple of 32 elements
   constexpr int VW = 16 / sizeof(T);
@@ -599,66 +555,110 @@ __device__ __forceinline__ void gmpc_dots_body(Blk bk, int jstep, long long N, c
         for (int l = 0; l < VW; ++l) acc[q] += (double)vv[l] * (double)wv[l];
       }
     }
+    if constexpr (WW) {
+#pragma unroll
+      for (int l = 0; l < VW; ++l) ww[0] += (double)wv[l] * (double)wv[l];
+    }
   }
   for (long long e = nv * VW + bk.gtid(); e < N; e += bk.gstride()) {
     const double wv = (double)w[e];
 #pragma unroll
     for (int q = 0; q < kMaxInnerGmres; ++q)
       if (q <= jstep) acc[q] += (double)Vbase[(long long)q * ldv + e] * wv;
+    if constexpr (WW) ww[0] += wv * wv;
   }
   block_partials<kMaxInnerGmres>(acc, jstep + 1, part_out, bk.n, bk.id);
+  if constexpr (WW) {
+    __syncthreads();   // block_partials' LDS is reused
+    block_partials<1>(ww, 1, part_out + (long long)(jstep + 1) * bk.n, bk.n, bk.id);
+  }
 }
 template <class T>
-__global__ void __launch_bounds__(kBlock)
-k_gmpc_dots(int jstep, long long N, const T* Vbase, long long ldv, const T* __restrict__ w,
-            const double* part_norm, int P_norm, double* part_out, SolveState* st) {
-  gmpc_dots_body(this_blk(), jstep, N, Vbase, ldv, w, part_norm, P_norm, part_out, st);
-}
-
-// GN: column j = k-1 of the Hessenberg from GD_j's partials (PC1) and the
-// partial squared norm of vs[j] w~_j - sum h(q,j) vs[q] (stored q), the
-// subdiagonal h(k,k-1) (PC0).  The vector itself is not stored.
-template <class T>
-__device__ __forceinline__ void gmpc_norm_body(Blk bk, int jstep, long long N, const T* Vbase, long long ldv,
-                                               const T* __restrict__ w, const double* part_in, int P_in,
-                                               double* part_out, SolveState* st) {
+__device__ __forceinline__ void gmpc_dots_body(Blk bk, int jstep, int k, long long N, const T* Vbase,
+                                               long long ldv, const T* __restrict__ w, const double* part_norm,
+                                               int P_norm, double* part_out, SolveState* st) {
   if (!wg_running(st)) return;
   PcScalars* pcs = &st->pc;
   if (jstep >= pcs->ncol) return;
-  __shared__ double s_c[kMaxInnerGmres];
-  const T cw = T(gm_column(bk, jstep, part_in, P_in, pcs, s_c));
-  double acc[1] = {0.0};
-  // 16-byte accesses as in k_gmpc_dots; the arithmetic per node is GF's
-  constexpr int VW = 16 / sizeof(T);
-  typedef T vec_t __attribute__((ext_vector_type(VW)));
-  const long long nv = N / VW;
-  for (long long qv = bk.gtid(); qv < nv; qv += bk.gstride()) {
-    const long long e = qv * VW;
-    const vec_t wv = *reinterpret_cast<const vec_t*>(w + e);
-    vec_t v;
-#pragma unroll
-    for (int l = 0; l < VW; ++l) v[l] = cw * wv[l];
-    for (int q = 0; q <= jstep; ++q) {
-      const vec_t vq = *reinterpret_cast<const vec_t*>(Vbase + (long long)q * ldv + e);
-      const T cq = T(s_c[q]);
-#pragma unroll
-      for (int l = 0; l < VW; ++l) v[l] -= cq * vq[l];
-    }
-#pragma unroll
-    for (int l = 0; l < VW; ++l) acc[0] += (double)v[l] * (double)v[l];
+  const double nrm = sqrt(block_sum_column(part_norm, P_norm, 0));
+  if (bk.id == 0 && threadIdx.x == 0) {
+    if (jstep == 0) pcs->beta0 = nrm;
+    else pcs->h[(jstep - 1) * (kMaxInner + 1) + jstep] = nrm;
+    pcs->vs[jstep] = nrm == 0.0 ? 0.0 : 1.0 / nrm;
+    if (nrm == 0.0) pcs->ncol = jstep;
   }
-  for (long long e = nv * VW + bk.gtid(); e < N; e += bk.gstride()) {
-    T v = cw * w[e];
-    for (int q = 0; q <= jstep; ++q) v -= T(s_c[q]) * Vbase[(long long)q * ldv + e];
-    acc[0] += (double)v * (double)v;
-  }
-  block_partials<1>(acc, 1, part_out, bk.n, bk.id);
+  if (nrm == 0.0) return;
+  if (jstep + 1 == k) gmpc_dots_t<T, true>(bk, jstep, N, Vbase, ldv, w, part_out);
+  else gmpc_dots_t<T, false>(bk, jstep, N, Vbase, ldv, w, part_out);
 }
 template <class T>
 __global__ void __launch_bounds__(kBlock)
-k_gmpc_norm(int jstep, long long N, const T* Vbase, long long ldv, const T* __restrict__ w,
-            const double* part_in, int P_in, double* part_out, SolveState* st) {
-  gmpc_norm_body(this_blk(), jstep, N, Vbase, ldv, w, part_in, P_in, part_out, st);
+k_gmpc_dots(int jstep, int k, long long N, const T* Vbase, long long ldv, const T* __restrict__ w,
+            const double* part_norm, int P_norm, double* part_out, SolveState* st) {
+  gmpc_dots_body(this_blk(), jstep, k, N, Vbase, ldv, w, part_norm, P_norm, part_out, st);
+}
+
+// GE: the end of the inner solve, one workgroup.  Column k-1 of the
+// Hessenberg from GD_{k-1}'s partials (PC1), its subdiagonal from the
+// Pythagorean identity h(k,k-1)^2 = ||w_{k-1}||^2 - sum_q h(q,k-1)^2
+// (exact for an orthonormal basis, as PIPEFGMRES takes its own norms; a
+// value <= 0 counts as a happy breakdown, h = 0), then the small least
+// squares min || beta0 e_0 - H y || over the active columns (Givens
+// rotations), stored as cf[q] = y_q vs[q] for the consumers.
+__device__ __forceinline__ void gmpc_finish_body(int k, const double* part, int P, SolveState* st) {
+  if (!wg_running(st)) return;
+  PcScalars* pcs = &st->pc;
+  constexpr int L = kMaxInner + 1, M = kMaxInnerGmres + 1;
+  __shared__ double s_col[kMaxInnerGmres + 1];
+  __shared__ double H[M * kMaxInnerGmres];
+  __shared__ double g[M], cs[kMaxInnerGmres], sn[kMaxInnerGmres], yv[kMaxInnerGmres];
+  const int nc = pcs->ncol;
+  if (nc == k) block_sum_columns(part, P, k + 1, s_col);   // <stored q, w~_{k-1}>, q < k; ||w~_{k-1}||^2
+  if (threadIdx.x != 0) return;
+  double hk = 0.0;
+  if (nc == k) {
+    const double sc = pcs->vs[k - 1];
+    double t = sc * sc * s_col[k];
+    for (int q = 0; q < k; ++q) {
+      const double hq = pcs->vs[q] * sc * s_col[q];
+      pcs->h[(k - 1) * L + q] = hq;
+      t -= hq * hq;
+    }
+    hk = t > 0.0 ? sqrt(t) : 0.0;
+  }
+  for (int jj = 0; jj < nc; ++jj)
+    for (int ii = 0; ii <= jj + 1; ++ii) H[jj * M + ii] = pcs->h[jj * L + ii];
+  if (nc == k && nc > 0) H[(nc - 1) * M + nc] = hk;
+  for (int ii = 0; ii <= nc; ++ii) g[ii] = 0.0;
+  g[0] = pcs->beta0;
+  for (int jj = 0; jj < nc; ++jj) {
+    double* col = &H[jj * M];
+    for (int ii = 0; ii < jj; ++ii) {
+      const double a = col[ii], b = col[ii + 1];
+      col[ii] = cs[ii] * a + sn[ii] * b;
+      col[ii + 1] = -sn[ii] * a + cs[ii] * b;
+    }
+    const double a = col[jj], b = col[jj + 1];
+    const double dd = hypot(a, b);
+    cs[jj] = dd == 0.0 ? 1.0 : a / dd;
+    sn[jj] = dd == 0.0 ? 0.0 : b / dd;
+    col[jj] = dd;
+    col[jj + 1] = 0.0;
+    const double gi = g[jj];
+    g[jj] = cs[jj] * gi;
+    g[jj + 1] = -sn[jj] * gi;
+  }
+  for (int ii = nc - 1; ii >= 0; --ii) {
+    double acc = g[ii];
+    for (int jj = ii + 1; jj < nc; ++jj) acc -= H[jj * M + ii] * yv[jj];
+    yv[ii] = acc / H[ii * M + ii];
+  }
+  for (int ii = 0; ii < nc; ++ii) pcs->cf[ii] = yv[ii] * pcs->vs[ii];
+  pcs->nv = nc;
+}
+__global__ void __launch_bounds__(kBlock)
+k_gmpc_finish(int k, const double* part, int P, SolveState* st) {
+  gmpc_finish_body(k, part, P, st);
 }
 
 // ---- block-Jacobi PCG ------------------------------------------------------

@@ -31,6 +31,9 @@ struct PcScalars {                 // one inner solve's scalars, indexed by inne
   double vs[kMaxInner + 1];
   double beta0;
   int ncol;
+  // its least-squares result: B(v) = D^-1 sum_q cf[q] (stored q), q < nv
+  double cf[kMaxInner + 1];
+  int nv;
   // noisy preconditioner: applications of B this solve has used so far, and
   // whether the current phase runs
   unsigned long long ndraws;
