@@ -1954,6 +1954,24 @@ void batch_inner_gmres(pfk_batch_s* Tb, const int* os, const int* ov, int n) {
   LAUNCH(kb_gmpc_finish, n, s1, Tb->d_sys, n);
 }
 
+// The batched consumer of the inner solve's output, instantiated per inner
+// kind and storage (all members share them).
+void launch_batch_pc_out(pfk_batch_s* T, const int* os, int n, int pipefcg) {
+  hipStream_t s1 = T->s1;
+  const int K = T->pc_kind;
+  if (K == kPcBlockPcg) {
+    if (T->fp32) LAUNCH((kb_apply_pc_out<kPcBlockPcg, 1>), T->tot[kBpSten], s1, T->d_sys, os, n, pipefcg);
+    else LAUNCH((kb_apply_pc_out<kPcBlockPcg, 0>), T->tot[kBpSten], s1, T->d_sys, os, n, pipefcg);
+  } else if (K == kPcJacobiPcg) {
+    if (T->fp32) LAUNCH((kb_apply_pc_out<kPcJacobiPcg, 1>), T->tot[kBpSten], s1, T->d_sys, os, n, pipefcg);
+    else LAUNCH((kb_apply_pc_out<kPcJacobiPcg, 0>), T->tot[kBpSten], s1, T->d_sys, os, n, pipefcg);
+  } else if (K == kPcJacobiGmres && T->fp32 && T->pc_k <= kGmRaw) {
+    LAUNCH((kb_apply_pc_out<kPcJacobiGmres, 1>), T->tot[kBpSten], s1, T->d_sys, os, n, pipefcg);
+  } else {
+    LAUNCH((kb_apply_pc_out<-1, 0>), T->tot[kBpSten], s1, T->d_sys, os, n, pipefcg);
+  }
+}
+
 // One outer iteration of every running member.
 void enqueue_batch_iteration(pfk_batch_s* T) {
   const int n = (int)T->rows.size();
@@ -1987,7 +2005,7 @@ void enqueue_batch_iteration(pfk_batch_s* T) {
       LAUNCH(kb_pipefcg_scalars, n, s2, T->d_sys);
       (void)hipEventRecord(T->ev_join, s2);
       pc();
-      LAUNCH(kb_apply_pc_out, T->tot[kBpSten], s1, T->d_sys, os, n, 1);
+      launch_batch_pc_out(T, os, n, 1);
       (void)hipStreamWaitEvent(s1, T->ev_join, 0);
       break;
     case PFK_FCG:
@@ -2006,7 +2024,7 @@ void enqueue_batch_iteration(pfk_batch_s* T) {
       LAUNCH(kb_pgm_scalars, n, s2, T->d_sys);
       (void)hipEventRecord(T->ev_join, s2);
       pc();
-      LAUNCH(kb_apply_pc_out, T->tot[kBpSten], s1, T->d_sys, os, n, 0);
+      launch_batch_pc_out(T, os, n, 0);
       (void)hipStreamWaitEvent(s1, T->ev_join, 0);
       LAUNCH(kb_gm_update_x, T->tot[kBpVec], s1, T->d_sys, ov, n);
       break;

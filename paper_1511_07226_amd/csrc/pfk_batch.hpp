@@ -65,16 +65,21 @@ __global__ void __launch_bounds__(kBlock) kb_pipefcg_scalars(const BSys* sys) {
   pipefcg_scalars_body(Blk{0, 1}, d.part_main, d.Pv, d.st, d.hist);
 }
 
-// m = u + B(w - r), n = A m (PIPEFCG); wbar = A B(zbar) (PIPEFGMRES, O unused)
+// m = u + B(w - r), n = A m (PIPEFCG); wbar = A B(zbar) (PIPEFGMRES, O unused).
+// Every member has the same inner kind and storage, so the host picks the
+// instantiation (K, F32) as for a single solve, and each carries only its
+// own registers (K < 0: NONE, JACOBI, FP64 GMRES, decided at run time).
+template <int K, int F32>
 __global__ void __launch_bounds__(kBlock) kb_apply_pc_out(const BSys* sys, const int* off, int nsys, int pipefcg) {
   const int s = batch_find(off, nsys, (int)blockIdx.x);
   const BSys& d = sys[s];
   const Blk bk{(int)blockIdx.x - off[s], d.Ps};
   if (bk.id >= bk.n) return;   // padding of the range
+  if (!wg_running(d.st)) return;
   if (pipefcg)
-    apply_pc_out_body<true>(bk, d.g, d.sg, d.pd, d.u, 1.0, d.m, d.n, 0, nullptr, d.part_b, d.st);
+    apply_pc_out_t<K, F32, false>(bk, d.g, d.sg, d.pd, d.u, 1.0, d.m, d.n, 0, nullptr, d.part_b, d.st);
   else
-    apply_pc_out_body<true>(bk, d.g, d.sg, d.pd, nullptr, 0.0, nullptr, d.z, 0, nullptr, d.part_b, d.st);
+    apply_pc_out_t<K, F32, false>(bk, d.g, d.sg, d.pd, nullptr, 0.0, nullptr, d.z, 0, nullptr, d.part_b, d.st);
 }
 
 // ---- the global inner solves of every system ----------------------------------

@@ -198,10 +198,10 @@ __device__ __forceinline__ void apply_pc_out_t(Blk bk, const Grid& g, const Sten
   }
   if (dots) block_partials<2>(acc, 2, part, sg.blocks(), bk.id);
 }
-// The inner solve's output kind and storage are fixed per instantiation for
-// the two inner-CG forms (the hot cases); the others decide at run time.
-// GM: the run-time branch also carries the FP32 inner-GMRES load-ahead path
-// (more registers; the phased batched kernel takes it, the persistent one not).
+// Every output kind in one body, for the persistent kernel (whose members'
+// kinds are NONE, JACOBI or block PCG): the two inner-CG forms have their own
+// branches, the others decide at run time.  GM: the run-time branch also
+// carries the FP32 inner-GMRES load-ahead path (more registers).
 template <bool GM = false>
 __device__ __forceinline__ void apply_pc_out_body(Blk bk, Grid g, StencilGeom sg, PcOutDesc pd, const double* X3,
                                                   double c3, double* __restrict__ O, double* __restrict__ Nout,
