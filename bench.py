@@ -216,6 +216,45 @@ def conv_diff_bench(pfk, torch, steps, warmup):
     return conv
 
 
+def conv_diff_tts(pfk, torch, contrasts=(4.0, 2.0), restarts=(30, 60), maxit=3000):
+    """Configuration 3 as a solve: the 256^3 convection-diffusion sinker to
+    rtol 1e-8 from x = 0 by FGMRES, PIPEFGMRES, GCR and PIPEGCR (GMRES(5)
+    inner solve in FP32 on BF16 viscosity), restart/window 30 and 60, at the
+    configured viscosity contrast 1e4 and at 1e2; CR types with stagnation
+    restarts (window 200).  Reports iterations, restarts, the true relative
+    residual reached and seconds (one solve each, graphs captured inside)."""
+    import gen
+    out = {"workload": "256^3 conv-diff sinker (cell Peclet 5), rtol 1e-8, maxit %d, B = GMRES(5) FP32/BF16" % maxit}
+    for c in contrasts:
+        log(f"generating the 256^3 convection-diffusion workload, contrast 1e{c:g}")
+        p = gen.make_problem(3, 256, 20, c, 0, convection=True)
+        A = pfk.Operator(p.dim, p.n, p.eta, p.vel)
+        B = pfk.Precond(A, "jacobi_gmres", INNER, precision=pfk.FP32_BF16COEF)
+        b = torch.as_tensor(p.b).cuda()
+        del p
+        sigma = pfk.estimate_sigma(A, B)
+        row = {}
+        for method in ("fgmres", "pipefgmres", "gcr", "pipegcr"):
+            for m in restarts:
+                opts = {"shift_sigma": sigma} if method == "pipefgmres" else {}
+                if method in ("gcr", "pipegcr"):
+                    opts.update(stall_window=200, max_restarts=1000)
+                x = torch.zeros_like(b)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                info = pfk.solve(A, B, method, b, x, rtol=1e-8, maxit=maxit, mmax=m, graph_iters=10, **opts)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                row[f"{method}_{m}"] = {"iterations": info.iterations, "restarts": info.restarts,
+                                        "converged": bool(info.converged),
+                                        "true_rel_resid": float(f"{info.true_rel_resid:.3e}"),
+                                        "seconds": round(dt, 2)}
+                log(f"contrast 1e{c:g} {method}({m}): {row[f'{method}_{m}']}")
+        out[f"contrast_1e{c:g}"] = row
+        del A, B, b
+    return out
+
+
 def size_sweep(pfk, torch, steps=40):
     """PIPEFCG against FCG per outer iteration on single systems of growing size
     (block-Jacobi inner solve, FP64, nu_max 30), in the graph-launched form and
@@ -700,6 +739,8 @@ def main():
     ap.add_argument("--serving-direct", action="store_true",
                     help="serving batches launch kernels directly instead of replaying graphs")
     ap.add_argument("--no-stagnation", action="store_true")
+    ap.add_argument("--conv-diff-tts", action="store_true",
+                    help="headline plus configuration 3 solved to rtol 1e-8 (256^3, contrasts 1e4 and 1e2)")
     ap.add_argument("--conv-diff-only", action="store_true",
                     help="headline plus the 256^3 convection-diffusion comparison")
     ap.add_argument("--stagnation-only", action="store_true",
@@ -783,6 +824,9 @@ def main():
     if args.conv_diff_only:
         args.headline_only = True
         extra["conv_diff_256"] = conv_diff_bench(pfk, torch, args.steps, args.warmup)
+    if args.conv_diff_tts:
+        args.headline_only = True
+        extra["conv_diff_tts"] = conv_diff_tts(pfk, torch)
     loads = tuple(float(v) for v in args.serving_loads.split(",") if v)
     if args.serving_only:
         args.headline_only = True
