@@ -690,6 +690,53 @@ def pmc_summary(csv_path: str, kernel: str = "", last: int = 0) -> str:
     return "\n".join(lines)
 
 
+def trace_overlap(trace_csv: str, group_a: str, group_b: str) -> str:
+    """How long two groups of kernels (comma-separated name prefixes, short
+    names) ran at the same time in a rocprofv3 kernel trace: the busy time of
+    each group (union of its kernels' intervals), of both together, and of
+    their intersection -- e.g. the kernels of two serving batches that run
+    on their own streams."""
+    import csv
+    pa = tuple(x for x in group_a.split(",") if x)
+    pb = tuple(x for x in group_b.split(",") if x)
+    ia, ib = [], []
+    with open(trace_csv, newline="") as f:
+        for r in csv.DictReader(f):
+            name = _short_kernel_name(r["Kernel_Name"])
+            iv = (int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
+            if name.startswith(pa):
+                ia.append(iv)
+            elif name.startswith(pb):
+                ib.append(iv)
+
+    def union(iv):
+        out = []
+        for s0, e0 in sorted(iv):
+            if out and s0 <= out[-1][1]:
+                out[-1][1] = max(out[-1][1], e0)
+            else:
+                out.append([s0, e0])
+        return out
+
+    ua, ub = union(ia), union(ib)
+    both = 0
+    i = j = 0
+    while i < len(ua) and j < len(ub):
+        lo, hi = max(ua[i][0], ub[j][0]), min(ua[i][1], ub[j][1])
+        if lo < hi:
+            both += hi - lo
+        if ua[i][1] < ub[j][1]:
+            i += 1
+        else:
+            j += 1
+    busy = lambda u: sum(e0 - s0 for s0, e0 in u) / 1e9
+    span = (max(e for _, e in ia + ib) - min(s for s, _ in ia + ib)) / 1e9 if ia and ib else 0.0
+    return (f"group A ({group_a}): {len(ia)} kernels, busy {busy(ua):.3f} s\n"
+            f"group B ({group_b}): {len(ib)} kernels, busy {busy(ub):.3f} s\n"
+            f"either busy {busy(union(ia + ib)):.3f} s over a span of {span:.3f} s; "
+            f"both at once {both / 1e9:.3f} s")
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--pmc-summary":
         sp = argparse.ArgumentParser()
@@ -698,6 +745,14 @@ def main():
         sp.add_argument("--last", type=int, default=0)
         a = sp.parse_args()
         print(pmc_summary(a.pmc_summary, a.kernel, a.last))
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "--trace-overlap":
+        sp = argparse.ArgumentParser()
+        sp.add_argument("--trace-overlap", required=True, help="rocprofv3 *_kernel_trace.csv")
+        sp.add_argument("--a", required=True, help="comma-separated kernel name prefixes")
+        sp.add_argument("--b", required=True, help="comma-separated kernel name prefixes")
+        a = sp.parse_args()
+        print(trace_overlap(a.trace_overlap, a.a, a.b))
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--trace-summary":
         sp = argparse.ArgumentParser()
