@@ -525,10 +525,31 @@ __device__ __forceinline__ void stencil_march(const G& g, const StencilGeom& sg,
 // part[c * P + b] (P = number of workgroups).  The sums over b are taken in
 // a fixed order by the consumer, so results are deterministic run to run.
 // ---------------------------------------------------------------------------
+// Sum over the 64 lanes of a wave, the same value in every lane: an
+// inclusive scan within each row of 16 lanes (DPP row shifts by 1, 2, 4, 8),
+// the row totals carried across rows (row broadcasts of lanes 15 and 31),
+// then lane 63's total read into a scalar.  DPP moves data between lanes in
+// the VALU; a shuffle would go through the LDS crossbar (two permutes per
+// step for a double): in the window update, which sums a dot per window
+// direction, the shuffle form cost about 1.3% of the kernel's time.
+// Lanes outside a row's shift range contribute 0 (bound_ctrl), rows outside
+// a broadcast's row mask keep their value.
+template <int CTRL, int RM>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, RM, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, RM, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
+  v += dpp_mov<0x111, 0xf>(v);   // row_shr:1
+  v += dpp_mov<0x112, 0xf>(v);   // row_shr:2
+  v += dpp_mov<0x114, 0xf>(v);   // row_shr:4
+  v += dpp_mov<0x118, 0xf>(v);   // row_shr:8
+  v += dpp_mov<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_mov<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 
 // Sum NC per-thread accumulators over the workgroup; column c of workgroup
