@@ -36,20 +36,29 @@ INNER = 5
 # two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB), each scaled by what the same counter reads for a 2 GiB
 # device-to-device copy (FETCH_SIZE reads 1,048,588 KiB for 2,097,152 KiB
 # moved: x2.000; WRITE_SIZE reads 2,097,152: x1.000).  Valid only for the
-# kernel source it was measured on (digest of its device body and of the
-# load/store helpers it uses).
-UPDATE_TRAFFIC = {"body_sha1": "05d1aabc1535ecd7", "fetch_kib": 8257680.1, "fetch_scale": 2.0,
-                  "write_kib": 1050720.5, "write_scale": 1.0}
+# kernel source it was measured on (digest of its device body, of the
+# load/store helpers and of the wave reduction it uses).
+UPDATE_TRAFFIC = {"body_sha1": "b68eb769c76b8849", "fetch_kib": 8257680.5, "fetch_scale": 2.0,
+                  "write_kib": 1052892.6, "write_scale": 1.0}
+
+
+def update_traffic_digest():
+    """Digest of k_pipefcg_update's device body, its load/store helpers and the
+    wave reduction it calls."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_1511_07226_amd", "csrc", "pfk_cg.hpp")).read()
+    i = src.index("__device__ __forceinline__ double2 ld2(")
+    j = src.index("k_pipefcg_update(", i)
+    dev = open(os.path.join(ROOT, "paper_1511_07226_amd", "csrc", "pfk_device.hpp")).read()
+    k = dev.index("template <int CTRL, int RM>")
+    m = dev.index("__device__ __forceinline__ void block_partials", k)
+    return hashlib.sha1((src[i:j] + dev[k:m]).encode()).hexdigest()[:16]
 
 
 def update_traffic_bytes():
     """Measured bytes per launch of k_pipefcg_update, or None when its source
     has changed since the counters were taken."""
-    import hashlib
-    src = open(os.path.join(ROOT, "paper_1511_07226_amd", "csrc", "pfk_cg.hpp")).read()
-    i = src.index("__device__ __forceinline__ double2 ld2(")
-    j = src.index("k_pipefcg_update(", i)
-    if hashlib.sha1(src[i:j].encode()).hexdigest()[:16] != UPDATE_TRAFFIC["body_sha1"]:
+    if update_traffic_digest() != UPDATE_TRAFFIC["body_sha1"]:
         return None
     t = UPDATE_TRAFFIC
     return round((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0)
