@@ -828,10 +828,16 @@ k_pipegcr_init_scalars(const double* part, int P, SolveState* st) {
 // q_j = m + sum beta q_d into slot j, then x += alpha p_j, r -= alpha s_j,
 // u -= alpha q_j.  m = u + B(w - r) is evaluated from the inner solve's
 // output; for the first direction after a (re)start it is q_0's B(s_0).
-__global__ void __launch_bounds__(kBlock)
-k_pipegcr_update(long long N, Window P, Window S, Window Q, double* __restrict__ x, double* __restrict__ r,
-                 double* __restrict__ u, const double* __restrict__ w, PcOutDesc pd, SolveState* st) {
-  if (!wg_running(st)) return;
+// As in PIPEFCG's update: two consecutive nodes per lane (16-byte accesses,
+// nontemporal for large solves), the three windows' loads of a direction
+// taken together (twelve in flight with the loop unrolled by four), and an
+// FP32 inner GMRES output read two nodes per 8-byte load.  Each node's
+// arithmetic is the one-node form's, in the same order.
+template <bool NT>
+__device__ __forceinline__ void pipegcr_update_body_t(Blk bk, long long N, Window P, Window S, Window Q,
+                                                      double* __restrict__ x, double* __restrict__ r,
+                                                      double* __restrict__ u, const double* __restrict__ w,
+                                                      PcOutDesc pd, SolveState* st) {
   __shared__ double s_beta[kNuMax];
   __shared__ long long s_off[kNuMax];
   const int j = st->j;
@@ -848,23 +854,61 @@ k_pipegcr_update(long long N, Window P, Window S, Window Q, double* __restrict__
   }
   __syncthreads();
   const long long ns = (long long)(j % numax) * P.ld;
-  for (long long e = gtid(); e < N; e += gstride()) {
-    const double ue = u[e];
-    double p = ue, s = w[e], q = cu * ue + pc(e);
+  const bool gm2 = gm_raw_ok(pc);
+  const float* gmV = static_cast<const float*>(pc.vbase);
+  const float* gmD = static_cast<const float*>(pc.dinv_in);
+  const long long npair = (N + 1) / 2;
+  for (long long qp = bk.gtid(); qp < npair; qp += bk.gstride()) {
+    const long long e = 2 * qp;
+    const bool full = e + 1 < N;
+    const double2 u0 = ld2<NT>(u, e, full), w0 = ld2<NT>(w, e, full);
+    double2 bv;
+    if (gm2 && full) {
+      float2 vq[kGmRaw];
+#pragma unroll
+      for (int q = 0; q < kGmRaw; ++q)
+        vq[q] = q < pc.nv ? *reinterpret_cast<const float2*>(gmV + (long long)q * pc.ldv + e) : make_float2(0.f, 0.f);
+      const float2 dv = *reinterpret_cast<const float2*>(gmD + e);
+      double r0 = 0.0, r1 = 0.0;
+#pragma unroll
+      for (int q = 0; q < kGmRaw; ++q) {
+        if (q < pc.nv) {
+          r0 += pc.cf[q] * (double)vq[q].x;
+          r1 += pc.cf[q] * (double)vq[q].y;
+        }
+      }
+      bv = make_double2((double)dv.x * r0, (double)dv.y * r1);
+    } else {
+      bv = make_double2(pc(e), full ? pc(e + 1) : 0.0);
+    }
+    double2 p = u0, sv = w0;
+    double2 q = make_double2(cu * u0.x + bv.x, cu * u0.y + bv.y);
+#pragma unroll 4
     for (int t = 0; t < nu; ++t) {
       const double b = s_beta[t];
       const long long o = s_off[t] + e;
-      p += b * P.base[o];
-      s += b * S.base[o];
-      q += b * Q.base[o];
+      const double2 pv = ld2<NT>(P.base, o, full), svv = ld2<NT>(S.base, o, full), qv = ld2<NT>(Q.base, o, full);
+      p.x += b * pv.x; p.y += b * pv.y;
+      sv.x += b * svv.x; sv.y += b * svv.y;
+      q.x += b * qv.x; q.y += b * qv.y;
     }
-    P.base[ns + e] = p;
-    S.base[ns + e] = s;
-    Q.base[ns + e] = q;
-    x[e] += alpha * p;
-    r[e] -= alpha * s;
-    u[e] = ue - alpha * q;
+    st2<NT>(P.base, ns + e, p, full);
+    st2<NT>(S.base, ns + e, sv, full);
+    st2<NT>(Q.base, ns + e, q, full);
+    double2 x0 = ld2<NT>(x, e, full), r0v = ld2<NT>(r, e, full);
+    x0.x += alpha * p.x; x0.y += alpha * p.y;
+    r0v.x -= alpha * sv.x; r0v.y -= alpha * sv.y;
+    st2<NT>(x, e, x0, full);
+    st2<NT>(r, e, r0v, full);
+    st2<NT>(u, e, make_double2(u0.x - alpha * q.x, u0.y - alpha * q.y), full);
   }
+}
+__global__ void __launch_bounds__(kBlock)
+k_pipegcr_update(long long N, Window P, Window S, Window Q, double* __restrict__ x, double* __restrict__ r,
+                 double* __restrict__ u, const double* __restrict__ w, PcOutDesc pd, SolveState* st) {
+  if (!wg_running(st)) return;
+  if (st->nt) pipegcr_update_body_t<true>(this_blk(), N, P, S, Q, x, r, u, w, pd, st);
+  else pipegcr_update_body_t<false>(this_blk(), N, P, S, Q, x, r, u, w, pd, st);
 }
 
 }  // namespace pfk
