@@ -86,10 +86,11 @@ def iteration_bytes(method: str, nu: int, k: int, N: int, pc: str = "global", mi
     vectors and D^-1 take w bytes (8, or 4 in the mixed form) and its
     viscosity c bytes (8, or 2 for BF16).
     Global Jacobi-PCG with k steps: A_1 reads the v inputs, D^-1 and eta and
-    writes p, q; each B_j reads p, q, rho (the v inputs for j = 1), y (j > 1)
-    and D^-1 and writes y, rho; each A_j (j > 1) reads rho, D^-1, p and eta and
+    writes p, q; each B_j reads q, rho (the v inputs for j = 1) and D^-1 and
+    writes rho, and the last one (j = k - 1) also reads p_1 .. p_{k-1} and
+    writes the iterate y; each A_j (j > 1) reads rho, D^-1, p and eta and
     writes p, q.  Block-Jacobi PCG: one pass reads the v inputs and eta and
-    writes y.  The consumer forms m = u + B(v) (PIPEFCG) and applies A."""
+    writes y.  The consumer forms m = u + B(v) (PIPEFCG) and applies A.""" 
     W = 8.0
     w, c = (4.0, 2.0) if mixed else (8.0, 8.0)
     if pc == "block":
@@ -97,10 +98,12 @@ def iteration_bytes(method: str, nu: int, k: int, N: int, pc: str = "global", mi
         tail_pc = w                                    # the consumer reads y
     else:
         pcb = 2 * W + w + c + 2 * w                    # A_1
-        # B_j: reads rho (the two FP64 v inputs for j = 1), y (j > 1), p, q, D^-1; writes y, rho
-        pcb += 2 * W + (k - 2) * w + (k - 2) * w + (k - 1) * (3 * w + 2 * w)
+        if k > 1:
+            # B_j: reads rho (the two FP64 v inputs for j = 1), q, D^-1; writes rho
+            pcb += 2 * W + 3 * w + (k - 2) * 4 * w
+            pcb += (k - 1) * w + w                     # the last B: p_1 .. p_{k-1} in, y out
         pcb += (k - 1) * (3 * w + c + 2 * w)           # A_j: rho, D^-1, p, eta; writes p, q
-        tail_pc = 2 * w                                # the consumer reads y and p_k
+        tail_pc = 2 * w if k > 1 else w                # the consumer reads y and p_k
     if method == "pipefcg":
         upd = (4 * nu + 14) * W
         tail = tail_pc + 2 * W + 2 * W                 # reads u, eta; writes m, n

@@ -417,11 +417,11 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 enum Vec {
   V_R, V_U, V_W, V_M, V_N,                       // outer work vectors
-  V_PC_P0, V_PC_P1, V_PC_Q, V_PC_RHO, V_PC_Y,    // inner PCG
+  V_PC_Q, V_PC_RHO, V_PC_Y,                      // inner PCG (its directions: window W_PCP)
   V_X0, V_Z, V_VIN,                              // GMRES family: cycle start x, z / wbar, basis input
   V_COUNT
 };
-enum Win { W_P, W_S, W_Q, W_Z, W_PCV, W_COUNT };  // W_PCV: inner GMRES basis
+enum Win { W_P, W_S, W_Q, W_Z, W_PCV, W_PCP, W_COUNT };  // W_PCV: inner GMRES basis; W_PCP: inner PCG directions
 enum Part { PT_MAIN, PT_A, PT_B, PT_PC0, PT_PC1, PT_COUNT };
 
 struct Layout {
@@ -473,6 +473,7 @@ Layout make_layout(const pfk_operator_s* A, const pfk_precond_s* B, int method, 
   }
   window_slots(method, mmax, L.slots);
   if (B && B->kind == PFK_PC_JACOBI_GMRES) L.slots[W_PCV] = B->k + 1;
+  if (B && B->kind == PFK_PC_JACOBI_PCG) L.slots[W_PCP] = B->k;
   for (int w = 0; w < W_COUNT; ++w) {
     L.win[w] = off;
     off += vbytes * (size_t)L.slots[w];
@@ -638,7 +639,8 @@ PcOutDesc pc_out_desc(const pfk_session_s* S, const double* X1, double c1, const
   if (d.kind == kPcJacobiPcg) {
     // A_1, (B_j, A_{j+1}) alternate the partial buffers: A_k writes PC0
     d.y = S->vec(V_PC_Y);
-    d.pk = S->vec((d.k - 1) & 1 ? V_PC_P1 : V_PC_P0);
+    d.pk = (const char*)S->win(W_PCP).base +
+           (size_t)(d.k - 1) * (size_t)S->L.ld * (d.fp32 ? sizeof(float) : sizeof(double));
     d.part = S->part(PT_PC0);
     d.P = S->Ps();
   } else if (d.kind == kPcBlockPcg) {
@@ -688,20 +690,22 @@ void enqueue_pc_kernels(pfk_session_s* S, hipStream_t s, const PcOutDesc& d, con
   const double c1 = d.c1, c2 = d.c2;
   double* part[2] = {S->part(PT_PC0), S->part(PT_PC1)};
   if (d.kind == kPcJacobiPcg) {
-    T* pp[2] = {(T*)S->vec(V_PC_P0), (T*)S->vec(V_PC_P1)};
+    // directions p_1 .. p_k in the window's slots 0 .. k-1 (T elements, ld apart)
+    T* Pb = (T*)S->win(W_PCP).base;
+    const long long ldp = S->L.ld;
     T* q = (T*)S->vec(V_PC_Q);
     T* rho = (T*)S->vec(V_PC_RHO);
     T* y = (T*)S->vec(V_PC_Y);
-    LAUNCH((k_pcg_a1<T, G>), S->Ps(), s, g, S->sg, dinv, X1, c1, X2, c2, pp[0], q, part[0],
+    LAUNCH((k_pcg_a1<T, G>), S->Ps(), s, g, S->sg, dinv, X1, c1, X2, c2, Pb, q, part[0],
            (const SolveState*)S->st);
     int t = 1, Pprev = S->Ps();
     for (int j = 1; j < d.k; ++j) {
-      LAUNCH((k_pcg_b<T>), S->Pv(), s, j, A->N, dinv, X1, c1, X2, c2, (const T*)pp[(j - 1) & 1], (const T*)q, rho,
+      LAUNCH((k_pcg_b<T>), S->Pv(), s, j, d.k, A->N, dinv, X1, c1, X2, c2, (const T*)Pb, ldp, (const T*)q, rho,
              y, (const double*)part[(t - 1) & 1], Pprev, part[t & 1], S->st);
       Pprev = S->Pv();
       ++t;
-      LAUNCH((k_pcg_a<T, G>), S->Ps(), s, j + 1, g, S->sg, dinv, (const T*)rho, (const T*)pp[(j - 1) & 1],
-             pp[j & 1], q, (const double*)part[(t - 1) & 1], Pprev, part[t & 1], S->st);
+      LAUNCH((k_pcg_a<T, G>), S->Ps(), s, j + 1, g, S->sg, dinv, (const T*)rho, (const T*)(Pb + (j - 1) * ldp),
+             Pb + j * ldp, q, (const double*)part[(t - 1) & 1], Pprev, part[t & 1], S->st);
       Pprev = S->Ps();
       ++t;
     }
@@ -1852,8 +1856,8 @@ BSys make_bsys(const pfk_session_s* S) {
   d.S = S->win(W_S);
   d.Q = S->win(W_Q);
   d.Z = S->win(W_Z);
-  d.pc_p0 = S->vec(V_PC_P0);
-  d.pc_p1 = S->vec(V_PC_P1);
+  d.pc_pbase = S->win(W_PCP).base;
+  d.pc_ldp = S->L.ld;
   d.pc_q = S->vec(V_PC_Q);
   d.pc_rho = S->vec(V_PC_RHO);
   d.part_pc0 = S->part(PT_PC0);

@@ -27,8 +27,9 @@ struct BSys {
   int bj_wx, bj_wy, bj_n; // its block-preconditioner launch (workgroups along x, y; total)
   int pc_k;               // inner iterations
   PcOutDesc pd;           // where B(v) comes from (input vectors, the inner solve's buffers)
-  void *pc_p0, *pc_p1;    // global inner solves' work vectors (arithmetic type of the inner sweeps):
-  void *pc_q, *pc_rho;    //   PCG directions, A p, residual; GMRES: pc_q holds w = A D^-1 V_j
+  void* pc_pbase;         // global inner solves' work vectors (arithmetic type of the inner sweeps):
+  long long pc_ldp;       //   PCG directions p_1 .. p_k (pc_ldp elements apart), A p, residual;
+  void *pc_q, *pc_rho;    //   GMRES: pc_q holds w~
   double *part_pc0, *part_pc1;   // their partial sums
   Window P, S, Q, Z;      // direction windows (method-dependent roles, as in a single solve)
   double *x, *r, *u, *w, *m, *n, *z, *x0;
@@ -102,12 +103,12 @@ __global__ void __launch_bounds__(kBlock) kb_pcg_a1(const BSys* sys, const int* 
   if (bk.id >= bk.n) return;   // padding of the range
   const PcOutDesc& pd = d.pd;
   with_inner_grid<T>(d, [&](const auto& g) {
-    pcg_a1_body<T>(bk, g, d.sg, (const T*)pd.dinv_in, pd.X1, pd.c1, pd.X2, pd.c2, (T*)d.pc_p0, (T*)d.pc_q,
+    pcg_a1_body<T>(bk, g, d.sg, (const T*)pd.dinv_in, pd.X1, pd.c1, pd.X2, pd.c2, (T*)d.pc_pbase, (T*)d.pc_q,
                    d.part_pc0, d.st);
   });
 }
 
-// B_j: y += alpha p_j, rho -= alpha q (reads A_j's partials, PC0; writes PC1)
+// B_j: rho -= alpha q, the last one also y (reads A_j's partials, PC0; writes PC1)
 template <class T>
 __global__ void __launch_bounds__(kBlock) kb_pcg_b(const BSys* sys, const int* off, int nsys, int j) {
   const int s = batch_find(off, nsys, (int)blockIdx.x);
@@ -115,9 +116,9 @@ __global__ void __launch_bounds__(kBlock) kb_pcg_b(const BSys* sys, const int* o
   const Blk bk{(int)blockIdx.x - off[s], d.Pv};
   if (bk.id >= bk.n) return;   // padding of the range
   const PcOutDesc& pd = d.pd;
-  const T* pj = (const T*)((j - 1) & 1 ? d.pc_p1 : d.pc_p0);
-  pcg_b_body<T>(bk, j, d.N, (const T*)pd.dinv_in, pd.X1, pd.c1, pd.X2, pd.c2, pj, (const T*)d.pc_q,
-                (T*)d.pc_rho, (T*)const_cast<void*>(pd.y), d.part_pc0, d.Ps, d.part_pc1, d.st);
+  pcg_b_body<T>(bk, j, d.pc_k, d.N, (const T*)pd.dinv_in, pd.X1, pd.c1, pd.X2, pd.c2, (const T*)d.pc_pbase,
+                d.pc_ldp, (const T*)d.pc_q, (T*)d.pc_rho, (T*)const_cast<void*>(pd.y), d.part_pc0, d.Ps,
+                d.part_pc1, d.st);
 }
 
 // A_{j+1}: p_{j+1} = D^-1 rho + beta p_j, q = A p_{j+1} (reads PC1, writes PC0)
@@ -128,8 +129,8 @@ __global__ void __launch_bounds__(kBlock) kb_pcg_a(const BSys* sys, const int* o
   const Blk bk{(int)blockIdx.x - off[s], d.Ps};
   if (bk.id >= bk.n) return;   // padding of the range
   const PcOutDesc& pd = d.pd;
-  const T* pj = (const T*)((j - 1) & 1 ? d.pc_p1 : d.pc_p0);
-  T* pn = (T*)(j & 1 ? d.pc_p1 : d.pc_p0);
+  const T* pj = (const T*)d.pc_pbase + (long long)(j - 1) * d.pc_ldp;
+  T* pn = (T*)d.pc_pbase + (long long)j * d.pc_ldp;
   with_inner_grid<T>(d, [&](const auto& g) {
     pcg_a_body<T>(bk, j + 1, g, d.sg, (const T*)pd.dinv_in, (const T*)d.pc_rho, pj, pn, (T*)d.pc_q,
                   d.part_pc1, d.Pv, d.part_pc0, d.st);

@@ -244,11 +244,18 @@ k_pcg_a1(G g, StencilGeom sg, const T* __restrict__ dinv,
   pcg_a1_body(this_blk(), g, sg, dinv, X1, c1, X2, c2, pout, qout, part, st);
 }
 
-// ---- B_j (1 <= j < k): y += alpha p, rho -= alpha q, partial <rho, D^-1 rho> --
+// ---- B_j (1 <= j < k): rho -= alpha q, partial <rho, D^-1 rho> ---------------
+// The iterate y = sum_{i<k} alpha_i p_i is formed once, by the last B
+// (j = k-1), from the stored directions p_1 .. p_{k-1} (slot i-1 of P) and
+// the step lengths the earlier B's recorded: the accumulation
+// y += alpha_i p_i in the same order and type as a running update, without
+// reading and writing y at every step (k = 5 at 256^3: six fewer vector
+// passes per inner solve).  A stopped step (zero or non-positive curvature)
+// leaves rho and y as they are, as does every later one.
 template <class T>
-__device__ __forceinline__ void pcg_b_body(Blk bk, int jstep, long long N, const T* __restrict__ dinv,
+__device__ __forceinline__ void pcg_b_body(Blk bk, int jstep, int k, long long N, const T* __restrict__ dinv,
         const double* X1, double c1, const double* X2, double c2,
-        const T* __restrict__ p, const T* __restrict__ q,
+        const T* Pbase, long long ldp, const T* __restrict__ q,
         T* __restrict__ rho, T* __restrict__ y,
         const double* part_in, int P_in, double* part_out, SolveState* st) {
   if (!wg_running(st)) return;
@@ -268,7 +275,30 @@ __device__ __forceinline__ void pcg_b_body(Blk bk, int jstep, long long N, const
   if (bk.id == 0 && threadIdx.x == 0) {
     if (jstep == 1) pcs->gamma[1] = gj;
     pcs->stopped[jstep] = stopped;
+    pcs->alpha[jstep] = (double)alpha;
   }
+  const bool last = jstep + 1 == k;
+  // the earlier steps' lengths (their stops are monotone: once stopped, every
+  // later step is); those with a stop contribute nothing
+  __shared__ double s_al[kMaxInner + 2];
+  __shared__ int s_nl;    // leading steps that contribute to y
+  if (last) {
+    if (threadIdx.x == 0) {
+      int nl = 0;
+      for (int i = 1; i < jstep; ++i) {
+        if (pcs->stopped[i]) break;
+        s_al[i] = pcs->alpha[i];
+        nl = i;
+      }
+      if (nl == jstep - 1 && !stopped) {
+        s_al[jstep] = (double)alpha;
+        nl = jstep;
+      }
+      s_nl = nl;
+    }
+    __syncthreads();
+  }
+  const int nl = last ? s_nl : 0;
   double acc[1] = {0.0};
   // VW nodes per lane (16-byte accesses to the T vectors; all vectors start
   // 16-byte aligned), the scalar tail after; nontemporal accesses for vectors
@@ -286,19 +316,10 @@ __device__ __forceinline__ void pcg_b_body(Blk bk, int jstep, long long N, const
       if constexpr (NT) stnt(a, v);
       else *a = v;
     };
-    auto node = [&](T r, T yv, T pv, T qv, T dv, T& ro, T& yo) {
-      if (!stopped) {
-        yv += alpha * pv;
-        r -= alpha * qv;
-      }
-      yo = yv;
-      ro = r;
-      acc[0] += (double)r * (double)(dv * r);
-    };
     const long long nv = N / VW;
     for (long long qv = bk.gtid(); qv < nv; qv += bk.gstride()) {
       const long long e = qv * VW;
-      tv_t r, yv;
+      tv_t r;
       if (jstep == 1) {
         const dv_t x1 = ld(reinterpret_cast<const dv_t*>(X1 + e));
         dv_t x2 = {};
@@ -308,46 +329,52 @@ __device__ __forceinline__ void pcg_b_body(Blk bk, int jstep, long long N, const
           double rv = c1 * x1[l];
           if (X2 != nullptr) rv += c2 * x2[l];
           r[l] = T(rv);
-          yv[l] = T(0);
         }
       } else {
         r = ld(reinterpret_cast<const tv_t*>(rho + e));
-        yv = ld(reinterpret_cast<const tv_t*>(y + e));
       }
-      tv_t pv = {}, qv4 = {};
-      if (!stopped) {
-        pv = ld(reinterpret_cast<const tv_t*>(p + e));
-        qv4 = ld(reinterpret_cast<const tv_t*>(q + e));
-      }
+      tv_t qv4 = {};
+      if (!stopped) qv4 = ld(reinterpret_cast<const tv_t*>(q + e));
       const tv_t dv = ld(reinterpret_cast<const tv_t*>(dinv + e));
-      tv_t ro, yo;
+      tv_t ro;
 #pragma unroll
       for (int l = 0; l < VW; ++l) {
-        T rl, yl;
-        node(r[l], yv[l], pv[l], qv4[l], dv[l], rl, yl);
+        T rl = r[l];
+        if (!stopped) rl -= alpha * qv4[l];
         ro[l] = rl;
-        yo[l] = yl;
+        acc[0] += (double)rl * (double)(dv[l] * rl);
       }
-      sto(reinterpret_cast<tv_t*>(y + e), yo);
       sto(reinterpret_cast<tv_t*>(rho + e), ro);
+      if (last) {
+        tv_t yv = {};
+#pragma unroll 4
+        for (int i = 1; i <= nl; ++i) {
+          const T ai = T(s_al[i]);
+          const tv_t pi = ld(reinterpret_cast<const tv_t*>(Pbase + (long long)(i - 1) * ldp + e));
+#pragma unroll
+          for (int l = 0; l < VW; ++l) yv[l] += ai * pi[l];
+        }
+        sto(reinterpret_cast<tv_t*>(y + e), yv);
+      }
     }
     for (long long e = nv * VW + bk.gtid(); e < N; e += bk.gstride()) {
-      T r, yv;
+      T r;
       if (jstep == 1) {
         double rv = c1 * ld(X1 + e);
         if (X2 != nullptr) rv += c2 * ld(X2 + e);
         r = T(rv);
-        yv = T(0);
       } else {
         r = ld(rho + e);
-        yv = ld(y + e);
       }
-      const T pv = stopped ? T(0) : ld(p + e);
-      const T qv = stopped ? T(0) : ld(q + e);
-      T ro, yo;
-      node(r, yv, pv, qv, ld(dinv + e), ro, yo);
-      sto(y + e, yo);
-      sto(rho + e, ro);
+      if (!stopped) r -= alpha * ld(q + e);
+      const T dv = ld(dinv + e);
+      acc[0] += (double)r * (double)(dv * r);
+      sto(rho + e, r);
+      if (last) {
+        T yv = T(0);
+        for (int i = 1; i <= nl; ++i) yv += T(s_al[i]) * ld(Pbase + (long long)(i - 1) * ldp + e);
+        sto(y + e, yv);
+      }
     }
   };
   if (st->nt) sweep(std::true_type{});
@@ -356,12 +383,12 @@ __device__ __forceinline__ void pcg_b_body(Blk bk, int jstep, long long N, const
 }
 template <class T>
 __global__ void __launch_bounds__(kBlock)
-k_pcg_b(int jstep, long long N, const T* __restrict__ dinv,
+k_pcg_b(int jstep, int k, long long N, const T* __restrict__ dinv,
         const double* X1, double c1, const double* X2, double c2,
-        const T* __restrict__ p, const T* __restrict__ q,
+        const T* Pbase, long long ldp, const T* __restrict__ q,
         T* __restrict__ rho, T* __restrict__ y,
         const double* part_in, int P_in, double* part_out, SolveState* st) {
-  pcg_b_body(this_blk(), jstep, N, dinv, X1, c1, X2, c2, p, q, rho, y, part_in, P_in, part_out, st);
+  pcg_b_body(this_blk(), jstep, k, N, dinv, X1, c1, X2, c2, Pbase, ldp, q, rho, y, part_in, P_in, part_out, st);
 }
 
 // ---- A_j (2 <= j <= k): p_j = D^-1 rho + beta p_{j-1}, q = A p_j -------------

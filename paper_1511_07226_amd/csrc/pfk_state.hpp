@@ -25,6 +25,7 @@ constexpr int kMaxInner = 32;      // largest inner iteration count of a precond
 struct PcScalars {                 // one inner solve's scalars, indexed by inner step
   double gamma[kMaxInner + 2];
   int stopped[kMaxInner + 2];
+  double alpha[kMaxInner + 2];    // inner PCG step lengths (in the inner arithmetic type)
   // inner GMRES: Hessenberg h(i,j) at h[j*(kMaxInner+1)+i], basis scales
   // (V_j = vs[j] * stored vector j), active columns
   double h[(kMaxInner + 1) * kMaxInner];

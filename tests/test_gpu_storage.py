@@ -14,9 +14,10 @@ layout differs from the paper's count the test names the reason:
   qbar and wbar are single work vectors, and zbar_k + sigma p_k is formed
   from the p and zbar windows where the update uses it.
 
-The fixed part is the same for every method: 13 work vectors (outer r, u,
-w, m, n; the inner PCG's five; x0, z, the basis input), plus the inner
-GMRES basis (k + 1 vectors) when that preconditioner is used.
+The fixed part is the same for every method: 11 work vectors (outer r, u,
+w, m, n; the inner PCG's q, rho and y; x0, z, the basis input), plus the
+inner PCG's k directions when that preconditioner is used (the iterate is
+formed once from them) or the inner GMRES basis (k + 1 vectors).
 """
 import sys
 
@@ -37,7 +38,7 @@ PER_DIRECTION = {
     "fgmres": (2, 2),
     "pipefgmres": (3, 4),
 }
-FIXED_VECTORS = 13
+FIXED_VECTORS = 11
 
 
 @pytest.fixture(scope="module")
@@ -82,10 +83,13 @@ def test_fixed_part_and_inner_gmres_basis(pfk):
     vb = _vec_bytes(A.N)
     Bp = pfk.Precond(A, "jacobi_pcg", 5)
     Bg = pfk.Precond(A, "jacobi_gmres", 5)
-    # the inner GMRES basis (k + 1 vectors) is the only preconditioner-dependent part
+    # the inner GMRES basis (k + 1 vectors) against the inner PCG's k directions
+    # is the only preconditioner-dependent part
+    Bn = pfk.Precond(A, "jacobi", 0)
     for method in ("fcg", "pipefcg", "fgmres"):
         d = pfk.workspace_bytes(A, Bg, method, 10, 200) - pfk.workspace_bytes(A, Bp, method, 10, 200)
-        assert d == 6 * vb
+        assert d == 1 * vb
+        assert pfk.workspace_bytes(A, Bp, method, 10, 200) - pfk.workspace_bytes(A, Bn, method, 10, 200) == 5 * vb
     # total minus the window slots is the same for every method (work vectors,
     # state, histories, partial sums) and holds the 13 work vectors
     m = 10
