@@ -727,14 +727,12 @@ void enqueue_pc_kernels(pfk_session_s* S, hipStream_t s, const PcOutDesc& d, con
     T* w[2] = {(T*)S->vec(V_PC_Q), V + (long long)d.k * ldv};
     const bool cv = A->vel != nullptr;
     for (int j = 0; j < d.k; ++j) {
-      // GF_j reads GD_{j-1}'s partials (PC1), writes PC0; GD_j reads PC0, writes PC1
+      // GF_j reads GF_{j-1}'s partials and writes its own (PC0 and PC1 in turn)
       const T* wp = j > 0 ? (const T*)w[(j - 1) & 1] : nullptr;
       launch_gmpc_fused<T, G>(S, s, cv, j, d.k, g, dinv, X1, c1, X2, c2, V, ldv, wp, w[j & 1],
-                              (const double*)part[1], S->Pv(), part[0]);
-      LAUNCH((k_gmpc_dots<T>), S->Pv(), s, j, d.k, A->N, (const T*)V, ldv, (const T*)w[j & 1],
-             (const double*)part[0], S->Ps(), part[1], S->st);
+                              (const double*)part[(j + 1) & 1], S->Ps(), part[j & 1]);
     }
-    LAUNCH(k_gmpc_finish, 1, s, d.k, (const double*)part[1], S->Pv(), S->st);
+    LAUNCH(k_gmpc_finish, 1, s, d.k, (const double*)part[(d.k - 1) & 1], S->Ps(), S->st);
   }
 }
 
@@ -1942,7 +1940,7 @@ void batch_inner_pcg(pfk_batch_s* Tb, const int* os, const int* ov, int n) {
   }
 }
 template <class T>
-void batch_inner_gmres(pfk_batch_s* Tb, const int* os, const int* ov, int n) {
+void batch_inner_gmres(pfk_batch_s* Tb, const int* os, int n) {
   hipStream_t s1 = Tb->s1;
   for (int j = 0; j < Tb->pc_k; ++j) {
     switch (j) {
@@ -1953,7 +1951,6 @@ void batch_inner_gmres(pfk_batch_s* Tb, const int* os, const int* ov, int n) {
       case 4: LAUNCH((kb_gmpc_fused<T, 4>), Tb->tot[kBpSten], s1, Tb->d_sys, os, n, j); break;
       default: LAUNCH((kb_gmpc_fused<T, kGfFixed + 1>), Tb->tot[kBpSten], s1, Tb->d_sys, os, n, j); break;
     }
-    LAUNCH((kb_gmpc_dots<T>), Tb->tot[kBpVec], s1, Tb->d_sys, ov, n, j);
   }
   LAUNCH(kb_gmpc_finish, n, s1, Tb->d_sys, n);
 }
@@ -1994,8 +1991,8 @@ void enqueue_batch_iteration(pfk_batch_s* T) {
         else batch_inner_pcg<double>(T, os, ov, n);
         break;
       case kPcJacobiGmres:
-        if (T->fp32) batch_inner_gmres<float>(T, os, ov, n);
-        else batch_inner_gmres<double>(T, os, ov, n);
+        if (T->fp32) batch_inner_gmres<float>(T, os, n);
+        else batch_inner_gmres<double>(T, os, n);
         break;
       default:
         break;   // NONE, JACOBI: B(v) is evaluated by its consumer

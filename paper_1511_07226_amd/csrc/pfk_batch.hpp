@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(kBlock) kb_apply_pc_out(const BSys* sys, const
 // ---- the global inner solves of every system ----------------------------------
 // The same phases a single solve launches (pfk_pc.hpp), each over all members:
 // k-step Jacobi-PCG as A_1, then (B_j, A_{j+1}) for j < k; k-step right-Jacobi
-// GMRES as G0, then (GA_j, GD_j, GO_j) for j < k.  Every member of a batch has
+// GMRES as GF_j for j < k, then GE.  Every member of a batch has
 // the same inner kind, precision and step count k.  T: the inner arithmetic
 // (FP32 sweeps run on the BF16 viscosity copy).
 template <class T, class F>
@@ -137,16 +137,19 @@ __global__ void __launch_bounds__(kBlock) kb_pcg_a(const BSys* sys, const int* o
   });
 }
 
-// The inner GMRES of every member (GF_j, GD_j, GE as in a single solve; w~
-// alternates between the inner vector and the basis window's slot k).
-// Velocities are loaded where used in every member (the load-ahead form of
-// a single solve rounds alike).
+// The inner GMRES of every member (GF_j and GE as in a single solve; w~
+// and the partials alternate between two buffers).  Velocities are loaded
+// where used in every member (the load-ahead form of a single solve rounds
+// alike).
 template <class T>
 __device__ __forceinline__ T* batch_gm_w(const BSys& d, int j) {
   const PcOutDesc& pd = d.pd;
   return (j & 1) ? (T*)const_cast<void*>(pd.vbase) + (long long)pd.k * pd.ldv : (T*)d.pc_q;
 }
-// GF_j: reads PC1 (GD_{j-1}), writes PC0
+__device__ __forceinline__ double* batch_gm_part(const BSys& d, int j) {
+  return (j & 1) ? d.part_pc1 : d.part_pc0;
+}
+// GF_j: reads GF_{j-1}'s partials, writes its own
 template <class T, int J>
 __global__ void __launch_bounds__(kBlock) kb_gmpc_fused(const BSys* sys, const int* off, int nsys, int j) {
   const int s = batch_find(off, nsys, (int)blockIdx.x);
@@ -156,28 +159,16 @@ __global__ void __launch_bounds__(kBlock) kb_gmpc_fused(const BSys* sys, const i
   const PcOutDesc& pd = d.pd;
   const T* wp = j > 0 ? batch_gm_w<T>(d, j - 1) : nullptr;
   with_inner_grid<T>(d, [&](const auto& g) {
-    gmpc_fused_body<T, std::decay_t<decltype(g)>, false, J>(
+    gmpc_fused_body<T, std::decay_t<decltype(g)>, 0, J>(
         bk, j, pd.k, g, d.sg, (const T*)pd.dinv_in, pd.X1, pd.c1, pd.X2, pd.c2, (T*)const_cast<void*>(pd.vbase),
-        pd.ldv, wp, batch_gm_w<T>(d, j), d.part_pc1, d.Pv, d.part_pc0, d.st);
+        pd.ldv, wp, batch_gm_w<T>(d, j), batch_gm_part(d, j + 1), d.Ps, batch_gm_part(d, j), d.st);
   });
 }
 
-// GD_j: reads PC0 (GF_j's norm partials, one per stencil workgroup), writes PC1
-template <class T>
-__global__ void __launch_bounds__(kBlock) kb_gmpc_dots(const BSys* sys, const int* off, int nsys, int j) {
-  const int s = batch_find(off, nsys, (int)blockIdx.x);
-  const BSys& d = sys[s];
-  const Blk bk{(int)blockIdx.x - off[s], d.Pv};
-  if (bk.id >= bk.n) return;   // padding of the range
-  const PcOutDesc& pd = d.pd;
-  gmpc_dots_body<T>(bk, j, pd.k, d.N, (const T*)pd.vbase, pd.ldv, batch_gm_w<T>(d, j), d.part_pc0, d.Ps,
-                    d.part_pc1, d.st);
-}
-
-// GE: one workgroup per member (reads PC1)
+// GE: one workgroup per member (reads GF_{k-1}'s partials)
 __global__ void __launch_bounds__(kBlock) kb_gmpc_finish(const BSys* sys, int nsys) {
   const BSys& d = sys[blockIdx.x];
-  gmpc_finish_body(d.pd.k, d.part_pc1, d.Pv, d.st);
+  gmpc_finish_body(d.pd.k, batch_gm_part(d, d.pd.k - 1), d.Ps, d.st);
 }
 
 // ---- the block-Jacobi inner solve of every system -----------------------------

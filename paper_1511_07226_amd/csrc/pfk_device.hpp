@@ -197,13 +197,18 @@ __device__ __forceinline__ void stnt(T* p, T v) {
 // and nothing else (its result is a value, or a struct of loaded values);
 // value(raw) forms the node's input u from them.  The engine issues loads
 // ahead and forms values only when their plane is reached, so no arithmetic
-// on loaded data makes a plane step wait for its own prefetch.  keep(t, raw)
-// is called once for every node the workgroup owns (never for its halo), with
-// the raw loads its value is formed from: a caller that also stores a value
-// derived from the input (the next inner basis vector, say) does it there.
+// on loaded data makes a plane step wait for its own prefetch.  keep(t, raw,
+// slot) is called once for every node the workgroup owns (never for its
+// halo), with the raw loads its value is formed from: a caller that also
+// stores a value derived from the input (the next inner basis vector, say)
+// does it there.  slot = 2 (plane & 1) + row names the node among the
+// thread's own nodes of two consecutive planes; a node is kept two plane
+// steps before its sink call, and a sink that takes a fourth argument gets
+// the same slot, so a caller can hand per-node data from keep to sink
+// through thread-private storage of four entries.
 struct NoKeep {
   template <class R>
-  __device__ __forceinline__ void operator()(long long, const R&) const {}
+  __device__ __forceinline__ void operator()(long long, const R&, int) const {}
 };
 template <class LoadF, class ValueF, class KeepF = NoKeep>
 struct StencilIn {
@@ -342,14 +347,14 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
       const long long t0 = vec_index(g, i, jr[r], k0);
       const Raw q = in.load(t0);
       uc[r] = T(in.value(q));
-      in.keep(t0, q);
+      in.keep(t0, q, ((k0 & 1) << 1) | r);
     }
     up[r] = zero;
     if (d3 && UOK(r, k0 + 1)) {
       const long long t1 = vec_index(g, i, jr[r], k0 + 1);
       const Raw q = in.load(t1);
       up[r] = T(in.value(q));
-      if (k0 + 1 < k1) in.keep(t1, q);
+      if (k0 + 1 < k1) in.keep(t1, q, (((k0 + 1) & 1) << 1) | r);
     }
     em[r] = d3 ? E(r, k0 - 1) : zero;
     ec[r] = E(r, k0);
@@ -475,7 +480,10 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
                               se[rr - 1][xo + 1], ep[r], em[r], su[rr][xo + 2], su[rr][xo], su[rr + 1][xo + 1],
                               su[rr - 1][xo + 1], up[r], um[r]);
         }
-        sink(vec_index(g, i, jr[r], k), uc[r], Au);
+        if constexpr (std::is_invocable_v<Sink&, long long, T, T, int>)
+          sink(vec_index(g, i, jr[r], k), uc[r], Au, ((k & 1) << 1) | r);
+        else
+          sink(vec_index(g, i, jr[r], k), uc[r], Au);
       }
       if constexpr (CV != 0) vzm[r] = vc[r][4];
       if constexpr (CV == 1) {
@@ -485,7 +493,7 @@ __device__ __forceinline__ void stencil_march_t(const G& g, const StencilGeom& s
       um[r] = uc[r];
       uc[r] = up[r];
       up[r] = c2.ok[r] ? T(in.value(c2.u[r])) : zero;
-      if (c2.ok[r] && k + 2 < k1) in.keep(vec_index(g, i, jr[r], k + 2), c2.u[r]);
+      if (c2.ok[r] && k + 2 < k1) in.keep(vec_index(g, i, jr[r], k + 2), c2.u[r], ((k & 1) << 1) | r);
       em[r] = ec[r];
       ec[r] = ep[r];
       ep[r] = T(to_real(c2.e[r]));

@@ -7,22 +7,20 @@
 //
 // Global k-step Jacobi-PCG (PCG of Alg. 3 with M = diag(A), from y = 0):
 //   A_1 : p_1 = D^-1 v, q = A p_1;           partials <p_1,q>, <v,p_1>
-//   B_j : alpha_j = gamma_j / <p_j,q>;  y += alpha_j p_j;  rho -= alpha_j q;
-//         partial gamma_{j+1} = <rho, D^-1 rho>                 (j < k)
+//   B_j : alpha_j = gamma_j / <p_j,q>;  rho -= alpha_j q;
+//         partial gamma_{j+1} = <rho, D^-1 rho>;  the last one (j = k-1)
+//         also forms y = sum_{i<k} alpha_i p_i from the stored directions
 //   A_j : beta_j = gamma_j/gamma_{j-1};  p_j = D^-1 rho + beta_j p_{j-1};
 //         q = A p_j;  partial <p_j,q>                            (2 <= j <= k)
 //   tail: y + alpha_k p_k, folded into the consumer.
 // Global k-step right-Jacobi GMRES (one GMRES(k) cycle on A D^-1 t = v from
 // t = 0, classical Gram-Schmidt; the basis is stored unnormalised with its
 // scales in PcScalars::vs):
-//   G0  : V_0 = v;                               partial ||v||^2
-//   GA_j: w = A D^-1 V_j
-//   GD_j: partials <V_i, w>, i <= j
-//   GO_j: h_ij; V_{j+1} = w - sum h_ij V_i;      partial ||V_{j+1}||^2
-//   tail: least squares on the (k+1) x k Hessenberg by Givens rotations in
-//         the consumer's prologue, B(v) = D^-1 sum c_j V_j.
-// Every kernel reduces the partials of its predecessor in its prologue (all
-// workgroups in the same fixed order), so no extra launch sits between them.
+//   GF_j: h(., j-1) from the previous step's partials; stored V_j formed
+//         (V_0 = v), w~_j = A D^-1 V_j;  partials ||V_j||^2, <V_q, w~_j>
+//   GE  : the last column and the least squares on the (k+1) x k
+//         Hessenberg by Givens rotations, once; the consumer forms
+//         B(v) = D^-1 sum c_j V_j.
 // Guards as in the definition: a zero preconditioned residual returns 0 and
 // a non-positive curvature <p,q> returns the current iterate; the stop is
 // recorded per step in PcScalars so later steps leave y untouched.
@@ -431,38 +429,56 @@ k_pcg_a(int jstep, G g, StencilGeom sg, const T* __restrict__ dinv,
 // Right-Jacobi GMRES(k) from x = 0 (Arnoldi with classical Gram-Schmidt).
 // The basis is stored unnormalised: stored vector q is nu_q V_q with
 // nu_q = ||stored q|| (vs[q] = 1/nu_q), and the operator is applied to the
-// stored vector, w~_j = A D^-1 (stored j) = nu_j A D^-1 V_j.  Per step j two
-// passes:
-//   GF_j (stencil): the stored vector j is formed at every node from the
-//     previous step's data -- j = 0: v = c1 X1 + c2 X2; j >= 1:
-//     vs[j-1] w~_{j-1} - sum_{q<j} h(q,j-1) vs[q] (stored q), which is
-//     w_{j-1} - sum h(q,j-1) V_q -- stored, its squared norm summed, and
-//     w~_j = A D^-1 (stored j) computed from it in the same pass;
-//   GD_j (streaming): nu_j from GF_j's partials (beta0 for j = 0, else the
-//     subdiagonal h(j,j-1)), then <stored q, w~_j> for q <= j, from which
-//     GF_{j+1} takes h(q,j) = vs[q] vs[j] <stored q, w~_j>.
-// GE (one workgroup) finishes: column k-1, its subdiagonal h(k,k-1) and the
-// least squares, whose coefficients the consumers read.  A zero norm nu_j
-// ends the cycle at j columns (beta0 = 0 gives B(v) = 0, a zero subdiagonal
-// is a happy breakdown).  w~ alternates between two buffers (GF_j reads one
-// at halo nodes while writing the other).  Partial buffers: GF_j writes PC0,
-// GD_j PC1.
+// stored vector, w~_j = A D^-1 (stored j) = nu_j A D^-1 V_j.  One stencil
+// pass GF_j per step j: the stored vector j is formed at every node from the
+// previous step's data -- j = 0: v = c1 X1 + c2 X2; j >= 1:
+// vs[j-1] w~_{j-1} - sum_{q<j} h(q,j-1) vs[q] (stored q), which is
+// w_{j-1} - sum h(q,j-1) V_q -- stored, its squared norm summed, and
+// w~_j = A D^-1 (stored j) computed from it; where w~_j of a node is known,
+// the node's stored vectors 0..j (read or formed two plane steps earlier and
+// held in thread-private LDS since) give its terms of <stored q, w~_j>.
+// GF_j's partials: column 0 ||stored j||^2, column 1 + q <stored q, w~_j>
+// (q <= j), and at the last step column j + 2 ||w~_j||^2.  GF_{j+1} takes
+// nu_j from column 0 (beta0 for j = 0, else the subdiagonal h(j,j-1)) and
+// h(q,j) = vs[q] vs[j] <stored q, w~_j> from the others.
+// GE (one workgroup) finishes: nu_{k-1}, column k-1, its subdiagonal
+// h(k,k-1) and the least squares, whose coefficients the consumers read.  A
+// zero norm nu_j ends the cycle at j columns (beta0 = 0 gives B(v) = 0, a
+// zero subdiagonal is a happy breakdown).  w~ alternates between two
+// buffers (GF_j reads one at halo nodes while writing the other), and so do
+// the partials.
 
-// Column `col` of the Hessenberg from GD_col's partials: h(q,col) into the
-// scalars (workgroup 0), and the coefficients of the next stored vector,
-// cw = vs[col] for w~_col and c[q] = h(q,col) vs[q].  Every thread calls it.
-__device__ __forceinline__ double gm_column(Blk bk, int col, const double* part, int P, PcScalars* pcs,
-                                            double* c) {
-  const double sc = pcs->vs[col];
-  for (int q = 0; q <= col; ++q) {
-    const double hq = pcs->vs[q] * sc * block_sum_column(part, P, q);
-    if (threadIdx.x == 0) {
-      c[q] = hq * pcs->vs[q];
+// Column `col` of the Hessenberg from GF_col's partials: nu_col (into the
+// scalars: beta0 or h(col,col-1), vs[col]; a zero norm ends the cycle at col
+// columns and returns false), h(q,col) into the scalars, and the
+// coefficients of the next stored vector, cw = vs[col] for w~_col and
+// c[q] = h(q,col) vs[q].  Workgroup 0 writes the scalars; every workgroup
+// sums the same partials in the same order, so all take the same values.
+// Every thread calls it.
+__device__ __forceinline__ bool gm_column(Blk bk, int col, const double* part, int P, PcScalars* pcs,
+                                          double* c, double& cw) {
+  __shared__ double s_col[kMaxInnerGmres + 1];
+  block_sum_columns(part, P, col + 2, s_col);
+  const double nrm = sqrt(s_col[0]);
+  const double sc = nrm == 0.0 ? 0.0 : 1.0 / nrm;
+  if (bk.id == 0 && threadIdx.x == 0) {
+    if (col == 0) pcs->beta0 = nrm;
+    else pcs->h[(col - 1) * (kMaxInner + 1) + col] = nrm;
+    pcs->vs[col] = sc;
+    if (nrm == 0.0) pcs->ncol = col;
+  }
+  if (nrm == 0.0) return false;
+  if (threadIdx.x == 0) {
+    for (int q = 0; q <= col; ++q) {
+      const double vq = q == col ? sc : pcs->vs[q];
+      const double hq = vq * sc * s_col[1 + q];
+      c[q] = hq * vq;
       if (bk.id == 0) pcs->h[col * (kMaxInner + 1) + q] = hq;
     }
   }
   __syncthreads();
-  return sc;
+  cw = sc;
+  return true;
 }
 
 // Raw loads of GF_J at a node: D^-1 and, for J >= 1, w~_{J-1} and the first
@@ -477,11 +493,12 @@ struct GfRaw {
 };
 template <class T>
 struct GfRaw<T, 0> {
+  static constexpr int RJ = 0;
   T d;
   double x1, x2;
 };
 
-template <class T, class G, bool CV, int J>
+template <class T, class G, int CV, int J>
 __device__ __forceinline__ void gmpc_fused_body(Blk bk, int jstep, int k, G g, StencilGeom sg,
                                                 const T* __restrict__ dinv, const double* X1, double c1,
                                                 const double* X2, double c2, T* Vbase, long long ldv,
@@ -490,9 +507,29 @@ __device__ __forceinline__ void gmpc_fused_body(Blk bk, int jstep, int k, G g, S
   if (!wg_running(st)) return;
   PcScalars* pcs = &st->pc;
   using R = GfRaw<T, J>;
-  double acc[1] = {0.0};
+  constexpr int RJ = R::RJ;
+  // columns: 0 ||stored j||^2, 1 + q <stored q, w~_j> for q < RJ, 1 + RJ
+  // <stored j, w~_j>, 2 + RJ ||w~_j||^2 (moved to 1 + j and 2 + j at the end
+  // when the basis length is taken at run time)
+  constexpr int NC = RJ + 3;
+  double acc[NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) acc[q] = 0.0;
+  const bool last = jstep + 1 == k;
+  // the thread's stored vectors 0..j of its nodes, from keep to sink: four
+  // node slots (plane parity, row), one entry per thread, so no barrier
+  __shared__ T s_v[4][RJ + 1][kBlock];
+  const int tid = threadIdx.x;
   T* Vj = Vbase + (long long)jstep * ldv;
-  auto sink = [&](long long idx, T, T Au) { wout[idx] = Au; };
+  auto sink = [&](long long idx, T, T Au, int slot) {
+    wout[idx] = Au;
+    const double wa = (double)Au;
+#pragma unroll
+    for (int p = 0; p < RJ; ++p)
+      if (J <= kGfFixed || p < jstep) acc[1 + p] += (double)s_v[slot][p][tid] * wa;
+    acc[1 + RJ] += (double)s_v[slot][RJ][tid] * wa;
+    if (last) acc[2 + RJ] += wa * wa;
+  };
   // FP32 with up to two basis terms: loads two plane steps ahead; longer
   // bases take one step (the second plane of raw loads would cost an
   // occupancy step: at 256^3, J = 3 and 4 ran 1-4% faster with one)
@@ -512,45 +549,64 @@ __device__ __forceinline__ void gmpc_fused_body(Blk bk, int jstep, int k, G g, S
       return T(v);
     };
     auto value = [&](const R& q) { return q.d * form(q); };
-    auto keep = [&](long long t, const R& q) {
+    auto keep = [&](long long t, const R& q, int slot) {
       const T v = form(q);
       Vj[t] = v;
+      s_v[slot][0][tid] = v;
       acc[0] += (double)v * (double)v;
     };
     stencil_march<T, CV, PD>(g, sg, bk.id, stencil_in(load, value, keep), sink);
   } else {
     if (jstep >= pcs->ncol) return;     // an earlier step ended the cycle
     __shared__ double s_c[kMaxInnerGmres];
-    const T cw = T(gm_column(bk, jstep - 1, part_in, P_in, pcs, s_c));
-    T c[R::RJ > 0 ? R::RJ : 1];
+    double cwd;
+    if (!gm_column(bk, jstep - 1, part_in, P_in, pcs, s_c, cwd)) return;
+    const T cw = T(cwd);
+    T c[RJ];
 #pragma unroll
-    for (int q = 0; q < R::RJ; ++q) c[q] = q < jstep ? T(s_c[q]) : T(0);
+    for (int q = 0; q < RJ; ++q) c[q] = q < jstep ? T(s_c[q]) : T(0);
     auto load = [&](long long t) {
       R q;
       q.d = dinv[t];
       q.w = wprev[t];
 #pragma unroll
-      for (int p = 0; p < R::RJ; ++p) q.v[p] = (J <= kGfFixed || p < jstep) ? Vbase[(long long)p * ldv + t] : T(0);
+      for (int p = 0; p < RJ; ++p) q.v[p] = (J <= kGfFixed || p < jstep) ? Vbase[(long long)p * ldv + t] : T(0);
       return q;
     };
     auto form = [&](const R& q) {
       T v = cw * q.w;
 #pragma unroll
-      for (int p = 0; p < R::RJ; ++p)
+      for (int p = 0; p < RJ; ++p)
         if (J <= kGfFixed || p < jstep) v -= c[p] * q.v[p];
       return v;
     };
     auto value = [&](const R& q) { return q.d * form(q); };
-    auto keep = [&](long long t, const R& q) {
+    auto keep = [&](long long t, const R& q, int slot) {
       const T v = form(q);
       Vj[t] = v;
+#pragma unroll
+      for (int p = 0; p < RJ; ++p)
+        if (J <= kGfFixed || p < jstep) s_v[slot][p][tid] = q.v[p];
+      s_v[slot][RJ][tid] = v;
       acc[0] += (double)v * (double)v;
     };
     stencil_march<T, CV, PD>(g, sg, bk.id, stencil_in(load, value, keep), sink);
   }
-  block_partials<1>(acc, 1, part_out, bk.n, bk.id);
+  if constexpr (J > kGfFixed) {
+    // basis length at run time: <stored j, w~_j> and ||w~_j||^2 to columns
+    // 1 + j and 2 + j (the columns between are zero)
+    const double dj = acc[1 + RJ], ww = acc[2 + RJ];
+    acc[1 + RJ] = 0.0;
+    acc[2 + RJ] = 0.0;
+#pragma unroll
+    for (int q = 1 + kGfFixed; q < NC; ++q) {
+      if (q == 1 + jstep) acc[q] = dj;
+      if (q == 2 + jstep) acc[q] = ww;
+    }
+  }
+  block_partials<NC>(acc, jstep + (last ? 3 : 2), part_out, bk.n, bk.id);
 }
-template <class T, class G, bool CV, int J>
+template <class T, class G, int CV, int J>
 __global__ void __launch_bounds__(kBlock)
 k_gmpc_fused(int jstep, int k, G g, StencilGeom sg, const T* __restrict__ dinv, const double* X1, double c1,
              const double* X2, double c2, T* Vbase, long long ldv, const T* wprev, T* __restrict__ wout,
@@ -559,103 +615,45 @@ k_gmpc_fused(int jstep, int k, G g, StencilGeom sg, const T* __restrict__ dinv, 
                                part_in, P_in, part_out, st);
 }
 
-// GD_j: nu_j from GF_j's partials (PC0), then partials <stored q, w~_j> for
-// q <= j (PC1).
-template <class T, bool WW>
-__device__ __forceinline__ void gmpc_dots_t(Blk bk, int jstep, long long N, const T* Vbase, long long ldv,
-                                            const T* __restrict__ w, double* part_out) {
-  // columns q <= j: <stored q, w~_j>; with WW (the last step) also column
-  // j+1: ||w~_j||^2, from which the last subdiagonal comes
-  double acc[kMaxInnerGmres];
-#pragma unroll
-  for (int q = 0; q < kMaxInnerGmres; ++q) acc[q] = 0.0;
-  double ww[1] = {0.0};
-  // 16-byte accesses (four FP32 or two FP64 nodes per lane); vectors start
-  // 256-byte aligned and ldv is a multiple of 32 elements
-  constexpr int VW = 16 / sizeof(T);
-  typedef T vec_t __attribute__((ext_vector_type(VW)));
-  const long long nv = N / VW;
-  for (long long qv = bk.gtid(); qv < nv; qv += bk.gstride()) {
-    const long long e = qv * VW;
-    const vec_t wv = *reinterpret_cast<const vec_t*>(w + e);
-#pragma unroll
-    for (int q = 0; q < kMaxInnerGmres; ++q) {
-      if (q <= jstep) {
-        const vec_t vv = *reinterpret_cast<const vec_t*>(Vbase + (long long)q * ldv + e);
-#pragma unroll
-        for (int l = 0; l < VW; ++l) acc[q] += (double)vv[l] * (double)wv[l];
-      }
-    }
-    if constexpr (WW) {
-#pragma unroll
-      for (int l = 0; l < VW; ++l) ww[0] += (double)wv[l] * (double)wv[l];
-    }
-  }
-  for (long long e = nv * VW + bk.gtid(); e < N; e += bk.gstride()) {
-    const double wv = (double)w[e];
-#pragma unroll
-    for (int q = 0; q < kMaxInnerGmres; ++q)
-      if (q <= jstep) acc[q] += (double)Vbase[(long long)q * ldv + e] * wv;
-    if constexpr (WW) ww[0] += wv * wv;
-  }
-  block_partials<kMaxInnerGmres>(acc, jstep + 1, part_out, bk.n, bk.id);
-  if constexpr (WW) {
-    __syncthreads();   // block_partials' LDS is reused
-    block_partials<1>(ww, 1, part_out + (long long)(jstep + 1) * bk.n, bk.n, bk.id);
-  }
-}
-template <class T>
-__device__ __forceinline__ void gmpc_dots_body(Blk bk, int jstep, int k, long long N, const T* Vbase,
-                                               long long ldv, const T* __restrict__ w, const double* part_norm,
-                                               int P_norm, double* part_out, SolveState* st) {
-  if (!wg_running(st)) return;
-  PcScalars* pcs = &st->pc;
-  if (jstep >= pcs->ncol) return;
-  const double nrm = sqrt(block_sum_column(part_norm, P_norm, 0));
-  if (bk.id == 0 && threadIdx.x == 0) {
-    if (jstep == 0) pcs->beta0 = nrm;
-    else pcs->h[(jstep - 1) * (kMaxInner + 1) + jstep] = nrm;
-    pcs->vs[jstep] = nrm == 0.0 ? 0.0 : 1.0 / nrm;
-    if (nrm == 0.0) pcs->ncol = jstep;
-  }
-  if (nrm == 0.0) return;
-  if (jstep + 1 == k) gmpc_dots_t<T, true>(bk, jstep, N, Vbase, ldv, w, part_out);
-  else gmpc_dots_t<T, false>(bk, jstep, N, Vbase, ldv, w, part_out);
-}
-template <class T>
-__global__ void __launch_bounds__(kBlock)
-k_gmpc_dots(int jstep, int k, long long N, const T* Vbase, long long ldv, const T* __restrict__ w,
-            const double* part_norm, int P_norm, double* part_out, SolveState* st) {
-  gmpc_dots_body(this_blk(), jstep, k, N, Vbase, ldv, w, part_norm, P_norm, part_out, st);
-}
-
-// GE: the end of the inner solve, one workgroup.  Column k-1 of the
-// Hessenberg from GD_{k-1}'s partials (PC1), its subdiagonal from the
-// Pythagorean identity h(k,k-1)^2 = ||w_{k-1}||^2 - sum_q h(q,k-1)^2
-// (exact for an orthonormal basis, as PIPEFGMRES takes its own norms; a
-// value <= 0 counts as a happy breakdown, h = 0), then the small least
-// squares min || beta0 e_0 - H y || over the active columns (Givens
-// rotations), stored as cf[q] = y_q vs[q] for the consumers.
+// GE: the end of the inner solve, one workgroup.  From GF_{k-1}'s partials:
+// nu_{k-1} (a zero norm ends the cycle at k-1 columns), column k-1 of the
+// Hessenberg, and its subdiagonal from the Pythagorean identity
+// h(k,k-1)^2 = ||w_{k-1}||^2 - sum_q h(q,k-1)^2 (exact for an orthonormal
+// basis, as PIPEFGMRES takes its own norms; a value <= 0 counts as a happy
+// breakdown, h = 0); then the small least squares min || beta0 e_0 - H y ||
+// over the active columns (Givens rotations), stored as cf[q] = y_q vs[q]
+// for the consumers.
 __device__ __forceinline__ void gmpc_finish_body(int k, const double* part, int P, SolveState* st) {
   if (!wg_running(st)) return;
   PcScalars* pcs = &st->pc;
   constexpr int L = kMaxInner + 1, M = kMaxInnerGmres + 1;
-  __shared__ double s_col[kMaxInnerGmres + 1];
+  __shared__ double s_col[kMaxInnerGmres + 2];
   __shared__ double H[M * kMaxInnerGmres];
   __shared__ double g[M], cs[kMaxInnerGmres], sn[kMaxInnerGmres], yv[kMaxInnerGmres];
-  const int nc = pcs->ncol;
-  if (nc == k) block_sum_columns(part, P, k + 1, s_col);   // <stored q, w~_{k-1}>, q < k; ||w~_{k-1}||^2
+  // ||stored k-1||^2, <stored q, w~_{k-1}> for q < k, ||w~_{k-1}||^2
+  if (pcs->ncol == k) block_sum_columns(part, P, k + 2, s_col);
   if (threadIdx.x != 0) return;
+  int nc = pcs->ncol;
   double hk = 0.0;
   if (nc == k) {
-    const double sc = pcs->vs[k - 1];
-    double t = sc * sc * s_col[k];
-    for (int q = 0; q < k; ++q) {
-      const double hq = pcs->vs[q] * sc * s_col[q];
-      pcs->h[(k - 1) * L + q] = hq;
-      t -= hq * hq;
+    const double nrm = sqrt(s_col[0]);
+    const double sc = nrm == 0.0 ? 0.0 : 1.0 / nrm;
+    if (k == 1) pcs->beta0 = nrm;
+    else pcs->h[(k - 2) * L + k - 1] = nrm;
+    pcs->vs[k - 1] = sc;
+    if (nrm == 0.0) {
+      nc = k - 1;
+      pcs->ncol = nc;
+    } else {
+      double t = sc * sc * s_col[k + 1];
+      for (int q = 0; q < k; ++q) {
+        const double vq = q == k - 1 ? sc : pcs->vs[q];
+        const double hq = vq * sc * s_col[1 + q];
+        pcs->h[(k - 1) * L + q] = hq;
+        t -= hq * hq;
+      }
+      hk = t > 0.0 ? sqrt(t) : 0.0;
     }
-    hk = t > 0.0 ? sqrt(t) : 0.0;
   }
   for (int jj = 0; jj < nc; ++jj)
     for (int ii = 0; ii <= jj + 1; ++ii) H[jj * M + ii] = pcs->h[jj * L + ii];
