@@ -660,8 +660,15 @@ template <class T, class G, bool CV>
 void launch_gmpc_fused_cv(pfk_session_s* S, hipStream_t s, int j, int k, const G& g, const T* dinv,
                           const double* X1, double c1, const double* X2, double c2, T* V, long long ldv,
                           const T* wp, T* wo, const double* pin, int Pin, double* pout) {
-#define PFK_GF(J) LAUNCH((k_gmpc_fused<T, G, CV, J>), S->Ps(), s, j, k, g, S->sg, dinv, X1, c1, X2, c2, V, ldv, wp, \
-                         wo, pin, Pin, pout, S->st)
+#define PFK_GF(J)                                                                                            \
+  do {                                                                                                       \
+    if (j + 1 == k)                                                                                          \
+      LAUNCH((k_gmpc_fused<T, G, CV, J, true>), S->Ps(), s, j, k, g, S->sg, dinv, X1, c1, X2, c2, V, ldv, wp,  \
+             wo, pin, Pin, pout, S->st);                                                                     \
+    else                                                                                                     \
+      LAUNCH((k_gmpc_fused<T, G, CV, J, false>), S->Ps(), s, j, k, g, S->sg, dinv, X1, c1, X2, c2, V, ldv, wp, \
+             wo, pin, Pin, pout, S->st);                                                                     \
+  } while (0)
   switch (j) {
     case 0: PFK_GF(0); break;
     case 1: PFK_GF(1); break;
@@ -1942,16 +1949,22 @@ void batch_inner_pcg(pfk_batch_s* Tb, const int* os, const int* ov, int n) {
 template <class T>
 void batch_inner_gmres(pfk_batch_s* Tb, const int* os, int n) {
   hipStream_t s1 = Tb->s1;
+#define PFK_KBGF(J)                                                                           \
+  do {                                                                                        \
+    if (j + 1 == Tb->pc_k) LAUNCH((kb_gmpc_fused<T, J, true>), Tb->tot[kBpSten], s1, Tb->d_sys, os, n, j); \
+    else LAUNCH((kb_gmpc_fused<T, J, false>), Tb->tot[kBpSten], s1, Tb->d_sys, os, n, j);                   \
+  } while (0)
   for (int j = 0; j < Tb->pc_k; ++j) {
     switch (j) {
-      case 0: LAUNCH((kb_gmpc_fused<T, 0>), Tb->tot[kBpSten], s1, Tb->d_sys, os, n, j); break;
-      case 1: LAUNCH((kb_gmpc_fused<T, 1>), Tb->tot[kBpSten], s1, Tb->d_sys, os, n, j); break;
-      case 2: LAUNCH((kb_gmpc_fused<T, 2>), Tb->tot[kBpSten], s1, Tb->d_sys, os, n, j); break;
-      case 3: LAUNCH((kb_gmpc_fused<T, 3>), Tb->tot[kBpSten], s1, Tb->d_sys, os, n, j); break;
-      case 4: LAUNCH((kb_gmpc_fused<T, 4>), Tb->tot[kBpSten], s1, Tb->d_sys, os, n, j); break;
-      default: LAUNCH((kb_gmpc_fused<T, kGfFixed + 1>), Tb->tot[kBpSten], s1, Tb->d_sys, os, n, j); break;
+      case 0: PFK_KBGF(0); break;
+      case 1: PFK_KBGF(1); break;
+      case 2: PFK_KBGF(2); break;
+      case 3: PFK_KBGF(3); break;
+      case 4: PFK_KBGF(4); break;
+      default: PFK_KBGF(kGfFixed + 1); break;
     }
   }
+#undef PFK_KBGF
   LAUNCH(kb_gmpc_finish, n, s1, Tb->d_sys, n);
 }
 

@@ -150,7 +150,7 @@ __device__ __forceinline__ double* batch_gm_part(const BSys& d, int j) {
   return (j & 1) ? d.part_pc1 : d.part_pc0;
 }
 // GF_j: reads GF_{j-1}'s partials, writes its own
-template <class T, int J>
+template <class T, int J, bool WW>
 __global__ void __launch_bounds__(kBlock) kb_gmpc_fused(const BSys* sys, const int* off, int nsys, int j) {
   const int s = batch_find(off, nsys, (int)blockIdx.x);
   const BSys& d = sys[s];
@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(kBlock) kb_gmpc_fused(const BSys* sys, const i
   const PcOutDesc& pd = d.pd;
   const T* wp = j > 0 ? batch_gm_w<T>(d, j - 1) : nullptr;
   with_inner_grid<T>(d, [&](const auto& g) {
-    gmpc_fused_body<T, std::decay_t<decltype(g)>, 0, J>(
+    gmpc_fused_body<T, std::decay_t<decltype(g)>, 0, J, WW>(
         bk, j, pd.k, g, d.sg, (const T*)pd.dinv_in, pd.X1, pd.c1, pd.X2, pd.c2, (T*)const_cast<void*>(pd.vbase),
         pd.ldv, wp, batch_gm_w<T>(d, j), batch_gm_part(d, j + 1), d.Ps, batch_gm_part(d, j), d.st);
   });

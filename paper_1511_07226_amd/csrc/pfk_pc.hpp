@@ -498,7 +498,8 @@ struct GfRaw<T, 0> {
   double x1, x2;
 };
 
-template <class T, class G, int CV, int J>
+// WW: the last step of the cycle, which also sums ||w~_j||^2.
+template <class T, class G, int CV, int J, bool WW>
 __device__ __forceinline__ void gmpc_fused_body(Blk bk, int jstep, int k, G g, StencilGeom sg,
                                                 const T* __restrict__ dinv, const double* X1, double c1,
                                                 const double* X2, double c2, T* Vbase, long long ldv,
@@ -509,17 +510,22 @@ __device__ __forceinline__ void gmpc_fused_body(Blk bk, int jstep, int k, G g, S
   using R = GfRaw<T, J>;
   constexpr int RJ = R::RJ;
   // columns: 0 ||stored j||^2, 1 + q <stored q, w~_j> for q < RJ, 1 + RJ
-  // <stored j, w~_j>, 2 + RJ ||w~_j||^2 (moved to 1 + j and 2 + j at the end
-  // when the basis length is taken at run time)
-  constexpr int NC = RJ + 3;
+  // <stored j, w~_j>, with WW 2 + RJ ||w~_j||^2 (moved to 1 + j and 2 + j at
+  // the end when the basis length is taken at run time)
+  constexpr int NC = RJ + (WW ? 3 : 2);
   double acc[NC];
 #pragma unroll
   for (int q = 0; q < NC; ++q) acc[q] = 0.0;
-  const bool last = jstep + 1 == k;
+  // the squared norms (columns 0 and 2 + RJ) accumulate in thread-private
+  // LDS: two fewer live registers keep these kernels at four workgroups per
+  // CU (the same additions in the same order as in a register)
+  __shared__ double s_nn[WW ? 2 : 1][kBlock];
   // the thread's stored vectors 0..j of its nodes, from keep to sink: four
   // node slots (plane parity, row), one entry per thread, so no barrier
   __shared__ T s_v[4][RJ + 1][kBlock];
   const int tid = threadIdx.x;
+  s_nn[0][tid] = 0.0;
+  if constexpr (WW) s_nn[WW][tid] = 0.0;
   T* Vj = Vbase + (long long)jstep * ldv;
   auto sink = [&](long long idx, T, T Au, int slot) {
     wout[idx] = Au;
@@ -528,7 +534,7 @@ __device__ __forceinline__ void gmpc_fused_body(Blk bk, int jstep, int k, G g, S
     for (int p = 0; p < RJ; ++p)
       if (J <= kGfFixed || p < jstep) acc[1 + p] += (double)s_v[slot][p][tid] * wa;
     acc[1 + RJ] += (double)s_v[slot][RJ][tid] * wa;
-    if (last) acc[2 + RJ] += wa * wa;
+    if constexpr (WW) s_nn[WW][tid] = s_nn[WW][tid] + wa * wa;
   };
   // FP32 with up to two basis terms: loads two plane steps ahead; longer
   // bases take one step (the second plane of raw loads would cost an
@@ -553,7 +559,7 @@ __device__ __forceinline__ void gmpc_fused_body(Blk bk, int jstep, int k, G g, S
       const T v = form(q);
       Vj[t] = v;
       s_v[slot][0][tid] = v;
-      acc[0] += (double)v * (double)v;
+      s_nn[0][tid] = s_nn[0][tid] + (double)v * (double)v;
     };
     stencil_march<T, CV, PD>(g, sg, bk.id, stencil_in(load, value, keep), sink);
   } else {
@@ -588,31 +594,33 @@ __device__ __forceinline__ void gmpc_fused_body(Blk bk, int jstep, int k, G g, S
       for (int p = 0; p < RJ; ++p)
         if (J <= kGfFixed || p < jstep) s_v[slot][p][tid] = q.v[p];
       s_v[slot][RJ][tid] = v;
-      acc[0] += (double)v * (double)v;
+      s_nn[0][tid] = s_nn[0][tid] + (double)v * (double)v;
     };
     stencil_march<T, CV, PD>(g, sg, bk.id, stencil_in(load, value, keep), sink);
   }
+  acc[0] = s_nn[0][tid];
+  if constexpr (WW) acc[NC - 1] = s_nn[WW][tid];
   if constexpr (J > kGfFixed) {
     // basis length at run time: <stored j, w~_j> and ||w~_j||^2 to columns
     // 1 + j and 2 + j (the columns between are zero)
-    const double dj = acc[1 + RJ], ww = acc[2 + RJ];
+    const double dj = acc[1 + RJ], ww = WW ? acc[NC - 1] : 0.0;
     acc[1 + RJ] = 0.0;
-    acc[2 + RJ] = 0.0;
+    if constexpr (WW) acc[NC - 1] = 0.0;
 #pragma unroll
     for (int q = 1 + kGfFixed; q < NC; ++q) {
       if (q == 1 + jstep) acc[q] = dj;
-      if (q == 2 + jstep) acc[q] = ww;
+      if (WW && q == 2 + jstep) acc[q] = ww;
     }
   }
-  block_partials<NC>(acc, jstep + (last ? 3 : 2), part_out, bk.n, bk.id);
+  block_partials<NC>(acc, jstep + (WW ? 3 : 2), part_out, bk.n, bk.id);
 }
-template <class T, class G, int CV, int J>
+template <class T, class G, int CV, int J, bool WW>
 __global__ void __launch_bounds__(kBlock)
 k_gmpc_fused(int jstep, int k, G g, StencilGeom sg, const T* __restrict__ dinv, const double* X1, double c1,
              const double* X2, double c2, T* Vbase, long long ldv, const T* wprev, T* __restrict__ wout,
              const double* part_in, int P_in, double* part_out, SolveState* st) {
-  gmpc_fused_body<T, G, CV, J>(this_blk(), jstep, k, g, sg, dinv, X1, c1, X2, c2, Vbase, ldv, wprev, wout,
-                               part_in, P_in, part_out, st);
+  gmpc_fused_body<T, G, CV, J, WW>(this_blk(), jstep, k, g, sg, dinv, X1, c1, X2, c2, Vbase, ldv, wprev, wout,
+                                   part_in, P_in, part_out, st);
 }
 
 // GE: the end of the inner solve, one workgroup.  From GF_{k-1}'s partials:
