@@ -563,7 +563,9 @@ __device__ __forceinline__ void gmpc_fused_body(Blk bk, int jstep, int k, G g, S
     };
     stencil_march<T, CV, PD>(g, sg, bk.id, stencil_in(load, value, keep), sink);
   } else {
-    if (jstep >= pcs->ncol) return;     // an earlier step ended the cycle
+    // an earlier step ended the cycle (workgroup 0 of this launch may be
+    // writing ncol: gm_column below ends it at jstep - 1 columns)
+    if (jstep >= wg_load(&pcs->ncol)) return;
     __shared__ double s_c[kMaxInnerGmres];
     double cwd;
     if (!gm_column(bk, jstep - 1, part_in, P_in, pcs, s_c, cwd)) return;

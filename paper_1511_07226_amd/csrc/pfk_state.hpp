@@ -128,4 +128,15 @@ __device__ __forceinline__ bool wg_running(const SolveState* st) {
   return s_run != 0;
 }
 
+// A value that another workgroup of the same launch may be writing, read once
+// for the whole workgroup (thread 0 reads, a barrier shares it), so all its
+// waves take the same side of the barriers that follow.
+__device__ __forceinline__ int wg_load(const int* p) {
+  __shared__ int s_val;
+  __syncthreads();
+  if (threadIdx.x == 0) s_val = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  return s_val;
+}
+
 }  // namespace pfk
