@@ -222,9 +222,18 @@ __device__ __forceinline__ void pcg_a1_body(Blk bk, G g, StencilGeom sg, const T
     return q.d * T(r);
   };
   const auto in = stencil_in(load, value);
+  // nontemporal stores on large systems: the halo lines that neighbouring
+  // tiles still read stay longer in the L2 (256^3: FETCH 1.23 -> 1.19x the
+  // algorithmic reads for A_j, 1.38 -> 1.32x for A_1)
+  const bool nt = st->nt != 0;
   auto sink = [&](long long idx, T pc, T q) {
-    pout[idx] = pc;
-    qout[idx] = q;
+    if (nt) {
+      stnt(pout + idx, pc);
+      stnt(qout + idx, q);
+    } else {
+      pout[idx] = pc;
+      qout[idx] = q;
+    }
     acc[0] += (double)pc * (double)q;
     acc[1] += (double)V(idx) * (double)pc;
   };
@@ -406,9 +415,18 @@ __device__ __forceinline__ void pcg_a_body(Blk bk, int jstep, G g, StencilGeom s
   struct Raw { T d, r, p; };
   const auto in = stencil_in([&](long long t) { return Raw{dinv[t], rho[t], pprev[t]}; },
                              [&](const Raw& q) { return q.d * q.r + beta * q.p; });
+  // nontemporal stores on large systems: the halo lines that neighbouring
+  // tiles still read stay longer in the L2 (256^3: FETCH 1.23 -> 1.19x the
+  // algorithmic reads for A_j, 1.38 -> 1.32x for A_1)
+  const bool nt = st->nt != 0;
   auto sink = [&](long long idx, T pc, T q) {
-    pout[idx] = pc;
-    qout[idx] = q;
+    if (nt) {
+      stnt(pout + idx, pc);
+      stnt(qout + idx, q);
+    } else {
+      pout[idx] = pc;
+      qout[idx] = q;
+    }
     acc[0] += (double)pc * (double)q;
   };
   // FP32 loads two plane steps ahead (no occupancy step lost; mixed PIPEFCG
