@@ -791,6 +791,9 @@ def main():
                     help="first run a 2 GiB device-to-device copy three times (the reference kernel "
                          "for calibrating hardware byte counters)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch geometry")
+    ap.add_argument("--tiling", default="",
+                    help="TILE_X,STENCIL_TARGET,VECTOR_BLOCKS: this launch geometry for every method of the "
+                         "headline pair instead of tuning one (a profiled run then uses the timed run's geometry)")
     ap.add_argument("--batched-only", action="store_true",
                     help="time only the batched workload (after the headline pair)")
     ap.add_argument("--no-batched", action="store_true")
@@ -841,7 +844,10 @@ def main():
 
     def tune(method):
         # each method is timed with the launch geometry tuned for it
-        if not args.no_autotune:
+        if args.tiling:
+            tx, target, vb = (int(v) for v in args.tiling.split(","))
+            tuning[method] = {"tile_x": tx, "stencil_target": target, "vector_blocks": vb, "given": True}
+        elif not args.no_autotune:
             tuning[method] = A.autotune(B, method, mmax=NU, reps=3)
             log(f"{method} tiling: {tuning[method]}")
 
