@@ -46,14 +46,14 @@ def _host(t):
 SIZES = [8, 13, 16, 20, 24, 17]
 
 
-def _members(pfk, kind, prec, conv=False, sizes=SIZES, tilings=None):
+def _members(pfk, kind, prec, conv=False, sizes=SIZES, tilings=None, k=4):
     out = []
     for i, n in enumerate(sizes):
         p = gen.make_problem(3, n, 3 + i, (2.0, 4.0), seed=100 + i, convection=conv)
         A = pfk.Operator(3, n, p.eta, p.vel)
         if tilings:
             A.set_tiling(*tilings[i % len(tilings)])
-        B = pfk.Precond(A, kind, 4, precision=prec, block=8)
+        B = pfk.Precond(A, kind, k, precision=prec, block=8)
         out.append((p, A, B))
     return out
 
@@ -117,12 +117,16 @@ GLOBAL_CASES = [("pipefgmres", "jacobi_gmres", 1, True), ("pipefgmres", "jacobi_
                 ("fcg", "jacobi_gmres", 1, False)]
 
 
-@pytest.mark.parametrize("case", GLOBAL_CASES,
-                         ids=[f"{m}-{k}-{'mixed' if p else 'fp64'}" for m, k, p, _ in GLOBAL_CASES])
+# inner step count 4, and 7 for the inner GMRES pass whose basis length is
+# taken at run time
+@pytest.mark.parametrize("case", GLOBAL_CASES + [("pipefgmres", "jacobi_gmres", 1, True, 7)],
+                         ids=[f"{c[0]}-{c[1]}-{'mixed' if c[2] else 'fp64'}" + (f"-k{c[4]}" if len(c) > 4 else "")
+                              for c in GLOBAL_CASES + [("pipefgmres", "jacobi_gmres", 1, True, 7)]])
 def test_global_inner_members_identical_to_single_solves(pfk, case):
-    method, kind, prec, conv = case
+    method, kind, prec, conv = case[:4]
+    kin = case[4] if len(case) > 4 else 4
     _say("batch identity, global inner solve", case)
-    mem = _members(pfk, kind, prec, conv, tilings=[(64, 2048, 32), (32, 64, 7), (64, 5, 100)])
+    mem = _members(pfk, kind, prec, conv, tilings=[(64, 2048, 32), (32, 64, 7), (64, 5, 100)], k=kin)
     singles = []
     for p, A, B in mem:
         x = _dev(np.zeros(A.N))

@@ -67,7 +67,8 @@ def test_bf16_rounding_pins():
 
 
 @pytest.mark.parametrize("kind,k,conv", [("jacobi_pcg", 2, False), ("jacobi_pcg", 5, False),
-                                         ("jacobi_gmres", 5, True), ("jacobi_gmres", 3, False)])
+                                         ("jacobi_gmres", 5, True), ("jacobi_gmres", 3, False),
+                                         ("jacobi_gmres", 7, True)])
 def test_mixed_inner_solve(pfk, kind, k, conv):
     _say("mixed inner", kind, k, conv)
     p = gen.make_problem(3, 24, 8, 4.0, seed=k, convection=conv)
