@@ -292,13 +292,27 @@ def size_sweep(pfk, torch, steps=40):
     return out
 
 
-def batched_bench(pfk, torch, steps, warmup, count=64, solve=True):
+def batch_member_tiling(A, n, tile_x, vector_blocks, zc):
+    """A batch member's launch geometry: stencil tiles of width tile_x, the
+    z-range cut into chunks of about zc planes, vector_blocks workgroups for
+    the vector kernels.  A single solve of a small grid wants many short
+    z-marches to fill the GPU; in a batch the members together fill it, so
+    each member's marches can be as long as on a large grid."""
+    ty = 2 * 256 // tile_x
+    tiles = -(-n // tile_x) * -(-n // ty)
+    A.set_tiling(tile_x, tiles * -(-n // zc), vector_blocks)
+
+
+def batched_bench(pfk, torch, steps, warmup, count=64, solve=True, batch_zc=0):
     """Configuration 4: 64 uneven SPD systems (edge 32..96, contrast 1e2..1e4),
     PIPEFCG nu_max 20 with the block-Jacobi inner solve (4 steps, FP32 on BF16
     viscosity), advanced by shared launches.  Tiling per size from the
     autotuner.  Reports steady-state batch iterations/s (every system advances
     one iteration), the same for FCG and for the systems stepped one at a time,
-    and the time to solve all of them to rtol 1e-8."""
+    and the time to solve all of them to rtol 1e-8.  batch_zc > 0 gives the
+    batch member tilings of the autotuned tile width and vector workgroups
+    with z-marches of about batch_zc planes (the one-at-a-time comparison
+    keeps the autotuned single-solve tilings)."""
     import gen
     NU4, K4 = 20, 4
     # the configuration gives no iteration limit: 20000 lets the slowest
@@ -317,9 +331,16 @@ def batched_bench(pfk, torch, steps, warmup, count=64, solve=True):
     for p, A, B in mem:
         if p.n not in tuning:
             tuning[p.n] = A.autotune(B, "pipefcg", mmax=NU4, reps=5)
-    for p, A, B in mem:
-        t = tuning[p.n]
-        A.set_tiling(t["tile_x"], t["stencil_target"], t["vector_blocks"])
+    def single_tiling():
+        for p, A, B in mem:
+            t = tuning[p.n]
+            A.set_tiling(t["tile_x"], t["stencil_target"], t["vector_blocks"])
+
+    def batch_tiling(zc):
+        for p, A, B in mem:
+            t = tuning[p.n]
+            batch_member_tiling(A, p.n, t["tile_x"], t["vector_blocks"], zc)
+
     total_n = sum(A.N for _, A, _ in mem)
     bs = [torch.as_tensor(p.b).cuda() for p, _, _ in mem]
     out = {"workload": f"{count} SPD sinker systems, edge in {{32,48,64,80,96}}, {total_n} unknowns; "
@@ -345,6 +366,13 @@ def batched_bench(pfk, torch, steps, warmup, count=64, solve=True):
             raise RuntimeError(f"batched {method}: {count - running} systems stopped during timing")
         return steps / dt
 
+    # optional: member tilings with z-chunks of batch_zc planes (longer
+    # z-marches than the single-solve tilings of these small grids)
+    if batch_zc > 0:
+        batch_tiling(batch_zc)
+        out["batch_zc"] = batch_zc
+    else:
+        single_tiling()
     for method in ("pipefcg", "fcg"):
         log(f"batched {method}: timing {steps} steps")
         r = steady(method)
@@ -355,7 +383,9 @@ def batched_bench(pfk, torch, steps, warmup, count=64, solve=True):
     for method in ("pipefcg", "fcg"):
         log(f"batched {method}, persistent form: timing {steps} steps")
         out[f"{method}_persistent_batch_iters_per_s"] = round(steady(method, persistent=1), 2)
-    # the same systems stepped one session at a time (one per size, scaled by count)
+    # the same systems stepped one session at a time (one per size, scaled by
+    # count), with the single-solve tilings; the batch tiling is restored after
+    single_tiling()
     seq_ms = 0.0
     for n in sorted(tuning):
         p, A, B = next(m for m in mem if m[0].n == n)
@@ -370,6 +400,8 @@ def batched_bench(pfk, torch, steps, warmup, count=64, solve=True):
     per_unknown = (4 * NU4 + 14) * 8 + (2 * 8 + 2 + 4) + (8 + 4 + 8 + 2 * 8)
     out["algorithmic_GBps_pipefcg"] = round(per_unknown * total_n * out["pipefcg_batch_iters_per_s"] / 1e9, 1)
     out["algorithmic_bytes_per_unknown_iteration"] = per_unknown
+    if batch_zc > 0:
+        batch_tiling(batch_zc)
     if not solve:
         return out
     log("batched pipefcg: solving all systems to rtol 1e-8")
@@ -403,7 +435,7 @@ def batched_bench(pfk, torch, steps, warmup, count=64, solve=True):
     return out
 
 
-def serving_bench(pfk, torch, nreq=240, seed=0, loads=(0.9,), direct=False, per_batch=64):
+def serving_bench(pfk, torch, nreq=240, seed=0, loads=(0.9,), direct=False, per_batch=64, zc=0):
     """Configuration 5: Poisson arrivals of PIPEFCG / PIPEFGMRES requests (50/50)
     on 3D sinker grids, edge lognormal (median 40, sigma_ln 0.5) clipped to
     16..128, contrast 10^U(1,4), rtol 1e-6 or 1e-8, admitted by a memory
@@ -423,6 +455,11 @@ def serving_bench(pfk, torch, nreq=240, seed=0, loads=(0.9,), direct=False, per_
         rtol = 1e-6 if rng.random() < 0.5 else 1e-8
         p = gen.make_problem(3, n, 20, (1.0, 4.0), seed=10000 + i)
         A = pfk.Operator(3, n, p.eta)
+        if zc > 0:
+            # batch member tiling: z-marches of about zc planes, the tile width
+            # that pads the grid least, the operator's vector workgroups
+            pad = {tx: -(-n // tx) * tx * -(-n // (512 // tx)) * (512 // tx) for tx in (64, 32)}
+            batch_member_tiling(A, n, 64 if pad[64] <= pad[32] else 32, A.tiling()[2], zc)
         if method == "pipefgmres":
             B = pfk.Precond(A, "jacobi_gmres", 5, precision=pfk.FP32_BF16COEF)
         else:
@@ -806,6 +843,13 @@ def main():
     ap.add_argument("--serving-loads", default="0.9",
                     help="Poisson offered loads as fractions of the measured capacity")
     ap.add_argument("--serving-per-batch", type=int, default=64, help="members per serving batch")
+    ap.add_argument("--batched-zc", type=int, default=0,
+                    help="z-chunk length (planes) of the batched systems' stencil tiling; 0: the autotuned one")
+    # 32: 240-request burst 10.0 s with the operator default (z-marches of one or
+    # two planes on these small grids), 9.9 / 9.2 / 8.8 / 12.9 / 12.1 s with 8 /
+    # 16 / 32 / 64 / 128 planes
+    ap.add_argument("--serving-zc", type=int, default=32,
+                    help="z-chunk length (planes) of the serving requests' stencil tiling; 0: the operator default")
     ap.add_argument("--serving-direct", action="store_true",
                     help="serving batches launch kernels directly instead of replaying graphs")
     ap.add_argument("--no-stagnation", action="store_true")
@@ -890,7 +934,8 @@ def main():
     extra = {}
     if args.batched_only:
         args.headline_only = True
-        extra["batched_64"] = batched_bench(pfk, torch, args.steps, args.warmup, solve=not args.no_batched_solve)
+        extra["batched_64"] = batched_bench(pfk, torch, args.steps, args.warmup, solve=not args.no_batched_solve,
+                                            batch_zc=args.batched_zc)
     if args.stagnation_only:
         args.headline_only = True
         extra["stagnation_study"] = stagnation_study(pfk, torch)
@@ -904,7 +949,8 @@ def main():
     if args.serving_only:
         args.headline_only = True
         extra["serving"] = serving_bench(pfk, torch, nreq=args.serving_requests, loads=loads,
-                                         direct=args.serving_direct, per_batch=args.serving_per_batch)
+                                         direct=args.serving_direct, per_batch=args.serving_per_batch,
+                                         zc=args.serving_zc)
     if not args.headline_only:
         # unpipelined baseline with a blocking (host-synchronised) reduction
         log("timing fcg host-sync")
@@ -958,12 +1004,13 @@ def main():
         extra["size_sweep_it_per_s"] = size_sweep(pfk, torch)
     if not args.headline_only and not args.no_batched:
         log("batched workload (64 uneven systems)")
-        extra["batched_64"] = batched_bench(pfk, torch, args.steps, args.warmup)
+        extra["batched_64"] = batched_bench(pfk, torch, args.steps, args.warmup, batch_zc=args.batched_zc)
         torch.cuda.empty_cache()
     if not args.headline_only and not args.no_serving:
         log("serving workload")
         extra["serving"] = serving_bench(pfk, torch, nreq=args.serving_requests, loads=loads,
-                                         direct=args.serving_direct, per_batch=args.serving_per_batch)
+                                         direct=args.serving_direct, per_batch=args.serving_per_batch,
+                                         zc=args.serving_zc)
 
     cpu = None
     if not args.no_cpu_baseline:
