@@ -661,9 +661,9 @@ def cpu_baseline(method, n=128, steady=6):
     scale = N / float(256 ** 3)
     nbytes = iteration_bytes(method, NU, INNER, N)
     return {"value": round(scale / best, 5), "unit": "outer_iters/s", "cores": best_cores, "kind": "oracle",
-            "sample": f"{method.upper()} steady-state iterations {NU + 1}..{NU + steady} (1 thread) and "
-                      f"{NU + steady + 1}..{NU + 2 * steady} ({cores} threads) of the same recipe at {n}^3, "
-                      f"numpy FP64, {total:.0f} s in all; value = the faster {n}^3 rate x {scale:g} (256^3 unit)",
+            "sample": f"{method.upper()} steady iterations {NU + 1}..{NU + steady} (1 thread), "
+                      f"{NU + steady + 1}..{NU + 2 * steady} ({cores} threads), same recipe at {n}^3, "
+                      f"numpy FP64, {total:.0f} s; value = faster {n}^3 rate x {scale:g} (256^3 unit)",
             f"it_per_s_{n}cube": {"1_thread": round(1.0 / one, 4), f"{cores}_threads": round(1.0 / allc, 4)},
             "algorithmic_GBps": {"1_thread": round(nbytes / one / 1e9, 3),
                                  f"{cores}_threads": round(nbytes / allc / 1e9, 3)},
@@ -1047,7 +1047,7 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": update_traffic_bytes() if main_m == "pipefcg" else None,
                      "kernel": upd_name, "avg_ms": round(avg_ms, 4),
-                     "algorithmic_bytes_per_launch": upd_bytes},
+                     "algorithmic_bytes_per_launch": int(upd_bytes)},
         "cpu_baseline": cpu,
         "compare": {
             other: results[other],
@@ -1095,7 +1095,8 @@ def compact_compare(cmp, other):
 
     c = {f"{other}_it_per_s": rate(cmp[other]), "pipelined_over_unpipelined": cmp["pipelined_over_unpipelined"],
          "GBps_whole_iteration": cmp["algorithmic_GBps_whole_iteration"]}
-    for k in ("fcg_host_sync", "pipefcg_mixed", "fcg_mixed", "pipefcg_block", "fcg_block",
+    # (the host-synchronised FCG baseline stays in the detail line)
+    for k in ("pipefcg_mixed", "fcg_mixed", "pipefcg_block", "fcg_block",
               "pipefcg_block_mixed", "fcg_block_mixed"):
         if k in cmp:
             c[k] = rate(cmp[k])
@@ -1114,7 +1115,8 @@ def compact_compare(cmp, other):
                            "pipefcg_persistent_it_per_s": bt.get("pipefcg_persistent_batch_iters_per_s"),
                            "speedup_vs_one_at_a_time": bt.get("batching_speedup"),
                            "solve_s": t.get("seconds"), "converged": t.get("converged"),
-                           "max_true_rel": t.get("max_true_rel_resid")}
+                           "max_true_rel": (float(f"{t['max_true_rel_resid']:.3g}")
+                                            if t.get("max_true_rel_resid") is not None else None)}
     sv = cmp.get("serving")
     if sv:
         row = {"capacity": {k: sv["burst"][k] for k in ("converged_solves_per_s", "p50_ms", "p99_ms", "converged",
