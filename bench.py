@@ -292,6 +292,13 @@ def size_sweep(pfk, torch, steps=40):
     return out
 
 
+def least_padding_tile(n):
+    """The stencil tile width (64: 64 x 8 tiles, 32: 32 x 16) that pads an n x n
+    plane least (64 on a tie)."""
+    pad = {tx: -(-n // tx) * tx * -(-n // (512 // tx)) * (512 // tx) for tx in (64, 32)}
+    return 64 if pad[64] <= pad[32] else 32
+
+
 def batch_member_tiling(A, n, tile_x, vector_blocks, zc):
     """A batch member's launch geometry: stencil tiles of width tile_x, the
     z-range cut into chunks of about zc planes, vector_blocks workgroups for
@@ -310,9 +317,9 @@ def batched_bench(pfk, torch, steps, warmup, count=64, solve=True, batch_zc=0):
     autotuner.  Reports steady-state batch iterations/s (every system advances
     one iteration), the same for FCG and for the systems stepped one at a time,
     and the time to solve all of them to rtol 1e-8.  batch_zc > 0 gives the
-    batch member tilings of the autotuned tile width and vector workgroups
-    with z-marches of about batch_zc planes (the one-at-a-time comparison
-    keeps the autotuned single-solve tilings)."""
+    batch member tilings of the least-padding tile width, the autotuned
+    vector workgroups and z-marches of about batch_zc planes (the
+    one-at-a-time comparison keeps the autotuned single-solve tilings)."""
     import gen
     NU4, K4 = 20, 4
     # the configuration gives no iteration limit: 20000 lets the slowest
@@ -338,8 +345,7 @@ def batched_bench(pfk, torch, steps, warmup, count=64, solve=True, batch_zc=0):
 
     def batch_tiling(zc):
         for p, A, B in mem:
-            t = tuning[p.n]
-            batch_member_tiling(A, p.n, t["tile_x"], t["vector_blocks"], zc)
+            batch_member_tiling(A, p.n, least_padding_tile(p.n), tuning[p.n]["vector_blocks"], zc)
 
     total_n = sum(A.N for _, A, _ in mem)
     bs = [torch.as_tensor(p.b).cuda() for p, _, _ in mem]
@@ -366,8 +372,9 @@ def batched_bench(pfk, torch, steps, warmup, count=64, solve=True, batch_zc=0):
             raise RuntimeError(f"batched {method}: {count - running} systems stopped during timing")
         return steps / dt
 
-    # optional: member tilings with z-chunks of batch_zc planes (longer
-    # z-marches than the single-solve tilings of these small grids)
+    # optional: member tilings with the least-padding tile width and z-chunks
+    # of batch_zc planes (longer z-marches than the single-solve tilings of
+    # these small grids)
     if batch_zc > 0:
         batch_tiling(batch_zc)
         out["batch_zc"] = batch_zc
@@ -458,8 +465,7 @@ def serving_bench(pfk, torch, nreq=240, seed=0, loads=(0.9,), direct=False, per_
         if zc > 0:
             # batch member tiling: z-marches of about zc planes, the tile width
             # that pads the grid least, the operator's vector workgroups
-            pad = {tx: -(-n // tx) * tx * -(-n // (512 // tx)) * (512 // tx) for tx in (64, 32)}
-            batch_member_tiling(A, n, 64 if pad[64] <= pad[32] else 32, A.tiling()[2], zc)
+            batch_member_tiling(A, n, least_padding_tile(n), A.tiling()[2], zc)
         if method == "pipefgmres":
             B = pfk.Precond(A, "jacobi_gmres", 5, precision=pfk.FP32_BF16COEF)
         else:
