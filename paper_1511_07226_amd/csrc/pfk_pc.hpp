@@ -734,9 +734,9 @@ k_gmpc_finish(int k, const double* part, int P, SolveState* st) {
 // blocks per workgroup.  The block's coefficients (diagonal, D^-1 and the six
 // in-block off-diagonals) are formed once from the viscosity and velocities
 // and stay in registers; directions are exchanged through LDS.  Block dot
-// products accumulate in FP64: a butterfly over the wave (every lane ends
-// with the same bits, since a + b == b + a) and, in 3D, the block's two wave
-// sums through LDS in a fixed order.
+// products accumulate in FP64: a DPP sum over the wave read back from its
+// last lane (every lane takes the same value) and, in 3D, the block's two
+// wave sums through LDS in a fixed order.
 constexpr int kBjEdge = 8;
 
 template <int D3>
@@ -746,12 +746,6 @@ struct BjShape {
   static constexpr int BPW = kWaves / WPB;      // blocks per workgroup (along x)
   static constexpr int ZL = D3 ? kBjEdge : 1;   // planes per block
 };
-
-__device__ __forceinline__ double wave_allsum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
 
 // Diagonal and in-block off-diagonal couplings of node (i, j, k); zl is its
 // plane within the block.  (A_bb u)_c = d u_c - sum_f o_f u_f, faces in the
@@ -901,7 +895,7 @@ __device__ __forceinline__ void block_pcg_body(Blk bk, G g, int wx, int wy, int 
 
   int par = 0;
   auto bsum = [&](double part) -> double {
-    double s = wave_allsum(part);
+    double s = wave_sum(part);
     if (WPB == 1) return s;
     if (lane == 0) sred[par][wave] = s;
     __syncthreads();
