@@ -1121,14 +1121,17 @@ def compact_compare(cmp, other):
                            "pipefcg_persistent_it_per_s": bt.get("pipefcg_persistent_batch_iters_per_s"),
                            "speedup_vs_one_at_a_time": bt.get("batching_speedup"),
                            "solve_s": t.get("seconds"), "converged": t.get("converged"),
-                           "max_true_rel": (float(f"{t['max_true_rel_resid']:.3g}")
+                           "max_true_rel": (float(f"{t['max_true_rel_resid']:.4g}")
                                             if t.get("max_true_rel_resid") is not None else None)}
     sv = cmp.get("serving")
     if sv:
-        row = {"capacity": {k: sv["burst"][k] for k in ("converged_solves_per_s", "p50_ms", "p99_ms", "converged",
-                                                        "requests")}}
+        def ms(v):
+            return round(v) if isinstance(v, (int, float)) else v
+
+        row = {"capacity": {k: (ms(sv["burst"][k]) if k.endswith("_ms") else sv["burst"][k])
+                            for k in ("converged_solves_per_s", "p50_ms", "p99_ms", "converged", "requests")}}
         for f, r in sv.get("poisson", {}).items():
-            row[f] = [r[k] for k in ("converged_solves_per_s", "p50_ms", "p99_ms")]
+            row[f] = [r["converged_solves_per_s"], ms(r["p50_ms"]), ms(r["p99_ms"])]
         c["serving"] = row
     sw = cmp.get("size_sweep_it_per_s")
     if sw:
