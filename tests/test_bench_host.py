@@ -90,3 +90,22 @@ def test_compact_line_is_short():
     c = bench.compact_compare(cmp, "fcg")
     assert "not_converged_sample" not in str(c)
     assert c["serving"]["0.5x"][0] == 12.0
+
+
+def test_batch_member_tiling():
+    # the tile width that pads an n x n plane least (64 x 8 or 32 x 16 tiles)
+    assert bench.least_padding_tile(32) == 32 and bench.least_padding_tile(96) == 32
+    assert bench.least_padding_tile(64) == 64 and bench.least_padding_tile(128) == 64
+    assert bench.least_padding_tile(80) == 32 and bench.least_padding_tile(40) == 64
+
+    class FakeOp:
+        def set_tiling(self, tx, target, vb):
+            self.args = (tx, target, vb)
+
+    # the stencil target makes the z-range into chunks of about zc planes:
+    # tiles per plane times ceil(n / zc)
+    A = FakeOp()
+    bench.batch_member_tiling(A, 96, 32, 512, 32)
+    assert A.args == (32, 3 * 6 * 3, 512)
+    bench.batch_member_tiling(A, 40, 64, 100, 16)
+    assert A.args == (64, 1 * 5 * 3, 100)
