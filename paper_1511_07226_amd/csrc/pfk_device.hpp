@@ -588,13 +588,22 @@ __device__ __forceinline__ void block_partials(double (&acc)[NC], int nc, double
 }
 
 // Sum column c of P partials with the whole workgroup (fixed order); the
-// result is returned to every thread.  Every thread must call this.
+// result is returned to every thread.  Every thread must call this.  Eight
+// independent partial sums per thread keep eight loads in flight (a kernel's
+// prologue reads up to 16384 partials of the previous launch).
 __device__ __forceinline__ double block_sum_column(const double* part, int P, int c) {
   __shared__ double sh[kWaves];
   __shared__ double result;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  double s = 0.0;
-  for (int b = threadIdx.x; b < P; b += kBlock) s += part[(long long)c * P + b];
+  const double* col = part + (long long)c * P;
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int b = threadIdx.x;
+  for (; b + 7 * kBlock < P; b += 8 * kBlock) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] += col[b + q * kBlock];
+  }
+  for (; b < P; b += kBlock) a[0] += col[b];
+  double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   s = wave_sum(s);
   if (lane == 0) sh[wid] = s;
   __syncthreads();
