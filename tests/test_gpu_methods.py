@@ -59,6 +59,25 @@ def test_inner_gmres_matches_oracle(pfk, k, conv):
     assert np.abs(y - ref).max() <= 1e-10 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("k", [1, 2, 5, 7])
+@pytest.mark.parametrize("mixed", [False, True])
+def test_inner_gmres_exact_breakdown(pfk, k, mixed):
+    # one node, eta = 1 (2D, h = 1/2): A = 16 and D^-1 = 1/16 exactly, so for
+    # v = 1 the operator A D^-1 is the identity in floating point and the
+    # second basis vector is exactly zero: a happy breakdown after one column
+    # (found by step 2's pass, or by the finish for k = 1), B(v) = 1/16
+    _say("inner gmres exact breakdown", k, mixed)
+    p = gen.make_problem(2, 1, 1, 1.0, seed=0)
+    eta = np.ones_like(p.eta)
+    Ao = oracle.StencilOperator(2, 1, eta)
+    ref = oracle.make_pc("jacobi_gmres", Ao, k)(np.array([1.0]))
+    assert ref[0] == 0.0625
+    Ag = pfk.Operator(2, 1, eta)
+    prec = pfk.FP32_BF16COEF if mixed else pfk.FP64
+    y = _host(pfk.Precond(Ag, "jacobi_gmres", k, precision=prec).apply(_dev(np.array([1.0]))))
+    assert y[0] == 0.0625, y
+
+
 def test_inner_gmres_zero_input(pfk):
     _say("inner gmres zero")
     p = gen.make_problem(2, 16, 2, 2.0, seed=0)
