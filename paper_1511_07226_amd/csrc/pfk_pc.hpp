@@ -223,8 +223,8 @@ __device__ __forceinline__ void pcg_a1_body(Blk bk, G g, StencilGeom sg, const T
   };
   const auto in = stencil_in(load, value);
   // nontemporal stores on large systems: the halo lines that neighbouring
-  // tiles still read stay longer in the L2 (256^3: FETCH 1.23 -> 1.19x the
-  // algorithmic reads for A_j, 1.38 -> 1.32x for A_1)
+  // tiles still read stay longer in the L2 (256^3, one geometry: FETCH of
+  // A_j 1.23 -> 1.19x its algorithmic reads, of A_1 1.38 -> 1.32x)
   const bool nt = st->nt != 0;
   auto sink = [&](long long idx, T pc, T q) {
     if (nt) {
@@ -416,8 +416,8 @@ __device__ __forceinline__ void pcg_a_body(Blk bk, int jstep, G g, StencilGeom s
   const auto in = stencil_in([&](long long t) { return Raw{dinv[t], rho[t], pprev[t]}; },
                              [&](const Raw& q) { return q.d * q.r + beta * q.p; });
   // nontemporal stores on large systems: the halo lines that neighbouring
-  // tiles still read stay longer in the L2 (256^3: FETCH 1.23 -> 1.19x the
-  // algorithmic reads for A_j, 1.38 -> 1.32x for A_1)
+  // tiles still read stay longer in the L2 (256^3, one geometry: FETCH of
+  // A_j 1.23 -> 1.19x its algorithmic reads, of A_1 1.38 -> 1.32x)
   const bool nt = st->nt != 0;
   auto sink = [&](long long idx, T pc, T q) {
     if (nt) {
