@@ -79,6 +79,20 @@ def test_jacobi_gmres_zero_input():
     assert not np.any(jacobi_gmres(A.apply, 1.0 / A.diagonal(), np.zeros(A.N), 3))
 
 
+@pytest.mark.parametrize("k", [1, 2, 5, 8])
+def test_jacobi_gmres_exact_breakdown_one_node(k):
+    # one node with eta = 1 in 2D (h = 1/2): A = 4 * 4 = 16 and A D^-1 = 1, so
+    # the Krylov space is span{v}; every k returns the exact solution
+    # t = v of A D^-1 t = v, i.e. B(v) = v / 16 (a zero second basis vector
+    # must end the cycle cleanly, not divide by its zero norm)
+    p = gen.make_problem(2, 1, 1, 1.0, seed=0)
+    A = StencilOperator(2, 1, np.ones_like(p.eta))
+    assert A.apply(np.array([1.0]))[0] == 16.0
+    for v in (1.0, -3.0, 0.5):
+        y = jacobi_gmres(A.apply, 1.0 / A.diagonal(), np.array([v]), k)
+        assert np.isfinite(y).all() and abs(y[0] - v / 16.0) <= 1e-15 * abs(v)
+
+
 @pytest.mark.parametrize("dim,n,bs,k,conv", [(2, 11, 4, 3, False), (3, 7, 3, 5, False), (3, 6, 4, 2, True)])
 def test_block_jacobi_pcg_matches_per_block_scipy_cg(dim, n, bs, k, conv):
     from oracle import block_jacobi_pcg
