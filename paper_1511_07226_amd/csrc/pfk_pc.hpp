@@ -207,7 +207,12 @@ __device__ __forceinline__ void pcg_a1_body(Blk bk, G g, StencilGeom sg, const T
          double* part, const SolveState* st) {
   if (!wg_running(st)) return;
   double acc[2] = {0.0, 0.0};
-  auto V = [&](long long t) { double r = c1 * X1[t]; if (X2 != nullptr) r += c2 * X2[t]; return T(r); };
+  // v at the thread's own nodes, from the plane step that loads it (keep) to
+  // the one that has p_1 and q there (sink), in thread-private LDS: the dot
+  // <v, p_1> reads no vector a second time
+  __shared__ T s_vk[4][kBlock];
+  const int tid = threadIdx.x;
+  auto V = [&](double x1, double x2) { double r = c1 * x1; if (X2 != nullptr) r += c2 * x2; return T(r); };
   struct Raw { T d; double x1, x2; };
   auto load = [&](long long t) {
     Raw q{};
@@ -216,17 +221,14 @@ __device__ __forceinline__ void pcg_a1_body(Blk bk, G g, StencilGeom sg, const T
     if (X2 != nullptr) q.x2 = X2[t];
     return q;
   };
-  auto value = [&](const Raw& q) {        // dinv * V, V's arithmetic
-    double r = c1 * q.x1;
-    if (X2 != nullptr) r += c2 * q.x2;
-    return q.d * T(r);
-  };
-  const auto in = stencil_in(load, value);
+  auto value = [&](const Raw& q) { return q.d * V(q.x1, q.x2); };
+  auto keep = [&](long long, const Raw& q, int slot) { s_vk[slot][tid] = V(q.x1, q.x2); };
+  const auto in = stencil_in(load, value, keep);
   // nontemporal stores on large systems: the halo lines that neighbouring
   // tiles still read stay longer in the L2 (256^3, one geometry: FETCH of
   // A_j 1.23 -> 1.19x its algorithmic reads, of A_1 1.38 -> 1.32x)
   const bool nt = st->nt != 0;
-  auto sink = [&](long long idx, T pc, T q) {
+  auto sink = [&](long long idx, T pc, T q, int slot) {
     if (nt) {
       stnt(pout + idx, pc);
       stnt(qout + idx, q);
@@ -235,7 +237,7 @@ __device__ __forceinline__ void pcg_a1_body(Blk bk, G g, StencilGeom sg, const T
       qout[idx] = q;
     }
     acc[0] += (double)pc * (double)q;
-    acc[1] += (double)V(idx) * (double)pc;
+    acc[1] += (double)s_vk[slot][tid] * (double)pc;
   };
   // FP32 loads two plane steps ahead (no occupancy step lost; mixed PIPEFCG
   // 213 -> 227 it/s at 256^3); FP64 one (a second plane would cost one)
